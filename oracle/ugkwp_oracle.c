@@ -1,0 +1,996 @@
+/*
+ * ugkwp_oracle.c -- plain, slow, double-precision CPU reference for one time step of the
+ * three-dimensional unified gas-kinetic wave-particle (UGKWP) method of Chen, Zhu and Xu,
+ * "A three-dimensional unified gas-kinetic wave-particle solver for flow computation in all
+ * regimes" (arXiv 2007.13091).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The product never links, loads or calls this file: only the
+ * tests, the smoke check and the CPU-baseline leg of the benchmark do.  It shares no code
+ * with the GPU library.  It has its own mesh preparation, Philox generator, Maxwellian
+ * moments, interface flux, sampling, tracking and update, written from the paper's
+ * equations and the readings of the paper written down in the design notes.
+ *
+ * Every loop is sequential, in the plain order of the scheme (paper Sec. 2.2-2.4):
+ *   primitives and the time step (Sec. 2.4(a)), hydro/particle split (Eq. of W^p),
+ *   wave flux per face (Eqs. of F^eq and F^{fr,wave}), sampling of hydro particles
+ *   (Sec. 2.4(b)), free-flight times (Eq. sampling_of_free_transport_time), free transport
+ *   (Sec. 2.3), particle sums and the conservative update (Eq. update_macro_variables),
+ *   deletion of collided particles (the four-step particle procedure of Sec. 2.3).
+ * All arithmetic is IEEE double with libm transcendental functions; it must be compiled
+ * with -ffp-contract=off and without -ffast-math.
+ *
+ * Pins (what fixes this code independently of itself) live in tests/test_oracle_*.py:
+ * Philox against numpy, moments and q-coefficients against quadrature, the uniform-state
+ * flux against the Euler flux, conservation in closed boxes, the free-molecular limit,
+ * brute-force tracking on two-cell meshes, exact sampling counts and masses, and the
+ * Euler-limit shock tube against an exact Riemann solver.  The complete multi-step
+ * trajectory at finite Knudsen number has no printed values in the paper: beyond those
+ * invariants it is "parity unpinned".
+ */
+#define _DEFAULT_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG 1
+#define ORC_E_MESH 2
+#define ORC_E_CAPACITY 3
+#define ORC_E_LOST 4
+#define ORC_E_NONPHYS 5
+
+enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2 };
+enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5 };
+
+/* ------------------------------------------------------------------------------------ */
+/* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter based.       */
+/* ------------------------------------------------------------------------------------ */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ULL * c0;
+        unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ULL * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* eta in (0,1): the top 52 bits plus one half, times 2^-52 (never 0 or 1). */
+static double u01(uint64_t r) { return ((double)(r >> 12) + 0.5) * 0x1p-52; }
+
+/* Four uniforms keyed by (particle id, step, tag, sub-index, instance); key = (seed, 0). */
+static void draw4(uint64_t seed, uint64_t uid, int64_t step, int tag, uint32_t sub,
+                  int64_t inst, double eta[4])
+{
+    uint64_t ctr[4] = {uid, (uint64_t)step, ((uint64_t)tag << 32) | sub, (uint64_t)inst};
+    uint64_t key[2] = {seed, 0};
+    uint64_t r[4];
+    orc_philox4x64_10(ctr, key, r);
+    for (int i = 0; i < 4; ++i) eta[i] = u01(r[i]);
+}
+
+/* Particle id: bit 63 born at a far-field face, bits 62..44 birth step, bits 43..20 birth
+ * cell (or face), bits 19..0 index within that cell and step. */
+uint64_t orc_make_uid(int ghost, int64_t step, int64_t where, int64_t k)
+{
+    return ((uint64_t)(ghost & 1) << 63) | (((uint64_t)step & 0x7FFFFULL) << 44) |
+           (((uint64_t)where & 0xFFFFFFULL) << 20) | ((uint64_t)k & 0xFFFFFULL);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Maxwellian moments (R = 1, K = 0).  <u^k> of a normalised 1D Maxwellian with mean U and  */
+/* lambda = 1/(2T); full range, u > 0 and u < 0.  Recursion                               */
+/*   <u^{k+2}> = U <u^{k+1}> + (k+1)/(2 lambda) <u^k>   (holds on each half line too).     */
+/* ------------------------------------------------------------------------------------ */
+#define NMOM 7
+void orc_moments(int range, double U, double lam, double m[NMOM])
+{
+    if (range == 0) {
+        m[0] = 1.0;
+        m[1] = U;
+    } else if (range > 0) {
+        m[0] = 0.5 * erfc(-sqrt(lam) * U);
+        m[1] = U * m[0] + 0.5 * exp(-lam * U * U) / sqrt(M_PI * lam);
+    } else {
+        m[0] = 0.5 * erfc(sqrt(lam) * U);
+        m[1] = U * m[0] - 0.5 * exp(-lam * U * U) / sqrt(M_PI * lam);
+    }
+    for (int k = 0; k + 2 < NMOM; ++k) m[k + 2] = U * m[k + 1] + (k + 1) / (2.0 * lam) * m[k];
+}
+
+/* Face frame: n, t1 = normalise(e_a x n) with a the axis of smallest |n_a| (lowest index on a
+ * tie), t2 = n x t1. */
+static void face_frame(const double n[3], double t1[3], double t2[3])
+{
+    int a = 0;
+    if (fabs(n[1]) < fabs(n[a])) a = 1;
+    if (fabs(n[2]) < fabs(n[a])) a = 2;
+    double e[3] = {0, 0, 0};
+    e[a] = 1.0;
+    double c[3] = {e[1] * n[2] - e[2] * n[1], e[2] * n[0] - e[0] * n[2], e[0] * n[1] - e[1] * n[0]};
+    double l = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    t1[0] = c[0] / l; t1[1] = c[1] / l; t1[2] = c[2] / l;
+    t2[0] = n[1] * t1[2] - n[2] * t1[1];
+    t2[1] = n[2] * t1[0] - n[0] * t1[2];
+    t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+/* Primitive state in a face frame. */
+typedef struct { double rho, un, v, w, lam, T; } prim_t;
+
+static prim_t to_frame(const double W[5], const double n[3], const double t1[3], const double t2[3])
+{
+    prim_t p;
+    p.rho = W[0];
+    double U = W[1] / W[0], V = W[2] / W[0], Wz = W[3] / W[0];
+    p.un = U * n[0] + V * n[1] + Wz * n[2];
+    p.v = U * t1[0] + V * t1[1] + Wz * t1[2];
+    p.w = U * t2[0] + V * t2[1] + Wz * t2[2];
+    p.T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+    p.lam = 1.0 / (2.0 * p.T);
+    return p;
+}
+
+/* <psi> and <u_n psi> of a unit-density Maxwellian in the face frame, with the normal
+ * moments m[] taken over the chosen range of u_n; psi = (1, u_n, v, w, (u_n^2+v^2+w^2)/2). */
+static void psi_moments(const prim_t *p, const double m[NMOM], double H[5], double G[5])
+{
+    double tr = p->v * p->v + p->w * p->w + 1.0 / p->lam; /* <v^2 + w^2> */
+    H[0] = m[0];
+    H[1] = m[1];
+    H[2] = m[0] * p->v;
+    H[3] = m[0] * p->w;
+    H[4] = 0.5 * (m[2] + m[0] * tr);
+    G[0] = m[1];
+    G[1] = m[2];
+    G[2] = m[1] * p->v;
+    G[3] = m[1] * p->w;
+    G[4] = 0.5 * (m[3] + m[1] * tr);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Time-integrated coefficients, Eq. of q1..q5, with x = dt/tau and e = exp(-x).  Only the */
+/* combinations the first-order flux needs are formed here:                               */
+/*   q1 = tau (x - 1 + e),   q4 - dt e = tau (1 - (1 + x) e).                              */
+/* For x < 1 both are summed as their Taylor series (terms x^2 .. x^24, Horner order):     */
+/*   q1/tau        = sum_{k>=2} (-1)^k x^k / k!                                            */
+/*   (q4-dt e)/tau = sum_{k>=2} (-1)^k (k-1) x^k / k!                                      */
+/* ------------------------------------------------------------------------------------ */
+#define QSER_X 1.0
+#define QSER_K 24
+void orc_qcoef(double dt, double tau, double out[5])
+{
+    double x = dt / tau;
+    double e = exp(-x);
+    double q1, q4m, q2, q3, q5p;
+    if (x < QSER_X) {
+        double fact[QSER_K + 1];
+        fact[0] = 1.0;
+        for (int k = 1; k <= QSER_K; ++k) fact[k] = fact[k - 1] * k;
+        double s1 = 0, s4 = 0, s2 = 0, s3 = 0, s5 = 0;
+        for (int k = QSER_K; k >= 2; --k) {
+            double sg = (k % 2 == 0) ? 1.0 : -1.0;
+            s1 = s1 * x + sg / fact[k];
+            s4 = s4 * x + sg * (k - 1) / fact[k];
+            if (k >= 3) {
+                s2 = s2 * x + sg * (k - 2) / fact[k];
+                s3 = s3 * x - sg / fact[k];
+                s5 = s5 * x + sg * (double)((k - 1) * (k - 2)) / (2.0 * fact[k]);
+            }
+        }
+        q1 = tau * (s1 * x * x);
+        q4m = tau * (s4 * x * x);
+        q2 = tau * tau * (s2 * x * x * x);
+        q3 = tau * tau * (s3 * x * x * x);
+        q5p = tau * tau * (s5 * x * x * x);
+    } else {
+        q1 = tau * (x - 1.0 + e);
+        q4m = tau * (1.0 - (1.0 + x) * e);
+        q2 = tau * tau * (2.0 * (1.0 - e) - x * (1.0 + e));
+        q3 = tau * tau * (0.5 * x * x - x + 1.0 - e);
+        q5p = tau * tau * ((1.0 + x + 0.5 * x * x) * e - 1.0);
+    }
+    out[0] = q1; out[1] = q2; out[2] = q3; out[3] = q4m; out[4] = q5p;
+}
+
+static void rotate_back(const double Ff[5], const double n[3], const double t1[3], const double t2[3],
+                        double F[5])
+{
+    F[0] = Ff[0];
+    for (int d = 0; d < 3; ++d) F[1 + d] = Ff[1] * n[d] + Ff[2] * t1[d] + Ff[3] * t2[d];
+    F[4] = Ff[4];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* First-order interface flux of the wave part over dt, per unit area, global frame:      */
+/*   F = F^eq + F^{fr,wave}                                                               */
+/*   F^eq      = rho0 q1 <u_n psi>_0           (g0 from the upwind moments of both sides)  */
+/*   F^{fr,wave} = sum_s rhoh_s (q4 - dt e) <u_n psi>_{s, half}                            */
+/* tau at the face = mu_ref T0^omega / p0 + C2 |pl - pr| / (pl + pr) dt (Sec. 2.4(d)).     */
+/* rhoh_l, rhoh_r: density of the hydro Maxwellian (U and T of the total state).           */
+/* ------------------------------------------------------------------------------------ */
+static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rhohr, double dt,
+                      double mu_ref, double omega, double c2, double Ff[5])
+{
+    double ml[NMOM], mr[NMOM], Hl[5], Gl[5], Hr[5], Gr[5];
+    orc_moments(+1, l->un, l->lam, ml);
+    orc_moments(-1, r->un, r->lam, mr);
+    psi_moments(l, ml, Hl, Gl);
+    psi_moments(r, mr, Hr, Gr);
+    double W0[5];
+    for (int k = 0; k < 5; ++k) W0[k] = l->rho * Hl[k] + r->rho * Hr[k];
+    prim_t z;
+    z.rho = W0[0];
+    z.un = W0[1] / W0[0];
+    z.v = W0[2] / W0[0];
+    z.w = W0[3] / W0[0];
+    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.lam = 1.0 / (2.0 * z.T);
+    double pl = l->rho * l->T, pr = r->rho * r->T;
+    double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
+    double q[5];
+    orc_qcoef(dt, tau, q);
+    double m0[NMOM], H0[5], G0[5];
+    orc_moments(0, z.un, z.lam, m0);
+    psi_moments(&z, m0, H0, G0);
+    for (int k = 0; k < 5; ++k)
+        Ff[k] = q[0] * z.rho * G0[k] + q[3] * (rhohl * Gl[k] + rhohr * Gr[k]);
+}
+
+void orc_flux_interior(const double Wl[5], const double Wr[5], double rhohl, double rhohr,
+                       const double n[3], double dt, double mu_ref, double omega, double c2,
+                       double F[5])
+{
+    double t1[3], t2[3], Ff[5];
+    face_frame(n, t1, t2);
+    prim_t l = to_frame(Wl, n, t1, t2), r = to_frame(Wr, n, t1, t2);
+    flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, Ff);
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* Specular (symmetry) wall: interior flux against the mirror state (u_n -> -u_n), then only
+ * the normal-momentum component is kept; n points out of the domain. */
+void orc_flux_specular(const double W[5], double rhoh, const double n[3], double dt,
+                       double mu_ref, double omega, double c2, double F[5])
+{
+    double t1[3], t2[3], Ff[5];
+    face_frame(n, t1, t2);
+    prim_t l = to_frame(W, n, t1, t2);
+    prim_t g = l;
+    g.un = -l.un;
+    flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, Ff);
+    Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* Diffuse isothermal wall (Sec. 2.4(e)), first order, n out of the domain.  Incoming part
+ * (u_n > 0): q1 g + (q4 - dt e) g^h at the cell state with the cell's tau; the wall emits
+ * rho_w M(T_w, U_w) over u_n < 0 for the whole step, rho_w fixed by zero net mass flux. */
+void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double n[3], double dt,
+                      double Tw, const double Uw[3], double F[5])
+{
+    double t1[3], t2[3], Ff[5];
+    face_frame(n, t1, t2);
+    prim_t l = to_frame(W, n, t1, t2);
+    double q[5];
+    orc_qcoef(dt, tau_c, q);
+    double ml[NMOM], Hl[5], Gl[5];
+    orc_moments(+1, l.un, l.lam, ml);
+    psi_moments(&l, ml, Hl, Gl);
+    double Fin[5];
+    for (int k = 0; k < 5; ++k) Fin[k] = q[0] * l.rho * Gl[k] + q[3] * rhoh * Gl[k];
+    prim_t w;
+    w.rho = 1.0;
+    w.un = Uw[0] * n[0] + Uw[1] * n[1] + Uw[2] * n[2];
+    w.v = Uw[0] * t1[0] + Uw[1] * t1[1] + Uw[2] * t1[2];
+    w.w = Uw[0] * t2[0] + Uw[1] * t2[1] + Uw[2] * t2[2];
+    w.T = Tw;
+    w.lam = 1.0 / (2.0 * Tw);
+    double mw[NMOM], Hw[5], Gw[5];
+    orc_moments(-1, w.un, w.lam, mw);
+    psi_moments(&w, mw, Hw, Gw);
+    double rhow = -Fin[0] / (dt * Gw[0]);
+    for (int k = 0; k < 5; ++k) Ff[k] = Fin[k] + dt * rhow * Gw[k];
+    Ff[0] = 0.0;
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Mesh: cells (4-node tetrahedra, 8-node axis-aligned boxes in VTK node order), faces     */
+/* found by matching sorted node sets.                                                    */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    int type;
+    double Tw, Uw[3], Winf[5];
+} obc_t;
+
+typedef struct {
+    int64_t key[4];
+    int64_t cell;
+    int lf;
+} fkey_t;
+
+typedef struct oracle {
+    /* parameters */
+    double mu_ref, omega, cfl, c2;
+    int n_ref, n_min, max_cross;
+    uint64_t seed;
+    int64_t inst;
+    /* mesh */
+    int64_t nc, nf;
+    int *ctype, *cnf;
+    double *vol, *xc, *dS;
+    int64_t *cface;   /* [nc][6] global face id */
+    int *csign;       /* [nc][6] +1 when the cell owns the face */
+    double *pn, *pd;  /* [nc][6][3], [nc][6]: outward plane n.x = d */
+    int64_t *cnb;     /* [nc][6] neighbour cell, or -1 - bc index */
+    int *cnblf;       /* [nc][6] local face index in the neighbour */
+    double *orig, *edge; /* sampling frame: [nc][3], [nc][3][3] */
+    int64_t *fown, *fnb; /* fnb: neighbour cell or -1 - bc index */
+    double *fn, *farea;
+    int nbc;
+    obc_t *bc;
+    /* state */
+    double *W, *P;    /* [nc][5] */
+    int64_t *nleft;
+    int64_t step;
+    double t;
+    /* particles */
+    int64_t np, cap;
+    double *px, *pu, *pm;
+    int64_t *pc;
+    uint64_t *pid;
+    /* last step statistics */
+    double st_dt;
+    int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits;
+} oracle_t;
+
+static int cmp_fkey(const void *a, const void *b)
+{
+    const fkey_t *x = (const fkey_t *)a, *y = (const fkey_t *)b;
+    for (int i = 0; i < 4; ++i) {
+        if (x->key[i] < y->key[i]) return -1;
+        if (x->key[i] > y->key[i]) return 1;
+    }
+    if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
+    return x->lf - y->lf;
+}
+
+static void sort_key(int64_t k[4], int nn)
+{
+    for (int i = 0; i < nn; ++i)
+        for (int j = i + 1; j < nn; ++j)
+            if (k[j] < k[i]) { int64_t t = k[i]; k[i] = k[j]; k[j] = t; }
+    for (int i = nn; i < 4; ++i) k[i] = -1;
+}
+
+/* local faces of a box hex (VTK order): x-, x+, y-, y+, z-, z+ */
+static const int HEXF[6][4] = {{0, 3, 7, 4}, {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 6, 7}, {0, 1, 2, 3}, {4, 5, 6, 7}};
+/* local faces of a tetrahedron: face i is opposite node i */
+static const int TETF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+
+void orc_destroy(oracle_t *o);
+
+static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
+
+oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const uint8_t *cell_type,
+                     const int64_t *cell_node_off, const int64_t *cell_nodes, int64_t n_bfaces,
+                     const int64_t *bface_nodes, const int32_t *bface_bc, int32_t n_bc,
+                     const int32_t *bc_type, const double *bc_Tw, const double *bc_Uw,
+                     const double *bc_Winf, double mu_ref, double omega, double cfl, double c2,
+                     int32_t n_ref, int32_t n_min, int32_t max_cross, uint64_t seed, int64_t inst,
+                     int32_t *status)
+{
+    *status = ORC_E_MESH;
+    if (n_cells <= 0 || n_nodes <= 0) { *status = ORC_E_ARG; return NULL; }
+    oracle_t *o = (oracle_t *)xcalloc(1, sizeof(oracle_t));
+    o->mu_ref = mu_ref; o->omega = omega; o->cfl = cfl; o->c2 = c2;
+    o->n_ref = n_ref; o->n_min = n_min; o->max_cross = max_cross;
+    o->seed = seed; o->inst = inst;
+    int64_t nc = n_cells;
+    o->nc = nc;
+    o->ctype = (int *)xcalloc(nc, sizeof(int));
+    o->cnf = (int *)xcalloc(nc, sizeof(int));
+    o->vol = (double *)xcalloc(nc, sizeof(double));
+    o->xc = (double *)xcalloc(3 * nc, sizeof(double));
+    o->dS = (double *)xcalloc(3 * nc, sizeof(double));
+    o->cface = (int64_t *)xcalloc(6 * nc, sizeof(int64_t));
+    o->csign = (int *)xcalloc(6 * nc, sizeof(int));
+    o->pn = (double *)xcalloc(18 * nc, sizeof(double));
+    o->pd = (double *)xcalloc(6 * nc, sizeof(double));
+    o->cnb = (int64_t *)xcalloc(6 * nc, sizeof(int64_t));
+    o->cnblf = (int *)xcalloc(6 * nc, sizeof(int));
+    o->orig = (double *)xcalloc(3 * nc, sizeof(double));
+    o->edge = (double *)xcalloc(9 * nc, sizeof(double));
+    o->W = (double *)xcalloc(5 * nc, sizeof(double));
+    o->P = (double *)xcalloc(5 * nc, sizeof(double));
+    o->nleft = (int64_t *)xcalloc(nc, sizeof(int64_t));
+    o->nbc = n_bc;
+    o->bc = (obc_t *)xcalloc(n_bc, sizeof(obc_t));
+    for (int b = 0; b < n_bc; ++b) {
+        o->bc[b].type = bc_type[b];
+        o->bc[b].Tw = bc_Tw[b];
+        for (int d = 0; d < 3; ++d) o->bc[b].Uw[d] = bc_Uw[3 * b + d];
+        for (int k = 0; k < 5; ++k) o->bc[b].Winf[k] = bc_Winf[5 * b + k];
+    }
+
+    /* per-cell local geometry: outward plane, area and face centre of each local face */
+    double *larea = (double *)xcalloc(6 * nc, sizeof(double));
+    int64_t nkeys = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t off = cell_node_off[c];
+        int nn = (int)(cell_node_off[c + 1] - off);
+        const int64_t *cn = cell_nodes + off;
+        for (int i = 0; i < nn; ++i)
+            if (cn[i] < 0 || cn[i] >= n_nodes) goto fail;
+        if (cell_type[c] == 8 && nn == 8) {
+            o->ctype[c] = 8;
+            o->cnf[c] = 6;
+            double x0 = xyz[3 * cn[0]], y0 = xyz[3 * cn[0] + 1], z0 = xyz[3 * cn[0] + 2];
+            double x1 = xyz[3 * cn[6]], y1 = xyz[3 * cn[6] + 1], z1 = xyz[3 * cn[6] + 2];
+            if (!(x1 > x0 && y1 > y0 && z1 > z0)) goto fail;
+            /* every node must sit on its corner of the box */
+            for (int i = 0; i < 8; ++i) {
+                int bx = (i == 1 || i == 2 || i == 5 || i == 6);
+                int by = (i == 2 || i == 3 || i == 6 || i == 7);
+                int bz = (i >= 4);
+                const double *p = xyz + 3 * cn[i];
+                if (p[0] != (bx ? x1 : x0) || p[1] != (by ? y1 : y0) || p[2] != (bz ? z1 : z0)) goto fail;
+            }
+            double dx = x1 - x0, dy = y1 - y0, dz = z1 - z0;
+            o->vol[c] = dx * dy * dz;
+            o->xc[3 * c] = 0.5 * (x0 + x1);
+            o->xc[3 * c + 1] = 0.5 * (y0 + y1);
+            o->xc[3 * c + 2] = 0.5 * (z0 + z1);
+            double lo[3] = {x0, y0, z0}, hi[3] = {x1, y1, z1}, ar[3] = {dy * dz, dx * dz, dx * dy};
+            for (int a = 0; a < 3; ++a) {
+                for (int s = 0; s < 2; ++s) {
+                    int lf = 2 * a + s;
+                    double *n = o->pn + 18 * c + 3 * lf;
+                    n[0] = n[1] = n[2] = 0.0;
+                    n[a] = s ? 1.0 : -1.0;
+                    o->pd[6 * c + lf] = s ? hi[a] : -lo[a];
+                    larea[6 * c + lf] = ar[a];
+                }
+            }
+            o->orig[3 * c] = x0; o->orig[3 * c + 1] = y0; o->orig[3 * c + 2] = z0;
+            double *E = o->edge + 9 * c;
+            for (int i = 0; i < 9; ++i) E[i] = 0.0;
+            E[0] = dx; E[4] = dy; E[8] = dz;
+        } else if (cell_type[c] == 4 && nn == 4) {
+            o->ctype[c] = 4;
+            o->cnf[c] = 4;
+            const double *A = xyz + 3 * cn[0], *B = xyz + 3 * cn[1], *C = xyz + 3 * cn[2], *D = xyz + 3 * cn[3];
+            double e1[3], e2[3], e3[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = B[d] - A[d]; e2[d] = C[d] - A[d]; e3[d] = D[d] - A[d]; }
+            double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+                         e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+            if (!(fabs(det) > 0.0)) goto fail;
+            o->vol[c] = fabs(det) / 6.0;
+            for (int d = 0; d < 3; ++d) {
+                o->xc[3 * c + d] = 0.25 * (A[d] + B[d] + C[d] + D[d]);
+                o->orig[3 * c + d] = A[d];
+                o->edge[9 * c + d] = e1[d];
+                o->edge[9 * c + 3 + d] = e2[d];
+                o->edge[9 * c + 6 + d] = e3[d];
+            }
+            for (int lf = 0; lf < 4; ++lf) {
+                const double *p = xyz + 3 * cn[TETF[lf][0]], *q = xyz + 3 * cn[TETF[lf][1]],
+                             *r = xyz + 3 * cn[TETF[lf][2]], *opp = xyz + 3 * cn[lf];
+                double a[3], b[3], N[3];
+                for (int d = 0; d < 3; ++d) { a[d] = q[d] - p[d]; b[d] = r[d] - p[d]; }
+                N[0] = a[1] * b[2] - a[2] * b[1];
+                N[1] = a[2] * b[0] - a[0] * b[2];
+                N[2] = a[0] * b[1] - a[1] * b[0];
+                double side = N[0] * (opp[0] - p[0]) + N[1] * (opp[1] - p[1]) + N[2] * (opp[2] - p[2]);
+                if (side > 0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+                double len = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+                double *n = o->pn + 18 * c + 3 * lf;
+                double fc[3];
+                for (int d = 0; d < 3; ++d) { n[d] = N[d] / len; fc[d] = (p[d] + q[d] + r[d]) / 3.0; }
+                o->pd[6 * c + lf] = n[0] * fc[0] + n[1] * fc[1] + n[2] * fc[2];
+                larea[6 * c + lf] = 0.5 * len;
+            }
+        } else {
+            goto fail;
+        }
+        nkeys += o->cnf[c];
+    }
+
+    /* face matching */
+    {
+        fkey_t *keys = (fkey_t *)xcalloc(nkeys, sizeof(fkey_t));
+        int64_t q = 0;
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t *cn = cell_nodes + cell_node_off[c];
+            for (int lf = 0; lf < o->cnf[c]; ++lf) {
+                fkey_t *k = keys + q++;
+                int nn = o->ctype[c] == 8 ? 4 : 3;
+                for (int i = 0; i < nn; ++i) k->key[i] = o->ctype[c] == 8 ? cn[HEXF[lf][i]] : cn[TETF[lf][i]];
+                sort_key(k->key, nn);
+                k->cell = c;
+                k->lf = lf;
+            }
+        }
+        qsort(keys, nkeys, sizeof(fkey_t), cmp_fkey);
+        fkey_t *bk = (fkey_t *)xcalloc(n_bfaces, sizeof(fkey_t));
+        for (int64_t b = 0; b < n_bfaces; ++b) {
+            int nn = bface_nodes[4 * b + 3] < 0 ? 3 : 4;
+            for (int i = 0; i < 4; ++i) bk[b].key[i] = bface_nodes[4 * b + i];
+            sort_key(bk[b].key, nn);
+            bk[b].cell = bface_bc[b];
+            bk[b].lf = 0;
+            if (bface_bc[b] < 0 || bface_bc[b] >= n_bc) { free(keys); free(bk); goto fail; }
+        }
+        qsort(bk, n_bfaces, sizeof(fkey_t), cmp_fkey);
+        o->fown = (int64_t *)xcalloc(nkeys, sizeof(int64_t));
+        o->fnb = (int64_t *)xcalloc(nkeys, sizeof(int64_t));
+        o->fn = (double *)xcalloc(3 * nkeys, sizeof(double));
+        o->farea = (double *)xcalloc(nkeys, sizeof(double));
+        int64_t nf = 0;
+        int bad = 0;
+        for (int64_t i = 0; i < nkeys && !bad;) {
+            int64_t j = i + 1;
+            while (j < nkeys && memcmp(keys[j].key, keys[i].key, sizeof(keys[i].key)) == 0) ++j;
+            int64_t c = keys[i].cell;
+            int lf = keys[i].lf;
+            if (j - i == 2) {
+                int64_t c2 = keys[i + 1].cell;
+                int lf2 = keys[i + 1].lf;
+                /* owner: the first cell in sorted order (lower index) */
+                o->fown[nf] = c;
+                o->fnb[nf] = c2;
+                for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
+                o->farea[nf] = larea[6 * c + lf];
+                o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
+                o->cface[6 * c2 + lf2] = nf; o->csign[6 * c2 + lf2] = -1;
+                o->cnb[6 * c + lf] = c2; o->cnblf[6 * c + lf] = lf2;
+                o->cnb[6 * c2 + lf2] = c; o->cnblf[6 * c2 + lf2] = lf;
+                /* the neighbour uses exactly the reversed plane of the owner */
+                for (int d = 0; d < 3; ++d) o->pn[18 * c2 + 3 * lf2 + d] = -o->pn[18 * c + 3 * lf + d];
+                o->pd[6 * c2 + lf2] = -o->pd[6 * c + lf];
+                ++nf;
+            } else if (j - i == 1) {
+                fkey_t probe = keys[i];
+                int64_t lo = 0, hi = n_bfaces - 1, found = -1;
+                while (lo <= hi) {
+                    int64_t mid = (lo + hi) / 2;
+                    int cm = 0;
+                    for (int t = 0; t < 4 && cm == 0; ++t)
+                        cm = bk[mid].key[t] < probe.key[t] ? -1 : (bk[mid].key[t] > probe.key[t] ? 1 : 0);
+                    if (cm == 0) { found = mid; break; }
+                    if (cm < 0) lo = mid + 1; else hi = mid - 1;
+                }
+                if (found < 0) { bad = 1; break; }
+                int b = (int)bk[found].cell;
+                o->fown[nf] = c;
+                o->fnb[nf] = -1 - b;
+                for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
+                o->farea[nf] = larea[6 * c + lf];
+                o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
+                o->cnb[6 * c + lf] = -1 - b; o->cnblf[6 * c + lf] = -1;
+                ++nf;
+            } else {
+                bad = 1;
+            }
+            i = j;
+        }
+        free(keys);
+        free(bk);
+        if (bad) goto fail;
+        o->nf = nf;
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int lf = 0; lf < o->cnf[c]; ++lf) {
+            const double *n = o->pn + 18 * c + 3 * lf;
+            double a = larea[6 * c + lf];
+            for (int d = 0; d < 3; ++d) o->dS[3 * c + d] += 0.5 * fabs(a * n[d]);
+        }
+    }
+    free(larea);
+    o->cap = 0;
+    *status = ORC_OK;
+    return o;
+fail:
+    free(larea);
+    orc_destroy(o);
+    return NULL;
+}
+
+void orc_destroy(oracle_t *o)
+{
+    if (!o) return;
+    free(o->ctype); free(o->cnf); free(o->vol); free(o->xc); free(o->dS);
+    free(o->cface); free(o->csign); free(o->pn); free(o->pd); free(o->cnb); free(o->cnblf);
+    free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
+    free(o->bc); free(o->W); free(o->P); free(o->nleft);
+    free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
+    free(o);
+}
+
+int64_t orc_n_cells(const oracle_t *o) { return o->nc; }
+int64_t orc_n_faces(const oracle_t *o) { return o->nf; }
+int64_t orc_n_particles(const oracle_t *o) { return o->np; }
+int64_t orc_step_index(const oracle_t *o) { return o->step; }
+double orc_time(const oracle_t *o) { return o->t; }
+
+void orc_geometry(const oracle_t *o, double *vol, double *xc, double *dS)
+{
+    memcpy(vol, o->vol, sizeof(double) * o->nc);
+    memcpy(xc, o->xc, sizeof(double) * 3 * o->nc);
+    memcpy(dS, o->dS, sizeof(double) * 3 * o->nc);
+}
+
+void orc_stats(const oracle_t *o, double *dt, int64_t out[6])
+{
+    *dt = o->st_dt;
+    out[0] = o->st_alive; out[1] = o->st_sampled; out[2] = o->st_collided;
+    out[3] = o->st_escaped; out[4] = o->st_cross; out[5] = o->st_wallhits;
+}
+
+int orc_set_state(oracle_t *o, const double *W)
+{
+    memcpy(o->W, W, sizeof(double) * 5 * o->nc);
+    memset(o->P, 0, sizeof(double) * 5 * o->nc);
+    memset(o->nleft, 0, sizeof(int64_t) * o->nc);
+    o->np = 0;
+    o->step = 0;
+    o->t = 0.0;
+    return ORC_OK;
+}
+
+void orc_get_state(const oracle_t *o, double *W, double *P, int64_t *nleft)
+{
+    memcpy(W, o->W, sizeof(double) * 5 * o->nc);
+    memcpy(P, o->P, sizeof(double) * 5 * o->nc);
+    memcpy(nleft, o->nleft, sizeof(int64_t) * o->nc);
+}
+
+void orc_get_particles(const oracle_t *o, double *x, double *u, double *m, int64_t *cell, uint64_t *uid)
+{
+    memcpy(x, o->px, sizeof(double) * 3 * o->np);
+    memcpy(u, o->pu, sizeof(double) * 3 * o->np);
+    memcpy(m, o->pm, sizeof(double) * o->np);
+    memcpy(cell, o->pc, sizeof(int64_t) * o->np);
+    memcpy(uid, o->pid, sizeof(uint64_t) * o->np);
+}
+
+static int reserve(oracle_t *o, int64_t n)
+{
+    if (n <= o->cap) return 0;
+    int64_t cap = o->cap ? o->cap : 1024;
+    while (cap < n) cap *= 2;
+    double *px = (double *)realloc(o->px, sizeof(double) * 3 * cap);
+    if (px) o->px = px;
+    double *pu = (double *)realloc(o->pu, sizeof(double) * 3 * cap);
+    if (pu) o->pu = pu;
+    double *pm = (double *)realloc(o->pm, sizeof(double) * cap);
+    if (pm) o->pm = pm;
+    int64_t *pc = (int64_t *)realloc(o->pc, sizeof(int64_t) * cap);
+    if (pc) o->pc = pc;
+    uint64_t *pid = (uint64_t *)realloc(o->pid, sizeof(uint64_t) * cap);
+    if (pid) o->pid = pid;
+    if (!px || !pu || !pm || !pc || !pid) return -1;
+    o->cap = cap;
+    return 0;
+}
+
+/* phi = m (1, u, |u|^2 / 2): mass, momentum and energy carried by a particle (K = 0). */
+static void add_phi(double S[5], double m, const double u[3])
+{
+    S[0] += m;
+    S[1] += m * u[0];
+    S[2] += m * u[1];
+    S[3] += m * u[2];
+    S[4] += m * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Free transport of one particle for time ts through the mesh (Sec. 2.3), face to face:  */
+/* exit time over the faces with n.u > 0 other than the entry face, clamped at 0, lowest  */
+/* local index on a tie; t_exit >= t_rem stays in the cell.  Walls: specular mirrors u;    */
+/* diffuse re-emits from the wall Maxwellian (flux-weighted normal component); far-field  */
+/* removes the particle.  Returns 0 (inside), 1 (escaped) or -1 (too many crossings).      */
+/* ------------------------------------------------------------------------------------ */
+int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double ts, uint64_t uid,
+              int64_t step, int64_t *ncross, int64_t *nwall)
+{
+    int64_t c = *cell;
+    int entry = -1;
+    double trem = ts;
+    int bounce = 0;
+    *ncross = 0;
+    for (;;) {
+        double best = INFINITY;
+        int bf = -1;
+        for (int lf = 0; lf < o->cnf[c]; ++lf) {
+            if (lf == entry) continue;
+            const double *n = o->pn + 18 * c + 3 * lf;
+            double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+            if (un > 0.0) {
+                double tt = (o->pd[6 * c + lf] - (n[0] * x[0] + n[1] * x[1] + n[2] * x[2])) / un;
+                if (tt < 0.0) tt = 0.0;
+                if (tt < best) { best = tt; bf = lf; }
+            }
+        }
+        if (bf < 0 || best >= trem) {
+            for (int d = 0; d < 3; ++d) x[d] = x[d] + u[d] * trem;
+            *cell = c;
+            return 0;
+        }
+        for (int d = 0; d < 3; ++d) x[d] = x[d] + u[d] * best;
+        trem = trem - best;
+        if (++*ncross > o->max_cross) { *cell = c; return -1; }
+        int64_t nb = o->cnb[6 * c + bf];
+        if (nb >= 0) {
+            entry = o->cnblf[6 * c + bf];
+            c = nb;
+            continue;
+        }
+        const obc_t *b = o->bc + (-1 - nb);
+        const double *n = o->pn + 18 * c + 3 * bf;
+        if (b->type == BC_SPECULAR) {
+            double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+            for (int d = 0; d < 3; ++d) u[d] = u[d] - 2.0 * un * n[d];
+            entry = bf;
+        } else if (b->type == BC_DIFFUSE) {
+            double eta[4], t1[3], t2[3];
+            draw4(o->seed, uid, step, TAG_WALL, (uint32_t)bounce, o->inst, eta);
+            ++bounce;
+            ++*nwall;
+            face_frame(n, t1, t2);
+            double sq = sqrt(b->Tw);
+            double vn = sqrt(-2.0 * b->Tw * log(eta[0]));
+            double r = sqrt(-2.0 * log(eta[1]));
+            double X1 = r * cos(2.0 * M_PI * eta[2]), X2 = r * sin(2.0 * M_PI * eta[2]);
+            for (int d = 0; d < 3; ++d) u[d] = b->Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+            entry = bf;
+        } else {
+            *cell = c;
+            return 1;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* One time step.                                                                          */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    double dt;
+    double *tau, *ec, *rhoh, *U, *T;
+} cellq_t;
+
+static void cellq_free(cellq_t *q)
+{
+    free(q->tau); free(q->ec); free(q->rhoh); free(q->U); free(q->T);
+}
+
+/* Primitives, relaxation time tau = mu_ref T^omega / p (Eq. tau_via_T_ref, T_ref = 1), the
+ * time step dt = CFL min Omega / sum_d (|U_d| + 3 sqrt(T)) dS_d (Sec. 2.4(a)), the hydro
+ * density rho^h = rho - rho^p clamped at 0, and the collisionless fraction exp(-dt/tau). */
+static int phase_cells(oracle_t *o, cellq_t *q)
+{
+    const int64_t nc = o->nc;
+    q->tau = (double *)xcalloc(nc, sizeof(double));
+    q->ec = (double *)xcalloc(nc, sizeof(double));
+    q->rhoh = (double *)xcalloc(nc, sizeof(double));
+    q->U = (double *)xcalloc(3 * nc, sizeof(double));
+    q->T = (double *)xcalloc(nc, sizeof(double));
+    double dtmin = INFINITY;
+    for (int64_t c = 0; c < nc; ++c) {
+        const double *W = o->W + 5 * c;
+        double rho = W[0];
+        if (!(rho > 0.0) || !isfinite(rho)) return ORC_E_NONPHYS;
+        double U = W[1] / rho, V = W[2] / rho, Z = W[3] / rho;
+        double T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / rho) / rho;
+        if (!(T > 0.0) || !isfinite(T)) return ORC_E_NONPHYS;
+        q->U[3 * c] = U; q->U[3 * c + 1] = V; q->U[3 * c + 2] = Z;
+        q->T[c] = T;
+        q->tau[c] = o->mu_ref * pow(T, o->omega) / (rho * T);
+        double cs = 3.0 * sqrt(T);
+        double lam = (fabs(U) + cs) * o->dS[3 * c] + (fabs(V) + cs) * o->dS[3 * c + 1] +
+                     (fabs(Z) + cs) * o->dS[3 * c + 2];
+        double r = o->vol[c] / lam;
+        if (r < dtmin) dtmin = r;
+    }
+    q->dt = o->cfl * dtmin;
+    for (int64_t c = 0; c < nc; ++c) {
+        double rh = o->W[5 * c] - o->P[5 * c] / o->vol[c];
+        q->rhoh[c] = rh > 0.0 ? rh : 0.0;
+        q->ec[c] = exp(-q->dt / q->tau[c]);
+    }
+    return ORC_OK;
+}
+
+/* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
+ * ones.  Per cell: rho^hp = exp(-dt/tau) rho^h, m_ref = (rho^p + rho^hp) Omega / N_ref,
+ * N_sam = 2 ceil(rho^hp Omega / (2 m_ref)) raised to cover N_min - N_left (rounded up to
+ * even), m_sam = rho^hp Omega / N_sam.  Pair j: X ~ N(0, I) by Box-Muller, velocities
+ * U + sqrt(T) X and U - sqrt(T) X; each partner its own uniform position in the cell.
+ * S (if given) receives the sums of phi over the new particles. */
+static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsampled)
+{
+    *nsampled = 0;
+    for (int64_t c = 0; c < o->nc; ++c) {
+        double rhohp = q->ec[c] * q->rhoh[c];
+        double rhop = o->P[5 * c] / o->vol[c];
+        if (!(rhohp > 0.0) || !(rhop + rhohp > 0.0)) continue;
+        double r = (0.5 * o->n_ref) * (rhohp / (rhop + rhohp));
+        int64_t ns = 2 * (int64_t)ceil(r);
+        int64_t need = (int64_t)o->n_min - o->nleft[c];
+        if (need > 0) {
+            int64_t ne = 2 * ((need + 1) / 2);
+            if (ne > ns) ns = ne;
+        }
+        if (ns > (1 << 20)) return ORC_E_CAPACITY;
+        double msam = rhohp * o->vol[c] / ns;
+        if (reserve(o, o->np + ns)) return ORC_E_CAPACITY;
+        double sT = sqrt(q->T[c]);
+        for (int64_t k = 0; k < ns; ++k) {
+            int64_t i = o->np++;
+            uint64_t uid = orc_make_uid(0, o->step, c, k);
+            uint64_t puid = orc_make_uid(0, o->step, c, k & ~(int64_t)1);
+            double ev[4], ep[4];
+            draw4(o->seed, puid, o->step, TAG_VEL, 0, o->inst, ev);
+            double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
+            double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
+            double sg = (k & 1) ? -1.0 : 1.0;
+            for (int d = 0; d < 3; ++d) o->pu[3 * i + d] = q->U[3 * c + d] + sg * (sT * X[d]);
+            draw4(o->seed, uid, o->step, TAG_POS, 0, o->inst, ep);
+            const double *org = o->orig + 3 * c, *Ed = o->edge + 9 * c;
+            double s = ep[0], t = ep[1], w = ep[2];
+            if (o->ctype[c] == 4) {
+                /* uniform point in a tetrahedron: fold the unit cube (Rocchini & Cignoni 2000) */
+                if (s + t > 1.0) { s = 1.0 - s; t = 1.0 - t; }
+                if (t + w > 1.0) {
+                    double tmp = w;
+                    w = 1.0 - s - t;
+                    t = 1.0 - tmp;
+                } else if (s + t + w > 1.0) {
+                    double tmp = w;
+                    w = s + t + w - 1.0;
+                    s = 1.0 - t - tmp;
+                }
+            }
+            for (int d = 0; d < 3; ++d)
+                o->px[3 * i + d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+            o->pm[i] = msam;
+            o->pc[i] = c;
+            o->pid[i] = uid;
+            if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i);
+        }
+        *nsampled += ns;
+    }
+    return ORC_OK;
+}
+
+/* Test hook: the cell phase and the sampling of the current step only (the new particles are
+ * appended at their sampled positions; nothing streams and the step does not advance). */
+int orc_sample_only(oracle_t *o, double *dt)
+{
+    cellq_t q = {0};
+    int st = phase_cells(o, &q);
+    int64_t ns = 0;
+    if (st == ORC_OK) st = phase_sample(o, &q, NULL, &ns);
+    *dt = q.dt;
+    o->st_sampled = ns;
+    cellq_free(&q);
+    return st;
+}
+
+int orc_step(oracle_t *o)
+{
+    const int64_t nc = o->nc, nf = o->nf;
+    cellq_t q = {0};
+    double *Phi = (double *)xcalloc(5 * nf, sizeof(double));
+    double *S = (double *)xcalloc(5 * nc, sizeof(double));
+    double *E = (double *)xcalloc(5 * nc, sizeof(double));
+    double *Pn = (double *)xcalloc(5 * nc, sizeof(double));
+    int64_t *nl = (int64_t *)xcalloc(nc, sizeof(int64_t));
+    int status = phase_cells(o, &q);
+    if (status != ORC_OK) goto done;
+    const double dt = q.dt;
+    o->st_dt = dt;
+
+    /* wave flux over every face, oriented owner -> neighbour, times the face area */
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t c = o->fown[f], nb = o->fnb[f];
+        const double *n = o->fn + 3 * f;
+        double F[5];
+        if (nb >= 0) {
+            orc_flux_interior(o->W + 5 * c, o->W + 5 * nb, q.rhoh[c], q.rhoh[nb], n, dt, o->mu_ref, o->omega,
+                              o->c2, F);
+        } else {
+            const obc_t *b = o->bc + (-1 - nb);
+            if (b->type == BC_SPECULAR)
+                orc_flux_specular(o->W + 5 * c, q.rhoh[c], n, dt, o->mu_ref, o->omega, o->c2, F);
+            else if (b->type == BC_DIFFUSE)
+                orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, F);
+            else
+                orc_flux_interior(o->W + 5 * c, b->Winf, q.rhoh[c], b->Winf[0], n, dt, o->mu_ref, o->omega,
+                                  o->c2, F);
+        }
+        for (int k = 0; k < 5; ++k) Phi[5 * f + k] = F[k] * o->farea[f];
+    }
+
+    /* particle sums at the start of the step: the particles left from the last step plus the
+       hydro particles sampled now */
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 5; ++k) S[5 * c + k] = o->P[5 * c + k];
+    int64_t nold = o->np;
+    int64_t nsampled = 0;
+    status = phase_sample(o, &q, S, &nsampled);
+    if (status != ORC_OK) goto done;
+    o->st_sampled = nsampled;
+
+    /* free-flight time of every old particle t_f = min(-tau ln eta, dt), with tau of the cell it
+       starts in; new particles fly for dt.  Stream, sum, and delete the collided and escaped. */
+    int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0;
+    for (int64_t i = 0; i < o->np; ++i) {
+        double ts = dt;
+        int collided = 0;
+        if (i < nold) {
+            double eta[4];
+            draw4(o->seed, o->pid[i], o->step, TAG_TF, 0, o->inst, eta);
+            double tf = -q.tau[o->pc[i]] * log(eta[0]);
+            if (tf < dt) { ts = tf; collided = 1; }
+        }
+        int64_t cross = 0;
+        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pc + i, ts, o->pid[i], o->step, &cross, &nwall);
+        ncross_tot += cross;
+        if (rc < 0) { status = ORC_E_LOST; goto done; }
+        if (rc == 1) { ++nesc; continue; }
+        int64_t c = o->pc[i];
+        add_phi(E + 5 * c, o->pm[i], o->pu + 3 * i);
+        if (collided) { ++ncoll; continue; }
+        add_phi(Pn + 5 * c, o->pm[i], o->pu + 3 * i);
+        nl[c] += 1;
+        if (keep != i) {
+            for (int d = 0; d < 3; ++d) { o->px[3 * keep + d] = o->px[3 * i + d]; o->pu[3 * keep + d] = o->pu[3 * i + d]; }
+            o->pm[keep] = o->pm[i];
+            o->pc[keep] = o->pc[i];
+            o->pid[keep] = o->pid[i];
+        }
+        ++keep;
+    }
+    o->np = keep;
+
+    /* conservative update: W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega, where E sums phi
+       over every particle that ends the step in the cell (collided ones where they collided)
+       and S over every particle that started it there (the net particle flux) */
+    for (int64_t c = 0; c < nc; ++c) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int lf = 0; lf < o->cnf[c]; ++lf) {
+            int64_t f = o->cface[6 * c + lf];
+            double s = (double)o->csign[6 * c + lf];
+            for (int k = 0; k < 5; ++k) acc[k] = acc[k] - s * Phi[5 * f + k];
+        }
+        for (int k = 0; k < 5; ++k) {
+            acc[k] = acc[k] + (E[5 * c + k] - S[5 * c + k]);
+            o->W[5 * c + k] = o->W[5 * c + k] + acc[k] / o->vol[c];
+            o->P[5 * c + k] = Pn[5 * c + k];
+        }
+        o->nleft[c] = nl[c];
+    }
+    o->st_collided = ncoll;
+    o->st_escaped = nesc;
+    o->st_alive = keep;
+    o->st_cross = ncross_tot;
+    o->st_wallhits = nwall;
+    o->step += 1;
+    o->t += dt;
+done:
+    cellq_free(&q);
+    free(Phi); free(S); free(E); free(Pn); free(nl);
+    return status;
+}

@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs: meshes, boundary tables, parameters and initial states.
+
+This module holds no arithmetic of the method itself.  It builds the inputs that both the
+GPU library and the CPU oracle consume: unstructured meshes given as node coordinates plus
+cell connectivity (4-node tetrahedra, 8-node axis-aligned boxes in VTK node order),
+tagged boundary faces, a boundary-condition table, solver parameters and the initial
+conservative state W = (rho, rho U, rho E) per cell (R = 1, monatomic, rho E = rho |U|^2/2 +
+3 rho T / 2).
+
+Workloads follow the paper's test cases (Sec. 4): the shock tube in a square column
+(Sec. 4.1), the lid-driven cubic cavity (Sec. 4.2), and the flow past a cube (Sec. 4.3),
+at the sizes of the hot-path configurations described in the design notes.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BC_SPECULAR = 0
+BC_DIFFUSE = 1
+BC_FARFIELD = 2
+
+CELL_TET = 4
+CELL_HEX = 8
+
+# box sides in the order the generators tag them
+SIDES = ("xlo", "xhi", "ylo", "yhi", "zlo", "zhi")
+
+
+@dataclass
+class BC:
+    type: int
+    Tw: float = 1.0
+    Uw: tuple = (0.0, 0.0, 0.0)
+    Winf: tuple = (0.0, 0.0, 0.0, 0.0, 0.0)
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray            # [n_nodes, 3] float64
+    cell_type: np.ndarray      # [n_cells] uint8 (4 or 8)
+    cell_node_off: np.ndarray  # [n_cells + 1] int64
+    cell_nodes: np.ndarray     # [sum nodes] int64
+    bface_nodes: np.ndarray    # [n_bfaces, 4] int64, -1 pads a triangle
+    bface_bc: np.ndarray       # [n_bfaces] int32, index into bcs
+    bcs: list = field(default_factory=list)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_type.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def bc_arrays(self):
+        t = np.array([b.type for b in self.bcs], dtype=np.int32)
+        tw = np.array([b.Tw for b in self.bcs], dtype=np.float64)
+        uw = np.array([b.Uw for b in self.bcs], dtype=np.float64).reshape(-1, 3)
+        wi = np.array([b.Winf for b in self.bcs], dtype=np.float64).reshape(-1, 5)
+        return t, tw, np.ascontiguousarray(uw), np.ascontiguousarray(wi)
+
+
+@dataclass
+class Params:
+    mu_ref: float
+    omega: float = 0.81
+    cfl: float = 0.5
+    c2: float = 0.0
+    n_ref: int = 200
+    n_min: int = 0
+    max_crossings: int = 1000
+    seed: int = 1
+    gamma: float = 5.0 / 3.0
+
+
+def mu_ref_from_kn(kn: float, omega: float) -> float:
+    """Reference viscosity of a VHS gas for a Knudsen number at rho = T = L = 1 (R = 1)."""
+    return 15.0 * math.sqrt(2.0 * math.pi) * kn / (2.0 * (5.0 - 2.0 * omega) * (7.0 - 2.0 * omega))
+
+
+def conservative(rho, U, T):
+    """W = (rho, rho U, rho E) for a monatomic gas with R = 1; rho E = rho |U|^2/2 + 3/2 rho T."""
+    rho = np.asarray(rho, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    W = np.empty(rho.shape + (5,), dtype=np.float64)
+    W[..., 0] = rho
+    W[..., 1:4] = rho[..., None] * U
+    W[..., 4] = 0.5 * rho * (U * U).sum(-1) + 1.5 * rho * T
+    return W
+
+
+# --------------------------------------------------------------------------------------
+# box-hex meshes
+# --------------------------------------------------------------------------------------
+def _axis_nodes(lo, hi, n, grading=None):
+    if grading is None:
+        return np.linspace(lo, hi, n + 1)
+    return np.asarray(grading, dtype=np.float64)
+
+
+def box_hex_mesh(n, lo, hi, side_bc, bcs, coords=None) -> Mesh:
+    """Structured box of axis-aligned hexahedra given as unstructured connectivity.
+
+    n: (nx, ny, nz); lo, hi: corners; side_bc: dict side name -> index into bcs;
+    coords: optional explicit node coordinates per axis (graded meshes).
+    Cells are numbered x fastest, then y, then z.
+    """
+    nx, ny, nz = n
+    ax = [coords[a] if coords is not None else _axis_nodes(lo[a], hi[a], n[a]) for a in range(3)]
+    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(), Z.transpose(2, 1, 0).ravel()], 1)
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i = i.transpose(2, 1, 0).ravel()
+    j = j.transpose(2, 1, 0).ravel()
+    k = k.transpose(2, 1, 0).ravel()
+    corners = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+    cn = np.stack([nid(i + a, j + b, k + c) for (a, b, c) in corners], 1).astype(np.int64)
+    nc = cn.shape[0]
+    bf, bt = _box_boundary(n, nid, side_bc)
+    return Mesh(xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+                cell_type=np.full(nc, CELL_HEX, dtype=np.uint8),
+                cell_node_off=np.arange(0, 8 * nc + 1, 8, dtype=np.int64),
+                cell_nodes=cn.ravel(), bface_nodes=bf, bface_bc=bt, bcs=list(bcs))
+
+
+def _box_boundary(n, nid, side_bc, tri_split=False):
+    nx, ny, nz = n
+    faces, tags = [], []
+
+    def quad(p, q, r, s, tag):
+        if tri_split:
+            # Kuhn split: the diagonal of each boundary quad runs through its lowest and highest
+            # corner (p and r in the order given), which matches the tetrahedra of tet_box_mesh
+            faces.append((p, q, r, -1)); tags.append(tag)
+            faces.append((p, r, s, -1)); tags.append(tag)
+        else:
+            faces.append((p, q, r, s)); tags.append(tag)
+
+    for jj in range(ny):
+        for kk in range(nz):
+            quad(nid(0, jj, kk), nid(0, jj + 1, kk), nid(0, jj + 1, kk + 1), nid(0, jj, kk + 1), side_bc["xlo"])
+            quad(nid(nx, jj, kk), nid(nx, jj + 1, kk), nid(nx, jj + 1, kk + 1), nid(nx, jj, kk + 1), side_bc["xhi"])
+    for ii in range(nx):
+        for kk in range(nz):
+            quad(nid(ii, 0, kk), nid(ii + 1, 0, kk), nid(ii + 1, 0, kk + 1), nid(ii, 0, kk + 1), side_bc["ylo"])
+            quad(nid(ii, ny, kk), nid(ii + 1, ny, kk), nid(ii + 1, ny, kk + 1), nid(ii, ny, kk + 1), side_bc["yhi"])
+    for ii in range(nx):
+        for jj in range(ny):
+            quad(nid(ii, jj, 0), nid(ii + 1, jj, 0), nid(ii + 1, jj + 1, 0), nid(ii, jj + 1, 0), side_bc["zlo"])
+            quad(nid(ii, jj, nz), nid(ii + 1, jj, nz), nid(ii + 1, jj + 1, nz), nid(ii, jj + 1, nz), side_bc["zhi"])
+    return np.array(faces, dtype=np.int64).reshape(-1, 4), np.array(tags, dtype=np.int32)
+
+
+# Kuhn (Freudenthal) split of a box into 6 tetrahedra along the diagonal from corner 0 to
+# corner 6: one tetrahedron per ordering of the three axes.  Conforming between neighbours.
+_KUHN = []
+for _perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+    _b = [0, 0, 0]
+    _path = [tuple(_b)]
+    for _a in _perm:
+        _b[_a] = 1
+        _path.append(tuple(_b))
+    _KUHN.append(_path)
+
+
+def tet_box_mesh(n, lo, hi, side_bc, bcs, jitter=0.0, seed=1, coords=None) -> Mesh:
+    """Box of hexahedra, each split into 6 tetrahedra (Kuhn split along the 0-6 diagonal).
+
+    jitter: interior nodes move uniformly within +-jitter*h per axis (h: local spacing),
+    seeded; boundary nodes stay on their planes (they move only within them).
+    """
+    nx, ny, nz = n
+    ax = [coords[a] if coords is not None else _axis_nodes(lo[a], hi[a], n[a]) for a in range(3)]
+    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(), Z.transpose(2, 1, 0).ravel()], 1)
+    if jitter > 0.0:
+        rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x4D455348], dtype=np.uint64)))
+        for a in range(3):
+            h = np.diff(ax[a])
+            hloc = np.minimum(np.concatenate([[h[0]], h]), np.concatenate([h, [h[-1]]]))
+            idx = [np.arange(n[0] + 1), np.arange(n[1] + 1), np.arange(n[2] + 1)]
+            I, J, K = np.meshgrid(*idx, indexing="ij")
+            I = I.transpose(2, 1, 0).ravel(); J = J.transpose(2, 1, 0).ravel(); K = K.transpose(2, 1, 0).ravel()
+            pos = (I, J, K)[a]
+            inner = (pos > 0) & (pos < n[a])
+            d = rng.uniform(-jitter, jitter, size=xyz.shape[0]) * hloc[pos]
+            xyz[:, a] = np.where(inner, xyz[:, a] + d, xyz[:, a])
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i = i.transpose(2, 1, 0).ravel(); j = j.transpose(2, 1, 0).ravel(); k = k.transpose(2, 1, 0).ravel()
+    tets = []
+    for path in _KUHN:
+        tets.append(np.stack([nid(i + a, j + b, k + c) for (a, b, c) in path], 1))
+    cn = np.stack(tets, 1).reshape(-1, 4).astype(np.int64)
+    nc = cn.shape[0]
+    bf, bt = _box_boundary(n, nid, side_bc, tri_split=True)
+    return Mesh(xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+                cell_type=np.full(nc, CELL_TET, dtype=np.uint8),
+                cell_node_off=np.arange(0, 4 * nc + 1, 4, dtype=np.int64),
+                cell_nodes=cn.ravel(), bface_nodes=bf, bface_bc=bt, bcs=list(bcs))
+
+
+def cell_centroids(mesh: Mesh) -> np.ndarray:
+    """Node average per cell (inputs only: used to place initial states)."""
+    off = mesh.cell_node_off
+    nn = np.diff(off)
+    out = np.zeros((mesh.n_cells, 3))
+    for k in np.unique(nn):
+        sel = np.nonzero(nn == k)[0]
+        idx = mesh.cell_nodes[off[sel][:, None] + np.arange(k)[None, :]]
+        out[sel] = mesh.xyz[idx].mean(1)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    params: Params
+    W0: np.ndarray  # [n_cells, 5]
+    steps: int
+
+
+def sod(nx=50, ny=2, nz=2, n_ref=200, kn=1e-3, cfl=0.5, steps=40, seed=1, tets=False) -> Workload:
+    """Shock tube in a square column (paper Sec. 4.1) at the hot-path size: [0,1]x[0,0.04]^2,
+    monatomic, rho = 1, p = 1 left of x = 0.5 and rho = 0.125, p = 0.1 right; all walls specular."""
+    h = 1.0 / nx
+    lo, hi = (0.0, 0.0, 0.0), (1.0, ny * h, nz * h)
+    bcs = [BC(BC_SPECULAR)]
+    side = {s: 0 for s in SIDES}
+    mesh = (tet_box_mesh if tets else box_hex_mesh)((nx, ny, nz), lo, hi, side, bcs)
+    xc = cell_centroids(mesh)
+    left = xc[:, 0] < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    W0 = conservative(rho, np.zeros((mesh.n_cells, 3)), p / rho)
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    return Workload("sod", mesh, prm, W0, steps)
+
+
+def cavity(n=32, n_ref=400, kn=0.075, cfl=0.95, steps=2000, seed=1, Tw=1.0) -> Workload:
+    """Lid-driven cubic cavity (paper Sec. 4.2) at the hot-path size: unit cube, n^3 boxes,
+    diffuse isothermal walls at T_w, lid z = 1 moving at U = (0.16 sqrt(gamma T_w), 0, 0)."""
+    lid = 0.16 * math.sqrt(5.0 / 3.0 * Tw)
+    bcs = [BC(BC_DIFFUSE, Tw=Tw), BC(BC_DIFFUSE, Tw=Tw, Uw=(lid, 0.0, 0.0))]
+    side = {s: 0 for s in SIDES}
+    side["zhi"] = 1
+    mesh = box_hex_mesh((n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), side, bcs)
+    nc = mesh.n_cells
+    W0 = conservative(np.ones(nc), np.zeros((nc, 3)), np.ones(nc))
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    return Workload("cavity", mesh, prm, W0, steps)
+
+
+def closed_box(n=(4, 3, 2), n_ref=50, kn=0.05, cfl=0.5, seed=7, bc=BC_SPECULAR, perturb=0.2, tets=False,
+               jitter=0.0) -> Workload:
+    """Small closed box with a seeded non-uniform initial state (for conservation checks)."""
+    bcs = [BC(bc, Tw=1.0)]
+    side = {s: 0 for s in SIDES}
+    if tets:
+        mesh = tet_box_mesh(n, (0.0, 0.0, 0.0), (1.0, 0.75, 0.5), side, bcs, jitter=jitter, seed=seed)
+    else:
+        mesh = box_hex_mesh(n, (0.0, 0.0, 0.0), (1.0, 0.75, 0.5), side, bcs)
+    rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x57415445], dtype=np.uint64)))
+    nc = mesh.n_cells
+    rho = 1.0 + perturb * rng.uniform(-1, 1, nc)
+    U = 0.3 * perturb * rng.uniform(-1, 1, (nc, 3))
+    T = 1.0 + perturb * rng.uniform(-1, 1, nc)
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    return Workload("closed_box", mesh, prm, conservative(rho, U, T), 10)
