@@ -41,6 +41,9 @@
 #define ORC_E_NONPHYS 5
 
 enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2 };
+
+/* relative floor of the hydro density rho^h = rho - rho^p (see phase_cells) */
+#define RHOH_EPS 1e-12
 enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5 };
 
 /* ------------------------------------------------------------------------------------ */
@@ -805,8 +808,11 @@ static int phase_cells(oracle_t *o, cellq_t *q)
     }
     q->dt = o->cfl * dtmin;
     for (int64_t c = 0; c < nc; ++c) {
+        /* rho^h = rho - rho^p is a difference of two sums; below 1e-12 rho it is roundoff of
+           that subtraction (e.g. free-molecular cells where the particles hold all the mass)
+           and counts as an empty hydro part */
         double rh = o->W[5 * c] - o->P[5 * c] / o->vol[c];
-        q->rhoh[c] = rh > 0.0 ? rh : 0.0;
+        q->rhoh[c] = rh > RHOH_EPS * o->W[5 * c] ? rh : 0.0;
         q->ec[c] = exp(-q->dt / q->tau[c]);
     }
     return ORC_OK;
