@@ -1,0 +1,162 @@
+"""Benchmark of the UGKWP hot path on one MI355X.
+
+Workload: the lid-driven cubic cavity (paper Sec. 4.2) at the hot-path size: unit cube of
+32^3 box hexes, diffuse isothermal walls at T_w = 1, lid z = 1 moving at 0.16 sqrt(gamma T_w),
+Kn 0.075 (VHS, omega = 0.81), 400 particles per cell (about 1.3e7 particles), CFL 0.95,
+synthetic initial state (gas at rest).  A step is one full time step of the scheme: wave
+flux, sampling, free-flight times, free transport, particle sums and the cell update.
+
+Prints ONE JSON line: particle moves/s (value) and cell-steps/s, the dominant kernel's
+roofline position (timed live with hip events on the library's stream), and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# algorithmic bytes of one particle move (FP64 state x, u, m, cell, uid read once and written once)
+BYTES_PER_MOVE_FP64 = 136
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2007_13091_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs, if the kernel
+    source has not changed since they were taken (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(kernel)
+    if not e or e.get("source_digest") != kernel_source_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(steps=3):
+    """The oracle as it stands, single-threaded, on the same workload from the same initial
+    state: the first `steps` steps (the first samples every particle, the rest are typical)."""
+    import oracle
+    from paper_2007_13091_amd import workloads as wl
+
+    w = wl.cavity()
+    o = oracle.Oracle(w.mesh, w.params)
+    o.set_state(w.W0)
+    moved = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step()
+        st = o.stats()
+        moved += st["n_alive"] + st["n_collided"] + st["n_escaped"]
+    el = time.perf_counter() - t0
+    return {"value": moved / el, "unit": "particle moves/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {steps} steps of the 32^3 cavity (400 particles/cell) from the initial state, "
+                      f"{moved} particle moves in {el:.1f} s; cell-steps/s {steps * w.mesh.n_cells / el:.3g}"}
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(no multi-GPU path is built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.cavity()
+    s = Solver(w.mesh, w.params)
+    s.init_state(w.W0)
+    st0 = s.step(max(args.warmup, 1), stats=True)
+    moved0 = st0["moved_total"]
+    s.profile(True)
+    s.profile_read()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.step(0, stats=True)
+    prof = s.profile_read()
+    s.profile(False)
+    el = t1 - t0
+    moves = st1["moved_total"] - moved0
+    nc = w.mesh.n_cells
+    value = moves / el
+    # dominant kernel: the slot with the largest summed time
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    moves_per_launch = moves / args.steps
+    achieved = BYTES_PER_MOVE_FP64 * moves_per_launch / (avg_ms * 1e-3) / 1e9
+    kname = {"stream": "k_stream", "gather": "k_gather"}.get(dom, dom)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
+            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": int(BYTES_PER_MOVE_FP64 * moves_per_launch)}
+    out = {
+        "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
+        "value": value,
+        "unit": "particle moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "lid-driven cavity, 32^3 box hexes, 400 particles/cell, Kn 0.075, diffuse walls, "
+                               "lid 0.16 sqrt(gamma T_w); FP64 plain form",
+                   "cells": nc, "faces": int(w.mesh.n_cells * 3 + 3 * 32 * 32), "particles_per_step": int(moves_per_launch)},
+        "cell_steps_per_s": nc * args.steps / el,
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

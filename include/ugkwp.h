@@ -1,0 +1,170 @@
+/*
+ * ugkwp.h -- C ABI of the MI355X (gfx950) hot path of the unified gas-kinetic wave-particle
+ * (UGKWP) method on unstructured meshes (Chen, Zhu & Xu, arXiv 2007.13091).
+ *
+ * One call of ugkwp_step advances the state by one time step of the scheme of Sec. 2:
+ *   S0 primitives, tau = mu/p and the CFL time step                  (Sec. 2.4(a))
+ *   S2 wave flux F^eq + F^{fr,wave} over every face                  (Sec. 2.2, Sec. 2.4)
+ *   S3 sampling of hydro particles from the Maxwellian of W^h         (Sec. 2.3, Sec. 2.4(b))
+ *   S4 free-flight time t_f = min(-tau ln eta, dt) of each particle   (Eq. for t_f, Sec. 2.3)
+ *   S5 face-to-face free transport with wall reflection              (Sec. 2.3, Sec. 2.4(e))
+ *   S6 net particle flux, conservative update, removal of collided    (Eq. update_macro_variables)
+ *      particles and new particle sums W^p
+ * All of it runs in HIP kernels on the caller's stream.
+ *
+ * Units: R = 1 (p = rho T, lambda = 1/(2T)); monatomic gas (gamma = 5/3, K = 0).
+ * Conservative state per cell, per unit volume: W = (rho, rho U, rho V, rho W, rho E) with
+ * rho E = rho |U|^2 / 2 + 3 rho T / 2.
+ *
+ * Memory and ownership.  Host arrays passed in are copied during the call and never
+ * retained.  All device memory the library uses lives in ONE caller-owned device buffer
+ * (the workspace) whose size ugkwp_workspace_bytes reports; the caller keeps it alive
+ * until ugkwp_destroy.  ugkwp_init_mesh carves it; no other call allocates device memory.
+ * Every device operation is ordered on the hip stream given to ugkwp_init_mesh.
+ *
+ * Errors.  Every function returns a ugkwp_status and never aborts.  Host-detectable errors
+ * return at once.  Errors found on the device (capacity, lost particle, non-physical
+ * state) are recorded in a device error word and reported by the next call that
+ * synchronises (ugkwp_step with stats, ugkwp_moments, ugkwp_export_particles); after such an
+ * error the context refuses ugkwp_step (UGKWP_E_STATE) until ugkwp_init_state is called.
+ * ugkwp_last_error gives a message for the last failure.
+ */
+#ifndef UGKWP_H
+#define UGKWP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ugkwp_ctx ugkwp_ctx; /* opaque */
+
+typedef enum {
+    UGKWP_OK = 0,
+    UGKWP_E_ARG = 1,      /* invalid argument or unsupported option */
+    UGKWP_E_MESH = 2,     /* unmatched face, untagged boundary face, bad cell, ... */
+    UGKWP_E_CAPACITY = 3, /* particle capacity or a per-cell limit exceeded */
+    UGKWP_E_LOST = 4,     /* a particle exceeded max_crossings face crossings in one step */
+    UGKWP_E_NONPHYS = 5,  /* rho <= 0, T <= 0 or a non-finite value in a cell */
+    UGKWP_E_DEVICE = 6,   /* a HIP runtime call failed */
+    UGKWP_E_STATE = 7     /* wrong call order, or the context is poisoned by an earlier error */
+} ugkwp_status;
+
+typedef enum {
+    UGKWP_BC_SPECULAR = 0, /* symmetry plane / specular wall (Sec. 4.1) */
+    UGKWP_BC_DIFFUSE = 1,  /* diffuse isothermal wall at T_w moving at U_w (Sec. 2.4(e)) */
+    UGKWP_BC_FARFIELD = 2  /* free stream W_inf; particles leaving are removed */
+} ugkwp_bc_type;
+
+typedef struct {
+    int32_t type;   /* ugkwp_bc_type */
+    double T_w;     /* wall temperature (diffuse) */
+    double U_w[3];  /* wall velocity, tangential to the wall (diffuse) */
+    double W_inf[5];/* free-stream conservative state (far field) */
+} ugkwp_bc;
+
+/* One mesh, host arrays.  Cells: 4-node tetrahedra (type 4) or 8-node axis-aligned boxes
+ * (type 8) in VTK node order.  Boundary faces: node lists of 4 (a triangle pads with -1),
+ * each tagged with an index into bc[].  Every cell face not shared by two cells must be a
+ * tagged boundary face. */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;            /* [n_nodes][3] */
+    int64_t n_cells;              /* at most 2^24 (particle ids carry the birth cell) */
+    const uint8_t *cell_type;     /* [n_cells] */
+    const int64_t *cell_node_off; /* [n_cells + 1] */
+    const int64_t *cell_nodes;    /* [cell_node_off[n_cells]] */
+    int64_t n_bfaces;
+    const int64_t *bface_nodes;   /* [n_bfaces][4] */
+    const int32_t *bface_bc;      /* [n_bfaces] */
+    int32_t n_bc;
+    const ugkwp_bc *bc;           /* [n_bc] */
+} ugkwp_mesh;
+
+typedef struct {
+    double gamma;         /* must be 5/3 (monatomic) */
+    double mu_ref;        /* tau = mu_ref T^omega / p  (T_ref = 1), Eq. tau_via_T_ref */
+    double omega;
+    double cfl;           /* C in dt = C min Omega / (Lambda^x + Lambda^y + Lambda^z) */
+    double c2;            /* numerical-dissipation constant C2 of Sec. 2.4(d) (0 = off) */
+    int32_t n_ref;        /* reference particle number per cell, Sec. 2.4(b) */
+    int32_t n_min;        /* minimum particle number per cell, Sec. 2.4(b) */
+    int32_t recon;        /* 0 = first order (only value supported) */
+    int32_t precision;    /* 0 = FP64 throughout (only value supported) */
+    int64_t capacity;     /* particle capacity (0 = library default from n_ref and n_cells) */
+    int32_t max_crossings;/* face crossings allowed per particle per step */
+    uint64_t seed;        /* Philox4x64-10 key word 0 */
+} ugkwp_params;
+
+typedef struct {
+    double dt, t;          /* time step just taken, time after it */
+    int64_t step;          /* steps taken since ugkwp_init_state */
+    int64_t n_alive;       /* particles left after the step */
+    int64_t n_sampled;     /* hydro particles sampled in the step */
+    int64_t n_collided;    /* particles removed as collided */
+    int64_t n_escaped;     /* particles removed at far-field faces */
+    int64_t n_moved;       /* particles streamed in the step (old + sampled) */
+    int64_t crossings;     /* face crossings in the step */
+    int64_t wall_hits;     /* diffuse re-emissions in the step */
+    uint32_t error_word;   /* device error bits (0 = none) */
+    int64_t moved_total;   /* particles streamed since ugkwp_init_state (sum of n_moved) */
+} ugkwp_step_stats;
+
+/* Device bytes needed for one mesh with these parameters.  Host-side only (no device call). */
+int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, const ugkwp_params *p, size_t *bytes);
+
+/* Validate the mesh, match faces, compute the geometry (Sec. 2.2 cells, faces, normals,
+ * areas, the projections Delta S of Sec. 2.4(a)), carve the workspace and upload.
+ * dev_workspace: device pointer of at least ugkwp_workspace_bytes bytes, 256-byte aligned.
+ * hip_stream: a hipStream_t (NULL = the default stream).  On success *ctx owns host-side
+ * bookkeeping only; free it with ugkwp_destroy. */
+int32_t ugkwp_init_mesh(ugkwp_ctx **ctx, const ugkwp_mesh *m, const ugkwp_params *p,
+                        void *dev_workspace, size_t ws_bytes, void *hip_stream);
+
+/* Set the conservative state W0 (host, [n_cells][5]); no particles (W^p = 0), step = 0, t = 0. */
+int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0);
+
+/* Advance n_steps time steps.  stats == NULL: asynchronous (nothing waits for the device).
+ * stats != NULL: waits for the stream and fills the statistics of the last step. */
+int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats);
+
+/* Copy a cell field out, [n_cells][5] doubles: which = 0 W, 1 W^p = P/Omega (particle part),
+ * 2 W^h = W - W^p, 3 primitives (rho, U, V, W, T).  out is host memory unless
+ * out_is_device != 0.  Synchronises the stream. */
+int32_t ugkwp_moments(ugkwp_ctx *ctx, int32_t which, double *out, int32_t out_is_device);
+
+/* Number of particles currently held (synchronises). */
+int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n);
+
+/* Copy the particles out to host arrays sized by ugkwp_particle_count:
+ * x [n][3], u [n][3], m [n], cell [n] (int32), uid [n].  Order: grouped by cell.
+ * Any pointer may be NULL to skip that field.  Synchronises. */
+int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell,
+                               uint64_t *uid);
+
+/* Per-cell geometry as the library computed it: volume [n_cells], centroid [n_cells][3],
+ * projections Delta S [n_cells][3] (host arrays). */
+int32_t ugkwp_geometry(ugkwp_ctx *ctx, double *vol, double *xc, double *dS);
+
+/* Measurement support.  While enabled, each group of kernel launches of ugkwp_step is
+ * bracketed by hip events recorded on the library's stream.  ugkwp_profile_read waits for
+ * the stream, writes the summed elapsed milliseconds and the number of timed groups for the
+ * first n_slots slots (see ugkwp_profile_slot_name; slot 5 is the free-transport kernel),
+ * and clears the sums.  Either output pointer may be NULL. */
+int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on);
+int32_t ugkwp_profile_read(ugkwp_ctx *ctx, int32_t n_slots, double *total_ms, int64_t *launches);
+/* Name of a profiling slot ("" if out of range); static storage. */
+const char *ugkwp_profile_slot_name(int32_t slot);
+
+/* Message for the last failure on this context (or of init when ctx is NULL). */
+const char *ugkwp_last_error(const ugkwp_ctx *ctx);
+
+/* Release the host-side context (the caller frees the workspace afterwards). */
+void ugkwp_destroy(ugkwp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UGKWP_H */

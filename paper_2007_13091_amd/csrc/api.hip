@@ -1,0 +1,486 @@
+// C ABI of the UGKWP library (declared in include/ugkwp.h): argument checks, workspace
+// carving, uploads and the per-step launch sequence on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+#include "mesh_prep.hpp"
+#include "ugkwp.h"
+
+using ugkwp::Dev;
+using ugkwp::DevBC;
+using ugkwp::HostMesh;
+using ugkwp::Scalars;
+
+namespace {
+// Measurement support: hip events bracket each group of kernel launches of a step on the
+// library's stream; elapsed times are summed when read.
+struct EventProf : ugkwp::Prof {
+    hipStream_t s = nullptr;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ugkwp::kNumSlots];
+    hipEvent_t open[ugkwp::kNumSlots] = {};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(int slot) override {
+        if (!on) return;
+        hipEvent_t e = get();
+        if (e) (void)hipEventRecord(e, s);
+        open[slot] = e;
+    }
+    void end(int slot) override {
+        if (!on || !open[slot]) return;
+        hipEvent_t e = get();
+        if (!e) return;
+        (void)hipEventRecord(e, s);
+        pending[slot].emplace_back(open[slot], e);
+        open[slot] = nullptr;
+    }
+    // sums (ms) and counts per slot; recycles the events
+    void drain(double *ms, int64_t *cnt, int n) {
+        for (int k = 0; k < ugkwp::kNumSlots; ++k) {
+            double acc = 0.0;
+            for (auto &pr : pending[k]) {
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) acc += t;
+                pool.push_back(pr.first);
+                pool.push_back(pr.second);
+            }
+            if (k < n) {
+                if (ms) ms[k] = acc;
+                if (cnt) cnt[k] = (int64_t)pending[k].size();
+            }
+            pending[k].clear();
+        }
+    }
+    ~EventProf() override {
+        for (auto &v : pending)
+            for (auto &pr : v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep", "scan_sample", "flux", "sample",
+                                             "stream", "scan_buckets", "scatter", "gather", "finalize"};
+}  // namespace
+
+struct ugkwp_ctx {
+    EventProf prof;
+    HostMesh H;
+    ugkwp_params p{};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Dev D{};
+    int buf = 0;
+    int gather_bs = 256;
+    bool have_state = false;
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+// Lay the workspace out; with base == nullptr only the size is computed.
+size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
+    Carver C{base};
+    const size_t nc = (size_t)H.nc, nf = (size_t)H.nf, nbc = H.bcs.size() ? H.bcs.size() : 1;
+    D.vol = C.take<double>(nc);
+    D.dS = C.take<double>(3 * nc);
+    D.orig = C.take<double>(3 * nc);
+    D.edge = C.take<double>(9 * nc);
+    D.nfc = C.take<uint8_t>(nc);
+    D.ctype = C.take<uint8_t>(nc);
+    D.plane = C.take<double4>(6 * nc);
+    D.nbl = C.take<int2>(6 * nc);
+    D.cface = C.take<int32_t>(6 * nc);
+    D.fown = C.take<int32_t>(nf);
+    D.fnb = C.take<int32_t>(nf);
+    D.fn = C.take<double>(3 * nf);
+    D.farea = C.take<double>(nf);
+    D.bc = C.take<DevBC>(nbc);
+    D.W = C.take<double>(5 * nc);
+    D.P = C.take<double>(5 * nc);
+    D.nleft = C.take<int32_t>(nc);
+    D.tau = C.take<double>(nc);
+    D.ec = C.take<double>(nc);
+    D.rhoh = C.take<double>(nc);
+    D.Phi = C.take<double>(5 * nf);
+    D.S = C.take<double>(5 * nc);
+    D.nsam = C.take<long long>(nc);
+    D.samoff = C.take<long long>(nc + 1);
+    D.scan64 = C.take<long long>((size_t)ugkwp::scan_partials_needed((long long)nc));
+    D.cnt = C.take<int32_t>(2 * nc);
+    D.off = C.take<int32_t>(2 * nc + 1);
+    D.cursor = C.take<int32_t>(2 * nc);
+    D.scan32 = C.take<int32_t>((size_t)ugkwp::scan_partials_needed(2 * (long long)nc));
+    D.key = C.take<int32_t>((size_t)cap);
+    D.perm = C.take<int32_t>((size_t)cap);
+    for (int b = 0; b < 2; ++b) {
+        ugkwp::Particles &P = D.pa[b];
+        P.x0 = C.take<double>((size_t)cap);
+        P.x1 = C.take<double>((size_t)cap);
+        P.x2 = C.take<double>((size_t)cap);
+        P.u0 = C.take<double>((size_t)cap);
+        P.u1 = C.take<double>((size_t)cap);
+        P.u2 = C.take<double>((size_t)cap);
+        P.m = C.take<double>((size_t)cap);
+        P.cell = C.take<int32_t>((size_t)cap);
+        P.uid = C.take<uint64_t>((size_t)cap);
+    }
+    D.sc = C.take<Scalars>(1);
+    return (C.off + 255) & ~size_t(255);
+}
+
+int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::string &err) {
+    if (!(std::fabs(p.gamma - 5.0 / 3.0) < 1e-12)) {
+        err = "params: only the monatomic gas (gamma = 5/3) is implemented";
+        return UGKWP_E_ARG;
+    }
+    if (!(p.mu_ref > 0.0) || !std::isfinite(p.omega) || !(p.cfl > 0.0 && p.cfl <= 1.0) || !(p.c2 >= 0.0)) {
+        err = "params: need mu_ref > 0, finite omega, 0 < cfl <= 1, c2 >= 0";
+        return UGKWP_E_ARG;
+    }
+    if (p.n_ref < 1 || p.n_ref > (1 << 20) || p.n_min < 0 || p.n_min > (1 << 20) || p.max_crossings < 1) {
+        err = "params: need 1 <= n_ref <= 2^20, 0 <= n_min <= 2^20, max_crossings >= 1";
+        return UGKWP_E_ARG;
+    }
+    if (p.recon != 0 || p.precision != 0) {
+        err = "params: only first-order reconstruction (recon 0) in FP64 (precision 0) is built";
+        return UGKWP_E_ARG;
+    }
+    long long c = p.capacity;
+    if (c == 0) {
+        long long per = (long long)(p.n_ref > p.n_min ? p.n_ref : p.n_min);
+        c = 2 * per * (long long)nc + 65536;
+    }
+    if (c < 1 || c > 2147483647LL - 1024) {
+        err = "params: capacity must fit in a 32-bit particle index";
+        return UGKWP_E_ARG;
+    }
+    cap = c;
+    return UGKWP_OK;
+}
+
+int32_t fail(ugkwp_ctx *ctx, int32_t code, const std::string &msg) {
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail((ctx), UGKWP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t up(T *dst, const std::vector<T> &src, hipStream_t s) {
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// [n][k] row-major host array -> [k][n] column-major
+std::vector<double> soa(const std::vector<double> &a, size_t n, size_t k) {
+    std::vector<double> o(n * k);
+    for (size_t i = 0; i < n; ++i)
+        for (size_t j = 0; j < k; ++j) o[j * n + i] = a[i * k + j];
+    return o;
+}
+
+int32_t device_error_code(uint32_t e) {
+    if (e & ugkwp::kErrNonPhys) return UGKWP_E_NONPHYS;
+    if (e & ugkwp::kErrLost) return UGKWP_E_LOST;
+    if (e & (ugkwp::kErrCapacity | ugkwp::kErrCellCount)) return UGKWP_E_CAPACITY;
+    return UGKWP_OK;
+}
+
+std::string device_error_text(uint32_t e) {
+    std::string s = "device error:";
+    if (e & ugkwp::kErrNonPhys) s += " non-physical cell state (rho <= 0 or T <= 0);";
+    if (e & ugkwp::kErrLost) s += " a particle exceeded max_crossings;";
+    if (e & ugkwp::kErrCapacity) s += " particle capacity exceeded;";
+    if (e & ugkwp::kErrCellCount) s += " more than 2^20 particles sampled in one cell;";
+    return s;
+}
+
+int32_t read_scalars(ugkwp_ctx *ctx, Scalars &s) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(&s, ctx->D.sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+    if (s.err) {
+        ctx->poisoned = true;
+        return fail(ctx, device_error_code(s.err), device_error_text(s.err));
+    }
+    return UGKWP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, const ugkwp_params *p, size_t *bytes) {
+    if (!m || !p || !bytes) return fail(nullptr, UGKWP_E_ARG, "null argument");
+    HostMesh H;
+    std::string err;
+    int32_t st = ugkwp::prepare_mesh(*m, H, err);
+    if (st != UGKWP_OK) return fail(nullptr, st, err);
+    long long cap = 0;
+    st = check_params(*p, H.nc, cap, err);
+    if (st != UGKWP_OK) return fail(nullptr, st, err);
+    Dev D{};
+    *bytes = carve(H, cap, D, nullptr);
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params *p, void *dev_workspace,
+                        size_t ws_bytes, void *hip_stream) {
+    if (!out || !m || !p || !dev_workspace) return fail(nullptr, UGKWP_E_ARG, "null argument");
+    *out = nullptr;
+    if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, UGKWP_E_ARG, "workspace must be 256-byte aligned");
+    ugkwp_ctx *ctx = new ugkwp_ctx();
+    std::string err;
+    int32_t st = ugkwp::prepare_mesh(*m, ctx->H, err);
+    long long cap = 0;
+    if (st == UGKWP_OK) st = check_params(*p, ctx->H.nc, cap, err);
+    if (st != UGKWP_OK) {
+        delete ctx;
+        return fail(nullptr, st, err);
+    }
+    ctx->p = *p;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->prof.s = ctx->stream;
+    ctx->ws = (char *)dev_workspace;
+    ctx->ws_bytes = ws_bytes;
+    Dev &D = ctx->D;
+    size_t need = carve(ctx->H, cap, D, ctx->ws);
+    if (ws_bytes < need) {
+        delete ctx;
+        return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    const HostMesh &H = ctx->H;
+    D.nc = H.nc;
+    D.nf = H.nf;
+    D.nbc = (int32_t)H.bcs.size();
+    D.mu_ref = p->mu_ref;
+    D.omega = p->omega;
+    D.cfl = p->cfl;
+    D.c2 = p->c2;
+    D.n_ref = p->n_ref;
+    D.n_min = p->n_min;
+    D.max_cross = p->max_crossings;
+    D.seed = p->seed;
+    D.cap = cap;
+    // a 64-wide block per cell where cells hold few particles, 256 otherwise
+    ctx->gather_bs = (p->n_ref > 128 || p->n_min > 128) ? 256 : 64;
+
+    hipStream_t s = ctx->stream;
+    const size_t nc = (size_t)H.nc, nf = (size_t)H.nf;
+    std::vector<double> dS = soa(H.dS, nc, 3), org = soa(H.orig, nc, 3), edg = soa(H.edge, nc, 9), fn = soa(H.fn, nf, 3);
+    std::vector<int2> nbl(6 * nc);
+    for (size_t i = 0; i < 6 * nc; ++i) nbl[i] = make_int2(H.nb[i], H.nblf[i]);
+    std::vector<DevBC> bcs(H.bcs.size() ? H.bcs.size() : 1);
+    std::memset(bcs.data(), 0, bcs.size() * sizeof(DevBC));
+    for (size_t b = 0; b < H.bcs.size(); ++b) {
+        bcs[b].type = H.bcs[b].type;
+        bcs[b].Tw = H.bcs[b].T_w;
+        for (int d = 0; d < 3; ++d) bcs[b].Uw[d] = H.bcs[b].U_w[d];
+        for (int k = 0; k < 5; ++k) bcs[b].Winf[k] = H.bcs[b].W_inf[k];
+    }
+    auto cleanup_fail = [&](const std::string &msg) {
+        delete ctx;
+        return fail(nullptr, UGKWP_E_DEVICE, msg);
+    };
+    hipError_t e = hipSuccess;
+    e = e ? e : up((double *)D.vol, H.vol, s);
+    e = e ? e : up((double *)D.dS, dS, s);
+    e = e ? e : up((double *)D.orig, org, s);
+    e = e ? e : up((double *)D.edge, edg, s);
+    e = e ? e : up((uint8_t *)D.nfc, H.nfc, s);
+    e = e ? e : up((uint8_t *)D.ctype, H.ctype, s);
+    e = e ? e : hipMemcpyAsync((void *)D.plane, H.plane.data(), H.plane.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    e = e ? e : up((int2 *)D.nbl, nbl, s);
+    e = e ? e : up((int32_t *)D.cface, H.cface, s);
+    e = e ? e : up((int32_t *)D.fown, H.fown, s);
+    e = e ? e : up((int32_t *)D.fnb, H.fnb, s);
+    e = e ? e : up((double *)D.fn, fn, s);
+    e = e ? e : up((double *)D.farea, H.farea, s);
+    e = e ? e : up((DevBC *)D.bc, bcs, s);
+    e = e ? e : hipStreamSynchronize(s);
+    if (e != hipSuccess) return cleanup_fail(std::string("upload: ") + hipGetErrorString(e));
+    *out = ctx;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
+    if (!ctx || !W0) return fail(ctx, UGKWP_E_ARG, "null argument");
+    const size_t nc = (size_t)ctx->H.nc;
+    for (size_t c = 0; c < nc; ++c) {
+        const double *w = W0 + 5 * c;
+        double rho = w[0];
+        double T = (2.0 / 3.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
+        if (!(rho > 0.0) || !(T > 0.0) || !std::isfinite(rho) || !std::isfinite(T))
+            return fail(ctx, UGKWP_E_NONPHYS, "init_state: cell " + std::to_string(c) + " has rho <= 0 or T <= 0");
+    }
+    std::vector<double> Wt(5 * nc);
+    for (size_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 5; ++k) Wt[k * nc + c] = W0[5 * c + k];
+    Dev &D = ctx->D;
+    hipStream_t s = ctx->stream;
+    Scalars sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.dtmin_bits = 0x7FF0000000000000ULL;
+    HIPCHK(ctx, up(D.W, Wt, s));
+    ugkwp::launch_fill_f64(D.P, 5 * (long long)nc, 0.0, s);
+    ugkwp::launch_fill_i32(D.nleft, (long long)nc, 0, s);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->buf = 0;
+    ctx->have_state = true;
+    ctx->poisoned = false;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
+    if (!ctx || n_steps < 0) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "step before init_state");
+    if (ctx->poisoned) return fail(ctx, UGKWP_E_STATE, "context poisoned by an earlier device error; call init_state");
+    for (int32_t i = 0; i < n_steps; ++i) {
+        ugkwp::launch_step(ctx->D, ctx->buf, ctx->gather_bs, ctx->stream, &ctx->prof);
+        ctx->buf ^= 1;
+    }
+    HIPCHK(ctx, hipGetLastError());
+    if (stats) {
+        Scalars s;
+        int32_t st = read_scalars(ctx, s);
+        std::memset(stats, 0, sizeof(*stats));
+        stats->dt = s.dt;
+        stats->t = s.t;
+        stats->step = s.step;
+        stats->n_alive = s.n_alive;
+        stats->n_sampled = (int64_t)s.n_sampled;
+        stats->n_collided = (int64_t)s.n_collided;
+        stats->n_escaped = (int64_t)s.n_escaped;
+        stats->crossings = (int64_t)s.n_cross;
+        stats->wall_hits = (int64_t)s.n_wall;
+        stats->error_word = s.err;
+        stats->moved_total = (int64_t)s.moved_total;
+        // particles streamed in the last step: those alive at its start plus the sampled ones
+        stats->n_moved = s.n_alive + (int64_t)s.n_collided + (int64_t)s.n_escaped;
+        if (st != UGKWP_OK) return st;
+    }
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_moments(ugkwp_ctx *ctx, int32_t which, double *out, int32_t out_is_device) {
+    if (!ctx || !out || which < 0 || which > 3) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "moments before init_state");
+    Dev &D = ctx->D;
+    double *scratch = D.S;  // [5][nc] per-step scratch, free between steps
+    ugkwp::launch_moments(D, which, scratch, ctx->stream);
+    HIPCHK(ctx, hipGetLastError());
+    size_t bytes = sizeof(double) * 5 * (size_t)D.nc;
+    HIPCHK(ctx, hipMemcpyAsync(out, scratch, bytes, out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               ctx->stream));
+    Scalars s;
+    return read_scalars(ctx, s);
+}
+
+int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n) {
+    if (!ctx || !n) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "no state");
+    Scalars s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(&s, ctx->D.sc, sizeof(Scalars), hipMemcpyDeviceToHost));
+    *n = s.n_old;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell, uint64_t *uid) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    int64_t n = 0;
+    int32_t st = ugkwp_particle_count(ctx, &n);
+    if (st != UGKWP_OK) return st;
+    const ugkwp::Particles &P = ctx->D.pa[ctx->buf];
+    std::vector<double> tmp((size_t)n);
+    double *const xs[3] = {P.x0, P.x1, P.x2};
+    double *const us[3] = {P.u0, P.u1, P.u2};
+    for (int d = 0; d < 3 && n > 0; ++d) {
+        if (x) {
+            HIPCHK(ctx, hipMemcpy(tmp.data(), xs[d], n * sizeof(double), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) x[3 * i + d] = tmp[i];
+        }
+        if (u) {
+            HIPCHK(ctx, hipMemcpy(tmp.data(), us[d], n * sizeof(double), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) u[3 * i + d] = tmp[i];
+        }
+    }
+    if (m && n > 0) HIPCHK(ctx, hipMemcpy(m, P.m, n * sizeof(double), hipMemcpyDeviceToHost));
+    if (cell && n > 0) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (uid && n > 0) HIPCHK(ctx, hipMemcpy(uid, P.uid, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_geometry(ugkwp_ctx *ctx, double *vol, double *xc, double *dS) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    const HostMesh &H = ctx->H;
+    if (vol) std::memcpy(vol, H.vol.data(), H.vol.size() * sizeof(double));
+    if (xc) std::memcpy(xc, H.xc.data(), H.xc.size() * sizeof(double));
+    if (dS) std::memcpy(dS, H.dS.data(), H.dS.size() * sizeof(double));
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    ctx->prof.on = on != 0;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_profile_read(ugkwp_ctx *ctx, int32_t n_slots, double *total_ms, int64_t *launches) {
+    if (!ctx || n_slots < 0) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof.drain(total_ms, launches, n_slots);
+    return UGKWP_OK;
+}
+
+const char *ugkwp_profile_slot_name(int32_t slot) {
+    return (slot >= 0 && slot < ugkwp::kNumSlots) ? kSlotNames[slot] : "";
+}
+
+const char *ugkwp_last_error(const ugkwp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+void ugkwp_destroy(ugkwp_ctx *ctx) { delete ctx; }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Device-side data layout and small device helpers shared by the UGKWP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ugkwp {
+
+// device error bits, reported through ugkwp_step_stats.error_word
+enum : uint32_t {
+    kErrNonPhys = 1u,    // rho <= 0, T <= 0 or non-finite in a cell
+    kErrCapacity = 2u,   // particles would exceed the capacity
+    kErrLost = 4u,       // a particle exceeded max_crossings
+    kErrCellCount = 8u,  // more than 2^20 particles sampled in one cell (particle-id field)
+};
+
+enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5 };
+
+struct DevBC {
+    int32_t type;
+    int32_t pad;
+    double Tw;
+    double Uw[3];
+    double Winf[5];
+};
+
+// Step scalars, resident in device memory: the host never reads them inside a step.
+struct Scalars {
+    unsigned long long dtmin_bits;  // bit pattern of min Omega/Lambda (positive doubles order as integers)
+    double dt;
+    double t;
+    long long step;
+    long long n_old;      // particles at the start of the step (grouped by cell)
+    long long n_new;      // particles sampled in the step (0 if the capacity check failed)
+    long long n_alive;    // particles after the step
+    unsigned long long n_sampled, n_collided, n_escaped, n_cross, n_wall;
+    unsigned long long moved_total;  // particles streamed since the state was set
+    unsigned int err;
+    unsigned int pad;
+};
+
+struct Particles {
+    double *x0, *x1, *x2;
+    double *u0, *u1, *u2;
+    double *m;
+    int32_t *cell;
+    uint64_t *uid;
+};
+
+struct Dev {
+    // mesh
+    int32_t nc, nf, nbc, pad0;
+    const double *vol;      // [nc]
+    const double *dS;       // [3][nc]
+    const double *orig;     // [3][nc]
+    const double *edge;     // [9][nc]  edge k component d at [3k+d][nc]
+    const uint8_t *nfc;     // [nc]
+    const uint8_t *ctype;   // [nc]
+    const double4 *plane;   // [nc*6]  (n, d) outward
+    const int2 *nbl;        // [nc*6]  (neighbour or -1-bc, local face in neighbour)
+    const int32_t *cface;   // [nc*6]  +-(f+1)
+    const int32_t *fown;    // [nf]
+    const int32_t *fnb;     // [nf]
+    const double *fn;       // [3][nf]
+    const double *farea;    // [nf]
+    const DevBC *bc;        // [nbc]
+    // parameters
+    double mu_ref, omega, cfl, c2;
+    int32_t n_ref, n_min, max_cross, pad1;
+    unsigned long long seed;
+    long long cap;
+    // state
+    double *W;              // [5][nc]
+    double *P;              // [5][nc] raw particle sums (W^p = P / Omega)
+    int32_t *nleft;         // [nc]
+    // per-step scratch
+    double *tau;            // [nc]
+    double *ec;             // [nc] exp(-dt/tau)
+    double *rhoh;           // [nc] max(rho - rho^p, 0)
+    double *Phi;            // [5][nf]
+    double *S;              // [5][nc] particle sums at the start of the step
+    long long *nsam;        // [nc]
+    long long *samoff;      // [nc+1]
+    long long *scan64;      // scan partials
+    int32_t *cnt;           // [2nc]
+    int32_t *off;           // [2nc+1]
+    int32_t *cursor;        // [2nc]
+    int32_t *scan32;        // scan partials
+    int32_t *key;           // [cap]
+    int32_t *perm;          // [cap]
+    Particles pa[2];
+    Scalars *sc;
+};
+
+}  // namespace ugkwp

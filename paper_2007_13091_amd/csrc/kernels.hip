@@ -1,0 +1,1002 @@
+// HIP kernels of one UGKWP time step for gfx950 (FP64 path).
+//
+// Order inside a step (paper Sec. 2.3, the four-step particle procedure, and Eq.
+// update_macro_variables):
+//   k_prim_dt      S0  primitives, tau = mu_ref T^omega / p, min Omega/Lambda     (Sec. 2.4(a))
+//   k_cell_prep    S0  dt, exp(-dt/tau), rho^h, sample counts N_sam            (Sec. 2.4(b))
+//   scan           exclusive prefix of N_sam -> slots of the new particles
+//   k_flux         S2  wave flux F^eq + F^{fr,wave} per face                    (Sec. 2.2, 2.4)
+//   k_sample       S3  antithetic Maxwellian pairs, uniform positions; start sums S
+//   k_stream       S4+S5 free-flight time and face-to-face transport; end-cell keys
+//   scan           exclusive prefix of the per-cell counts
+//   k_scatter      bucket the particles by end cell (survivors, then collided)
+//   k_gather       S6  deterministic order per cell, sums E and W^p, update of W
+//   k_finalize     step bookkeeping
+// No floating-point atomics: per-cell sums use fixed reduction trees, so a run is bitwise
+// reproducible.  Integer atomics only hand out bucket slots and counts; the order inside a
+// bucket is then fixed by sorting the source indices.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace ugkwp {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11); counter = (uid, step, tag<<32|sub, 0),
+// key = (seed, 0).
+// ---------------------------------------------------------------------------------------
+struct U4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ U4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    U4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ U4 draw(uint64_t seed, uint64_t uid, long long step, int tag, uint32_t sub) {
+    return philox(uid, (uint64_t)step, ((uint64_t)tag << 32) | sub, 0ULL, seed, 0ULL);
+}
+
+// (top 52 bits + 1/2) * 2^-52: uniform in (0, 1), never 0 or 1
+__device__ __forceinline__ double unif(uint64_t r) { return ((double)(r >> 12) + 0.5) * 0x1p-52; }
+
+__device__ __forceinline__ uint64_t make_uid(long long step, int cell, long long k) {
+    return (((uint64_t)step & 0x7FFFFULL) << 44) | (((uint64_t)cell & 0xFFFFFFULL) << 20) | ((uint64_t)k & 0xFFFFFULL);
+}
+
+// ---------------------------------------------------------------------------------------
+// Maxwellian moments in a face frame (R = 1, K = 0), lambda = 1/(2T).
+// m[k] = <u_n^k> over the full line (rng 0), u_n > 0 (rng 1) or u_n < 0 (rng -1);
+// <u^{k+2}> = U <u^{k+1}> + (k+1)/(2 lambda) <u^k> holds on each half line as well.
+// ---------------------------------------------------------------------------------------
+struct Prim {
+    double rho, un, v, w, lam, T;
+};
+
+__device__ __forceinline__ void moments4(int rng, double U, double lam, double m[4]) {
+    if (rng == 0) {
+        m[0] = 1.0;
+        m[1] = U;
+    } else if (rng > 0) {
+        m[0] = 0.5 * erfc(-sqrt(lam) * U);
+        m[1] = U * m[0] + 0.5 * exp(-lam * U * U) / sqrt(kPi * lam);
+    } else {
+        m[0] = 0.5 * erfc(sqrt(lam) * U);
+        m[1] = U * m[0] - 0.5 * exp(-lam * U * U) / sqrt(kPi * lam);
+    }
+    m[2] = U * m[1] + 1.0 / (2.0 * lam) * m[0];
+    m[3] = U * m[2] + 2.0 / (2.0 * lam) * m[1];
+}
+
+// <psi> (H) and <u_n psi> (G) of a unit-density Maxwellian; psi = (1, u_n, v, w, |u|^2/2)
+__device__ __forceinline__ void psi_moments(const Prim &p, const double m[4], double H[5], double G[5]) {
+    double tr = p.v * p.v + p.w * p.w + 1.0 / p.lam;
+    H[0] = m[0];
+    H[1] = m[1];
+    H[2] = m[0] * p.v;
+    H[3] = m[0] * p.w;
+    H[4] = 0.5 * (m[2] + m[0] * tr);
+    G[0] = m[1];
+    G[1] = m[2];
+    G[2] = m[1] * p.v;
+    G[3] = m[1] * p.w;
+    G[4] = 0.5 * (m[3] + m[1] * tr);
+}
+
+// face frame: t1 = normalise(e_a x n), a = axis of the smallest |n_a| (lowest on ties); t2 = n x t1
+__device__ __forceinline__ void face_frame(const double n[3], double t1[3], double t2[3]) {
+    int a = 0;
+    if (fabs(n[1]) < fabs(n[a])) a = 1;
+    if (fabs(n[2]) < fabs(n[a])) a = 2;
+    double e0 = a == 0 ? 1.0 : 0.0, e1 = a == 1 ? 1.0 : 0.0, e2 = a == 2 ? 1.0 : 0.0;
+    double c0 = e1 * n[2] - e2 * n[1], c1 = e2 * n[0] - e0 * n[2], c2 = e0 * n[1] - e1 * n[0];
+    double l = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    t1[0] = c0 / l;
+    t1[1] = c1 / l;
+    t1[2] = c2 / l;
+    t2[0] = n[1] * t1[2] - n[2] * t1[1];
+    t2[1] = n[2] * t1[0] - n[0] * t1[2];
+    t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+__device__ __forceinline__ Prim to_frame(const double W[5], const double n[3], const double t1[3], const double t2[3]) {
+    Prim p;
+    p.rho = W[0];
+    double U = W[1] / W[0], V = W[2] / W[0], Z = W[3] / W[0];
+    p.un = U * n[0] + V * n[1] + Z * n[2];
+    p.v = U * t1[0] + V * t1[1] + Z * t1[2];
+    p.w = U * t2[0] + V * t2[1] + Z * t2[2];
+    p.T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+    p.lam = 1.0 / (2.0 * p.T);
+    return p;
+}
+
+// Taylor coefficients (-1)^k/k! and (-1)^k (k-1)/k!, k = 2..24, for the series forms of
+//   q1/tau = x - 1 + e^-x   and   (q4 - dt e)/tau = 1 - (1 + x) e^-x.
+struct QSeries {
+    double a[25], b[25];
+    constexpr QSeries() : a(), b() {
+        double f = 1.0;
+        for (int k = 1; k <= 24; ++k) {
+            f = f * k;
+            double s = (k % 2 == 0) ? 1.0 : -1.0;
+            a[k] = s / f;
+            b[k] = s * (k - 1) / f;
+        }
+    }
+};
+__constant__ QSeries kQ = QSeries();
+
+// q1 and q4 - dt e of the time-integrated interface distribution (Eq. of q1..q5), x = dt/tau:
+// series below x = 1 (terms x^2..x^24, Horner), closed forms above
+__device__ __forceinline__ void qcoef(double dt, double tau, double &q1, double &q4m) {
+    double x = dt / tau;
+    if (x < 1.0) {
+        double s1 = 0.0, s4 = 0.0;
+#pragma unroll
+        for (int k = 24; k >= 2; --k) {
+            s1 = s1 * x + kQ.a[k];
+            s4 = s4 * x + kQ.b[k];
+        }
+        q1 = tau * (s1 * x * x);
+        q4m = tau * (s4 * x * x);
+    } else {
+        double e = exp(-x);
+        q1 = tau * (x - 1.0 + e);
+        q4m = tau * (1.0 - (1.0 + x) * e);
+    }
+}
+
+// First-order wave flux between two face-frame states:
+//   F = rho0 q1 <u_n psi>_0 + (q4 - dt e) (rhoh_l <u_n psi>_{l,u>0} + rhoh_r <u_n psi>_{r,u<0})
+// with g0 from the upwind moments of both sides and tau at the face from g0 plus the
+// numerical dissipation C2 |pl - pr| / (pl + pr) dt of Sec. 2.4(d).
+__device__ __forceinline__ void flux_pair(const Prim &l, const Prim &r, double hl, double hr, double dt, double mu_ref,
+                                          double omega, double c2, double Ff[5]) {
+    double ml[4], mr[4], Hl[5], Gl[5], Hr[5], Gr[5];
+    moments4(1, l.un, l.lam, ml);
+    moments4(-1, r.un, r.lam, mr);
+    psi_moments(l, ml, Hl, Gl);
+    psi_moments(r, mr, Hr, Gr);
+    double W0[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) W0[k] = l.rho * Hl[k] + r.rho * Hr[k];
+    Prim z;
+    z.rho = W0[0];
+    z.un = W0[1] / W0[0];
+    z.v = W0[2] / W0[0];
+    z.w = W0[3] / W0[0];
+    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.lam = 1.0 / (2.0 * z.T);
+    double pl = l.rho * l.T, pr = r.rho * r.T;
+    double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
+    double q1, q4m;
+    qcoef(dt, tau, q1, q4m);
+    double m0[4], H0[5], G0[5];
+    moments4(0, z.un, z.lam, m0);
+    psi_moments(z, m0, H0, G0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Ff[k] = q1 * z.rho * G0[k] + q4m * (hl * Gl[k] + hr * Gr[k]);
+}
+
+// ---------------------------------------------------------------------------------------
+// wave reductions with a fixed butterfly (deterministic)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = v + __shfl_xor(v, s);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = v + __shfl_xor(v, s);
+    return v;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Wave-aggregated slot allocation: every lane with key >= 0 gets old(cnt[key]) + its rank
+// among the lanes of the wave holding the same key.  Must be called by the whole wave.
+__device__ __forceinline__ int agg_slot(int32_t *cnt, int key) {
+    const int lane = lane_id();
+    const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    unsigned long long todo = __ballot(key >= 0);
+    int slot = -1;
+    while (todo) {
+        int leader = __ffsll((long long)todo) - 1;
+        int lkey = __shfl(key, leader);
+        unsigned long long same = __ballot(key == lkey) & todo;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[lkey], (int)__popcll(same));
+        base = __shfl(base, leader);
+        if (key == lkey) slot = base + (int)__popcll(same & below);
+        todo &= ~same;
+    }
+    return slot;
+}
+
+// ---------------------------------------------------------------------------------------
+// S0: primitives, tau, min Omega / Lambda
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
+    __shared__ double smin[256];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Scalars *s = D.sc;
+        s->n_sampled = 0;
+        s->n_collided = 0;
+        s->n_escaped = 0;
+        s->n_cross = 0;
+        s->n_wall = 0;
+    }
+    double r = INFINITY;
+    if (c < D.nc) {
+        const int nc = D.nc;
+        double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
+        bool bad = !(rho > 0.0) || !isfinite(rho);
+        double T = 0.0;
+        double U = 0.0, V = 0.0, Z = 0.0;
+        if (!bad) {
+            U = m0 / rho;
+            V = m1 / rho;
+            Z = m2 / rho;
+            T = (2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
+            bad = !(T > 0.0) || !isfinite(T);
+        }
+        if (bad) {
+            atomicOr(&D.sc->err, kErrNonPhys);
+            D.tau[c] = 1.0;
+        } else {
+            D.tau[c] = D.mu_ref * pow(T, D.omega) / (rho * T);
+            double cs = 3.0 * sqrt(T);
+            double lam = (fabs(U) + cs) * D.dS[c] + (fabs(V) + cs) * D.dS[nc + c] + (fabs(Z) + cs) * D.dS[2 * nc + c];
+            r = D.vol[c] / lam;
+        }
+    }
+    smin[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && smin[0] < INFINITY && smin[0] > 0.0)
+        atomicMin(&D.sc->dtmin_bits, (unsigned long long)__double_as_longlong(smin[0]));
+}
+
+// ---------------------------------------------------------------------------------------
+// S0 (cont.): dt, collisionless fraction, hydro density, number of particles to sample
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
+    const double dt = D.cfl * __longlong_as_double((long long)D.sc->dtmin_bits);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) D.sc->dt = dt;
+    if (c >= D.nc) return;
+    const double vol = D.vol[c];
+    const double rhop = D.P[c] / vol;
+    // the hydro density is a difference of sums; below 1e-12 rho it is roundoff of that
+    // subtraction (particles hold all the mass) and counts as zero
+    const double rho = D.W[c];
+    const double rh = rho - rhop;
+    const double rhoh = rh > 1e-12 * rho ? rh : 0.0;
+    const double e = exp(-dt / D.tau[c]);
+    D.rhoh[c] = rhoh;
+    D.ec[c] = e;
+    const double rhohp = e * rhoh;
+    long long ns = 0;
+    if (rhohp > 0.0 && rhop + rhohp > 0.0) {
+        double r = (0.5 * D.n_ref) * (rhohp / (rhop + rhohp));
+        double cr = ceil(r);
+        if (!(cr <= 524288.0)) {
+            atomicOr(&D.sc->err, kErrCellCount);
+        } else {
+            ns = 2 * (long long)cr;
+            long long need = (long long)D.n_min - D.nleft[c];
+            if (need > 0) {
+                long long ne = 2 * ((need + 1) / 2);
+                if (ne > ns) ns = ne;
+            }
+            if (ns > (1LL << 20)) {
+                atomicOr(&D.sc->err, kErrCellCount);
+                ns = 0;
+            }
+        }
+    }
+    D.nsam[c] = ns;
+}
+
+// capacity check of the step: old + new must fit
+__global__ void k_sample_setup(Dev D) {
+    Scalars *s = D.sc;
+    long long nn = D.samoff[D.nc];
+    if (s->n_old + nn > D.cap) {
+        atomicOr(&s->err, kErrCapacity);
+        s->n_new = 0;
+    } else {
+        s->n_new = nn;
+    }
+    s->n_sampled = (unsigned long long)s->n_new;
+}
+
+// ---------------------------------------------------------------------------------------
+// S2: wave flux per face, times the area, oriented owner -> neighbour
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(128) k_flux(Dev D) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= D.nf) return;
+    const int nc = D.nc, nf = D.nf;
+    const double dt = D.sc->dt;
+    const int c = D.fown[f];
+    const int nb = D.fnb[f];
+    double n[3] = {D.fn[f], D.fn[nf + f], D.fn[2 * nf + f]};
+    double t1[3], t2[3];
+    face_frame(n, t1, t2);
+    double Wl[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Wl[k] = D.W[k * nc + c];
+    const Prim l = to_frame(Wl, n, t1, t2);
+    double Ff[5];
+    if (nb >= 0) {
+        double Wr[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wr[k] = D.W[k * nc + nb];
+        const Prim r = to_frame(Wr, n, t1, t2);
+        flux_pair(l, r, D.rhoh[c], D.rhoh[nb], dt, D.mu_ref, D.omega, D.c2, Ff);
+    } else {
+        const DevBC bc = D.bc[-1 - nb];
+        if (bc.type == 0) {
+            // specular wall: mirror state, keep only the normal momentum
+            Prim g = l;
+            g.un = -l.un;
+            double h = D.rhoh[c];
+            flux_pair(l, g, h, h, dt, D.mu_ref, D.omega, D.c2, Ff);
+            Ff[0] = 0.0;
+            Ff[2] = 0.0;
+            Ff[3] = 0.0;
+            Ff[4] = 0.0;
+        } else if (bc.type == 1) {
+            // diffuse wall: incoming q1 g + (q4 - dt e) g^h with the cell tau; the wall emits
+            // rho_w M(T_w, U_w) over u_n < 0 for the step, rho_w from zero net mass flux
+            double q1, q4m;
+            qcoef(dt, D.tau[c], q1, q4m);
+            double ml[4], Hl[5], Gl[5];
+            moments4(1, l.un, l.lam, ml);
+            psi_moments(l, ml, Hl, Gl);
+            const double h = D.rhoh[c];
+            double Fin[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Fin[k] = q1 * l.rho * Gl[k] + q4m * h * Gl[k];
+            Prim w;
+            w.rho = 1.0;
+            w.un = bc.Uw[0] * n[0] + bc.Uw[1] * n[1] + bc.Uw[2] * n[2];
+            w.v = bc.Uw[0] * t1[0] + bc.Uw[1] * t1[1] + bc.Uw[2] * t1[2];
+            w.w = bc.Uw[0] * t2[0] + bc.Uw[1] * t2[1] + bc.Uw[2] * t2[2];
+            w.T = bc.Tw;
+            w.lam = 1.0 / (2.0 * bc.Tw);
+            double mw[4], Hw[5], Gw[5];
+            moments4(-1, w.un, w.lam, mw);
+            psi_moments(w, mw, Hw, Gw);
+            const double rhow = -Fin[0] / (dt * Gw[0]);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Ff[k] = Fin[k] + dt * rhow * Gw[k];
+            Ff[0] = 0.0;
+        } else {
+            // far field: the free stream as the right state (hydro density = its density)
+            const Prim r = to_frame(bc.Winf, n, t1, t2);
+            flux_pair(l, r, D.rhoh[c], bc.Winf[0], dt, D.mu_ref, D.omega, D.c2, Ff);
+        }
+    }
+    const double a = D.farea[f];
+    D.Phi[f] = Ff[0] * a;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) D.Phi[(1 + d) * nf + f] = (Ff[1] * n[d] + Ff[2] * t1[d] + Ff[3] * t2[d]) * a;
+    D.Phi[4 * nf + f] = Ff[4] * a;
+}
+
+// ---------------------------------------------------------------------------------------
+// S3: hydro particles, one wave per cell.  Pair j shares X ~ N(0, I) (Box-Muller on the draw
+// keyed by the even partner's id); partners get U + sqrt(T) X and U - sqrt(T) X and their own
+// uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
+// S = P + sum of phi over the new particles (fixed tree over the wave).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int c = blockIdx.x * (blockDim.x / kWave) + wave;
+    if (c >= D.nc) return;
+    const int nc = D.nc;
+    const Scalars *sc = D.sc;
+    const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ns > 0) {
+        const Particles pa = D.pa[buf];
+        const long long base = sc->n_old + D.samoff[c];
+        const long long step = sc->step;
+        const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
+        const double U[3] = {m0 / rho, m1 / rho, m2 / rho};
+        const double T = (2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
+        const double sT = sqrt(T);
+        const double vol = D.vol[c];
+        const double msam = D.ec[c] * D.rhoh[c] * vol / (double)ns;
+        const double org[3] = {D.orig[c], D.orig[nc + c], D.orig[2 * nc + c]};
+        double Ed[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ed[q] = D.edge[q * nc + c];
+        const bool tet = D.ctype[c] == 4;
+        for (long long k = lane; k < ns; k += kWave) {
+            const long long i = base + k;
+            const uint64_t uid = make_uid(step, c, k);
+            const uint64_t puid = make_uid(step, c, k & ~1LL);
+            U4 rv = draw(D.seed, puid, step, kTagVel, 0);
+            double e0 = unif(rv.v[0]), e1 = unif(rv.v[1]), e2 = unif(rv.v[2]), e3 = unif(rv.v[3]);
+            double r1 = sqrt(-2.0 * log(e0)), r2 = sqrt(-2.0 * log(e2));
+            double X[3] = {r1 * cos(2.0 * kPi * e1), r1 * sin(2.0 * kPi * e1), r2 * cos(2.0 * kPi * e3)};
+            const double sg = (k & 1) ? -1.0 : 1.0;
+            double u[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
+            U4 rp = draw(D.seed, uid, step, kTagPos, 0);
+            double s = unif(rp.v[0]), t = unif(rp.v[1]), w = unif(rp.v[2]);
+            if (tet) {
+                if (s + t > 1.0) {
+                    s = 1.0 - s;
+                    t = 1.0 - t;
+                }
+                if (t + w > 1.0) {
+                    double tmp = w;
+                    w = 1.0 - s - t;
+                    t = 1.0 - tmp;
+                } else if (s + t + w > 1.0) {
+                    double tmp = w;
+                    w = s + t + w - 1.0;
+                    s = 1.0 - t - tmp;
+                }
+            }
+            double x[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+            pa.x0[i] = x[0];
+            pa.x1[i] = x[1];
+            pa.x2[i] = x[2];
+            pa.u0[i] = u[0];
+            pa.u1[i] = u[1];
+            pa.u2[i] = u[2];
+            pa.m[i] = msam;
+            pa.cell[i] = c;
+            pa.uid[i] = uid;
+            acc[0] += msam;
+            acc[1] += msam * u[0];
+            acc[2] += msam * u[1];
+            acc[3] += msam * u[2];
+            acc[4] += msam * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) D.S[k * nc + c] = D.P[k * nc + c] + acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// S4 + S5: free-flight time and face-to-face transport of one particle.
+// Returns 0 inside (cell updated), 1 escaped through a far-field face, -1 lost.
+// ---------------------------------------------------------------------------------------
+__device__ int track(const Dev &D, double x[3], double u[3], int &cell, double ts, uint64_t uid, long long step,
+                     int &ncross, int &nwall) {
+    int c = cell;
+    int entry = -1;
+    double trem = ts;
+    int bounce = 0;
+    ncross = 0;
+    for (;;) {
+        const int nfc = D.nfc[c];
+        double best = INFINITY;
+        int bf = -1;
+        for (int lf = 0; lf < nfc; ++lf) {
+            if (lf == entry) continue;
+            const double4 p = D.plane[c * 6 + lf];
+            const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
+            if (un > 0.0) {
+                double tt = (p.w - (p.x * x[0] + p.y * x[1] + p.z * x[2])) / un;
+                if (tt < 0.0) tt = 0.0;
+                if (tt < best) {
+                    best = tt;
+                    bf = lf;
+                }
+            }
+        }
+        if (bf < 0 || best >= trem) {
+            x[0] = x[0] + u[0] * trem;
+            x[1] = x[1] + u[1] * trem;
+            x[2] = x[2] + u[2] * trem;
+            cell = c;
+            return 0;
+        }
+        x[0] = x[0] + u[0] * best;
+        x[1] = x[1] + u[1] * best;
+        x[2] = x[2] + u[2] * best;
+        trem = trem - best;
+        if (++ncross > D.max_cross) {
+            cell = c;
+            return -1;
+        }
+        const int2 nb = D.nbl[c * 6 + bf];
+        if (nb.x >= 0) {
+            entry = nb.y;
+            c = nb.x;
+            continue;
+        }
+        const DevBC &b = D.bc[-1 - nb.x];
+        const double4 p = D.plane[c * 6 + bf];
+        const double n[3] = {p.x, p.y, p.z};
+        if (b.type == 0) {
+            const double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+            u[0] = u[0] - 2.0 * un * n[0];
+            u[1] = u[1] - 2.0 * un * n[1];
+            u[2] = u[2] - 2.0 * un * n[2];
+            entry = bf;
+        } else if (b.type == 1) {
+            // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential
+            // components N(U_w, T_w) in the face frame
+            U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
+            ++bounce;
+            ++nwall;
+            double t1[3], t2[3];
+            face_frame(n, t1, t2);
+            const double sq = sqrt(b.Tw);
+            const double vn = sqrt(-2.0 * b.Tw * log(unif(r.v[0])));
+            const double rr = sqrt(-2.0 * log(unif(r.v[1])));
+            const double a = 2.0 * kPi * unif(r.v[2]);
+            const double X1 = rr * cos(a), X2 = rr * sin(a);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] = b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+            entry = bf;
+        } else {
+            cell = c;
+            return 1;
+        }
+    }
+}
+
+// One thread per particle (grid stride).  Key of the end bucket: end cell for particles
+// that stay collisionless, nc + end cell for collided ones, -1 for escaped.
+__global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
+    const Scalars *sc = D.sc;
+    const long long n_old = sc->n_old;
+    const long long n_tot = n_old + sc->n_new;
+    const double dt = sc->dt;
+    const long long step = sc->step;
+    const Particles pa = D.pa[buf];
+    const int nc = D.nc;
+    unsigned long long ncoll = 0, nesc = 0, ncross = 0, nwall = 0;
+    bool lost = false;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 < n_tot; i0 += stride) {
+        const long long i = i0 + threadIdx.x;
+        int key = -1;
+        if (i < n_tot) {
+            int c = pa.cell[i];
+            const uint64_t uid = pa.uid[i];
+            double x[3] = {pa.x0[i], pa.x1[i], pa.x2[i]};
+            double u[3] = {pa.u0[i], pa.u1[i], pa.u2[i]};
+            double ts = dt;
+            bool collided = false;
+            if (i < n_old) {
+                U4 r = draw(D.seed, uid, step, kTagTF, 0);
+                const double tf = -D.tau[c] * log(unif(r.v[0]));
+                if (tf < dt) {
+                    ts = tf;
+                    collided = true;
+                }
+            }
+            int nx = 0, nw = 0;
+            const int rc = track(D, x, u, c, ts, uid, step, nx, nw);
+            ncross += (unsigned long long)nx;
+            nwall += (unsigned long long)nw;
+            pa.x0[i] = x[0];
+            pa.x1[i] = x[1];
+            pa.x2[i] = x[2];
+            pa.u0[i] = u[0];
+            pa.u1[i] = u[1];
+            pa.u2[i] = u[2];
+            pa.cell[i] = c;
+            if (rc == 1) {
+                ++nesc;
+            } else {
+                if (rc < 0) lost = true;
+                if (collided) ++ncoll;
+                key = collided ? nc + c : c;
+            }
+            D.key[i] = key;
+        }
+        agg_slot(D.cnt, key);
+    }
+    if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
+    ncoll = wave_sum_u64(ncoll);
+    nesc = wave_sum_u64(nesc);
+    ncross = wave_sum_u64(ncross);
+    nwall = wave_sum_u64(nwall);
+    if (lane_id() == 0) {
+        Scalars *s = D.sc;
+        if (ncoll) atomicAdd(&s->n_collided, ncoll);
+        if (nesc) atomicAdd(&s->n_escaped, nesc);
+        if (ncross) atomicAdd(&s->n_cross, ncross);
+        if (nwall) atomicAdd(&s->n_wall, nwall);
+    }
+}
+
+// bucket the particle indices by key: perm[off[key] + slot] = i
+__global__ void __launch_bounds__(256) k_scatter(Dev D) {
+    const Scalars *sc = D.sc;
+    const long long n_tot = sc->n_old + sc->n_new;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 < n_tot; i0 += stride) {
+        const long long i = i0 + threadIdx.x;
+        const int key = i < n_tot ? D.key[i] : -1;
+        const int slot = agg_slot(D.cursor, key);
+        if (key >= 0) D.perm[D.off[key] + slot] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// block-wide sort of a short list of distinct ints, ascending.  Bitonic network whose
+// comparators all put the smaller value first, so entries past len behave as +infinity and
+// are never touched.  a may point to LDS or to global memory.
+// ---------------------------------------------------------------------------------------
+template <int BS>
+__device__ void block_sort(int *a, int len) {
+    if (len < 2) return;
+    int bad = 0;
+    for (int i = threadIdx.x; i + 1 < len; i += BS) bad |= a[i] > a[i + 1];
+    if (!__syncthreads_or(bad)) return;
+    int N = 1;
+    while (N < len) N <<= 1;
+    for (int k = 2; k <= N; k <<= 1) {
+        const int h = k >> 1;
+        for (int p = threadIdx.x; p < N / 2; p += BS) {
+            const int i = (p / h) * k + (p % h);
+            const int j = i ^ (k - 1);
+            if (j < len) {
+                int ai = a[i], aj = a[j];
+                if (ai > aj) {
+                    a[i] = aj;
+                    a[j] = ai;
+                }
+            }
+        }
+        __syncthreads();
+        for (int j = h >> 1; j > 0; j >>= 1) {
+            for (int p = threadIdx.x; p < N / 2; p += BS) {
+                const int i = (p / j) * 2 * j + (p % j);
+                const int q = i + j;
+                if (q < len) {
+                    int ai = a[i], aq = a[q];
+                    if (ai > aq) {
+                        a[i] = aq;
+                        a[q] = ai;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int BS>
+__device__ void block_sum5(double v[5], double *red /* [BS/64][5] LDS */) {
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = wave_sum(v[k]);
+    if (lane_id() == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) red[wave * 5 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 5; ++k) {
+            double s = red[k];
+            for (int w = 1; w < BS / kWave; ++w) s = s + red[w * 5 + k];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int kSortLDS = 4096;
+
+// ---------------------------------------------------------------------------------------
+// S6: one block per cell.  Survivors ending in the cell are written, in ascending source
+// order, to the next buffer; sums over survivors give P^{n+1}, sums over every particle
+// ending in the cell give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.
+// ---------------------------------------------------------------------------------------
+template <int BS>
+__global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
+    __shared__ int lds[kSortLDS];
+    __shared__ double red[(BS / kWave) * 5];
+    const int c = blockIdx.x;
+    const int nc = D.nc;
+    const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
+    double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
+    for (int part = 0; part < 2; ++part) {
+        const int k0 = part == 0 ? c : nc + c;
+        const int a0 = D.off[k0], a1 = D.off[k0 + 1];
+        const int len = a1 - a0;
+        int *list;
+        if (len <= kSortLDS) {
+            for (int j = threadIdx.x; j < len; j += BS) lds[j] = D.perm[a0 + j];
+            __syncthreads();
+            list = lds;
+        } else {
+            list = D.perm + a0;
+        }
+        block_sort<BS>(list, len);
+        double *acc = part == 0 ? Pn : Cn;
+        for (int j = threadIdx.x; j < len; j += BS) {
+            const int s = list[j];
+            const double m = src.m[s];
+            const double u0 = src.u0[s], u1 = src.u1[s], u2 = src.u2[s];
+            acc[0] += m;
+            acc[1] += m * u0;
+            acc[2] += m * u1;
+            acc[3] += m * u2;
+            acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+            if (part == 0) {
+                const int o = a0 + j;
+                dst.x0[o] = src.x0[s];
+                dst.x1[o] = src.x1[s];
+                dst.x2[o] = src.x2[s];
+                dst.u0[o] = u0;
+                dst.u1[o] = u1;
+                dst.u2[o] = u2;
+                dst.m[o] = m;
+                dst.cell[o] = c;
+                dst.uid[o] = src.uid[s];
+            }
+        }
+        __syncthreads();
+    }
+    block_sum5<BS>(Pn, red);
+    block_sum5<BS>(Cn, red);
+    if (threadIdx.x == 0) {
+        const int nf = D.nf;
+        const double vol = D.vol[c];
+        double acc[5] = {0, 0, 0, 0, 0};
+        const int nfc = D.nfc[c];
+        for (int lf = 0; lf < nfc; ++lf) {
+            const int code = D.cface[c * 6 + lf];
+            const int f = (code > 0 ? code : -code) - 1;
+            const double s = code > 0 ? 1.0 : -1.0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) acc[k] = acc[k] - s * D.Phi[k * nf + f];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const double E = Pn[k] + Cn[k];
+            acc[k] = acc[k] + (E - D.S[k * nc + c]);
+            D.W[k * nc + c] = D.W[k * nc + c] + acc[k] / vol;
+            D.P[k * nc + c] = Pn[k];
+        }
+        D.nleft[c] = D.off[c + 1] - D.off[c];
+    }
+}
+
+__global__ void k_finalize(Dev D) {
+    Scalars *s = D.sc;
+    const long long alive = D.off[D.nc];
+    s->moved_total = s->moved_total + (unsigned long long)(s->n_old + s->n_new);
+    s->n_alive = alive;
+    s->n_old = alive;
+    s->n_new = 0;
+    s->t = s->t + s->dt;
+    s->step = s->step + 1;
+    s->dtmin_bits = 0x7FF0000000000000ULL;
+}
+
+// ---------------------------------------------------------------------------------------
+// exclusive scan (integers, deterministic): out[i] = sum_{j<i} in[j], out[n] = total
+// ---------------------------------------------------------------------------------------
+constexpr int kScanBS = 256, kScanPer = 8, kScanTile = kScanBS * kScanPer;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *sh, T &total) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 1; s < kScanBS; s <<= 1) {
+        T t = (int)threadIdx.x >= s ? sh[threadIdx.x - s] : T(0);
+        __syncthreads();
+        sh[threadIdx.x] = sh[threadIdx.x] + t;
+        __syncthreads();
+    }
+    T incl = sh[threadIdx.x];
+    total = sh[kScanBS - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename T>
+__global__ void k_scan_reduce(const T *in, long long n, T *part) {
+    __shared__ T sh[kScanBS];
+    const long long base = (long long)blockIdx.x * kScanTile;
+    T s = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        long long i = base + (long long)threadIdx.x * kScanPer + q;
+        if (i < n) s = s + in[i];
+    }
+    T tot;
+    block_exclusive_scan<T>(s, sh, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void k_scan_partials(T *part, int nb, T *total_out) {
+    __shared__ T sh[kScanBS];
+    T carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanBS) {
+        const int b = b0 + threadIdx.x;
+        T v = b < nb ? part[b] : T(0);
+        T tot;
+        T ex = block_exclusive_scan<T>(v, sh, tot);
+        if (b < nb) part[b] = carry + ex;
+        carry = carry + tot;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+template <typename T>
+__global__ void k_scan_apply(const T *in, long long n, const T *part, T *out) {
+    __shared__ T sh[kScanBS];
+    const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
+    T v[kScanPer];
+    T s = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        long long i = base + q;
+        v[q] = i < n ? in[i] : T(0);
+        s = s + v[q];
+    }
+    T tot;
+    T ex = block_exclusive_scan<T>(s, sh, tot) + part[blockIdx.x];
+    for (int q = 0; q < kScanPer; ++q) {
+        long long i = base + q;
+        if (i < n) out[i] = ex;
+        ex = ex + v[q];
+    }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, long long n, T v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// field output for ugkwp_moments, [nc][5] in out
+__global__ void k_moments(Dev D, int which, double *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= D.nc) return;
+    const int nc = D.nc;
+    const double vol = D.vol[c];
+    double W[5], P[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        W[k] = D.W[k * nc + c];
+        P[k] = D.P[k * nc + c] / vol;
+    }
+    double o[5];
+    if (which == 0) {
+        for (int k = 0; k < 5; ++k) o[k] = W[k];
+    } else if (which == 1) {
+        for (int k = 0; k < 5; ++k) o[k] = P[k];
+    } else if (which == 2) {
+        for (int k = 0; k < 5; ++k) o[k] = W[k] - P[k];
+    } else {
+        const double rho = W[0];
+        o[0] = rho;
+        o[1] = W[1] / rho;
+        o[2] = W[2] / rho;
+        o[3] = W[3] / rho;
+        o[4] = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / rho) / rho;
+    }
+    for (int k = 0; k < 5; ++k) out[5 * c + k] = o[k];
+}
+
+template <typename T>
+void scan(const T *in, long long n, T *out, T *part, hipStream_t s) {
+    const int nb = (int)((n + kScanTile - 1) / kScanTile);
+    if (nb == 0) {
+        k_fill<T><<<1, 1, 0, s>>>(out, 1, T(0));
+        return;
+    }
+    k_scan_reduce<T><<<nb, kScanBS, 0, s>>>(in, n, part);
+    k_scan_partials<T><<<1, kScanBS, 0, s>>>(part, nb, out + n);
+    k_scan_apply<T><<<nb, kScanBS, 0, s>>>(in, n, part, out);
+}
+
+}  // namespace
+
+long long scan_partials_needed(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+int particle_grid() { return 2048; }
+
+void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s) {
+    if (n > 0) k_fill<int32_t><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_f64(double *p, long long n, double v, hipStream_t s) {
+    if (n > 0) k_fill<double><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
+}
+
+void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) {
+    const int nc = D.nc, nf = D.nf;
+    const unsigned gc = (unsigned)((nc + 255) / 256);
+    Prof none;
+    if (!pr) pr = &none;
+    pr->begin(kSlotPrim);
+    k_prim_dt<<<gc, 256, 0, s>>>(D);
+    pr->end(kSlotPrim);
+    pr->begin(kSlotCellPrep);
+    k_cell_prep<<<gc, 256, 0, s>>>(D);
+    pr->end(kSlotCellPrep);
+    pr->begin(kSlotScan);
+    scan<long long>(D.nsam, nc, D.samoff, D.scan64, s);
+    k_sample_setup<<<1, 1, 0, s>>>(D);
+    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt, 2LL * nc, 0);
+    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cursor, 2LL * nc, 0);
+    pr->end(kSlotScan);
+    pr->begin(kSlotFlux);
+    if (nf > 0) k_flux<<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+    pr->end(kSlotFlux);
+    pr->begin(kSlotSample);
+    k_sample<<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+    pr->end(kSlotSample);
+    pr->begin(kSlotStream);
+    k_stream<<<particle_grid(), 256, 0, s>>>(D, buf);
+    pr->end(kSlotStream);
+    pr->begin(kSlotScan2);
+    scan<int32_t>(D.cnt, 2LL * nc, D.off, D.scan32, s);
+    pr->end(kSlotScan2);
+    pr->begin(kSlotScatter);
+    k_scatter<<<particle_grid(), 256, 0, s>>>(D);
+    pr->end(kSlotScatter);
+    pr->begin(kSlotGather);
+    if (gather_bs == 64)
+        k_gather<64><<<nc, 64, 0, s>>>(D, buf);
+    else
+        k_gather<256><<<nc, 256, 0, s>>>(D, buf);
+    pr->end(kSlotGather);
+    pr->begin(kSlotFinal);
+    k_finalize<<<1, 1, 0, s>>>(D);
+    pr->end(kSlotFinal);
+}
+
+void launch_moments(const Dev &D, int which, double *out, hipStream_t s) {
+    k_moments<<<(unsigned)((D.nc + 255) / 256), 256, 0, s>>>(D, which, out);
+}
+
+}  // namespace ugkwp

@@ -1,0 +1,41 @@
+// Host-callable launchers of the UGKWP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace ugkwp {
+
+// scan partial slots needed for an exclusive scan over n integers
+long long scan_partials_needed(long long n);
+// blocks of the grid-stride particle kernels
+int particle_grid();
+
+// measurement hook: called around each group of launches of a step (no-op by default)
+enum ProfSlot : int {
+    kSlotPrim = 0,      // k_prim_dt
+    kSlotCellPrep,      // k_cell_prep
+    kSlotScan,          // scan of N_sam, capacity check, clearing of the bucket counters
+    kSlotFlux,          // k_flux
+    kSlotSample,        // k_sample
+    kSlotStream,        // k_stream
+    kSlotScan2,         // scan of the bucket counts
+    kSlotScatter,       // k_scatter
+    kSlotGather,        // k_gather
+    kSlotFinal,         // k_finalize
+    kNumSlots
+};
+struct Prof {
+    virtual ~Prof() {}
+    virtual void begin(int) {}
+    virtual void end(int) {}
+};
+
+void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s);
+void launch_fill_f64(double *p, long long n, double v, hipStream_t s);
+// one full time step on stream s; particles are read from pa[buf] and left in pa[buf ^ 1]
+void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr);
+// [nc][5] field (0 W, 1 W^p, 2 W^h, 3 primitives) into device memory out
+void launch_moments(const Dev &D, int which, double *out, hipStream_t s);
+
+}  // namespace ugkwp

@@ -1,0 +1,38 @@
+// Host-side mesh preparation for the UGKWP library: validation, face matching and the
+// geometry the kernels read (cell volumes and centroids, outward face planes, face normals
+// and areas, the projections Delta S of the time-step formula, sampling frames).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ugkwp.h"
+
+namespace ugkwp {
+
+constexpr int kMaxFaces = 6;  // faces per cell slot (box hex); tetrahedra use 4
+
+struct HostMesh {
+    int32_t nc = 0, nf = 0;
+    std::vector<double> vol;     // [nc]
+    std::vector<double> xc;      // [nc][3]
+    std::vector<double> dS;      // [nc][3]
+    std::vector<uint8_t> nfc;    // faces per cell (4 or 6)
+    std::vector<uint8_t> ctype;  // 4 or 8
+    std::vector<double> plane;   // [nc][6][4]: outward unit normal n and d with n.x = d on the face
+    std::vector<int32_t> nb;     // [nc][6]: neighbour cell, or -1 - bc index at a boundary
+    std::vector<int32_t> nblf;   // [nc][6]: the face's local index in the neighbour (-1 at a boundary)
+    std::vector<int32_t> cface;  // [nc][6]: global face f as f + 1 (owner) or -(f + 1) (neighbour)
+    std::vector<double> orig;    // [nc][3]  sampling frame: x = orig + s e1 + t e2 + w e3
+    std::vector<double> edge;    // [nc][3][3]
+    std::vector<int32_t> fown;   // [nf]
+    std::vector<int32_t> fnb;    // [nf]: neighbour cell, or -1 - bc index
+    std::vector<double> fn;      // [nf][3]  unit normal, owner -> neighbour (out of the domain at walls)
+    std::vector<double> farea;   // [nf]
+    std::vector<ugkwp_bc> bcs;
+};
+
+// Returns UGKWP_OK or UGKWP_E_ARG / UGKWP_E_MESH with a message in *err.
+int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &out, std::string &err);
+
+}  // namespace ugkwp

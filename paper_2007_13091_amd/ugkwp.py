@@ -1,0 +1,235 @@
+"""Python binding of the UGKWP C ABI (include/ugkwp.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libugkwp.so.  PyTorch provides the
+device workspace (one uint8 tensor) and the stream.  There is no fallback: if the library
+or a GPU is missing, construction fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libugkwp.so")
+
+OK, E_ARG, E_MESH, E_CAPACITY, E_LOST, E_NONPHYS, E_DEVICE, E_STATE = range(8)
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_MESH", 3: "E_CAPACITY", 4: "E_LOST", 5: "E_NONPHYS",
+                6: "E_DEVICE", 7: "E_STATE"}
+
+# every entry point the header declares
+SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkwp_step", "ugkwp_moments",
+           "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
+           "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy")
+N_PROFILE_SLOTS = 10
+
+
+class UgkwpBC(C.Structure):
+    _fields_ = [("type", C.c_int32), ("T_w", C.c_double), ("U_w", C.c_double * 3), ("W_inf", C.c_double * 5)]
+
+
+class UgkwpMesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_cells", C.c_int64),
+                ("cell_type", C.POINTER(C.c_uint8)), ("cell_node_off", C.POINTER(C.c_int64)),
+                ("cell_nodes", C.POINTER(C.c_int64)), ("n_bfaces", C.c_int64),
+                ("bface_nodes", C.POINTER(C.c_int64)), ("bface_bc", C.POINTER(C.c_int32)),
+                ("n_bc", C.c_int32), ("bc", C.POINTER(UgkwpBC))]
+
+
+class UgkwpParams(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("mu_ref", C.c_double), ("omega", C.c_double), ("cfl", C.c_double),
+                ("c2", C.c_double), ("n_ref", C.c_int32), ("n_min", C.c_int32), ("recon", C.c_int32),
+                ("precision", C.c_int32), ("capacity", C.c_int64), ("max_crossings", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class UgkwpStats(C.Structure):
+    _fields_ = [("dt", C.c_double), ("t", C.c_double), ("step", C.c_int64), ("n_alive", C.c_int64),
+                ("n_sampled", C.c_int64), ("n_collided", C.c_int64), ("n_escaped", C.c_int64),
+                ("n_moved", C.c_int64), ("crossings", C.c_int64), ("wall_hits", C.c_int64),
+                ("error_word", C.c_uint32), ("moved_total", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class UgkwpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libugkwp.so (built by __graft_entry__.build() / paper_2007_13091_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        L.ugkwp_workspace_bytes.restype = C.c_int32
+        L.ugkwp_workspace_bytes.argtypes = [P(UgkwpMesh), P(UgkwpParams), P(C.c_size_t)]
+        L.ugkwp_init_mesh.restype = C.c_int32
+        L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), P(UgkwpParams), vp, C.c_size_t, vp]
+        L.ugkwp_init_state.restype = C.c_int32
+        L.ugkwp_init_state.argtypes = [vp, P(C.c_double)]
+        L.ugkwp_step.restype = C.c_int32
+        L.ugkwp_step.argtypes = [vp, C.c_int32, P(UgkwpStats)]
+        L.ugkwp_moments.restype = C.c_int32
+        L.ugkwp_moments.argtypes = [vp, C.c_int32, vp, C.c_int32]
+        L.ugkwp_particle_count.restype = C.c_int32
+        L.ugkwp_particle_count.argtypes = [vp, P(C.c_int64)]
+        L.ugkwp_export_particles.restype = C.c_int32
+        L.ugkwp_export_particles.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int32),
+                                             P(C.c_uint64)]
+        L.ugkwp_geometry.restype = C.c_int32
+        L.ugkwp_geometry.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.ugkwp_profile_enable.restype = C.c_int32
+        L.ugkwp_profile_enable.argtypes = [vp, C.c_int32]
+        L.ugkwp_profile_read.restype = C.c_int32
+        L.ugkwp_profile_read.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_int64)]
+        L.ugkwp_profile_slot_name.restype = C.c_char_p
+        L.ugkwp_profile_slot_name.argtypes = [C.c_int32]
+        L.ugkwp_last_error.restype = C.c_char_p
+        L.ugkwp_last_error.argtypes = [vp]
+        L.ugkwp_destroy.restype = None
+        L.ugkwp_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class _MeshArgs:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, mesh):
+        self.xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+        self.ct = np.ascontiguousarray(mesh.cell_type, dtype=np.uint8)
+        self.off = np.ascontiguousarray(mesh.cell_node_off, dtype=np.int64)
+        self.cn = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int64)
+        self.bf = np.ascontiguousarray(mesh.bface_nodes, dtype=np.int64).reshape(-1, 4)
+        self.bt = np.ascontiguousarray(mesh.bface_bc, dtype=np.int32)
+        self.bcs = (UgkwpBC * max(len(mesh.bcs), 1))()
+        for i, b in enumerate(mesh.bcs):
+            self.bcs[i].type = b.type
+            self.bcs[i].T_w = b.Tw
+            for d in range(3):
+                self.bcs[i].U_w[d] = b.Uw[d]
+            for k in range(5):
+                self.bcs[i].W_inf[k] = b.Winf[k]
+        self.s = UgkwpMesh(self.xyz.shape[0], _ptr(self.xyz, C.c_double), self.ct.shape[0], _ptr(self.ct, C.c_uint8),
+                           _ptr(self.off, C.c_int64), _ptr(self.cn, C.c_int64), self.bf.shape[0],
+                           _ptr(self.bf, C.c_int64), _ptr(self.bt, C.c_int32), len(mesh.bcs), self.bcs)
+
+
+def make_params(p, capacity=0, recon=0, precision=0) -> UgkwpParams:
+    return UgkwpParams(p.gamma, p.mu_ref, p.omega, p.cfl, p.c2, p.n_ref, p.n_min, recon, precision, capacity,
+                       p.max_crossings, p.seed)
+
+
+def workspace_bytes(mesh, params, capacity=0) -> int:
+    """Device bytes the library needs (host-side computation: mesh checks and layout)."""
+    L = lib()
+    m = _MeshArgs(mesh)
+    pr = make_params(params, capacity)
+    n = C.c_size_t(0)
+    st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
+    if st != OK:
+        raise UgkwpError(st, L.ugkwp_last_error(None).decode())
+    return int(n.value)
+
+
+class Solver:
+    """One mesh on one GPU.  `mesh`, `params`: see paper_2007_13091_amd.workloads."""
+
+    def __init__(self, mesh, params, capacity=0, device="cuda"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a GPU (the HIP library has no CPU path)")
+        L = lib()
+        self.torch = torch
+        self.nc = mesh.n_cells
+        m = _MeshArgs(mesh)
+        pr = make_params(params, capacity)
+        n = C.c_size_t(0)
+        st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
+        if st != OK:
+            raise UgkwpError(st, L.ugkwp_last_error(None).decode())
+        self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.ws.device)
+        h = C.c_void_p(0)
+        st = L.ugkwp_init_mesh(C.byref(h), C.byref(m.s), C.byref(pr), C.c_void_p(self.ws.data_ptr()), n.value,
+                               C.c_void_p(self.stream.cuda_stream))
+        if st != OK:
+            raise UgkwpError(st, L.ugkwp_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            raise UgkwpError(st, lib().ugkwp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ugkwp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_state(self, W0):
+        W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(self.nc, 5)
+        self._check(lib().ugkwp_init_state(self.h, _ptr(W0, C.c_double)))
+
+    def step(self, n=1, stats=True):
+        """Advance n steps; returns the last step's statistics (synchronising) if stats."""
+        if stats:
+            s = UgkwpStats()
+            self._check(lib().ugkwp_step(self.h, int(n), C.byref(s)))
+            return s.as_dict()
+        self._check(lib().ugkwp_step(self.h, int(n), None))
+        return None
+
+    def moments(self, which=0):
+        out = np.zeros((self.nc, 5), dtype=np.float64)
+        self._check(lib().ugkwp_moments(self.h, int(which), C.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def particle_count(self):
+        n = C.c_int64(0)
+        self._check(lib().ugkwp_particle_count(self.h, C.byref(n)))
+        return int(n.value)
+
+    def particles(self):
+        n = self.particle_count()
+        x = np.zeros((n, 3)); u = np.zeros((n, 3)); m = np.zeros(n)
+        c = np.zeros(n, dtype=np.int32); uid = np.zeros(n, dtype=np.uint64)
+        self._check(lib().ugkwp_export_particles(self.h, _ptr(x, C.c_double), _ptr(u, C.c_double),
+                                                 _ptr(m, C.c_double), _ptr(c, C.c_int32), _ptr(uid, C.c_uint64)))
+        return dict(x=x, u=u, m=m, cell=c, uid=uid)
+
+    def profile(self, on=True):
+        """Bracket each kernel group of a step with hip events (measurement support)."""
+        self._check(lib().ugkwp_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{slot name: (total ms, timed launches)} since the last read; waits for the stream."""
+        ms = np.zeros(N_PROFILE_SLOTS)
+        cnt = np.zeros(N_PROFILE_SLOTS, dtype=np.int64)
+        self._check(lib().ugkwp_profile_read(self.h, N_PROFILE_SLOTS, _ptr(ms, C.c_double), _ptr(cnt, C.c_int64)))
+        return {lib().ugkwp_profile_slot_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(N_PROFILE_SLOTS)}
+
+    def geometry(self):
+        vol = np.zeros(self.nc); xc = np.zeros((self.nc, 3)); dS = np.zeros((self.nc, 3))
+        self._check(lib().ugkwp_geometry(self.h, _ptr(vol, C.c_double), _ptr(xc, C.c_double), _ptr(dS, C.c_double)))
+        return vol, xc, dS

@@ -1,0 +1,73 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every symbol the header declares,
+and its host-side mesh checks (ugkwp_workspace_bytes, no device call) accept the workloads
+and reject broken meshes and parameters with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2007_13091_amd import ugkwp as U
+from paper_2007_13091_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ugkwp.h")).read()
+    declared = set(re.findall(r"\b(ugkwp_[a-z_]+)\s*\(", hdr))
+    assert declared == set(U.SYMBOLS)
+    L = U.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_for_workloads():
+    for w in (wl.sod(), wl.cavity(n=8), wl.closed_box(tets=True, jitter=0.1)):
+        n = U.workspace_bytes(w.mesh, w.params)
+        assert n > 0 and n % 256 == 0
+    # the cavity at full size: particle buffers dominate (2 x 68 B x capacity)
+    w = wl.cavity()
+    n = U.workspace_bytes(w.mesh, w.params)
+    cap = 2 * 400 * 32**3 + 65536
+    assert n > 2 * 68 * cap
+
+
+def test_mesh_errors_are_reported():
+    w = wl.sod(nx=4, ny=1, nz=1)
+    m = w.mesh
+    # drop one boundary face: its cell face is neither shared nor tagged
+    bad = wl.Mesh(m.xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes[1:], m.bface_bc[1:], m.bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_MESH
+    # a hex that is not an axis-aligned box
+    xyz = m.xyz.copy()
+    xyz[m.cell_nodes[6]] += 1e-3
+    bad = wl.Mesh(xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes, m.bface_bc, m.bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_MESH
+    # an untagged boundary face (tag out of range)
+    bt = m.bface_bc.copy()
+    bt[0] = 7
+    bad = wl.Mesh(m.xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes, bt, m.bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_MESH
+
+
+def test_param_errors_are_reported():
+    w = wl.sod(nx=4, ny=1, nz=1)
+    for field, val in (("gamma", 1.4), ("mu_ref", -1.0), ("cfl", 1.5), ("n_ref", 0)):
+        p = wl.Params(**{**w.params.__dict__, field: val})
+        with pytest.raises(U.UgkwpError) as e:
+            U.workspace_bytes(w.mesh, p)
+        assert e.value.status == U.E_ARG, field
+
+
+def test_tet_meshes_pass_host_checks():
+    w = wl.sod(nx=6, ny=2, nz=2, tets=True)
+    assert U.workspace_bytes(w.mesh, w.params) > 0
+    w = wl.closed_box(n=(3, 3, 3), tets=True, jitter=0.15)
+    assert U.workspace_bytes(w.mesh, w.params) > 0
