@@ -41,6 +41,8 @@ def compare_particles(pg, po, length=1.0, vscale=1.0, rtol=RTOL, what=""):
     np.testing.assert_array_equal(pg["uid"][ig], po["uid"][io], err_msg=f"{what} particle ids")
     np.testing.assert_array_equal(pg["cell"][ig].astype(np.int64), po["cell"][io].astype(np.int64),
                                   err_msg=f"{what} particle cells")
+    if pg["uid"].size == 0:
+        return
     dx = np.abs(pg["x"][ig] - po["x"][io]).max() / length
     du = np.abs(pg["u"][ig] - po["u"][io]).max() / vscale
     # particle masses: m = rho^hp Omega / N_sam, and rho^h = rho - rho^p cancels where particles
