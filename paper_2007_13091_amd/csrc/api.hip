@@ -121,6 +121,7 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.edge = C.take<double>(9 * nc);
     D.nfc = C.take<uint8_t>(nc);
     D.ctype = C.take<uint8_t>(nc);
+    D.box = C.take<double>(6 * nc);
     D.plane = C.take<double4>(6 * nc);
     D.nbl = C.take<int2>(6 * nc);
     D.cface = C.take<int32_t>(6 * nc);
@@ -144,6 +145,11 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.off = C.take<int32_t>(2 * nc + 1);
     D.cursor = C.take<int32_t>(2 * nc);
     D.scan32 = C.take<int32_t>((size_t)ugkwp::scan_partials_needed(2 * (long long)nc));
+    D.spart = C.take<unsigned long long>(128);
+    D.cnts = C.take<int32_t>(2 * nc);
+    D.rank = C.take<int32_t>((size_t)cap);
+    D.segoff[0] = C.take<int32_t>(nc + 1);
+    D.segoff[1] = C.take<int32_t>(nc + 1);
     D.key = C.take<int32_t>((size_t)cap);
     D.perm = C.take<int32_t>((size_t)cap);
     for (int b = 0; b < 2; ++b) {
@@ -302,8 +308,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     D.max_cross = p->max_crossings;
     D.seed = p->seed;
     D.cap = cap;
-    // a 64-wide block per cell where cells hold few particles, 256 otherwise
-    ctx->gather_bs = (p->n_ref > 128 || p->n_min > 128) ? 256 : 64;
+    // one wave per cell: blocks of 64 threads need no cross-wave barriers
+    ctx->gather_bs = 64;
 
     hipStream_t s = ctx->stream;
     const size_t nc = (size_t)H.nc, nf = (size_t)H.nf;
@@ -326,6 +332,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     e = e ? e : up((double *)D.vol, H.vol, s);
     e = e ? e : up((double *)D.dS, dS, s);
     e = e ? e : up((double *)D.orig, org, s);
+    e = e ? e : up((double *)D.box, H.box, s);
     e = e ? e : up((double *)D.edge, edg, s);
     e = e ? e : up((uint8_t *)D.nfc, H.nfc, s);
     e = e ? e : up((uint8_t *)D.ctype, H.ctype, s);
@@ -364,6 +371,8 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     HIPCHK(ctx, up(D.W, Wt, s));
     ugkwp::launch_fill_f64(D.P, 5 * (long long)nc, 0.0, s);
     ugkwp::launch_fill_i32(D.nleft, (long long)nc, 0, s);
+    ugkwp::launch_fill_i32(D.segoff[0], (long long)nc + 1, 0, s);
+    ugkwp::launch_fill_i32(D.segoff[1], (long long)nc + 1, 0, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipStreamSynchronize(s));

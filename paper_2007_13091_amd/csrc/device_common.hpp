@@ -16,6 +16,9 @@ enum : uint32_t {
 
 enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5 };
 
+// bucket key flag: the particle stays collisionless in the cell it started in
+constexpr int32_t kStayBit = 1 << 30;
+
 struct DevBC {
     int32_t type;
     int32_t pad;
@@ -56,6 +59,7 @@ struct Dev {
     const double *edge;     // [9][nc]  edge k component d at [3k+d][nc]
     const uint8_t *nfc;     // [nc]
     const uint8_t *ctype;   // [nc]
+    const double *box;      // [nc][6] lo[3], hi[3] of box hexes (unused for tetrahedra)
     const double4 *plane;   // [nc*6]  (n, d) outward
     const int2 *nbl;        // [nc*6]  (neighbour or -1-bc, local face in neighbour)
     const int32_t *cface;   // [nc*6]  +-(f+1)
@@ -86,6 +90,10 @@ struct Dev {
     int32_t *off;           // [2nc+1]
     int32_t *cursor;        // [2nc]
     int32_t *scan32;        // scan partials
+    unsigned long long *spart; // [2][64] crossings and wall hits, spread over 64 slots
+    int32_t *cnts;          // [2nc] stayers per bucket
+    int32_t *rank;          // [cap] slot of a mover / collided particle inside its bucket
+    int32_t *segoff[2];     // [nc+1] each: survivor segments per cell in pa[0] / pa[1]
     int32_t *key;           // [cap]
     int32_t *perm;          // [cap]
     Particles pa[2];

@@ -253,10 +253,6 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Scalars *s = D.sc;
         s->n_sampled = 0;
-        s->n_collided = 0;
-        s->n_escaped = 0;
-        s->n_cross = 0;
-        s->n_wall = 0;
     }
     double r = INFINITY;
     if (c < D.nc) {
@@ -331,6 +327,12 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
         }
     }
     D.nsam[c] = ns;
+}
+
+// bucket sizes: movers / collided (cnt) plus stayers (cnts)
+__global__ void k_bucket_total(Dev D) {
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 2LL * D.nc) D.cursor[k] = D.cnt[k] + D.cnts[k];
 }
 
 // capacity check of the step: old + new must fit
@@ -508,9 +510,29 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
 }
 
 // ---------------------------------------------------------------------------------------
-// S4 + S5: free-flight time and face-to-face transport of one particle.
-// Returns 0 inside (cell updated), 1 escaped through a far-field face, -1 lost.
+// S4 + S5: face-to-face transport of one particle for time ts (Sec. 2.3).
+// Exit time over the faces with n.u > 0 other than the entry face, clamped at 0, lowest local
+// face on a tie; an exit time >= the remaining time keeps the particle in the cell.
+// Box hexes take a path that evaluates only the three candidate faces; its arithmetic is
+// the plane formula (d - n.x) / (n.u) with n = +-e_d, term by term, so both paths give the
+// same bits.  Returns 0 inside (cell updated), 1 escaped through a far-field face, -1 lost.
 // ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, const double n[3], double u[3],
+                                               uint64_t uid, long long step, int bounce) {
+    // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential components
+    // N(U_w, T_w) in the face frame
+    U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
+    double t1[3], t2[3];
+    face_frame(n, t1, t2);
+    const double sq = sqrt(b.Tw);
+    const double vn = sqrt(-2.0 * b.Tw * log(unif(r.v[0])));
+    const double rr = sqrt(-2.0 * log(unif(r.v[1])));
+    const double a = 2.0 * kPi * unif(r.v[2]);
+    const double X1 = rr * cos(a), X2 = rr * sin(a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+}
+
 __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double ts, uint64_t uid, long long step,
                      int &ncross, int &nwall) {
     int c = cell;
@@ -519,19 +541,46 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
     int bounce = 0;
     ncross = 0;
     for (;;) {
-        const int nfc = D.nfc[c];
         double best = INFINITY;
         int bf = -1;
-        for (int lf = 0; lf < nfc; ++lf) {
-            if (lf == entry) continue;
-            const double4 p = D.plane[c * 6 + lf];
-            const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
-            if (un > 0.0) {
-                double tt = (p.w - (p.x * x[0] + p.y * x[1] + p.z * x[2])) / un;
-                if (tt < 0.0) tt = 0.0;
-                if (tt < best) {
-                    best = tt;
-                    bf = lf;
+        if (D.ctype[c] == 8) {
+            const double *B = D.box + 6 * c;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double ud = u[d];
+                if (ud > 0.0) {
+                    if (2 * d + 1 != entry) {
+                        double tt = (B[3 + d] - x[d]) / ud;
+                        if (tt < 0.0) tt = 0.0;
+                        if (tt < best) {
+                            best = tt;
+                            bf = 2 * d + 1;
+                        }
+                    }
+                } else if (ud < 0.0) {
+                    if (2 * d != entry) {
+                        double tt = (x[d] - B[d]) / (-ud);
+                        if (tt < 0.0) tt = 0.0;
+                        if (tt < best) {
+                            best = tt;
+                            bf = 2 * d;
+                        }
+                    }
+                }
+            }
+        } else {
+            const int nfc = D.nfc[c];
+            for (int lf = 0; lf < nfc; ++lf) {
+                if (lf == entry) continue;
+                const double4 p = D.plane[c * 6 + lf];
+                const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
+                if (un > 0.0) {
+                    double tt = (p.w - (p.x * x[0] + p.y * x[1] + p.z * x[2])) / un;
+                    if (tt < 0.0) tt = 0.0;
+                    if (tt < best) {
+                        best = tt;
+                        bf = lf;
+                    }
                 }
             }
         }
@@ -557,29 +606,25 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
             continue;
         }
         const DevBC &b = D.bc[-1 - nb.x];
-        const double4 p = D.plane[c * 6 + bf];
-        const double n[3] = {p.x, p.y, p.z};
         if (b.type == 0) {
-            const double un = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
-            u[0] = u[0] - 2.0 * un * n[0];
-            u[1] = u[1] - 2.0 * un * n[1];
-            u[2] = u[2] - 2.0 * un * n[2];
+            if (D.ctype[c] == 8) {
+                // u - 2 (u.n) n with n = +-e_d flips exactly component d
+                const int d = bf >> 1;
+                u[d] = -u[d];
+            } else {
+                const double4 p = D.plane[c * 6 + bf];
+                const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
+                u[0] = u[0] - 2.0 * un * p.x;
+                u[1] = u[1] - 2.0 * un * p.y;
+                u[2] = u[2] - 2.0 * un * p.z;
+            }
             entry = bf;
         } else if (b.type == 1) {
-            // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential
-            // components N(U_w, T_w) in the face frame
-            U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
+            const double4 p = D.plane[c * 6 + bf];
+            const double n[3] = {p.x, p.y, p.z};
+            reemit_diffuse(D, b, n, u, uid, step, bounce);
             ++bounce;
             ++nwall;
-            double t1[3], t2[3];
-            face_frame(n, t1, t2);
-            const double sq = sqrt(b.Tw);
-            const double vn = sqrt(-2.0 * b.Tw * log(unif(r.v[0])));
-            const double rr = sqrt(-2.0 * log(unif(r.v[1])));
-            const double a = 2.0 * kPi * unif(r.v[2]);
-            const double X1 = rr * cos(a), X2 = rr * sin(a);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) u[d] = b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
             entry = bf;
         } else {
             cell = c;
@@ -588,84 +633,102 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
     }
 }
 
-// One thread per particle (grid stride).  Key of the end bucket: end cell for particles
-// that stay collisionless, nc + end cell for collided ones, -1 for escaped.
+// One thread per particle; blocks past the live particles exit at once.  The free-flight
+// time of an old particle is t_f = -tau ln eta with tau of its start cell; it collides iff
+// t_f < dt.  Since t_f < dt <=> eta > exp(-dt/tau), eta clear of exp(-dt/tau) by a relative
+// 1e-12 decides the comparison without the logarithm (the same decision as the formula; the
+// formula itself is evaluated near the threshold and for every collided particle).
+// Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
+// (escaped).  Bucket counts by wave-aggregated integer atomics; crossings and wall hits per
+// block into partial slots (reduced in k_finalize).
 __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
+    __shared__ unsigned long long red[2][4];
     const Scalars *sc = D.sc;
     const long long n_old = sc->n_old;
     const long long n_tot = n_old + sc->n_new;
+    const long long i0 = (long long)blockIdx.x * blockDim.x;
+    if (i0 >= n_tot) return;
+    const long long i = i0 + threadIdx.x;
     const double dt = sc->dt;
     const long long step = sc->step;
     const Particles pa = D.pa[buf];
     const int nc = D.nc;
-    unsigned long long ncoll = 0, nesc = 0, ncross = 0, nwall = 0;
+    int key = -1;
+    bool stay = false;
+    unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 < n_tot; i0 += stride) {
-        const long long i = i0 + threadIdx.x;
-        int key = -1;
-        if (i < n_tot) {
-            int c = pa.cell[i];
-            const uint64_t uid = pa.uid[i];
-            double x[3] = {pa.x0[i], pa.x1[i], pa.x2[i]};
-            double u[3] = {pa.u0[i], pa.u1[i], pa.u2[i]};
-            double ts = dt;
-            bool collided = false;
-            if (i < n_old) {
-                U4 r = draw(D.seed, uid, step, kTagTF, 0);
-                const double tf = -D.tau[c] * log(unif(r.v[0]));
+    if (i < n_tot) {
+        int c = pa.cell[i];
+        const int c0 = c;
+        const uint64_t uid = pa.uid[i];
+        double x[3] = {pa.x0[i], pa.x1[i], pa.x2[i]};
+        double u[3] = {pa.u0[i], pa.u1[i], pa.u2[i]};
+        double ts = dt;
+        bool collided = false;
+        if (i < n_old) {
+            const U4 r = draw(D.seed, uid, step, kTagTF, 0);
+            const double eta = unif(r.v[0]);
+            const double e = D.ec[c];
+            if (!(eta < e * (1.0 - 1e-12))) {
+                const double tf = -D.tau[c] * log(eta);
                 if (tf < dt) {
                     ts = tf;
                     collided = true;
                 }
             }
-            int nx = 0, nw = 0;
-            const int rc = track(D, x, u, c, ts, uid, step, nx, nw);
-            ncross += (unsigned long long)nx;
-            nwall += (unsigned long long)nw;
-            pa.x0[i] = x[0];
-            pa.x1[i] = x[1];
-            pa.x2[i] = x[2];
-            pa.u0[i] = u[0];
-            pa.u1[i] = u[1];
-            pa.u2[i] = u[2];
-            pa.cell[i] = c;
-            if (rc == 1) {
-                ++nesc;
-            } else {
-                if (rc < 0) lost = true;
-                if (collided) ++ncoll;
-                key = collided ? nc + c : c;
-            }
-            D.key[i] = key;
         }
-        agg_slot(D.cnt, key);
+        int nx = 0, nw = 0;
+        const int rc = track(D, x, u, c, ts, uid, step, nx, nw);
+        nx_ = (unsigned long long)nx;
+        nw_ = (unsigned long long)nw;
+        pa.x0[i] = x[0];
+        pa.x1[i] = x[1];
+        pa.x2[i] = x[2];
+        pa.u0[i] = u[0];
+        pa.u1[i] = u[1];
+        pa.u2[i] = u[2];
+        pa.cell[i] = c;
+        if (rc != 1) {
+            lost = rc < 0;
+            key = collided ? nc + c : c;
+            stay = !collided && c == c0;
+        }
+        D.key[i] = stay ? (key | kStayBit) : key;
     }
+    // stayers are only counted; movers and collided particles get their slot in the bucket
+    agg_slot(D.cnts, stay ? key : -1);
+    const int slot = agg_slot(D.cnt, stay ? -1 : key);
+    if (key >= 0 && !stay) D.rank[i] = slot;
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
-    ncoll = wave_sum_u64(ncoll);
-    nesc = wave_sum_u64(nesc);
-    ncross = wave_sum_u64(ncross);
-    nwall = wave_sum_u64(nwall);
+    nx_ = wave_sum_u64(nx_);
+    nw_ = wave_sum_u64(nw_);
+    const int wave = threadIdx.x / kWave;
     if (lane_id() == 0) {
-        Scalars *s = D.sc;
-        if (ncoll) atomicAdd(&s->n_collided, ncoll);
-        if (nesc) atomicAdd(&s->n_escaped, nesc);
-        if (ncross) atomicAdd(&s->n_cross, ncross);
-        if (nwall) atomicAdd(&s->n_wall, nwall);
+        red[0][wave] = nx_;
+        red[1][wave] = nw_;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const unsigned long long b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        const int slot64 = blockIdx.x & 63;
+        if (a) atomicAdd(&D.spart[slot64], a);
+        if (b) atomicAdd(&D.spart[64 + slot64], b);
     }
 }
 
-// bucket the particle indices by key: perm[off[key] + slot] = i
+// bucket the movers (collisionless particles that changed cell) and the collided particles:
+// perm[off[key] + rank] = i, rank handed out in k_stream (cnt holds their number per bucket)
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
     const Scalars *sc = D.sc;
     const long long n_tot = sc->n_old + sc->n_new;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i0 = (long long)blockIdx.x * blockDim.x; i0 < n_tot; i0 += stride) {
-        const long long i = i0 + threadIdx.x;
-        const int key = i < n_tot ? D.key[i] : -1;
-        const int slot = agg_slot(D.cursor, key);
-        if (key >= 0) D.perm[D.off[key] + slot] = (int32_t)i;
-    }
+    const long long i0 = (long long)blockIdx.x * blockDim.x;
+    if (i0 >= n_tot) return;
+    const long long i = i0 + threadIdx.x;
+    if (i >= n_tot) return;
+    const int key = D.key[i];
+    // stayers are collected by the gather from their own segment
+    if (key >= 0 && !(key & kStayBit)) D.perm[D.off[key] + D.rank[i]] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -734,24 +797,61 @@ __device__ void block_sum5(double v[5], double *red /* [BS/64][5] LDS */) {
 constexpr int kSortLDS = 4096;
 
 // ---------------------------------------------------------------------------------------
-// S6: one block per cell.  Survivors ending in the cell are written, in ascending source
-// order, to the next buffer; sums over survivors give P^{n+1}, sums over every particle
-// ending in the cell give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.
+// S6: one block per cell c.  The survivors ending in c are laid out in the next buffer as
+//   [movers into c, ascending source index] [stayers of c, in their segment order]
+// where stayers (collisionless, ended where they started) are found by scanning c's own
+// start segments (old particles, then the ones sampled this step) and movers come bucketed
+// by k_scatter.  Sums over survivors give P^{n+1}; with the collided particles ending in c
+// they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-thread
+// assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
 template <int BS>
+__device__ __forceinline__ void take_phi(const Particles &src, int s, double acc[5], double &m, double &u0,
+                                         double &u1, double &u2) {
+    m = src.m[s];
+    u0 = src.u0[s];
+    u1 = src.u1[s];
+    u2 = src.u2[s];
+    acc[0] += m;
+    acc[1] += m * u0;
+    acc[2] += m * u1;
+    acc[3] += m * u2;
+    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+}
+
+__device__ __forceinline__ void put(const Particles &src, const Particles &dst, int s, int o, int c, double m,
+                                    double u0, double u1, double u2) {
+    dst.x0[o] = src.x0[s];
+    dst.x1[o] = src.x1[s];
+    dst.x2[o] = src.x2[s];
+    dst.u0[o] = u0;
+    dst.u1[o] = u1;
+    dst.u2[o] = u2;
+    dst.m[o] = m;
+    dst.cell[o] = c;
+    dst.uid[o] = src.uid[s];
+}
+
+template <int BS>
 __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
-    __shared__ int lds[kSortLDS];
+    constexpr int kLds = BS == 64 ? 1024 : kSortLDS;
+    __shared__ int lds[kLds];
     __shared__ double red[(BS / kWave) * 5];
+    __shared__ int wtot[BS / kWave];
     const int c = blockIdx.x;
     const int nc = D.nc;
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
+    const Scalars *sc = D.sc;
     double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
+    const int base = D.off[c];
+    const int nmov = D.cnt[c];
+    // movers (part 0) and collided (part 1): sorted source lists
     for (int part = 0; part < 2; ++part) {
-        const int k0 = part == 0 ? c : nc + c;
-        const int a0 = D.off[k0], a1 = D.off[k0 + 1];
-        const int len = a1 - a0;
+        const int a0 = part == 0 ? base : D.off[nc + c];
+        const int len = part == 0 ? nmov : D.off[nc + c + 1] - a0;
         int *list;
-        if (len <= kSortLDS) {
+        if (len <= kLds) {
             for (int j = threadIdx.x; j < len; j += BS) lds[j] = D.perm[a0 + j];
             __syncthreads();
             list = lds;
@@ -759,30 +859,47 @@ __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
             list = D.perm + a0;
         }
         block_sort<BS>(list, len);
-        double *acc = part == 0 ? Pn : Cn;
         for (int j = threadIdx.x; j < len; j += BS) {
             const int s = list[j];
-            const double m = src.m[s];
-            const double u0 = src.u0[s], u1 = src.u1[s], u2 = src.u2[s];
-            acc[0] += m;
-            acc[1] += m * u0;
-            acc[2] += m * u1;
-            acc[3] += m * u2;
-            acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
-            if (part == 0) {
-                const int o = a0 + j;
-                dst.x0[o] = src.x0[s];
-                dst.x1[o] = src.x1[s];
-                dst.x2[o] = src.x2[s];
-                dst.u0[o] = u0;
-                dst.u1[o] = u1;
-                dst.u2[o] = u2;
-                dst.m[o] = m;
-                dst.cell[o] = c;
-                dst.uid[o] = src.uid[s];
-            }
+            double m, u0, u1, u2;
+            take_phi<BS>(src, s, part == 0 ? Pn : Cn, m, u0, u1, u2);
+            if (part == 0) put(src, dst, s, a0 + j, c, m, u0, u1, u2);
         }
         __syncthreads();
+    }
+    // stayers: own segment of old particles, then own new particles, compacted in order
+    const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
+    int pos = base + nmov;
+    for (int seg = 0; seg < 2; ++seg) {
+        long long s0, s1;
+        if (seg == 0) {
+            s0 = D.segoff[buf][c];
+            s1 = D.segoff[buf][c + 1];
+        } else {
+            s0 = sc->n_old + D.samoff[c];
+            s1 = sc->n_old + D.samoff[c + 1];
+            if (sc->n_new == 0) s1 = s0;
+        }
+        for (long long j0 = s0; j0 < s1; j0 += BS) {
+            const long long j = j0 + threadIdx.x;
+            const bool st = j < s1 && (D.key[j] & kStayBit) != 0 && D.key[j] >= 0;
+            const unsigned long long msk = __ballot(st);
+            if (lane == 0) wtot[wave] = (int)__popcll(msk);
+            __syncthreads();
+            int before = 0, tot = 0;
+            for (int w = 0; w < BS / kWave; ++w) {
+                before += w < wave ? wtot[w] : 0;
+                tot += wtot[w];
+            }
+            if (st) {
+                const int o = pos + before + (int)__popcll(msk & below);
+                double m, u0, u1, u2;
+                take_phi<BS>(src, (int)j, Pn, m, u0, u1, u2);
+                put(src, dst, (int)j, o, c, m, u0, u1, u2);
+            }
+            pos += tot;
+            __syncthreads();
+        }
     }
     block_sum5<BS>(Pn, red);
     block_sum5<BS>(Cn, red);
@@ -806,19 +923,43 @@ __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
             D.P[k * nc + c] = Pn[k];
         }
         D.nleft[c] = D.off[c + 1] - D.off[c];
+        D.segoff[buf ^ 1][c] = D.off[c];
+        if (pos != D.off[c + 1]) atomicOr(&D.sc->err, kErrCapacity);
     }
 }
 
-__global__ void k_finalize(Dev D) {
+__global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
+    __shared__ unsigned long long red[2][64];
     Scalars *s = D.sc;
-    const long long alive = D.off[D.nc];
-    s->moved_total = s->moved_total + (unsigned long long)(s->n_old + s->n_new);
-    s->n_alive = alive;
-    s->n_old = alive;
-    s->n_new = 0;
-    s->t = s->t + s->dt;
-    s->step = s->step + 1;
-    s->dtmin_bits = 0x7FF0000000000000ULL;
+    const long long n_tot = s->n_old + s->n_new;
+    if (threadIdx.x < 64) {
+        red[0][threadIdx.x] = D.spart[threadIdx.x];
+        red[1][threadIdx.x] = D.spart[64 + threadIdx.x];
+    }
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long alive = D.off[D.nc];
+        const long long ended = D.off[2 * D.nc];
+        s->n_cross = red[0][0];
+        s->n_wall = red[1][0];
+        s->n_collided = (unsigned long long)(ended - alive);
+        s->n_escaped = (unsigned long long)(n_tot - ended);
+        s->moved_total = s->moved_total + (unsigned long long)n_tot;
+        s->n_alive = alive;
+        s->n_old = alive;
+        D.segoff[buf ^ 1][D.nc] = (int32_t)alive;
+        s->n_new = 0;
+        s->t = s->t + s->dt;
+        s->step = s->step + 1;
+        s->dtmin_bits = 0x7FF0000000000000ULL;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -943,7 +1084,7 @@ void scan(const T *in, long long n, T *out, T *part, hipStream_t s) {
 
 long long scan_partials_needed(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-int particle_grid() { return 2048; }
+long long stream_blocks(long long cap) { return (cap + 255) / 256; }
 
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s) {
     if (n > 0) k_fill<int32_t><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
@@ -967,7 +1108,8 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     scan<long long>(D.nsam, nc, D.samoff, D.scan64, s);
     k_sample_setup<<<1, 1, 0, s>>>(D);
     k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt, 2LL * nc, 0);
-    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cursor, 2LL * nc, 0);
+    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnts, 2LL * nc, 0);
+    k_fill<unsigned long long><<<1, 128, 0, s>>>(D.spart, 128, 0ULL);
     pr->end(kSlotScan);
     pr->begin(kSlotFlux);
     if (nf > 0) k_flux<<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
@@ -976,13 +1118,15 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     k_sample<<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
     pr->end(kSlotSample);
     pr->begin(kSlotStream);
-    k_stream<<<particle_grid(), 256, 0, s>>>(D, buf);
+    const unsigned pb = (unsigned)stream_blocks(D.cap);
+    k_stream<<<pb, 256, 0, s>>>(D, buf);
     pr->end(kSlotStream);
     pr->begin(kSlotScan2);
-    scan<int32_t>(D.cnt, 2LL * nc, D.off, D.scan32, s);
+    k_bucket_total<<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D);
+    scan<int32_t>(D.cursor, 2LL * nc, D.off, D.scan32, s);
     pr->end(kSlotScan2);
     pr->begin(kSlotScatter);
-    k_scatter<<<particle_grid(), 256, 0, s>>>(D);
+    k_scatter<<<pb, 256, 0, s>>>(D);
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
     if (gather_bs == 64)
@@ -991,7 +1135,7 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
         k_gather<256><<<nc, 256, 0, s>>>(D, buf);
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
-    k_finalize<<<1, 1, 0, s>>>(D);
+    k_finalize<<<1, 256, 0, s>>>(D, buf);
     pr->end(kSlotFinal);
 }
 

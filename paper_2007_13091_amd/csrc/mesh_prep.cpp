@@ -86,6 +86,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     H.nblf.assign((size_t)nc * kMaxFaces, -1);
     H.cface.assign((size_t)nc * kMaxFaces, 0);
     H.orig.assign(3 * (size_t)nc, 0.0);
+    H.box.assign(6 * (size_t)nc, 0.0);
     H.edge.assign(9 * (size_t)nc, 0.0);
     H.bcs.assign(m.bc, m.bc + m.n_bc);
     std::vector<double> larea((size_t)nc * kMaxFaces, 0.0);
@@ -128,6 +129,8 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
                 }
                 H.xc[3 * c + d] = 0.5 * (lo[d] + hi[d]);
                 H.orig[3 * c + d] = lo[d];
+                H.box[6 * c + d] = lo[d];
+                H.box[6 * c + 3 + d] = hi[d];
                 H.edge[9 * c + 4 * d] = ext[d];
             }
             H.vol[c] = ext[0] * ext[1] * ext[2];

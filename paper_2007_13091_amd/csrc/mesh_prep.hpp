@@ -23,6 +23,7 @@ struct HostMesh {
     std::vector<int32_t> nb;     // [nc][6]: neighbour cell, or -1 - bc index at a boundary
     std::vector<int32_t> nblf;   // [nc][6]: the face's local index in the neighbour (-1 at a boundary)
     std::vector<int32_t> cface;  // [nc][6]: global face f as f + 1 (owner) or -(f + 1) (neighbour)
+    std::vector<double> box;     // [nc][6]  lo[3], hi[3] of a box hex (the exact node coordinates)
     std::vector<double> orig;    // [nc][3]  sampling frame: x = orig + s e1 + t e2 + w e3
     std::vector<double> edge;    // [nc][3][3]
     std::vector<int32_t> fown;   // [nf]
