@@ -76,8 +76,9 @@ struct EventProf : ugkwp::Prof {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
-const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep", "scan_sample", "flux", "sample",
-                                             "stream", "scan_buckets", "scatter", "gather", "finalize"};
+const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep", "scan_sample", "flux",   "sample",
+                                             "stream",  "count",     "scan_buckets", "scatter", "gather",
+                                             "finalize"};
 }  // namespace
 
 struct ugkwp_ctx {
@@ -146,7 +147,7 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.cursor = C.take<int32_t>(2 * nc);
     D.scan32 = C.take<int32_t>((size_t)ugkwp::scan_partials_needed(2 * (long long)nc));
     D.spart = C.take<unsigned long long>(128);
-    D.cnts = C.take<int32_t>(2 * nc);
+    D.cnt64 = C.take<unsigned long long>(2 * nc);
     D.rank = C.take<int32_t>((size_t)cap);
     D.segoff[0] = C.take<int32_t>(nc + 1);
     D.segoff[1] = C.take<int32_t>(nc + 1);
@@ -154,15 +155,8 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.perm = C.take<int32_t>((size_t)cap);
     for (int b = 0; b < 2; ++b) {
         ugkwp::Particles &P = D.pa[b];
-        P.x0 = C.take<double>((size_t)cap);
-        P.x1 = C.take<double>((size_t)cap);
-        P.x2 = C.take<double>((size_t)cap);
-        P.u0 = C.take<double>((size_t)cap);
-        P.u1 = C.take<double>((size_t)cap);
-        P.u2 = C.take<double>((size_t)cap);
-        P.m = C.take<double>((size_t)cap);
+        P.rec = C.take<ugkwp::PRec>((size_t)cap);
         P.cell = C.take<int32_t>((size_t)cap);
-        P.uid = C.take<uint64_t>((size_t)cap);
     }
     D.sc = C.take<Scalars>(1);
     return (C.off + 255) & ~size_t(255);
@@ -443,22 +437,19 @@ int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, 
     int32_t st = ugkwp_particle_count(ctx, &n);
     if (st != UGKWP_OK) return st;
     const ugkwp::Particles &P = ctx->D.pa[ctx->buf];
-    std::vector<double> tmp((size_t)n);
-    double *const xs[3] = {P.x0, P.x1, P.x2};
-    double *const us[3] = {P.u0, P.u1, P.u2};
-    for (int d = 0; d < 3 && n > 0; ++d) {
-        if (x) {
-            HIPCHK(ctx, hipMemcpy(tmp.data(), xs[d], n * sizeof(double), hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < n; ++i) x[3 * i + d] = tmp[i];
+    if (n > 0) {
+        std::vector<ugkwp::PRec> rec((size_t)n);
+        HIPCHK(ctx, hipMemcpy(rec.data(), P.rec, n * sizeof(ugkwp::PRec), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) {
+                if (x) x[3 * i + d] = rec[i].x[d];
+                if (u) u[3 * i + d] = rec[i].u[d];
+            }
+            if (m) m[i] = rec[i].m;
+            if (uid) uid[i] = rec[i].uid;
         }
-        if (u) {
-            HIPCHK(ctx, hipMemcpy(tmp.data(), us[d], n * sizeof(double), hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < n; ++i) u[3 * i + d] = tmp[i];
-        }
+        if (cell) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
     }
-    if (m && n > 0) HIPCHK(ctx, hipMemcpy(m, P.m, n * sizeof(double), hipMemcpyDeviceToHost));
-    if (cell && n > 0) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (uid && n > 0) HIPCHK(ctx, hipMemcpy(uid, P.uid, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
     return UGKWP_OK;
 }
 

@@ -42,12 +42,18 @@ struct Scalars {
     unsigned int pad;
 };
 
+// One particle: position, velocity, mass and id in a 64-byte record, so that a particle
+// read from anywhere costs one memory transaction; the cell index lives in its own array.
+struct alignas(64) PRec {
+    double x[3];
+    double u[3];
+    double m;
+    uint64_t uid;
+};
+
 struct Particles {
-    double *x0, *x1, *x2;
-    double *u0, *u1, *u2;
-    double *m;
+    PRec *rec;
     int32_t *cell;
-    uint64_t *uid;
 };
 
 struct Dev {
@@ -86,12 +92,12 @@ struct Dev {
     long long *nsam;        // [nc]
     long long *samoff;      // [nc+1]
     long long *scan64;      // scan partials
-    int32_t *cnt;           // [2nc]
+    int32_t *cnt;           // [2nc] movers (or collided) per bucket
     int32_t *off;           // [2nc+1]
     int32_t *cursor;        // [2nc]
     int32_t *scan32;        // scan partials
     unsigned long long *spart; // [2][64] crossings and wall hits, spread over 64 slots
-    int32_t *cnts;          // [2nc] stayers per bucket
+    unsigned long long *cnt64; // [2nc] per bucket: stayers << 32 | movers (or collided)
     int32_t *rank;          // [cap] slot of a mover / collided particle inside its bucket
     int32_t *segoff[2];     // [nc+1] each: survivor segments per cell in pa[0] / pa[1]
     int32_t *key;           // [cap]

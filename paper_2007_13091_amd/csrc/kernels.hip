@@ -38,13 +38,25 @@ struct U4 {
     uint64_t v[4];
 };
 
+// 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds (v_mad_u64_u32); the low
+// half reuses the partial products of the high half
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    const uint64_t p0 = (uint64_t)al * bl;
+    const uint64_t t = (uint64_t)al * bh + (p0 >> 32);
+    const uint64_t v = (uint64_t)ah * bl + (t & 0xFFFFFFFFULL);
+    hi = (uint64_t)ah * bh + ((t >> 32) + (v >> 32));
+    lo = (v << 32) | (p0 & 0xFFFFFFFFULL);
+}
+
 __device__ __forceinline__ U4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1) {
     constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
     constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, c0, hi0, lo0);
+        mulhilo64(M1, c2, hi1, lo1);
         uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -224,24 +236,30 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-// Wave-aggregated slot allocation: every lane with key >= 0 gets old(cnt[key]) + its rank
-// among the lanes of the wave holding the same key.  Must be called by the whole wave.
-__device__ __forceinline__ int agg_slot(int32_t *cnt, int key) {
+// Bucket counting for k_stream: lanes are grouped by key with ballots only; then every
+// group leader issues its 64-bit atomic in the same instruction (movers in the low word,
+// stayers in the high word), so the wave waits for one round trip instead of one per key.
+// Movers get their slot in the bucket.  Must be called by the whole wave.
+__device__ __forceinline__ int agg_count(unsigned long long *cnt, int key, bool stay) {
     const int lane = lane_id();
     const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    const unsigned long long stays = __ballot(stay);
     unsigned long long todo = __ballot(key >= 0);
-    int slot = -1;
+    unsigned long long mine = 0;
     while (todo) {
-        int leader = __ffsll((long long)todo) - 1;
-        int lkey = __shfl(key, leader);
-        unsigned long long same = __ballot(key == lkey) & todo;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&cnt[lkey], (int)__popcll(same));
-        base = __shfl(base, leader);
-        if (key == lkey) slot = base + (int)__popcll(same & below);
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lkey = __shfl(key, leader);
+        const unsigned long long same = __ballot(key == lkey) & todo;
+        if (key == lkey) mine = same;
         todo &= ~same;
     }
-    return slot;
+    const int leader = mine ? __ffsll((long long)mine) - 1 : lane;
+    const unsigned long long movers = mine & ~stays;
+    unsigned long long base = 0;
+    if (mine && lane == leader)
+        base = atomicAdd(&cnt[key], ((unsigned long long)__popcll(mine & stays) << 32) | __popcll(movers));
+    base = __shfl(base, leader);
+    return (key >= 0 && !stay) ? (int)(base & 0xFFFFFFFFULL) + (int)__popcll(movers & below) : -1;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -329,10 +347,14 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
     D.nsam[c] = ns;
 }
 
-// bucket sizes: movers / collided (cnt) plus stayers (cnts)
+// bucket sizes: movers / collided (low word) plus stayers (high word)
 __global__ void k_bucket_total(Dev D) {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < 2LL * D.nc) D.cursor[k] = D.cnt[k] + D.cnts[k];
+    if (k < 2LL * D.nc) {
+        const unsigned long long v = D.cnt64[k];
+        D.cnt[k] = (int32_t)(v & 0xFFFFFFFFULL);                    // movers / collided
+        D.cursor[k] = (int32_t)(v & 0xFFFFFFFFULL) + (int32_t)(v >> 32);  // bucket size
+    }
 }
 
 // capacity check of the step: old + new must fit
@@ -485,15 +507,12 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
             double x[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
-            pa.x0[i] = x[0];
-            pa.x1[i] = x[1];
-            pa.x2[i] = x[2];
-            pa.u0[i] = u[0];
-            pa.u1[i] = u[1];
-            pa.u2[i] = u[2];
-            pa.m[i] = msam;
+            double2 *r = reinterpret_cast<double2 *>(pa.rec + i);
+            r[0] = make_double2(x[0], x[1]);
+            r[1] = make_double2(x[2], u[0]);
+            r[2] = make_double2(u[1], u[2]);
+            r[3] = make_double2(msam, __longlong_as_double((long long)uid));
             pa.cell[i] = c;
-            pa.uid[i] = uid;
             acc[0] += msam;
             acc[1] += msam * u[0];
             acc[2] += msam * u[1];
@@ -547,10 +566,13 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
             const double *B = D.box + 6 * c;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
+                // a face at distance a >= |u_d| trem (1 + 1e-12) has a computed exit time
+                // >= trem, so it can be neither the minimum nor a crossing: no division
                 const double ud = u[d];
                 if (ud > 0.0) {
-                    if (2 * d + 1 != entry) {
-                        double tt = (B[3 + d] - x[d]) / ud;
+                    const double a = B[3 + d] - x[d];
+                    if (2 * d + 1 != entry && !(a >= ud * trem * (1.0 + 1e-12))) {
+                        double tt = a / ud;
                         if (tt < 0.0) tt = 0.0;
                         if (tt < best) {
                             best = tt;
@@ -558,8 +580,9 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
                         }
                     }
                 } else if (ud < 0.0) {
-                    if (2 * d != entry) {
-                        double tt = (x[d] - B[d]) / (-ud);
+                    const double a = x[d] - B[d];
+                    if (2 * d != entry && !(a >= (-ud) * trem * (1.0 + 1e-12))) {
+                        double tt = a / (-ud);
                         if (tt < 0.0) tt = 0.0;
                         if (tt < best) {
                             best = tt;
@@ -635,12 +658,11 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
 
 // One thread per particle; blocks past the live particles exit at once.  The free-flight
 // time of an old particle is t_f = -tau ln eta with tau of its start cell; it collides iff
-// t_f < dt.  Since t_f < dt <=> eta > exp(-dt/tau), eta clear of exp(-dt/tau) by a relative
-// 1e-12 decides the comparison without the logarithm (the same decision as the formula; the
-// formula itself is evaluated near the threshold and for every collided particle).
+// t_f < dt.  Since t_f < dt <=> eta > exp(-dt/tau), eta below exp(-dt/tau) by a relative
+// 1e-12 decides the comparison without the logarithm (the same decision as the formula,
+// which is evaluated near the threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
-// (escaped).  Bucket counts by wave-aggregated integer atomics; crossings and wall hits per
-// block into partial slots (reduced in k_finalize).
+// (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
 __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     __shared__ unsigned long long red[2][4];
     const Scalars *sc = D.sc;
@@ -652,25 +674,25 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     const double dt = sc->dt;
     const long long step = sc->step;
     const Particles pa = D.pa[buf];
-    const int nc = D.nc;
-    int key = -1;
-    bool stay = false;
     unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
     if (i < n_tot) {
         int c = pa.cell[i];
         const int c0 = c;
-        const uint64_t uid = pa.uid[i];
-        double x[3] = {pa.x0[i], pa.x1[i], pa.x2[i]};
-        double u[3] = {pa.u0[i], pa.u1[i], pa.u2[i]};
+        double2 *rp = reinterpret_cast<double2 *>(pa.rec + i);
+        const double2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+        const uint64_t uid = (uint64_t)__double_as_longlong(r3.y);
+        // start-cell data, loaded before the generator runs
+        const double e = D.ec[c], tauc = D.tau[c];
+        double x[3] = {r0.x, r0.y, r1.x};
+        double u[3] = {r1.y, r2.x, r2.y};
         double ts = dt;
         bool collided = false;
         if (i < n_old) {
             const U4 r = draw(D.seed, uid, step, kTagTF, 0);
             const double eta = unif(r.v[0]);
-            const double e = D.ec[c];
             if (!(eta < e * (1.0 - 1e-12))) {
-                const double tf = -D.tau[c] * log(eta);
+                const double tf = -tauc * log(eta);
                 if (tf < dt) {
                     ts = tf;
                     collided = true;
@@ -681,24 +703,20 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
         const int rc = track(D, x, u, c, ts, uid, step, nx, nw);
         nx_ = (unsigned long long)nx;
         nw_ = (unsigned long long)nw;
-        pa.x0[i] = x[0];
-        pa.x1[i] = x[1];
-        pa.x2[i] = x[2];
-        pa.u0[i] = u[0];
-        pa.u1[i] = u[1];
-        pa.u2[i] = u[2];
+        rp[0] = make_double2(x[0], x[1]);
+        rp[1] = make_double2(x[2], u[0]);
+        rp[2] = make_double2(u[1], u[2]);
+        rp[3] = r3;
         pa.cell[i] = c;
+        int key = -1;
+        bool stay = false;
         if (rc != 1) {
             lost = rc < 0;
-            key = collided ? nc + c : c;
+            key = collided ? D.nc + c : c;
             stay = !collided && c == c0;
         }
         D.key[i] = stay ? (key | kStayBit) : key;
     }
-    // stayers are only counted; movers and collided particles get their slot in the bucket
-    agg_slot(D.cnts, stay ? key : -1);
-    const int slot = agg_slot(D.cnt, stay ? -1 : key);
-    if (key >= 0 && !stay) D.rank[i] = slot;
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
     nw_ = wave_sum_u64(nw_);
@@ -715,6 +733,21 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
         if (a) atomicAdd(&D.spart[slot64], a);
         if (b) atomicAdd(&D.spart[64 + slot64], b);
     }
+}
+
+// bucket counts: stayers are only counted, movers and collided particles get their slot in
+// the bucket (the order of those slots is fixed later by sorting in the gather)
+__global__ void __launch_bounds__(256) k_count(Dev D) {
+    const Scalars *sc = D.sc;
+    const long long n_tot = sc->n_old + sc->n_new;
+    const long long i0 = (long long)blockIdx.x * blockDim.x;
+    if (i0 >= n_tot) return;
+    const long long i = i0 + threadIdx.x;
+    const int kraw = i < n_tot ? D.key[i] : -1;
+    const bool stay = kraw >= 0 && (kraw & kStayBit) != 0;
+    const int key = kraw >= 0 ? (kraw & ~kStayBit) : -1;
+    const int slot = agg_count(D.cnt64, key, stay);
+    if (key >= 0 && !stay) D.rank[i] = slot;
 }
 
 // bucket the movers (collisionless particles that changed cell) and the collided particles:
@@ -775,26 +808,7 @@ __device__ void block_sort(int *a, int len) {
     }
 }
 
-template <int BS>
-__device__ void block_sum5(double v[5], double *red /* [BS/64][5] LDS */) {
-    const int wave = threadIdx.x / kWave;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] = wave_sum(v[k]);
-    if (lane_id() == 0)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) red[wave * 5 + k] = v[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < 5; ++k) {
-            double s = red[k];
-            for (int w = 1; w < BS / kWave; ++w) s = s + red[w * 5 + k];
-            v[k] = s;
-        }
-    }
-    __syncthreads();
-}
 
-constexpr int kSortLDS = 4096;
 
 // ---------------------------------------------------------------------------------------
 // S6: one block per cell c.  The survivors ending in c are laid out in the next buffer as
@@ -805,13 +819,29 @@ constexpr int kSortLDS = 4096;
 // they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-thread
 // assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-template <int BS>
-__device__ __forceinline__ void take_phi(const Particles &src, int s, double acc[5], double &m, double &u0,
-                                         double &u1, double &u2) {
-    m = src.m[s];
-    u0 = src.u0[s];
-    u1 = src.u1[s];
-    u2 = src.u2[s];
+// copy one 64-byte record (4 x 16 bytes) and add its phi = m (1, u, |u|^2/2) to acc
+__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c, double acc[5]) {
+    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
+    const double2 r0 = a[0], r1 = a[1], r2 = a[2], r3 = a[3];
+    const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
+    acc[0] += m;
+    acc[1] += m * u0;
+    acc[2] += m * u1;
+    acc[3] += m * u2;
+    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+    double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
+    b[0] = r0;
+    b[1] = r1;
+    b[2] = r2;
+    b[3] = r3;
+    dst.cell[o] = c;
+}
+
+// add phi of a record without copying it (collided particles)
+__device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5]) {
+    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
+    const double2 r1 = a[1], r2 = a[2], r3 = a[3];
+    const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
     acc[0] += m;
     acc[1] += m * u0;
     acc[2] += m * u1;
@@ -819,112 +849,134 @@ __device__ __forceinline__ void take_phi(const Particles &src, int s, double acc
     acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
 }
 
-__device__ __forceinline__ void put(const Particles &src, const Particles &dst, int s, int o, int c, double m,
-                                    double u0, double u1, double u2) {
-    dst.x0[o] = src.x0[s];
-    dst.x1[o] = src.x1[s];
-    dst.x2[o] = src.x2[s];
-    dst.u0[o] = u0;
-    dst.u1[o] = u1;
-    dst.u2[o] = u2;
-    dst.m[o] = m;
-    dst.cell[o] = c;
-    dst.uid[o] = src.uid[s];
-}
-
 template <int BS>
 __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
-    constexpr int kLds = BS == 64 ? 1024 : kSortLDS;
+    static_assert(BS == kWave, "one wave per cell");
+    constexpr int kLds = 1024;
     __shared__ int lds[kLds];
-    __shared__ double red[(BS / kWave) * 5];
-    __shared__ int wtot[BS / kWave];
-    const int c = blockIdx.x;
-    const int nc = D.nc;
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    // blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
+    // that neighbouring cells (whose particles are exchanged) share an L2
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int xcd = b & 7, q = G >> 3, r = G & 7;
+    const int c = xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+    const int nc = D.nc, nf = D.nf;
+    const int lane = lane_id();
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
     const Scalars *sc = D.sc;
-    double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
-    const int base = D.off[c];
+    // every per-cell scalar in one round of independent loads
+    const int base = D.off[c], bend = D.off[c + 1];
     const int nmov = D.cnt[c];
-    // movers (part 0) and collided (part 1): sorted source lists
+    const int cb0 = D.off[nc + c], cb1 = D.off[nc + c + 1];
+    const long long s00 = D.segoff[buf][c], s01 = D.segoff[buf][c + 1];
+    const long long n_old = sc->n_old, n_new = sc->n_new;
+    const long long s10 = n_old + D.samoff[c], s11 = n_old + D.samoff[c + 1];
+    const int nfc = D.nfc[c];
+    // face fluxes of this cell, lane k < 5 owns component k: acc_k = -sum_f s_f Phi_f,k
+    const int code = lane < nfc ? D.cface[c * 6 + lane] : 0;
+    double facc = 0.0;
+    {
+        int codes[6];
+#pragma unroll
+        for (int lf = 0; lf < 6; ++lf) codes[lf] = __shfl(code, lf);
+        if (lane < 5) {
+            double ph[6];
+#pragma unroll
+            for (int lf = 0; lf < 6; ++lf) {
+                const int cd = codes[lf];
+                const int f = (cd > 0 ? cd : -cd) - 1;
+                ph[lf] = lf < nfc ? D.Phi[lane * nf + f] : 0.0;
+            }
+            for (int lf = 0; lf < nfc; ++lf) {
+                const double sg = codes[lf] > 0 ? 1.0 : -1.0;
+                facc = facc - sg * ph[lf];
+            }
+        }
+    }
+    double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
+    // movers (part 0) and collided (part 1): source lists sorted ascending
     for (int part = 0; part < 2; ++part) {
-        const int a0 = part == 0 ? base : D.off[nc + c];
-        const int len = part == 0 ? nmov : D.off[nc + c + 1] - a0;
+        const int a0 = part == 0 ? base : cb0;
+        const int len = part == 0 ? nmov : cb1 - cb0;
         int *list;
         if (len <= kLds) {
-            for (int j = threadIdx.x; j < len; j += BS) lds[j] = D.perm[a0 + j];
+            for (int j = lane; j < len; j += BS) lds[j] = D.perm[a0 + j];
             __syncthreads();
             list = lds;
         } else {
             list = D.perm + a0;
         }
         block_sort<BS>(list, len);
-        for (int j = threadIdx.x; j < len; j += BS) {
-            const int s = list[j];
-            double m, u0, u1, u2;
-            take_phi<BS>(src, s, part == 0 ? Pn : Cn, m, u0, u1, u2);
-            if (part == 0) put(src, dst, s, a0 + j, c, m, u0, u1, u2);
+#pragma unroll 2
+        for (int j = lane; j < len; j += BS) {
+            const int sidx = list[j];
+            if (part == 0)
+                move_rec(src, dst, sidx, a0 + j, c, Pn);
+            else
+                add_rec(src, sidx, Cn);
         }
         __syncthreads();
     }
-    // stayers: own segment of old particles, then own new particles, compacted in order
+    // stayers: own segment of old particles, then own new particles, compacted in order;
+    // a record is loaded together with its key (same cache lines as its neighbours anyway)
     const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
     int pos = base + nmov;
     for (int seg = 0; seg < 2; ++seg) {
-        long long s0, s1;
-        if (seg == 0) {
-            s0 = D.segoff[buf][c];
-            s1 = D.segoff[buf][c + 1];
-        } else {
-            s0 = sc->n_old + D.samoff[c];
-            s1 = sc->n_old + D.samoff[c + 1];
-            if (sc->n_new == 0) s1 = s0;
-        }
+        const long long s0 = seg == 0 ? s00 : s10;
+        const long long s1 = seg == 0 ? s01 : (n_new == 0 ? s10 : s11);
         for (long long j0 = s0; j0 < s1; j0 += BS) {
-            const long long j = j0 + threadIdx.x;
-            const bool st = j < s1 && (D.key[j] & kStayBit) != 0 && D.key[j] >= 0;
+            const long long j = j0 + lane;
+            int k = -1;
+            double2 r0, r1, r2, r3;
+            if (j < s1) {
+                k = D.key[j];
+                const double2 *a = reinterpret_cast<const double2 *>(src.rec + j);
+                r0 = a[0];
+                r1 = a[1];
+                r2 = a[2];
+                r3 = a[3];
+            }
+            const bool st = k >= 0 && (k & kStayBit) != 0;
             const unsigned long long msk = __ballot(st);
-            if (lane == 0) wtot[wave] = (int)__popcll(msk);
-            __syncthreads();
-            int before = 0, tot = 0;
-            for (int w = 0; w < BS / kWave; ++w) {
-                before += w < wave ? wtot[w] : 0;
-                tot += wtot[w];
-            }
             if (st) {
-                const int o = pos + before + (int)__popcll(msk & below);
-                double m, u0, u1, u2;
-                take_phi<BS>(src, (int)j, Pn, m, u0, u1, u2);
-                put(src, dst, (int)j, o, c, m, u0, u1, u2);
+                const int o = pos + (int)__popcll(msk & below);
+                const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
+                Pn[0] += m;
+                Pn[1] += m * u0;
+                Pn[2] += m * u1;
+                Pn[3] += m * u2;
+                Pn[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+                double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
+                b[0] = r0;
+                b[1] = r1;
+                b[2] = r2;
+                b[3] = r3;
+                dst.cell[o] = c;
             }
-            pos += tot;
-            __syncthreads();
+            pos += (int)__popcll(msk);
         }
     }
-    block_sum5<BS>(Pn, red);
-    block_sum5<BS>(Cn, red);
-    if (threadIdx.x == 0) {
-        const int nf = D.nf;
-        const double vol = D.vol[c];
-        double acc[5] = {0, 0, 0, 0, 0};
-        const int nfc = D.nfc[c];
-        for (int lf = 0; lf < nfc; ++lf) {
-            const int code = D.cface[c * 6 + lf];
-            const int f = (code > 0 ? code : -code) - 1;
-            const double s = code > 0 ? 1.0 : -1.0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) acc[k] = acc[k] - s * D.Phi[k * nf + f];
-        }
+    for (int k = 0; k < 5; ++k) {
+        Pn[k] = wave_sum(Pn[k]);
+        Cn[k] = wave_sum(Cn[k]);
+    }
+    if (lane < 5) {
+        double Pk = Pn[0], Ck = Cn[0];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const double E = Pn[k] + Cn[k];
-            acc[k] = acc[k] + (E - D.S[k * nc + c]);
-            D.W[k * nc + c] = D.W[k * nc + c] + acc[k] / vol;
-            D.P[k * nc + c] = Pn[k];
-        }
-        D.nleft[c] = D.off[c + 1] - D.off[c];
-        D.segoff[buf ^ 1][c] = D.off[c];
-        if (pos != D.off[c + 1]) atomicOr(&D.sc->err, kErrCapacity);
+        for (int k = 1; k < 5; ++k)
+            if (lane == k) {
+                Pk = Pn[k];
+                Ck = Cn[k];
+            }
+        const double E = Pk + Ck;
+        const double acc = facc + (E - D.S[lane * nc + c]);
+        D.W[lane * nc + c] = D.W[lane * nc + c] + acc / D.vol[c];
+        D.P[lane * nc + c] = Pk;
+    }
+    if (lane == 0) {
+        D.nleft[c] = bend - base;
+        D.segoff[buf ^ 1][c] = base;
+        if (pos != bend) atomicOr(&D.sc->err, kErrCapacity);
     }
 }
 
@@ -1107,8 +1159,7 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     pr->begin(kSlotScan);
     scan<long long>(D.nsam, nc, D.samoff, D.scan64, s);
     k_sample_setup<<<1, 1, 0, s>>>(D);
-    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt, 2LL * nc, 0);
-    k_fill<int32_t><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnts, 2LL * nc, 0);
+    k_fill<unsigned long long><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt64, 2LL * nc, 0ULL);
     k_fill<unsigned long long><<<1, 128, 0, s>>>(D.spart, 128, 0ULL);
     pr->end(kSlotScan);
     pr->begin(kSlotFlux);
@@ -1121,6 +1172,9 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     const unsigned pb = (unsigned)stream_blocks(D.cap);
     k_stream<<<pb, 256, 0, s>>>(D, buf);
     pr->end(kSlotStream);
+    pr->begin(kSlotCount);
+    k_count<<<pb, 256, 0, s>>>(D);
+    pr->end(kSlotCount);
     pr->begin(kSlotScan2);
     k_bucket_total<<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D);
     scan<int32_t>(D.cursor, 2LL * nc, D.off, D.scan32, s);
@@ -1129,10 +1183,8 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     k_scatter<<<pb, 256, 0, s>>>(D);
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
-    if (gather_bs == 64)
-        k_gather<64><<<nc, 64, 0, s>>>(D, buf);
-    else
-        k_gather<256><<<nc, 256, 0, s>>>(D, buf);
+    (void)gather_bs;
+    k_gather<64><<<nc, 64, 0, s>>>(D, buf);
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
     k_finalize<<<1, 256, 0, s>>>(D, buf);

@@ -20,6 +20,7 @@ enum ProfSlot : int {
     kSlotFlux,          // k_flux
     kSlotSample,        // k_sample
     kSlotStream,        // k_stream
+    kSlotCount,         // k_count
     kSlotScan2,         // scan of the bucket counts
     kSlotScatter,       // k_scatter
     kSlotGather,        // k_gather

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_MESH", 3: "E_CAPACITY", 4: "E_LOST", 
 SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkwp_step", "ugkwp_moments",
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy")
-N_PROFILE_SLOTS = 10
+N_PROFILE_SLOTS = 11
 
 
 class UgkwpBC(C.Structure):
