@@ -81,12 +81,54 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
+def timed_run(w, precision, warmup, steps):
+    """W untimed steps, then K timed steps bracketed by device synchronisation; per-kernel
+    times from hip events on the library's stream over the timed steps."""
+    import torch
+
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    s = Solver(w.mesh, w.params, precision=precision)
+    s.init_state(w.W0)
+    st0 = s.step(max(warmup, 1), stats=True)
+    moved0 = st0["moved_total"]
+    s.profile(True)
+    s.profile_read()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.step(0, stats=True)
+    prof = s.profile_read()
+    s.profile(False)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return t1 - t0, st1["moved_total"] - moved0, prof
+
+
+def stated_fp32_error():
+    """The FP32 form's error against the FP64 oracle, as measured by tests/test_gpu_fp32.py
+    and committed under profiles/ (L1 and Linf of rho, |U|, T, with the seed-to-seed noise)."""
+    f = os.path.join(ROOT, "profiles", "fp32_error_cavity16.json")
+    try:
+        with open(f) as fh:
+            rows = json.load(fh)
+        last = rows[-1]
+        return {"workload": "cavity 16^3, 400 particles/cell", "step": last["step"],
+                "fp32_vs_fp64_oracle": last["fp32_vs_oracle"], "fp64_seed_noise": last["noise_floor"]}
+    except (OSError, ValueError, KeyError, IndexError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -98,29 +140,11 @@ def main():
         copy_calibration()
         return
 
-    import torch
-
     from paper_2007_13091_amd import workloads as wl
-    from paper_2007_13091_amd.ugkwp import Solver
 
     w = wl.cavity()
-    s = Solver(w.mesh, w.params)
-    s.init_state(w.W0)
-    st0 = s.step(max(args.warmup, 1), stats=True)
-    moved0 = st0["moved_total"]
-    s.profile(True)
-    s.profile_read()  # clear
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps, stats=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = s.step(0, stats=True)
-    prof = s.profile_read()
-    s.profile(False)
-    el = t1 - t0
-    moves = st1["moved_total"] - moved0
     nc = w.mesh.n_cells
+    el, moves, prof = timed_run(w, 0, args.warmup, args.steps)
     value = moves / el
     # dominant kernel: the slot with the largest summed time
     dom = max(prof, key=lambda k: prof[k][0])
@@ -128,7 +152,7 @@ def main():
     avg_ms = dom_ms / max(dom_n, 1)
     moves_per_launch = moves / args.steps
     achieved = BYTES_PER_MOVE_FP64 * moves_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"stream": "k_stream", "gather": "k_gather"}.get(dom, dom)
+    kname = {"stream": "k_stream<double>", "gather": "k_gather<double>"}.get(dom, dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
             "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
@@ -153,6 +177,13 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    if not args.no_fp32:
+        el32, moves32, prof32 = timed_run(w, 1, args.warmup, args.steps)
+        out["fp32_form"] = {"value": moves32 / el32, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
+                            "ms_per_step": el32 / args.steps * 1e3, "cell_steps_per_s": nc * args.steps / el32,
+                            "speedup_vs_fp64_plain": (moves32 / el32) / value,
+                            "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
+                            "stated_error": stated_fp32_error()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -92,7 +92,8 @@ typedef struct {
     int32_t n_ref;        /* reference particle number per cell, Sec. 2.4(b) */
     int32_t n_min;        /* minimum particle number per cell, Sec. 2.4(b) */
     int32_t recon;        /* 0 = first order (only value supported) */
-    int32_t precision;    /* 0 = FP64 throughout (only value supported) */
+    int32_t precision;    /* 0 = FP64 throughout; 1 = FP32 form: flux and particle transport in
+                             FP32, per-cell sums, W - W^p and energy -> T in FP64 */
     int64_t capacity;     /* particle capacity (0 = library default from n_ref and n_cells) */
     int32_t max_crossings;/* face crossings allowed per particle per step */
     uint64_t seed;        /* Philox4x64-10 key word 0 */

@@ -113,7 +113,7 @@ struct Carver {
 };
 
 // Lay the workspace out; with base == nullptr only the size is computed.
-size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
+size_t carve(const HostMesh &H, long long cap, int prec, Dev &D, char *base) {
     Carver C{base};
     const size_t nc = (size_t)H.nc, nf = (size_t)H.nf, nbc = H.bcs.size() ? H.bcs.size() : 1;
     D.vol = C.take<double>(nc);
@@ -124,6 +124,8 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.ctype = C.take<uint8_t>(nc);
     D.box = C.take<double>(6 * nc);
     D.plane = C.take<double4>(6 * nc);
+    D.box32 = prec == 1 ? C.take<float>(6 * nc) : nullptr;
+    D.plane32 = prec == 1 ? C.take<float4>(6 * nc) : nullptr;
     D.nbl = C.take<int2>(6 * nc);
     D.cface = C.take<int32_t>(6 * nc);
     D.fown = C.take<int32_t>(nf);
@@ -155,7 +157,15 @@ size_t carve(const HostMesh &H, long long cap, Dev &D, char *base) {
     D.perm = C.take<int32_t>((size_t)cap);
     for (int b = 0; b < 2; ++b) {
         ugkwp::Particles &P = D.pa[b];
-        P.rec = C.take<ugkwp::PRec>((size_t)cap);
+        P.rec = nullptr;
+        P.rec32 = nullptr;
+        P.m32 = nullptr;
+        if (prec == 1) {
+            P.rec32 = C.take<ugkwp::PRec32>((size_t)cap);
+            P.m32 = C.take<float>((size_t)cap);
+        } else {
+            P.rec = C.take<ugkwp::PRec>((size_t)cap);
+        }
         P.cell = C.take<int32_t>((size_t)cap);
     }
     D.sc = C.take<Scalars>(1);
@@ -175,8 +185,8 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
         err = "params: need 1 <= n_ref <= 2^20, 0 <= n_min <= 2^20, max_crossings >= 1";
         return UGKWP_E_ARG;
     }
-    if (p.recon != 0 || p.precision != 0) {
-        err = "params: only first-order reconstruction (recon 0) in FP64 (precision 0) is built";
+    if (p.recon != 0 || (p.precision != 0 && p.precision != 1)) {
+        err = "params: only first-order reconstruction (recon 0) is built; precision is 0 (FP64) or 1 (FP32 form)";
         return UGKWP_E_ARG;
     }
     long long c = p.capacity;
@@ -260,7 +270,7 @@ int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, const ugkwp_params *p, size_t
     st = check_params(*p, H.nc, cap, err);
     if (st != UGKWP_OK) return fail(nullptr, st, err);
     Dev D{};
-    *bytes = carve(H, cap, D, nullptr);
+    *bytes = carve(H, cap, p->precision, D, nullptr);
     return UGKWP_OK;
 }
 
@@ -284,7 +294,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     ctx->ws = (char *)dev_workspace;
     ctx->ws_bytes = ws_bytes;
     Dev &D = ctx->D;
-    size_t need = carve(ctx->H, cap, D, ctx->ws);
+    size_t need = carve(ctx->H, cap, p->precision, D, ctx->ws);
     if (ws_bytes < need) {
         delete ctx;
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -302,6 +312,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     D.max_cross = p->max_crossings;
     D.seed = p->seed;
     D.cap = cap;
+    D.prec = p->precision;
     // one wave per cell: blocks of 64 threads need no cross-wave barriers
     ctx->gather_bs = 64;
 
@@ -327,6 +338,13 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     e = e ? e : up((double *)D.dS, dS, s);
     e = e ? e : up((double *)D.orig, org, s);
     e = e ? e : up((double *)D.box, H.box, s);
+    std::vector<float> box32, plane32;
+    if (D.prec == 1) {
+        box32.assign(H.box.begin(), H.box.end());
+        plane32.assign(H.plane.begin(), H.plane.end());
+        e = e ? e : up((float *)D.box32, box32, s);
+        e = e ? e : hipMemcpyAsync((void *)D.plane32, plane32.data(), plane32.size() * sizeof(float), hipMemcpyHostToDevice, s);
+    }
     e = e ? e : up((double *)D.edge, edg, s);
     e = e ? e : up((uint8_t *)D.nfc, H.nfc, s);
     e = e ? e : up((uint8_t *)D.ctype, H.ctype, s);
@@ -437,7 +455,21 @@ int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, 
     int32_t st = ugkwp_particle_count(ctx, &n);
     if (st != UGKWP_OK) return st;
     const ugkwp::Particles &P = ctx->D.pa[ctx->buf];
-    if (n > 0) {
+    if (n > 0 && ctx->D.prec == 1) {
+        std::vector<ugkwp::PRec32> rec((size_t)n);
+        std::vector<float> mm((size_t)n);
+        HIPCHK(ctx, hipMemcpy(rec.data(), P.rec32, n * sizeof(ugkwp::PRec32), hipMemcpyDeviceToHost));
+        HIPCHK(ctx, hipMemcpy(mm.data(), P.m32, n * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) {
+                if (x) x[3 * i + d] = rec[i].x[d];
+                if (u) u[3 * i + d] = rec[i].u[d];
+            }
+            if (m) m[i] = mm[i];
+            if (uid) uid[i] = rec[i].uid;
+        }
+        if (cell) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    } else if (n > 0) {
         std::vector<ugkwp::PRec> rec((size_t)n);
         HIPCHK(ctx, hipMemcpy(rec.data(), P.rec, n * sizeof(ugkwp::PRec), hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < n; ++i) {

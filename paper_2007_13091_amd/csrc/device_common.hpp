@@ -51,8 +51,18 @@ struct alignas(64) PRec {
     uint64_t uid;
 };
 
+// FP32 form: position and velocity in single precision with the id in a 32-byte record; the
+// mass (single precision) in its own array, since transport never reads it.
+struct alignas(32) PRec32 {
+    float x[3];
+    float u[3];
+    uint64_t uid;
+};
+
 struct Particles {
-    PRec *rec;
+    PRec *rec;      // FP64 form
+    PRec32 *rec32;  // FP32 form
+    float *m32;     // FP32 form
     int32_t *cell;
 };
 
@@ -67,6 +77,8 @@ struct Dev {
     const uint8_t *ctype;   // [nc]
     const double *box;      // [nc][6] lo[3], hi[3] of box hexes (unused for tetrahedra)
     const double4 *plane;   // [nc*6]  (n, d) outward
+    const float *box32;     // FP32 copies for the FP32 form
+    const float4 *plane32;
     const int2 *nbl;        // [nc*6]  (neighbour or -1-bc, local face in neighbour)
     const int32_t *cface;   // [nc*6]  +-(f+1)
     const int32_t *fown;    // [nf]
@@ -76,7 +88,7 @@ struct Dev {
     const DevBC *bc;        // [nbc]
     // parameters
     double mu_ref, omega, cfl, c2;
-    int32_t n_ref, n_min, max_cross, pad1;
+    int32_t n_ref, n_min, max_cross, prec;  // prec: 0 FP64 plain, 1 FP32 form
     unsigned long long seed;
     long long cap;
     // state

@@ -77,8 +77,18 @@ __device__ __forceinline__ U4 draw(uint64_t seed, uint64_t uid, long long step, 
     return philox(uid, (uint64_t)step, ((uint64_t)tag << 32) | sub, 0ULL, seed, 0ULL);
 }
 
-// (top 52 bits + 1/2) * 2^-52: uniform in (0, 1), never 0 or 1
-__device__ __forceinline__ double unif(uint64_t r) { return ((double)(r >> 12) + 0.5) * 0x1p-52; }
+// uniform in (0, 1), never 0 or 1: FP64 (top 52 bits + 1/2) * 2^-52; FP32 (top 23 bits + 1/2)
+// * 2^-23, the leading bits of the same draw
+template <typename R>
+__device__ __forceinline__ R unif(uint64_t r);
+template <>
+__device__ __forceinline__ double unif<double>(uint64_t r) {
+    return ((double)(r >> 12) + 0.5) * 0x1p-52;
+}
+template <>
+__device__ __forceinline__ float unif<float>(uint64_t r) {
+    return ((float)(uint32_t)(r >> 41) + 0.5f) * 0x1p-23f;
+}
 
 __device__ __forceinline__ uint64_t make_uid(long long step, int cell, long long k) {
     return (((uint64_t)step & 0x7FFFFULL) << 44) | (((uint64_t)cell & 0xFFFFFFULL) << 20) | ((uint64_t)k & 0xFFFFFULL);
@@ -88,49 +98,55 @@ __device__ __forceinline__ uint64_t make_uid(long long step, int cell, long long
 // Maxwellian moments in a face frame (R = 1, K = 0), lambda = 1/(2T).
 // m[k] = <u_n^k> over the full line (rng 0), u_n > 0 (rng 1) or u_n < 0 (rng -1);
 // <u^{k+2}> = U <u^{k+1}> + (k+1)/(2 lambda) <u^k> holds on each half line as well.
+// The transport type R is double (plain form) or float (FP32 form).
 // ---------------------------------------------------------------------------------------
+template <typename R>
 struct Prim {
-    double rho, un, v, w, lam, T;
+    R rho, un, v, w, lam, T;
 };
 
-__device__ __forceinline__ void moments4(int rng, double U, double lam, double m[4]) {
+template <typename R>
+__device__ __forceinline__ void moments4(int rng, R U, R lam, R m[4]) {
+    const R pi = (R)kPi;
     if (rng == 0) {
-        m[0] = 1.0;
+        m[0] = (R)1;
         m[1] = U;
     } else if (rng > 0) {
-        m[0] = 0.5 * erfc(-sqrt(lam) * U);
-        m[1] = U * m[0] + 0.5 * exp(-lam * U * U) / sqrt(kPi * lam);
+        m[0] = (R)0.5 * erfc(-sqrt(lam) * U);
+        m[1] = U * m[0] + (R)0.5 * exp(-lam * U * U) / sqrt(pi * lam);
     } else {
-        m[0] = 0.5 * erfc(sqrt(lam) * U);
-        m[1] = U * m[0] - 0.5 * exp(-lam * U * U) / sqrt(kPi * lam);
+        m[0] = (R)0.5 * erfc(sqrt(lam) * U);
+        m[1] = U * m[0] - (R)0.5 * exp(-lam * U * U) / sqrt(pi * lam);
     }
-    m[2] = U * m[1] + 1.0 / (2.0 * lam) * m[0];
-    m[3] = U * m[2] + 2.0 / (2.0 * lam) * m[1];
+    m[2] = U * m[1] + (R)1 / ((R)2 * lam) * m[0];
+    m[3] = U * m[2] + (R)2 / ((R)2 * lam) * m[1];
 }
 
 // <psi> (H) and <u_n psi> (G) of a unit-density Maxwellian; psi = (1, u_n, v, w, |u|^2/2)
-__device__ __forceinline__ void psi_moments(const Prim &p, const double m[4], double H[5], double G[5]) {
-    double tr = p.v * p.v + p.w * p.w + 1.0 / p.lam;
+template <typename R>
+__device__ __forceinline__ void psi_moments(const Prim<R> &p, const R m[4], R H[5], R G[5]) {
+    R tr = p.v * p.v + p.w * p.w + (R)1 / p.lam;
     H[0] = m[0];
     H[1] = m[1];
     H[2] = m[0] * p.v;
     H[3] = m[0] * p.w;
-    H[4] = 0.5 * (m[2] + m[0] * tr);
+    H[4] = (R)0.5 * (m[2] + m[0] * tr);
     G[0] = m[1];
     G[1] = m[2];
     G[2] = m[1] * p.v;
     G[3] = m[1] * p.w;
-    G[4] = 0.5 * (m[3] + m[1] * tr);
+    G[4] = (R)0.5 * (m[3] + m[1] * tr);
 }
 
 // face frame: t1 = normalise(e_a x n), a = axis of the smallest |n_a| (lowest on ties); t2 = n x t1
-__device__ __forceinline__ void face_frame(const double n[3], double t1[3], double t2[3]) {
+template <typename R>
+__device__ __forceinline__ void face_frame(const R n[3], R t1[3], R t2[3]) {
     int a = 0;
     if (fabs(n[1]) < fabs(n[a])) a = 1;
     if (fabs(n[2]) < fabs(n[a])) a = 2;
-    double e0 = a == 0 ? 1.0 : 0.0, e1 = a == 1 ? 1.0 : 0.0, e2 = a == 2 ? 1.0 : 0.0;
-    double c0 = e1 * n[2] - e2 * n[1], c1 = e2 * n[0] - e0 * n[2], c2 = e0 * n[1] - e1 * n[0];
-    double l = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    R e0 = a == 0 ? (R)1 : (R)0, e1 = a == 1 ? (R)1 : (R)0, e2 = a == 2 ? (R)1 : (R)0;
+    R c0 = e1 * n[2] - e2 * n[1], c1 = e2 * n[0] - e0 * n[2], c2 = e0 * n[1] - e1 * n[0];
+    R l = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
     t1[0] = c0 / l;
     t1[1] = c1 / l;
     t1[2] = c2 / l;
@@ -139,15 +155,19 @@ __device__ __forceinline__ void face_frame(const double n[3], double t1[3], doub
     t2[2] = n[0] * t1[1] - n[1] * t1[0];
 }
 
-__device__ __forceinline__ Prim to_frame(const double W[5], const double n[3], const double t1[3], const double t2[3]) {
-    Prim p;
-    p.rho = W[0];
-    double U = W[1] / W[0], V = W[2] / W[0], Z = W[3] / W[0];
-    p.un = U * n[0] + V * n[1] + Z * n[2];
-    p.v = U * t1[0] + V * t1[1] + Z * t1[2];
-    p.w = U * t2[0] + V * t2[1] + Z * t2[2];
-    p.T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
-    p.lam = 1.0 / (2.0 * p.T);
+// primitives of a cell state in the face frame; the energy -> temperature recovery is FP64
+template <typename R>
+__device__ __forceinline__ Prim<R> to_frame(const double W[5], const R n[3], const R t1[3], const R t2[3]) {
+    Prim<R> p;
+    const double U = W[1] / W[0], V = W[2] / W[0], Z = W[3] / W[0];
+    const double T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+    const R u = (R)U, v = (R)V, z = (R)Z;
+    p.rho = (R)W[0];
+    p.un = u * n[0] + v * n[1] + z * n[2];
+    p.v = u * t1[0] + v * t1[1] + z * t1[2];
+    p.w = u * t2[0] + v * t2[1] + z * t2[2];
+    p.T = (R)T;
+    p.lam = (R)1 / ((R)2 * p.T);
     return p;
 }
 
@@ -155,35 +175,47 @@ __device__ __forceinline__ Prim to_frame(const double W[5], const double n[3], c
 //   q1/tau = x - 1 + e^-x   and   (q4 - dt e)/tau = 1 - (1 + x) e^-x.
 struct QSeries {
     double a[25], b[25];
-    constexpr QSeries() : a(), b() {
+    float af[25], bf[25];
+    constexpr QSeries() : a(), b(), af(), bf() {
         double f = 1.0;
         for (int k = 1; k <= 24; ++k) {
             f = f * k;
             double s = (k % 2 == 0) ? 1.0 : -1.0;
             a[k] = s / f;
             b[k] = s * (k - 1) / f;
+            af[k] = (float)a[k];
+            bf[k] = (float)b[k];
         }
     }
 };
 __constant__ QSeries kQ = QSeries();
 
 // q1 and q4 - dt e of the time-integrated interface distribution (Eq. of q1..q5), x = dt/tau:
-// series below x = 1 (terms x^2..x^24, Horner), closed forms above
-__device__ __forceinline__ void qcoef(double dt, double tau, double &q1, double &q4m) {
-    double x = dt / tau;
-    if (x < 1.0) {
-        double s1 = 0.0, s4 = 0.0;
+// series below x = 1 (terms x^2..x^24 in FP64, x^2..x^12 in FP32, Horner), closed forms above
+template <typename R>
+__device__ __forceinline__ void qcoef(R dt, R tau, R &q1, R &q4m) {
+    const R x = dt / tau;
+    if (x < (R)1) {
+        R s1 = (R)0, s4 = (R)0;
+        if constexpr (sizeof(R) == 8) {
 #pragma unroll
-        for (int k = 24; k >= 2; --k) {
-            s1 = s1 * x + kQ.a[k];
-            s4 = s4 * x + kQ.b[k];
+            for (int k = 24; k >= 2; --k) {
+                s1 = s1 * x + kQ.a[k];
+                s4 = s4 * x + kQ.b[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 12; k >= 2; --k) {
+                s1 = s1 * x + kQ.af[k];
+                s4 = s4 * x + kQ.bf[k];
+            }
         }
         q1 = tau * (s1 * x * x);
         q4m = tau * (s4 * x * x);
     } else {
-        double e = exp(-x);
-        q1 = tau * (x - 1.0 + e);
-        q4m = tau * (1.0 - (1.0 + x) * e);
+        const R e = exp(-x);
+        q1 = tau * (x - (R)1 + e);
+        q4m = tau * ((R)1 - ((R)1 + x) * e);
     }
 }
 
@@ -191,30 +223,31 @@ __device__ __forceinline__ void qcoef(double dt, double tau, double &q1, double 
 //   F = rho0 q1 <u_n psi>_0 + (q4 - dt e) (rhoh_l <u_n psi>_{l,u>0} + rhoh_r <u_n psi>_{r,u<0})
 // with g0 from the upwind moments of both sides and tau at the face from g0 plus the
 // numerical dissipation C2 |pl - pr| / (pl + pr) dt of Sec. 2.4(d).
-__device__ __forceinline__ void flux_pair(const Prim &l, const Prim &r, double hl, double hr, double dt, double mu_ref,
-                                          double omega, double c2, double Ff[5]) {
-    double ml[4], mr[4], Hl[5], Gl[5], Hr[5], Gr[5];
-    moments4(1, l.un, l.lam, ml);
-    moments4(-1, r.un, r.lam, mr);
-    psi_moments(l, ml, Hl, Gl);
-    psi_moments(r, mr, Hr, Gr);
-    double W0[5];
+template <typename R>
+__device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R hl, R hr, R dt, R mu_ref, R omega,
+                                          R c2, R Ff[5]) {
+    R ml[4], mr[4], Hl[5], Gl[5], Hr[5], Gr[5];
+    moments4<R>(1, l.un, l.lam, ml);
+    moments4<R>(-1, r.un, r.lam, mr);
+    psi_moments<R>(l, ml, Hl, Gl);
+    psi_moments<R>(r, mr, Hr, Gr);
+    R W0[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) W0[k] = l.rho * Hl[k] + r.rho * Hr[k];
-    Prim z;
+    Prim<R> z;
     z.rho = W0[0];
     z.un = W0[1] / W0[0];
     z.v = W0[2] / W0[0];
     z.w = W0[3] / W0[0];
-    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
-    z.lam = 1.0 / (2.0 * z.T);
-    double pl = l.rho * l.T, pr = r.rho * r.T;
-    double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
-    double q1, q4m;
-    qcoef(dt, tau, q1, q4m);
-    double m0[4], H0[5], G0[5];
-    moments4(0, z.un, z.lam, m0);
-    psi_moments(z, m0, H0, G0);
+    z.T = ((R)2 / (R)3) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.lam = (R)1 / ((R)2 * z.T);
+    R pl = l.rho * l.T, pr = r.rho * r.T;
+    R tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
+    R q1, q4m;
+    qcoef<R>(dt, tau, q1, q4m);
+    R m0[4], H0[5], G0[5];
+    moments4<R>(0, z.un, z.lam, m0);
+    psi_moments<R>(z, m0, H0, G0);
 #pragma unroll
     for (int k = 0; k < 5; ++k) Ff[k] = q1 * z.rho * G0[k] + q4m * (hl * Gl[k] + hr * Gr[k]);
 }
@@ -371,78 +404,110 @@ __global__ void k_sample_setup(Dev D) {
 }
 
 // ---------------------------------------------------------------------------------------
-// S2: wave flux per face, times the area, oriented owner -> neighbour
+// S2: wave flux per face, times the area, oriented owner -> neighbour.  Arithmetic in R
+// (FP32 form: float), inputs recovered from the FP64 state, result stored in FP64.
 // ---------------------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(128) k_flux(Dev D) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= D.nf) return;
     const int nc = D.nc, nf = D.nf;
-    const double dt = D.sc->dt;
+    const R dt = (R)D.sc->dt;
+    const R mu = (R)D.mu_ref, om = (R)D.omega, c2 = (R)D.c2;
     const int c = D.fown[f];
     const int nb = D.fnb[f];
-    double n[3] = {D.fn[f], D.fn[nf + f], D.fn[2 * nf + f]};
-    double t1[3], t2[3];
-    face_frame(n, t1, t2);
+    R n[3] = {(R)D.fn[f], (R)D.fn[nf + f], (R)D.fn[2 * nf + f]};
+    R t1[3], t2[3];
+    face_frame<R>(n, t1, t2);
     double Wl[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) Wl[k] = D.W[k * nc + c];
-    const Prim l = to_frame(Wl, n, t1, t2);
-    double Ff[5];
+    const Prim<R> l = to_frame<R>(Wl, n, t1, t2);
+    R Ff[5];
     if (nb >= 0) {
         double Wr[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) Wr[k] = D.W[k * nc + nb];
-        const Prim r = to_frame(Wr, n, t1, t2);
-        flux_pair(l, r, D.rhoh[c], D.rhoh[nb], dt, D.mu_ref, D.omega, D.c2, Ff);
+        const Prim<R> r = to_frame<R>(Wr, n, t1, t2);
+        flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
         if (bc.type == 0) {
             // specular wall: mirror state, keep only the normal momentum
-            Prim g = l;
+            Prim<R> g = l;
             g.un = -l.un;
-            double h = D.rhoh[c];
-            flux_pair(l, g, h, h, dt, D.mu_ref, D.omega, D.c2, Ff);
-            Ff[0] = 0.0;
-            Ff[2] = 0.0;
-            Ff[3] = 0.0;
-            Ff[4] = 0.0;
+            const R h = (R)D.rhoh[c];
+            flux_pair<R>(l, g, h, h, dt, mu, om, c2, Ff);
+            Ff[0] = (R)0;
+            Ff[2] = (R)0;
+            Ff[3] = (R)0;
+            Ff[4] = (R)0;
         } else if (bc.type == 1) {
             // diffuse wall: incoming q1 g + (q4 - dt e) g^h with the cell tau; the wall emits
             // rho_w M(T_w, U_w) over u_n < 0 for the step, rho_w from zero net mass flux
-            double q1, q4m;
-            qcoef(dt, D.tau[c], q1, q4m);
-            double ml[4], Hl[5], Gl[5];
-            moments4(1, l.un, l.lam, ml);
-            psi_moments(l, ml, Hl, Gl);
-            const double h = D.rhoh[c];
-            double Fin[5];
+            R q1, q4m;
+            qcoef<R>(dt, (R)D.tau[c], q1, q4m);
+            R ml[4], Hl[5], Gl[5];
+            moments4<R>(1, l.un, l.lam, ml);
+            psi_moments<R>(l, ml, Hl, Gl);
+            const R h = (R)D.rhoh[c];
+            R Fin[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k) Fin[k] = q1 * l.rho * Gl[k] + q4m * h * Gl[k];
-            Prim w;
-            w.rho = 1.0;
-            w.un = bc.Uw[0] * n[0] + bc.Uw[1] * n[1] + bc.Uw[2] * n[2];
-            w.v = bc.Uw[0] * t1[0] + bc.Uw[1] * t1[1] + bc.Uw[2] * t1[2];
-            w.w = bc.Uw[0] * t2[0] + bc.Uw[1] * t2[1] + bc.Uw[2] * t2[2];
-            w.T = bc.Tw;
-            w.lam = 1.0 / (2.0 * bc.Tw);
-            double mw[4], Hw[5], Gw[5];
-            moments4(-1, w.un, w.lam, mw);
-            psi_moments(w, mw, Hw, Gw);
-            const double rhow = -Fin[0] / (dt * Gw[0]);
+            const R uw[3] = {(R)bc.Uw[0], (R)bc.Uw[1], (R)bc.Uw[2]};
+            Prim<R> w;
+            w.rho = (R)1;
+            w.un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
+            w.v = uw[0] * t1[0] + uw[1] * t1[1] + uw[2] * t1[2];
+            w.w = uw[0] * t2[0] + uw[1] * t2[1] + uw[2] * t2[2];
+            w.T = (R)bc.Tw;
+            w.lam = (R)1 / ((R)2 * w.T);
+            R mw[4], Hw[5], Gw[5];
+            moments4<R>(-1, w.un, w.lam, mw);
+            psi_moments<R>(w, mw, Hw, Gw);
+            const R rhow = -Fin[0] / (dt * Gw[0]);
 #pragma unroll
             for (int k = 0; k < 5; ++k) Ff[k] = Fin[k] + dt * rhow * Gw[k];
-            Ff[0] = 0.0;
+            Ff[0] = (R)0;
         } else {
             // far field: the free stream as the right state (hydro density = its density)
-            const Prim r = to_frame(bc.Winf, n, t1, t2);
-            flux_pair(l, r, D.rhoh[c], bc.Winf[0], dt, D.mu_ref, D.omega, D.c2, Ff);
+            const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2);
+            flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, Ff);
         }
     }
-    const double a = D.farea[f];
-    D.Phi[f] = Ff[0] * a;
+    const R a = (R)D.farea[f];
+    D.Phi[f] = (double)(Ff[0] * a);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) D.Phi[(1 + d) * nf + f] = (Ff[1] * n[d] + Ff[2] * t1[d] + Ff[3] * t2[d]) * a;
-    D.Phi[4 * nf + f] = Ff[4] * a;
+    for (int d = 0; d < 3; ++d) D.Phi[(1 + d) * nf + f] = (double)((Ff[1] * n[d] + Ff[2] * t1[d] + Ff[3] * t2[d]) * a);
+    D.Phi[4 * nf + f] = (double)(Ff[4] * a);
+}
+
+// particle store access for the two forms
+__device__ __forceinline__ void store_new(const Particles &pa, long long i, const double x[3], const double u[3],
+                                          double m, uint64_t uid) {
+    double2 *r = reinterpret_cast<double2 *>(pa.rec + i);
+    r[0] = make_double2(x[0], x[1]);
+    r[1] = make_double2(x[2], u[0]);
+    r[2] = make_double2(u[1], u[2]);
+    r[3] = make_double2(m, __longlong_as_double((long long)uid));
+}
+__device__ __forceinline__ void store_new(const Particles &pa, long long i, const float x[3], const float u[3],
+                                          float m, uint64_t uid) {
+    float4 *r = reinterpret_cast<float4 *>(pa.rec32 + i);
+    r[0] = make_float4(x[0], x[1], x[2], u[0]);
+    r[1] = make_float4(u[1], u[2], __uint_as_float((uint32_t)uid), __uint_as_float((uint32_t)(uid >> 32)));
+    pa.m32[i] = m;
+}
+
+// phi = m (1, u, |u|^2 / 2) of a stored particle, accumulated in FP64
+template <typename R>
+__device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
+    const double m = (double)m_, u0 = (double)u_[0], u1 = (double)u_[1], u2 = (double)u_[2];
+    acc[0] += m;
+    acc[1] += m * u0;
+    acc[2] += m * u1;
+    acc[3] += m * u2;
+    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -451,6 +516,7 @@ __global__ void __launch_bounds__(128) k_flux(Dev D) {
 // uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -465,59 +531,52 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
         const long long base = sc->n_old + D.samoff[c];
         const long long step = sc->step;
         const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
-        const double U[3] = {m0 / rho, m1 / rho, m2 / rho};
-        const double T = (2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
-        const double sT = sqrt(T);
+        const R U[3] = {(R)(m0 / rho), (R)(m1 / rho), (R)(m2 / rho)};
+        const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
+        const R sT = sqrt(T);
         const double vol = D.vol[c];
-        const double msam = D.ec[c] * D.rhoh[c] * vol / (double)ns;
-        const double org[3] = {D.orig[c], D.orig[nc + c], D.orig[2 * nc + c]};
-        double Ed[9];
+        const R msam = (R)(D.ec[c] * D.rhoh[c] * vol / (double)ns);
+        const R org[3] = {(R)D.orig[c], (R)D.orig[nc + c], (R)D.orig[2 * nc + c]};
+        R Ed[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Ed[q] = D.edge[q * nc + c];
+        for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
         const bool tet = D.ctype[c] == 4;
+        const R one = (R)1, two_pi = (R)2 * (R)kPi;
         for (long long k = lane; k < ns; k += kWave) {
             const long long i = base + k;
             const uint64_t uid = make_uid(step, c, k);
             const uint64_t puid = make_uid(step, c, k & ~1LL);
             U4 rv = draw(D.seed, puid, step, kTagVel, 0);
-            double e0 = unif(rv.v[0]), e1 = unif(rv.v[1]), e2 = unif(rv.v[2]), e3 = unif(rv.v[3]);
-            double r1 = sqrt(-2.0 * log(e0)), r2 = sqrt(-2.0 * log(e2));
-            double X[3] = {r1 * cos(2.0 * kPi * e1), r1 * sin(2.0 * kPi * e1), r2 * cos(2.0 * kPi * e3)};
-            const double sg = (k & 1) ? -1.0 : 1.0;
-            double u[3];
+            R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
+            R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
+            R X[3] = {r1 * cos(two_pi * e1), r1 * sin(two_pi * e1), r2 * cos(two_pi * e3)};
+            const R sg = (k & 1) ? -one : one;
+            R u[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
             U4 rp = draw(D.seed, uid, step, kTagPos, 0);
-            double s = unif(rp.v[0]), t = unif(rp.v[1]), w = unif(rp.v[2]);
+            R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
             if (tet) {
-                if (s + t > 1.0) {
-                    s = 1.0 - s;
-                    t = 1.0 - t;
+                if (s + t > one) {
+                    s = one - s;
+                    t = one - t;
                 }
-                if (t + w > 1.0) {
-                    double tmp = w;
-                    w = 1.0 - s - t;
-                    t = 1.0 - tmp;
-                } else if (s + t + w > 1.0) {
-                    double tmp = w;
-                    w = s + t + w - 1.0;
-                    s = 1.0 - t - tmp;
+                if (t + w > one) {
+                    R tmp = w;
+                    w = one - s - t;
+                    t = one - tmp;
+                } else if (s + t + w > one) {
+                    R tmp = w;
+                    w = s + t + w - one;
+                    s = one - t - tmp;
                 }
             }
-            double x[3];
+            R x[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
-            double2 *r = reinterpret_cast<double2 *>(pa.rec + i);
-            r[0] = make_double2(x[0], x[1]);
-            r[1] = make_double2(x[2], u[0]);
-            r[2] = make_double2(u[1], u[2]);
-            r[3] = make_double2(msam, __longlong_as_double((long long)uid));
+            store_new(pa, i, x, u, msam, uid);
             pa.cell[i] = c;
-            acc[0] += msam;
-            acc[1] += msam * u[0];
-            acc[2] += msam * u[1];
-            acc[3] += msam * u[2];
-            acc[4] += msam * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+            add_phi<R>(acc, msam, u);
         }
     }
 #pragma unroll
@@ -536,54 +595,84 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
 // the plane formula (d - n.x) / (n.u) with n = +-e_d, term by term, so both paths give the
 // same bits.  Returns 0 inside (cell updated), 1 escaped through a far-field face, -1 lost.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, const double n[3], double u[3],
-                                               uint64_t uid, long long step, int bounce) {
-    // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential components
-    // N(U_w, T_w) in the face frame
-    U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
-    double t1[3], t2[3];
-    face_frame(n, t1, t2);
-    const double sq = sqrt(b.Tw);
-    const double vn = sqrt(-2.0 * b.Tw * log(unif(r.v[0])));
-    const double rr = sqrt(-2.0 * log(unif(r.v[1])));
-    const double a = 2.0 * kPi * unif(r.v[2]);
-    const double X1 = rr * cos(a), X2 = rr * sin(a);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) u[d] = b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+template <typename R>
+__device__ __forceinline__ const R *cell_box(const Dev &D, int c);
+template <>
+__device__ __forceinline__ const double *cell_box<double>(const Dev &D, int c) {
+    return D.box + 6 * c;
+}
+template <>
+__device__ __forceinline__ const float *cell_box<float>(const Dev &D, int c) {
+    return D.box32 + 6 * c;
+}
+__device__ __forceinline__ void cell_plane(const Dev &D, int s, double p[4]) {
+    const double4 q = D.plane[s];
+    p[0] = q.x;
+    p[1] = q.y;
+    p[2] = q.z;
+    p[3] = q.w;
+}
+__device__ __forceinline__ void cell_plane(const Dev &D, int s, float p[4]) {
+    const float4 q = D.plane32[s];
+    p[0] = q.x;
+    p[1] = q.y;
+    p[2] = q.z;
+    p[3] = q.w;
 }
 
-__device__ int track(const Dev &D, double x[3], double u[3], int &cell, double ts, uint64_t uid, long long step,
-                     int &ncross, int &nwall) {
+// diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential components
+// N(U_w, T_w) in the face frame
+template <typename R>
+__device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, const R n[3], R u[3], uint64_t uid,
+                                               long long step, int bounce) {
+    U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
+    R t1[3], t2[3];
+    face_frame<R>(n, t1, t2);
+    const R Tw = (R)b.Tw;
+    const R sq = sqrt(Tw);
+    const R vn = sqrt((R)-2 * Tw * log(unif<R>(r.v[0])));
+    const R rr = sqrt((R)-2 * log(unif<R>(r.v[1])));
+    const R a = (R)2 * (R)kPi * unif<R>(r.v[2]);
+    const R X1 = rr * cos(a), X2 = rr * sin(a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d] = (R)b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+}
+
+template <typename R>
+__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, uint64_t uid, long long step, int &ncross,
+                     int &nwall) {
+    // margin of the exact division skip below: well above the rounding of the products
+    const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
     int c = cell;
     int entry = -1;
-    double trem = ts;
+    R trem = ts;
     int bounce = 0;
     ncross = 0;
     for (;;) {
-        double best = INFINITY;
+        R best = (R)INFINITY;
         int bf = -1;
         if (D.ctype[c] == 8) {
-            const double *B = D.box + 6 * c;
+            const R *B = cell_box<R>(D, c);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                // a face at distance a >= |u_d| trem (1 + 1e-12) has a computed exit time
+                // a face at distance a >= |u_d| trem (1 + margin) has a computed exit time
                 // >= trem, so it can be neither the minimum nor a crossing: no division
-                const double ud = u[d];
-                if (ud > 0.0) {
-                    const double a = B[3 + d] - x[d];
-                    if (2 * d + 1 != entry && !(a >= ud * trem * (1.0 + 1e-12))) {
-                        double tt = a / ud;
-                        if (tt < 0.0) tt = 0.0;
+                const R ud = u[d];
+                if (ud > (R)0) {
+                    const R a = B[3 + d] - x[d];
+                    if (2 * d + 1 != entry && !(a >= ud * trem * skip)) {
+                        R tt = a / ud;
+                        if (tt < (R)0) tt = (R)0;
                         if (tt < best) {
                             best = tt;
                             bf = 2 * d + 1;
                         }
                     }
-                } else if (ud < 0.0) {
-                    const double a = x[d] - B[d];
-                    if (2 * d != entry && !(a >= (-ud) * trem * (1.0 + 1e-12))) {
-                        double tt = a / (-ud);
-                        if (tt < 0.0) tt = 0.0;
+                } else if (ud < (R)0) {
+                    const R a = x[d] - B[d];
+                    if (2 * d != entry && !(a >= (-ud) * trem * skip)) {
+                        R tt = a / (-ud);
+                        if (tt < (R)0) tt = (R)0;
                         if (tt < best) {
                             best = tt;
                             bf = 2 * d;
@@ -595,11 +684,12 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
             const int nfc = D.nfc[c];
             for (int lf = 0; lf < nfc; ++lf) {
                 if (lf == entry) continue;
-                const double4 p = D.plane[c * 6 + lf];
-                const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
-                if (un > 0.0) {
-                    double tt = (p.w - (p.x * x[0] + p.y * x[1] + p.z * x[2])) / un;
-                    if (tt < 0.0) tt = 0.0;
+                R p[4];
+                cell_plane(D, c * 6 + lf, p);
+                const R un = p[0] * u[0] + p[1] * u[1] + p[2] * u[2];
+                if (un > (R)0) {
+                    R tt = (p[3] - (p[0] * x[0] + p[1] * x[1] + p[2] * x[2])) / un;
+                    if (tt < (R)0) tt = (R)0;
                     if (tt < best) {
                         best = tt;
                         bf = lf;
@@ -635,17 +725,19 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
                 const int d = bf >> 1;
                 u[d] = -u[d];
             } else {
-                const double4 p = D.plane[c * 6 + bf];
-                const double un = p.x * u[0] + p.y * u[1] + p.z * u[2];
-                u[0] = u[0] - 2.0 * un * p.x;
-                u[1] = u[1] - 2.0 * un * p.y;
-                u[2] = u[2] - 2.0 * un * p.z;
+                R p[4];
+                cell_plane(D, c * 6 + bf, p);
+                const R un = p[0] * u[0] + p[1] * u[1] + p[2] * u[2];
+                u[0] = u[0] - (R)2 * un * p[0];
+                u[1] = u[1] - (R)2 * un * p[1];
+                u[2] = u[2] - (R)2 * un * p[2];
             }
             entry = bf;
         } else if (b.type == 1) {
-            const double4 p = D.plane[c * 6 + bf];
-            const double n[3] = {p.x, p.y, p.z};
-            reemit_diffuse(D, b, n, u, uid, step, bounce);
+            R p[4];
+            cell_plane(D, c * 6 + bf, p);
+            const R n[3] = {p[0], p[1], p[2]};
+            reemit_diffuse<R>(D, b, n, u, uid, step, bounce);
             ++bounce;
             ++nwall;
             entry = bf;
@@ -656,13 +748,70 @@ __device__ int track(const Dev &D, double x[3], double u[3], int &cell, double t
     }
 }
 
+// load / store of the transported state of particle i
+struct StateF64 {
+    double2 r3;
+};
+struct StateF32 {};
+__device__ __forceinline__ void load_state(const Particles &pa, long long i, double x[3], double u[3], uint64_t &uid,
+                                           StateF64 &keep) {
+    const double2 *rp = reinterpret_cast<const double2 *>(pa.rec + i);
+    const double2 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+    keep.r3 = rp[3];
+    uid = (uint64_t)__double_as_longlong(keep.r3.y);
+    x[0] = r0.x;
+    x[1] = r0.y;
+    x[2] = r1.x;
+    u[0] = r1.y;
+    u[1] = r2.x;
+    u[2] = r2.y;
+}
+__device__ __forceinline__ void store_state(const Particles &pa, long long i, const double x[3], const double u[3],
+                                            const StateF64 &keep) {
+    double2 *rp = reinterpret_cast<double2 *>(pa.rec + i);
+    rp[0] = make_double2(x[0], x[1]);
+    rp[1] = make_double2(x[2], u[0]);
+    rp[2] = make_double2(u[1], u[2]);
+    rp[3] = keep.r3;
+}
+__device__ __forceinline__ void load_state(const Particles &pa, long long i, float x[3], float u[3], uint64_t &uid,
+                                           StateF32 &) {
+    const float4 *rp = reinterpret_cast<const float4 *>(pa.rec32 + i);
+    const float4 a = rp[0], b = rp[1];
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = a.z;
+    u[0] = a.w;
+    u[1] = b.x;
+    u[2] = b.y;
+    uid = (uint64_t)__float_as_uint(b.z) | ((uint64_t)__float_as_uint(b.w) << 32);
+}
+__device__ __forceinline__ void store_state(const Particles &pa, long long i, const float x[3], const float u[3],
+                                            const StateF32 &) {
+    float4 *rp = reinterpret_cast<float4 *>(pa.rec32 + i);
+    rp[0] = make_float4(x[0], x[1], x[2], u[0]);
+    float2 *q = reinterpret_cast<float2 *>(rp + 1);
+    q[0] = make_float2(u[1], u[2]);
+}
+template <typename R>
+struct StateOf;
+template <>
+struct StateOf<double> {
+    using T = StateF64;
+};
+template <>
+struct StateOf<float> {
+    using T = StateF32;
+};
+
 // One thread per particle; blocks past the live particles exit at once.  The free-flight
 // time of an old particle is t_f = -tau ln eta with tau of its start cell; it collides iff
 // t_f < dt.  Since t_f < dt <=> eta > exp(-dt/tau), eta below exp(-dt/tau) by a relative
-// 1e-12 decides the comparison without the logarithm (the same decision as the formula,
+// margin decides the comparison without the logarithm (the same decision as the formula,
 // which is evaluated near the threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
 // (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
+template <typename R>
 __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     __shared__ unsigned long long red[2][4];
     const Scalars *sc = D.sc;
@@ -671,28 +820,28 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     const long long i0 = (long long)blockIdx.x * blockDim.x;
     if (i0 >= n_tot) return;
     const long long i = i0 + threadIdx.x;
-    const double dt = sc->dt;
+    const R dt = (R)sc->dt;
     const long long step = sc->step;
     const Particles pa = D.pa[buf];
+    const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
     if (i < n_tot) {
         int c = pa.cell[i];
         const int c0 = c;
-        double2 *rp = reinterpret_cast<double2 *>(pa.rec + i);
-        const double2 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
-        const uint64_t uid = (uint64_t)__double_as_longlong(r3.y);
+        R x[3], u[3];
+        uint64_t uid;
+        typename StateOf<R>::T keep;
+        load_state(pa, i, x, u, uid, keep);
         // start-cell data, loaded before the generator runs
-        const double e = D.ec[c], tauc = D.tau[c];
-        double x[3] = {r0.x, r0.y, r1.x};
-        double u[3] = {r1.y, r2.x, r2.y};
-        double ts = dt;
+        const R e = (R)D.ec[c], tauc = (R)D.tau[c];
+        R ts = dt;
         bool collided = false;
         if (i < n_old) {
             const U4 r = draw(D.seed, uid, step, kTagTF, 0);
-            const double eta = unif(r.v[0]);
-            if (!(eta < e * (1.0 - 1e-12))) {
-                const double tf = -tauc * log(eta);
+            const R eta = unif<R>(r.v[0]);
+            if (!(eta < e * lmargin)) {
+                const R tf = -tauc * log(eta);
                 if (tf < dt) {
                     ts = tf;
                     collided = true;
@@ -700,13 +849,10 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
             }
         }
         int nx = 0, nw = 0;
-        const int rc = track(D, x, u, c, ts, uid, step, nx, nw);
+        const int rc = track<R>(D, x, u, c, ts, uid, step, nx, nw);
         nx_ = (unsigned long long)nx;
         nw_ = (unsigned long long)nw;
-        rp[0] = make_double2(x[0], x[1]);
-        rp[1] = make_double2(x[2], u[0]);
-        rp[2] = make_double2(u[1], u[2]);
-        rp[3] = r3;
+        store_state(pa, i, x, u, keep);
         pa.cell[i] = c;
         int key = -1;
         bool stay = false;
@@ -819,16 +965,13 @@ __device__ void block_sort(int *a, int len) {
 // they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-thread
 // assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-// copy one 64-byte record (4 x 16 bytes) and add its phi = m (1, u, |u|^2/2) to acc
-__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c, double acc[5]) {
+// copy one particle record and add its phi = m (1, u, |u|^2/2) (FP64 sums) to acc
+__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c,
+                                         double acc[5], double) {
     const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
     const double2 r0 = a[0], r1 = a[1], r2 = a[2], r3 = a[3];
-    const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
-    acc[0] += m;
-    acc[1] += m * u0;
-    acc[2] += m * u1;
-    acc[3] += m * u2;
-    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+    const double u[3] = {r1.y, r2.x, r2.y};
+    add_phi<double>(acc, r3.x, u);
     double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
     b[0] = r0;
     b[1] = r1;
@@ -836,29 +979,53 @@ __device__ __forceinline__ void move_rec(const Particles &src, const Particles &
     b[3] = r3;
     dst.cell[o] = c;
 }
-
-// add phi of a record without copying it (collided particles)
-__device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5]) {
-    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
-    const double2 r1 = a[1], r2 = a[2], r3 = a[3];
-    const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
-    acc[0] += m;
-    acc[1] += m * u0;
-    acc[2] += m * u1;
-    acc[3] += m * u2;
-    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c,
+                                         double acc[5], float) {
+    const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
+    const float4 r0 = a[0], r1 = a[1];
+    const float m = src.m32[s];
+    const float u[3] = {r0.w, r1.x, r1.y};
+    add_phi<float>(acc, m, u);
+    float4 *b = reinterpret_cast<float4 *>(dst.rec32 + o);
+    b[0] = r0;
+    b[1] = r1;
+    dst.m32[o] = m;
+    dst.cell[o] = c;
 }
 
-template <int BS>
-__global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
-    static_assert(BS == kWave, "one wave per cell");
+// add phi of a record without copying it (collided particles)
+__device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5], double) {
+    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
+    const double2 r1 = a[1], r2 = a[2], r3 = a[3];
+    const double u[3] = {r1.y, r2.x, r2.y};
+    add_phi<double>(acc, r3.x, u);
+}
+__device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5], float) {
+    const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
+    const float4 r0 = a[0], r1 = a[1];
+    const float u[3] = {r0.w, r1.x, r1.y};
+    add_phi<float>(acc, src.m32[s], u);
+}
+
+// ---------------------------------------------------------------------------------------
+// S6: one wave per cell c.  The survivors ending in c are laid out in the next buffer as
+//   [movers into c, ascending source index] [stayers of c, in their segment order]
+// where stayers (collisionless, ended where they started) are found by scanning c's own
+// start segments (old particles, then the ones sampled this step) and movers come bucketed
+// by k_scatter.  Sums over survivors give P^{n+1}; with the collided particles ending in c
+// they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-lane
+// assignment and reduction tree: bitwise reproducible.
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
+    constexpr int BS = kWave;
     constexpr int kLds = 1024;
     __shared__ int lds[kLds];
     // blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
     // that neighbouring cells (whose particles are exchanged) share an L2
-    const int G = (int)gridDim.x, b = (int)blockIdx.x;
-    const int xcd = b & 7, q = G >> 3, r = G & 7;
-    const int c = xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+    const int G = (int)gridDim.x, bidx = (int)blockIdx.x;
+    const int xcd = bidx & 7, q = G >> 3, rr = G & 7;
+    const int c = xcd * q + (xcd < rr ? xcd : rr) + (bidx >> 3);
     const int nc = D.nc, nf = D.nf;
     const int lane = lane_id();
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
@@ -910,14 +1077,13 @@ __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
         for (int j = lane; j < len; j += BS) {
             const int sidx = list[j];
             if (part == 0)
-                move_rec(src, dst, sidx, a0 + j, c, Pn);
+                move_rec(src, dst, sidx, a0 + j, c, Pn, R(0));
             else
-                add_rec(src, sidx, Cn);
+                add_rec(src, sidx, Cn, R(0));
         }
         __syncthreads();
     }
-    // stayers: own segment of old particles, then own new particles, compacted in order;
-    // a record is loaded together with its key (same cache lines as its neighbours anyway)
+    // stayers: own segment of old particles, then own new particles, compacted in order
     const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
     int pos = base + nmov;
     for (int seg = 0; seg < 2; ++seg) {
@@ -925,33 +1091,10 @@ __global__ void __launch_bounds__(BS) k_gather(Dev D, int buf) {
         const long long s1 = seg == 0 ? s01 : (n_new == 0 ? s10 : s11);
         for (long long j0 = s0; j0 < s1; j0 += BS) {
             const long long j = j0 + lane;
-            int k = -1;
-            double2 r0, r1, r2, r3;
-            if (j < s1) {
-                k = D.key[j];
-                const double2 *a = reinterpret_cast<const double2 *>(src.rec + j);
-                r0 = a[0];
-                r1 = a[1];
-                r2 = a[2];
-                r3 = a[3];
-            }
+            const int k = j < s1 ? D.key[j] : -1;
             const bool st = k >= 0 && (k & kStayBit) != 0;
             const unsigned long long msk = __ballot(st);
-            if (st) {
-                const int o = pos + (int)__popcll(msk & below);
-                const double m = r3.x, u0 = r1.y, u1 = r2.x, u2 = r2.y;
-                Pn[0] += m;
-                Pn[1] += m * u0;
-                Pn[2] += m * u1;
-                Pn[3] += m * u2;
-                Pn[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
-                double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
-                b[0] = r0;
-                b[1] = r1;
-                b[2] = r2;
-                b[3] = r3;
-                dst.cell[o] = c;
-            }
+            if (st) move_rec(src, dst, (int)j, pos + (int)__popcll(msk & below), c, Pn, R(0));
             pos += (int)__popcll(msk);
         }
     }
@@ -1162,15 +1305,27 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     k_fill<unsigned long long><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt64, 2LL * nc, 0ULL);
     k_fill<unsigned long long><<<1, 128, 0, s>>>(D.spart, 128, 0ULL);
     pr->end(kSlotScan);
+    const bool f32 = D.prec == 1;
     pr->begin(kSlotFlux);
-    if (nf > 0) k_flux<<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+    if (nf > 0) {
+        if (f32)
+            k_flux<float><<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+        else
+            k_flux<double><<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+    }
     pr->end(kSlotFlux);
     pr->begin(kSlotSample);
-    k_sample<<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+    if (f32)
+        k_sample<float><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+    else
+        k_sample<double><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
     pr->end(kSlotSample);
     pr->begin(kSlotStream);
     const unsigned pb = (unsigned)stream_blocks(D.cap);
-    k_stream<<<pb, 256, 0, s>>>(D, buf);
+    if (f32)
+        k_stream<float><<<pb, 256, 0, s>>>(D, buf);
+    else
+        k_stream<double><<<pb, 256, 0, s>>>(D, buf);
     pr->end(kSlotStream);
     pr->begin(kSlotCount);
     k_count<<<pb, 256, 0, s>>>(D);
@@ -1184,7 +1339,10 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
     (void)gather_bs;
-    k_gather<64><<<nc, 64, 0, s>>>(D, buf);
+    if (f32)
+        k_gather<float><<<nc, 64, 0, s>>>(D, buf);
+    else
+        k_gather<double><<<nc, 64, 0, s>>>(D, buf);
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
     k_finalize<<<1, 256, 0, s>>>(D, buf);

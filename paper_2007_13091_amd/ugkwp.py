@@ -134,11 +134,11 @@ def make_params(p, capacity=0, recon=0, precision=0) -> UgkwpParams:
                        p.max_crossings, p.seed)
 
 
-def workspace_bytes(mesh, params, capacity=0) -> int:
+def workspace_bytes(mesh, params, capacity=0, precision=0) -> int:
     """Device bytes the library needs (host-side computation: mesh checks and layout)."""
     L = lib()
     m = _MeshArgs(mesh)
-    pr = make_params(params, capacity)
+    pr = make_params(params, capacity, precision=precision)
     n = C.c_size_t(0)
     st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
     if st != OK:
@@ -149,7 +149,7 @@ def workspace_bytes(mesh, params, capacity=0) -> int:
 class Solver:
     """One mesh on one GPU.  `mesh`, `params`: see paper_2007_13091_amd.workloads."""
 
-    def __init__(self, mesh, params, capacity=0, device="cuda"):
+    def __init__(self, mesh, params, capacity=0, precision=0, device="cuda"):
         import torch
 
         if not torch.cuda.is_available():
@@ -158,11 +158,12 @@ class Solver:
         self.torch = torch
         self.nc = mesh.n_cells
         m = _MeshArgs(mesh)
-        pr = make_params(params, capacity)
+        pr = make_params(params, capacity, precision=precision)
         n = C.c_size_t(0)
         st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
         if st != OK:
             raise UgkwpError(st, L.ugkwp_last_error(None).decode())
+        self.precision = precision
         self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
         self.stream = torch.cuda.current_stream(self.ws.device)
         h = C.c_void_p(0)
