@@ -68,8 +68,10 @@ def lib():
         L.orc_step.argtypes = [vp]
         L.orc_sample_only.restype = C.c_int
         L.orc_sample_only.argtypes = [vp, P(d)]
+        L.orc_flux_speed.restype = d
+        L.orc_flux_speed.argtypes = [d, d]
         L.orc_track.restype = C.c_int
-        L.orc_track.argtypes = [vp, P(d), P(d), P(i64), d, u64, i64, P(i64), P(i64)]
+        L.orc_track.argtypes = [vp, P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
         _lib = L
     return _lib
 
@@ -84,6 +86,11 @@ def philox(ctr, key):
     out = np.zeros(4, dtype=np.uint64)
     lib().orc_philox4x64_10(_p(c, C.c_uint64), _p(k, C.c_uint64), _p(out, C.c_uint64))
     return out
+
+
+def flux_speed(a, eta):
+    """z > 0 with the flux-weighted half-normal distribution function G(z) = eta (drift a)."""
+    return float(lib().orc_flux_speed(float(a), float(eta)))
 
 
 def make_uid(ghost, step, where, k):
@@ -191,10 +198,10 @@ class Oracle:
 
     def stats(self):
         dt = C.c_double(0)
-        out = np.zeros(6, dtype=np.int64)
+        out = np.zeros(7, dtype=np.int64)
         lib().orc_stats(self.h, C.byref(dt), _p(out, C.c_int64))
         return dict(dt=dt.value, n_alive=int(out[0]), n_sampled=int(out[1]), n_collided=int(out[2]),
-                    n_escaped=int(out[3]), crossings=int(out[4]), wall_hits=int(out[5]))
+                    n_escaped=int(out[3]), crossings=int(out[4]), wall_hits=int(out[5]), n_injected=int(out[6]))
 
     def geometry(self):
         vol = np.zeros(self.nc)
@@ -230,6 +237,6 @@ class Oracle:
         """Free transport of one particle (for tracking pins); returns (rc, x, u, cell, crossings)."""
         x = np.array(x, dtype=np.float64); u = np.array(u, dtype=np.float64)
         c = C.c_int64(cell); nc = C.c_int64(0); nw = C.c_int64(0)
-        rc = lib().orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(c), ts, uid, step,
+        rc = lib().orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(c), ts, -1, uid, step,
                              C.byref(nc), C.byref(nw))
         return rc, x, u, c.value, nc.value

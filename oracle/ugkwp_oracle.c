@@ -337,6 +337,9 @@ typedef struct oracle {
     int *csign;       /* [nc][6] +1 when the cell owns the face */
     double *pn, *pd;  /* [nc][6][3], [nc][6]: outward plane n.x = d */
     int64_t *cnb;     /* [nc][6] neighbour cell, or -1 - bc index */
+    int64_t *cbf;     /* [nc][6] input index of the boundary face, or -1 */
+    double *bo, *be1, *be2, *barea; /* per input boundary face: corner, two edges, area */
+    int *btri;                       /* triangle (1) or parallelogram (0) */
     int *cnblf;       /* [nc][6] local face index in the neighbour */
     double *orig, *edge; /* sampling frame: [nc][3], [nc][3][3] */
     int64_t *fown, *fnb; /* fnb: neighbour cell or -1 - bc index */
@@ -355,7 +358,7 @@ typedef struct oracle {
     uint64_t *pid;
     /* last step statistics */
     double st_dt;
-    int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits;
+    int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits, st_injected;
 } oracle_t;
 
 static int cmp_fkey(const void *a, const void *b)
@@ -412,6 +415,8 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     o->pn = (double *)xcalloc(18 * nc, sizeof(double));
     o->pd = (double *)xcalloc(6 * nc, sizeof(double));
     o->cnb = (int64_t *)xcalloc(6 * nc, sizeof(int64_t));
+    o->cbf = (int64_t *)xcalloc(6 * nc, sizeof(int64_t));
+    for (int64_t i = 0; i < 6 * nc; ++i) o->cbf[i] = -1;
     o->cnblf = (int *)xcalloc(6 * nc, sizeof(int));
     o->orig = (double *)xcalloc(3 * nc, sizeof(double));
     o->edge = (double *)xcalloc(9 * nc, sizeof(double));
@@ -532,7 +537,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
             for (int i = 0; i < 4; ++i) bk[b].key[i] = bface_nodes[4 * b + i];
             sort_key(bk[b].key, nn);
             bk[b].cell = bface_bc[b];
-            bk[b].lf = 0;
+            bk[b].lf = (int)b;
             if (bface_bc[b] < 0 || bface_bc[b] >= n_bc) { free(keys); free(bk); goto fail; }
         }
         qsort(bk, n_bfaces, sizeof(fkey_t), cmp_fkey);
@@ -582,6 +587,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                 o->farea[nf] = larea[6 * c + lf];
                 o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
                 o->cnb[6 * c + lf] = -1 - b; o->cnblf[6 * c + lf] = -1;
+                o->cbf[6 * c + lf] = bk[found].lf;
                 ++nf;
             } else {
                 bad = 1;
@@ -601,6 +607,29 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
         }
     }
     free(larea);
+    /* boundary faces in input order: p0, edges p1 - p0 and (p2 or p3) - p0, area */
+    o->bo = (double *)xcalloc(3 * n_bfaces, sizeof(double));
+    o->be1 = (double *)xcalloc(3 * n_bfaces, sizeof(double));
+    o->be2 = (double *)xcalloc(3 * n_bfaces, sizeof(double));
+    o->barea = (double *)xcalloc(n_bfaces, sizeof(double));
+    o->btri = (int *)xcalloc(n_bfaces, sizeof(int));
+    for (int64_t b = 0; b < n_bfaces; ++b) {
+        const int64_t *bn = bface_nodes + 4 * b;
+        int tri = bn[3] < 0;
+        const double *p0 = xyz + 3 * bn[0], *p1 = xyz + 3 * bn[1], *pq = xyz + 3 * (tri ? bn[2] : bn[3]);
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) {
+            o->bo[3 * b + d] = p0[d];
+            e1[d] = p1[d] - p0[d];
+            e2[d] = pq[d] - p0[d];
+            o->be1[3 * b + d] = e1[d];
+            o->be2[3 * b + d] = e2[d];
+        }
+        double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+        double cr = sqrt(cx * cx + cy * cy + cz * cz);
+        o->barea[b] = tri ? 0.5 * cr : cr;
+        o->btri[b] = tri;
+    }
     o->cap = 0;
     *status = ORC_OK;
     return o;
@@ -614,7 +643,8 @@ void orc_destroy(oracle_t *o)
 {
     if (!o) return;
     free(o->ctype); free(o->cnf); free(o->vol); free(o->xc); free(o->dS);
-    free(o->cface); free(o->csign); free(o->pn); free(o->pd); free(o->cnb); free(o->cnblf);
+    free(o->cface); free(o->csign); free(o->pn); free(o->pd); free(o->cnb); free(o->cnblf); free(o->cbf);
+    free(o->bo); free(o->be1); free(o->be2); free(o->barea); free(o->btri);
     free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
     free(o->bc); free(o->W); free(o->P); free(o->nleft);
     free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
@@ -634,11 +664,11 @@ void orc_geometry(const oracle_t *o, double *vol, double *xc, double *dS)
     memcpy(dS, o->dS, sizeof(double) * 3 * o->nc);
 }
 
-void orc_stats(const oracle_t *o, double *dt, int64_t out[6])
+void orc_stats(const oracle_t *o, double *dt, int64_t out[7])
 {
     *dt = o->st_dt;
     out[0] = o->st_alive; out[1] = o->st_sampled; out[2] = o->st_collided;
-    out[3] = o->st_escaped; out[4] = o->st_cross; out[5] = o->st_wallhits;
+    out[3] = o->st_escaped; out[4] = o->st_cross; out[5] = o->st_wallhits; out[6] = o->st_injected;
 }
 
 int orc_set_state(oracle_t *o, const double *W)
@@ -705,11 +735,11 @@ static void add_phi(double S[5], double m, const double u[3])
 /* diffuse re-emits from the wall Maxwellian (flux-weighted normal component); far-field  */
 /* removes the particle.  Returns 0 (inside), 1 (escaped) or -1 (too many crossings).      */
 /* ------------------------------------------------------------------------------------ */
-int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double ts, uint64_t uid,
+int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double ts, int entry0, uint64_t uid,
               int64_t step, int64_t *ncross, int64_t *nwall)
 {
     int64_t c = *cell;
-    int entry = -1;
+    int entry = entry0;
     double trem = ts;
     int bounce = 0;
     *ncross = 0;
@@ -880,6 +910,106 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
     return ORC_OK;
 }
 
+/* Normal speed of a particle entering from a Maxwellian reservoir: z = v_n / sigma has the
+ * flux-weighted density z phi(z - a) / Z(a) on z > 0 (a = drift / sigma, phi the standard
+ * normal density, Z(a) = phi(a) + a Phi(a)); its distribution function is
+ *   G(z) = (phi(a) - phi(z - a) + a (Phi(z - a) - Phi(-a))) / Z(a).
+ * G(z) = eta is solved by 60 bisections of [0, max(a, 0) + 40]. */
+static double npdf(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * M_PI); }
+static double ncdf(double t) { return 0.5 * erfc(-t / sqrt(2.0)); }
+double orc_flux_speed(double a, double eta)
+{
+    double Z = npdf(a) + a * ncdf(a);
+    double lo = 0.0, hi = (a > 0.0 ? a : 0.0) + 40.0;
+    for (int it = 0; it < 60; ++it) {
+        double z = 0.5 * (lo + hi);
+        double G = (npdf(a) - npdf(z - a) + a * (ncdf(z - a) - ncdf(-a))) / Z;
+        if (G < eta) lo = z; else hi = z;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Free-stream particles entering through far-field faces (a reading of the far-field
+ * boundary for the particle part): the outside is a reservoir of the free stream W_inf, whose
+ * collisionless hydro part exp(-dt/tau_inf) rho_inf crosses each face with the one-sided
+ * number flux Gamma = s Phi(s/sigma) + sigma phi(s/sigma) (s = U_inf . n_in, sigma =
+ * sqrt(T_inf)).  Face of area A on cell Omega: mass M = exp(-dt/tau_inf) rho_inf Gamma A dt,
+ * N = ceil(Gamma A dt N_ref / Omega) particles of mass M / N (the reference mass of the cell
+ * in the free stream); none when that ratio is below 1e-9.  Particle k: normal speed from the
+ * flux-weighted half-Maxwellian, tangential components N(U_inf.t, T_inf) in the face frame,
+ * entry uniform in time over the step and uniform on the face; it then flies for the rest of
+ * the step with the face as entry face.  Appended after the sampled particles; tin[] and ein[]
+ * receive their flight time and entry face. */
+static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t *ninj)
+{
+    *ninj = 0;
+    int64_t cap = 0;
+    for (int64_t c = 0; c < o->nc; ++c) {
+        for (int lf = 0; lf < o->cnf[c]; ++lf) {
+            int64_t nb = o->cnb[6 * c + lf];
+            if (nb >= 0 || o->bc[-1 - nb].type != BC_FARFIELD) continue;
+            const obc_t *b = o->bc + (-1 - nb);
+            const double *Wi = b->Winf;
+            double rho = Wi[0];
+            double Ui[3] = {Wi[1] / rho, Wi[2] / rho, Wi[3] / rho};
+            double T = (2.0 / 3.0) * (Wi[4] - 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2] + Wi[3] * Wi[3]) / rho) / rho;
+            double tau = o->mu_ref * pow(T, o->omega) / (rho * T);
+            double e = exp(-dt / tau);
+            int64_t bf = o->cbf[6 * c + lf];
+            const double *n = o->pn + 18 * c + 3 * lf; /* out of the domain */
+            double nin[3] = {-n[0], -n[1], -n[2]};
+            double t1[3], t2[3];
+            face_frame(nin, t1, t2);
+            double sig = sqrt(T);
+            double sd = Ui[0] * nin[0] + Ui[1] * nin[1] + Ui[2] * nin[2];
+            double a = sd / sig;
+            double Gam = sig * (npdf(a) + a * ncdf(a));
+            double area = o->barea[bf];
+            double r = Gam * area * dt * o->n_ref / o->vol[c];
+            if (!(e * rho > 0.0) || !(r >= 1e-9)) continue;
+            int64_t N = (int64_t)ceil(r);
+            if (N > (1 << 20)) return ORC_E_CAPACITY;
+            double msam = (e * rho * Gam * area * dt) / N;
+            double vt1 = Ui[0] * t1[0] + Ui[1] * t1[1] + Ui[2] * t1[2];
+            double vt2 = Ui[0] * t2[0] + Ui[1] * t2[1] + Ui[2] * t2[2];
+            const double *fo = o->bo + 3 * bf, *f1 = o->be1 + 3 * bf, *f2 = o->be2 + 3 * bf;
+            for (int64_t k = 0; k < N; ++k) {
+                uint64_t uid = orc_make_uid(1, o->step, bf, k);
+                double ev[4], ep[4];
+                draw4(o->seed, uid, o->step, TAG_INJECT, 0, o->inst, ev);
+                draw4(o->seed, uid, o->step, TAG_POS, 0, o->inst, ep);
+                double vn = sig * orc_flux_speed(a, ev[0]);
+                double rr = sqrt(-2.0 * log(ev[1]));
+                double X1 = rr * cos(2.0 * M_PI * ev[2]), X2 = rr * sin(2.0 * M_PI * ev[2]);
+                double w1 = vt1 + sig * X1, w2 = vt2 + sig * X2;
+                double u[3], xs[3];
+                for (int d = 0; d < 3; ++d) u[d] = vn * nin[d] + w1 * t1[d] + w2 * t2[d];
+                double p1 = ep[0], p2 = ep[1];
+                if (o->btri[bf] && p1 + p2 > 1.0) { p1 = 1.0 - p1; p2 = 1.0 - p2; }
+                for (int d = 0; d < 3; ++d) xs[d] = fo[d] + p1 * f1[d] + p2 * f2[d];
+                if (reserve(o, o->np + 1)) return ORC_E_CAPACITY;
+                if (*ninj + 1 > cap) {
+                    cap = cap ? 2 * cap : 1024;
+                    double *tn = (double *)realloc(*tin, sizeof(double) * cap);
+                    if (tn) *tin = tn;
+                    int *en = (int *)realloc(*ein, sizeof(int) * cap);
+                    if (en) *ein = en;
+                    if (!tn || !en) return ORC_E_CAPACITY;
+                }
+                int64_t i = o->np++;
+                for (int d = 0; d < 3; ++d) { o->px[3 * i + d] = xs[d]; o->pu[3 * i + d] = u[d]; }
+                o->pm[i] = msam;
+                o->pc[i] = c;
+                o->pid[i] = uid;
+                (*tin)[*ninj] = ev[3] * dt;
+                (*ein)[*ninj] = lf;
+                ++*ninj;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
 /* Test hook: the cell phase and the sampling of the current step only (the new particles are
  * appended at their sampled positions; nothing streams and the step does not advance). */
 int orc_sample_only(oracle_t *o, double *dt)
@@ -903,6 +1033,8 @@ int orc_step(oracle_t *o)
     double *E = (double *)xcalloc(5 * nc, sizeof(double));
     double *Pn = (double *)xcalloc(5 * nc, sizeof(double));
     int64_t *nl = (int64_t *)xcalloc(nc, sizeof(int64_t));
+    double *tin = NULL;
+    int *ein = NULL;
     int status = phase_cells(o, &q);
     if (status != ORC_OK) goto done;
     const double dt = q.dt;
@@ -938,13 +1070,21 @@ int orc_step(oracle_t *o)
     status = phase_sample(o, &q, S, &nsampled);
     if (status != ORC_OK) goto done;
     o->st_sampled = nsampled;
+    int64_t ninj_start = o->np, ninj = 0;
+    status = phase_inject(o, dt, &tin, &ein, &ninj);
+    if (status != ORC_OK) goto done;
+    o->st_injected = ninj;
 
     /* free-flight time of every old particle t_f = min(-tau ln eta, dt), with tau of the cell it
        starts in; new particles fly for dt.  Stream, sum, and delete the collided and escaped. */
     int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0;
     for (int64_t i = 0; i < o->np; ++i) {
         double ts = dt;
-        int collided = 0;
+        int collided = 0, entry0 = -1;
+        if (i >= ninj_start) {
+            ts = tin[i - ninj_start];
+            entry0 = ein[i - ninj_start];
+        }
         if (i < nold) {
             double eta[4];
             draw4(o->seed, o->pid[i], o->step, TAG_TF, 0, o->inst, eta);
@@ -952,7 +1092,8 @@ int orc_step(oracle_t *o)
             if (tf < dt) { ts = tf; collided = 1; }
         }
         int64_t cross = 0;
-        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pc + i, ts, o->pid[i], o->step, &cross, &nwall);
+        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pc + i, ts, entry0, o->pid[i], o->step, &cross,
+                           &nwall);
         ncross_tot += cross;
         if (rc < 0) { status = ORC_E_LOST; goto done; }
         if (rc == 1) { ++nesc; continue; }
@@ -997,6 +1138,6 @@ int orc_step(oracle_t *o)
     o->t += dt;
 done:
     cellq_free(&q);
-    free(Phi); free(S); free(E); free(Pn); free(nl);
+    free(Phi); free(S); free(E); free(Pn); free(nl); free(tin); free(ein);
     return status;
 }
