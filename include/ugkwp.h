@@ -55,7 +55,9 @@ typedef enum {
 typedef enum {
     UGKWP_BC_SPECULAR = 0, /* symmetry plane / specular wall (Sec. 4.1) */
     UGKWP_BC_DIFFUSE = 1,  /* diffuse isothermal wall at T_w moving at U_w (Sec. 2.4(e)) */
-    UGKWP_BC_FARFIELD = 2  /* free stream W_inf; particles leaving are removed */
+    UGKWP_BC_FARFIELD = 2  /* free stream W_inf outside (Sec. 4.3): wave flux against W_inf,
+                              particles leaving are removed, and the collisionless part of
+                              the free stream enters as particles (see ugkwp_step_stats) */
 } ugkwp_bc_type;
 
 typedef struct {
@@ -106,11 +108,15 @@ typedef struct {
     int64_t n_sampled;     /* hydro particles sampled in the step */
     int64_t n_collided;    /* particles removed as collided */
     int64_t n_escaped;     /* particles removed at far-field faces */
-    int64_t n_moved;       /* particles streamed in the step (old + sampled) */
+    int64_t n_moved;       /* particles streamed in the step (old + sampled + entering) */
     int64_t crossings;     /* face crossings in the step */
     int64_t wall_hits;     /* diffuse re-emissions in the step */
     uint32_t error_word;   /* device error bits (0 = none) */
     int64_t moved_total;   /* particles streamed since ugkwp_init_state (sum of n_moved) */
+    int64_t n_injected;    /* free-stream particles that entered through far-field faces: per
+                              face exp(-dt/tau_inf) rho_inf Gamma A dt of mass (Gamma the one-sided
+                              number flux of the free-stream Maxwellian) in
+                              ceil(Gamma A dt n_ref / Omega) equal particles */
 } ugkwp_step_stats;
 
 /* Device bytes needed for one mesh with these parameters.  Host-side only (no device call). */

@@ -133,6 +133,12 @@ size_t carve(const HostMesh &H, long long cap, int prec, Dev &D, char *base) {
     D.fn = C.take<double>(3 * nf);
     D.farea = C.take<double>(nf);
     D.bc = C.take<DevBC>(nbc);
+    const size_t nff = (size_t)H.nff;
+    D.ffi = C.take<int4>(nff);
+    D.ffg = C.take<double>(10 * nff);
+    D.bflf = C.take<uint8_t>(H.bf_lf.size());
+    D.ninj = C.take<long long>(nff);
+    D.injoff = C.take<long long>(nff + 1);
     D.W = C.take<double>(5 * nc);
     D.P = C.take<double>(5 * nc);
     D.nleft = C.take<int32_t>(nc);
@@ -143,7 +149,7 @@ size_t carve(const HostMesh &H, long long cap, int prec, Dev &D, char *base) {
     D.S = C.take<double>(5 * nc);
     D.nsam = C.take<long long>(nc);
     D.samoff = C.take<long long>(nc + 1);
-    D.scan64 = C.take<long long>((size_t)ugkwp::scan_partials_needed((long long)nc));
+    D.scan64 = C.take<long long>((size_t)ugkwp::scan_partials_needed((long long)(nc > nff ? nc : nff)));
     D.cnt = C.take<int32_t>(2 * nc);
     D.off = C.take<int32_t>(2 * nc + 1);
     D.cursor = C.take<int32_t>(2 * nc);
@@ -303,6 +309,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     D.nc = H.nc;
     D.nf = H.nf;
     D.nbc = (int32_t)H.bcs.size();
+    D.nff = H.nff;
     D.mu_ref = p->mu_ref;
     D.omega = p->omega;
     D.cfl = p->cfl;
@@ -329,6 +336,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
         for (int d = 0; d < 3; ++d) bcs[b].Uw[d] = H.bcs[b].U_w[d];
         for (int k = 0; k < 5; ++k) bcs[b].Winf[k] = H.bcs[b].W_inf[k];
     }
+    std::vector<int4> ffi((size_t)H.nff);
+    for (int32_t j = 0; j < H.nff; ++j) ffi[j] = make_int4(H.ff_cell[j], H.ff_lf[j] | (H.ff_tri[j] << 8), H.ff_bf[j], H.ff_bc[j]);
     auto cleanup_fail = [&](const std::string &msg) {
         delete ctx;
         return fail(nullptr, UGKWP_E_DEVICE, msg);
@@ -356,6 +365,9 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     e = e ? e : up((double *)D.fn, fn, s);
     e = e ? e : up((double *)D.farea, H.farea, s);
     e = e ? e : up((DevBC *)D.bc, bcs, s);
+    e = e ? e : up((int4 *)D.ffi, ffi, s);
+    e = e ? e : up((double *)D.ffg, H.ff_geo, s);
+    e = e ? e : up((uint8_t *)D.bflf, H.bf_lf, s);
     e = e ? e : hipStreamSynchronize(s);
     if (e != hipSuccess) return cleanup_fail(std::string("upload: ") + hipGetErrorString(e));
     *out = ctx;
@@ -418,7 +430,9 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
         stats->wall_hits = (int64_t)s.n_wall;
         stats->error_word = s.err;
         stats->moved_total = (int64_t)s.moved_total;
-        // particles streamed in the last step: those alive at its start plus the sampled ones
+        stats->n_injected = (int64_t)s.n_injected;
+        // particles streamed in the last step: those alive at its start, the sampled and the
+        // entering ones
         stats->n_moved = s.n_alive + (int64_t)s.n_collided + (int64_t)s.n_escaped;
         if (st != UGKWP_OK) return st;
     }

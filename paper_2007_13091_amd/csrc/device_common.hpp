@@ -35,8 +35,9 @@ struct Scalars {
     long long step;
     long long n_old;      // particles at the start of the step (grouped by cell)
     long long n_new;      // particles sampled in the step (0 if the capacity check failed)
+    long long n_inj;      // free-stream particles entering in the step, stored after the sampled ones
     long long n_alive;    // particles after the step
-    unsigned long long n_sampled, n_collided, n_escaped, n_cross, n_wall;
+    unsigned long long n_sampled, n_injected, n_collided, n_escaped, n_cross, n_wall;
     unsigned long long moved_total;  // particles streamed since the state was set
     unsigned int err;
     unsigned int pad;
@@ -86,6 +87,10 @@ struct Dev {
     const double *fn;       // [3][nf]
     const double *farea;    // [nf]
     const DevBC *bc;        // [nbc]
+    int32_t nff, pad1;      // far-field faces
+    const int4 *ffi;        // [nff]  (cell, local face | triangle << 8, input boundary-face index, bc)
+    const double *ffg;      // [nff][10]  corner, two edges, area of the face as listed
+    const uint8_t *bflf;    // [n_bfaces]  local face of an input boundary face
     // parameters
     double mu_ref, omega, cfl, c2;
     int32_t n_ref, n_min, max_cross, prec;  // prec: 0 FP64 plain, 1 FP32 form
@@ -104,6 +109,8 @@ struct Dev {
     long long *nsam;        // [nc]
     long long *samoff;      // [nc+1]
     long long *scan64;      // scan partials
+    long long *ninj;        // [nff] particles entering through each far-field face
+    long long *injoff;      // [nff+1]
     int32_t *cnt;           // [2nc] movers (or collided) per bucket
     int32_t *off;           // [2nc+1]
     int32_t *cursor;        // [2nc]

@@ -390,17 +390,21 @@ __global__ void k_bucket_total(Dev D) {
     }
 }
 
-// capacity check of the step: old + new must fit
+// capacity check of the step: old + sampled + entering must fit
 __global__ void k_sample_setup(Dev D) {
     Scalars *s = D.sc;
-    long long nn = D.samoff[D.nc];
-    if (s->n_old + nn > D.cap) {
+    const long long nn = D.samoff[D.nc];
+    const long long ni = D.nff > 0 ? D.injoff[D.nff] : 0;
+    if (s->n_old + nn + ni > D.cap) {
         atomicOr(&s->err, kErrCapacity);
         s->n_new = 0;
+        s->n_inj = 0;
     } else {
         s->n_new = nn;
+        s->n_inj = ni;
     }
     s->n_sampled = (unsigned long long)s->n_new;
+    s->n_injected = (unsigned long long)s->n_inj;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -588,6 +592,134 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
 }
 
 // ---------------------------------------------------------------------------------------
+// S5 (far field): free-stream particles entering through far-field faces.  Outside the
+// domain the gas is the free stream W_inf; the part of it that reaches a face without a
+// collision in the step, exp(-dt/tau_inf) of its density, crosses the face with the
+// one-sided number flux Gamma = sigma (phi(a) + a Phi(a)) (a = U_inf.n_in / sigma, sigma =
+// sqrt(T_inf)).  Face of area A on cell Omega: mass exp(-dt/tau_inf) rho_inf Gamma A dt in
+// N = ceil(Gamma A dt N_ref / Omega) equal particles, none below a ratio of 1e-9.  Particle
+// k: normal speed from the flux-weighted half-Maxwellian, tangential components Gaussian
+// about U_inf in the face frame, entry point uniform on the face, entry time uniform in
+// the step (drawn again by the transport, which starts it on that face).  Computed in FP64
+// in both forms; the FP32 form rounds what it stores.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double npdf(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * kPi); }
+__device__ __forceinline__ double ncdf(double t) { return 0.5 * erfc(-t / sqrt(2.0)); }
+
+// z = v_n / sigma has density z phi(z - a) / Z(a) on z > 0, Z(a) = phi(a) + a Phi(a), and
+// distribution G(z) = (phi(a) - phi(z - a) + a (Phi(z - a) - Phi(-a))) / Z(a); G(z) = eta by
+// 60 bisections of [0, max(a, 0) + 40] (the interval ends below 4e-17 wide)
+__device__ double flux_speed(double a, double eta) {
+    const double pa = npdf(a), Z = pa + a * ncdf(a), cm = ncdf(-a);
+    double lo = 0.0, hi = (a > 0.0 ? a : 0.0) + 40.0;
+    for (int it = 0; it < 60; ++it) {
+        const double z = 0.5 * (lo + hi);
+        const double G = (pa - npdf(z - a) + a * (ncdf(z - a) - cm)) / Z;
+        if (G < eta)
+            lo = z;
+        else
+            hi = z;
+    }
+    return 0.5 * (lo + hi);
+}
+
+struct Inflow {
+    int c, lf, bf, tri;
+    long long N;
+    double m, sig, a, vt1, vt2;
+    double nin[3], t1[3], t2[3];
+};
+
+__device__ Inflow inflow_face(const Dev &D, int j, double dt) {
+    Inflow q;
+    const int4 fi = D.ffi[j];
+    q.c = fi.x;
+    q.lf = fi.y & 0xFF;
+    q.tri = fi.y >> 8;
+    q.bf = fi.z;
+    const DevBC &b = D.bc[fi.w];
+    const double rho = b.Winf[0];
+    const double Ui[3] = {b.Winf[1] / rho, b.Winf[2] / rho, b.Winf[3] / rho};
+    const double T =
+        (2.0 / 3.0) * (b.Winf[4] - 0.5 * (b.Winf[1] * b.Winf[1] + b.Winf[2] * b.Winf[2] + b.Winf[3] * b.Winf[3]) / rho) /
+        rho;
+    const double tau = D.mu_ref * pow(T, D.omega) / (rho * T);
+    const double e = exp(-dt / tau);
+    const double4 pl = D.plane[q.c * 6 + q.lf];  // outward: the particle enters along -n
+    q.nin[0] = -pl.x;
+    q.nin[1] = -pl.y;
+    q.nin[2] = -pl.z;
+    face_frame<double>(q.nin, q.t1, q.t2);
+    q.sig = sqrt(T);
+    const double sd = Ui[0] * q.nin[0] + Ui[1] * q.nin[1] + Ui[2] * q.nin[2];
+    q.a = sd / q.sig;
+    const double Gam = q.sig * (npdf(q.a) + q.a * ncdf(q.a));
+    const double area = D.ffg[10 * j + 9];
+    const double r = Gam * area * dt * (double)D.n_ref / D.vol[q.c];
+    q.N = 0;
+    q.m = 0.0;
+    if (e * rho > 0.0 && r >= 1e-9) {
+        const double cr = ceil(r);
+        q.N = cr <= 1048576.0 ? (long long)cr : -1;
+        if (q.N > 0) q.m = (e * rho * Gam * area * dt) / (double)q.N;
+    }
+    q.vt1 = Ui[0] * q.t1[0] + Ui[1] * q.t1[1] + Ui[2] * q.t1[2];
+    q.vt2 = Ui[0] * q.t2[0] + Ui[1] * q.t2[1] + Ui[2] * q.t2[2];
+    return q;
+}
+
+__global__ void __launch_bounds__(256) k_inject_count(Dev D) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= D.nff) return;
+    const Inflow q = inflow_face(D, j, D.sc->dt);
+    long long n = q.N;
+    if (n < 0) {
+        atomicOr(&D.sc->err, kErrCellCount);
+        n = 0;
+    }
+    D.ninj[j] = n;
+}
+
+// one wave per far-field face, lanes over its particles; they follow the sampled ones
+template <typename R>
+__global__ void __launch_bounds__(64) k_inject(Dev D, int buf) {
+    const int j = blockIdx.x;
+    const Scalars *sc = D.sc;
+    if (sc->n_inj == 0) return;
+    const long long n = D.ninj[j];
+    if (n <= 0) return;
+    const Inflow q = inflow_face(D, j, sc->dt);
+    const long long base = sc->n_old + sc->n_new + D.injoff[j];
+    const long long step = sc->step;
+    const Particles pa = D.pa[buf];
+    const double *g = D.ffg + 10 * j;
+    const double two_pi = 2.0 * kPi;
+    for (long long k = lane_id(); k < n; k += kWave) {
+        const uint64_t uid = (1ULL << 63) | make_uid(step, q.bf, k);
+        const U4 rv = draw(D.seed, uid, step, kTagInject, 0);
+        const U4 rp = draw(D.seed, uid, step, kTagPos, 0);
+        const double vn = q.sig * flux_speed(q.a, unif<double>(rv.v[0]));
+        const double rr = sqrt(-2.0 * log(unif<double>(rv.v[1])));
+        const double ang = two_pi * unif<double>(rv.v[2]);
+        const double X1 = rr * cos(ang), X2 = rr * sin(ang);
+        const double w1 = q.vt1 + q.sig * X1, w2 = q.vt2 + q.sig * X2;
+        double p1 = unif<double>(rp.v[0]), p2 = unif<double>(rp.v[1]);
+        if (q.tri && p1 + p2 > 1.0) {
+            p1 = 1.0 - p1;
+            p2 = 1.0 - p2;
+        }
+        R x[3], u[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            u[d] = (R)(vn * q.nin[d] + w1 * q.t1[d] + w2 * q.t2[d]);
+            x[d] = (R)(g[d] + p1 * g[3 + d] + p2 * g[6 + d]);
+        }
+        store_new(pa, base + k, x, u, (R)q.m, uid);
+        pa.cell[base + k] = q.c;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // S4 + S5: face-to-face transport of one particle for time ts (Sec. 2.3).
 // Exit time over the faces with n.u > 0 other than the entry face, clamped at 0, lowest local
 // face on a tie; an exit time >= the remaining time keeps the particle in the cell.
@@ -639,12 +771,12 @@ __device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, con
 }
 
 template <typename R>
-__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, uint64_t uid, long long step, int &ncross,
-                     int &nwall) {
+__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, uint64_t uid, long long step,
+                     int &ncross, int &nwall) {
     // margin of the exact division skip below: well above the rounding of the products
     const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
     int c = cell;
-    int entry = -1;
+    int entry = entry0;
     R trem = ts;
     int bounce = 0;
     ncross = 0;
@@ -816,7 +948,8 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     __shared__ unsigned long long red[2][4];
     const Scalars *sc = D.sc;
     const long long n_old = sc->n_old;
-    const long long n_tot = n_old + sc->n_new;
+    const long long n_smp = n_old + sc->n_new;
+    const long long n_tot = n_smp + sc->n_inj;
     const long long i0 = (long long)blockIdx.x * blockDim.x;
     if (i0 >= n_tot) return;
     const long long i = i0 + threadIdx.x;
@@ -828,7 +961,7 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     bool lost = false;
     if (i < n_tot) {
         int c = pa.cell[i];
-        const int c0 = c;
+        int c0 = c;
         R x[3], u[3];
         uint64_t uid;
         typename StateOf<R>::T keep;
@@ -836,8 +969,16 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
         // start-cell data, loaded before the generator runs
         const R e = (R)D.ec[c], tauc = (R)D.tau[c];
         R ts = dt;
+        int entry0 = -1;
         bool collided = false;
-        if (i < n_old) {
+        if (i >= n_smp) {
+            // entering through a far-field face: from its entry time to the end of the step,
+            // starting on that face; never a stayer (it did not start in a cell)
+            const U4 r = draw(D.seed, uid, step, kTagInject, 0);
+            ts = (R)(unif<double>(r.v[3]) * sc->dt);
+            entry0 = D.bflf[(uid >> 20) & 0xFFFFFFULL];
+            c0 = -1;
+        } else if (i < n_old) {
             const U4 r = draw(D.seed, uid, step, kTagTF, 0);
             const R eta = unif<R>(r.v[0]);
             if (!(eta < e * lmargin)) {
@@ -849,7 +990,7 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
             }
         }
         int nx = 0, nw = 0;
-        const int rc = track<R>(D, x, u, c, ts, uid, step, nx, nw);
+        const int rc = track<R>(D, x, u, c, ts, entry0, uid, step, nx, nw);
         nx_ = (unsigned long long)nx;
         nw_ = (unsigned long long)nw;
         store_state(pa, i, x, u, keep);
@@ -885,7 +1026,7 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
 // the bucket (the order of those slots is fixed later by sorting in the gather)
 __global__ void __launch_bounds__(256) k_count(Dev D) {
     const Scalars *sc = D.sc;
-    const long long n_tot = sc->n_old + sc->n_new;
+    const long long n_tot = sc->n_old + sc->n_new + sc->n_inj;
     const long long i0 = (long long)blockIdx.x * blockDim.x;
     if (i0 >= n_tot) return;
     const long long i = i0 + threadIdx.x;
@@ -900,7 +1041,7 @@ __global__ void __launch_bounds__(256) k_count(Dev D) {
 // perm[off[key] + rank] = i, rank handed out in k_stream (cnt holds their number per bucket)
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
     const Scalars *sc = D.sc;
-    const long long n_tot = sc->n_old + sc->n_new;
+    const long long n_tot = sc->n_old + sc->n_new + sc->n_inj;
     const long long i0 = (long long)blockIdx.x * blockDim.x;
     if (i0 >= n_tot) return;
     const long long i = i0 + threadIdx.x;
@@ -1126,7 +1267,7 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
 __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
     __shared__ unsigned long long red[2][64];
     Scalars *s = D.sc;
-    const long long n_tot = s->n_old + s->n_new;
+    const long long n_tot = s->n_old + s->n_new + s->n_inj;
     if (threadIdx.x < 64) {
         red[0][threadIdx.x] = D.spart[threadIdx.x];
         red[1][threadIdx.x] = D.spart[64 + threadIdx.x];
@@ -1151,6 +1292,7 @@ __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
         s->n_old = alive;
         D.segoff[buf ^ 1][D.nc] = (int32_t)alive;
         s->n_new = 0;
+        s->n_inj = 0;
         s->t = s->t + s->dt;
         s->step = s->step + 1;
         s->dtmin_bits = 0x7FF0000000000000ULL;
@@ -1301,6 +1443,10 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     pr->end(kSlotCellPrep);
     pr->begin(kSlotScan);
     scan<long long>(D.nsam, nc, D.samoff, D.scan64, s);
+    if (D.nff > 0) {
+        k_inject_count<<<(unsigned)((D.nff + 255) / 256), 256, 0, s>>>(D);
+        scan<long long>(D.ninj, D.nff, D.injoff, D.scan64, s);
+    }
     k_sample_setup<<<1, 1, 0, s>>>(D);
     k_fill<unsigned long long><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt64, 2LL * nc, 0ULL);
     k_fill<unsigned long long><<<1, 128, 0, s>>>(D.spart, 128, 0ULL);
@@ -1319,6 +1465,12 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
         k_sample<float><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
     else
         k_sample<double><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+    if (D.nff > 0) {
+        if (f32)
+            k_inject<float><<<(unsigned)D.nff, 64, 0, s>>>(D, buf);
+        else
+            k_inject<double><<<(unsigned)D.nff, 64, 0, s>>>(D, buf);
+    }
     pr->end(kSlotSample);
     pr->begin(kSlotStream);
     const unsigned pb = (unsigned)stream_blocks(D.cap);

@@ -192,7 +192,11 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     }
 
     // boundary faces by sorted node key
-    std::unordered_map<Key, int32_t, KeyHash> bmap;
+    struct BFace {
+        int32_t bc;
+        int64_t b;
+    };
+    std::unordered_map<Key, BFace, KeyHash> bmap;
     bmap.reserve((size_t)m.n_bfaces * 2 + 1);
     for (int64_t b = 0; b < m.n_bfaces; ++b) {
         const int64_t *bn = m.bface_nodes + 4 * b;
@@ -201,7 +205,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
             err = "mesh: boundary face " + std::to_string(b) + " has no valid tag";
             return UGKWP_E_MESH;
         }
-        if (!bmap.emplace(make_key(bn, nn), m.bface_bc[b]).second) {
+        if (!bmap.emplace(make_key(bn, nn), BFace{m.bface_bc[b], b}).second) {
             err = "mesh: boundary face listed twice";
             return UGKWP_E_MESH;
         }
@@ -247,6 +251,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
         }
     }
     // what is left open must be a tagged boundary face; visit in cell order for a stable numbering
+    H.bf_lf.assign((size_t)m.n_bfaces, 0);
     std::vector<std::pair<int32_t, int32_t>> rest;
     rest.reserve(open.size());
     for (auto &kv : open) rest.emplace_back(kv.second.cell, kv.second.lf);
@@ -266,11 +271,43 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
         ++matched_b;
         size_t so = (size_t)c * kMaxFaces + lf;
         int32_t f = (int32_t)fown.size();
+        const int32_t bci = it->second.bc;
+        const int64_t b = it->second.b;
         fown.push_back(c);
-        fnb.push_back(-1 - it->second);
+        fnb.push_back(-1 - bci);
         for (int d = 0; d < 3; ++d) fn.push_back(H.plane[4 * so + d]);
         farea.push_back(larea[so]);
-        H.nb[so] = -1 - it->second;
+        H.bf_lf[(size_t)b] = (uint8_t)lf;
+        if (m.bc[bci].type == UGKWP_BC_FARFIELD) {
+            if (b >= (int64_t(1) << 24)) {
+                err = "mesh: far-field faces need an input index below 2^24 (particle ids hold it in 24 bits)";
+                return UGKWP_E_MESH;
+            }
+            // the entry face as listed: corner p0 and the edges to p1 and to p2 (triangle) or p3
+            // (parallelogram p0 p1 p2 p3), area from their cross product
+            const int64_t *bn = m.bface_nodes + 4 * b;
+            const int tri = bn[3] < 0;
+            const double *p0 = m.xyz + 3 * bn[0], *p1 = m.xyz + 3 * bn[1], *pq = m.xyz + 3 * (tri ? bn[2] : bn[3]);
+            double g[10], e1[3], e2[3];
+            for (int d = 0; d < 3; ++d) {
+                g[d] = p0[d];
+                e1[d] = p1[d] - p0[d];
+                e2[d] = pq[d] - p0[d];
+                g[3 + d] = e1[d];
+                g[6 + d] = e2[d];
+            }
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                         cz = e1[0] * e2[1] - e1[1] * e2[0];
+            const double cr = std::sqrt(cx * cx + cy * cy + cz * cz);
+            g[9] = tri ? 0.5 * cr : cr;
+            H.ff_cell.push_back(c);
+            H.ff_lf.push_back(lf);
+            H.ff_bf.push_back((int32_t)b);
+            H.ff_bc.push_back(bci);
+            H.ff_tri.push_back(tri);
+            H.ff_geo.insert(H.ff_geo.end(), g, g + 10);
+        }
+        H.nb[so] = -1 - bci;
         H.nblf[so] = -1;
         H.cface[so] = f + 1;
     }
@@ -278,6 +315,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
         err = "mesh: a boundary face does not belong to any cell";
         return UGKWP_E_MESH;
     }
+    H.nff = (int32_t)H.ff_cell.size();
     H.nf = (int32_t)fown.size();
     H.fown.swap(fown);
     H.fnb.swap(fnb);

@@ -31,6 +31,11 @@ struct HostMesh {
     std::vector<double> fn;      // [nf][3]  unit normal, owner -> neighbour (out of the domain at walls)
     std::vector<double> farea;   // [nf]
     std::vector<ugkwp_bc> bcs;
+    // far-field faces, in (cell, local face) order: where free-stream particles enter
+    int32_t nff = 0;
+    std::vector<int32_t> ff_cell, ff_lf, ff_bf, ff_bc, ff_tri;  // [nff]; ff_bf: input boundary-face index
+    std::vector<double> ff_geo;  // [nff][10]: corner p0, edges p1 - p0 and (p2 or p3) - p0, area
+    std::vector<uint8_t> bf_lf;  // [n_bfaces]: local face of an input boundary face in its cell
 };
 
 // Returns UGKWP_OK or UGKWP_E_ARG / UGKWP_E_MESH with a message in *err.

@@ -48,7 +48,7 @@ class UgkwpStats(C.Structure):
     _fields_ = [("dt", C.c_double), ("t", C.c_double), ("step", C.c_int64), ("n_alive", C.c_int64),
                 ("n_sampled", C.c_int64), ("n_collided", C.c_int64), ("n_escaped", C.c_int64),
                 ("n_moved", C.c_int64), ("crossings", C.c_int64), ("wall_hits", C.c_int64),
-                ("error_word", C.c_uint32), ("moved_total", C.c_int64)]
+                ("error_word", C.c_uint32), ("moved_total", C.c_int64), ("n_injected", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

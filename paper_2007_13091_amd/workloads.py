@@ -285,16 +285,27 @@ def closed_box(n=(4, 3, 2), n_ref=50, kn=0.05, cfl=0.5, seed=7, bc=BC_SPECULAR, 
 
 
 def free_stream_box(n=(4, 3, 3), U=(0.8, 0.3, 0.0), T=1.0, rho=1.0, n_ref=100, kn=0.5, cfl=0.5, seed=11,
-                    tets=False, jitter=0.0) -> Workload:
-    """Box with far-field faces on every side, filled with the free stream it is bathed in."""
-    nc_ = n[0] * n[1] * n[2]
+                    tets=False, jitter=0.0, perturb=0.0, walls=None) -> Workload:
+    """Box of [0,1]x[0,0.75]x[0,0.5] with far-field faces on its sides, filled with the free stream
+    it is bathed in (perturb > 0: a seeded non-uniform initial state instead).  walls: optional
+    dict side name -> BC for sides that are not far field."""
     Winf = conservative(np.array([rho]), np.array([U]), np.array([T]))[0]
     bcs = [BC(BC_FARFIELD, Winf=tuple(float(v) for v in Winf))]
     side = {s_: 0 for s_ in SIDES}
+    for nm, b in (walls or {}).items():
+        side[nm] = len(bcs)
+        bcs.append(b)
     gen = tet_box_mesh if tets else box_hex_mesh
     kw = dict(jitter=jitter, seed=seed) if tets else {}
     mesh = gen(n, (0.0, 0.0, 0.0), (1.0, 0.75, 0.5), side, bcs, **kw)
     nc_ = mesh.n_cells
-    W0 = np.tile(Winf, (nc_, 1))
+    if perturb > 0.0:
+        rng = np.random.default_rng(seed)
+        r = rho * (1.0 + perturb * rng.uniform(-1, 1, nc_))
+        Uc = np.asarray(U, dtype=np.float64)[None, :] * (1.0 + perturb * rng.uniform(-1, 1, (nc_, 3)))
+        Tc = T * (1.0 + perturb * rng.uniform(-1, 1, nc_))
+        W0 = conservative(r, Uc, Tc)
+    else:
+        W0 = np.tile(Winf, (nc_, 1))
     prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
     return Workload("free_stream_box", mesh, prm, W0, 10)

@@ -105,6 +105,35 @@ def test_numerical_dissipation_c2():
     run_pair(w, 10, every=5, name="sod-c2")
 
 
+def test_farfield_box_transitional():
+    # far field on all six sides, non-uniform inside: wave flux against W_inf, particles
+    # leaving are removed and free-stream particles enter
+    w = wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=120, kn=0.05, perturb=0.3)
+    run_pair(w, 8, name="farfield-hex")
+
+
+def test_farfield_box_tets_jittered():
+    w = wl.free_stream_box(n=(4, 3, 3), U=(0.5, 0.4, -0.3), T=1.2, n_ref=80, kn=0.2, perturb=0.2, tets=True,
+                           jitter=0.15)
+    run_pair(w, 6, name="farfield-tet")
+
+
+def test_farfield_free_molecular_inflow_only():
+    # collisionless: everything that enters is a particle; the hydro part comes only from
+    # the free stream
+    w = wl.free_stream_box(n=(4, 3, 2), U=(0.6, 0.0, 0.0), n_ref=150, kn=1e6)
+    run_pair(w, 6, name="farfield-free-molecular")
+
+
+def test_supersonic_inflow_with_diffuse_walls():
+    # Mach 3 stream along x over a diffuse cold wall (z = 0), specular side planes
+    U = 3.0 * np.sqrt(5.0 / 3.0)
+    w = wl.free_stream_box(n=(6, 2, 4), U=(U, 0.0, 0.0), n_ref=60, kn=0.1, perturb=0.1,
+                           walls={"zlo": wl.BC(wl.BC_DIFFUSE, Tw=1.0), "ylo": wl.BC(wl.BC_SPECULAR),
+                                  "yhi": wl.BC(wl.BC_SPECULAR)})
+    run_pair(w, 8, name="supersonic-wall")
+
+
 def test_deterministic_rerun_bitwise():
     w = wl.cavity(n=6, n_ref=300)
     a = _solver(w)
