@@ -21,8 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# algorithmic bytes of one particle move (FP64 state x, u, m, cell, uid read once and written once)
+# algorithmic bytes of one particle move: the particle state read once and written once
+# (FP64: x 24 + u 24 + m 8 + cell 4 + uid 8 = 68 B; FP32 form: 12 + 12 + 4 + 4 + 8 = 40 B)
 BYTES_PER_MOVE_FP64 = 136
+BYTES_PER_MOVE_FP32 = 80
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -48,7 +50,7 @@ def measured_traffic(kernel):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(steps=3):
+def cpu_baseline(steps=12):
     """The oracle as it stands, single-threaded, on the same workload from the same initial
     state: the first `steps` steps (the first samples every particle, the rest are typical)."""
     import oracle
@@ -122,6 +124,20 @@ def stated_fp32_error():
         return None
 
 
+def roofline(prof, moves_per_launch, bytes_per_move, rtype):
+    """Roofline position of the dominant kernel (the slot with the largest summed time): the
+    algorithmic bytes of the particle moves one launch performs over its average duration."""
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_ms = dom_ms / max(dom_n, 1)
+    achieved = bytes_per_move * moves_per_launch / (avg_ms * 1e-3) / 1e9
+    kname = {"stream": f"k_stream<{rtype}>", "gather": f"k_gather<{rtype}>"}.get(dom, dom)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
+            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": int(bytes_per_move * moves_per_launch)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,7 +145,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -146,17 +162,8 @@ def main():
     nc = w.mesh.n_cells
     el, moves, prof = timed_run(w, 0, args.warmup, args.steps)
     value = moves / el
-    # dominant kernel: the slot with the largest summed time
-    dom = max(prof, key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
     moves_per_launch = moves / args.steps
-    achieved = BYTES_PER_MOVE_FP64 * moves_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"stream": "k_stream<double>", "gather": "k_gather<double>"}.get(dom, dom)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": int(BYTES_PER_MOVE_FP64 * moves_per_launch)}
+    roof = roofline(prof, moves_per_launch, BYTES_PER_MOVE_FP64, "double")
     out = {
         "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
         "value": value,
@@ -183,6 +190,7 @@ def main():
                             "ms_per_step": el32 / args.steps * 1e3, "cell_steps_per_s": nc * args.steps / el32,
                             "speedup_vs_fp64_plain": (moves32 / el32) / value,
                             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
+                            "roofline": roofline(prof32, moves32 / args.steps, BYTES_PER_MOVE_FP32, "float"),
                             "stated_error": stated_fp32_error()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
