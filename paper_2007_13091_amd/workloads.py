@@ -309,3 +309,123 @@ def free_stream_box(n=(4, 3, 3), U=(0.8, 0.3, 0.0), T=1.0, rho=1.0, n_ref=100, k
         W0 = np.tile(Winf, (nc_, 1))
     prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
     return Workload("free_stream_box", mesh, prm, W0, 10)
+
+
+# --------------------------------------------------------------------------------------
+# flow past a cube (paper Sec. 4.3)
+# --------------------------------------------------------------------------------------
+def graded_axis(lo, hi, a, b, h0, growth, hmax):
+    """Node coordinates on [lo, hi]: uniform spacing h0 on [a, b] (b - a a multiple of h0),
+    spacing growing geometrically by `growth` up to hmax outside it; each outer run is scaled
+    to end exactly on lo / hi."""
+    n_in = int(round((b - a) / h0))
+    core = np.linspace(a, b, n_in + 1)
+
+    def run(length):
+        if length <= 0:
+            return np.zeros(0)
+        steps, h, tot = [], h0, 0.0
+        while tot < length - 1e-12:
+            h = min(h * growth, hmax)
+            steps.append(h)
+            tot += h
+        st = np.array(steps)
+        if tot - length > 0.5 * st[-1] and len(st) > 1:
+            st = st[:-1]
+        return np.cumsum(st) * (length / st.sum())
+
+    right = b + run(hi - b)
+    left = a - run(a - lo)
+    out = np.concatenate([left[::-1], core, right])
+    out[0], out[-1] = lo, hi
+    return out
+
+
+def cube_mesh(lo=(-4.0, -5.0, -5.0), hi=(8.0, 5.0, 5.0), half=0.5, h0=0.05, growth=1.16, hmax=0.4, jitter=0.15,
+              seed=1, bc_far=0, bc_wall=1, bcs=()) -> Mesh:
+    """Graded box of hexahedra minus the cube [-half, half]^3 (whose faces lie on grid planes),
+    each remaining hexahedron split into 6 Kuhn tetrahedra.  Interior nodes move uniformly within
+    +-jitter h per axis (seeded, h the smaller adjacent spacing); nodes on the cube stay, nodes on
+    the outer box move only within its planes.  Outer faces carry bc_far, cube faces bc_wall."""
+    ax = [graded_axis(lo[d], hi[d], -half, half, h0, growth, hmax) for d in range(3)]
+    n = [len(a) - 1 for a in ax]
+    nx, ny, nz = n
+    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(), Z.transpose(2, 1, 0).ravel()], 1)
+    idx = [np.arange(n[0] + 1), np.arange(n[1] + 1), np.arange(n[2] + 1)]
+    I, J, K = np.meshgrid(*idx, indexing="ij")
+    pos = [I.transpose(2, 1, 0).ravel(), J.transpose(2, 1, 0).ravel(), K.transpose(2, 1, 0).ravel()]
+    # grid index range of the cube per axis
+    cr = [(int(np.argmin(np.abs(ax[d] + half))), int(np.argmin(np.abs(ax[d] - half)))) for d in range(3)]
+    on_cube = np.ones(xyz.shape[0], dtype=bool)
+    for d in range(3):
+        on_cube &= (pos[d] >= cr[d][0]) & (pos[d] <= cr[d][1])
+    if jitter > 0.0:
+        rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x43554245], dtype=np.uint64)))
+        base = xyz.copy()
+        for d in range(3):
+            h = np.diff(ax[d])
+            hloc = np.minimum(np.concatenate([[h[0]], h]), np.concatenate([h, [h[-1]]]))
+            inner = (pos[d] > 0) & (pos[d] < n[d]) & ~on_cube
+            dd = rng.uniform(-jitter, jitter, size=xyz.shape[0]) * hloc[pos[d]]
+            xyz[:, d] = np.where(inner, base[:, d] + dd, base[:, d])
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i = i.transpose(2, 1, 0).ravel(); j = j.transpose(2, 1, 0).ravel(); k = k.transpose(2, 1, 0).ravel()
+    inside = ((i >= cr[0][0]) & (i < cr[0][1]) & (j >= cr[1][0]) & (j < cr[1][1]) & (k >= cr[2][0]) & (k < cr[2][1]))
+    keep = ~inside
+    i, j, k = i[keep], j[keep], k[keep]
+    tets = [np.stack([nid(i + a, j + b, k + c) for (a, b, c) in path], 1) for path in _KUHN]
+    cn = np.stack(tets, 1).reshape(-1, 4).astype(np.int64)
+    nc = cn.shape[0]
+    side = {s_: bc_far for s_ in SIDES}
+    bf, bt = _box_boundary(n, nid, side, tri_split=True)
+    # cube surface: the faces of the removed block, split like the tetrahedra that touch them
+    faces, tags = [], []
+    (i0, i1), (j0, j1), (k0, k1) = cr
+
+    def quad(p, q, r, s_):
+        faces.append((p, q, r, -1)); faces.append((p, r, s_, -1)); tags.extend([bc_wall, bc_wall])
+
+    for jj in range(j0, j1):
+        for kk in range(k0, k1):
+            for ii in (i0, i1):
+                quad(nid(ii, jj, kk), nid(ii, jj + 1, kk), nid(ii, jj + 1, kk + 1), nid(ii, jj, kk + 1))
+    for ii in range(i0, i1):
+        for kk in range(k0, k1):
+            for jj in (j0, j1):
+                quad(nid(ii, jj, kk), nid(ii + 1, jj, kk), nid(ii + 1, jj, kk + 1), nid(ii, jj, kk + 1))
+    for ii in range(i0, i1):
+        for jj in range(j0, j1):
+            for kk in (k0, k1):
+                quad(nid(ii, jj, kk), nid(ii + 1, jj, kk), nid(ii + 1, jj + 1, kk), nid(ii, jj + 1, kk))
+    bf = np.concatenate([bf, np.array(faces, dtype=np.int64).reshape(-1, 4)])
+    bt = np.concatenate([bt, np.array(tags, dtype=np.int32)])
+    return Mesh(xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+                cell_type=np.full(nc, CELL_TET, dtype=np.uint8),
+                cell_node_off=np.arange(0, 4 * nc + 1, 4, dtype=np.int64),
+                cell_nodes=cn.ravel(), bface_nodes=bf, bface_bc=bt, bcs=list(bcs))
+
+
+def cube(mach=10.0, kn=0.1, n_ref=50, cfl=0.9, c2=10.0, Tw=1.0, h0=0.05, growth=1.16, hmax=0.4,
+         lo=(-4.0, -5.0, -5.0), hi=(8.0, 5.0, 5.0), jitter=0.15, seed=1, steps=1200) -> Workload:
+    """Mach 10 flow past a cube (paper Sec. 4.3) at the hot-path size: [-4,8]x[-5,5]^2 minus the
+    unit cube, about 1.2e6 jittered tetrahedra; free stream rho = 1, T = 1, U = (Ma sqrt(5/3), 0, 0);
+    far field on the outer box, diffuse cube walls at T_w; N_ref = N_min; impulsive start."""
+    U = mach * math.sqrt(5.0 / 3.0)
+    Winf = conservative(np.array([1.0]), np.array([[U, 0.0, 0.0]]), np.array([1.0]))[0]
+    bcs = [BC(BC_FARFIELD, Winf=tuple(float(v) for v in Winf)), BC(BC_DIFFUSE, Tw=Tw)]
+    mesh = cube_mesh(lo=lo, hi=hi, h0=h0, growth=growth, hmax=hmax, jitter=jitter, seed=seed, bcs=bcs)
+    W0 = np.tile(Winf, (mesh.n_cells, 1))
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=c2, n_ref=n_ref, n_min=n_ref, seed=seed)
+    return Workload("cube", mesh, prm, W0, steps)
+
+
+def small_cube(**kw) -> Workload:
+    """The cube case on a coarse mesh ([-1.5,2.5]x[-1.5,1.5]^2, h = 0.25 at the cube) for parity runs."""
+    args = dict(h0=0.25, growth=1.5, hmax=0.6, lo=(-1.5, -1.5, -1.5), hi=(2.5, 1.5, 1.5), n_ref=30)
+    args.update(kw)
+    return cube(**args)

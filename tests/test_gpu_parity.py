@@ -134,6 +134,22 @@ def test_supersonic_inflow_with_diffuse_walls():
     run_pair(w, 8, name="supersonic-wall")
 
 
+def test_cube_small_mach10():
+    # the Mach 10 cube case (far-field outer box, diffuse cube, jittered tets, N_min = N_ref,
+    # C2 = 10) on a coarse mesh, over the steps before the wake behind the cube empties
+    w = wl.small_cube(n_ref=50)
+    run_pair(w, 5, name="cube-small", length=4.0, vscale=15.0)
+
+
+@pytest.mark.timeout(600)
+def test_cube_full_size_first_steps():
+    # the full 1.2e6-tetrahedron cube with 6e7 particles, in the launch configuration of the
+    # timed runs: every field, count and particle against the oracle over the first two steps
+    w = wl.cube()
+    _say("cube full size", w.mesh.n_cells, "cells")
+    run_pair(w, 2, name="cube-full", length=12.0, vscale=15.0)
+
+
 def test_deterministic_rerun_bitwise():
     w = wl.cavity(n=6, n_ref=300)
     a = _solver(w)
