@@ -22,6 +22,15 @@
  * until ugkwp_destroy.  ugkwp_init_mesh carves it; no other call allocates device memory.
  * Every device operation is ordered on the hip stream given to ugkwp_init_mesh.
  *
+ * Batches.  ugkwp_init_mesh takes n_inst independent instances (each its own mesh and
+ * parameters).  They run together: every kernel of a step covers all instances in one
+ * launch, and one ugkwp_step advances each instance by one of its own time steps (each has
+ * its own dt from its own CFL condition, its own clock and step counter).  Instance k draws
+ * its random numbers with k in the last Philox counter word and numbers its particles by
+ * its own cell indices, so it evolves exactly as it would alone with instance index k.
+ * Cell-indexed host arrays (W0, moments, geometry, particle cells) concatenate the
+ * instances' cells in instance order.
+ *
  * Errors.  Every function returns a ugkwp_status and never aborts.  Host-detectable errors
  * return at once.  Errors found on the device (capacity, lost particle, non-physical
  * state) are recorded in a device error word and reported by the next call that
@@ -101,6 +110,8 @@ typedef struct {
     uint64_t seed;        /* Philox4x64-10 key word 0 */
 } ugkwp_params;
 
+/* Statistics of a step.  For a batch, ugkwp_step reports the counts summed over the
+ * instances and dt, t, step of instance 0. */
 typedef struct {
     double dt, t;          /* time step just taken, time after it */
     int64_t step;          /* steps taken since ugkwp_init_state */
@@ -119,23 +130,32 @@ typedef struct {
                               ceil(Gamma A dt n_ref / Omega) equal particles */
 } ugkwp_step_stats;
 
-/* Device bytes needed for one mesh with these parameters.  Host-side only (no device call). */
-int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, const ugkwp_params *p, size_t *bytes);
+/* Device bytes needed for n_inst >= 1 instances: m[n_inst], p[n_inst].  Host-side only (no
+ * device call).  All instances must share precision; the capacity is the sum of theirs. */
+int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p, size_t *bytes);
 
 /* Validate the mesh, match faces, compute the geometry (Sec. 2.2 cells, faces, normals,
  * areas, the projections Delta S of Sec. 2.4(a)), carve the workspace and upload.
  * dev_workspace: device pointer of at least ugkwp_workspace_bytes bytes, 256-byte aligned.
  * hip_stream: a hipStream_t (NULL = the default stream).  On success *ctx owns host-side
  * bookkeeping only; free it with ugkwp_destroy. */
-int32_t ugkwp_init_mesh(ugkwp_ctx **ctx, const ugkwp_mesh *m, const ugkwp_params *p,
+int32_t ugkwp_init_mesh(ugkwp_ctx **ctx, const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p,
                         void *dev_workspace, size_t ws_bytes, void *hip_stream);
 
-/* Set the conservative state W0 (host, [n_cells][5]); no particles (W^p = 0), step = 0, t = 0. */
+/* Set the conservative state W0 (host, [total cells][5]); no particles (W^p = 0), every
+ * instance at step 0, t = 0. */
 int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0);
 
 /* Advance n_steps time steps.  stats == NULL: asynchronous (nothing waits for the device).
  * stats != NULL: waits for the stream and fills the statistics of the last step. */
 int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats);
+
+/* Statistics of the last step of one instance (synchronises).  crossings and wall_hits are
+ * counted for the batch as a whole and read -1 here when n_inst > 1. */
+int32_t ugkwp_instance_stats(ugkwp_ctx *ctx, int32_t inst, ugkwp_step_stats *stats);
+
+/* Cells [cell0, cell1) of instance inst in the concatenated cell numbering. */
+int32_t ugkwp_instance_cells(const ugkwp_ctx *ctx, int32_t inst, int64_t *cell0, int64_t *cell1);
 
 /* Copy a cell field out, [n_cells][5] doubles: which = 0 W, 1 W^p = P/Omega (particle part),
  * 2 W^h = W - W^p, 3 primitives (rho, U, V, W, T).  out is host memory unless

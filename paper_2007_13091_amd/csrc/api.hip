@@ -84,7 +84,9 @@ const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep", "scan_sample
 struct ugkwp_ctx {
     EventProf prof;
     HostMesh H;
-    ugkwp_params p{};
+    ugkwp_params p{};                          // instance 0 (shared settings: precision)
+    std::vector<ugkwp_params> ps;              // per instance
+    std::vector<ugkwp::InstRange> ranges;      // per instance
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -113,8 +115,11 @@ struct Carver {
 };
 
 // Lay the workspace out; with base == nullptr only the size is computed.
-size_t carve(const HostMesh &H, long long cap, int prec, Dev &D, char *base) {
+size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, Dev &D, char *base) {
     Carver C{base};
+    D.ip = C.take<ugkwp::InstP>((size_t)n_inst);
+    D.is = C.take<ugkwp::InstS>((size_t)n_inst);
+    D.cinst = n_inst > 1 ? C.take<int32_t>((size_t)H.nc) : nullptr;
     const size_t nc = (size_t)H.nc, nf = (size_t)H.nf, nbc = H.bcs.size() ? H.bcs.size() : 1;
     D.vol = C.take<double>(nc);
     D.dS = C.take<double>(3 * nc);
@@ -208,6 +213,41 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
     return UGKWP_OK;
 }
 
+// Validate and prepare every instance, concatenate them, and total the capacity.
+int32_t prepare_batch(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p, HostMesh &H,
+                      std::vector<ugkwp::InstRange> &ranges, long long &cap, std::string &err) {
+    if (n_inst < 1 || n_inst > 65536) {
+        err = "batch: need 1 <= n_inst <= 65536";
+        return UGKWP_E_ARG;
+    }
+    std::vector<HostMesh> parts((size_t)n_inst);
+    cap = 0;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        int32_t st = ugkwp::prepare_mesh(m[k], parts[k], err);
+        long long ck = 0;
+        if (st == UGKWP_OK) st = check_params(p[k], parts[k].nc, ck, err);
+        if (st == UGKWP_OK && p[k].precision != p[0].precision) {
+            err = "params: every instance of a batch must use the same precision";
+            st = UGKWP_E_ARG;
+        }
+        if (st != UGKWP_OK) {
+            if (n_inst > 1) err = "instance " + std::to_string(k) + ": " + err;
+            return st;
+        }
+        cap += ck;
+    }
+    if (cap > 2147483647LL - 1024) {
+        err = "batch: total capacity must fit in a 32-bit particle index";
+        return UGKWP_E_ARG;
+    }
+    if (n_inst == 1) {
+        H = std::move(parts[0]);
+        ranges.assign(1, ugkwp::InstRange{0, H.nc, 0, H.nff, 0});
+        return UGKWP_OK;
+    }
+    return ugkwp::concat_meshes(parts, H, ranges, err);
+}
+
 int32_t fail(ugkwp_ctx *ctx, int32_t code, const std::string &msg) {
     if (ctx)
         ctx->err = msg;
@@ -266,41 +306,40 @@ int32_t read_scalars(ugkwp_ctx *ctx, Scalars &s) {
 
 extern "C" {
 
-int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, const ugkwp_params *p, size_t *bytes) {
+int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p, size_t *bytes) {
     if (!m || !p || !bytes) return fail(nullptr, UGKWP_E_ARG, "null argument");
     HostMesh H;
+    std::vector<ugkwp::InstRange> ranges;
     std::string err;
-    int32_t st = ugkwp::prepare_mesh(*m, H, err);
-    if (st != UGKWP_OK) return fail(nullptr, st, err);
     long long cap = 0;
-    st = check_params(*p, H.nc, cap, err);
+    int32_t st = prepare_batch(m, n_inst, p, H, ranges, cap, err);
     if (st != UGKWP_OK) return fail(nullptr, st, err);
     Dev D{};
-    *bytes = carve(H, cap, p->precision, D, nullptr);
+    *bytes = carve(H, n_inst, cap, p[0].precision, D, nullptr);
     return UGKWP_OK;
 }
 
-int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params *p, void *dev_workspace,
-                        size_t ws_bytes, void *hip_stream) {
+int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p,
+                        void *dev_workspace, size_t ws_bytes, void *hip_stream) {
     if (!out || !m || !p || !dev_workspace) return fail(nullptr, UGKWP_E_ARG, "null argument");
     *out = nullptr;
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(nullptr, UGKWP_E_ARG, "workspace must be 256-byte aligned");
     ugkwp_ctx *ctx = new ugkwp_ctx();
     std::string err;
-    int32_t st = ugkwp::prepare_mesh(*m, ctx->H, err);
     long long cap = 0;
-    if (st == UGKWP_OK) st = check_params(*p, ctx->H.nc, cap, err);
+    int32_t st = prepare_batch(m, n_inst, p, ctx->H, ctx->ranges, cap, err);
     if (st != UGKWP_OK) {
         delete ctx;
         return fail(nullptr, st, err);
     }
-    ctx->p = *p;
+    ctx->p = p[0];
+    ctx->ps.assign(p, p + n_inst);
     ctx->stream = (hipStream_t)hip_stream;
     ctx->prof.s = ctx->stream;
     ctx->ws = (char *)dev_workspace;
     ctx->ws_bytes = ws_bytes;
     Dev &D = ctx->D;
-    size_t need = carve(ctx->H, cap, p->precision, D, ctx->ws);
+    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, D, ctx->ws);
     if (ws_bytes < need) {
         delete ctx;
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -310,16 +349,31 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     D.nf = H.nf;
     D.nbc = (int32_t)H.bcs.size();
     D.nff = H.nff;
-    D.mu_ref = p->mu_ref;
-    D.omega = p->omega;
-    D.cfl = p->cfl;
-    D.c2 = p->c2;
-    D.n_ref = p->n_ref;
-    D.n_min = p->n_min;
-    D.max_cross = p->max_crossings;
-    D.seed = p->seed;
+    D.n_inst = n_inst;
     D.cap = cap;
-    D.prec = p->precision;
+    D.prec = p[0].precision;
+    std::vector<ugkwp::InstP> ip((size_t)n_inst);
+    std::vector<int32_t> cinst;
+    if (n_inst > 1) cinst.resize((size_t)H.nc);
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const ugkwp::InstRange &r = ctx->ranges[k];
+        ugkwp::InstP &q = ip[k];
+        std::memset(&q, 0, sizeof(q));
+        q.mu_ref = p[k].mu_ref;
+        q.omega = p[k].omega;
+        q.cfl = p[k].cfl;
+        q.c2 = p[k].c2;
+        q.n_ref = p[k].n_ref;
+        q.n_min = p[k].n_min;
+        q.max_cross = p[k].max_crossings;
+        q.seed = p[k].seed;
+        q.cell0 = r.cell0;
+        q.cell1 = r.cell1;
+        q.ff0 = r.ff0;
+        q.ff1 = r.ff1;
+        q.bf0 = r.bf0;
+        for (int32_t c = r.cell0; c < r.cell1 && n_inst > 1; ++c) cinst[c] = k;
+    }
     // one wave per cell: blocks of 64 threads need no cross-wave barriers
     ctx->gather_bs = 64;
 
@@ -368,6 +422,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, const ugkwp_params
     e = e ? e : up((int4 *)D.ffi, ffi, s);
     e = e ? e : up((double *)D.ffg, H.ff_geo, s);
     e = e ? e : up((uint8_t *)D.bflf, H.bf_lf, s);
+    e = e ? e : up((ugkwp::InstP *)D.ip, ip, s);
+    if (n_inst > 1) e = e ? e : up((int32_t *)D.cinst, cinst, s);
     e = e ? e : hipStreamSynchronize(s);
     if (e != hipSuccess) return cleanup_fail(std::string("upload: ") + hipGetErrorString(e));
     *out = ctx;
@@ -399,6 +455,10 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     ugkwp::launch_fill_i32(D.segoff[1], (long long)nc + 1, 0, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
+    std::vector<ugkwp::InstS> is((size_t)D.n_inst);
+    std::memset(is.data(), 0, is.size() * sizeof(ugkwp::InstS));
+    for (auto &v : is) v.dtmin_bits = 0x7FF0000000000000ULL;
+    HIPCHK(ctx, up(D.is, is, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     ctx->buf = 0;
     ctx->have_state = true;
@@ -436,6 +496,38 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
         stats->n_moved = s.n_alive + (int64_t)s.n_collided + (int64_t)s.n_escaped;
         if (st != UGKWP_OK) return st;
     }
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_instance_stats(ugkwp_ctx *ctx, int32_t inst, ugkwp_step_stats *stats) {
+    if (!ctx || !stats || inst < 0 || inst >= ctx->D.n_inst) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "no state");
+    Scalars s;
+    int32_t st = read_scalars(ctx, s);
+    ugkwp::InstS I;
+    HIPCHK(ctx, hipMemcpy(&I, ctx->D.is + inst, sizeof(I), hipMemcpyDeviceToHost));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->dt = I.dt;
+    stats->t = I.t;
+    stats->step = I.step;
+    stats->n_alive = I.n_alive;
+    stats->n_sampled = I.n_sampled;
+    stats->n_injected = I.n_injected;
+    stats->n_collided = I.n_collided;
+    stats->n_escaped = I.n_escaped;
+    stats->n_moved = I.n_alive + I.n_collided + I.n_escaped;
+    stats->moved_total = I.moved_total;
+    stats->crossings = ctx->D.n_inst > 1 ? -1 : (int64_t)s.n_cross;
+    stats->wall_hits = ctx->D.n_inst > 1 ? -1 : (int64_t)s.n_wall;
+    stats->error_word = s.err;
+    return st;
+}
+
+int32_t ugkwp_instance_cells(const ugkwp_ctx *ctx, int32_t inst, int64_t *cell0, int64_t *cell1) {
+    if (!ctx || !cell0 || !cell1 || inst < 0 || inst >= (int32_t)ctx->ranges.size())
+        return fail(nullptr, UGKWP_E_ARG, "bad argument");
+    *cell0 = ctx->ranges[inst].cell0;
+    *cell1 = ctx->ranges[inst].cell1;
     return UGKWP_OK;
 }
 

@@ -27,7 +27,29 @@ struct DevBC {
     double Winf[5];
 };
 
-// Step scalars, resident in device memory: the host never reads them inside a step.
+// Parameters of one instance of a batch (constant after set-up).  An instance owns a
+// contiguous range of cells and of far-field faces of the concatenated mesh.
+struct InstP {
+    double mu_ref, omega, cfl, c2;
+    int32_t n_ref, n_min, max_cross, pad;
+    unsigned long long seed;
+    int32_t cell0, cell1;  // cells [cell0, cell1)
+    int32_t ff0, ff1;      // far-field faces [ff0, ff1)
+    long long bf0;         // its first input boundary face in the concatenated list
+};
+
+// Step state of one instance: its own time step, time and step counter, and the counts of
+// its last step.
+struct InstS {
+    unsigned long long dtmin_bits;  // bit pattern of min Omega/Lambda over its cells
+    double dt, t;
+    long long step;
+    long long n_alive, n_sampled, n_injected, n_collided, n_escaped;
+    long long moved_total;
+};
+
+// Step scalars of the whole batch, resident in device memory: the host never reads them
+// inside a step.  dt, t and step mirror instance 0.
 struct Scalars {
     unsigned long long dtmin_bits;  // bit pattern of min Omega/Lambda (positive doubles order as integers)
     double dt;
@@ -92,9 +114,10 @@ struct Dev {
     const double *ffg;      // [nff][10]  corner, two edges, area of the face as listed
     const uint8_t *bflf;    // [n_bfaces]  local face of an input boundary face
     // parameters
-    double mu_ref, omega, cfl, c2;
-    int32_t n_ref, n_min, max_cross, prec;  // prec: 0 FP64 plain, 1 FP32 form
-    unsigned long long seed;
+    int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
+    const InstP *ip;        // [n_inst]
+    InstS *is;              // [n_inst]
+    const int32_t *cinst;   // [nc] instance of each cell (n_inst > 1 only)
     long long cap;
     // state
     double *W;              // [5][nc]

@@ -73,9 +73,20 @@ __device__ __forceinline__ U4 philox(uint64_t c0, uint64_t c1, uint64_t c2, uint
     return o;
 }
 
-__device__ __forceinline__ U4 draw(uint64_t seed, uint64_t uid, long long step, int tag, uint32_t sub) {
-    return philox(uid, (uint64_t)step, ((uint64_t)tag << 32) | sub, 0ULL, seed, 0ULL);
+// counter (particle id, step, tag << 32 | sub, instance), key (seed, 0)
+__device__ __forceinline__ U4 draw(uint64_t seed, uint64_t uid, long long step, int tag, uint32_t sub, int inst) {
+    return philox(uid, (uint64_t)step, ((uint64_t)tag << 32) | sub, (uint64_t)inst, seed, 0ULL);
 }
+
+// instance of a cell (a single instance needs no table)
+__device__ __forceinline__ int inst_of(const Dev &D, int c) { return D.n_inst > 1 ? D.cinst[c] : 0; }
+
+// what the transport of one particle needs from its instance
+struct StepCtx {
+    unsigned long long seed;
+    long long step;
+    int inst, max_cross;
+};
 
 // uniform in (0, 1), never 0 or 1: FP64 (top 52 bits + 1/2) * 2^-52; FP32 (top 23 bits + 1/2)
 // * 2^-23, the leading bits of the same draw
@@ -306,8 +317,11 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
         s->n_sampled = 0;
     }
     double r = INFINITY;
+    int inst = 0;
     if (c < D.nc) {
         const int nc = D.nc;
+        inst = inst_of(D, c);
+        const InstP &P = D.ip[inst];
         double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
         bool bad = !(rho > 0.0) || !isfinite(rho);
         double T = 0.0;
@@ -323,11 +337,19 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
             atomicOr(&D.sc->err, kErrNonPhys);
             D.tau[c] = 1.0;
         } else {
-            D.tau[c] = D.mu_ref * pow(T, D.omega) / (rho * T);
+            D.tau[c] = P.mu_ref * pow(T, P.omega) / (rho * T);
             double cs = 3.0 * sqrt(T);
             double lam = (fabs(U) + cs) * D.dS[c] + (fabs(V) + cs) * D.dS[nc + c] + (fabs(Z) + cs) * D.dS[2 * nc + c];
             r = D.vol[c] / lam;
         }
+    }
+    // the min over each instance's cells; a block whose cells straddle two instances
+    // reports per cell (positive doubles order as their bit patterns)
+    const int cfirst = blockIdx.x * blockDim.x;
+    const int clast = min(cfirst + (int)blockDim.x, D.nc) - 1;
+    if (D.n_inst > 1 && D.cinst[cfirst] != D.cinst[clast]) {
+        if (r < INFINITY && r > 0.0) atomicMin(&D.is[inst].dtmin_bits, (unsigned long long)__double_as_longlong(r));
+        return;
     }
     smin[threadIdx.x] = r;
     __syncthreads();
@@ -336,17 +358,22 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
         __syncthreads();
     }
     if (threadIdx.x == 0 && smin[0] < INFINITY && smin[0] > 0.0)
-        atomicMin(&D.sc->dtmin_bits, (unsigned long long)__double_as_longlong(smin[0]));
+        atomicMin(&D.is[inst_of(D, cfirst)].dtmin_bits, (unsigned long long)__double_as_longlong(smin[0]));
 }
 
 // ---------------------------------------------------------------------------------------
 // S0 (cont.): dt, collisionless fraction, hydro density, number of particles to sample
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
-    const double dt = D.cfl * __longlong_as_double((long long)D.sc->dtmin_bits);
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c == 0) D.sc->dt = dt;
     if (c >= D.nc) return;
+    const int inst = inst_of(D, c);
+    const InstP &P = D.ip[inst];
+    const double dt = P.cfl * __longlong_as_double((long long)D.is[inst].dtmin_bits);
+    if (c == P.cell0) {
+        D.is[inst].dt = dt;
+        if (inst == 0) D.sc->dt = dt;
+    }
     const double vol = D.vol[c];
     const double rhop = D.P[c] / vol;
     // the hydro density is a difference of sums; below 1e-12 rho it is roundoff of that
@@ -360,13 +387,13 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
     const double rhohp = e * rhoh;
     long long ns = 0;
     if (rhohp > 0.0 && rhop + rhohp > 0.0) {
-        double r = (0.5 * D.n_ref) * (rhohp / (rhop + rhohp));
+        double r = (0.5 * P.n_ref) * (rhohp / (rhop + rhohp));
         double cr = ceil(r);
         if (!(cr <= 524288.0)) {
             atomicOr(&D.sc->err, kErrCellCount);
         } else {
             ns = 2 * (long long)cr;
-            long long need = (long long)D.n_min - D.nleft[c];
+            long long need = (long long)P.n_min - D.nleft[c];
             if (need > 0) {
                 long long ne = 2 * ((need + 1) / 2);
                 if (ne > ns) ns = ne;
@@ -416,9 +443,11 @@ __global__ void __launch_bounds__(128) k_flux(Dev D) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= D.nf) return;
     const int nc = D.nc, nf = D.nf;
-    const R dt = (R)D.sc->dt;
-    const R mu = (R)D.mu_ref, om = (R)D.omega, c2 = (R)D.c2;
     const int c = D.fown[f];
+    const int inst = inst_of(D, c);
+    const InstP &P = D.ip[inst];
+    const R dt = (R)D.is[inst].dt;
+    const R mu = (R)P.mu_ref, om = (R)P.omega, c2 = (R)P.c2;
     const int nb = D.fnb[f];
     R n[3] = {(R)D.fn[f], (R)D.fn[nf + f], (R)D.fn[2 * nf + f]};
     R t1[3], t2[3];
@@ -533,7 +562,11 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
     if (ns > 0) {
         const Particles pa = D.pa[buf];
         const long long base = sc->n_old + D.samoff[c];
-        const long long step = sc->step;
+        const int inst = inst_of(D, c);
+        const InstP &P = D.ip[inst];
+        const long long step = D.is[inst].step;
+        const unsigned long long seed = P.seed;
+        const int cl = c - P.cell0;  // ids carry the cell index within the instance
         const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
         const R U[3] = {(R)(m0 / rho), (R)(m1 / rho), (R)(m2 / rho)};
         const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
@@ -548,9 +581,9 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
         const R one = (R)1, two_pi = (R)2 * (R)kPi;
         for (long long k = lane; k < ns; k += kWave) {
             const long long i = base + k;
-            const uint64_t uid = make_uid(step, c, k);
-            const uint64_t puid = make_uid(step, c, k & ~1LL);
-            U4 rv = draw(D.seed, puid, step, kTagVel, 0);
+            const uint64_t uid = make_uid(step, cl, k);
+            const uint64_t puid = make_uid(step, cl, k & ~1LL);
+            U4 rv = draw(seed, puid, step, kTagVel, 0, inst);
             R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
             R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
             R X[3] = {r1 * cos(two_pi * e1), r1 * sin(two_pi * e1), r2 * cos(two_pi * e3)};
@@ -558,7 +591,7 @@ __global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
             R u[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
-            U4 rp = draw(D.seed, uid, step, kTagPos, 0);
+            U4 rp = draw(seed, uid, step, kTagPos, 0, inst);
             R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
             if (tet) {
                 if (s + t > one) {
@@ -624,16 +657,21 @@ __device__ double flux_speed(double a, double eta) {
 }
 
 struct Inflow {
-    int c, lf, bf, tri;
+    int c, lf, bf, tri, inst;
+    double dt;
     long long N;
     double m, sig, a, vt1, vt2;
     double nin[3], t1[3], t2[3];
 };
 
-__device__ Inflow inflow_face(const Dev &D, int j, double dt) {
+__device__ Inflow inflow_face(const Dev &D, int j) {
     Inflow q;
     const int4 fi = D.ffi[j];
     q.c = fi.x;
+    q.inst = inst_of(D, q.c);
+    const InstP &P = D.ip[q.inst];
+    const double dt = D.is[q.inst].dt;
+    q.dt = dt;
     q.lf = fi.y & 0xFF;
     q.tri = fi.y >> 8;
     q.bf = fi.z;
@@ -643,7 +681,7 @@ __device__ Inflow inflow_face(const Dev &D, int j, double dt) {
     const double T =
         (2.0 / 3.0) * (b.Winf[4] - 0.5 * (b.Winf[1] * b.Winf[1] + b.Winf[2] * b.Winf[2] + b.Winf[3] * b.Winf[3]) / rho) /
         rho;
-    const double tau = D.mu_ref * pow(T, D.omega) / (rho * T);
+    const double tau = P.mu_ref * pow(T, P.omega) / (rho * T);
     const double e = exp(-dt / tau);
     const double4 pl = D.plane[q.c * 6 + q.lf];  // outward: the particle enters along -n
     q.nin[0] = -pl.x;
@@ -655,7 +693,7 @@ __device__ Inflow inflow_face(const Dev &D, int j, double dt) {
     q.a = sd / q.sig;
     const double Gam = q.sig * (npdf(q.a) + q.a * ncdf(q.a));
     const double area = D.ffg[10 * j + 9];
-    const double r = Gam * area * dt * (double)D.n_ref / D.vol[q.c];
+    const double r = Gam * area * dt * (double)P.n_ref / D.vol[q.c];
     q.N = 0;
     q.m = 0.0;
     if (e * rho > 0.0 && r >= 1e-9) {
@@ -671,7 +709,7 @@ __device__ Inflow inflow_face(const Dev &D, int j, double dt) {
 __global__ void __launch_bounds__(256) k_inject_count(Dev D) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= D.nff) return;
-    const Inflow q = inflow_face(D, j, D.sc->dt);
+    const Inflow q = inflow_face(D, j);
     long long n = q.N;
     if (n < 0) {
         atomicOr(&D.sc->err, kErrCellCount);
@@ -688,16 +726,17 @@ __global__ void __launch_bounds__(64) k_inject(Dev D, int buf) {
     if (sc->n_inj == 0) return;
     const long long n = D.ninj[j];
     if (n <= 0) return;
-    const Inflow q = inflow_face(D, j, sc->dt);
+    const Inflow q = inflow_face(D, j);
     const long long base = sc->n_old + sc->n_new + D.injoff[j];
-    const long long step = sc->step;
+    const long long step = D.is[q.inst].step;
+    const unsigned long long seed = D.ip[q.inst].seed;
     const Particles pa = D.pa[buf];
     const double *g = D.ffg + 10 * j;
     const double two_pi = 2.0 * kPi;
     for (long long k = lane_id(); k < n; k += kWave) {
         const uint64_t uid = (1ULL << 63) | make_uid(step, q.bf, k);
-        const U4 rv = draw(D.seed, uid, step, kTagInject, 0);
-        const U4 rp = draw(D.seed, uid, step, kTagPos, 0);
+        const U4 rv = draw(seed, uid, step, kTagInject, 0, q.inst);
+        const U4 rp = draw(seed, uid, step, kTagPos, 0, q.inst);
         const double vn = q.sig * flux_speed(q.a, unif<double>(rv.v[0]));
         const double rr = sqrt(-2.0 * log(unif<double>(rv.v[1])));
         const double ang = two_pi * unif<double>(rv.v[2]);
@@ -755,9 +794,9 @@ __device__ __forceinline__ void cell_plane(const Dev &D, int s, float p[4]) {
 // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential components
 // N(U_w, T_w) in the face frame
 template <typename R>
-__device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, const R n[3], R u[3], uint64_t uid,
-                                               long long step, int bounce) {
-    U4 r = draw(D.seed, uid, step, kTagWall, (uint32_t)bounce);
+__device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u[3], uint64_t uid, const StepCtx &sx,
+                                               int bounce) {
+    U4 r = draw(sx.seed, uid, sx.step, kTagWall, (uint32_t)bounce, sx.inst);
     R t1[3], t2[3];
     face_frame<R>(n, t1, t2);
     const R Tw = (R)b.Tw;
@@ -771,7 +810,7 @@ __device__ __forceinline__ void reemit_diffuse(const Dev &D, const DevBC &b, con
 }
 
 template <typename R>
-__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, uint64_t uid, long long step,
+__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, uint64_t uid, const StepCtx &sx,
                      int &ncross, int &nwall) {
     // margin of the exact division skip below: well above the rounding of the products
     const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
@@ -840,7 +879,7 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, 
         x[1] = x[1] + u[1] * best;
         x[2] = x[2] + u[2] * best;
         trem = trem - best;
-        if (++ncross > D.max_cross) {
+        if (++ncross > sx.max_cross) {
             cell = c;
             return -1;
         }
@@ -869,7 +908,7 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, 
             R p[4];
             cell_plane(D, c * 6 + bf, p);
             const R n[3] = {p[0], p[1], p[2]};
-            reemit_diffuse<R>(D, b, n, u, uid, step, bounce);
+            reemit_diffuse<R>(b, n, u, uid, sx, bounce);
             ++bounce;
             ++nwall;
             entry = bf;
@@ -953,8 +992,6 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     const long long i0 = (long long)blockIdx.x * blockDim.x;
     if (i0 >= n_tot) return;
     const long long i = i0 + threadIdx.x;
-    const R dt = (R)sc->dt;
-    const long long step = sc->step;
     const Particles pa = D.pa[buf];
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     unsigned long long nx_ = 0, nw_ = 0;
@@ -968,18 +1005,23 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
         load_state(pa, i, x, u, uid, keep);
         // start-cell data, loaded before the generator runs
         const R e = (R)D.ec[c], tauc = (R)D.tau[c];
+        const int inst = inst_of(D, c);
+        const InstP &P = D.ip[inst];
+        const double dt64 = D.is[inst].dt;
+        const R dt = (R)dt64;
+        const StepCtx sx{P.seed, D.is[inst].step, inst, P.max_cross};
         R ts = dt;
         int entry0 = -1;
         bool collided = false;
         if (i >= n_smp) {
             // entering through a far-field face: from its entry time to the end of the step,
             // starting on that face; never a stayer (it did not start in a cell)
-            const U4 r = draw(D.seed, uid, step, kTagInject, 0);
-            ts = (R)(unif<double>(r.v[3]) * sc->dt);
-            entry0 = D.bflf[(uid >> 20) & 0xFFFFFFULL];
+            const U4 r = draw(sx.seed, uid, sx.step, kTagInject, 0, inst);
+            ts = (R)(unif<double>(r.v[3]) * dt64);
+            entry0 = D.bflf[P.bf0 + (long long)((uid >> 20) & 0xFFFFFFULL)];
             c0 = -1;
         } else if (i < n_old) {
-            const U4 r = draw(D.seed, uid, step, kTagTF, 0);
+            const U4 r = draw(sx.seed, uid, sx.step, kTagTF, 0, inst);
             const R eta = unif<R>(r.v[0]);
             if (!(eta < e * lmargin)) {
                 const R tf = -tauc * log(eta);
@@ -990,7 +1032,7 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
             }
         }
         int nx = 0, nw = 0;
-        const int rc = track<R>(D, x, u, c, ts, entry0, uid, step, nx, nw);
+        const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
         nx_ = (unsigned long long)nx;
         nw_ = (unsigned long long)nw;
         store_state(pa, i, x, u, keep);
@@ -1267,7 +1309,8 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
 __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
     __shared__ unsigned long long red[2][64];
     Scalars *s = D.sc;
-    const long long n_tot = s->n_old + s->n_new + s->n_inj;
+    const long long n_old = s->n_old, n_new = s->n_new, n_inj = s->n_inj;
+    const long long n_tot = n_old + n_new + n_inj;
     if (threadIdx.x < 64) {
         red[0][threadIdx.x] = D.spart[threadIdx.x];
         red[1][threadIdx.x] = D.spart[64 + threadIdx.x];
@@ -1280,9 +1323,32 @@ __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
         }
         __syncthreads();
     }
+    // per instance: its particles occupy the buckets of its cell range, its old particles
+    // the survivor segments of those cells, its new ones the sampled and entering ranges of
+    // its cells and far-field faces; then its own clock advances
+    const int nc = D.nc;
+    for (int k = threadIdx.x; k < D.n_inst; k += blockDim.x) {
+        const InstP &P = D.ip[k];
+        InstS &I = D.is[k];
+        const long long alive = D.off[P.cell1] - D.off[P.cell0];
+        const long long coll = D.off[nc + P.cell1] - D.off[nc + P.cell0];
+        const long long old = D.segoff[buf][P.cell1] - D.segoff[buf][P.cell0];
+        const long long smp = n_new > 0 ? D.samoff[P.cell1] - D.samoff[P.cell0] : 0;
+        const long long inj = (n_inj > 0 && P.ff1 > P.ff0) ? D.injoff[P.ff1] - D.injoff[P.ff0] : 0;
+        const long long tot = old + smp + inj;
+        I.n_alive = alive;
+        I.n_collided = coll;
+        I.n_escaped = tot - alive - coll;
+        I.n_sampled = smp;
+        I.n_injected = inj;
+        I.moved_total = I.moved_total + tot;
+        I.t = I.t + I.dt;
+        I.step = I.step + 1;
+        I.dtmin_bits = 0x7FF0000000000000ULL;
+    }
     if (threadIdx.x == 0) {
-        const long long alive = D.off[D.nc];
-        const long long ended = D.off[2 * D.nc];
+        const long long alive = D.off[nc];
+        const long long ended = D.off[2 * nc];
         s->n_cross = red[0][0];
         s->n_wall = red[1][0];
         s->n_collided = (unsigned long long)(ended - alive);
@@ -1290,12 +1356,11 @@ __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
         s->moved_total = s->moved_total + (unsigned long long)n_tot;
         s->n_alive = alive;
         s->n_old = alive;
-        D.segoff[buf ^ 1][D.nc] = (int32_t)alive;
+        D.segoff[buf ^ 1][nc] = (int32_t)alive;
         s->n_new = 0;
         s->n_inj = 0;
         s->t = s->t + s->dt;
         s->step = s->step + 1;
-        s->dtmin_bits = 0x7FF0000000000000ULL;
     }
 }
 

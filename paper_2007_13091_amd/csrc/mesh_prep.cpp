@@ -330,4 +330,62 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     return UGKWP_OK;
 }
 
+
+int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::vector<InstRange> &ranges,
+                      std::string &err) {
+    int64_t nc = 0, nf = 0, nff = 0, nbf = 0;
+    for (const HostMesh &h : parts) {
+        nc += h.nc;
+        nf += h.nf;
+        nff += h.nff;
+        nbf += (int64_t)h.bf_lf.size();
+    }
+    if (nc > 2147483647LL - 1 || nf > 2147483647LL - 1) {
+        err = "batch: more than 2^31 - 1 cells or faces in total";
+        return UGKWP_E_ARG;
+    }
+    HostMesh o;
+    o.nc = (int32_t)nc;
+    o.nf = (int32_t)nf;
+    o.nff = (int32_t)nff;
+    ranges.clear();
+    int32_t coff = 0, foff = 0, boff = 0, ffoff = 0;
+    int64_t bfoff = 0;
+    auto app = [](auto &dst, const auto &src) { dst.insert(dst.end(), src.begin(), src.end()); };
+    for (const HostMesh &h : parts) {
+        ranges.push_back(InstRange{coff, coff + h.nc, ffoff, ffoff + h.nff, bfoff});
+        app(o.vol, h.vol);
+        app(o.xc, h.xc);
+        app(o.dS, h.dS);
+        app(o.nfc, h.nfc);
+        app(o.ctype, h.ctype);
+        app(o.plane, h.plane);
+        app(o.box, h.box);
+        app(o.orig, h.orig);
+        app(o.edge, h.edge);
+        app(o.nblf, h.nblf);
+        for (int32_t v : h.nb) o.nb.push_back(v >= 0 ? v + coff : -1 - (-1 - v + boff));
+        for (int32_t v : h.cface) o.cface.push_back(v > 0 ? v + foff : (v < 0 ? v - foff : 0));
+        for (int32_t v : h.fown) o.fown.push_back(v + coff);
+        for (int32_t v : h.fnb) o.fnb.push_back(v >= 0 ? v + coff : -1 - (-1 - v + boff));
+        app(o.fn, h.fn);
+        app(o.farea, h.farea);
+        app(o.bcs, h.bcs);
+        for (int32_t v : h.ff_cell) o.ff_cell.push_back(v + coff);
+        app(o.ff_lf, h.ff_lf);
+        app(o.ff_bf, h.ff_bf);
+        for (int32_t v : h.ff_bc) o.ff_bc.push_back(v + boff);
+        app(o.ff_tri, h.ff_tri);
+        app(o.ff_geo, h.ff_geo);
+        app(o.bf_lf, h.bf_lf);
+        coff += h.nc;
+        foff += h.nf;
+        boff += (int32_t)h.bcs.size();
+        ffoff += h.nff;
+        bfoff += (int64_t)h.bf_lf.size();
+    }
+    out = std::move(o);
+    return UGKWP_OK;
+}
+
 }  // namespace ugkwp

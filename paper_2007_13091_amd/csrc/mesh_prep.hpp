@@ -41,4 +41,18 @@ struct HostMesh {
 // Returns UGKWP_OK or UGKWP_E_ARG / UGKWP_E_MESH with a message in *err.
 int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &out, std::string &err);
 
+// Where instance k of a batch sits in the concatenated mesh.
+struct InstRange {
+    int32_t cell0, cell1;  // cells
+    int32_t ff0, ff1;      // far-field faces
+    int64_t bf0;           // input boundary faces (index into bf_lf)
+};
+
+// Concatenate the prepared meshes of a batch into one mesh of disconnected parts: cell,
+// face and boundary-condition indices are offset; far-field faces keep the instance-local
+// index of their input boundary face.  Fails with UGKWP_E_ARG if the total exceeds 32-bit
+// indices.
+int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::vector<InstRange> &ranges,
+                      std::string &err);
+
 }  // namespace ugkwp

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_MESH", 3: "E_CAPACITY", 4: "E_LOST", 
 # every entry point the header declares
 SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkwp_step", "ugkwp_moments",
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
-           "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy")
+           "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
+           "ugkwp_instance_stats", "ugkwp_instance_cells")
 N_PROFILE_SLOTS = 11
 
 
@@ -72,9 +73,13 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, vp = C.POINTER, C.c_void_p
         L.ugkwp_workspace_bytes.restype = C.c_int32
-        L.ugkwp_workspace_bytes.argtypes = [P(UgkwpMesh), P(UgkwpParams), P(C.c_size_t)]
+        L.ugkwp_workspace_bytes.argtypes = [P(UgkwpMesh), C.c_int32, P(UgkwpParams), P(C.c_size_t)]
         L.ugkwp_init_mesh.restype = C.c_int32
-        L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), P(UgkwpParams), vp, C.c_size_t, vp]
+        L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), C.c_int32, P(UgkwpParams), vp, C.c_size_t, vp]
+        L.ugkwp_instance_stats.restype = C.c_int32
+        L.ugkwp_instance_stats.argtypes = [vp, C.c_int32, P(UgkwpStats)]
+        L.ugkwp_instance_cells.restype = C.c_int32
+        L.ugkwp_instance_cells.argtypes = [vp, C.c_int32, P(C.c_int64), P(C.c_int64)]
         L.ugkwp_init_state.restype = C.c_int32
         L.ugkwp_init_state.argtypes = [vp, P(C.c_double)]
         L.ugkwp_step.restype = C.c_int32
@@ -134,40 +139,60 @@ def make_params(p, capacity=0, recon=0, precision=0) -> UgkwpParams:
                        p.max_crossings, p.seed)
 
 
+class _BatchArgs:
+    """C arrays of meshes and parameters for n instances (single objects count as one)."""
+
+    def __init__(self, meshes, params, capacity=0, precision=0):
+        if not isinstance(meshes, (list, tuple)):
+            meshes, params = [meshes], [params]
+        if not isinstance(params, (list, tuple)):
+            params = [params] * len(meshes)
+        if len(params) != len(meshes):
+            raise ValueError("one params per mesh")
+        caps = capacity if isinstance(capacity, (list, tuple)) else [capacity] * len(meshes)
+        self.n = len(meshes)
+        self.margs = [_MeshArgs(m) for m in meshes]
+        self.m = (UgkwpMesh * self.n)(*[a.s for a in self.margs])
+        self.p = (UgkwpParams * self.n)(*[make_params(pp, cc, precision=precision) for pp, cc in zip(params, caps)])
+        self.ncells = [m.n_cells for m in meshes]
+
+
 def workspace_bytes(mesh, params, capacity=0, precision=0) -> int:
-    """Device bytes the library needs (host-side computation: mesh checks and layout)."""
+    """Device bytes the library needs (host-side computation: mesh checks and layout).
+    mesh/params may be lists (a batch of instances)."""
     L = lib()
-    m = _MeshArgs(mesh)
-    pr = make_params(params, capacity, precision=precision)
+    b = _BatchArgs(mesh, params, capacity, precision)
     n = C.c_size_t(0)
-    st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
+    st = L.ugkwp_workspace_bytes(b.m, b.n, b.p, C.byref(n))
     if st != OK:
         raise UgkwpError(st, L.ugkwp_last_error(None).decode())
     return int(n.value)
 
 
 class Solver:
-    """One mesh on one GPU.  `mesh`, `params`: see paper_2007_13091_amd.workloads."""
+    """One mesh, or a batch of independent instances (lists of meshes and params), on one
+    GPU.  `mesh`, `params`: see paper_2007_13091_amd.workloads.  stream: a torch stream to
+    order the work on (default: the current stream)."""
 
-    def __init__(self, mesh, params, capacity=0, precision=0, device="cuda"):
+    def __init__(self, mesh, params, capacity=0, precision=0, device="cuda", stream=None):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a GPU (the HIP library has no CPU path)")
         L = lib()
         self.torch = torch
-        self.nc = mesh.n_cells
-        m = _MeshArgs(mesh)
-        pr = make_params(params, capacity, precision=precision)
+        b = _BatchArgs(mesh, params, capacity, precision)
+        self.n_inst = b.n
+        self.nc = int(sum(b.ncells))
         n = C.c_size_t(0)
-        st = L.ugkwp_workspace_bytes(C.byref(m.s), C.byref(pr), C.byref(n))
+        st = L.ugkwp_workspace_bytes(b.m, b.n, b.p, C.byref(n))
         if st != OK:
             raise UgkwpError(st, L.ugkwp_last_error(None).decode())
         self.precision = precision
         self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
-        self.stream = torch.cuda.current_stream(self.ws.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
         h = C.c_void_p(0)
-        st = L.ugkwp_init_mesh(C.byref(h), C.byref(m.s), C.byref(pr), C.c_void_p(self.ws.data_ptr()), n.value,
+        st = L.ugkwp_init_mesh(C.byref(h), b.m, b.n, b.p, C.c_void_p(self.ws.data_ptr()), n.value,
                                C.c_void_p(self.stream.cuda_stream))
         if st != OK:
             raise UgkwpError(st, L.ugkwp_last_error(None).decode())
@@ -200,6 +225,16 @@ class Solver:
             return s.as_dict()
         self._check(lib().ugkwp_step(self.h, int(n), None))
         return None
+
+    def instance_stats(self, k):
+        s = UgkwpStats()
+        self._check(lib().ugkwp_instance_stats(self.h, int(k), C.byref(s)))
+        return s.as_dict()
+
+    def instance_cells(self, k):
+        a, b = C.c_int64(0), C.c_int64(0)
+        self._check(lib().ugkwp_instance_cells(self.h, int(k), C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     def moments(self, which=0):
         out = np.zeros((self.nc, 5), dtype=np.float64)

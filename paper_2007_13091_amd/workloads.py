@@ -429,3 +429,30 @@ def small_cube(**kw) -> Workload:
     args = dict(h0=0.25, growth=1.5, hmax=0.6, lo=(-1.5, -1.5, -1.5), hi=(2.5, 1.5, 1.5), n_ref=30)
     args.update(kw)
     return cube(**args)
+
+
+# --------------------------------------------------------------------------------------
+# batches of independent instances
+# --------------------------------------------------------------------------------------
+def batched(n_inst=64, cells=(2e3, 2e5), kn=(1e-4, 1.0), n_ref=(50, 500), cfl=0.5, seed=1):
+    """Independent instances alternating shock tube and cavity: cell counts log-uniform in
+    `cells`, Knudsen numbers log-uniform in `kn`, N_ref uniform integers in `n_ref` (seeded).
+    Tube: N_x x 2 x 2 boxes with N_x = ceil(cells / 4), h = 1 / N_x, the Sod data.  Cavity: n^3
+    boxes with n = round(cells^(1/3)), the lid-driven cavity data.  All CFL `cfl`, N_min 0."""
+    rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x42415443], dtype=np.uint64)))
+    out = []
+    for k in range(n_inst):
+        nc = math.exp(rng.uniform(math.log(cells[0]), math.log(cells[1])))
+        knk = math.exp(rng.uniform(math.log(kn[0]), math.log(kn[1])))
+        nr = int(rng.integers(n_ref[0], n_ref[1] + 1))
+        if k % 2 == 0:
+            w = sod(nx=max(2, math.ceil(nc / 4)), ny=2, nz=2, n_ref=nr, kn=knk, cfl=cfl, seed=seed)
+        else:
+            w = cavity(n=max(2, int(round(nc ** (1.0 / 3.0)))), n_ref=nr, kn=knk, cfl=cfl, seed=seed)
+        out.append(w)
+    return out
+
+
+def small_batch(n_inst=6, seed=1):
+    """A batch small enough for the oracle: 20 to 200 cells, 20 to 60 particles per cell."""
+    return batched(n_inst=n_inst, cells=(20, 200), kn=(1e-3, 1.0), n_ref=(20, 60), seed=seed)

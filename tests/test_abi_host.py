@@ -1,6 +1,7 @@
 """CPU-only checks of the C-ABI library: it loads, exports every symbol the header declares,
 and its host-side mesh checks (ugkwp_workspace_bytes, no device call) accept the workloads
 and reject broken meshes and parameters with the documented status codes."""
+import copy
 import os
 import re
 
@@ -71,3 +72,32 @@ def test_tet_meshes_pass_host_checks():
     assert U.workspace_bytes(w.mesh, w.params) > 0
     w = wl.closed_box(n=(3, 3, 3), tets=True, jitter=0.15)
     assert U.workspace_bytes(w.mesh, w.params) > 0
+
+
+def test_batch_workspace_and_checks():
+    ws = wl.small_batch(4)
+    meshes = [w.mesh for w in ws]
+    params = [w.params for w in ws]
+    nb = U.workspace_bytes(meshes, params)
+    singles = sum(U.workspace_bytes(w.mesh, w.params) for w in ws)
+    # one workspace for the batch: the per-instance arrays plus small instance tables
+    assert nb >= 0.9 * singles
+    with pytest.raises(U.UgkwpError):
+        U.workspace_bytes([], [])
+    bad = copy.deepcopy(params)
+    bad[2].mu_ref = -1.0
+    with pytest.raises(U.UgkwpError, match="instance 2"):
+        U.workspace_bytes(meshes, bad)
+
+
+def test_batched_generator_shapes():
+    ws = wl.batched(n_inst=8, seed=3)
+    for k, w in enumerate(ws):
+        nc = w.mesh.n_cells
+        if k % 2 == 0:
+            assert w.name == "sod" and nc % 4 == 0
+        else:
+            assert w.name == "cavity" and round(nc ** (1 / 3)) ** 3 == nc
+        assert 50 <= w.params.n_ref <= 500
+    ws2 = wl.batched(n_inst=8, seed=3)
+    assert [w.mesh.n_cells for w in ws] == [w.mesh.n_cells for w in ws2]
