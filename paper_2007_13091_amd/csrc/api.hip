@@ -92,10 +92,21 @@ struct ugkwp_ctx {
     size_t ws_bytes = 0;
     Dev D{};
     int buf = 0;
-    int gather_bs = 256;
+    ugkwp::LaunchCfg cfg;
     bool have_state = false;
     bool poisoned = false;
+    // graph replay: one captured step per starting particle buffer
+    bool graph_on = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
     std::string err;
+    void drop_graphs() {
+        for (auto &g : gexec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
+    ~ugkwp_ctx() { drop_graphs(); }
 };
 
 namespace {
@@ -374,8 +385,6 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         q.bf0 = r.bf0;
         for (int32_t c = r.cell0; c < r.cell1 && n_inst > 1; ++c) cinst[c] = k;
     }
-    // one wave per cell: blocks of 64 threads need no cross-wave barriers
-    ctx->gather_bs = 64;
 
     hipStream_t s = ctx->stream;
     const size_t nc = (size_t)H.nc, nf = (size_t)H.nf;
@@ -471,7 +480,27 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
     if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "step before init_state");
     if (ctx->poisoned) return fail(ctx, UGKWP_E_STATE, "context poisoned by an earlier device error; call init_state");
     for (int32_t i = 0; i < n_steps; ++i) {
-        ugkwp::launch_step(ctx->D, ctx->buf, ctx->gather_bs, ctx->stream, &ctx->prof);
+        if (ctx->graph_on) {
+            hipGraphExec_t &ge = ctx->gexec[ctx->buf];
+            if (!ge) {
+                // capture the launch sequence of a step once; every count it needs is read
+                // on the device, so the same graph serves every later step
+                hipGraph_t g = nullptr;
+                HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                ugkwp::launch_step(ctx->D, ctx->buf, ctx->cfg, ctx->stream, nullptr);
+                hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+                if (e != hipSuccess) return fail(ctx, UGKWP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+                e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    ge = nullptr;
+                    return fail(ctx, UGKWP_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                }
+            }
+            HIPCHK(ctx, hipGraphLaunch(ge, ctx->stream));
+        } else {
+            ugkwp::launch_step(ctx->D, ctx->buf, ctx->cfg, ctx->stream, &ctx->prof);
+        }
         ctx->buf ^= 1;
     }
     HIPCHK(ctx, hipGetLastError());
@@ -598,6 +627,119 @@ int32_t ugkwp_geometry(ugkwp_ctx *ctx, double *vol, double *xc, double *dS) {
     if (xc) std::memcpy(xc, H.xc.data(), H.xc.size() * sizeof(double));
     if (dS) std::memcpy(dS, H.dS.data(), H.dS.size() * sizeof(double));
     return UGKWP_OK;
+}
+
+int32_t ugkwp_graph_enable(ugkwp_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (on && !ctx->stream)
+        return fail(ctx, UGKWP_E_ARG, "graph replay needs a created stream (the null stream cannot be captured)");
+    if (!on) ctx->drop_graphs();
+    ctx->graph_on = on != 0;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg) {
+    if (!ctx || !cfg) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    ugkwp::LaunchCfg c;
+    c.stream_bs = cfg[0];
+    c.stream_blocks_per_cu = cfg[1];
+    c.sample_wpb = cfg[2];
+    c.flux_bs = cfg[3];
+    if (!ugkwp::launch_cfg_valid(c)) return fail(ctx, UGKWP_E_ARG, "launch configuration out of range");
+    ctx->cfg = c;
+    ctx->drop_graphs();
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg) {
+    if (!ctx || !cfg) return fail(nullptr, UGKWP_E_ARG, "bad argument");
+    cfg[0] = ctx->cfg.stream_bs;
+    cfg[1] = ctx->cfg.stream_blocks_per_cu;
+    cfg[2] = ctx->cfg.sample_wpb;
+    cfg[3] = ctx->cfg.flux_bs;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out) {
+    if (!ctx || steps_per_trial < 1) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "autotune before init_state");
+    if (ctx->poisoned) return fail(ctx, UGKWP_E_STATE, "context poisoned by an earlier device error; call init_state");
+    // one pass of coordinate search: each tunable kernel is timed under each of its shapes
+    // (hip events around that kernel only) over real steps, holding the others fixed
+    const bool prof_was = ctx->prof.on;
+    const bool graph_was = ctx->graph_on;
+    ctx->graph_on = false;
+    ctx->prof.on = true;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof.drain(nullptr, nullptr, 0);
+    ugkwp::LaunchCfg best = ctx->cfg;
+    struct Dim {
+        int slot;
+        std::vector<ugkwp::LaunchCfg> cand;
+    };
+    std::vector<Dim> dims(3);
+    dims[0].slot = ugkwp::kSlotStream;
+    const int sopt[][2] = {{128, 0}, {256, 0}, {512, 0}, {256, 4}, {256, 8}, {512, 2}, {512, 4}};
+    for (auto &o : sopt) {
+        ugkwp::LaunchCfg c;
+        c.stream_bs = o[0];
+        c.stream_blocks_per_cu = o[1];
+        dims[0].cand.push_back(c);
+    }
+    dims[1].slot = ugkwp::kSlotSample;
+    for (int w : {1, 2, 4, 8}) {
+        ugkwp::LaunchCfg c;
+        c.sample_wpb = w;
+        dims[1].cand.push_back(c);
+    }
+    dims[2].slot = ugkwp::kSlotFlux;
+    for (int b : {64, 128, 256}) {
+        ugkwp::LaunchCfg c;
+        c.flux_bs = b;
+        dims[2].cand.push_back(c);
+    }
+    int32_t st = UGKWP_OK;
+    for (int d = 0; d < 3 && st == UGKWP_OK; ++d) {
+        double best_ms = INFINITY;
+        ugkwp::LaunchCfg keep = best;
+        for (const auto &c0 : dims[d].cand) {
+            ugkwp::LaunchCfg c = best;
+            if (d == 0) {
+                c.stream_bs = c0.stream_bs;
+                c.stream_blocks_per_cu = c0.stream_blocks_per_cu;
+            } else if (d == 1) {
+                c.sample_wpb = c0.sample_wpb;
+            } else {
+                c.flux_bs = c0.flux_bs;
+            }
+            ctx->cfg = c;
+            // one untimed step (first use of a kernel variant), then the timed ones
+            ugkwp::launch_step(ctx->D, ctx->buf, c, ctx->stream, nullptr);
+            ctx->buf ^= 1;
+            for (int32_t k = 0; k < steps_per_trial; ++k) {
+                ugkwp::launch_step(ctx->D, ctx->buf, c, ctx->stream, &ctx->prof);
+                ctx->buf ^= 1;
+            }
+            double ms[ugkwp::kNumSlots];
+            int64_t cnt[ugkwp::kNumSlots];
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            ctx->prof.drain(ms, cnt, ugkwp::kNumSlots);
+            const double t = ms[dims[d].slot] / (double)(cnt[dims[d].slot] ? cnt[dims[d].slot] : 1);
+            if (t < best_ms) {
+                best_ms = t;
+                keep = c;
+            }
+        }
+        best = keep;
+        Scalars s;
+        st = read_scalars(ctx, s);
+    }
+    ctx->cfg = best;
+    ctx->drop_graphs();
+    ctx->graph_on = graph_was;
+    ctx->prof.on = prof_was;
+    if (cfg_out) (void)ugkwp_get_launch(ctx, cfg_out);
+    return st;
 }
 
 int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on) {

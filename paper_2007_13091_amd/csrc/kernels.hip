@@ -438,8 +438,8 @@ __global__ void k_sample_setup(Dev D) {
 // S2: wave flux per face, times the area, oriented owner -> neighbour.  Arithmetic in R
 // (FP32 form: float), inputs recovered from the FP64 state, result stored in FP64.
 // ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(128) k_flux(Dev D) {
+template <typename R, int BS>
+__global__ void __launch_bounds__(BS) k_flux(Dev D) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= D.nf) return;
     const int nc = D.nc, nf = D.nf;
@@ -549,11 +549,11 @@ __device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
 // uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(256) k_sample(Dev D, int buf) {
+template <typename R, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int c = blockIdx.x * (blockDim.x / kWave) + wave;
+    const int c = blockIdx.x * WPB + wave;
     if (c >= D.nc) return;
     const int nc = D.nc;
     const Scalars *sc = D.sc;
@@ -982,21 +982,24 @@ struct StateOf<float> {
 // which is evaluated near the threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
 // (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
-template <typename R>
-__global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
-    __shared__ unsigned long long red[2][4];
+template <typename R, int BS>
+__global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
+    constexpr int NW = BS / 64;
+    __shared__ unsigned long long red[2][NW];
     const Scalars *sc = D.sc;
     const long long n_old = sc->n_old;
     const long long n_smp = n_old + sc->n_new;
     const long long n_tot = n_smp + sc->n_inj;
-    const long long i0 = (long long)blockIdx.x * blockDim.x;
+    const long long i0 = (long long)blockIdx.x * BS;
     if (i0 >= n_tot) return;
-    const long long i = i0 + threadIdx.x;
+    // one particle per thread over a grid that covers them all, or a grid-stride loop over
+    // a persistent grid (the launch configuration decides; the results are the same)
+    const long long stride = (long long)gridDim.x * BS;
     const Particles pa = D.pa[buf];
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
-    if (i < n_tot) {
+    for (long long i = i0 + threadIdx.x; i < n_tot; i += stride) {
         int c = pa.cell[i];
         int c0 = c;
         R x[3], u[3];
@@ -1033,14 +1036,14 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
         }
         int nx = 0, nw = 0;
         const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
-        nx_ = (unsigned long long)nx;
-        nw_ = (unsigned long long)nw;
+        nx_ += (unsigned long long)nx;
+        nw_ += (unsigned long long)nw;
         store_state(pa, i, x, u, keep);
         pa.cell[i] = c;
         int key = -1;
         bool stay = false;
         if (rc != 1) {
-            lost = rc < 0;
+            lost = lost || rc < 0;
             key = collided ? D.nc + c : c;
             stay = !collided && c == c0;
         }
@@ -1056,8 +1059,12 @@ __global__ void __launch_bounds__(256) k_stream(Dev D, int buf) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        const unsigned long long b = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        unsigned long long a = 0, b = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+        }
         const int slot64 = blockIdx.x & 63;
         if (a) atomicAdd(&D.spart[slot64], a);
         if (b) atomicAdd(&D.spart[64 + slot64], b);
@@ -1495,7 +1502,61 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s) {
     if (n > 0) k_fill<double><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
 }
 
-void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) {
+namespace {
+template <typename R>
+void launch_stream(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+    const int bs = cfg.stream_bs;
+    const long long full = (D.cap + bs - 1) / bs;
+    long long nb = full;
+    if (cfg.stream_blocks_per_cu > 0) {
+        const long long pers = (long long)kNumCUs * cfg.stream_blocks_per_cu;
+        nb = pers < full ? pers : full;
+    }
+    const unsigned g = (unsigned)(nb > 0 ? nb : 1);
+    if (bs == 128)
+        k_stream<R, 128><<<g, 128, 0, s>>>(D, buf);
+    else if (bs == 512)
+        k_stream<R, 512><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_stream<R, 256><<<g, 256, 0, s>>>(D, buf);
+}
+
+template <typename R>
+void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+    const int w = cfg.sample_wpb, nc = D.nc;
+    const unsigned g = (unsigned)((nc + w - 1) / w);
+    if (w == 1)
+        k_sample<R, 1><<<g, 64, 0, s>>>(D, buf);
+    else if (w == 2)
+        k_sample<R, 2><<<g, 128, 0, s>>>(D, buf);
+    else if (w == 8)
+        k_sample<R, 8><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_sample<R, 4><<<g, 256, 0, s>>>(D, buf);
+}
+
+template <typename R>
+void launch_flux(const Dev &D, const LaunchCfg &cfg, hipStream_t s) {
+    const int bs = cfg.flux_bs, nf = D.nf;
+    const unsigned g = (unsigned)((nf + bs - 1) / bs);
+    if (bs == 64)
+        k_flux<R, 64><<<g, 64, 0, s>>>(D);
+    else if (bs == 256)
+        k_flux<R, 256><<<g, 256, 0, s>>>(D);
+    else
+        k_flux<R, 128><<<g, 128, 0, s>>>(D);
+}
+}  // namespace
+
+bool launch_cfg_valid(const LaunchCfg &c) {
+    const bool sb = c.stream_bs == 128 || c.stream_bs == 256 || c.stream_bs == 512;
+    const bool sp = c.stream_blocks_per_cu >= 0 && c.stream_blocks_per_cu <= 64;
+    const bool sw = c.sample_wpb == 1 || c.sample_wpb == 2 || c.sample_wpb == 4 || c.sample_wpb == 8;
+    const bool fb = c.flux_bs == 64 || c.flux_bs == 128 || c.flux_bs == 256;
+    return sb && sp && sw && fb;
+}
+
+void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr) {
     const int nc = D.nc, nf = D.nf;
     const unsigned gc = (unsigned)((nc + 255) / 256);
     Prof none;
@@ -1520,16 +1581,16 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     pr->begin(kSlotFlux);
     if (nf > 0) {
         if (f32)
-            k_flux<float><<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+            launch_flux<float>(D, cfg, s);
         else
-            k_flux<double><<<(unsigned)((nf + 127) / 128), 128, 0, s>>>(D);
+            launch_flux<double>(D, cfg, s);
     }
     pr->end(kSlotFlux);
     pr->begin(kSlotSample);
     if (f32)
-        k_sample<float><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+        launch_sample<float>(D, buf, cfg, s);
     else
-        k_sample<double><<<(unsigned)((nc + 3) / 4), 256, 0, s>>>(D, buf);
+        launch_sample<double>(D, buf, cfg, s);
     if (D.nff > 0) {
         if (f32)
             k_inject<float><<<(unsigned)D.nff, 64, 0, s>>>(D, buf);
@@ -1538,12 +1599,12 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     }
     pr->end(kSlotSample);
     pr->begin(kSlotStream);
-    const unsigned pb = (unsigned)stream_blocks(D.cap);
     if (f32)
-        k_stream<float><<<pb, 256, 0, s>>>(D, buf);
+        launch_stream<float>(D, buf, cfg, s);
     else
-        k_stream<double><<<pb, 256, 0, s>>>(D, buf);
+        launch_stream<double>(D, buf, cfg, s);
     pr->end(kSlotStream);
+    const unsigned pb = (unsigned)stream_blocks(D.cap);
     pr->begin(kSlotCount);
     k_count<<<pb, 256, 0, s>>>(D);
     pr->end(kSlotCount);
@@ -1555,7 +1616,6 @@ void launch_step(const Dev &D, int buf, int gather_bs, hipStream_t s, Prof *pr) 
     k_scatter<<<pb, 256, 0, s>>>(D);
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
-    (void)gather_bs;
     if (f32)
         k_gather<float><<<nc, 64, 0, s>>>(D, buf);
     else

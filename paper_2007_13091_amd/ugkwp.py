@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_MESH", 3: "E_CAPACITY", 4: "E_LOST", 
 SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkwp_step", "ugkwp_moments",
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
-           "ugkwp_instance_stats", "ugkwp_instance_cells")
+           "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
+           "ugkwp_get_launch", "ugkwp_autotune")
 N_PROFILE_SLOTS = 11
 
 
@@ -78,6 +79,14 @@ def lib():
         L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), C.c_int32, P(UgkwpParams), vp, C.c_size_t, vp]
         L.ugkwp_instance_stats.restype = C.c_int32
         L.ugkwp_instance_stats.argtypes = [vp, C.c_int32, P(UgkwpStats)]
+        L.ugkwp_graph_enable.restype = C.c_int32
+        L.ugkwp_graph_enable.argtypes = [vp, C.c_int32]
+        L.ugkwp_set_launch.restype = C.c_int32
+        L.ugkwp_set_launch.argtypes = [vp, P(C.c_int32)]
+        L.ugkwp_get_launch.restype = C.c_int32
+        L.ugkwp_get_launch.argtypes = [vp, P(C.c_int32)]
+        L.ugkwp_autotune.restype = C.c_int32
+        L.ugkwp_autotune.argtypes = [vp, C.c_int32, P(C.c_int32)]
         L.ugkwp_instance_cells.restype = C.c_int32
         L.ugkwp_instance_cells.argtypes = [vp, C.c_int32, P(C.c_int64), P(C.c_int64)]
         L.ugkwp_init_state.restype = C.c_int32
@@ -235,6 +244,26 @@ class Solver:
         a, b = C.c_int64(0), C.c_int64(0)
         self._check(lib().ugkwp_instance_cells(self.h, int(k), C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
+
+    def graph(self, on=True):
+        """Replay each step from a captured hip graph (needs a created stream)."""
+        self._check(lib().ugkwp_graph_enable(self.h, 1 if on else 0))
+
+    def launch_config(self, cfg=None):
+        """Get (and with cfg, first set) the launch shapes (stream_bs, stream_blocks_per_cu,
+        sample_wpb, flux_bs)."""
+        if cfg is not None:
+            a = np.ascontiguousarray(cfg, dtype=np.int32)
+            self._check(lib().ugkwp_set_launch(self.h, _ptr(a, C.c_int32)))
+        out = np.zeros(4, dtype=np.int32)
+        self._check(lib().ugkwp_get_launch(self.h, _ptr(out, C.c_int32)))
+        return tuple(int(v) for v in out)
+
+    def autotune(self, steps_per_trial=3):
+        """Pick the fastest launch shapes on real steps (the state advances)."""
+        out = np.zeros(4, dtype=np.int32)
+        self._check(lib().ugkwp_autotune(self.h, int(steps_per_trial), _ptr(out, C.c_int32)))
+        return tuple(int(v) for v in out)
 
     def moments(self, which=0):
         out = np.zeros((self.nc, 5), dtype=np.float64)

@@ -1,0 +1,112 @@
+"""Launch shapes, graph replay and the autotuner change nothing in the results: every launch
+shape of the tunable kernels gives bit-identical fields and particles; a step replayed from a
+captured hip graph equals the eagerly launched step at every step (with eager work and
+synchronisation between replays); an autotuned run equals a plain run of as many steps."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2007_13091_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-launch]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _state(s):
+    p = s.particles()
+    o = np.argsort(p["uid"])
+    return s.moments(0), {k: v[o] for k, v in p.items()}
+
+
+def _same(a, b, what):
+    np.testing.assert_array_equal(a[0], b[0], err_msg=f"{what}: W")
+    for k in ("uid", "cell", "x", "u", "m"):
+        np.testing.assert_array_equal(a[1][k], b[1][k], err_msg=f"{what}: particles {k}")
+
+
+SHAPES = [(128, 0, 1, 64), (512, 0, 8, 256), (256, 4, 2, 128), (256, 8, 4, 64), (512, 2, 1, 256), (128, 1, 8, 128)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_launch_shape_gives_identical_results(precision):
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    ws = [wl.cavity(n=8, n_ref=200), wl.free_stream_box(n=(4, 3, 3), n_ref=60, kn=0.2, perturb=0.2, tets=True,
+                                                         jitter=0.15)]
+    ref = None
+    for shape in [None] + SHAPES:
+        _say("precision", precision, "shape", shape)
+        s = Solver([w.mesh for w in ws], [w.params for w in ws], precision=precision)
+        s.init_state(np.concatenate([w.W0 for w in ws]))
+        if shape is not None:
+            assert s.launch_config(shape) == shape
+        s.step(5)
+        st = _state(s)
+        if ref is None:
+            ref = st
+        else:
+            _same(st, ref, f"shape {shape}")
+        s.close()
+
+
+def test_graph_replay_equals_eager_every_step():
+    import torch
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=60, kn=0.05, perturb=0.3)
+    stream = torch.cuda.Stream()
+    a = Solver(w.mesh, w.params, stream=stream)
+    b = Solver(w.mesh, w.params, stream=stream)
+    a.init_state(w.W0)
+    b.init_state(w.W0)
+    b.graph(True)
+    for k in range(7):
+        a.step(1, stats=False)
+        b.step(1, stats=False)
+        torch.cuda.synchronize()
+        # eager work between replays
+        x = torch.ones(1000, device="cuda").cumsum(0)
+        assert float(x[-1]) == 1000.0
+        _same(_state(b), _state(a), f"graph replay step {k}")
+        if k == 3:
+            b.graph(False)
+            b.step(1, stats=False)
+            a.step(1, stats=False)
+            b.graph(True)
+    sa, sb = a.step(2), b.step(2)
+    for key in ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits", "step"):
+        assert sa[key] == sb[key], key
+    _same(_state(b), _state(a), "graph replay end")
+
+
+def test_graph_needs_a_created_stream():
+    from paper_2007_13091_amd.ugkwp import Solver, UgkwpError
+    import torch
+
+    w = wl.cavity(n=4, n_ref=50)
+    s = Solver(w.mesh, w.params, stream=torch.cuda.default_stream())
+    with pytest.raises(UgkwpError, match="stream"):
+        s.graph(True)
+
+
+def test_autotuned_run_equals_plain_run():
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    ws = wl.small_batch(4)
+    a = Solver([w.mesh for w in ws], [w.params for w in ws], precision=1)
+    b = Solver([w.mesh for w in ws], [w.params for w in ws], precision=1)
+    W0 = np.concatenate([w.W0 for w in ws])
+    a.init_state(W0)
+    b.init_state(W0)
+    cfg = a.autotune(steps_per_trial=1)
+    _say("autotuned", cfg)
+    n = a.instance_stats(0)["step"]
+    assert n == 2 * 14
+    b.step(n)
+    _same(_state(a), _state(b), "autotuned vs plain")
+    assert a.launch_config() == cfg
