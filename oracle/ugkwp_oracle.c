@@ -851,8 +851,10 @@ static int phase_cells(oracle_t *o, cellq_t *q)
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
  * ones.  Per cell: rho^hp = exp(-dt/tau) rho^h, m_ref = (rho^p + rho^hp) Omega / N_ref,
  * N_sam = 2 ceil(rho^hp Omega / (2 m_ref)) raised to cover N_min - N_left (rounded up to
- * even), m_sam = rho^hp Omega / N_sam.  Pair j: X ~ N(0, I) by Box-Muller, velocities
- * U + sqrt(T) X and U - sqrt(T) X; each partner its own uniform position in the cell.
+ * even), m_sam = rho^hp Omega / N_sam.  Pair j: X_j ~ N(0, I) by Box-Muller, velocities
+ * U + s sqrt(T) X_j and U - s sqrt(T) X_j with s = sqrt(3 N_sam/2 / sum_j |X_j|^2) (one factor
+ * per cell: the sample then carries exactly the mass, momentum and energy of the hydro
+ * wave's collisionless part); each partner its own uniform position in the cell.
  * S (if given) receives the sums of phi over the new particles. */
 static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsampled)
 {
@@ -872,6 +874,21 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
         double msam = rhohp * o->vol[c] / ns;
         if (reserve(o, o->np + ns)) return ORC_E_CAPACITY;
         double sT = sqrt(q->T[c]);
+        {
+            /* energy-exact pairs: the pairs already carry the momentum rho^hp U exactly; one
+               factor on every thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2),
+               makes their energy rho^hp (|U|^2/2 + 3T/2) exact as well */
+            double sx2 = 0.0;
+            for (int64_t j = 0; j < ns; j += 2) {
+                uint64_t puid = orc_make_uid(0, o->step, c, j);
+                double ev[4];
+                draw4(o->seed, puid, o->step, TAG_VEL, 0, o->inst, ev);
+                double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
+                double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
+                sx2 += X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
+            }
+            sT = sT * sqrt(3.0 * (double)(ns / 2) / sx2);
+        }
         for (int64_t k = 0; k < ns; ++k) {
             int64_t i = o->np++;
             uint64_t uid = orc_make_uid(0, o->step, c, k);
