@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -124,6 +126,77 @@ def stated_fp32_error():
         return None
 
 
+def batched_run(steps, warmup, plain_steps):
+    """The batched form on 64 independent tube and cavity instances (log-uniform cell counts in
+    [2e3, 2e5], Kn in [1e-4, 1], 50 to 500 particles per cell): FP32 transport, all instances in
+    one launch per kernel, launch shapes autotuned on real steps, steps replayed from a
+    captured hip graph.  Against it: the FP64 plain form run instance by instance (each alone,
+    eager launches), timed over `plain_steps` steps after the same number of warm-up steps."""
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    ws = wl.batched()
+    meshes, params = [w.mesh for w in ws], [w.params for w in ws]
+    W0 = np.concatenate([w.W0 for w in ws])
+    nc = int(sum(w.mesh.n_cells for w in ws))
+    # capacity: N_sam = 2 ceil(r) adds at least two particles per cell and step wherever the
+    # hydro wave has a collisionless part, and rarefied cells lose only their collided share,
+    # so counts drift up by up to two per cell and step on top of about N_ref
+    total_steps = warmup + 10 * 2 + 1 + steps
+    caps = [int(1.3 * w.params.n_ref * w.mesh.n_cells + 2.2 * total_steps * w.mesh.n_cells) + 65536 for w in ws]
+    stream = torch.cuda.Stream()
+    s = Solver(meshes, params, capacity=caps, precision=1, stream=stream)
+    s.init_state(W0)
+    s.step(max(warmup, 1), stats=False)
+    cfg = s.autotune(steps_per_trial=1)
+    s.graph(True)
+    st0 = s.step(1, stats=True)
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.step(0, stats=True)
+    done_steps = st1["step"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    el = t1 - t0
+    moves = st1["moved_total"] - st0["moved_total"]
+    out = {"value": moves / el, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
+           "ms_per_step": el / steps * 1e3, "cell_steps_per_s": nc * steps / el, "steps": steps,
+           "warmup_and_tuning_steps": int(done_steps - steps),
+           "instances": len(ws), "cells": nc, "particles_per_step": int(moves / steps),
+           "launch_config": {"stream_bs": cfg[0], "sample_wpb": cfg[1], "flux_bs": cfg[2]},
+           "graph_replay": True}
+    # FP64 plain, one instance after the other, each on the current stream with eager launches
+    pm, pt, pc = 0, 0.0, 0
+    for w, cap in zip(ws, caps):
+        g = Solver(w.mesh, w.params, capacity=cap, precision=0)
+        g.init_state(w.W0)
+        a = g.step(int(done_steps - steps), stats=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        g.step(plain_steps, stats=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        b = g.step(0, stats=True)
+        pm += b["moved_total"] - a["moved_total"]
+        pt += tb - ta
+        pc += w.mesh.n_cells * plain_steps
+        g.close()
+        del g
+    torch.cuda.empty_cache()
+    out["fp64_plain_one_by_one"] = {"value": pm / pt, "unit": "particle moves/s", "cell_steps_per_s": pc / pt,
+                                    "steps": plain_steps}
+    out["speedup_vs_fp64_plain_one_by_one"] = out["value"] / (pm / pt)
+    return out
+
+
 def roofline(prof, moves_per_launch, bytes_per_move, rtype):
     """Roofline position of the dominant kernel (the slot with the largest summed time): the
     algorithmic bytes of the particle moves one launch performs over its average duration."""
@@ -147,6 +220,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=40)
+    ap.add_argument("--batched-warmup", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -192,6 +268,8 @@ def main():
                             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
                             "roofline": roofline(prof32, moves32 / args.steps, BYTES_PER_MOVE_FP32, "float"),
                             "stated_error": stated_fp32_error()}
+    if not args.no_batched:
+        out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -642,9 +642,8 @@ int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg) {
     if (!ctx || !cfg) return fail(ctx, UGKWP_E_ARG, "bad argument");
     ugkwp::LaunchCfg c;
     c.stream_bs = cfg[0];
-    c.stream_blocks_per_cu = cfg[1];
-    c.sample_wpb = cfg[2];
-    c.flux_bs = cfg[3];
+    c.sample_wpb = cfg[1];
+    c.flux_bs = cfg[2];
     if (!ugkwp::launch_cfg_valid(c)) return fail(ctx, UGKWP_E_ARG, "launch configuration out of range");
     ctx->cfg = c;
     ctx->drop_graphs();
@@ -654,9 +653,8 @@ int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg) {
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg) {
     if (!ctx || !cfg) return fail(nullptr, UGKWP_E_ARG, "bad argument");
     cfg[0] = ctx->cfg.stream_bs;
-    cfg[1] = ctx->cfg.stream_blocks_per_cu;
-    cfg[2] = ctx->cfg.sample_wpb;
-    cfg[3] = ctx->cfg.flux_bs;
+    cfg[1] = ctx->cfg.sample_wpb;
+    cfg[2] = ctx->cfg.flux_bs;
     return UGKWP_OK;
 }
 
@@ -679,11 +677,9 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     };
     std::vector<Dim> dims(3);
     dims[0].slot = ugkwp::kSlotStream;
-    const int sopt[][2] = {{128, 0}, {256, 0}, {512, 0}, {256, 4}, {256, 8}, {512, 2}, {512, 4}};
-    for (auto &o : sopt) {
+    for (int b : {128, 256, 512}) {
         ugkwp::LaunchCfg c;
-        c.stream_bs = o[0];
-        c.stream_blocks_per_cu = o[1];
+        c.stream_bs = b;
         dims[0].cand.push_back(c);
     }
     dims[1].slot = ugkwp::kSlotSample;
@@ -706,7 +702,6 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
             ugkwp::LaunchCfg c = best;
             if (d == 0) {
                 c.stream_bs = c0.stream_bs;
-                c.stream_blocks_per_cu = c0.stream_blocks_per_cu;
             } else if (d == 1) {
                 c.sample_wpb = c0.sample_wpb;
             } else {

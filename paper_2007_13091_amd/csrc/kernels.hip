@@ -545,7 +545,8 @@ __device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
 
 // ---------------------------------------------------------------------------------------
 // S3: hydro particles, one wave per cell.  Pair j shares X ~ N(0, I) (Box-Muller on the draw
-// keyed by the even partner's id); partners get U + sqrt(T) X and U - sqrt(T) X and their own
+// keyed by the even partner's id); partners get U + s sqrt(T) X and U - s sqrt(T) X (s: the
+// cell's energy-exact factor) and their own
 // uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
@@ -570,7 +571,24 @@ __global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
         const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
         const R U[3] = {(R)(m0 / rho), (R)(m1 / rho), (R)(m2 / rho)};
         const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
-        const R sT = sqrt(T);
+        R sT = sqrt(T);
+        const R one = (R)1, two_pi = (R)2 * (R)kPi;
+        {
+            // energy-exact pairs: the pairs carry the momentum exactly; one factor on every
+            // thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2), makes the energy
+            // exact too (a first pass over the pairs' normal draws, summed in FP64)
+            double sx2 = 0.0;
+            for (long long j = 2 * lane; j < ns; j += 2 * kWave) {
+                const U4 rv = draw(seed, make_uid(step, cl, j), step, kTagVel, 0, inst);
+                const R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
+                const R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
+                const double X0 = (double)(r1 * cos(two_pi * e1)), X1 = (double)(r1 * sin(two_pi * e1)),
+                             X2 = (double)(r2 * cos(two_pi * e3));
+                sx2 += X0 * X0 + X1 * X1 + X2 * X2;
+            }
+            sx2 = wave_sum(sx2);
+            sT = (R)((double)sT * sqrt(3.0 * (double)(ns / 2) / sx2));
+        }
         const double vol = D.vol[c];
         const R msam = (R)(D.ec[c] * D.rhoh[c] * vol / (double)ns);
         const R org[3] = {(R)D.orig[c], (R)D.orig[nc + c], (R)D.orig[2 * nc + c]};
@@ -578,7 +596,6 @@ __global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
         const bool tet = D.ctype[c] == 4;
-        const R one = (R)1, two_pi = (R)2 * (R)kPi;
         for (long long k = lane; k < ns; k += kWave) {
             const long long i = base + k;
             const uint64_t uid = make_uid(step, cl, k);
@@ -982,7 +999,7 @@ struct StateOf<float> {
 // which is evaluated near the threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
 // (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
-template <typename R, int BS>
+template <typename R, int BS, bool MULTI>
 __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     constexpr int NW = BS / 64;
     __shared__ unsigned long long red[2][NW];
@@ -992,14 +1009,12 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     const long long n_tot = n_smp + sc->n_inj;
     const long long i0 = (long long)blockIdx.x * BS;
     if (i0 >= n_tot) return;
-    // one particle per thread over a grid that covers them all, or a grid-stride loop over
-    // a persistent grid (the launch configuration decides; the results are the same)
-    const long long stride = (long long)gridDim.x * BS;
+    const long long i = i0 + threadIdx.x;
     const Particles pa = D.pa[buf];
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
-    for (long long i = i0 + threadIdx.x; i < n_tot; i += stride) {
+    if (i < n_tot) {
         int c = pa.cell[i];
         int c0 = c;
         R x[3], u[3];
@@ -1008,7 +1023,8 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
         load_state(pa, i, x, u, uid, keep);
         // start-cell data, loaded before the generator runs
         const R e = (R)D.ec[c], tauc = (R)D.tau[c];
-        const int inst = inst_of(D, c);
+        // a single instance reads its values through uniform addresses
+        const int inst = MULTI ? D.cinst[c] : 0;
         const InstP &P = D.ip[inst];
         const double dt64 = D.is[inst].dt;
         const R dt = (R)dt64;
@@ -1036,14 +1052,14 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
         }
         int nx = 0, nw = 0;
         const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
-        nx_ += (unsigned long long)nx;
-        nw_ += (unsigned long long)nw;
+        nx_ = (unsigned long long)nx;
+        nw_ = (unsigned long long)nw;
         store_state(pa, i, x, u, keep);
         pa.cell[i] = c;
         int key = -1;
         bool stay = false;
         if (rc != 1) {
-            lost = lost || rc < 0;
+            lost = rc < 0;
             key = collided ? D.nc + c : c;
             stay = !collided && c == c0;
         }
@@ -1503,22 +1519,25 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s) {
 }
 
 namespace {
+template <typename R, bool MULTI>
+void launch_stream_t(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+    // one thread per particle over the capacity; blocks past the live particles exit at once
+    const int bs = cfg.stream_bs;
+    const unsigned g = (unsigned)((D.cap + bs - 1) / bs);
+    if (bs == 128)
+        k_stream<R, 128, MULTI><<<g, 128, 0, s>>>(D, buf);
+    else if (bs == 512)
+        k_stream<R, 512, MULTI><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_stream<R, 256, MULTI><<<g, 256, 0, s>>>(D, buf);
+}
+
 template <typename R>
 void launch_stream(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
-    const int bs = cfg.stream_bs;
-    const long long full = (D.cap + bs - 1) / bs;
-    long long nb = full;
-    if (cfg.stream_blocks_per_cu > 0) {
-        const long long pers = (long long)kNumCUs * cfg.stream_blocks_per_cu;
-        nb = pers < full ? pers : full;
-    }
-    const unsigned g = (unsigned)(nb > 0 ? nb : 1);
-    if (bs == 128)
-        k_stream<R, 128><<<g, 128, 0, s>>>(D, buf);
-    else if (bs == 512)
-        k_stream<R, 512><<<g, 512, 0, s>>>(D, buf);
+    if (D.n_inst > 1)
+        launch_stream_t<R, true>(D, buf, cfg, s);
     else
-        k_stream<R, 256><<<g, 256, 0, s>>>(D, buf);
+        launch_stream_t<R, false>(D, buf, cfg, s);
 }
 
 template <typename R>
@@ -1550,10 +1569,9 @@ void launch_flux(const Dev &D, const LaunchCfg &cfg, hipStream_t s) {
 
 bool launch_cfg_valid(const LaunchCfg &c) {
     const bool sb = c.stream_bs == 128 || c.stream_bs == 256 || c.stream_bs == 512;
-    const bool sp = c.stream_blocks_per_cu >= 0 && c.stream_blocks_per_cu <= 64;
     const bool sw = c.sample_wpb == 1 || c.sample_wpb == 2 || c.sample_wpb == 4 || c.sample_wpb == 8;
     const bool fb = c.flux_bs == 64 || c.flux_bs == 128 || c.flux_bs == 256;
-    return sb && sp && sw && fb;
+    return sb && sw && fb;
 }
 
 void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr) {

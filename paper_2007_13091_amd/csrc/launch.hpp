@@ -35,13 +35,10 @@ struct Prof {
 
 // launch shapes of the kernels whose shape is tunable; every choice gives the same results
 struct LaunchCfg {
-    int stream_bs = 256;           // k_stream block size: 128, 256 or 512
-    int stream_blocks_per_cu = 0;  // 0: one particle per thread over the capacity; k > 0: a
-                                   // persistent grid of k blocks per compute unit
-    int sample_wpb = 4;            // k_sample waves (cells) per block: 1, 2, 4 or 8
-    int flux_bs = 128;             // k_flux block size: 64, 128 or 256
+    int stream_bs = 256;  // k_stream block size: 128, 256 or 512
+    int sample_wpb = 4;   // k_sample waves (cells) per block: 1, 2, 4 or 8
+    int flux_bs = 128;    // k_flux block size: 64, 128 or 256
 };
-constexpr int kNumCUs = 256;  // compute units of an MI355X
 bool launch_cfg_valid(const LaunchCfg &c);
 
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s);
