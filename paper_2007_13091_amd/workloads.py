@@ -456,3 +456,133 @@ def batched(n_inst=64, cells=(2e3, 2e5), kn=(1e-4, 1.0), n_ref=(50, 500), cfl=0.
 def small_batch(n_inst=6, seed=1):
     """A batch small enough for the oracle: 20 to 200 cells, 20 to 60 particles per cell."""
     return batched(n_inst=n_inst, cells=(20, 200), kn=(1e-3, 1.0), n_ref=(20, 60), seed=seed)
+
+
+# --------------------------------------------------------------------------------------
+# a body cut out of a graded box (the sphere-cone vehicle, paper Sec. 4.4)
+# --------------------------------------------------------------------------------------
+def carved_tet_mesh(ax, inside, jitter=0.15, seed=1, bc_far=0, bc_wall=1, bcs=()) -> Mesh:
+    """Box of hexahedra on the node coordinates ax[0..2] with every hexahedron whose centroid
+    satisfies inside(x, y, z) removed (a staircase body), the rest split into 6 Kuhn
+    tetrahedra.  Faces between kept and removed hexahedra carry bc_wall, the outer box bc_far;
+    boundary quads are split along their lowest-highest diagonal like the tetrahedra.
+    Interior nodes move within +-jitter h per axis (seeded); nodes on the body stay, nodes on
+    the outer box move only within its planes."""
+    n = [len(a) - 1 for a in ax]
+    nx, ny, nz = n
+    cx = [0.5 * (a[1:] + a[:-1]) for a in ax]
+    CX, CY, CZ = np.meshgrid(cx[0], cx[1], cx[2], indexing="ij")
+    removed = inside(CX, CY, CZ)  # [nx, ny, nz]
+    keep = ~removed
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    # nodes touching a removed hexahedron lie on the body: they do not move
+    on_body = np.zeros((nx + 1, ny + 1, nz + 1), dtype=bool)
+    ri, rj, rk = np.nonzero(removed)
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                on_body[ri + a, rj + b, rk + c] = True
+    X, Y, Z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    xyz = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(), Z.transpose(2, 1, 0).ravel()], 1)
+    I, J, K = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    pos = [I.transpose(2, 1, 0).ravel(), J.transpose(2, 1, 0).ravel(), K.transpose(2, 1, 0).ravel()]
+    fixed = on_body.transpose(2, 1, 0).ravel()
+    if jitter > 0.0:
+        rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x43415256], dtype=np.uint64)))
+        base = xyz.copy()
+        for d in range(3):
+            h = np.diff(ax[d])
+            hloc = np.minimum(np.concatenate([[h[0]], h]), np.concatenate([h, [h[-1]]]))
+            inner = (pos[d] > 0) & (pos[d] < n[d]) & ~fixed
+            dd = rng.uniform(-jitter, jitter, size=xyz.shape[0]) * hloc[pos[d]]
+            xyz[:, d] = np.where(inner, base[:, d] + dd, base[:, d])
+    # tetrahedra of the kept hexahedra, in (i fastest, then j, k) order
+    ki, kj, kk = np.nonzero(keep.transpose(2, 1, 0))  # z, y, x order so that x runs fastest
+    i, j, k = kk, kj, ki
+    tets = [np.stack([nid(i + a, j + b, k + c) for (a, b, c) in path], 1) for path in _KUHN]
+    cn = np.stack(tets, 1).reshape(-1, 4).astype(np.int64)
+    nc = cn.shape[0]
+    faces, tags = [], []
+
+    def add_quads(d, p, q, r, tag):
+        # quad on the node plane p of axis d spanning cells q, r of the two other axes
+        e1, e2 = [a for a in range(3) if a != d]
+        def node(pp, qq, rr):
+            idx = [None, None, None]
+            idx[d], idx[e1], idx[e2] = pp, qq, rr
+            return nid(idx[0], idx[1], idx[2])
+        n00, n10, n11, n01 = node(p, q, r), node(p, q + 1, r), node(p, q + 1, r + 1), node(p, q, r + 1)
+        t1 = np.stack([n00, n10, n11, -np.ones_like(n00)], 1)
+        t2 = np.stack([n00, n11, n01, -np.ones_like(n00)], 1)
+        f = np.stack([t1, t2], 1).reshape(-1, 4)
+        faces.append(f)
+        tags.append(np.full(f.shape[0], tag, dtype=np.int32))
+
+    for d in range(3):
+        kd = np.moveaxis(keep, d, 0)  # [n_d, ., .]
+        # outer planes
+        for p, sl in ((0, 0), (n[d], n[d] - 1)):
+            qq, rr = np.nonzero(kd[sl])
+            add_quads(d, np.full(qq.shape, p), qq, rr, bc_far)
+        # interior planes between cells a = p - 1 and b = p
+        a, b = kd[:-1], kd[1:]
+        pp, qq, rr = np.nonzero(a != b)
+        add_quads(d, pp + 1, qq, rr, bc_wall)
+    bf = np.concatenate(faces).astype(np.int64)
+    bt = np.concatenate(tags)
+    return Mesh(xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+                cell_type=np.full(nc, CELL_TET, dtype=np.uint8),
+                cell_node_off=np.arange(0, 4 * nc + 1, 4, dtype=np.int64),
+                cell_nodes=cn.ravel(), bface_nodes=bf, bface_bc=bt, bcs=list(bcs))
+
+
+def sphere_cone_inside(rn=0.3, half_angle_deg=20.0, length=2.0, nose=0.0):
+    """Inside test of a sphere-cone along +x: spherical nose of radius rn with its tip at
+    x = nose, a cone of the given half angle tangent to it, a flat base at x = nose + length."""
+    th = math.radians(half_angle_deg)
+    xt = nose + rn * (1.0 - math.sin(th))
+    rt = rn * math.cos(th)
+
+    def inside(x, y, z):
+        r = np.sqrt(y * y + z * z)
+        xs = x - nose
+        sph = (xs - rn) ** 2 + r * r <= rn * rn
+        cone = (x >= xt) & (x <= nose + length) & (r <= rt + (x - xt) * math.tan(th))
+        return (xs >= 0.0) & ((x < xt) & sph | cone)
+
+    return inside
+
+
+def vehicle(mach=15.0, kn=1e-3, n_ref=50, cfl=0.95, c2=10.0, h0=0.0435, growth=1.15, hmax=0.3,
+            lo=(-2.0, -3.0, -3.0), hi=(6.0, 3.0, 3.0), refine=((-0.2, 2.2), (-1.1, 1.1), (-1.1, 1.1)),
+            jitter=0.15, seed=1, steps=1200) -> Workload:
+    """Mach 15 flow past a blunt sphere-cone (nose radius 0.3, half angle 20 degrees, length 2,
+    axis along x) in [-2,6]x[-3,3]^2: graded hexahedra (h0 in the refined box around the body,
+    growing to hmax), the body's hexahedra removed, Kuhn tetrahedra with jitter; diffuse wall at
+    T_w = 0.2 T_0 (T_0 = 1 + (gamma - 1)/2 Ma^2 the stagnation temperature), far field outside;
+    free stream rho = 1, T = 1; N_ref = N_min."""
+    ax = []
+    for d in range(3):
+        a, b = refine[d]
+        nce = max(1, int(round((b - a) / h0)))
+        b = a + nce * h0
+        ax.append(graded_axis(lo[d], hi[d], a, b, h0, growth, hmax))
+    U = mach * math.sqrt(5.0 / 3.0)
+    T0 = 1.0 + (5.0 / 3.0 - 1.0) / 2.0 * mach * mach
+    Winf = conservative(np.array([1.0]), np.array([[U, 0.0, 0.0]]), np.array([1.0]))[0]
+    bcs = [BC(BC_FARFIELD, Winf=tuple(float(v) for v in Winf)), BC(BC_DIFFUSE, Tw=0.2 * T0)]
+    mesh = carved_tet_mesh(ax, sphere_cone_inside(), jitter=jitter, seed=seed, bcs=bcs)
+    W0 = np.tile(Winf, (mesh.n_cells, 1))
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=c2, n_ref=n_ref, n_min=n_ref, seed=seed)
+    return Workload("vehicle", mesh, prm, W0, steps)
+
+
+def small_vehicle(**kw) -> Workload:
+    """The vehicle case on a coarse mesh for parity runs."""
+    args = dict(h0=0.2, growth=1.5, hmax=0.8, lo=(-1.0, -1.6, -1.6), hi=(3.0, 1.6, 1.6),
+                refine=((-0.2, 2.2), (-1.0, 1.0), (-1.0, 1.0)), n_ref=30)
+    args.update(kw)
+    return vehicle(**args)

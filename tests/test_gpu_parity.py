@@ -150,6 +150,22 @@ def test_cube_full_size_first_steps():
     run_pair(w, 2, name="cube-full", length=12.0, vscale=15.0)
 
 
+@pytest.mark.parametrize("kn", [1e-3, 1.0])
+def test_vehicle_small_mach15(kn):
+    # the Mach 15 sphere-cone (staircase body, diffuse wall at 0.2 T_0, far field) on a coarse
+    # mesh at both ends of its Knudsen range, over the steps before its wake empties
+    w = wl.small_vehicle(kn=kn)
+    run_pair(w, 5, name=f"vehicle-small-kn{kn}", length=4.0, vscale=25.0)
+
+
+@pytest.mark.timeout(900)
+def test_vehicle_full_size_first_step():
+    # 3.1e6 tetrahedra and 1.6e8 particles: every field, count and particle after one step
+    w = wl.vehicle()
+    _say("vehicle full size", w.mesh.n_cells, "cells")
+    run_pair(w, 1, name="vehicle-full", length=8.0, vscale=25.0)
+
+
 def test_deterministic_rerun_bitwise():
     w = wl.cavity(n=6, n_ref=300)
     a = _solver(w)
