@@ -70,6 +70,15 @@ def lib():
         L.orc_sample_only.argtypes = [vp, P(d)]
         L.orc_flux_speed.restype = d
         L.orc_flux_speed.argtypes = [d, d]
+        L.orc_slope.argtypes = [d, d, d, d, P(d), P(d)]
+        L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, P(d)]
+        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, P(d)]
+        L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, P(d)]
+        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, P(d)]
+        L.orc_set_recon.restype = C.c_int
+        L.orc_set_recon.argtypes = [vp, C.c_int, d]
+        L.orc_gradients.restype = C.c_int
+        L.orc_gradients.argtypes = [vp, P(d), P(d), P(d)]
         L.orc_track.restype = C.c_int
         L.orc_track.argtypes = [vp, P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
         _lib = L
@@ -123,6 +132,51 @@ def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2):
     return F
 
 
+def slope(un, v, w, lam, b):
+    """Micro slope a with <(a . psi) psi> = b over the unit Maxwellian (face frame)."""
+    b = _v(b, 5)
+    a = np.zeros(5)
+    lib().orc_slope(float(un), float(v), float(w), float(lam), _p(b, C.c_double), _p(a, C.c_double))
+    return a
+
+
+def mvec(p, q, r, a, rng, un, v, w, lam):
+    """<u^p v^q w^r (a . psi) psi> (a None: without the a . psi factor) over the unit Maxwellian."""
+    out = np.zeros(5)
+    ap = None if a is None else _v(a, 5)
+    lib().orc_mvec(int(p), int(q), int(r), None if ap is None else _p(ap, C.c_double), int(rng), float(un),
+                   float(v), float(w), float(lam), _p(out, C.c_double))
+    return out
+
+
+def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2):
+    """Second-order interior flux; G[k][d] = dW_k/dx_d ([5][3])."""
+    F = np.zeros(5)
+    args = [_v(Wl, 5), _v(Wr, 5), _v(Whl, 5), _v(Whr, 5), _v(Gl, 15), _v(Gr, 15), _v(Ghl, 15), _v(Ghr, 15)]
+    n = _v(n, 3)
+    lib().orc_flux2_interior(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
+                             _p(F, C.c_double))
+    return F
+
+
+def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2):
+    F = np.zeros(5)
+    args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15)]
+    n = _v(n, 3)
+    lib().orc_flux2_specular(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
+                             _p(F, C.c_double))
+    return F
+
+
+def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2):
+    F = np.zeros(5)
+    args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15), _v(Winf, 5)]
+    n = _v(n, 3)
+    lib().orc_flux2_farfield(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
+                             _p(F, C.c_double))
+    return F
+
+
 def flux_specular(W, rhoh, n, dt, mu_ref, omega, c2):
     F = np.zeros(5)
     W, n = _v(W, 5), _v(n, 3)
@@ -170,6 +224,11 @@ class Oracle:
         if not h:
             raise OracleError(f"orc_create failed with status {st.value}")
         self.h = C.c_void_p(h)
+        recon = int(getattr(params, "recon", 0))
+        if recon:
+            rc = L.orc_set_recon(self.h, recon, float(getattr(params, "venkat_k", 1.0)))
+            if rc != OK:
+                raise OracleError(f"orc_set_recon failed with status {rc}")
         self.nc = int(L.orc_n_cells(self.h))
         self.nf = int(L.orc_n_faces(self.h))
 
@@ -224,6 +283,14 @@ class Oracle:
         lib().orc_get_particles(self.h, _p(x, C.c_double), _p(u, C.c_double), _p(m, C.c_double),
                                 _p(c, C.c_int64), _p(uid, C.c_uint64))
         return dict(x=x, u=u, m=m, cell=c, uid=uid)
+
+    def gradients(self):
+        """Limited gradients of W and of the hydro state ([nc][5][3] each) and the hydro state."""
+        gW = np.zeros((self.nc, 5, 3)); gH = np.zeros((self.nc, 5, 3)); Wh = np.zeros((self.nc, 5))
+        rc = lib().orc_gradients(self.h, _p(gW, C.c_double), _p(gH, C.c_double), _p(Wh, C.c_double))
+        if rc != OK:
+            raise OracleError(f"orc_gradients failed with status {rc}")
+        return gW, gH, Wh
 
     def sample_only(self):
         """Test hook: run the cell phase and the sampling of the current step only."""

@@ -309,6 +309,309 @@ void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Second order (Sec. 2.2: the initial distribution with slopes, the equilibrium state    */
+/* with its slopes and time derivative; Sec. 2.4 for the wave part).                       */
+/*                                                                                          */
+/* Moments of polynomials in (u, v, w) (face frame) over a Maxwellian: a polynomial of     */
+/* degree < 7 in each variable as dense coefficients, multiplied out and integrated term   */
+/* by term with <u^a v^b w^c> = <u^a>_range <v^b> <w^c>.                                    */
+/* ------------------------------------------------------------------------------------ */
+#define PD 7
+typedef struct { double c[PD][PD][PD]; } poly_t;
+
+static void poly_clear(poly_t *p) { memset(p, 0, sizeof(*p)); }
+
+static void poly_mono(int a, int b, int c, poly_t *p)
+{
+    poly_clear(p);
+    p->c[a][b][c] = 1.0;
+}
+
+/* psi_k: 1, u, v, w, (u^2 + v^2 + w^2)/2 */
+static void poly_psi(int k, poly_t *p)
+{
+    poly_clear(p);
+    if (k == 0) p->c[0][0][0] = 1.0;
+    else if (k == 1) p->c[1][0][0] = 1.0;
+    else if (k == 2) p->c[0][1][0] = 1.0;
+    else if (k == 3) p->c[0][0][1] = 1.0;
+    else { p->c[2][0][0] = 0.5; p->c[0][2][0] = 0.5; p->c[0][0][2] = 0.5; }
+}
+
+/* a . psi */
+static void poly_apsi(const double a[5], poly_t *p)
+{
+    poly_clear(p);
+    p->c[0][0][0] = a[0];
+    p->c[1][0][0] = a[1];
+    p->c[0][1][0] = a[2];
+    p->c[0][0][1] = a[3];
+    p->c[2][0][0] = 0.5 * a[4];
+    p->c[0][2][0] = 0.5 * a[4];
+    p->c[0][0][2] = 0.5 * a[4];
+}
+
+static int g_poly_overflow = 0;
+
+static void poly_mul(const poly_t *x, const poly_t *y, poly_t *z)
+{
+    poly_clear(z);
+    for (int i = 0; i < PD; ++i)
+        for (int j = 0; j < PD; ++j)
+            for (int k = 0; k < PD; ++k) {
+                double a = x->c[i][j][k];
+                if (a == 0.0) continue;
+                for (int l = 0; l < PD; ++l)
+                    for (int m = 0; m < PD; ++m)
+                        for (int n = 0; n < PD; ++n) {
+                            double b = y->c[l][m][n];
+                            if (b == 0.0) continue;
+                            if (i + l >= PD || j + m >= PD || k + n >= PD) { g_poly_overflow = 1; continue; }
+                            z->c[i + l][j + m][k + n] += a * b;
+                        }
+            }
+}
+
+/* <p> over a unit-density Maxwellian g in the face frame, u over range (0 all, +1 u > 0,
+ * -1 u < 0), v and w over the full line */
+static double poly_moment(const poly_t *p, int range, const prim_t *g)
+{
+    double mu[NMOM], mv[NMOM], mw[NMOM];
+    orc_moments(range, g->un, g->lam, mu);
+    orc_moments(0, g->v, g->lam, mv);
+    orc_moments(0, g->w, g->lam, mw);
+    double s = 0.0;
+    for (int i = 0; i < PD; ++i)
+        for (int j = 0; j < PD; ++j)
+            for (int k = 0; k < PD; ++k)
+                if (p->c[i][j][k] != 0.0) s += p->c[i][j][k] * mu[i] * mv[j] * mw[k];
+    return s;
+}
+
+/* out_k = < pre (a . psi) psi_k > (a == NULL: < pre psi_k >) */
+static void mvec(const poly_t *pre, const double *a, int range, const prim_t *g, double out[5])
+{
+    poly_t t, ap, pk, r;
+    if (a) {
+        poly_apsi(a, &ap);
+        poly_mul(pre, &ap, &t);
+    } else {
+        t = *pre;
+    }
+    for (int k = 0; k < 5; ++k) {
+        poly_psi(k, &pk);
+        poly_mul(&t, &pk, &r);
+        out[k] = poly_moment(&r, range, g);
+    }
+}
+
+/* Micro slope from a macro derivative (Sec. 2.2): a with < (a . psi) psi > = b over the full
+ * Maxwellian g (b = derivative of W divided by the density).  With c = u - U, the moments
+ * <c^2> = T = 1/(2 lambda) per direction give, for K = 0:
+ *   R = 2 b5 - (|U|^2 + 3/(2 lambda)) b1,  R_i = b_{i+1} - U_i b1 (i = 1..3)
+ *   a5 = (4 lambda^2 / 3) (R - 2 sum_i U_i R_i),  a_{i+1} = 2 lambda R_i - U_i a5,
+ *   a1 = b1 - sum_i U_i a_{i+1} - a5 (|U|^2 + 3/(2 lambda)) / 2. */
+void orc_slope(double un, double v, double w, double lam, const double b[5], double a[5])
+{
+    double U[3] = {un, v, w};
+    double q2 = un * un + v * v + w * w;
+    double R = 2.0 * b[4] - (q2 + 3.0 / (2.0 * lam)) * b[0];
+    double Ri[3];
+    for (int i = 0; i < 3; ++i) Ri[i] = b[1 + i] - U[i] * b[0];
+    a[4] = (4.0 * lam * lam / 3.0) * (R - 2.0 * (U[0] * Ri[0] + U[1] * Ri[1] + U[2] * Ri[2]));
+    for (int i = 0; i < 3; ++i) a[1 + i] = 2.0 * lam * Ri[i] - U[i] * a[4];
+    a[0] = b[0] - (U[0] * a[1] + U[1] * a[2] + U[2] * a[3]) - 0.5 * a[4] * (q2 + 3.0 / (2.0 * lam));
+}
+
+static void slope_of(const prim_t *g, const double dW[5], double a[5])
+{
+    double b[5];
+    for (int k = 0; k < 5; ++k) b[k] = dW[k] / g->rho;
+    orc_slope(g->un, g->v, g->w, g->lam, b, a);
+}
+
+/* test hook: <u^p v^q w^r (a . psi) psi> over a Maxwellian in the frame */
+void orc_mvec(int p, int q, int r, const double *a, int range, double un, double v, double w, double lam,
+              double out[5])
+{
+    poly_t pre;
+    poly_mono(p, q, r, &pre);
+    prim_t g;
+    g.rho = 1.0; g.un = un; g.v = v; g.w = w; g.lam = lam; g.T = 1.0 / (2.0 * lam);
+    mvec(&pre, a, range, &g, out);
+}
+
+/* One side of a face for the second-order flux, in the face frame: the reconstructed state
+ * (total W) with its derivatives along n, t1, t2, and the reconstructed hydro state W~^h with
+ * its derivatives (hydro density 0: no hydro part). */
+typedef struct {
+    prim_t g;
+    double dW[3][5];
+    prim_t h;
+    double dWh[3][5];
+} side_t;
+
+/* Second-order interface flux over dt, per unit area, face frame (SURVEY-style steps):
+ *   W0 from the upwind half moments of the two reconstructed states;
+ *   side slopes a_{s,d} from their derivatives; the equilibrium slope abar_d from
+ *   W_x = rho_l <(a_l,d . psi) psi>_{>0} + rho_r <(a_r,d . psi) psi>_{<0} (W_x = int f_x psi);
+ *   Abar from the compatibility condition <(u abar_n + v abar_t1 + w abar_t2 + Abar) . psi psi> = 0;
+ *   F^eq = rho0 [q1 <u psi> + q2 <u (u abar_n + v abar_t1 + w abar_t2) . psi psi> + q3 <u (Abar . psi) psi>];
+ *   F^wave = sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e / 2) <u (u a~_n + v a~_t1 + w a~_t2) . psi psi>_s]
+ *   over the half spaces, with a~ the slopes of W~^h. */
+static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_ref, double omega, double c2,
+                       double Ff[5])
+{
+    poly_t one, pu, pv, pw, puu, puv, puw;
+    poly_mono(0, 0, 0, &one);
+    poly_mono(1, 0, 0, &pu);
+    poly_mono(0, 1, 0, &pv);
+    poly_mono(0, 0, 1, &pw);
+    poly_mono(2, 0, 0, &puu);
+    poly_mono(1, 1, 0, &puv);
+    poly_mono(1, 0, 1, &puw);
+    double Hl[5], Hr[5], W0[5];
+    mvec(&one, NULL, +1, &L->g, Hl);
+    mvec(&one, NULL, -1, &R->g, Hr);
+    for (int k = 0; k < 5; ++k) W0[k] = L->g.rho * Hl[k] + R->g.rho * Hr[k];
+    prim_t z;
+    z.rho = W0[0];
+    z.un = W0[1] / W0[0];
+    z.v = W0[2] / W0[0];
+    z.w = W0[3] / W0[0];
+    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.lam = 1.0 / (2.0 * z.T);
+    double abar[3][5];
+    for (int d = 0; d < 3; ++d) {
+        double al[5], ar[5], Sl[5], Sr[5], Wx[5];
+        slope_of(&L->g, L->dW[d], al);
+        slope_of(&R->g, R->dW[d], ar);
+        mvec(&one, al, +1, &L->g, Sl);
+        mvec(&one, ar, -1, &R->g, Sr);
+        for (int k = 0; k < 5; ++k) Wx[k] = L->g.rho * Sl[k] + R->g.rho * Sr[k];
+        slope_of(&z, Wx, abar[d]);
+    }
+    double t0[5], t1[5], t2[5], bt[5], At[5];
+    mvec(&pu, abar[0], 0, &z, t0);
+    mvec(&pv, abar[1], 0, &z, t1);
+    mvec(&pw, abar[2], 0, &z, t2);
+    for (int k = 0; k < 5; ++k) bt[k] = -(t0[k] + t1[k] + t2[k]);
+    orc_slope(z.un, z.v, z.w, z.lam, bt, At);
+    double pl = L->g.rho * L->g.T, pr = R->g.rho * R->g.T;
+    double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
+    double q[5];
+    orc_qcoef(dt, tau, q);
+    double G0[5], X0[5], X1[5], X2[5], GA[5];
+    mvec(&pu, NULL, 0, &z, G0);
+    mvec(&puu, abar[0], 0, &z, X0);
+    mvec(&puv, abar[1], 0, &z, X1);
+    mvec(&puw, abar[2], 0, &z, X2);
+    mvec(&pu, At, 0, &z, GA);
+    for (int k = 0; k < 5; ++k)
+        Ff[k] = z.rho * (q[0] * G0[k] + q[1] * (X0[k] + X1[k] + X2[k]) + q[2] * GA[k]);
+    const side_t *S[2] = {L, R};
+    for (int s = 0; s < 2; ++s) {
+        const prim_t *h = &S[s]->h;
+        if (!(h->rho > 0.0)) continue;
+        int range = s == 0 ? +1 : -1;
+        double ah[3][5], Gh[5], Y0[5], Y1[5], Y2[5];
+        for (int d = 0; d < 3; ++d) slope_of(h, S[s]->dWh[d], ah[d]);
+        mvec(&pu, NULL, range, h, Gh);
+        mvec(&puu, ah[0], range, h, Y0);
+        mvec(&puv, ah[1], range, h, Y1);
+        mvec(&puw, ah[2], range, h, Y2);
+        for (int k = 0; k < 5; ++k) Ff[k] += h->rho * (q[3] * Gh[k] + q[4] * (Y0[k] + Y1[k] + Y2[k]));
+    }
+}
+
+/* derivatives of a conservative state along n, t1, t2 from its gradient G[k][d] (global
+ * frame), in frame components */
+static void frame_derivs(const double G[15], const double n[3], const double t1[3], const double t2[3],
+                         double out[3][5])
+{
+    const double *e[3] = {n, t1, t2};
+    for (int d = 0; d < 3; ++d) {
+        double dk[5];
+        for (int k = 0; k < 5; ++k) dk[k] = G[3 * k] * e[d][0] + G[3 * k + 1] * e[d][1] + G[3 * k + 2] * e[d][2];
+        out[d][0] = dk[0];
+        out[d][1] = dk[1] * n[0] + dk[2] * n[1] + dk[3] * n[2];
+        out[d][2] = dk[1] * t1[0] + dk[2] * t1[1] + dk[3] * t1[2];
+        out[d][3] = dk[1] * t2[0] + dk[2] * t2[1] + dk[3] * t2[2];
+        out[d][4] = dk[4];
+    }
+}
+
+static void make_side(const double W[5], const double G[15], const double Wh[5], const double Gh[15],
+                      const double n[3], const double t1[3], const double t2[3], side_t *s)
+{
+    s->g = to_frame(W, n, t1, t2);
+    frame_derivs(G, n, t1, t2, s->dW);
+    if (Wh[0] > 0.0) {
+        s->h = to_frame(Wh, n, t1, t2);
+        frame_derivs(Gh, n, t1, t2, s->dWh);
+    } else {
+        memset(&s->h, 0, sizeof(s->h));
+        memset(s->dWh, 0, sizeof(s->dWh));
+    }
+}
+
+/* Second-order interior flux (global frame): reconstructed face states Wl, Wr and hydro
+ * states Whl, Whr (conservative), gradients G[k][d] = dW_k/dx_d of each. */
+void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl[5], const double Whr[5],
+                        const double Gl[15], const double Gr[15], const double Ghl[15], const double Ghr[15],
+                        const double n[3], double dt, double mu_ref, double omega, double c2, double F[5])
+{
+    double t1[3], t2[3], Ff[5];
+    face_frame(n, t1, t2);
+    side_t L, R;
+    make_side(Wl, Gl, Whl, Ghl, n, t1, t2, &L);
+    make_side(Wr, Gr, Whr, Ghr, n, t1, t2, &R);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* Specular wall at second order: the mirror image of the reconstructed field (normal
+ * momentum and normal derivatives flip sign, twice for the normal momentum's normal
+ * derivative), then only the normal-momentum component is kept. */
+void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
+                        const double n[3], double dt, double mu_ref, double omega, double c2, double F[5])
+{
+    double t1[3], t2[3], Ff[5];
+    face_frame(n, t1, t2);
+    side_t L, R;
+    make_side(W, G, Wh, Gh, n, t1, t2, &L);
+    R = L;
+    R.g.un = -L.g.un;
+    R.h.un = -L.h.un;
+    for (int d = 0; d < 3; ++d) {
+        double sd = d == 0 ? -1.0 : 1.0; /* derivative along n flips */
+        for (int k = 0; k < 5; ++k) {
+            double sk = k == 1 ? -1.0 : 1.0; /* normal momentum flips */
+            R.dW[d][k] = sd * sk * L.dW[d][k];
+            R.dWh[d][k] = sd * sk * L.dWh[d][k];
+        }
+    }
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* Far field at second order: the free stream with zero gradients as the right side. */
+void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
+                        const double Winf[5], const double n[3], double dt, double mu_ref, double omega,
+                        double c2, double F[5])
+{
+    double t1[3], t2[3], Ff[5], zero[15];
+    memset(zero, 0, sizeof(zero));
+    face_frame(n, t1, t2);
+    side_t L, R;
+    make_side(W, G, Wh, Gh, n, t1, t2, &L);
+    make_side(Winf, zero, Winf, zero, n, t1, t2, &R);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    rotate_back(Ff, n, t1, t2, F);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Mesh: cells (4-node tetrahedra, 8-node axis-aligned boxes in VTK node order), faces     */
 /* found by matching sorted node sets.                                                    */
 /* ------------------------------------------------------------------------------------ */
@@ -342,6 +645,10 @@ typedef struct oracle {
     int *btri;                       /* triangle (1) or parallelogram (0) */
     int *cnblf;       /* [nc][6] local face index in the neighbour */
     double *orig, *edge; /* sampling frame: [nc][3], [nc][3][3] */
+    double *lfx;         /* [nc][6][3] centre of each local face */
+    double *fx;          /* [nf][3] face centre (the owner's) */
+    int recon;           /* 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan */
+    double venkat_k;     /* Venkatakrishnan constant K in eps^2 = (K h)^3 */
     int64_t *fown, *fnb; /* fnb: neighbour cell or -1 - bc index */
     double *fn, *farea;
     int nbc;
@@ -419,6 +726,8 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     for (int64_t i = 0; i < 6 * nc; ++i) o->cbf[i] = -1;
     o->cnblf = (int *)xcalloc(6 * nc, sizeof(int));
     o->orig = (double *)xcalloc(3 * nc, sizeof(double));
+    o->lfx = (double *)xcalloc(18 * nc, sizeof(double));
+    o->venkat_k = 1.0;
     o->edge = (double *)xcalloc(9 * nc, sizeof(double));
     o->W = (double *)xcalloc(5 * nc, sizeof(double));
     o->P = (double *)xcalloc(5 * nc, sizeof(double));
@@ -469,6 +778,8 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                     n[a] = s ? 1.0 : -1.0;
                     o->pd[6 * c + lf] = s ? hi[a] : -lo[a];
                     larea[6 * c + lf] = ar[a];
+                    for (int d = 0; d < 3; ++d)
+                        o->lfx[18 * c + 3 * lf + d] = d == a ? (s ? hi[a] : lo[a]) : o->xc[3 * c + d];
                 }
             }
             o->orig[3 * c] = x0; o->orig[3 * c + 1] = y0; o->orig[3 * c + 2] = z0;
@@ -508,6 +819,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                 for (int d = 0; d < 3; ++d) { n[d] = N[d] / len; fc[d] = (p[d] + q[d] + r[d]) / 3.0; }
                 o->pd[6 * c + lf] = n[0] * fc[0] + n[1] * fc[1] + n[2] * fc[2];
                 larea[6 * c + lf] = 0.5 * len;
+                for (int d = 0; d < 3; ++d) o->lfx[18 * c + 3 * lf + d] = fc[d];
             }
         } else {
             goto fail;
@@ -545,6 +857,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
         o->fnb = (int64_t *)xcalloc(nkeys, sizeof(int64_t));
         o->fn = (double *)xcalloc(3 * nkeys, sizeof(double));
         o->farea = (double *)xcalloc(nkeys, sizeof(double));
+        o->fx = (double *)xcalloc(3 * nkeys, sizeof(double));
         int64_t nf = 0;
         int bad = 0;
         for (int64_t i = 0; i < nkeys && !bad;) {
@@ -559,6 +872,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                 o->fown[nf] = c;
                 o->fnb[nf] = c2;
                 for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
+                for (int d = 0; d < 3; ++d) o->fx[3 * nf + d] = o->lfx[18 * c + 3 * lf + d];
                 o->farea[nf] = larea[6 * c + lf];
                 o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
                 o->cface[6 * c2 + lf2] = nf; o->csign[6 * c2 + lf2] = -1;
@@ -584,6 +898,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                 o->fown[nf] = c;
                 o->fnb[nf] = -1 - b;
                 for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
+                for (int d = 0; d < 3; ++d) o->fx[3 * nf + d] = o->lfx[18 * c + 3 * lf + d];
                 o->farea[nf] = larea[6 * c + lf];
                 o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
                 o->cnb[6 * c + lf] = -1 - b; o->cnblf[6 * c + lf] = -1;
@@ -646,6 +961,7 @@ void orc_destroy(oracle_t *o)
     free(o->cface); free(o->csign); free(o->pn); free(o->pd); free(o->cnb); free(o->cnblf); free(o->cbf);
     free(o->bo); free(o->be1); free(o->be2); free(o->barea); free(o->btri);
     free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
+    free(o->lfx); free(o->fx);
     free(o->bc); free(o->W); free(o->P); free(o->nleft);
     free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
     free(o);
@@ -656,6 +972,15 @@ int64_t orc_n_faces(const oracle_t *o) { return o->nf; }
 int64_t orc_n_particles(const oracle_t *o) { return o->np; }
 int64_t orc_step_index(const oracle_t *o) { return o->step; }
 double orc_time(const oracle_t *o) { return o->t; }
+
+/* reconstruction: 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan (K) */
+int orc_set_recon(oracle_t *o, int recon, double venkat_k)
+{
+    if (recon < 0 || recon > 2 || !(venkat_k > 0.0)) return ORC_E_ARG;
+    o->recon = recon;
+    o->venkat_k = venkat_k;
+    return ORC_OK;
+}
 
 void orc_geometry(const oracle_t *o, double *vol, double *xc, double *dS)
 {
@@ -801,11 +1126,14 @@ int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double
 typedef struct {
     double dt;
     double *tau, *ec, *rhoh, *U, *T;
+    double *Wh;      /* [nc][5] hydro state (rho^h / rho) W (second order) */
+    double *gW, *gH; /* [nc][5][3] limited gradients of W and of the hydro state */
 } cellq_t;
 
 static void cellq_free(cellq_t *q)
 {
     free(q->tau); free(q->ec); free(q->rhoh); free(q->U); free(q->T);
+    free(q->Wh); free(q->gW); free(q->gH);
 }
 
 /* Primitives, relaxation time tau = mu_ref T^omega / p (Eq. tau_via_T_ref, T_ref = 1), the
@@ -846,6 +1174,151 @@ static int phase_cells(oracle_t *o, cellq_t *q)
         q->ec[c] = exp(-q->dt / q->tau[c]);
     }
     return ORC_OK;
+}
+
+/* Temperature of a conservative state (R = 1, K = 0). */
+static double temp_of(const double W[5])
+{
+    return (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+}
+
+/* The state seen across local face lf of cell c for the gradient: the neighbour's (at its
+ * centre) or, at a boundary, a ghost at the centre mirrored in the face plane: specular, the
+ * mirror state (normal momentum reversed); diffuse, density and temperature of the cell with
+ * the velocity reflected about the wall's (2 U_w - U); far field, the free stream.  The
+ * ghost's hydro state is (rho^h / rho) times its state (the free stream: all of it). */
+static void across(const oracle_t *o, const cellq_t *q, int64_t c, int lf, double xj[3], double Wj[5],
+                   double Whj[5])
+{
+    int64_t nb = o->cnb[6 * c + lf];
+    const double *xc = o->xc + 3 * c, *Wc = o->W + 5 * c;
+    if (nb >= 0) {
+        for (int d = 0; d < 3; ++d) xj[d] = o->xc[3 * nb + d];
+        for (int k = 0; k < 5; ++k) { Wj[k] = o->W[5 * nb + k]; Whj[k] = q->Wh[5 * nb + k]; }
+        return;
+    }
+    const double *n = o->pn + 18 * c + 3 * lf;
+    double dist = o->pd[6 * c + lf] - (n[0] * xc[0] + n[1] * xc[1] + n[2] * xc[2]);
+    for (int d = 0; d < 3; ++d) xj[d] = xc[d] + 2.0 * dist * n[d];
+    const obc_t *b = o->bc + (-1 - nb);
+    if (b->type == BC_FARFIELD) {
+        for (int k = 0; k < 5; ++k) { Wj[k] = b->Winf[k]; Whj[k] = b->Winf[k]; }
+        return;
+    }
+    double rho = Wc[0], U[3] = {Wc[1] / rho, Wc[2] / rho, Wc[3] / rho}, T = temp_of(Wc), Ug[3];
+    if (b->type == BC_SPECULAR) {
+        double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
+        for (int d = 0; d < 3; ++d) Ug[d] = U[d] - 2.0 * un * n[d];
+    } else {
+        for (int d = 0; d < 3; ++d) Ug[d] = 2.0 * b->Uw[d] - U[d];
+    }
+    Wj[0] = rho;
+    for (int d = 0; d < 3; ++d) Wj[1 + d] = rho * Ug[d];
+    Wj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 1.5 * rho * T;
+    double f = q->rhoh[c] / rho;
+    for (int k = 0; k < 5; ++k) Whj[k] = f * Wj[k];
+}
+
+/* Gradients for second order (Sec. 2.2, reconstruction): the unweighted least-squares
+ * gradient over the face neighbours, g = (sum d d^T)^-1 sum d (W_j - W_c) with d = x_j - x_c,
+ * of the 5 components of W and of the hydro state W~^h = (rho^h / rho) W; then per component
+ * a limiter phi = min over the faces of
+ *   Barth-Jespersen:  min(1, (W_max - W_c) / D) for D > 0, min(1, (W_min - W_c) / D) for D < 0
+ *   Venkatakrishnan:  ((M^2 + eps^2) D + 2 D^2 M) / (D (M^2 + 2 D^2 + M D + eps^2)), M the same
+ *                     bound minus W_c, eps^2 = (K h)^3, h = Omega^(1/3)
+ * with D = g . (x_f - x_c) (1 where D = 0), W_max and W_min over the cell and its neighbours.
+ * A cell whose limited face states include rho <= 0, T <= 0 or a negative hydro density
+ * (or a hydro temperature <= 0) falls back to first order (all its gradients zero). */
+static void phase_grad(oracle_t *o, cellq_t *q)
+{
+    const int64_t nc = o->nc;
+    q->Wh = (double *)xcalloc(5 * nc, sizeof(double));
+    q->gW = (double *)xcalloc(15 * nc, sizeof(double));
+    q->gH = (double *)xcalloc(15 * nc, sizeof(double));
+    for (int64_t c = 0; c < nc; ++c) {
+        double f = q->rhoh[c] / o->W[5 * c];
+        for (int k = 0; k < 5; ++k) q->Wh[5 * c + k] = f * o->W[5 * c + k];
+    }
+    for (int64_t c = 0; c < nc; ++c) {
+        const double *xc = o->xc + 3 * c;
+        double A[3][3] = {{0}}, r[10][3] = {{0}}, vmax[10], vmin[10], vc[10];
+        for (int k = 0; k < 5; ++k) { vc[k] = o->W[5 * c + k]; vc[5 + k] = q->Wh[5 * c + k]; }
+        for (int k = 0; k < 10; ++k) vmax[k] = vmin[k] = vc[k];
+        for (int lf = 0; lf < o->cnf[c]; ++lf) {
+            double xj[3], Wj[5], Whj[5], dx[3], vj[10];
+            across(o, q, c, lf, xj, Wj, Whj);
+            for (int d = 0; d < 3; ++d) dx[d] = xj[d] - xc[d];
+            for (int k = 0; k < 5; ++k) { vj[k] = Wj[k]; vj[5 + k] = Whj[k]; }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) A[a][b] += dx[a] * dx[b];
+            for (int k = 0; k < 10; ++k) {
+                for (int a = 0; a < 3; ++a) r[k][a] += dx[a] * (vj[k] - vc[k]);
+                if (vj[k] > vmax[k]) vmax[k] = vj[k];
+                if (vj[k] < vmin[k]) vmin[k] = vj[k];
+            }
+        }
+        /* inverse of the symmetric 3x3 normal matrix by cofactors */
+        double C[3][3];
+        C[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        C[0][1] = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+        C[0][2] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+        C[1][0] = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+        C[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+        C[1][2] = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+        C[2][0] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+        C[2][1] = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+        C[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        double det = A[0][0] * C[0][0] + A[0][1] * C[1][0] + A[0][2] * C[2][0];
+        double g[10][3];
+        for (int k = 0; k < 10; ++k)
+            for (int a = 0; a < 3; ++a)
+                g[k][a] = (C[a][0] * r[k][0] + C[a][1] * r[k][1] + C[a][2] * r[k][2]) / det;
+        if (o->recon == 1 || o->recon == 2) {
+            double h = cbrt(o->vol[c]);
+            double eps2 = pow(o->venkat_k * h, 3.0);
+            for (int k = 0; k < 10; ++k) {
+                double phi = 1.0;
+                for (int lf = 0; lf < o->cnf[c]; ++lf) {
+                    const double *xf = o->lfx + 18 * c + 3 * lf;
+                    double D = g[k][0] * (xf[0] - xc[0]) + g[k][1] * (xf[1] - xc[1]) + g[k][2] * (xf[2] - xc[2]);
+                    double pf = 1.0;
+                    if (D != 0.0) {
+                        double M = D > 0.0 ? vmax[k] - vc[k] : vmin[k] - vc[k];
+                        if (o->recon == 1) {
+                            pf = M / D;
+                            if (pf > 1.0) pf = 1.0;
+                        } else {
+                            pf = ((M * M + eps2) * D + 2.0 * D * D * M) / (D * (M * M + 2.0 * D * D + M * D + eps2));
+                        }
+                    }
+                    if (pf < phi) phi = pf;
+                }
+                for (int a = 0; a < 3; ++a) g[k][a] *= phi;
+            }
+        }
+        int ok = 1;
+        for (int lf = 0; lf < o->cnf[c] && ok; ++lf) {
+            const double *xf = o->lfx + 18 * c + 3 * lf;
+            double Wf[10];
+            for (int k = 0; k < 10; ++k)
+                Wf[k] = vc[k] + g[k][0] * (xf[0] - xc[0]) + g[k][1] * (xf[1] - xc[1]) + g[k][2] * (xf[2] - xc[2]);
+            if (!(Wf[0] > 0.0) || !(temp_of(Wf) > 0.0)) ok = 0;
+            if (!(Wf[5] >= 0.0)) ok = 0;
+            if (Wf[5] > 0.0 && !(temp_of(Wf + 5) > 0.0)) ok = 0;
+        }
+        for (int k = 0; k < 5; ++k)
+            for (int a = 0; a < 3; ++a) {
+                q->gW[15 * c + 3 * k + a] = ok ? g[k][a] : 0.0;
+                q->gH[15 * c + 3 * k + a] = ok ? g[5 + k][a] : 0.0;
+            }
+    }
+}
+
+/* a cell's state extrapolated to a point: V_c + g . (x - x_c) */
+static void extrap(const double *Vc, const double *g, const double *xc, const double *x, double out[5])
+{
+    for (int k = 0; k < 5; ++k)
+        out[k] = Vc[k] + g[3 * k] * (x[0] - xc[0]) + g[3 * k + 1] * (x[1] - xc[1]) + g[3 * k + 2] * (x[2] - xc[2]);
 }
 
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
@@ -1029,6 +1502,23 @@ static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t
 
 /* Test hook: the cell phase and the sampling of the current step only (the new particles are
  * appended at their sampled positions; nothing streams and the step does not advance). */
+/* Test hook: the limited gradients of W and of the hydro state for the current state
+ * ([nc][5][3] each) and the hydro state ([nc][5]); nothing advances. */
+int orc_gradients(oracle_t *o, double *gW, double *gH, double *Wh)
+{
+    cellq_t q;
+    memset(&q, 0, sizeof(q));
+    int st = phase_cells(o, &q);
+    if (st == ORC_OK) {
+        phase_grad(o, &q);
+        memcpy(gW, q.gW, sizeof(double) * 15 * o->nc);
+        memcpy(gH, q.gH, sizeof(double) * 15 * o->nc);
+        memcpy(Wh, q.Wh, sizeof(double) * 5 * o->nc);
+    }
+    cellq_free(&q);
+    return st;
+}
+
 int orc_sample_only(oracle_t *o, double *dt)
 {
     cellq_t q = {0};
@@ -1057,12 +1547,36 @@ int orc_step(oracle_t *o)
     const double dt = q.dt;
     o->st_dt = dt;
 
+    if (o->recon) phase_grad(o, &q);
+
     /* wave flux over every face, oriented owner -> neighbour, times the face area */
     for (int64_t f = 0; f < nf; ++f) {
         int64_t c = o->fown[f], nb = o->fnb[f];
         const double *n = o->fn + 3 * f;
         double F[5];
-        if (nb >= 0) {
+        if (o->recon) {
+            /* second order: states extrapolated to the face centre from both sides */
+            const double *xf = o->fx + 3 * f;
+            double Wl[5], Whl[5];
+            extrap(o->W + 5 * c, q.gW + 15 * c, o->xc + 3 * c, xf, Wl);
+            extrap(q.Wh + 5 * c, q.gH + 15 * c, o->xc + 3 * c, xf, Whl);
+            if (nb >= 0) {
+                double Wr[5], Whr[5];
+                extrap(o->W + 5 * nb, q.gW + 15 * nb, o->xc + 3 * nb, xf, Wr);
+                extrap(q.Wh + 5 * nb, q.gH + 15 * nb, o->xc + 3 * nb, xf, Whr);
+                orc_flux2_interior(Wl, Wr, Whl, Whr, q.gW + 15 * c, q.gW + 15 * nb, q.gH + 15 * c, q.gH + 15 * nb, n,
+                                   dt, o->mu_ref, o->omega, o->c2, F);
+            } else {
+                const obc_t *b = o->bc + (-1 - nb);
+                if (b->type == BC_SPECULAR)
+                    orc_flux2_specular(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, n, dt, o->mu_ref, o->omega, o->c2, F);
+                else if (b->type == BC_DIFFUSE)
+                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, F);
+                else
+                    orc_flux2_farfield(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, b->Winf, n, dt, o->mu_ref, o->omega,
+                                       o->c2, F);
+            }
+        } else if (nb >= 0) {
             orc_flux_interior(o->W + 5 * c, o->W + 5 * nb, q.rhoh[c], q.rhoh[nb], n, dt, o->mu_ref, o->omega,
                               o->c2, F);
         } else {

@@ -74,6 +74,8 @@ class Params:
     max_crossings: int = 1000
     seed: int = 1
     gamma: float = 5.0 / 3.0
+    recon: int = 0          # 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan
+    venkat_k: float = 1.0   # Venkatakrishnan constant K
 
 
 def mu_ref_from_kn(kn: float, omega: float) -> float:
