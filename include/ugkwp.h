@@ -102,12 +102,15 @@ typedef struct {
     double c2;            /* numerical-dissipation constant C2 of Sec. 2.4(d) (0 = off) */
     int32_t n_ref;        /* reference particle number per cell, Sec. 2.4(b) */
     int32_t n_min;        /* minimum particle number per cell, Sec. 2.4(b) */
-    int32_t recon;        /* 0 = first order (only value supported) */
+    int32_t recon;        /* 0 first order; 1 least-squares gradients + Barth-Jespersen limiter;
+                             2 least-squares gradients + Venkatakrishnan limiter (Sec. 2.2) */
     int32_t precision;    /* 0 = FP64 throughout; 1 = FP32 form: flux and particle transport in
                              FP32, per-cell sums, W - W^p and energy -> T in FP64 */
     int64_t capacity;     /* particle capacity (0 = library default from n_ref and n_cells) */
     int32_t max_crossings;/* face crossings allowed per particle per step */
     uint64_t seed;        /* Philox4x64-10 key word 0 */
+    double venkat_k;      /* Venkatakrishnan constant K, eps^2 = (K h)^3 with h = Omega^(1/3)
+                             (recon = 2; must be > 0 then) */
 } ugkwp_params;
 
 /* Statistics of a step.  For a batch, ugkwp_step reports the counts summed over the

@@ -126,7 +126,7 @@ struct Carver {
 };
 
 // Lay the workspace out; with base == nullptr only the size is computed.
-size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, Dev &D, char *base) {
+size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, Dev &D, char *base) {
     Carver C{base};
     D.ip = C.take<ugkwp::InstP>((size_t)n_inst);
     D.is = C.take<ugkwp::InstS>((size_t)n_inst);
@@ -149,6 +149,12 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, Dev &D, cha
     D.fn = C.take<double>(3 * nf);
     D.farea = C.take<double>(nf);
     D.bc = C.take<DevBC>(nbc);
+    D.xc = recon ? C.take<double>(3 * nc) : nullptr;
+    D.lfx = recon ? C.take<double>(18 * nc) : nullptr;
+    D.fx = recon ? C.take<double>(3 * nf) : nullptr;
+    D.Wh = recon ? C.take<double>(5 * nc) : nullptr;
+    D.gW = recon ? C.take<double>(15 * nc) : nullptr;
+    D.gH = recon ? C.take<double>(15 * nc) : nullptr;
     const size_t nff = (size_t)H.nff;
     D.ffi = C.take<int4>(nff);
     D.ffg = C.take<double>(10 * nff);
@@ -207,8 +213,9 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
         err = "params: need 1 <= n_ref <= 2^20, 0 <= n_min <= 2^20, max_crossings >= 1";
         return UGKWP_E_ARG;
     }
-    if (p.recon != 0 || (p.precision != 0 && p.precision != 1)) {
-        err = "params: only first-order reconstruction (recon 0) is built; precision is 0 (FP64) or 1 (FP32 form)";
+    if (p.recon < 0 || p.recon > 2 || (p.recon == 2 && !(p.venkat_k > 0.0)) ||
+        (p.precision != 0 && p.precision != 1)) {
+        err = "params: recon is 0, 1 or 2 (2 needs venkat_k > 0); precision is 0 (FP64) or 1 (FP32 form)";
         return UGKWP_E_ARG;
     }
     long long c = p.capacity;
@@ -326,7 +333,9 @@ int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_p
     int32_t st = prepare_batch(m, n_inst, p, H, ranges, cap, err);
     if (st != UGKWP_OK) return fail(nullptr, st, err);
     Dev D{};
-    *bytes = carve(H, n_inst, cap, p[0].precision, D, nullptr);
+    bool recon = false;
+    for (int32_t k = 0; k < n_inst; ++k) recon = recon || p[k].recon != 0;
+    *bytes = carve(H, n_inst, cap, p[0].precision, recon, D, nullptr);
     return UGKWP_OK;
 }
 
@@ -350,7 +359,12 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     ctx->ws = (char *)dev_workspace;
     ctx->ws_bytes = ws_bytes;
     Dev &D = ctx->D;
-    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, D, ctx->ws);
+    bool recon_any = false, recon_all = true;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        recon_any = recon_any || p[k].recon != 0;
+        recon_all = recon_all && p[k].recon != 0;
+    }
+    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, recon_any, D, ctx->ws);
     if (ws_bytes < need) {
         delete ctx;
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -361,6 +375,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     D.nbc = (int32_t)H.bcs.size();
     D.nff = H.nff;
     D.n_inst = n_inst;
+    D.recon_any = recon_any ? 1 : 0;
+    D.recon_all = recon_all ? 1 : 0;
     D.cap = cap;
     D.prec = p[0].precision;
     std::vector<ugkwp::InstP> ip((size_t)n_inst);
@@ -377,6 +393,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         q.n_ref = p[k].n_ref;
         q.n_min = p[k].n_min;
         q.max_cross = p[k].max_crossings;
+        q.recon = p[k].recon;
+        q.venkat_k = p[k].venkat_k;
         q.seed = p[k].seed;
         q.cell0 = r.cell0;
         q.cell1 = r.cell1;
@@ -432,6 +450,14 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     e = e ? e : up((double *)D.ffg, H.ff_geo, s);
     e = e ? e : up((uint8_t *)D.bflf, H.bf_lf, s);
     e = e ? e : up((ugkwp::InstP *)D.ip, ip, s);
+    std::vector<double> xcs, fxs;
+    if (recon_any) {
+        xcs = soa(H.xc, nc, 3);
+        fxs = soa(H.fx, nf, 3);
+        e = e ? e : up((double *)D.xc, xcs, s);
+        e = e ? e : up((double *)D.lfx, H.lfx, s);
+        e = e ? e : up((double *)D.fx, fxs, s);
+    }
     if (n_inst > 1) e = e ? e : up((int32_t *)D.cinst, cinst, s);
     e = e ? e : hipStreamSynchronize(s);
     if (e != hipSuccess) return cleanup_fail(std::string("upload: ") + hipGetErrorString(e));

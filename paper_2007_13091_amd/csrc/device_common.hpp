@@ -31,7 +31,8 @@ struct DevBC {
 // contiguous range of cells and of far-field faces of the concatenated mesh.
 struct InstP {
     double mu_ref, omega, cfl, c2;
-    int32_t n_ref, n_min, max_cross, pad;
+    int32_t n_ref, n_min, max_cross, recon;  // recon: 0 first order, 1 LSQ + BJ, 2 LSQ + Venkatakrishnan
+    double venkat_k;
     unsigned long long seed;
     int32_t cell0, cell1;  // cells [cell0, cell1)
     int32_t ff0, ff1;      // far-field faces [ff0, ff1)
@@ -109,12 +110,16 @@ struct Dev {
     const double *fn;       // [3][nf]
     const double *farea;    // [nf]
     const DevBC *bc;        // [nbc]
+    const double *xc;       // [3][nc] cell centres (second order)
+    const double *lfx;      // [nc*6][3] local face centres (second order)
+    const double *fx;       // [3][nf] face centres (second order)
     int32_t nff, pad1;      // far-field faces
     const int4 *ffi;        // [nff]  (cell, local face | triangle << 8, input boundary-face index, bc)
     const double *ffg;      // [nff][10]  corner, two edges, area of the face as listed
     const uint8_t *bflf;    // [n_bfaces]  local face of an input boundary face
     // parameters
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
+    int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     const InstP *ip;        // [n_inst]
     InstS *is;              // [n_inst]
     const int32_t *cinst;   // [nc] instance of each cell (n_inst > 1 only)
@@ -128,6 +133,8 @@ struct Dev {
     double *ec;             // [nc] exp(-dt/tau)
     double *rhoh;           // [nc] max(rho - rho^p, 0)
     double *Phi;            // [5][nf]
+    double *Wh;             // [5][nc] hydro state (rho^h / rho) W (second order)
+    double *gW, *gH;        // [15][nc] limited gradients dW_k/dx_d at [3k+d][nc] (second order)
     double *S;              // [5][nc] particle sums at the start of the step
     long long *nsam;        // [nc]
     long long *samoff;      // [nc+1]

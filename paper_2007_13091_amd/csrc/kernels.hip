@@ -184,18 +184,26 @@ __device__ __forceinline__ Prim<R> to_frame(const double W[5], const R n[3], con
 
 // Taylor coefficients (-1)^k/k! and (-1)^k (k-1)/k!, k = 2..24, for the series forms of
 //   q1/tau = x - 1 + e^-x   and   (q4 - dt e)/tau = 1 - (1 + x) e^-x.
+// For second order also (k = 3..24), with q2, q3, q5 + dt^2 e / 2 = tau^2 x^3 times
+//   sum (-1)^k (k-2)/k! x^(k-3),  -sum (-1)^k / k! x^(k-3),  sum (-1)^k (k-1)(k-2)/(2 k!) x^(k-3).
 struct QSeries {
-    double a[25], b[25];
-    float af[25], bf[25];
-    constexpr QSeries() : a(), b(), af(), bf() {
+    double a[25], b[25], c[25], d[25], e[25];
+    float af[25], bf[25], cf[25], df[25], ef[25];
+    constexpr QSeries() : a(), b(), c(), d(), e(), af(), bf(), cf(), df(), ef() {
         double f = 1.0;
         for (int k = 1; k <= 24; ++k) {
             f = f * k;
             double s = (k % 2 == 0) ? 1.0 : -1.0;
             a[k] = s / f;
             b[k] = s * (k - 1) / f;
+            c[k] = s * (k - 2) / f;
+            d[k] = -s / f;
+            e[k] = s * (double)((k - 1) * (k - 2)) / (2.0 * f);
             af[k] = (float)a[k];
             bf[k] = (float)b[k];
+            cf[k] = (float)c[k];
+            df[k] = (float)d[k];
+            ef[k] = (float)e[k];
         }
     }
 };
@@ -434,6 +442,37 @@ __global__ void k_sample_setup(Dev D) {
     s->n_injected = (unsigned long long)s->n_inj;
 }
 
+// Diffuse isothermal wall (Sec. 2.4(e)), first order at the state l (n out of the domain):
+// incoming q1 g + (q4 - dt e) g^h with the cell tau; the wall emits rho_w M(T_w, U_w) over
+// u_n < 0 for the step, rho_w from zero net mass flux; the mass component is exactly 0.
+template <typename R>
+__device__ __forceinline__ void diffuse_flux(const Prim<R> &l, R h, R tau_c, const R n[3], const R t1[3],
+                                             const R t2[3], const DevBC &bc, R dt, R Ff[5]) {
+    R q1, q4m;
+    qcoef<R>(dt, tau_c, q1, q4m);
+    R ml[4], Hl[5], Gl[5];
+    moments4<R>(1, l.un, l.lam, ml);
+    psi_moments<R>(l, ml, Hl, Gl);
+    R Fin[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Fin[k] = q1 * l.rho * Gl[k] + q4m * h * Gl[k];
+    const R uw[3] = {(R)bc.Uw[0], (R)bc.Uw[1], (R)bc.Uw[2]};
+    Prim<R> w;
+    w.rho = (R)1;
+    w.un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
+    w.v = uw[0] * t1[0] + uw[1] * t1[1] + uw[2] * t1[2];
+    w.w = uw[0] * t2[0] + uw[1] * t2[1] + uw[2] * t2[2];
+    w.T = (R)bc.Tw;
+    w.lam = (R)1 / ((R)2 * w.T);
+    R mw[4], Hw[5], Gw[5];
+    moments4<R>(-1, w.un, w.lam, mw);
+    psi_moments<R>(w, mw, Hw, Gw);
+    const R rhow = -Fin[0] / (dt * Gw[0]);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Ff[k] = Fin[k] + dt * rhow * Gw[k];
+    Ff[0] = (R)0;
+}
+
 // ---------------------------------------------------------------------------------------
 // S2: wave flux per face, times the area, oriented owner -> neighbour.  Arithmetic in R
 // (FP32 form: float), inputs recovered from the FP64 state, result stored in FP64.
@@ -446,6 +485,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
     const int c = D.fown[f];
     const int inst = inst_of(D, c);
     const InstP &P = D.ip[inst];
+    if (P.recon != 0) return;
     const R dt = (R)D.is[inst].dt;
     const R mu = (R)P.mu_ref, om = (R)P.omega, c2 = (R)P.c2;
     const int nb = D.fnb[f];
@@ -476,36 +516,497 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
             Ff[3] = (R)0;
             Ff[4] = (R)0;
         } else if (bc.type == 1) {
-            // diffuse wall: incoming q1 g + (q4 - dt e) g^h with the cell tau; the wall emits
-            // rho_w M(T_w, U_w) over u_n < 0 for the step, rho_w from zero net mass flux
-            R q1, q4m;
-            qcoef<R>(dt, (R)D.tau[c], q1, q4m);
-            R ml[4], Hl[5], Gl[5];
-            moments4<R>(1, l.un, l.lam, ml);
-            psi_moments<R>(l, ml, Hl, Gl);
-            const R h = (R)D.rhoh[c];
-            R Fin[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) Fin[k] = q1 * l.rho * Gl[k] + q4m * h * Gl[k];
-            const R uw[3] = {(R)bc.Uw[0], (R)bc.Uw[1], (R)bc.Uw[2]};
-            Prim<R> w;
-            w.rho = (R)1;
-            w.un = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
-            w.v = uw[0] * t1[0] + uw[1] * t1[1] + uw[2] * t1[2];
-            w.w = uw[0] * t2[0] + uw[1] * t2[1] + uw[2] * t2[2];
-            w.T = (R)bc.Tw;
-            w.lam = (R)1 / ((R)2 * w.T);
-            R mw[4], Hw[5], Gw[5];
-            moments4<R>(-1, w.un, w.lam, mw);
-            psi_moments<R>(w, mw, Hw, Gw);
-            const R rhow = -Fin[0] / (dt * Gw[0]);
-#pragma unroll
-            for (int k = 0; k < 5; ++k) Ff[k] = Fin[k] + dt * rhow * Gw[k];
-            Ff[0] = (R)0;
+            diffuse_flux<R>(l, (R)D.rhoh[c], (R)D.tau[c], n, t1, t2, bc, dt, Ff);
         } else {
             // far field: the free stream as the right state (hydro density = its density)
             const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2);
             flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, Ff);
+        }
+    }
+    const R a = (R)D.farea[f];
+    D.Phi[f] = (double)(Ff[0] * a);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) D.Phi[(1 + d) * nf + f] = (double)((Ff[1] * n[d] + Ff[2] * t1[d] + Ff[3] * t2[d]) * a);
+    D.Phi[4 * nf + f] = (double)(Ff[4] * a);
+}
+
+// ---------------------------------------------------------------------------------------
+// Second order (Sec. 2.2 with slopes and time derivative; Sec. 2.4 for the wave part).
+// ---------------------------------------------------------------------------------------
+
+// q1, q2, q3, q4 - dt e, q5 + dt^2 e / 2 (series below x = 1, closed forms above)
+template <typename R>
+__device__ __forceinline__ void qcoef5(R dt, R tau, R q[5]) {
+    const R x = dt / tau;
+    if (x < (R)1) {
+        R s1 = (R)0, s4 = (R)0, s2 = (R)0, s3 = (R)0, s5 = (R)0;
+        constexpr int K = sizeof(R) == 8 ? 24 : 12;
+#pragma unroll
+        for (int k = K; k >= 2; --k) {
+            if constexpr (sizeof(R) == 8) {
+                s1 = s1 * x + kQ.a[k];
+                s4 = s4 * x + kQ.b[k];
+                if (k >= 3) {
+                    s2 = s2 * x + kQ.c[k];
+                    s3 = s3 * x + kQ.d[k];
+                    s5 = s5 * x + kQ.e[k];
+                }
+            } else {
+                s1 = s1 * x + kQ.af[k];
+                s4 = s4 * x + kQ.bf[k];
+                if (k >= 3) {
+                    s2 = s2 * x + kQ.cf[k];
+                    s3 = s3 * x + kQ.df[k];
+                    s5 = s5 * x + kQ.ef[k];
+                }
+            }
+        }
+        q[0] = tau * (s1 * x * x);
+        q[3] = tau * (s4 * x * x);
+        q[1] = tau * tau * (s2 * x * x * x);
+        q[2] = tau * tau * (s3 * x * x * x);
+        q[4] = tau * tau * (s5 * x * x * x);
+    } else {
+        const R e = exp(-x);
+        q[0] = tau * (x - (R)1 + e);
+        q[3] = tau * ((R)1 - ((R)1 + x) * e);
+        q[1] = tau * tau * ((R)2 * ((R)1 - e) - x * ((R)1 + e));
+        q[2] = tau * tau * ((R)0.5 * x * x - x + (R)1 - e);
+        q[4] = tau * tau * (((R)1 + x + (R)0.5 * x * x) * e - (R)1);
+    }
+}
+
+// <u^k>, k < N, over a range (0 all, +1 u > 0, -1 u < 0)
+template <typename R, int N>
+__device__ __forceinline__ void moments_n(int rng, R U, R lam, R m[N]) {
+    R m4[4];
+    moments4<R>(rng, U, lam, m4);
+    m[0] = m4[0];
+    m[1] = m4[1];
+#pragma unroll
+    for (int k = 0; k + 2 < N; ++k) m[k + 2] = U * m[k + 1] + (R)(k + 1) / ((R)2 * lam) * m[k];
+}
+
+// normal moments over a range to order 6, tangential ones over the full line to order 5
+template <typename R>
+struct Mom3 {
+    R u[7], v[6], w[6];
+};
+template <typename R>
+__device__ __forceinline__ void mom3(int rng, const Prim<R> &g, Mom3<R> &M) {
+    moments_n<R, 7>(rng, g.un, g.lam, M.u);
+    moments_n<R, 6>(0, g.v, g.lam, M.v);
+    moments_n<R, 6>(0, g.w, g.lam, M.w);
+}
+template <int I, int J, int K, typename R>
+__device__ __forceinline__ R mono(const Mom3<R> &M) {
+    return M.u[I] * M.v[J] * M.w[K];
+}
+// < u^I v^J w^K (a . psi) >
+template <int I, int J, int K, typename R>
+__device__ __forceinline__ R amom(const Mom3<R> &M, const R a[5]) {
+    return a[0] * mono<I, J, K>(M) + a[1] * mono<I + 1, J, K>(M) + a[2] * mono<I, J + 1, K>(M) +
+           a[3] * mono<I, J, K + 1>(M) +
+           (R)0.5 * a[4] * (mono<I + 2, J, K>(M) + mono<I, J + 2, K>(M) + mono<I, J, K + 2>(M));
+}
+// out_k = < u^P v^Q w^S (a . psi) psi_k >
+template <int P, int Q, int S, typename R>
+__device__ __forceinline__ void gvec(const Mom3<R> &M, const R a[5], R out[5]) {
+    out[0] = amom<P, Q, S>(M, a);
+    out[1] = amom<P + 1, Q, S>(M, a);
+    out[2] = amom<P, Q + 1, S>(M, a);
+    out[3] = amom<P, Q, S + 1>(M, a);
+    out[4] = (R)0.5 * (amom<P + 2, Q, S>(M, a) + amom<P, Q + 2, S>(M, a) + amom<P, Q, S + 2>(M, a));
+}
+// out_k = < u psi_k >
+template <typename R>
+__device__ __forceinline__ void uvec(const Mom3<R> &M, R out[5]) {
+    out[0] = mono<1, 0, 0>(M);
+    out[1] = mono<2, 0, 0>(M);
+    out[2] = mono<1, 1, 0>(M);
+    out[3] = mono<1, 0, 1>(M);
+    out[4] = (R)0.5 * (mono<3, 0, 0>(M) + mono<1, 2, 0>(M) + mono<1, 0, 2>(M));
+}
+
+// micro slope a with <(a . psi) psi> = b over the unit Maxwellian g (K = 0):
+//   R = 2 b5 - (|U|^2 + 3/(2 lambda)) b1, R_i = b_{i+1} - U_i b1, a5 = 4 lambda^2/3 (R - 2 U.R_i),
+//   a_{i+1} = 2 lambda R_i - U_i a5, a1 = b1 - U.a_{2..4} - a5 (|U|^2 + 3/(2 lambda))/2
+template <typename R>
+__device__ __forceinline__ void slope(const Prim<R> &g, const R b[5], R a[5]) {
+    const R U0 = g.un, U1 = g.v, U2 = g.w, lam = g.lam;
+    const R q2 = U0 * U0 + U1 * U1 + U2 * U2;
+    const R th = (R)3 / ((R)2 * lam);
+    const R Rr = (R)2 * b[4] - (q2 + th) * b[0];
+    const R R0 = b[1] - U0 * b[0], R1 = b[2] - U1 * b[0], R2 = b[3] - U2 * b[0];
+    a[4] = ((R)4 * lam * lam / (R)3) * (Rr - (R)2 * (U0 * R0 + U1 * R1 + U2 * R2));
+    a[1] = (R)2 * lam * R0 - U0 * a[4];
+    a[2] = (R)2 * lam * R1 - U1 * a[4];
+    a[3] = (R)2 * lam * R2 - U2 * a[4];
+    a[0] = b[0] - (U0 * a[1] + U1 * a[2] + U2 * a[3]) - (R)0.5 * a[4] * (q2 + th);
+}
+template <typename R>
+__device__ __forceinline__ void slope_of(const Prim<R> &g, const R dW[5], R a[5]) {
+    R b[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) b[k] = dW[k] / g.rho;
+    slope<R>(g, b, a);
+}
+
+// one side of a face in the face frame: reconstructed state and hydro state with their
+// derivatives along n, t1, t2 (hydro density 0: no hydro part)
+template <typename R>
+struct Side2 {
+    Prim<R> g, h;
+    R dW[3][5], dWh[3][5];
+};
+
+// derivatives of a conservative state along n, t1, t2 from its gradient (G at [3k+d] of a
+// [15][stride] array), in frame components
+template <typename R>
+__device__ __forceinline__ void frame_derivs(const double *G, long long stride, long long idx, const R n[3],
+                                             const R t1[3], const R t2[3], R out[3][5]) {
+    R g[5][3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[k][d] = (R)G[(3 * k + d) * stride + idx];
+    const R *e[3] = {n, t1, t2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R dk[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) dk[k] = g[k][0] * e[d][0] + g[k][1] * e[d][1] + g[k][2] * e[d][2];
+        out[d][0] = dk[0];
+        out[d][1] = dk[1] * n[0] + dk[2] * n[1] + dk[3] * n[2];
+        out[d][2] = dk[1] * t1[0] + dk[2] * t1[1] + dk[3] * t1[2];
+        out[d][3] = dk[1] * t2[0] + dk[2] * t2[1] + dk[3] * t2[2];
+        out[d][4] = dk[4];
+    }
+}
+
+// second-order flux between two sides (face frame), per unit area:
+//   W0 from the upwind half moments; side slopes; abar_d from W_x = rho_l <(a_l . psi) psi>_{>0}
+//   + rho_r <(a_r . psi) psi>_{<0}; Abar from <(u abar_n + v abar_t1 + w abar_t2 + Abar) . psi psi> = 0;
+//   F = rho0 [q1 <u psi> + q2 <u (u.abar) psi> + q3 <u Abar psi>]
+//     + sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e/2) <u (u.a~_s) psi>_s]
+template <typename R>
+__device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref, R omega, R c2, R Ff[5]) {
+    Mom3<R> ML, MR, M0;
+    mom3<R>(1, L.g, ML);
+    mom3<R>(-1, Rs.g, MR);
+    R W0[5];
+    {
+        const R one[5] = {(R)1, (R)0, (R)0, (R)0, (R)0};
+        R Hl[5], Hr[5];
+        gvec<0, 0, 0, R>(ML, one, Hl);
+        gvec<0, 0, 0, R>(MR, one, Hr);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) W0[k] = L.g.rho * Hl[k] + Rs.g.rho * Hr[k];
+    }
+    Prim<R> z;
+    z.rho = W0[0];
+    z.un = W0[1] / W0[0];
+    z.v = W0[2] / W0[0];
+    z.w = W0[3] / W0[0];
+    z.T = ((R)2 / (R)3) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.lam = (R)1 / ((R)2 * z.T);
+    mom3<R>(0, z, M0);
+    R abar[3][5];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R al[5], ar[5], Sl[5], Sr[5], Wx[5];
+        slope_of<R>(L.g, L.dW[d], al);
+        slope_of<R>(Rs.g, Rs.dW[d], ar);
+        gvec<0, 0, 0, R>(ML, al, Sl);
+        gvec<0, 0, 0, R>(MR, ar, Sr);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wx[k] = L.g.rho * Sl[k] + Rs.g.rho * Sr[k];
+        slope_of<R>(z, Wx, abar[d]);
+    }
+    R At[5];
+    {
+        R t0[5], t1[5], t2[5], bt[5];
+        gvec<1, 0, 0, R>(M0, abar[0], t0);
+        gvec<0, 1, 0, R>(M0, abar[1], t1);
+        gvec<0, 0, 1, R>(M0, abar[2], t2);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) bt[k] = -(t0[k] + t1[k] + t2[k]);
+        slope<R>(z, bt, At);
+    }
+    const R pl = L.g.rho * L.g.T, pr = Rs.g.rho * Rs.g.T;
+    const R tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
+    R q[5];
+    qcoef5<R>(dt, tau, q);
+    {
+        R G0[5], X0[5], X1[5], X2[5], GA[5];
+        uvec<R>(M0, G0);
+        gvec<2, 0, 0, R>(M0, abar[0], X0);
+        gvec<1, 1, 0, R>(M0, abar[1], X1);
+        gvec<1, 0, 1, R>(M0, abar[2], X2);
+        gvec<1, 0, 0, R>(M0, At, GA);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Ff[k] = z.rho * (q[0] * G0[k] + q[1] * (X0[k] + X1[k] + X2[k]) + q[2] * GA[k]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const Side2<R> &S = s == 0 ? L : Rs;
+        if (!(S.h.rho > (R)0)) continue;
+        Mom3<R> MH;
+        mom3<R>(s == 0 ? 1 : -1, S.h, MH);
+        R ah[5], Gh[5], Y[5], acc[5];
+        uvec<R>(MH, Gh);
+        slope_of<R>(S.h, S.dWh[0], ah);
+        gvec<2, 0, 0, R>(MH, ah, acc);
+        slope_of<R>(S.h, S.dWh[1], ah);
+        gvec<1, 1, 0, R>(MH, ah, Y);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[k] += Y[k];
+        slope_of<R>(S.h, S.dWh[2], ah);
+        gvec<1, 0, 1, R>(MH, ah, Y);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Ff[k] += S.h.rho * (q[3] * Gh[k] + q[4] * (acc[k] + Y[k]));
+    }
+}
+
+// temperature of a conservative state (R = 1, K = 0)
+__device__ __forceinline__ double temp_of(const double W[5]) {
+    return (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+}
+
+// Gradients for second order, one cell per thread, FP64 in both forms: the unweighted
+// least-squares gradient over the face neighbours of the 5 components of W and of the hydro
+// state (rho^h / rho) W; boundary ghosts at the centre mirrored in the face plane (specular:
+// mirror state; diffuse: the cell's density and temperature, velocity reflected about the
+// wall's; far field: the free stream); a limiter per component (Barth-Jespersen or
+// Venkatakrishnan with eps^2 = (K h)^3, h = Omega^(1/3)); a cell whose limited face states are
+// non-physical (rho <= 0, T <= 0, hydro density < 0 or hydro temperature <= 0) falls back to
+// first order.
+__global__ void __launch_bounds__(128) k_grad(Dev D) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= D.nc) return;
+    const int nc = D.nc;
+    const InstP &P = D.ip[inst_of(D, c)];
+    if (P.recon == 0) return;
+    double vc[10];
+    const double fc = D.rhoh[c] / D.W[c];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        vc[k] = D.W[k * nc + c];
+        vc[5 + k] = fc * vc[k];
+        D.Wh[k * nc + c] = vc[5 + k];
+    }
+    const double xc[3] = {D.xc[c], D.xc[nc + c], D.xc[2 * nc + c]};
+    double A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0;
+    double r[10][3], vmax[10], vmin[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        r[k][0] = r[k][1] = r[k][2] = 0.0;
+        vmax[k] = vmin[k] = vc[k];
+    }
+    const int nfc = D.nfc[c];
+    for (int lf = 0; lf < nfc; ++lf) {
+        const int2 nbl = D.nbl[c * 6 + lf];
+        double xj[3], vj[10];
+        if (nbl.x >= 0) {
+            const int j = nbl.x;
+            const double fj = D.rhoh[j] / D.W[j];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xj[d] = D.xc[d * nc + j];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                vj[k] = D.W[k * nc + j];
+                vj[5 + k] = fj * vj[k];
+            }
+        } else {
+            const double4 pl = D.plane[c * 6 + lf];
+            const double nn[3] = {pl.x, pl.y, pl.z};
+            const double dist = pl.w - (nn[0] * xc[0] + nn[1] * xc[1] + nn[2] * xc[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xj[d] = xc[d] + 2.0 * dist * nn[d];
+            const DevBC &b = D.bc[-1 - nbl.x];
+            if (b.type == 2) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) vj[k] = vj[5 + k] = b.Winf[k];
+            } else {
+                const double rho = vc[0];
+                const double U[3] = {vc[1] / rho, vc[2] / rho, vc[3] / rho};
+                const double T = temp_of(vc);
+                double Ug[3];
+                if (b.type == 0) {
+                    const double un = U[0] * nn[0] + U[1] * nn[1] + U[2] * nn[2];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) Ug[d] = U[d] - 2.0 * un * nn[d];
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) Ug[d] = 2.0 * b.Uw[d] - U[d];
+                }
+                vj[0] = rho;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vj[1 + d] = rho * Ug[d];
+                vj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 1.5 * rho * T;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) vj[5 + k] = fc * vj[k];
+            }
+        }
+        const double dx[3] = {xj[0] - xc[0], xj[1] - xc[1], xj[2] - xc[2]};
+        A00 += dx[0] * dx[0];
+        A01 += dx[0] * dx[1];
+        A02 += dx[0] * dx[2];
+        A11 += dx[1] * dx[1];
+        A12 += dx[1] * dx[2];
+        A22 += dx[2] * dx[2];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const double dv = vj[k] - vc[k];
+            r[k][0] += dx[0] * dv;
+            r[k][1] += dx[1] * dv;
+            r[k][2] += dx[2] * dv;
+            vmax[k] = fmax(vmax[k], vj[k]);
+            vmin[k] = fmin(vmin[k], vj[k]);
+        }
+    }
+    // inverse of the symmetric normal matrix by cofactors
+    const double C00 = A11 * A22 - A12 * A12, C01 = A02 * A12 - A01 * A22, C02 = A01 * A12 - A02 * A11;
+    const double C11 = A00 * A22 - A02 * A02, C12 = A02 * A01 - A00 * A12, C22 = A00 * A11 - A01 * A01;
+    const double det = A00 * C00 + A01 * C01 + A02 * C02;
+    double g[10][3];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        g[k][0] = (C00 * r[k][0] + C01 * r[k][1] + C02 * r[k][2]) / det;
+        g[k][1] = (C01 * r[k][0] + C11 * r[k][1] + C12 * r[k][2]) / det;
+        g[k][2] = (C02 * r[k][0] + C12 * r[k][1] + C22 * r[k][2]) / det;
+    }
+    const double *lfx = D.lfx + (long long)c * 18;
+    {
+        const double h = cbrt(D.vol[c]);
+        const double kh = P.venkat_k * h;
+        const double eps2 = kh * kh * kh;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            double phi = 1.0;
+            for (int lf = 0; lf < nfc; ++lf) {
+                const double Dk = g[k][0] * (lfx[3 * lf] - xc[0]) + g[k][1] * (lfx[3 * lf + 1] - xc[1]) +
+                                  g[k][2] * (lfx[3 * lf + 2] - xc[2]);
+                double pf = 1.0;
+                if (Dk != 0.0) {
+                    const double M = Dk > 0.0 ? vmax[k] - vc[k] : vmin[k] - vc[k];
+                    if (P.recon == 1)
+                        pf = fmin(1.0, M / Dk);
+                    else
+                        pf = ((M * M + eps2) * Dk + 2.0 * Dk * Dk * M) / (Dk * (M * M + 2.0 * Dk * Dk + M * Dk + eps2));
+                }
+                phi = fmin(phi, pf);
+            }
+            g[k][0] *= phi;
+            g[k][1] *= phi;
+            g[k][2] *= phi;
+        }
+    }
+    bool ok = true;
+    for (int lf = 0; lf < nfc; ++lf) {
+        double wf[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            wf[k] = vc[k] + g[k][0] * (lfx[3 * lf] - xc[0]) + g[k][1] * (lfx[3 * lf + 1] - xc[1]) +
+                    g[k][2] * (lfx[3 * lf + 2] - xc[2]);
+        if (!(wf[0] > 0.0) || !(temp_of(wf) > 0.0)) ok = false;
+        if (!(wf[5] >= 0.0)) ok = false;
+        if (wf[5] > 0.0 && !(temp_of(wf + 5) > 0.0)) ok = false;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            D.gW[(3 * k + d) * nc + c] = ok ? g[k][d] : 0.0;
+            D.gH[(3 * k + d) * nc + c] = ok ? g[5 + k][d] : 0.0;
+        }
+}
+
+// a cell's state (and hydro state) extrapolated to point x, FP64
+__device__ __forceinline__ void extrap(const Dev &D, int c, const double x[3], double W[5], double Wh[5]) {
+    const int nc = D.nc;
+    const double dx[3] = {x[0] - D.xc[c], x[1] - D.xc[nc + c], x[2] - D.xc[2 * nc + c]};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        W[k] = D.W[k * nc + c] + D.gW[(3 * k) * nc + c] * dx[0] + D.gW[(3 * k + 1) * nc + c] * dx[1] +
+               D.gW[(3 * k + 2) * nc + c] * dx[2];
+        Wh[k] = D.Wh[k * nc + c] + D.gH[(3 * k) * nc + c] * dx[0] + D.gH[(3 * k + 1) * nc + c] * dx[1] +
+                D.gH[(3 * k + 2) * nc + c] * dx[2];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void make_side(const Dev &D, int c, const double W[5], const double Wh[5], const R n[3],
+                                          const R t1[3], const R t2[3], Side2<R> &S) {
+    S.g = to_frame<R>(W, n, t1, t2);
+    frame_derivs<R>(D.gW, D.nc, c, n, t1, t2, S.dW);
+    if (Wh[0] > 0.0) {
+        S.h = to_frame<R>(Wh, n, t1, t2);
+        frame_derivs<R>(D.gH, D.nc, c, n, t1, t2, S.dWh);
+    } else {
+        S.h.rho = (R)0;
+    }
+}
+
+// S2 at second order: per face, states extrapolated to the face centre from both sides
+// (limited gradients), the flux of flux2_pair; specular walls mirror the reconstructed field
+// (derivatives along n and the normal momentum flip), diffuse walls stay first order at the
+// reconstructed face state, far-field faces see the free stream with zero gradients.
+template <typename R, int BS>
+__global__ void __launch_bounds__(BS) k_flux2(Dev D) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= D.nf) return;
+    const int nf = D.nf;
+    const int c = D.fown[f];
+    const int inst = inst_of(D, c);
+    const InstP &P = D.ip[inst];
+    if (P.recon == 0) return;
+    const R dt = (R)D.is[inst].dt;
+    const R mu = (R)P.mu_ref, om = (R)P.omega, c2 = (R)P.c2;
+    const int nb = D.fnb[f];
+    R n[3] = {(R)D.fn[f], (R)D.fn[nf + f], (R)D.fn[2 * nf + f]};
+    R t1[3], t2[3];
+    face_frame<R>(n, t1, t2);
+    const double xf[3] = {D.fx[f], D.fx[nf + f], D.fx[2 * nf + f]};
+    double Wl[5], Whl[5];
+    extrap(D, c, xf, Wl, Whl);
+    Side2<R> L, Rs;
+    make_side<R>(D, c, Wl, Whl, n, t1, t2, L);
+    R Ff[5];
+    if (nb >= 0) {
+        double Wr[5], Whr[5];
+        extrap(D, nb, xf, Wr, Whr);
+        make_side<R>(D, nb, Wr, Whr, n, t1, t2, Rs);
+        flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
+    } else {
+        const DevBC bc = D.bc[-1 - nb];
+        if (bc.type == 0) {
+            Rs = L;
+            Rs.g.un = -L.g.un;
+            Rs.h.un = -L.h.un;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const R sg = ((d == 0) != (k == 1)) ? (R)-1 : (R)1;
+                    Rs.dW[d][k] = sg * L.dW[d][k];
+                    Rs.dWh[d][k] = sg * L.dWh[d][k];
+                }
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
+            Ff[0] = (R)0;
+            Ff[2] = (R)0;
+            Ff[3] = (R)0;
+            Ff[4] = (R)0;
+        } else if (bc.type == 1) {
+            diffuse_flux<R>(L.g, (R)Whl[0], (R)D.tau[c], n, t1, t2, bc, dt, Ff);
+        } else {
+            Rs.g = to_frame<R>(bc.Winf, n, t1, t2);
+            Rs.h = Rs.g;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Rs.dW[d][k] = Rs.dWh[d][k] = (R)0;
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
         }
     }
     const R a = (R)D.farea[f];
@@ -1558,6 +2059,18 @@ template <typename R>
 void launch_flux(const Dev &D, const LaunchCfg &cfg, hipStream_t s) {
     const int bs = cfg.flux_bs, nf = D.nf;
     const unsigned g = (unsigned)((nf + bs - 1) / bs);
+    if (D.recon_any) {
+        // second order: gradients (one thread per cell), then the faces of reconstructing
+        // instances; the first-order kernel takes the others
+        k_grad<<<(unsigned)((D.nc + 127) / 128), 128, 0, s>>>(D);
+        if (bs == 64)
+            k_flux2<R, 64><<<g, 64, 0, s>>>(D);
+        else if (bs == 256)
+            k_flux2<R, 256><<<g, 256, 0, s>>>(D);
+        else
+            k_flux2<R, 128><<<g, 128, 0, s>>>(D);
+        if (D.recon_all) return;
+    }
     if (bs == 64)
         k_flux<R, 64><<<g, 64, 0, s>>>(D);
     else if (bs == 256)

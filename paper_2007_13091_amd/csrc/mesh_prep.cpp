@@ -77,6 +77,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     const int32_t nc = (int32_t)m.n_cells;
     H.nc = nc;
     H.vol.assign(nc, 0.0);
+    H.lfx.assign((size_t)nc * kMaxFaces * 3, 0.0);
     H.xc.assign(3 * (size_t)nc, 0.0);
     H.dS.assign(3 * (size_t)nc, 0.0);
     H.nfc.assign(nc, 0);
@@ -142,6 +143,8 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
                 P[4 * lf + ax] = up ? 1.0 : -1.0;
                 P[4 * lf + 3] = up ? hi[ax] : -lo[ax];
                 larea[(size_t)c * kMaxFaces + lf] = area[ax];
+                for (int d = 0; d < 3; ++d)
+                    H.lfx[((size_t)c * kMaxFaces + lf) * 3 + d] = d == ax ? (up ? hi[ax] : lo[ax]) : H.xc[3 * c + d];
             }
         } else {
             H.ctype[c] = 4;
@@ -187,6 +190,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
                 }
                 P[4 * lf + 3] = P[4 * lf] * cen[0] + P[4 * lf + 1] * cen[1] + P[4 * lf + 2] * cen[2];
                 larea[(size_t)c * kMaxFaces + lf] = 0.5 * len;
+                for (int d = 0; d < 3; ++d) H.lfx[((size_t)c * kMaxFaces + lf) * 3 + d] = cen[d];
             }
         }
     }
@@ -240,6 +244,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
             fown.push_back(own.cell);
             fnb.push_back(c);
             for (int d = 0; d < 3; ++d) fn.push_back(H.plane[4 * so + d]);
+            for (int d = 0; d < 3; ++d) H.fx.push_back(H.lfx[so * 3 + d]);
             farea.push_back(larea[so]);
             H.nb[so] = c;
             H.nblf[so] = lf;
@@ -276,6 +281,7 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
         fown.push_back(c);
         fnb.push_back(-1 - bci);
         for (int d = 0; d < 3; ++d) fn.push_back(H.plane[4 * so + d]);
+        for (int d = 0; d < 3; ++d) H.fx.push_back(H.lfx[so * 3 + d]);
         farea.push_back(larea[so]);
         H.bf_lf[(size_t)b] = (uint8_t)lf;
         if (m.bc[bci].type == UGKWP_BC_FARFIELD) {
@@ -370,6 +376,8 @@ int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::ve
         for (int32_t v : h.fnb) o.fnb.push_back(v >= 0 ? v + coff : -1 - (-1 - v + boff));
         app(o.fn, h.fn);
         app(o.farea, h.farea);
+        app(o.lfx, h.lfx);
+        app(o.fx, h.fx);
         app(o.bcs, h.bcs);
         for (int32_t v : h.ff_cell) o.ff_cell.push_back(v + coff);
         app(o.ff_lf, h.ff_lf);

@@ -30,6 +30,8 @@ struct HostMesh {
     std::vector<int32_t> fnb;    // [nf]: neighbour cell, or -1 - bc index
     std::vector<double> fn;      // [nf][3]  unit normal, owner -> neighbour (out of the domain at walls)
     std::vector<double> farea;   // [nf]
+    std::vector<double> lfx;     // [nc][6][3] centre of each local face
+    std::vector<double> fx;      // [nf][3] face centre (the owner's local face)
     std::vector<ugkwp_bc> bcs;
     // far-field faces, in (cell, local face) order: where free-stream particles enter
     int32_t nff = 0;

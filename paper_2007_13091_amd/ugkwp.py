@@ -43,7 +43,7 @@ class UgkwpParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu_ref", C.c_double), ("omega", C.c_double), ("cfl", C.c_double),
                 ("c2", C.c_double), ("n_ref", C.c_int32), ("n_min", C.c_int32), ("recon", C.c_int32),
                 ("precision", C.c_int32), ("capacity", C.c_int64), ("max_crossings", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("venkat_k", C.c_double)]
 
 
 class UgkwpStats(C.Structure):
@@ -143,9 +143,9 @@ class _MeshArgs:
                            _ptr(self.bf, C.c_int64), _ptr(self.bt, C.c_int32), len(mesh.bcs), self.bcs)
 
 
-def make_params(p, capacity=0, recon=0, precision=0) -> UgkwpParams:
-    return UgkwpParams(p.gamma, p.mu_ref, p.omega, p.cfl, p.c2, p.n_ref, p.n_min, recon, precision, capacity,
-                       p.max_crossings, p.seed)
+def make_params(p, capacity=0, precision=0) -> UgkwpParams:
+    return UgkwpParams(p.gamma, p.mu_ref, p.omega, p.cfl, p.c2, p.n_ref, p.n_min, int(getattr(p, "recon", 0)),
+                       precision, capacity, p.max_crossings, p.seed, float(getattr(p, "venkat_k", 1.0)))
 
 
 class _BatchArgs:

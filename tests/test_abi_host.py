@@ -101,3 +101,18 @@ def test_batched_generator_shapes():
         assert 50 <= w.params.n_ref <= 500
     ws2 = wl.batched(n_inst=8, seed=3)
     assert [w.mesh.n_cells for w in ws] == [w.mesh.n_cells for w in ws2]
+
+
+def test_reconstruction_parameters():
+    w = wl.sod(nx=10)
+    for recon in (1, 2):
+        p = copy.deepcopy(w.params)
+        p.recon = recon
+        assert U.workspace_bytes(w.mesh, p) > U.workspace_bytes(w.mesh, w.params)
+    p = copy.deepcopy(w.params)
+    p.recon = 3
+    with pytest.raises(U.UgkwpError):
+        U.workspace_bytes(w.mesh, p)
+    p.recon, p.venkat_k = 2, 0.0
+    with pytest.raises(U.UgkwpError):
+        U.workspace_bytes(w.mesh, p)

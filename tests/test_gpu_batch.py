@@ -80,6 +80,14 @@ def test_mixed_batch_with_far_field_and_tets():
     _run_batch(ws, 6, name="mixed-batch")
 
 
+def test_batch_mixing_first_and_second_order():
+    ws = [wl.sod(nx=12, ny=2, nz=2, n_ref=40), wl.cavity(n=4, n_ref=60, kn=0.01),
+          wl.free_stream_box(n=(4, 3, 3), U=(0.5, 0.4, -0.3), n_ref=50, kn=0.05, perturb=0.2, tets=True, jitter=0.15)]
+    ws[0].params.recon = 1
+    ws[2].params.recon = 2
+    _run_batch(ws, 5, name="mixed-order-batch")
+
+
 def test_batch_of_one_is_the_single_run():
     from paper_2007_13091_amd.ugkwp import Solver
 

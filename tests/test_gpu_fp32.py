@@ -132,6 +132,17 @@ def test_fp32_vehicle_error_statement():
         assert last["fp32_vs_oracle"][q]["L1"] <= 1.1 * last["noise_floor"][q]["L1"]
 
 
+def test_fp32_second_order_sod_error_statement():
+    w = wl.sod(n_ref=100)
+    w.params.recon = 2
+    rows = _runs(w, 30, 10)
+    _record("sod_recon2", rows)
+    first, last = rows[0], rows[-1]
+    for q in ("rho", "U", "T"):
+        assert first["fp32_vs_oracle"][q]["L1"] <= 0.05 * max(first["noise_floor"][q]["L1"], 1e-12)
+        assert last["fp32_vs_oracle"][q]["L1"] <= 1.1 * last["noise_floor"][q]["L1"]
+
+
 def test_fp32_counts_match_on_first_step():
     """First step from a fresh state: no old particles, the same sampled particles; only the
     end cells of the rare particles that FP32 rounding moves across a face can differ."""

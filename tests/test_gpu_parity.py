@@ -166,6 +166,35 @@ def test_vehicle_full_size_first_step():
     run_pair(w, 1, name="vehicle-full", length=8.0, vscale=25.0)
 
 
+@pytest.mark.parametrize("recon", [1, 2])
+def test_second_order_sod(recon):
+    # second order: least-squares gradients with Barth-Jespersen (1) or Venkatakrishnan (2)
+    w = wl.sod(n_ref=100)
+    w.params.recon = recon
+    run_pair(w, 20, every=5, name=f"sod-recon{recon}")
+
+
+@pytest.mark.parametrize("recon", [1, 2])
+def test_second_order_farfield_tets(recon):
+    w = wl.free_stream_box(n=(4, 3, 3), U=(0.5, 0.4, -0.3), T=1.2, n_ref=60, kn=0.05, perturb=0.2, tets=True,
+                           jitter=0.15)
+    w.params.recon = recon
+    run_pair(w, 6, name=f"farfield-tet-recon{recon}")
+
+
+def test_second_order_cavity_diffuse_walls():
+    w = wl.cavity(n=8, n_ref=200, kn=0.01)
+    w.params.recon = 2
+    run_pair(w, 8, every=2, name="cavity-recon2")
+
+
+def test_second_order_specular_tets_near_continuum():
+    w = wl.closed_box(n=(4, 3, 3), n_ref=40, kn=1e-3, perturb=0.3, tets=True, jitter=0.15)
+    w.params.recon = 1
+    w.params.c2 = 1.0
+    run_pair(w, 8, name="tet-box-recon1")
+
+
 def test_deterministic_rerun_bitwise():
     w = wl.cavity(n=6, n_ref=300)
     a = _solver(w)
