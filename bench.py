@@ -94,6 +94,7 @@ def timed_run(w, precision, warmup, steps):
 
     s = Solver(w.mesh, w.params, precision=precision)
     s.init_state(w.W0)
+    cfg = s.launch_config()
     st0 = s.step(max(warmup, 1), stats=True)
     moved0 = st0["moved_total"]
     s.profile(True)
@@ -109,7 +110,7 @@ def timed_run(w, precision, warmup, steps):
     s.close()
     del s
     torch.cuda.empty_cache()
-    return t1 - t0, st1["moved_total"] - moved0, prof
+    return t1 - t0, st1["moved_total"] - moved0, prof, cfg
 
 
 def stated_fp32_error():
@@ -144,7 +145,7 @@ def batched_run(steps, warmup, plain_steps):
     # capacity: N_sam = 2 ceil(r) adds at least two particles per cell and step wherever the
     # hydro wave has a collisionless part, and rarefied cells lose only their collided share,
     # so counts drift up by up to two per cell and step on top of about N_ref
-    total_steps = warmup + 10 * 2 + 1 + steps
+    total_steps = warmup + 13 * 2 + 1 + steps
     caps = [int(1.3 * w.params.n_ref * w.mesh.n_cells + 2.2 * total_steps * w.mesh.n_cells) + 65536 for w in ws]
     stream = torch.cuda.Stream()
     s = Solver(meshes, params, capacity=caps, precision=1, stream=stream)
@@ -171,7 +172,7 @@ def batched_run(steps, warmup, plain_steps):
            "ms_per_step": el / steps * 1e3, "cell_steps_per_s": nc * steps / el, "steps": steps,
            "warmup_and_tuning_steps": int(done_steps - steps),
            "instances": len(ws), "cells": nc, "particles_per_step": int(moves / steps),
-           "launch_config": {"stream_bs": cfg[0], "sample_wpb": cfg[1], "flux_bs": cfg[2]},
+           "launch_config": {"stream_bs": cfg[0], "stream_ilp": cfg[1], "sample_wpb": cfg[2], "flux_bs": cfg[3]},
            "graph_replay": True}
     # FP64 plain, one instance after the other, each on the current stream with eager launches
     pm, pt, pc = 0, 0.0, 0
@@ -197,14 +198,15 @@ def batched_run(steps, warmup, plain_steps):
     return out
 
 
-def roofline(prof, moves_per_launch, bytes_per_move, rtype):
+def roofline(prof, moves_per_launch, bytes_per_move, rtype, cfg):
     """Roofline position of the dominant kernel (the slot with the largest summed time): the
-    algorithmic bytes of the particle moves one launch performs over its average duration."""
+    algorithmic bytes of the particle moves one launch performs over its average duration.
+    cfg: the solver's launch shapes (they name the kernel instance that ran)."""
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_ms = dom_ms / max(dom_n, 1)
     achieved = bytes_per_move * moves_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"stream": f"k_stream<{rtype}>", "gather": f"k_gather<{rtype}>"}.get(dom, dom)
+    kname = {"stream": f"k_stream<{rtype}, {cfg[0]}, false, {cfg[1]}>", "gather": f"k_gather<{rtype}>"}.get(dom, dom)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
             "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
@@ -236,10 +238,10 @@ def main():
 
     w = wl.cavity()
     nc = w.mesh.n_cells
-    el, moves, prof = timed_run(w, 0, args.warmup, args.steps)
+    el, moves, prof, cfg = timed_run(w, 0, args.warmup, args.steps)
     value = moves / el
     moves_per_launch = moves / args.steps
-    roof = roofline(prof, moves_per_launch, BYTES_PER_MOVE_FP64, "double")
+    roof = roofline(prof, moves_per_launch, BYTES_PER_MOVE_FP64, "double", cfg)
     out = {
         "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
         "value": value,
@@ -261,12 +263,12 @@ def main():
         "roofline": roof,
     }
     if not args.no_fp32:
-        el32, moves32, prof32 = timed_run(w, 1, args.warmup, args.steps)
+        el32, moves32, prof32, cfg32 = timed_run(w, 1, args.warmup, args.steps)
         out["fp32_form"] = {"value": moves32 / el32, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
                             "ms_per_step": el32 / args.steps * 1e3, "cell_steps_per_s": nc * args.steps / el32,
                             "speedup_vs_fp64_plain": (moves32 / el32) / value,
                             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
-                            "roofline": roofline(prof32, moves32 / args.steps, BYTES_PER_MOVE_FP32, "float"),
+                            "roofline": roofline(prof32, moves32 / args.steps, BYTES_PER_MOVE_FP32, "float", cfg32),
                             "stated_error": stated_fp32_error()}
     if not args.no_batched:
         out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)

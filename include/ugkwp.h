@@ -184,17 +184,17 @@ int32_t ugkwp_geometry(ugkwp_ctx *ctx, double *vol, double *xc, double *dS);
  * on, the per-kernel event timing of ugkwp_profile_enable is not recorded. */
 int32_t ugkwp_graph_enable(ugkwp_ctx *ctx, int32_t on);
 
-/* Launch shapes of the tunable kernels, cfg[3] = {k_stream block size (128, 256, 512),
- * k_sample cells (waves) per block (1, 2, 4, 8), k_flux block size (64, 128, 256)}.  Every
- * shape gives bit-identical results. */
+/* Launch shapes of the tunable kernels, cfg[4] = {k_stream block size (128, 256, 512),
+ * k_stream particles per thread (1, 2), k_sample cells (waves) per block (1, 2, 4, 8), k_flux
+ * block size (64, 128, 256)}.  Every shape gives bit-identical results. */
 int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg);
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
 
 /* Autotuner: one pass of coordinate search over the shapes above, each candidate timed with
  * hip events around its own kernel over steps_per_trial steps (after one untimed step).
  * The trial steps are real steps of the simulation (the shape does not change results): the
- * state advances by (steps_per_trial + 1) x 10 steps.  The fastest shapes are kept and
- * returned in cfg_out[3] (may be NULL).  Discards pending ugkwp_profile_read records. */
+ * state advances by (steps_per_trial + 1) x 13 steps.  The fastest shapes are kept and
+ * returned in cfg_out[4] (may be NULL).  Discards pending ugkwp_profile_read records. */
 int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out);
 
 /* Measurement support.  While enabled, each group of kernel launches of ugkwp_step is

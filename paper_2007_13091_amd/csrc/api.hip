@@ -354,6 +354,9 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     }
     ctx->p = p[0];
     ctx->ps.assign(p, p + n_inst);
+    // two particles per thread in the FP32 form's transport (measured faster there; the FP64
+    // kernel loses an occupancy level to it)
+    if (p[0].precision == 1) ctx->cfg.stream_ilp = 2;
     ctx->stream = (hipStream_t)hip_stream;
     ctx->prof.s = ctx->stream;
     ctx->ws = (char *)dev_workspace;
@@ -668,8 +671,9 @@ int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg) {
     if (!ctx || !cfg) return fail(ctx, UGKWP_E_ARG, "bad argument");
     ugkwp::LaunchCfg c;
     c.stream_bs = cfg[0];
-    c.sample_wpb = cfg[1];
-    c.flux_bs = cfg[2];
+    c.stream_ilp = cfg[1];
+    c.sample_wpb = cfg[2];
+    c.flux_bs = cfg[3];
     if (!ugkwp::launch_cfg_valid(c)) return fail(ctx, UGKWP_E_ARG, "launch configuration out of range");
     ctx->cfg = c;
     ctx->drop_graphs();
@@ -679,8 +683,9 @@ int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg) {
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg) {
     if (!ctx || !cfg) return fail(nullptr, UGKWP_E_ARG, "bad argument");
     cfg[0] = ctx->cfg.stream_bs;
-    cfg[1] = ctx->cfg.sample_wpb;
-    cfg[2] = ctx->cfg.flux_bs;
+    cfg[1] = ctx->cfg.stream_ilp;
+    cfg[2] = ctx->cfg.sample_wpb;
+    cfg[3] = ctx->cfg.flux_bs;
     return UGKWP_OK;
 }
 
@@ -703,11 +708,13 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     };
     std::vector<Dim> dims(3);
     dims[0].slot = ugkwp::kSlotStream;
-    for (int b : {128, 256, 512}) {
-        ugkwp::LaunchCfg c;
-        c.stream_bs = b;
-        dims[0].cand.push_back(c);
-    }
+    for (int ilp : {1, 2})
+        for (int b : {128, 256, 512}) {
+            ugkwp::LaunchCfg c;
+            c.stream_bs = b;
+            c.stream_ilp = ilp;
+            dims[0].cand.push_back(c);
+        }
     dims[1].slot = ugkwp::kSlotSample;
     for (int w : {1, 2, 4, 8}) {
         ugkwp::LaunchCfg c;
@@ -728,6 +735,7 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
             ugkwp::LaunchCfg c = best;
             if (d == 0) {
                 c.stream_bs = c0.stream_bs;
+                c.stream_ilp = c0.stream_ilp;
             } else if (d == 1) {
                 c.sample_wpb = c0.sample_wpb;
             } else {

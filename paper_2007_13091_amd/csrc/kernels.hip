@@ -1493,14 +1493,66 @@ struct StateOf<float> {
     using T = StateF32;
 };
 
-// One thread per particle; blocks past the live particles exit at once.  The free-flight
-// time of an old particle is t_f = -tau ln eta with tau of its start cell; it collides iff
-// t_f < dt.  Since t_f < dt <=> eta > exp(-dt/tau), eta below exp(-dt/tau) by a relative
-// margin decides the comparison without the logarithm (the same decision as the formula,
-// which is evaluated near the threshold and for every collided particle).
+// Free flight and transport of the particles, ILP particles per thread (their loads are all
+// issued before the first is tracked, so that each thread keeps ILP memory chains in flight);
+// blocks past the live particles exit at once.  The free-flight time of an old particle is
+// t_f = -tau ln eta with tau of its start cell; it collides iff t_f < dt.  Since t_f < dt <=>
+// eta > exp(-dt/tau), eta below exp(-dt/tau) by a relative margin decides the comparison
+// without the logarithm (the same decision as the formula, which is evaluated near the
+// threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
 // (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
-template <typename R, int BS, bool MULTI>
+template <typename R, bool MULTI>
+__device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, long long i, long long n_old,
+                                           long long n_smp, int c, R x[3], R u[3], uint64_t uid,
+                                           const typename StateOf<R>::T &keep, R e, R tauc,
+                                           unsigned long long &nx_, unsigned long long &nw_, bool &lost) {
+    const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
+    int c0 = c;
+    // a single instance reads its values through uniform addresses
+    const int inst = MULTI ? D.cinst[c] : 0;
+    const InstP &P = D.ip[inst];
+    const double dt64 = D.is[inst].dt;
+    const R dt = (R)dt64;
+    const StepCtx sx{P.seed, D.is[inst].step, inst, P.max_cross};
+    R ts = dt;
+    int entry0 = -1;
+    bool collided = false;
+    if (i >= n_smp) {
+        // entering through a far-field face: from its entry time to the end of the step,
+        // starting on that face; never a stayer (it did not start in a cell)
+        const U4 r = draw(sx.seed, uid, sx.step, kTagInject, 0, inst);
+        ts = (R)(unif<double>(r.v[3]) * dt64);
+        entry0 = D.bflf[P.bf0 + (long long)((uid >> 20) & 0xFFFFFFULL)];
+        c0 = -1;
+    } else if (i < n_old) {
+        const U4 r = draw(sx.seed, uid, sx.step, kTagTF, 0, inst);
+        const R eta = unif<R>(r.v[0]);
+        if (!(eta < e * lmargin)) {
+            const R tf = -tauc * log(eta);
+            if (tf < dt) {
+                ts = tf;
+                collided = true;
+            }
+        }
+    }
+    int nx = 0, nw = 0;
+    const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
+    nx_ += (unsigned long long)nx;
+    nw_ += (unsigned long long)nw;
+    store_state(pa, i, x, u, keep);
+    pa.cell[i] = c;
+    int key = -1;
+    bool stay = false;
+    if (rc != 1) {
+        lost = lost || rc < 0;
+        key = collided ? D.nc + c : c;
+        stay = !collided && c == c0;
+    }
+    D.key[i] = stay ? (key | kStayBit) : key;
+}
+
+template <typename R, int BS, bool MULTI, int ILP>
 __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     constexpr int NW = BS / 64;
     __shared__ unsigned long long red[2][NW];
@@ -1508,64 +1560,36 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     const long long n_old = sc->n_old;
     const long long n_smp = n_old + sc->n_new;
     const long long n_tot = n_smp + sc->n_inj;
-    const long long i0 = (long long)blockIdx.x * BS;
+    const long long i0 = (long long)blockIdx.x * (BS * ILP);
     if (i0 >= n_tot) return;
-    const long long i = i0 + threadIdx.x;
     const Particles pa = D.pa[buf];
-    const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     unsigned long long nx_ = 0, nw_ = 0;
     bool lost = false;
-    if (i < n_tot) {
-        int c = pa.cell[i];
-        int c0 = c;
-        R x[3], u[3];
-        uint64_t uid;
-        typename StateOf<R>::T keep;
-        load_state(pa, i, x, u, uid, keep);
-        // start-cell data, loaded before the generator runs
-        const R e = (R)D.ec[c], tauc = (R)D.tau[c];
-        // a single instance reads its values through uniform addresses
-        const int inst = MULTI ? D.cinst[c] : 0;
-        const InstP &P = D.ip[inst];
-        const double dt64 = D.is[inst].dt;
-        const R dt = (R)dt64;
-        const StepCtx sx{P.seed, D.is[inst].step, inst, P.max_cross};
-        R ts = dt;
-        int entry0 = -1;
-        bool collided = false;
-        if (i >= n_smp) {
-            // entering through a far-field face: from its entry time to the end of the step,
-            // starting on that face; never a stayer (it did not start in a cell)
-            const U4 r = draw(sx.seed, uid, sx.step, kTagInject, 0, inst);
-            ts = (R)(unif<double>(r.v[3]) * dt64);
-            entry0 = D.bflf[P.bf0 + (long long)((uid >> 20) & 0xFFFFFFULL)];
-            c0 = -1;
-        } else if (i < n_old) {
-            const U4 r = draw(sx.seed, uid, sx.step, kTagTF, 0, inst);
-            const R eta = unif<R>(r.v[0]);
-            if (!(eta < e * lmargin)) {
-                const R tf = -tauc * log(eta);
-                if (tf < dt) {
-                    ts = tf;
-                    collided = true;
-                }
-            }
+    long long ii[ILP];
+    int cc[ILP];
+    R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP];
+    uint64_t id[ILP];
+    typename StateOf<R>::T kk[ILP];
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+        ii[j] = i0 + j * BS + threadIdx.x;
+        if (ii[j] < n_tot) {
+            cc[j] = pa.cell[ii[j]];
+            load_state(pa, ii[j], xx[j], uu[j], id[j], kk[j]);
         }
-        int nx = 0, nw = 0;
-        const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
-        nx_ = (unsigned long long)nx;
-        nw_ = (unsigned long long)nw;
-        store_state(pa, i, x, u, keep);
-        pa.cell[i] = c;
-        int key = -1;
-        bool stay = false;
-        if (rc != 1) {
-            lost = rc < 0;
-            key = collided ? D.nc + c : c;
-            stay = !collided && c == c0;
-        }
-        D.key[i] = stay ? (key | kStayBit) : key;
     }
+    // start-cell data, loaded before the generators run
+#pragma unroll
+    for (int j = 0; j < ILP; ++j)
+        if (ii[j] < n_tot) {
+            ee[j] = (R)D.ec[cc[j]];
+            tt[j] = (R)D.tau[cc[j]];
+        }
+#pragma unroll
+    for (int j = 0; j < ILP; ++j)
+        if (ii[j] < n_tot)
+            stream_one<R, MULTI>(D, pa, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], kk[j], ee[j], tt[j], nx_, nw_,
+                                 lost);
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
     nw_ = wave_sum_u64(nw_);
@@ -2020,17 +2044,25 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s) {
 }
 
 namespace {
+template <typename R, bool MULTI, int ILP>
+void launch_stream_i(const Dev &D, int buf, int bs, hipStream_t s) {
+    // ILP particles per thread over the capacity; blocks past the live particles exit at once
+    const long long per = (long long)bs * ILP;
+    const unsigned g = (unsigned)((D.cap + per - 1) / per);
+    if (bs == 128)
+        k_stream<R, 128, MULTI, ILP><<<g, 128, 0, s>>>(D, buf);
+    else if (bs == 512)
+        k_stream<R, 512, MULTI, ILP><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_stream<R, 256, MULTI, ILP><<<g, 256, 0, s>>>(D, buf);
+}
+
 template <typename R, bool MULTI>
 void launch_stream_t(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
-    // one thread per particle over the capacity; blocks past the live particles exit at once
-    const int bs = cfg.stream_bs;
-    const unsigned g = (unsigned)((D.cap + bs - 1) / bs);
-    if (bs == 128)
-        k_stream<R, 128, MULTI><<<g, 128, 0, s>>>(D, buf);
-    else if (bs == 512)
-        k_stream<R, 512, MULTI><<<g, 512, 0, s>>>(D, buf);
+    if (cfg.stream_ilp == 2)
+        launch_stream_i<R, MULTI, 2>(D, buf, cfg.stream_bs, s);
     else
-        k_stream<R, 256, MULTI><<<g, 256, 0, s>>>(D, buf);
+        launch_stream_i<R, MULTI, 1>(D, buf, cfg.stream_bs, s);
 }
 
 template <typename R>
@@ -2081,7 +2113,8 @@ void launch_flux(const Dev &D, const LaunchCfg &cfg, hipStream_t s) {
 }  // namespace
 
 bool launch_cfg_valid(const LaunchCfg &c) {
-    const bool sb = c.stream_bs == 128 || c.stream_bs == 256 || c.stream_bs == 512;
+    const bool sb = (c.stream_bs == 128 || c.stream_bs == 256 || c.stream_bs == 512) &&
+                    (c.stream_ilp == 1 || c.stream_ilp == 2);
     const bool sw = c.sample_wpb == 1 || c.sample_wpb == 2 || c.sample_wpb == 4 || c.sample_wpb == 8;
     const bool fb = c.flux_bs == 64 || c.flux_bs == 128 || c.flux_bs == 256;
     return sb && sw && fb;

@@ -36,6 +36,7 @@ struct Prof {
 // launch shapes of the kernels whose shape is tunable; every choice gives the same results
 struct LaunchCfg {
     int stream_bs = 256;  // k_stream block size: 128, 256 or 512
+    int stream_ilp = 1;   // k_stream particles per thread: 1 or 2
     int sample_wpb = 4;   // k_sample waves (cells) per block: 1, 2, 4 or 8
     int flux_bs = 128;    // k_flux block size: 64, 128 or 256
 };

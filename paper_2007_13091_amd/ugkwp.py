@@ -250,17 +250,17 @@ class Solver:
         self._check(lib().ugkwp_graph_enable(self.h, 1 if on else 0))
 
     def launch_config(self, cfg=None):
-        """Get (and with cfg, first set) the launch shapes (stream_bs, sample_wpb, flux_bs)."""
+        """Get (and with cfg, first set) the launch shapes (stream_bs, stream_ilp, sample_wpb, flux_bs)."""
         if cfg is not None:
             a = np.ascontiguousarray(cfg, dtype=np.int32)
             self._check(lib().ugkwp_set_launch(self.h, _ptr(a, C.c_int32)))
-        out = np.zeros(3, dtype=np.int32)
+        out = np.zeros(4, dtype=np.int32)
         self._check(lib().ugkwp_get_launch(self.h, _ptr(out, C.c_int32)))
         return tuple(int(v) for v in out)
 
     def autotune(self, steps_per_trial=3):
         """Pick the fastest launch shapes on real steps (the state advances)."""
-        out = np.zeros(3, dtype=np.int32)
+        out = np.zeros(4, dtype=np.int32)
         self._check(lib().ugkwp_autotune(self.h, int(steps_per_trial), _ptr(out, C.c_int32)))
         return tuple(int(v) for v in out)
 

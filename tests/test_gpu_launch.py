@@ -29,7 +29,7 @@ def _same(a, b, what):
         np.testing.assert_array_equal(a[1][k], b[1][k], err_msg=f"{what}: particles {k}")
 
 
-SHAPES = [(128, 1, 64), (512, 8, 256), (256, 2, 128), (256, 4, 64), (512, 1, 256), (128, 8, 128)]
+SHAPES = [(128, 1, 1, 64), (512, 2, 8, 256), (256, 2, 2, 128), (256, 1, 4, 64), (512, 1, 1, 256), (128, 2, 8, 128)]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -106,7 +106,7 @@ def test_autotuned_run_equals_plain_run():
     cfg = a.autotune(steps_per_trial=1)
     _say("autotuned", cfg)
     n = a.instance_stats(0)["step"]
-    assert n == 2 * 10
+    assert n == 2 * 13
     b.step(n)
     _same(_state(a), _state(b), "autotuned vs plain")
     assert a.launch_config() == cfg
