@@ -204,6 +204,8 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
  * and clears the sums.  Either output pointer may be NULL. */
 int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on);
 int32_t ugkwp_profile_read(ugkwp_ctx *ctx, int32_t n_slots, double *total_ms, int64_t *launches);
+/* Record only the slots whose bit is set in mask (default: all); fewer events, less overhead. */
+int32_t ugkwp_profile_mask(ugkwp_ctx *ctx, uint32_t mask);
 /* Name of a profiling slot ("" if out of range); static storage. */
 const char *ugkwp_profile_slot_name(int32_t slot);
 

@@ -23,6 +23,7 @@ namespace {
 struct EventProf : ugkwp::Prof {
     hipStream_t s = nullptr;
     bool on = false;
+    uint32_t mask = 0xFFFFFFFFu;  // slots recorded while on
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ugkwp::kNumSlots];
     hipEvent_t open[ugkwp::kNumSlots] = {};
@@ -37,7 +38,7 @@ struct EventProf : ugkwp::Prof {
         return e;
     }
     void begin(int slot) override {
-        if (!on) return;
+        if (!on || !((mask >> slot) & 1u)) return;
         hipEvent_t e = get();
         if (e) (void)hipEventRecord(e, s);
         open[slot] = e;
@@ -696,9 +697,11 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     // one pass of coordinate search: each tunable kernel is timed under each of its shapes
     // (hip events around that kernel only) over real steps, holding the others fixed
     const bool prof_was = ctx->prof.on;
+    const uint32_t mask_was = ctx->prof.mask;
     const bool graph_was = ctx->graph_on;
     ctx->graph_on = false;
     ctx->prof.on = true;
+    ctx->prof.mask = 0xFFFFFFFFu;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->prof.drain(nullptr, nullptr, 0);
     ugkwp::LaunchCfg best = ctx->cfg;
@@ -767,6 +770,7 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     ctx->drop_graphs();
     ctx->graph_on = graph_was;
     ctx->prof.on = prof_was;
+    ctx->prof.mask = mask_was;
     if (cfg_out) (void)ugkwp_get_launch(ctx, cfg_out);
     return st;
 }
@@ -774,6 +778,12 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
 int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on) {
     if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
     ctx->prof.on = on != 0;
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_profile_mask(ugkwp_ctx *ctx, uint32_t mask) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    ctx->prof.mask = mask;
     return UGKWP_OK;
 }
 

@@ -23,7 +23,7 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
-           "ugkwp_get_launch", "ugkwp_autotune")
+           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask")
 N_PROFILE_SLOTS = 11
 
 
@@ -79,6 +79,8 @@ def lib():
         L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), C.c_int32, P(UgkwpParams), vp, C.c_size_t, vp]
         L.ugkwp_instance_stats.restype = C.c_int32
         L.ugkwp_instance_stats.argtypes = [vp, C.c_int32, P(UgkwpStats)]
+        L.ugkwp_profile_mask.restype = C.c_int32
+        L.ugkwp_profile_mask.argtypes = [vp, C.c_uint32]
         L.ugkwp_graph_enable.restype = C.c_int32
         L.ugkwp_graph_enable.argtypes = [vp, C.c_int32]
         L.ugkwp_set_launch.restype = C.c_int32
@@ -282,8 +284,15 @@ class Solver:
                                                  _ptr(m, C.c_double), _ptr(c, C.c_int32), _ptr(uid, C.c_uint64)))
         return dict(x=x, u=u, m=m, cell=c, uid=uid)
 
-    def profile(self, on=True):
-        """Bracket each kernel group of a step with hip events (measurement support)."""
+    def profile(self, on=True, slots=None):
+        """Bracket each kernel group of a step with hip events (measurement support); slots:
+        names of the groups to time (default all)."""
+        if slots is None:
+            mask = 0xFFFFFFFF
+        else:
+            names = [lib().ugkwp_profile_slot_name(k).decode() for k in range(N_PROFILE_SLOTS)]
+            mask = sum(1 << names.index(n) for n in slots)
+        self._check(lib().ugkwp_profile_mask(self.h, mask))
         self._check(lib().ugkwp_profile_enable(self.h, 1 if on else 0))
 
     def profile_read(self):

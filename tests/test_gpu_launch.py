@@ -110,3 +110,31 @@ def test_autotuned_run_equals_plain_run():
     b.step(n)
     _same(_state(a), _state(b), "autotuned vs plain")
     assert a.launch_config() == cfg
+
+
+def test_profile_events_change_nothing_and_mask_selects_slots():
+    """Timing every kernel group, or one of them, leaves the results bit-identical to an
+    untimed run; a mask times only the named group."""
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.cavity(n=8, n_ref=200)
+    runs = []
+    for slots in ("off", None, ["stream"]):
+        _say("profile slots", slots)
+        s = Solver(w.mesh, w.params)
+        s.init_state(w.W0)
+        if slots != "off":
+            s.profile(True, slots=slots)
+        s.step(4)
+        if slots != "off":
+            prof = s.profile_read()
+            timed = {k for k, v in prof.items() if v[1] > 0}
+            if slots is None:
+                assert {"stream", "gather", "flux", "sample"} <= timed
+                assert all(v[1] == 4 for k, v in prof.items() if k in ("stream", "gather"))
+            else:
+                assert timed == {"stream"} and prof["stream"][1] == 4 and prof["stream"][0] > 0
+        runs.append(_state(s))
+        s.close()
+    _same(runs[1], runs[0], "all groups timed")
+    _same(runs[2], runs[0], "stream timed")
