@@ -173,9 +173,7 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     D.nsam = C.take<long long>(nc);
     D.samoff = C.take<long long>(nc + 1);
     D.scan64 = C.take<long long>((size_t)ugkwp::scan_partials_needed((long long)(nc > nff ? nc : nff)));
-    D.cnt = C.take<int32_t>(2 * nc);
     D.off = C.take<int32_t>(2 * nc + 1);
-    D.cursor = C.take<int32_t>(2 * nc);
     D.scan32 = C.take<int32_t>((size_t)ugkwp::scan_partials_needed(2 * (long long)nc));
     D.spart = C.take<unsigned long long>(128);
     D.cnt64 = C.take<unsigned long long>(2 * nc);

@@ -141,9 +141,7 @@ struct Dev {
     long long *scan64;      // scan partials
     long long *ninj;        // [nff] particles entering through each far-field face
     long long *injoff;      // [nff+1]
-    int32_t *cnt;           // [2nc] movers (or collided) per bucket
     int32_t *off;           // [2nc+1]
-    int32_t *cursor;        // [2nc]
     int32_t *scan32;        // scan partials
     unsigned long long *spart; // [2][64] crossings and wall hits, spread over 64 slots
     unsigned long long *cnt64; // [2nc] per bucket: stayers << 32 | movers (or collided)

@@ -29,6 +29,8 @@ namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
+constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
+constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
 
 // ---------------------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11); counter = (uid, step, tag<<32|sub, 0),
@@ -288,32 +290,6 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-// Bucket counting for k_stream: lanes are grouped by key with ballots only; then every
-// group leader issues its 64-bit atomic in the same instruction (movers in the low word,
-// stayers in the high word), so the wave waits for one round trip instead of one per key.
-// Movers get their slot in the bucket.  Must be called by the whole wave.
-__device__ __forceinline__ int agg_count(unsigned long long *cnt, int key, bool stay) {
-    const int lane = lane_id();
-    const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    const unsigned long long stays = __ballot(stay);
-    unsigned long long todo = __ballot(key >= 0);
-    unsigned long long mine = 0;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lkey = __shfl(key, leader);
-        const unsigned long long same = __ballot(key == lkey) & todo;
-        if (key == lkey) mine = same;
-        todo &= ~same;
-    }
-    const int leader = mine ? __ffsll((long long)mine) - 1 : lane;
-    const unsigned long long movers = mine & ~stays;
-    unsigned long long base = 0;
-    if (mine && lane == leader)
-        base = atomicAdd(&cnt[key], ((unsigned long long)__popcll(mine & stays) << 32) | __popcll(movers));
-    base = __shfl(base, leader);
-    return (key >= 0 && !stay) ? (int)(base & 0xFFFFFFFFULL) + (int)__popcll(movers & below) : -1;
-}
-
 // ---------------------------------------------------------------------------------------
 // S0: primitives, tau, min Omega / Lambda
 // ---------------------------------------------------------------------------------------
@@ -324,6 +300,8 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
         Scalars *s = D.sc;
         s->n_sampled = 0;
     }
+    // partial sums of crossings and wall hits of this step's transport
+    if (blockIdx.x == 0 && threadIdx.x < 128) D.spart[threadIdx.x] = 0ULL;
     double r = INFINITY;
     int inst = 0;
     if (c < D.nc) {
@@ -375,6 +353,9 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
 __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= D.nc) return;
+    // bucket counters of this step's transport (survivors ending in c, collided ending in c)
+    D.cnt64[c] = 0ULL;
+    D.cnt64[D.nc + c] = 0ULL;
     const int inst = inst_of(D, c);
     const InstP &P = D.ip[inst];
     const double dt = P.cfl * __longlong_as_double((long long)D.is[inst].dtmin_bits);
@@ -413,16 +394,6 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
         }
     }
     D.nsam[c] = ns;
-}
-
-// bucket sizes: movers / collided (low word) plus stayers (high word)
-__global__ void k_bucket_total(Dev D) {
-    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < 2LL * D.nc) {
-        const unsigned long long v = D.cnt64[k];
-        D.cnt[k] = (int32_t)(v & 0xFFFFFFFFULL);                    // movers / collided
-        D.cursor[k] = (int32_t)(v & 0xFFFFFFFFULL) + (int32_t)(v >> 32);  // bucket size
-    }
 }
 
 // capacity check of the step: old + sampled + entering must fit
@@ -1045,14 +1016,25 @@ __device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
 }
 
 // ---------------------------------------------------------------------------------------
-// S3: hydro particles, one wave per cell.  Pair j shares X ~ N(0, I) (Box-Muller on the draw
-// keyed by the even partner's id); partners get U + s sqrt(T) X and U - s sqrt(T) X (s: the
-// cell's energy-exact factor) and their own
+// S3: hydro particles, one wave per cell, lane l takes the pairs l, l + 64, ...  Pair p
+// shares X ~ N(0, I) (Box-Muller on the draw keyed by the even partner's id); partners get
+// U + s sqrt(T) X and U - s sqrt(T) X (s: the cell's energy-exact factor) and their own
 // uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
+// The first pass sums |X|^2 for s and keeps each lane's first X for the second.
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void pair_normal(uint64_t seed, uint64_t puid, long long step, int inst, R X[3]) {
+    const R two_pi = (R)2 * (R)kPi;
+    const U4 rv = draw(seed, puid, step, kTagVel, 0, inst);
+    const R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
+    const R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
+    X[0] = r1 * cos(two_pi * e1);
+    X[1] = r1 * sin(two_pi * e1);
+    X[2] = r2 * cos(two_pi * e3);
+}
 template <typename R, int WPB>
-__global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     const int c = blockIdx.x * WPB + wave;
@@ -1073,22 +1055,27 @@ __global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
         const R U[3] = {(R)(m0 / rho), (R)(m1 / rho), (R)(m2 / rho)};
         const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
         R sT = sqrt(T);
-        const R one = (R)1, two_pi = (R)2 * (R)kPi;
+        const R one = (R)1;
+        const long long npair = ns / 2;  // ns is even
+        R Xfirst[3] = {(R)0, (R)0, (R)0};
         {
             // energy-exact pairs: the pairs carry the momentum exactly; one factor on every
             // thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2), makes the energy
             // exact too (a first pass over the pairs' normal draws, summed in FP64)
             double sx2 = 0.0;
-            for (long long j = 2 * lane; j < ns; j += 2 * kWave) {
-                const U4 rv = draw(seed, make_uid(step, cl, j), step, kTagVel, 0, inst);
-                const R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
-                const R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
-                const double X0 = (double)(r1 * cos(two_pi * e1)), X1 = (double)(r1 * sin(two_pi * e1)),
-                             X2 = (double)(r2 * cos(two_pi * e3));
+            for (long long q = lane; q < npair; q += kWave) {
+                R X[3];
+                pair_normal<R>(seed, make_uid(step, cl, 2 * q), step, inst, X);
+                if (q == lane) {
+                    Xfirst[0] = X[0];
+                    Xfirst[1] = X[1];
+                    Xfirst[2] = X[2];
+                }
+                const double X0 = (double)X[0], X1 = (double)X[1], X2 = (double)X[2];
                 sx2 += X0 * X0 + X1 * X1 + X2 * X2;
             }
             sx2 = wave_sum(sx2);
-            sT = (R)((double)sT * sqrt(3.0 * (double)(ns / 2) / sx2));
+            sT = (R)((double)sT * sqrt(3.0 * (double)npair / sx2));
         }
         const double vol = D.vol[c];
         const R msam = (R)(D.ec[c] * D.rhoh[c] * vol / (double)ns);
@@ -1097,41 +1084,48 @@ __global__ void __launch_bounds__(WPB * 64) k_sample(Dev D, int buf) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
         const bool tet = D.ctype[c] == 4;
-        for (long long k = lane; k < ns; k += kWave) {
-            const long long i = base + k;
-            const uint64_t uid = make_uid(step, cl, k);
-            const uint64_t puid = make_uid(step, cl, k & ~1LL);
-            U4 rv = draw(seed, puid, step, kTagVel, 0, inst);
-            R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
-            R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
-            R X[3] = {r1 * cos(two_pi * e1), r1 * sin(two_pi * e1), r2 * cos(two_pi * e3)};
-            const R sg = (k & 1) ? -one : one;
-            R u[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
-            U4 rp = draw(seed, uid, step, kTagPos, 0, inst);
-            R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
-            if (tet) {
-                if (s + t > one) {
-                    s = one - s;
-                    t = one - t;
-                }
-                if (t + w > one) {
-                    R tmp = w;
-                    w = one - s - t;
-                    t = one - tmp;
-                } else if (s + t + w > one) {
-                    R tmp = w;
-                    w = s + t + w - one;
-                    s = one - t - tmp;
-                }
+        for (long long q = lane; q < npair; q += kWave) {
+            R X[3];
+            if (q == lane) {
+                X[0] = Xfirst[0];
+                X[1] = Xfirst[1];
+                X[2] = Xfirst[2];
+            } else {
+                pair_normal<R>(seed, make_uid(step, cl, 2 * q), step, inst, X);
             }
-            R x[3];
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                const long long k = 2 * q + h;
+                const long long i = base + k;
+                const uint64_t uid = make_uid(step, cl, k);
+                const R sg = h ? -one : one;
+                R u[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
-            store_new(pa, i, x, u, msam, uid);
-            pa.cell[i] = c;
-            add_phi<R>(acc, msam, u);
+                for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
+                U4 rp = draw(seed, uid, step, kTagPos, 0, inst);
+                R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
+                if (tet) {
+                    if (s + t > one) {
+                        s = one - s;
+                        t = one - t;
+                    }
+                    if (t + w > one) {
+                        R tmp = w;
+                        w = one - s - t;
+                        t = one - tmp;
+                    } else if (s + t + w > one) {
+                        R tmp = w;
+                        w = s + t + w - one;
+                        s = one - t - tmp;
+                    }
+                }
+                R x[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+                store_new(pa, i, x, u, msam, uid);
+                pa.cell[i] = c;
+                add_phi<R>(acc, msam, u);
+            }
         }
     }
 #pragma unroll
@@ -1437,17 +1431,13 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, 
     }
 }
 
-// load / store of the transported state of particle i
-struct StateF64 {
-    double2 r3;
-};
-struct StateF32 {};
-__device__ __forceinline__ void load_state(const Particles &pa, long long i, double x[3], double u[3], uint64_t &uid,
-                                           StateF64 &keep) {
+// load / store of the transported state of particle i: position and velocity change in
+// place, mass and id (the last 16 bytes of an FP64 record, the last 8 of an FP32 one) are
+// read for the id and never rewritten
+__device__ __forceinline__ void load_state(const Particles &pa, long long i, double x[3], double u[3], uint64_t &uid) {
     const double2 *rp = reinterpret_cast<const double2 *>(pa.rec + i);
     const double2 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-    keep.r3 = rp[3];
-    uid = (uint64_t)__double_as_longlong(keep.r3.y);
+    uid = (uint64_t)__double_as_longlong(reinterpret_cast<const double *>(rp + 3)[1]);
     x[0] = r0.x;
     x[1] = r0.y;
     x[2] = r1.x;
@@ -1455,16 +1445,13 @@ __device__ __forceinline__ void load_state(const Particles &pa, long long i, dou
     u[1] = r2.x;
     u[2] = r2.y;
 }
-__device__ __forceinline__ void store_state(const Particles &pa, long long i, const double x[3], const double u[3],
-                                            const StateF64 &keep) {
+__device__ __forceinline__ void store_state(const Particles &pa, long long i, const double x[3], const double u[3]) {
     double2 *rp = reinterpret_cast<double2 *>(pa.rec + i);
     rp[0] = make_double2(x[0], x[1]);
     rp[1] = make_double2(x[2], u[0]);
     rp[2] = make_double2(u[1], u[2]);
-    rp[3] = keep.r3;
 }
-__device__ __forceinline__ void load_state(const Particles &pa, long long i, float x[3], float u[3], uint64_t &uid,
-                                           StateF32 &) {
+__device__ __forceinline__ void load_state(const Particles &pa, long long i, float x[3], float u[3], uint64_t &uid) {
     const float4 *rp = reinterpret_cast<const float4 *>(pa.rec32 + i);
     const float4 a = rp[0], b = rp[1];
     x[0] = a.x;
@@ -1475,23 +1462,12 @@ __device__ __forceinline__ void load_state(const Particles &pa, long long i, flo
     u[2] = b.y;
     uid = (uint64_t)__float_as_uint(b.z) | ((uint64_t)__float_as_uint(b.w) << 32);
 }
-__device__ __forceinline__ void store_state(const Particles &pa, long long i, const float x[3], const float u[3],
-                                            const StateF32 &) {
+__device__ __forceinline__ void store_state(const Particles &pa, long long i, const float x[3], const float u[3]) {
     float4 *rp = reinterpret_cast<float4 *>(pa.rec32 + i);
     rp[0] = make_float4(x[0], x[1], x[2], u[0]);
     float2 *q = reinterpret_cast<float2 *>(rp + 1);
     q[0] = make_float2(u[1], u[2]);
 }
-template <typename R>
-struct StateOf;
-template <>
-struct StateOf<double> {
-    using T = StateF64;
-};
-template <>
-struct StateOf<float> {
-    using T = StateF32;
-};
 
 // Free flight and transport of the particles, ILP particles per thread (their loads are all
 // issued before the first is tracked, so that each thread keeps ILP memory chains in flight);
@@ -1505,7 +1481,7 @@ struct StateOf<float> {
 template <typename R, bool MULTI>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, long long i, long long n_old,
                                            long long n_smp, int c, R x[3], R u[3], uint64_t uid,
-                                           const typename StateOf<R>::T &keep, R e, R tauc,
+                                           R e, R tauc,
                                            unsigned long long &nx_, unsigned long long &nw_, bool &lost) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
@@ -1540,7 +1516,7 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, lo
     const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
     nx_ += (unsigned long long)nx;
     nw_ += (unsigned long long)nw;
-    store_state(pa, i, x, u, keep);
+    store_state(pa, i, x, u);
     pa.cell[i] = c;
     int key = -1;
     bool stay = false;
@@ -1569,13 +1545,12 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     int cc[ILP];
     R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP];
     uint64_t id[ILP];
-    typename StateOf<R>::T kk[ILP];
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
         ii[j] = i0 + j * BS + threadIdx.x;
         if (ii[j] < n_tot) {
             cc[j] = pa.cell[ii[j]];
-            load_state(pa, ii[j], xx[j], uu[j], id[j], kk[j]);
+            load_state(pa, ii[j], xx[j], uu[j], id[j]);
         }
     }
     // start-cell data, loaded before the generators run
@@ -1588,7 +1563,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
 #pragma unroll
     for (int j = 0; j < ILP; ++j)
         if (ii[j] < n_tot)
-            stream_one<R, MULTI>(D, pa, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], kk[j], ee[j], tt[j], nx_, nw_,
+            stream_one<R, MULTI>(D, pa, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_, nw_,
                                  lost);
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
@@ -1612,33 +1587,123 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     }
 }
 
+// Lanes of a wave grouped by key with ballots only: mine = the lanes that share this lane's
+// key (0 for key < 0).  Must be called by the whole wave.
+__device__ __forceinline__ unsigned long long key_group(int key) {
+    unsigned long long todo = __ballot(key >= 0);
+    unsigned long long mine = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lkey = __shfl(key, leader);
+        const unsigned long long same = __ballot(key == lkey) & todo;
+        if (key == lkey) mine = same;
+        todo &= ~same;
+    }
+    return mine;
+}
+
 // bucket counts: stayers are only counted, movers and collided particles get their slot in
-// the bucket (the order of those slots is fixed later by sorting in the gather)
+// the bucket (the order of those slots is fixed later by sorting in the gather).  A block
+// takes 4 waves x kCountChunks runs of 64 consecutive particles.  In each run the lanes are
+// grouped by key with ballots; each group's leader adds (stayers << 32 | movers) to the
+// key's entry of an LDS hash table (open addressing, as many entries as the block has
+// particles, so it cannot fill up), whose returned value places the group's movers within
+// the block.  Then one global 64-bit atomic per distinct key of the block adds the block's
+// count to the bucket counter and returns the block's base.  Particles are sorted by start
+// cell, so a block holds a few dozen distinct keys.
 __global__ void __launch_bounds__(256) k_count(Dev D) {
+    constexpr int CH = kCountChunks, TS = 256 * kCountChunks;
+    constexpr int LOG_TS = __builtin_ctz(TS);
+    static_assert((TS & (TS - 1)) == 0, "hash table size must be a power of two");
+    __shared__ int tkey[TS];
+    __shared__ unsigned long long tcnt[TS];
     const Scalars *sc = D.sc;
     const long long n_tot = sc->n_old + sc->n_new + sc->n_inj;
-    const long long i0 = (long long)blockIdx.x * blockDim.x;
-    if (i0 >= n_tot) return;
-    const long long i = i0 + threadIdx.x;
-    const int kraw = i < n_tot ? D.key[i] : -1;
-    const bool stay = kraw >= 0 && (kraw & kStayBit) != 0;
-    const int key = kraw >= 0 ? (kraw & ~kStayBit) : -1;
-    const int slot = agg_count(D.cnt64, key, stay);
-    if (key >= 0 && !stay) D.rank[i] = slot;
+    const long long b0 = (long long)blockIdx.x * TS;
+    if (b0 >= n_tot) return;
+    const int lane = lane_id();
+    const long long w0 = b0 + (long long)(threadIdx.x / kWave) * (kWave * CH);
+    for (int h = threadIdx.x; h < TS; h += 256) {
+        tkey[h] = -1;
+        tcnt[h] = 0ULL;
+    }
+    int key[CH];
+    bool stay[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const long long i = w0 + j * kWave + lane;
+        const int kraw = i < n_tot ? D.key[i] : -1;
+        stay[j] = kraw >= 0 && (kraw & kStayBit) != 0;
+        key[j] = kraw >= 0 ? (kraw & ~kStayBit) : -1;
+    }
+    __syncthreads();
+    const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    int slot[CH];
+    unsigned int local[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const unsigned long long stays = __ballot(stay[j]);
+        const unsigned long long mine = key_group(key[j]);
+        const int leader = mine ? __ffsll((long long)mine) - 1 : lane;
+        const unsigned long long movers = mine & ~stays;
+        int sl = -1;
+        unsigned long long prev = 0ULL;
+        if (mine && lane == leader) {
+            unsigned int h = ((unsigned int)key[j] * 0x9E3779B1u) >> (32 - LOG_TS);
+            for (int probe = 0; probe < TS; ++probe) {
+                const int k = atomicCAS(&tkey[h], -1, key[j]);
+                if (k == -1 || k == key[j]) {
+                    sl = (int)h;
+                    break;
+                }
+                h = (h + 1) & (unsigned int)(TS - 1);
+            }
+            // always found: distinct keys <= particles of the block = TS
+            if (sl >= 0)
+                prev = atomicAdd(&tcnt[sl], ((unsigned long long)__popcll(mine & stays) << 32) | __popcll(movers));
+            else
+                atomicOr(&D.sc->err, kErrLost);
+        }
+        slot[j] = __shfl(sl, leader);
+        local[j] = (unsigned int)(__shfl(prev, leader) & 0xFFFFFFFFULL) + (unsigned int)__popcll(movers & below);
+    }
+    __syncthreads();
+    // block totals into the buckets; the entry's count is replaced by the block's base
+    for (int h = threadIdx.x; h < TS; h += 256) {
+        const int k = tkey[h];
+        if (k >= 0) tcnt[h] = atomicAdd(&D.cnt64[k], tcnt[h]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+        if (key[j] >= 0 && !stay[j] && slot[j] >= 0)
+            D.rank[w0 + j * kWave + lane] = (int)(tcnt[slot[j]] & 0xFFFFFFFFULL) + (int)local[j];
 }
 
 // bucket the movers (collisionless particles that changed cell) and the collided particles:
-// perm[off[key] + rank] = i, rank handed out in k_stream (cnt holds their number per bucket)
+// perm[off[key] + rank] = i (cnt holds their number per bucket); stayers are collected by
+// the gather from their own segment.  kScatterChunks particles per thread, strided by the
+// block; their loads are issued before the first store.
 __global__ void __launch_bounds__(256) k_scatter(Dev D) {
+    constexpr int CH = kScatterChunks;
     const Scalars *sc = D.sc;
     const long long n_tot = sc->n_old + sc->n_new + sc->n_inj;
-    const long long i0 = (long long)blockIdx.x * blockDim.x;
-    if (i0 >= n_tot) return;
-    const long long i = i0 + threadIdx.x;
-    if (i >= n_tot) return;
-    const int key = D.key[i];
-    // stayers are collected by the gather from their own segment
-    if (key >= 0 && !(key & kStayBit)) D.perm[D.off[key] + D.rank[i]] = (int32_t)i;
+    const long long b0 = (long long)blockIdx.x * (256 * CH);
+    if (b0 >= n_tot) return;
+    int key[CH], dst[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const long long i = b0 + j * 256 + threadIdx.x;
+        key[j] = i < n_tot ? D.key[i] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const long long i = b0 + j * 256 + threadIdx.x;
+        dst[j] = (key[j] >= 0 && !(key[j] & kStayBit)) ? D.off[key[j]] + D.rank[i] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j)
+        if (dst[j] >= 0) D.perm[dst[j]] = (int32_t)(b0 + j * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1696,34 +1761,6 @@ __device__ void block_sort(int *a, int len) {
 // they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-thread
 // assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-// copy one particle record and add its phi = m (1, u, |u|^2/2) (FP64 sums) to acc
-__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c,
-                                         double acc[5], double) {
-    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
-    const double2 r0 = a[0], r1 = a[1], r2 = a[2], r3 = a[3];
-    const double u[3] = {r1.y, r2.x, r2.y};
-    add_phi<double>(acc, r3.x, u);
-    double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
-    b[0] = r0;
-    b[1] = r1;
-    b[2] = r2;
-    b[3] = r3;
-    dst.cell[o] = c;
-}
-__device__ __forceinline__ void move_rec(const Particles &src, const Particles &dst, int s, int o, int c,
-                                         double acc[5], float) {
-    const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
-    const float4 r0 = a[0], r1 = a[1];
-    const float m = src.m32[s];
-    const float u[3] = {r0.w, r1.x, r1.y};
-    add_phi<float>(acc, m, u);
-    float4 *b = reinterpret_cast<float4 *>(dst.rec32 + o);
-    b[0] = r0;
-    b[1] = r1;
-    dst.m32[o] = m;
-    dst.cell[o] = c;
-}
-
 // add phi of a record without copying it (collided particles)
 __device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5], double) {
     const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
@@ -1736,6 +1773,65 @@ __device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[
     const float4 r0 = a[0], r1 = a[1];
     const float u[3] = {r0.w, r1.x, r1.y};
     add_phi<float>(acc, src.m32[s], u);
+}
+
+// a whole record in registers, so that several loads can be in flight before the stores
+// (scalar arrays: kept in registers, where structs of vectors went to scratch)
+struct Rec64 {
+    double v[8];  // x0 x1 | x2 u0 | u1 u2 | m id
+};
+struct Rec32 {
+    float v[9];  // x0 x1 x2 u0 | u1 u2 id.lo id.hi, then m
+};
+template <typename R>
+struct RecOf;
+template <>
+struct RecOf<double> {
+    using T = Rec64;
+};
+template <>
+struct RecOf<float> {
+    using T = Rec32;
+};
+__device__ __forceinline__ void load_rec(const Particles &src, int s, Rec64 &q) {
+    const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 t = a[k];
+        q.v[2 * k] = t.x;
+        q.v[2 * k + 1] = t.y;
+    }
+}
+__device__ __forceinline__ void load_rec(const Particles &src, int s, Rec32 &q) {
+    const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
+    const float4 t0 = a[0], t1 = a[1];
+    q.v[0] = t0.x;
+    q.v[1] = t0.y;
+    q.v[2] = t0.z;
+    q.v[3] = t0.w;
+    q.v[4] = t1.x;
+    q.v[5] = t1.y;
+    q.v[6] = t1.z;
+    q.v[7] = t1.w;
+    q.v[8] = src.m32[s];
+}
+// add phi of the record to acc and write it to slot o of dst (cell c)
+__device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, const Rec64 &q, double acc[5]) {
+    const double u[3] = {q.v[3], q.v[4], q.v[5]};
+    add_phi<double>(acc, q.v[6], u);
+    double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = make_double2(q.v[2 * k], q.v[2 * k + 1]);
+    dst.cell[o] = c;
+}
+__device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, const Rec32 &q, double acc[5]) {
+    const float u[3] = {q.v[3], q.v[4], q.v[5]};
+    add_phi<float>(acc, q.v[8], u);
+    float4 *b = reinterpret_cast<float4 *>(dst.rec32 + o);
+    b[0] = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    b[1] = make_float4(q.v[4], q.v[5], q.v[6], q.v[7]);
+    dst.m32[o] = q.v[8];
+    dst.cell[o] = c;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1763,7 +1859,7 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
     const Scalars *sc = D.sc;
     // every per-cell scalar in one round of independent loads
     const int base = D.off[c], bend = D.off[c + 1];
-    const int nmov = D.cnt[c];
+    const int nmov = (int)(D.cnt64[c] & 0xFFFFFFFFULL);
     const int cb0 = D.off[nc + c], cb1 = D.off[nc + c + 1];
     const long long s00 = D.segoff[buf][c], s01 = D.segoff[buf][c + 1];
     const long long n_old = sc->n_old, n_new = sc->n_new;
@@ -1804,13 +1900,19 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
             list = D.perm + a0;
         }
         block_sort<BS>(list, len);
+        if (part == 0) {
+            // two records per lane in flight: both loads before either store
+            for (int j = lane; j < len; j += 2 * BS) {
+                const bool hb = j + BS < len;
+                typename RecOf<R>::T A{}, B{};
+                load_rec(src, list[j], A);
+                if (hb) load_rec(src, list[j + BS], B);
+                put_rec(dst, a0 + j, c, A, Pn);
+                if (hb) put_rec(dst, a0 + j + BS, c, B, Pn);
+            }
+        } else {
 #pragma unroll 2
-        for (int j = lane; j < len; j += BS) {
-            const int sidx = list[j];
-            if (part == 0)
-                move_rec(src, dst, sidx, a0 + j, c, Pn, R(0));
-            else
-                add_rec(src, sidx, Cn, R(0));
+            for (int j = lane; j < len; j += BS) add_rec(src, list[j], Cn, R(0));
         }
         __syncthreads();
     }
@@ -1820,13 +1922,20 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
     for (int seg = 0; seg < 2; ++seg) {
         const long long s0 = seg == 0 ? s00 : s10;
         const long long s1 = seg == 0 ? s01 : (n_new == 0 ? s10 : s11);
-        for (long long j0 = s0; j0 < s1; j0 += BS) {
-            const long long j = j0 + lane;
-            const int k = j < s1 ? D.key[j] : -1;
-            const bool st = k >= 0 && (k & kStayBit) != 0;
-            const unsigned long long msk = __ballot(st);
-            if (st) move_rec(src, dst, (int)j, pos + (int)__popcll(msk & below), c, Pn, R(0));
-            pos += (int)__popcll(msk);
+        // two runs of 64 per pass: both key loads, then both record loads, then the stores
+        for (long long j0 = s0; j0 < s1; j0 += 2 * BS) {
+            const long long ja = j0 + lane, jb = j0 + BS + lane;
+            const int ka = ja < s1 ? D.key[ja] : -1;
+            const int kb = jb < s1 ? D.key[jb] : -1;
+            const bool sa = ka >= 0 && (ka & kStayBit) != 0, sb = kb >= 0 && (kb & kStayBit) != 0;
+            const unsigned long long ma = __ballot(sa), mb = __ballot(sb);
+            typename RecOf<R>::T A{}, B{};
+            if (sa) load_rec(src, (int)ja, A);
+            if (sb) load_rec(src, (int)jb, B);
+            if (sa) put_rec(dst, pos + (int)__popcll(ma & below), c, A, Pn);
+            pos += (int)__popcll(ma);
+            if (sb) put_rec(dst, pos + (int)__popcll(mb & below), c, B, Pn);
+            pos += (int)__popcll(mb);
         }
     }
 #pragma unroll
@@ -1917,6 +2026,21 @@ __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
 // ---------------------------------------------------------------------------------------
 constexpr int kScanBS = 256, kScanPer = 8, kScanTile = kScanBS * kScanPer;
 
+// scan inputs: a plain array, or the bucket sizes (movers / collided in the low word of the
+// bucket counter, stayers in the high word)
+template <typename T>
+struct LoadPlain {
+    const T *p;
+    __device__ T operator()(long long i) const { return p[i]; }
+};
+struct LoadBucket {
+    const unsigned long long *p;
+    __device__ int32_t operator()(long long i) const {
+        const unsigned long long v = p[i];
+        return (int32_t)(v & 0xFFFFFFFFULL) + (int32_t)(v >> 32);
+    }
+};
+
 template <typename T>
 __device__ T block_exclusive_scan(T v, T *sh, T &total) {
     sh[threadIdx.x] = v;
@@ -1933,14 +2057,14 @@ __device__ T block_exclusive_scan(T v, T *sh, T &total) {
     return incl - v;
 }
 
-template <typename T>
-__global__ void k_scan_reduce(const T *in, long long n, T *part) {
+template <typename T, typename L>
+__global__ void k_scan_reduce(L in, long long n, T *part) {
     __shared__ T sh[kScanBS];
     const long long base = (long long)blockIdx.x * kScanTile;
     T s = 0;
     for (int q = 0; q < kScanPer; ++q) {
         long long i = base + (long long)threadIdx.x * kScanPer + q;
-        if (i < n) s = s + in[i];
+        if (i < n) s = s + in(i);
     }
     T tot;
     block_exclusive_scan<T>(s, sh, tot);
@@ -1962,15 +2086,15 @@ __global__ void k_scan_partials(T *part, int nb, T *total_out) {
     if (threadIdx.x == 0) *total_out = carry;
 }
 
-template <typename T>
-__global__ void k_scan_apply(const T *in, long long n, const T *part, T *out) {
+template <typename T, typename L>
+__global__ void k_scan_apply(L in, long long n, const T *part, T *out) {
     __shared__ T sh[kScanBS];
     const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
     T v[kScanPer];
     T s = 0;
     for (int q = 0; q < kScanPer; ++q) {
         long long i = base + q;
-        v[q] = i < n ? in[i] : T(0);
+        v[q] = i < n ? in(i) : T(0);
         s = s + v[q];
     }
     T tot;
@@ -2018,23 +2142,23 @@ __global__ void k_moments(Dev D, int which, double *out) {
     for (int k = 0; k < 5; ++k) out[5 * c + k] = o[k];
 }
 
-template <typename T>
-void scan(const T *in, long long n, T *out, T *part, hipStream_t s) {
+// exclusive scan of n entries of in into out[0..n]; part: scan_partials_needed(n) entries
+template <typename T, typename L>
+void scan(L in, long long n, T *out, T *part, hipStream_t s) {
     const int nb = (int)((n + kScanTile - 1) / kScanTile);
     if (nb == 0) {
         k_fill<T><<<1, 1, 0, s>>>(out, 1, T(0));
         return;
     }
-    k_scan_reduce<T><<<nb, kScanBS, 0, s>>>(in, n, part);
+    k_scan_reduce<T, L><<<nb, kScanBS, 0, s>>>(in, n, part);
     k_scan_partials<T><<<1, kScanBS, 0, s>>>(part, nb, out + n);
-    k_scan_apply<T><<<nb, kScanBS, 0, s>>>(in, n, part, out);
+    k_scan_apply<T, L><<<nb, kScanBS, 0, s>>>(in, n, part, out);
 }
 
 }  // namespace
 
 long long scan_partials_needed(long long n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-long long stream_blocks(long long cap) { return (cap + 255) / 256; }
 
 void launch_fill_i32(int32_t *p, long long n, int32_t v, hipStream_t s) {
     if (n > 0) k_fill<int32_t><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, v);
@@ -2132,14 +2256,12 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     k_cell_prep<<<gc, 256, 0, s>>>(D);
     pr->end(kSlotCellPrep);
     pr->begin(kSlotScan);
-    scan<long long>(D.nsam, nc, D.samoff, D.scan64, s);
+    scan<long long>(LoadPlain<long long>{D.nsam}, nc, D.samoff, D.scan64, s);
     if (D.nff > 0) {
         k_inject_count<<<(unsigned)((D.nff + 255) / 256), 256, 0, s>>>(D);
-        scan<long long>(D.ninj, D.nff, D.injoff, D.scan64, s);
+        scan<long long>(LoadPlain<long long>{D.ninj}, D.nff, D.injoff, D.scan64, s);
     }
     k_sample_setup<<<1, 1, 0, s>>>(D);
-    k_fill<unsigned long long><<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D.cnt64, 2LL * nc, 0ULL);
-    k_fill<unsigned long long><<<1, 128, 0, s>>>(D.spart, 128, 0ULL);
     pr->end(kSlotScan);
     const bool f32 = D.prec == 1;
     pr->begin(kSlotFlux);
@@ -2168,16 +2290,14 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     else
         launch_stream<double>(D, buf, cfg, s);
     pr->end(kSlotStream);
-    const unsigned pb = (unsigned)stream_blocks(D.cap);
     pr->begin(kSlotCount);
-    k_count<<<pb, 256, 0, s>>>(D);
+    k_count<<<(unsigned)((D.cap + 256 * kCountChunks - 1) / (256 * kCountChunks)), 256, 0, s>>>(D);
     pr->end(kSlotCount);
     pr->begin(kSlotScan2);
-    k_bucket_total<<<(unsigned)((2LL * nc + 255) / 256), 256, 0, s>>>(D);
-    scan<int32_t>(D.cursor, 2LL * nc, D.off, D.scan32, s);
+    scan<int32_t>(LoadBucket{D.cnt64}, 2LL * nc, D.off, D.scan32, s);
     pr->end(kSlotScan2);
     pr->begin(kSlotScatter);
-    k_scatter<<<pb, 256, 0, s>>>(D);
+    k_scatter<<<(unsigned)((D.cap + 256 * kScatterChunks - 1) / (256 * kScatterChunks)), 256, 0, s>>>(D);
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
     if (f32)

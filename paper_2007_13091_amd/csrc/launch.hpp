@@ -8,9 +8,6 @@ namespace ugkwp {
 
 // scan partial slots needed for an exclusive scan over n integers
 long long scan_partials_needed(long long n);
-// blocks of the one-particle-per-thread kernels for a capacity (blocks past the live
-// particles exit at once)
-long long stream_blocks(long long cap);
 
 // measurement hook: called around each group of launches of a step (no-op by default)
 enum ProfSlot : int {
