@@ -186,7 +186,8 @@ int32_t ugkwp_graph_enable(ugkwp_ctx *ctx, int32_t on);
 
 /* Launch shapes of the tunable kernels, cfg[4] = {k_stream block size (128, 256, 512),
  * k_stream particles per thread (1, 2), k_sample cells (waves) per block (1, 2, 4, 8), k_flux
- * block size (64, 128, 256)}.  Every shape gives bit-identical results. */
+ * block size (64, 128, 256)}.  Every shape gives bit-identical results.  Defaults: {256, 1,
+ * 4, 128} in the FP64 form, {512, 2, 4, 128} in the FP32 form. */
 int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg);
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
 
@@ -200,8 +201,9 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
 /* Measurement support.  While enabled, each group of kernel launches of ugkwp_step is
  * bracketed by hip events recorded on the library's stream.  ugkwp_profile_read waits for
  * the stream, writes the summed elapsed milliseconds and the number of timed groups for the
- * first n_slots slots (see ugkwp_profile_slot_name; slot 5 is the free-transport kernel),
- * and clears the sums.  Either output pointer may be NULL. */
+ * first n_slots slots (see ugkwp_profile_slot_name; slot 5 is the free-transport kernel,
+ * slot 6 the kernel that finishes the flights stopped at diffuse walls), and clears the
+ * sums.  Either output pointer may be NULL. */
 int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on);
 int32_t ugkwp_profile_read(ugkwp_ctx *ctx, int32_t n_slots, double *total_ms, int64_t *launches);
 /* Record only the slots whose bit is set in mask (default: all); fewer events, less overhead. */

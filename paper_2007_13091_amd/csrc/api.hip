@@ -77,9 +77,9 @@ struct EventProf : ugkwp::Prof {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
-const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep", "scan_sample", "flux",   "sample",
-                                             "stream",  "count",     "scan_buckets", "scatter", "gather",
-                                             "finalize"};
+const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep",    "scan_sample", "flux",    "sample",
+                                             "stream",  "stream_wall",  "count",       "scan_buckets", "scatter",
+                                             "gather",  "finalize"};
 }  // namespace
 
 struct ugkwp_ctx {
@@ -177,7 +177,8 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     D.scan32 = C.take<int32_t>((size_t)ugkwp::scan_partials_needed(2 * (long long)nc));
     D.spart = C.take<unsigned long long>(128);
     D.cnt64 = C.take<unsigned long long>(2 * nc);
-    D.rank = C.take<int32_t>((size_t)cap);
+    D.rank = C.take<int32_t>((size_t)(cap + ugkwp::kWallSlack));
+    D.wallq = C.take<unsigned int>(ugkwp::kWallSeg);
     D.segoff[0] = C.take<int32_t>(nc + 1);
     D.segoff[1] = C.take<int32_t>(nc + 1);
     D.key = C.take<int32_t>((size_t)cap);
@@ -353,9 +354,12 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     }
     ctx->p = p[0];
     ctx->ps.assign(p, p + n_inst);
-    // two particles per thread in the FP32 form's transport (measured faster there; the FP64
-    // kernel loses an occupancy level to it)
-    if (p[0].precision == 1) ctx->cfg.stream_ilp = 2;
+    // blocks of 512 threads with two particles each in the FP32 form's transport (measured
+    // fastest there); one particle per thread in blocks of 256 in the FP64 form
+    if (p[0].precision == 1) {
+        ctx->cfg.stream_bs = 512;
+        ctx->cfg.stream_ilp = 2;
+    }
     ctx->stream = (hipStream_t)hip_stream;
     ctx->prof.s = ctx->stream;
     ctx->ws = (char *)dev_workspace;
@@ -379,6 +383,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     D.n_inst = n_inst;
     D.recon_any = recon_any ? 1 : 0;
     D.recon_all = recon_all ? 1 : 0;
+    D.any_diffuse = 0;
+    for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
     D.cap = cap;
     D.prec = p[0].precision;
     std::vector<ugkwp::InstP> ip((size_t)n_inst);

@@ -51,6 +51,13 @@ struct InstS {
 
 // Step scalars of the whole batch, resident in device memory: the host never reads them
 // inside a step.  dt, t and step mirror instance 0.
+// wall queue: segment s takes the particles stopped at diffuse walls by the transport
+// blocks b with b % kWallSeg == s (one counter per segment, not one for the whole grid);
+// a segment holds ceil(blocks / kWallSeg) x (particles per block) entries, so the segments
+// need at most kWallSlack entries beyond the capacity
+constexpr int kWallSeg = 64;
+constexpr long long kWallSlack = (long long)kWallSeg * 1024;
+
 struct Scalars {
     unsigned long long dtmin_bits;  // bit pattern of min Omega/Lambda (positive doubles order as integers)
     double dt;
@@ -120,6 +127,7 @@ struct Dev {
     // parameters
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
+    int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
     const InstP *ip;        // [n_inst]
     InstS *is;              // [n_inst]
     const int32_t *cinst;   // [nc] instance of each cell (n_inst > 1 only)
@@ -145,7 +153,9 @@ struct Dev {
     int32_t *scan32;        // scan partials
     unsigned long long *spart; // [2][64] crossings and wall hits, spread over 64 slots
     unsigned long long *cnt64; // [2nc] per bucket: stayers << 32 | movers (or collided)
-    int32_t *rank;          // [cap] slot of a mover / collided particle inside its bucket
+    int32_t *rank;          // [cap + kWallSlack] slot of a mover / collided particle inside its
+                            // bucket; during transport, the wall queue (kWallSeg segments)
+    unsigned int *wallq;    // [kWallSeg] particles queued in each wall-queue segment
     int32_t *segoff[2];     // [nc+1] each: survivor segments per cell in pa[0] / pa[1]
     int32_t *key;           // [cap]
     int32_t *perm;          // [cap]

@@ -31,6 +31,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
 constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
+constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (1, 2 and 4 measured alike)
 
 // ---------------------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11); counter = (uid, step, tag<<32|sub, 0),
@@ -300,6 +301,7 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
         Scalars *s = D.sc;
         s->n_sampled = 0;
     }
+    if (blockIdx.x == 0 && threadIdx.x < kWallSeg) D.wallq[threadIdx.x] = 0u;
     // partial sums of crossings and wall hits of this step's transport
     if (blockIdx.x == 0 && threadIdx.x < 128) D.spart[threadIdx.x] = 0ULL;
     double r = INFINITY;
@@ -1321,16 +1323,20 @@ __device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u
     for (int d = 0; d < 3; ++d) u[d] = (R)b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
 }
 
-template <typename R>
-__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, uint64_t uid, const StepCtx &sx,
-                     int &ncross, int &nwall) {
+// Flight of one particle for the time ts from cell `cell`, entered through its local face
+// `entry` (-1: none).  Returns 0 (ends inside the domain), 1 (left through a far-field face)
+// or -1 (more than max_cross crossings); ncross, nwall and bounce (diffuse re-emissions so
+// far, which keys the wall draws) carry on from their values at the call.  With STOP, a
+// diffuse wall ends the call with 2: x is then the wall point, u the incoming velocity,
+// cell the cell at the wall, entry the wall face and ts the time still to fly; the
+// re-emission and the rest of the flight are left to a later call (the wall kernel).
+template <typename R, bool STOP>
+__device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry, uint64_t uid, const StepCtx &sx,
+                     int &ncross, int &nwall, int &bounce) {
     // margin of the exact division skip below: well above the rounding of the products
     const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
     int c = cell;
-    int entry = entry0;
     R trem = ts;
-    int bounce = 0;
-    ncross = 0;
     for (;;) {
         R best = (R)INFINITY;
         int bf = -1;
@@ -1417,6 +1423,12 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R ts, int entry0, 
             }
             entry = bf;
         } else if (b.type == 1) {
+            if (STOP) {
+                cell = c;
+                ts = trem;
+                entry = bf;
+                return 2;
+            }
             R p[4];
             cell_plane(D, c * 6 + bf, p);
             const R n[3] = {p[0], p[1], p[2]};
@@ -1478,11 +1490,50 @@ __device__ __forceinline__ void store_state(const Particles &pa, long long i, co
 // threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
 // (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
+// A particle that meets a diffuse wall stops there (its state at the wall is stored) and is
+// queued with what its flight still needs (WallCont, kept in the next step's buffer, which
+// is free until the gather); the wall kernel re-emits it and finishes the flight with the
+// same draws and arithmetic.  The re-emission (logarithm, sine, cosine) is thereby kept out
+// of the transport kernel's registers.
+template <typename R>
+struct WallCont {
+    R trem;                   // flight time left at the wall
+    int ncross, bounce;       // crossings so far (the wall included), re-emissions so far
+    int entry, c0, collided;  // wall face, start cell (-1: entered this step), collided flag
+};
+static_assert(sizeof(WallCont<double>) <= sizeof(PRec) && sizeof(WallCont<float>) <= sizeof(PRec32),
+              "a continuation fits in a particle record");
+template <typename R>
+__device__ __forceinline__ WallCont<R> *wall_cont(const Particles &p, long long i);
+template <>
+__device__ __forceinline__ WallCont<double> *wall_cont<double>(const Particles &p, long long i) {
+    return reinterpret_cast<WallCont<double> *>(p.rec + i);
+}
+template <>
+__device__ __forceinline__ WallCont<float> *wall_cont<float>(const Particles &p, long long i) {
+    return reinterpret_cast<WallCont<float> *>(p.rec32 + i);
+}
+
+// end of a flight: state, cell and bucket key of particle i
+template <typename R>
+__device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa, long long i, const R x[3],
+                                              const R u[3], int c, int rc, bool collided, int c0, bool &lost) {
+    store_state(pa, i, x, u);
+    pa.cell[i] = c;
+    int key = -1;
+    bool stay = false;
+    if (rc != 1) {
+        lost = lost || rc < 0;
+        key = collided ? D.nc + c : c;
+        stay = !collided && c == c0;
+    }
+    D.key[i] = stay ? (key | kStayBit) : key;
+}
+
 template <typename R, bool MULTI>
-__device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, long long i, long long n_old,
-                                           long long n_smp, int c, R x[3], R u[3], uint64_t uid,
-                                           R e, R tauc,
-                                           unsigned long long &nx_, unsigned long long &nw_, bool &lost) {
+__device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
+                                           long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
+                                           R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
     // a single instance reads its values through uniform addresses
@@ -1512,24 +1563,22 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, lo
             }
         }
     }
-    int nx = 0, nw = 0;
-    const int rc = track<R>(D, x, u, c, ts, entry0, uid, sx, nx, nw);
+    int nx = 0, nw = 0, bounce = 0;
+    int entry = entry0;
+    const int rc = track<R, true>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
     nx_ += (unsigned long long)nx;
-    nw_ += (unsigned long long)nw;
-    store_state(pa, i, x, u);
-    pa.cell[i] = c;
-    int key = -1;
-    bool stay = false;
-    if (rc != 1) {
-        lost = lost || rc < 0;
-        key = collided ? D.nc + c : c;
-        stay = !collided && c == c0;
+    if (rc == 2) {
+        store_state(pa, i, x, u);
+        pa.cell[i] = c;
+        *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0};
+        queued = true;
+        return;
     }
-    D.key[i] = stay ? (key | kStayBit) : key;
+    finish_flight<R>(D, pa, i, x, u, c, rc, collided, c0, lost);
 }
 
 template <typename R, int BS, bool MULTI, int ILP>
-__global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
+__global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     constexpr int NW = BS / 64;
     __shared__ unsigned long long red[2][NW];
     const Scalars *sc = D.sc;
@@ -1538,11 +1587,12 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     const long long n_tot = n_smp + sc->n_inj;
     const long long i0 = (long long)blockIdx.x * (BS * ILP);
     if (i0 >= n_tot) return;
-    const Particles pa = D.pa[buf];
-    unsigned long long nx_ = 0, nw_ = 0;
+    const Particles pa = D.pa[buf], pc = D.pa[buf ^ 1];
+    unsigned long long nx_ = 0;
     bool lost = false;
     long long ii[ILP];
     int cc[ILP];
+    bool qq[ILP];
     R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP];
     uint64_t id[ILP];
 #pragma unroll
@@ -1561,10 +1611,76 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
             tt[j] = (R)D.tau[cc[j]];
         }
 #pragma unroll
-    for (int j = 0; j < ILP; ++j)
+    for (int j = 0; j < ILP; ++j) {
+        qq[j] = false;
         if (ii[j] < n_tot)
-            stream_one<R, MULTI>(D, pa, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_, nw_,
-                                 lost);
+            stream_one<R, MULTI>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_, lost,
+                                 qq[j]);
+    }
+    // wall queue (held in the rank array, which the bucket count fills only later): this
+    // block's segment, qseg entries from seg * qseg
+    const int lane = lane_id();
+    const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    const int seg = (int)(blockIdx.x % kWallSeg);
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+        const unsigned long long m = __ballot(qq[j]);
+        if (m) {
+            const int first = __ffsll((long long)m) - 1;
+            unsigned int base = 0;
+            if (lane == first) base = atomicAdd(&D.wallq[seg], (unsigned int)__popcll(m));
+            base = __shfl(base, first);
+            if (qq[j]) D.rank[seg * qseg + base + __popcll(m & below)] = (int32_t)ii[j];
+        }
+    }
+    if (__ballot(lost) && lane == 0) atomicOr(&D.sc->err, kErrLost);
+    nx_ = wave_sum_u64(nx_);
+    const int wave = threadIdx.x / kWave;
+    if (lane == 0) red[0][wave] = nx_;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a += red[0][w];
+        if (a) atomicAdd(&D.spart[blockIdx.x & 63], a);
+    }
+}
+
+// The diffuse re-emissions queued by k_stream and the rest of those flights (further walls
+// re-emitted here directly).  Block b serves queue segment b % kWallSeg in a block-stride
+// loop together with the other gridDim / kWallSeg blocks of that segment.
+template <typename R, bool MULTI>
+__global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long qseg) {
+    __shared__ unsigned long long red[2][4];
+    const int seg = (int)(blockIdx.x % kWallSeg);
+    const long long nq = (long long)D.wallq[seg];
+    const long long per = (long long)(gridDim.x / kWallSeg) * 256;
+    const Particles pa = D.pa[buf], pc = D.pa[buf ^ 1];
+    unsigned long long nx_ = 0, nw_ = 0;
+    bool lost = false;
+    for (long long q = (long long)(blockIdx.x / kWallSeg) * 256 + threadIdx.x; q < nq; q += per) {
+        const long long i = D.rank[seg * qseg + q];
+        R x[3], u[3];
+        uint64_t uid;
+        load_state(pa, i, x, u, uid);
+        int c = pa.cell[i];
+        const WallCont<R> w = *wall_cont<R>(pc, i);
+        const int inst = MULTI ? D.cinst[c] : 0;
+        const InstP &P = D.ip[inst];
+        const StepCtx sx{P.seed, D.is[inst].step, inst, P.max_cross};
+        const DevBC &b = D.bc[-1 - D.nbl[c * 6 + w.entry].x];
+        R p[4];
+        cell_plane(D, c * 6 + w.entry, p);
+        const R n[3] = {p[0], p[1], p[2]};
+        reemit_diffuse<R>(b, n, u, uid, sx, w.bounce);
+        int nx = w.ncross, nw = 1, bounce = w.bounce + 1;
+        int entry = w.entry;
+        R ts = w.trem;
+        const int rc = track<R, false>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
+        nx_ += (unsigned long long)(nx - w.ncross);
+        nw_ += (unsigned long long)nw;
+        finish_flight<R>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, lost);
+    }
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
     nw_ = wave_sum_u64(nw_);
@@ -1575,15 +1691,11 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            a += red[0][w];
-            b += red[1][w];
-        }
+        const unsigned long long a = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        const unsigned long long bw = red[1][0] + red[1][1] + red[1][2] + red[1][3];
         const int slot64 = blockIdx.x & 63;
         if (a) atomicAdd(&D.spart[slot64], a);
-        if (b) atomicAdd(&D.spart[64 + slot64], b);
+        if (bw) atomicAdd(&D.spart[64 + slot64], bw);
     }
 }
 
@@ -1707,21 +1819,28 @@ __global__ void __launch_bounds__(256) k_scatter(Dev D) {
 }
 
 // ---------------------------------------------------------------------------------------
-// block-wide sort of a short list of distinct ints, ascending.  Bitonic network whose
+// Sort by one wave of a short list of distinct ints, ascending.  Bitonic network whose
 // comparators all put the smaller value first, so entries past len behave as +infinity and
-// are never touched.  a may point to LDS or to global memory.
+// are never touched.  a may point to LDS or to global memory; only this wave touches it.
 // ---------------------------------------------------------------------------------------
-template <int BS>
-__device__ void block_sort(int *a, int len) {
+// orders this wave's LDS and global accesses (its lanes run together: no barrier needed)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ void wave_sort(int *a, int len) {
+    constexpr int BS = kWave;
     if (len < 2) return;
+    const int lane = lane_id();
     int bad = 0;
-    for (int i = threadIdx.x; i + 1 < len; i += BS) bad |= a[i] > a[i + 1];
-    if (!__syncthreads_or(bad)) return;
+    for (int i = lane; i + 1 < len; i += BS) bad |= a[i] > a[i + 1];
+    if (!__ballot(bad)) return;
     int N = 1;
     while (N < len) N <<= 1;
     for (int k = 2; k <= N; k <<= 1) {
         const int h = k >> 1;
-        for (int p = threadIdx.x; p < N / 2; p += BS) {
+        for (int p = lane; p < N / 2; p += BS) {
             const int i = (p / h) * k + (p % h);
             const int j = i ^ (k - 1);
             if (j < len) {
@@ -1732,9 +1851,9 @@ __device__ void block_sort(int *a, int len) {
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         for (int j = h >> 1; j > 0; j >>= 1) {
-            for (int p = threadIdx.x; p < N / 2; p += BS) {
+            for (int p = lane; p < N / 2; p += BS) {
                 const int i = (p / j) * 2 * j + (p % j);
                 const int q = i + j;
                 if (q < len) {
@@ -1745,7 +1864,7 @@ __device__ void block_sort(int *a, int len) {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     }
 }
@@ -1843,17 +1962,21 @@ __device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, cons
 // they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-lane
 // assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-template <typename R>
-__global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
+template <typename R, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     constexpr int BS = kWave;
     constexpr int kLds = 1024;
-    __shared__ int lds[kLds];
-    // blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
+    __shared__ int lds_all[WPB][kLds];
+    // WPB waves per block, one cell each, independent of one another (no block barrier).
+    // Blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
     // that neighbouring cells (whose particles are exchanged) share an L2
     const int G = (int)gridDim.x, bidx = (int)blockIdx.x;
     const int xcd = bidx & 7, q = G >> 3, rr = G & 7;
-    const int c = xcd * q + (xcd < rr ? xcd : rr) + (bidx >> 3);
+    const int wave = (int)(threadIdx.x / kWave);
+    const int c = (xcd * q + (xcd < rr ? xcd : rr) + (bidx >> 3)) * WPB + wave;
     const int nc = D.nc, nf = D.nf;
+    if (c >= nc) return;
+    int *lds = lds_all[wave];
     const int lane = lane_id();
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
     const Scalars *sc = D.sc;
@@ -1894,12 +2017,12 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
         int *list;
         if (len <= kLds) {
             for (int j = lane; j < len; j += BS) lds[j] = D.perm[a0 + j];
-            __syncthreads();
+            wave_sync();
             list = lds;
         } else {
             list = D.perm + a0;
         }
-        block_sort<BS>(list, len);
+        wave_sort(list, len);
         if (part == 0) {
             // two records per lane in flight: both loads before either store
             for (int j = lane; j < len; j += 2 * BS) {
@@ -1914,7 +2037,7 @@ __global__ void __launch_bounds__(64) k_gather(Dev D, int buf) {
 #pragma unroll 2
             for (int j = lane; j < len; j += BS) add_rec(src, list[j], Cn, R(0));
         }
-        __syncthreads();
+        wave_sync();
     }
     // stayers: own segment of old particles, then own new particles, compacted in order
     const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
@@ -2168,33 +2291,46 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s) {
 }
 
 namespace {
+// entries of one wall-queue segment for a transport grid of g blocks of `per` particles;
+// kWallSeg segments take at most cap + kWallSlack entries
+long long wall_qseg(long long g, long long per) { return (g + kWallSeg - 1) / kWallSeg * per; }
+
 template <typename R, bool MULTI, int ILP>
-void launch_stream_i(const Dev &D, int buf, int bs, hipStream_t s) {
+long long launch_stream_i(const Dev &D, int buf, int bs, hipStream_t s) {
     // ILP particles per thread over the capacity; blocks past the live particles exit at once
     const long long per = (long long)bs * ILP;
     const unsigned g = (unsigned)((D.cap + per - 1) / per);
+    const long long qseg = wall_qseg(g, per);
     if (bs == 128)
-        k_stream<R, 128, MULTI, ILP><<<g, 128, 0, s>>>(D, buf);
+        k_stream<R, 128, MULTI, ILP><<<g, 128, 0, s>>>(D, buf, qseg);
     else if (bs == 512)
-        k_stream<R, 512, MULTI, ILP><<<g, 512, 0, s>>>(D, buf);
+        k_stream<R, 512, MULTI, ILP><<<g, 512, 0, s>>>(D, buf, qseg);
     else
-        k_stream<R, 256, MULTI, ILP><<<g, 256, 0, s>>>(D, buf);
+        k_stream<R, 256, MULTI, ILP><<<g, 256, 0, s>>>(D, buf, qseg);
+    return qseg;
 }
 
 template <typename R, bool MULTI>
-void launch_stream_t(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
-    if (cfg.stream_ilp == 2)
-        launch_stream_i<R, MULTI, 2>(D, buf, cfg.stream_bs, s);
-    else
-        launch_stream_i<R, MULTI, 1>(D, buf, cfg.stream_bs, s);
+long long launch_stream_t(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+    if (cfg.stream_ilp == 2) return launch_stream_i<R, MULTI, 2>(D, buf, cfg.stream_bs, s);
+    return launch_stream_i<R, MULTI, 1>(D, buf, cfg.stream_bs, s);
+}
+
+// returns the wall-queue segment length the transport grid used
+template <typename R>
+long long launch_stream(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+    if (D.n_inst > 1) return launch_stream_t<R, true>(D, buf, cfg, s);
+    return launch_stream_t<R, false>(D, buf, cfg, s);
 }
 
 template <typename R>
-void launch_stream(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
+void launch_stream_wall(const Dev &D, int buf, long long qseg, hipStream_t s) {
+    // 16 blocks per queue segment, each segment's length known only on the device
+    const unsigned g = 16 * kWallSeg;
     if (D.n_inst > 1)
-        launch_stream_t<R, true>(D, buf, cfg, s);
+        k_stream_wall<R, true><<<g, 256, 0, s>>>(D, buf, qseg);
     else
-        launch_stream_t<R, false>(D, buf, cfg, s);
+        k_stream_wall<R, false><<<g, 256, 0, s>>>(D, buf, qseg);
 }
 
 template <typename R>
@@ -2285,11 +2421,16 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     }
     pr->end(kSlotSample);
     pr->begin(kSlotStream);
-    if (f32)
-        launch_stream<float>(D, buf, cfg, s);
-    else
-        launch_stream<double>(D, buf, cfg, s);
+    const long long qseg = f32 ? launch_stream<float>(D, buf, cfg, s) : launch_stream<double>(D, buf, cfg, s);
     pr->end(kSlotStream);
+    pr->begin(kSlotStreamWall);
+    if (D.any_diffuse) {
+        if (f32)
+            launch_stream_wall<float>(D, buf, qseg, s);
+        else
+            launch_stream_wall<double>(D, buf, qseg, s);
+    }
+    pr->end(kSlotStreamWall);
     pr->begin(kSlotCount);
     k_count<<<(unsigned)((D.cap + 256 * kCountChunks - 1) / (256 * kCountChunks)), 256, 0, s>>>(D);
     pr->end(kSlotCount);
@@ -2300,10 +2441,14 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     k_scatter<<<(unsigned)((D.cap + 256 * kScatterChunks - 1) / (256 * kScatterChunks)), 256, 0, s>>>(D);
     pr->end(kSlotScatter);
     pr->begin(kSlotGather);
-    if (f32)
-        k_gather<float><<<nc, 64, 0, s>>>(D, buf);
-    else
-        k_gather<double><<<nc, 64, 0, s>>>(D, buf);
+    {
+        constexpr int WPB = kGatherWaves;
+        const unsigned g = (unsigned)((nc + WPB - 1) / WPB);
+        if (f32)
+            k_gather<float, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+        else
+            k_gather<double, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+    }
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
     k_finalize<<<1, 256, 0, s>>>(D, buf);

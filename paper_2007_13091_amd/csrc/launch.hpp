@@ -17,6 +17,7 @@ enum ProfSlot : int {
     kSlotFlux,          // k_flux
     kSlotSample,        // k_sample
     kSlotStream,        // k_stream
+    kSlotStreamWall,    // k_stream_wall (diffuse re-emissions queued by k_stream)
     kSlotCount,         // k_count
     kSlotScan2,         // scan of the bucket counts
     kSlotScatter,       // k_scatter

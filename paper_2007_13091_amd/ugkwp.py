@@ -24,7 +24,7 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
            "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask")
-N_PROFILE_SLOTS = 11
+N_PROFILE_SLOTS = 12
 
 
 class UgkwpBC(C.Structure):
