@@ -27,6 +27,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # (FP64: x 24 + u 24 + m 8 + cell 4 + uid 8 = 68 B; FP32 form: 12 + 12 + 4 + 4 + 8 = 40 B)
 BYTES_PER_MOVE_FP64 = 136
 BYTES_PER_MOVE_FP32 = 80
+# algorithmic bytes of the gather (S6): a survivor's record read and written with its cell,
+# plus its bucket key read (FP64: 64 + 64 + 4 + 4 = 136 B; FP32: 36 + 40 + 4 = 80 B); a
+# collided particle's velocity and mass read with its key (FP64: 48 + 4 = 52 B; FP32: 36 + 4)
+BYTES_PER_SURVIVOR = {"double": 136, "float": 80}
+BYTES_PER_COLLIDED = {"double": 52, "float": 40}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -119,7 +124,7 @@ def timed_run(w, precision, warmup, steps):
     torch.cuda.empty_cache()
     kern = {k: v for k, v in warm.items()}
     kern[dom] = prof[dom]
-    return t1 - t0, st1["moved_total"] - moved0, kern, cfg, dom
+    return t1 - t0, st1["moved_total"] - moved0, kern, cfg, dom, st1
 
 
 def stated_fp32_error():
@@ -207,18 +212,25 @@ def batched_run(steps, warmup, plain_steps):
     return out
 
 
-def roofline(prof, dom, moves_per_launch, bytes_per_move, rtype, cfg):
-    """Roofline position of the dominant kernel group dom: the algorithmic bytes of the
-    particle moves one launch performs over its average duration.  cfg: the solver's launch
-    shapes (they name the kernel instance that ran)."""
+def roofline(prof, dom, moves_per_launch, last, rtype, cfg):
+    """Roofline position of the dominant kernel group dom (transport or gather): its
+    algorithmic bytes per launch over its average duration.  Transport: the particle moves
+    of a step; gather: the survivors and collided particles of a step (last: statistics of
+    the last timed step).  cfg: the solver's launch shapes (they name the kernel instance)."""
     dom_ms, dom_n = prof[dom]
     avg_ms = dom_ms / max(dom_n, 1)
-    achieved = bytes_per_move * moves_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = {"stream": f"k_stream<{rtype}, {cfg[0]}, false, {cfg[1]}>", "gather": f"k_gather<{rtype}>"}.get(dom, dom)
+    if dom == "stream":
+        algo = (BYTES_PER_MOVE_FP64 if rtype == "double" else BYTES_PER_MOVE_FP32) * moves_per_launch
+        kname = f"k_stream<{rtype}, {cfg[0]}, false, {cfg[1]}>"
+    elif dom == "gather":
+        algo = BYTES_PER_SURVIVOR[rtype] * last["n_alive"] + BYTES_PER_COLLIDED[rtype] * last["n_collided"]
+        kname = f"k_gather<{rtype}, 1>"  # one wave (cell) per block
+    else:
+        raise RuntimeError(f"no algorithmic byte count for kernel group {dom}")
+    achieved = algo / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": int(bytes_per_move * moves_per_launch)}
+            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(algo)}
 
 
 def main():
@@ -246,10 +258,10 @@ def main():
 
     w = wl.cavity()
     nc = w.mesh.n_cells
-    el, moves, prof, cfg, dom = timed_run(w, 0, args.warmup, args.steps)
+    el, moves, prof, cfg, dom, last = timed_run(w, 0, args.warmup, args.steps)
     value = moves / el
     moves_per_launch = moves / args.steps
-    roof = roofline(prof, dom, moves_per_launch, BYTES_PER_MOVE_FP64, "double", cfg)
+    roof = roofline(prof, dom, moves_per_launch, last, "double", cfg)
     out = {
         "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
         "value": value,
@@ -271,12 +283,12 @@ def main():
         "roofline": roof,
     }
     if not args.no_fp32:
-        el32, moves32, prof32, cfg32, dom32 = timed_run(w, 1, args.warmup, args.steps)
+        el32, moves32, prof32, cfg32, dom32, last32 = timed_run(w, 1, args.warmup, args.steps)
         out["fp32_form"] = {"value": moves32 / el32, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
                             "ms_per_step": el32 / args.steps * 1e3, "cell_steps_per_s": nc * args.steps / el32,
                             "speedup_vs_fp64_plain": (moves32 / el32) / value,
                             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
-                            "roofline": roofline(prof32, dom32, moves32 / args.steps, BYTES_PER_MOVE_FP32, "float", cfg32),
+                            "roofline": roofline(prof32, dom32, moves32 / args.steps, last32, "float", cfg32),
                             "stated_error": stated_fp32_error()}
     if not args.no_batched:
         out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)
