@@ -346,8 +346,8 @@ int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::ve
         nff += h.nff;
         nbf += (int64_t)h.bf_lf.size();
     }
-    if (nc > 2147483647LL - 1 || nf > 2147483647LL - 1) {
-        err = "batch: more than 2^31 - 1 cells or faces in total";
+    if (nc > 2147483647LL - 1 || nf > 2147483647LL - 1 || nbf > 2147483647LL - 1) {
+        err = "batch: more than 2^31 - 1 cells, faces or boundary faces in total";
         return UGKWP_E_ARG;
     }
     HostMesh o;
