@@ -1500,6 +1500,7 @@ struct WallCont {
     R trem;                   // flight time left at the wall
     int ncross, bounce;       // crossings so far (the wall included), re-emissions so far
     int entry, c0, collided;  // wall face, start cell (-1: entered this step), collided flag
+    int cell;                 // cell at the wall
 };
 static_assert(sizeof(WallCont<double>) <= sizeof(PRec) && sizeof(WallCont<float>) <= sizeof(PRec32),
               "a continuation fits in a particle record");
@@ -1514,12 +1515,12 @@ __device__ __forceinline__ WallCont<float> *wall_cont<float>(const Particles &p,
     return reinterpret_cast<WallCont<float> *>(p.rec32 + i);
 }
 
-// end of a flight: state, cell and bucket key of particle i
+// end of a flight: state and bucket key of particle i (the key carries the end cell; the
+// cell array of this buffer is not read again, the gather writes the next one)
 template <typename R>
 __device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa, long long i, const R x[3],
                                               const R u[3], int c, int rc, bool collided, int c0, bool &lost) {
     store_state(pa, i, x, u);
-    pa.cell[i] = c;
     int key = -1;
     bool stay = false;
     if (rc != 1) {
@@ -1569,8 +1570,7 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, co
     nx_ += (unsigned long long)nx;
     if (rc == 2) {
         store_state(pa, i, x, u);
-        pa.cell[i] = c;
-        *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0};
+        *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0, c};
         queued = true;
         return;
     }
@@ -1663,8 +1663,8 @@ __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long q
         R x[3], u[3];
         uint64_t uid;
         load_state(pa, i, x, u, uid);
-        int c = pa.cell[i];
         const WallCont<R> w = *wall_cont<R>(pc, i);
+        int c = w.cell;
         const int inst = MULTI ? D.cinst[c] : 0;
         const InstP &P = D.ip[inst];
         const StepCtx sx{P.seed, D.is[inst].step, inst, P.max_cross};
