@@ -245,6 +245,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=8)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg and print its JSON object (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -252,6 +254,10 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_form": batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)}),
+              flush=True)
         return
 
     from paper_2007_13091_amd import workloads as wl
