@@ -1953,6 +1953,56 @@ __device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, cons
     dst.cell[o] = c;
 }
 
+// Staged output: a lane adds phi of its record, puts the record into its slot of the wave's
+// LDS stage and writes the small per-particle arrays (cell; FP32: mass) itself; then the wave
+// stores the run of staged records with consecutive lanes on consecutive 16-byte chunks, a
+// few whole cache lines per instruction instead of a 16-byte piece of 64 lines.
+template <typename R>
+struct RecChunks;
+template <>
+struct RecChunks<double> {
+    static constexpr int N = 4;  // x0 x1 | x2 u0 | u1 u2 | m id
+};
+template <>
+struct RecChunks<float> {
+    static constexpr int N = 2;  // x0 x1 x2 u0 | u1 u2 id
+};
+__device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, const Rec64 &q, double acc[5],
+                                          uint4 *slot) {
+    const double u[3] = {q.v[3], q.v[4], q.v[5]};
+    add_phi<double>(acc, q.v[6], u);
+    double2 *b = reinterpret_cast<double2 *>(slot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = make_double2(q.v[2 * k], q.v[2 * k + 1]);
+    dst.cell[o] = c;
+}
+__device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, const Rec32 &q, double acc[5],
+                                          uint4 *slot) {
+    const float u[3] = {q.v[3], q.v[4], q.v[5]};
+    add_phi<float>(acc, q.v[8], u);
+    float4 *b = reinterpret_cast<float4 *>(slot);
+    b[0] = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    b[1] = make_float4(q.v[4], q.v[5], q.v[6], q.v[7]);
+    dst.m32[o] = q.v[8];
+    dst.cell[o] = c;
+}
+__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, double) {
+    return reinterpret_cast<uint4 *>(p.rec + i);
+}
+__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, float) {
+    return reinterpret_cast<uint4 *>(p.rec32 + i);
+}
+// the wave's n staged records to dst from record o0 on (called by the whole wave; the fences
+// order this wave's LDS accesses, which the hardware performs in order)
+template <typename R>
+__device__ __forceinline__ void stage_out(const uint4 *st, const Particles &dst, int o0, int n) {
+    constexpr int CPR = RecChunks<R>::N;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    uint4 *g = rec_chunks(dst, o0, R(0));
+    for (int k = lane_id(); k < n * CPR; k += kWave) g[k] = st[k];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // ---------------------------------------------------------------------------------------
 // S6: one wave per cell c.  The survivors ending in c are laid out in the next buffer as
 //   [movers into c, ascending source index] [stayers of c, in their segment order]
@@ -1965,8 +2015,10 @@ __device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, cons
 template <typename R, int WPB>
 __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     constexpr int BS = kWave;
-    constexpr int kLds = 1024;
+    constexpr int kLds = 256;  // longer source lists are sorted in place in global memory
+    constexpr int CPR = RecChunks<R>::N;
     __shared__ int lds_all[WPB][kLds];
+    __shared__ uint4 st_all[WPB][kWave * CPR];
     // WPB waves per block, one cell each, independent of one another (no block barrier).
     // Blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
     // that neighbouring cells (whose particles are exchanged) share an L2
@@ -1977,6 +2029,7 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     const int nc = D.nc, nf = D.nf;
     if (c >= nc) return;
     int *lds = lds_all[wave];
+    uint4 *st = st_all[wave];
     const int lane = lane_id();
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
     const Scalars *sc = D.sc;
@@ -2025,13 +2078,16 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
         wave_sort(list, len);
         if (part == 0) {
             // two records per lane in flight: both loads before either store
-            for (int j = lane; j < len; j += 2 * BS) {
-                const bool hb = j + BS < len;
+            for (int j0 = 0; j0 < len; j0 += 2 * BS) {
+                const int j = j0 + lane;
+                const bool ha = j < len, hb = j + BS < len;
                 typename RecOf<R>::T A{}, B{};
-                load_rec(src, list[j], A);
+                if (ha) load_rec(src, list[j], A);
                 if (hb) load_rec(src, list[j + BS], B);
-                put_rec(dst, a0 + j, c, A, Pn);
-                if (hb) put_rec(dst, a0 + j + BS, c, B, Pn);
+                if (ha) stage_rec(dst, a0 + j, c, A, Pn, st + lane * CPR);
+                stage_out<R>(st, dst, a0 + j0, min(BS, len - j0));
+                if (hb) stage_rec(dst, a0 + j + BS, c, B, Pn, st + lane * CPR);
+                stage_out<R>(st, dst, a0 + j0 + BS, max(0, min(BS, len - j0 - BS)));
             }
         } else {
 #pragma unroll 2
@@ -2055,9 +2111,12 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             typename RecOf<R>::T A{}, B{};
             if (sa) load_rec(src, (int)ja, A);
             if (sb) load_rec(src, (int)jb, B);
-            if (sa) put_rec(dst, pos + (int)__popcll(ma & below), c, A, Pn);
+            const int ra = (int)__popcll(ma & below), rb = (int)__popcll(mb & below);
+            if (sa) stage_rec(dst, pos + ra, c, A, Pn, st + ra * CPR);
+            stage_out<R>(st, dst, pos, (int)__popcll(ma));
             pos += (int)__popcll(ma);
-            if (sb) put_rec(dst, pos + (int)__popcll(mb & below), c, B, Pn);
+            if (sb) stage_rec(dst, pos + rb, c, B, Pn, st + rb * CPR);
+            stage_out<R>(st, dst, pos, (int)__popcll(mb));
             pos += (int)__popcll(mb);
         }
     }
