@@ -1515,12 +1515,13 @@ __device__ __forceinline__ WallCont<float> *wall_cont<float>(const Particles &p,
     return reinterpret_cast<WallCont<float> *>(p.rec32 + i);
 }
 
-// end of a flight: state and bucket key of particle i (the key carries the end cell; the
-// cell array of this buffer is not read again, the gather writes the next one)
-template <typename R>
+// end of a flight: state (unless the caller stores it) and bucket key of particle i (the key
+// carries the end cell; the cell array of this buffer is not read again, the gather writes
+// the next one)
+template <typename R, bool STORE>
 __device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa, long long i, const R x[3],
                                               const R u[3], int c, int rc, bool collided, int c0, bool &lost) {
-    store_state(pa, i, x, u);
+    if (STORE) store_state(pa, i, x, u);
     int key = -1;
     bool stay = false;
     if (rc != 1) {
@@ -1531,7 +1532,7 @@ __device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa,
     D.key[i] = stay ? (key | kStayBit) : key;
 }
 
-template <typename R, bool MULTI>
+template <typename R, bool MULTI, bool STORE>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
                                            long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
                                            R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued) {
@@ -1569,18 +1570,61 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, co
     const int rc = track<R, true>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
     nx_ += (unsigned long long)nx;
     if (rc == 2) {
-        store_state(pa, i, x, u);
+        if (STORE) store_state(pa, i, x, u);
         *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0, c};
         queued = true;
         return;
     }
-    finish_flight<R>(D, pa, i, x, u, c, rc, collided, c0, lost);
+    finish_flight<R, STORE>(D, pa, i, x, u, c, rc, collided, c0, lost);
+}
+
+// a record as 16-byte chunks
+template <typename R>
+struct RecChunks;
+template <>
+struct RecChunks<double> {
+    static constexpr int N = 4;  // x0 x1 | x2 u0 | u1 u2 | m id
+};
+template <>
+struct RecChunks<float> {
+    static constexpr int N = 2;  // x0 x1 x2 u0 | u1 u2 id
+};
+__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, double) {
+    return reinterpret_cast<uint4 *>(p.rec + i);
+}
+__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, float) {
+    return reinterpret_cast<uint4 *>(p.rec32 + i);
+}
+
+// the transported state of a lane's particle into its slot of the wave's stage: position and
+// velocity with the mass and id chunk (FP64) or id words (FP32) as loaded
+__device__ __forceinline__ void stage_state(uint4 *slot, const double x[3], const double u[3], const uint4 &tail) {
+    double2 *d = reinterpret_cast<double2 *>(slot);
+    d[0] = make_double2(x[0], x[1]);
+    d[1] = make_double2(x[2], u[0]);
+    d[2] = make_double2(u[1], u[2]);
+    slot[3] = tail;
+}
+__device__ __forceinline__ void stage_state(uint4 *slot, const float x[3], const float u[3], const uint4 &tail) {
+    float4 *f = reinterpret_cast<float4 *>(slot);
+    f[0] = make_float4(x[0], x[1], x[2], u[0]);
+    f[1] = make_float4(u[1], u[2], __uint_as_float(tail.z), __uint_as_float(tail.w));
+}
+// the last 16 bytes of a record as loaded (FP64: mass and id; FP32: u1 u2 and the id words)
+__device__ __forceinline__ uint4 rec_tail(const Particles &pa, long long i, double) {
+    return reinterpret_cast<const uint4 *>(pa.rec + i)[3];
+}
+__device__ __forceinline__ uint4 rec_tail(const Particles &pa, long long i, float) {
+    return reinterpret_cast<const uint4 *>(pa.rec32 + i)[1];
 }
 
 template <typename R, int BS, bool MULTI, int ILP>
 __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     constexpr int NW = BS / 64;
+    constexpr int CPR = RecChunks<R>::N;
     __shared__ unsigned long long red[2][NW];
+    // output stage: the records of each wave's run, stored whole and coalesced at the end
+    __shared__ uint4 stage[NW][ILP][kWave * CPR];
     const Scalars *sc = D.sc;
     const long long n_old = sc->n_old;
     const long long n_smp = n_old + sc->n_new;
@@ -1593,6 +1637,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     long long ii[ILP];
     int cc[ILP];
     bool qq[ILP];
+    uint4 tl[ILP];
     R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP];
     uint64_t id[ILP];
 #pragma unroll
@@ -1601,6 +1646,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
         if (ii[j] < n_tot) {
             cc[j] = pa.cell[ii[j]];
             load_state(pa, ii[j], xx[j], uu[j], id[j]);
+            tl[j] = rec_tail(pa, ii[j], R(0));
         }
     }
     // start-cell data, loaded before the generators run
@@ -1613,9 +1659,21 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
         qq[j] = false;
-        if (ii[j] < n_tot)
-            stream_one<R, MULTI>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_, lost,
-                                 qq[j]);
+        if (ii[j] < n_tot) {
+            stream_one<R, MULTI, false>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_,
+                                        lost, qq[j]);
+            stage_state(&stage[threadIdx.x / kWave][j][lane_id() * CPR], xx[j], uu[j], tl[j]);
+        }
+    }
+    // each wave stores its runs of records whole, consecutive lanes on consecutive chunks
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+        const long long wb = i0 + j * BS + (threadIdx.x / kWave) * kWave;  // the run's first record
+        const long long nr = n_tot - wb;
+        const int nch = (nr <= 0 ? 0 : (nr >= kWave ? kWave : (int)nr)) * CPR;
+        uint4 *g = rec_chunks(pa, wb, R(0));
+        for (int k = lane_id(); k < nch; k += kWave) g[k] = stage[threadIdx.x / kWave][j][k];
     }
     // wall queue (held in the rank array, which the bucket count fills only later): this
     // block's segment, qseg entries from seg * qseg
@@ -1679,7 +1737,7 @@ __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long q
         const int rc = track<R, false>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
         nx_ += (unsigned long long)(nx - w.ncross);
         nw_ += (unsigned long long)nw;
-        finish_flight<R>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, lost);
+        finish_flight<R, true>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, lost);
     }
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
@@ -1957,16 +2015,6 @@ __device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, cons
 // LDS stage and writes the small per-particle arrays (cell; FP32: mass) itself; then the wave
 // stores the run of staged records with consecutive lanes on consecutive 16-byte chunks, a
 // few whole cache lines per instruction instead of a 16-byte piece of 64 lines.
-template <typename R>
-struct RecChunks;
-template <>
-struct RecChunks<double> {
-    static constexpr int N = 4;  // x0 x1 | x2 u0 | u1 u2 | m id
-};
-template <>
-struct RecChunks<float> {
-    static constexpr int N = 2;  // x0 x1 x2 u0 | u1 u2 id
-};
 __device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, const Rec64 &q, double acc[5],
                                           uint4 *slot) {
     const double u[3] = {q.v[3], q.v[4], q.v[5]};
@@ -1985,12 +2033,6 @@ __device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, co
     b[1] = make_float4(q.v[4], q.v[5], q.v[6], q.v[7]);
     dst.m32[o] = q.v[8];
     dst.cell[o] = c;
-}
-__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, double) {
-    return reinterpret_cast<uint4 *>(p.rec + i);
-}
-__device__ __forceinline__ uint4 *rec_chunks(const Particles &p, long long i, float) {
-    return reinterpret_cast<uint4 *>(p.rec32 + i);
 }
 // the wave's n staged records to dst from record o0 on (called by the whole wave; the fences
 // order this wave's LDS accesses, which the hardware performs in order)
