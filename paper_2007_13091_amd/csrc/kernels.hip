@@ -1774,13 +1774,14 @@ __device__ __forceinline__ unsigned long long key_group(int key) {
 
 // bucket counts: stayers are only counted, movers and collided particles get their slot in
 // the bucket (the order of those slots is fixed later by sorting in the gather).  A block
-// takes 4 waves x kCountChunks runs of 64 consecutive particles.  In each run the lanes are
-// grouped by key with ballots; each group's leader adds (stayers << 32 | movers) to the
-// key's entry of an LDS hash table (open addressing, as many entries as the block has
-// particles, so it cannot fill up), whose returned value places the group's movers within
-// the block.  Then one global 64-bit atomic per distinct key of the block adds the block's
-// count to the bucket counter and returns the block's base.  Particles are sorted by start
-// cell, so a block holds a few dozen distinct keys.
+// takes 4 waves x kCountChunks runs of 64 consecutive particles and counts them in an LDS
+// hash table keyed by bucket (open addressing, as many entries as the block has particles,
+// so it cannot fill up; entry = stayers << 32 | movers).  Stayers are grouped by ballots
+// (one LDS atomic per group); a mover or collided particle adds itself, and the returned
+// count is its place among the block's particles of that key.  Then one global 64-bit
+// atomic per distinct key of the block adds the block's count to the bucket counter and
+// returns the block's base.  Particles are sorted by start cell, so a block holds a few
+// dozen distinct keys.
 __global__ void __launch_bounds__(256) k_count(Dev D) {
     constexpr int CH = kCountChunks, TS = 256 * kCountChunks;
     constexpr int LOG_TS = __builtin_ctz(TS);
@@ -1807,18 +1808,21 @@ __global__ void __launch_bounds__(256) k_count(Dev D) {
         key[j] = kraw >= 0 ? (kraw & ~kStayBit) : -1;
     }
     __syncthreads();
-    const unsigned long long below = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
     int slot[CH];
     unsigned int local[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-        const unsigned long long stays = __ballot(stay[j]);
-        const unsigned long long mine = key_group(key[j]);
+        // stayers (most lanes, usually one or two keys per run): grouped by ballots, each
+        // group's leader counts the group in the high word of its key's entry
+        const unsigned long long mine = key_group(stay[j] ? key[j] : -1);
         const int leader = mine ? __ffsll((long long)mine) - 1 : lane;
-        const unsigned long long movers = mine & ~stays;
-        int sl = -1;
-        unsigned long long prev = 0ULL;
-        if (mine && lane == leader) {
+        const bool lead = mine && lane == leader;
+        // movers and collided particles (mostly distinct keys within a run): each lane on its
+        // own entry, whose low word hands out its place among the block's particles of the key
+        slot[j] = -1;
+        local[j] = 0;
+        if (lead || (key[j] >= 0 && !stay[j])) {
+            int sl = -1;
             unsigned int h = ((unsigned int)key[j] * 0x9E3779B1u) >> (32 - LOG_TS);
             for (int probe = 0; probe < TS; ++probe) {
                 const int k = atomicCAS(&tkey[h], -1, key[j]);
@@ -1829,13 +1833,15 @@ __global__ void __launch_bounds__(256) k_count(Dev D) {
                 h = (h + 1) & (unsigned int)(TS - 1);
             }
             // always found: distinct keys <= particles of the block = TS
-            if (sl >= 0)
-                prev = atomicAdd(&tcnt[sl], ((unsigned long long)__popcll(mine & stays) << 32) | __popcll(movers));
-            else
+            if (sl < 0) {
                 atomicOr(&D.sc->err, kErrLost);
+            } else if (stay[j]) {
+                atomicAdd(&tcnt[sl], (unsigned long long)__popcll(mine) << 32);
+            } else {
+                slot[j] = sl;
+                local[j] = (unsigned int)(atomicAdd(&tcnt[sl], 1ULL) & 0xFFFFFFFFULL);
+            }
         }
-        slot[j] = __shfl(sl, leader);
-        local[j] = (unsigned int)(__shfl(prev, leader) & 0xFFFFFFFFULL) + (unsigned int)__popcll(movers & below);
     }
     __syncthreads();
     // block totals into the buckets; the entry's count is replaced by the block's base
