@@ -1018,22 +1018,27 @@ __device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
 }
 
 // ---------------------------------------------------------------------------------------
-// S3: hydro particles, one wave per cell, lane l takes the pairs l, l + 64, ...  Pair p
-// shares X ~ N(0, I) (Box-Muller on the draw keyed by the even partner's id); partners get
+// S3: hydro particles, one wave per cell, lane l takes the particles l, l + 64, ...  Pair
+// (2p, 2p+1) shares X ~ N(0, I) from Box-Muller on the draw keyed by the even partner's id:
+// X0, X1 = r1 (cos, sin)(2 pi e1), r1 = sqrt(-2 ln e0), and X2 = r2 cos(2 pi e3), r2 =
+// sqrt(-2 ln e2).  The even partner evaluates the first half, the odd one the second (the
+// same code on the other two uniforms), and they exchange halves.  Partners get
 // U + s sqrt(T) X and U - s sqrt(T) X (s: the cell's energy-exact factor) and their own
 // uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
-// The first pass sums |X|^2 for s and keeps each lane's first X for the second.
+// The first pass sums |X|^2 for s and keeps each lane's first half for the second.
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
+// this lane's half of its pair's normal: (r cos a, r sin a), r = sqrt(-2 ln e0 or e2),
+// a = 2 pi e1 or e3 (odd lanes use only the cosine)
 template <typename R>
-__device__ __forceinline__ void pair_normal(uint64_t seed, uint64_t puid, long long step, int inst, R X[3]) {
+__device__ __forceinline__ void half_normal(uint64_t seed, uint64_t puid, long long step, int inst, bool odd,
+                                            R &h0, R &h1) {
     const R two_pi = (R)2 * (R)kPi;
     const U4 rv = draw(seed, puid, step, kTagVel, 0, inst);
-    const R e0 = unif<R>(rv.v[0]), e1 = unif<R>(rv.v[1]), e2 = unif<R>(rv.v[2]), e3 = unif<R>(rv.v[3]);
-    const R r1 = sqrt((R)-2 * log(e0)), r2 = sqrt((R)-2 * log(e2));
-    X[0] = r1 * cos(two_pi * e1);
-    X[1] = r1 * sin(two_pi * e1);
-    X[2] = r2 * cos(two_pi * e3);
+    const R ea = unif<R>(odd ? rv.v[2] : rv.v[0]), eb = unif<R>(odd ? rv.v[3] : rv.v[1]);
+    const R r = sqrt((R)-2 * log(ea));
+    h0 = r * cos(two_pi * eb);
+    h1 = r * sin(two_pi * eb);
 }
 template <typename R, int WPB>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
@@ -1043,7 +1048,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     if (c >= D.nc) return;
     const int nc = D.nc;
     const Scalars *sc = D.sc;
-    const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;
+    const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;  // even
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (ns > 0) {
         const Particles pa = D.pa[buf];
@@ -1058,26 +1063,25 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
         R sT = sqrt(T);
         const R one = (R)1;
-        const long long npair = ns / 2;  // ns is even
-        R Xfirst[3] = {(R)0, (R)0, (R)0};
+        const bool odd = (lane & 1) != 0;
+        R f0 = (R)0, f1 = (R)0;  // this lane's half of its first pair's normal
         {
             // energy-exact pairs: the pairs carry the momentum exactly; one factor on every
             // thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2), makes the energy
             // exact too (a first pass over the pairs' normal draws, summed in FP64)
             double sx2 = 0.0;
-            for (long long q = lane; q < npair; q += kWave) {
-                R X[3];
-                pair_normal<R>(seed, make_uid(step, cl, 2 * q), step, inst, X);
-                if (q == lane) {
-                    Xfirst[0] = X[0];
-                    Xfirst[1] = X[1];
-                    Xfirst[2] = X[2];
+            for (long long k = lane; k < ns; k += kWave) {
+                R h0, h1;
+                half_normal<R>(seed, make_uid(step, cl, k & ~1LL), step, inst, odd, h0, h1);
+                if (k == lane) {
+                    f0 = h0;
+                    f1 = h1;
                 }
-                const double X0 = (double)X[0], X1 = (double)X[1], X2 = (double)X[2];
-                sx2 += X0 * X0 + X1 * X1 + X2 * X2;
+                const double a = (double)h0, b = (double)h1;
+                sx2 += odd ? a * a : a * a + b * b;
             }
             sx2 = wave_sum(sx2);
-            sT = (R)((double)sT * sqrt(3.0 * (double)npair / sx2));
+            sT = (R)((double)sT * sqrt(3.0 * (double)(ns / 2) / sx2));
         }
         const double vol = D.vol[c];
         const R msam = (R)(D.ec[c] * D.rhoh[c] * vol / (double)ns);
@@ -1086,21 +1090,17 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
         const bool tet = D.ctype[c] == 4;
-        for (long long q = lane; q < npair; q += kWave) {
-            R X[3];
-            if (q == lane) {
-                X[0] = Xfirst[0];
-                X[1] = Xfirst[1];
-                X[2] = Xfirst[2];
-            } else {
-                pair_normal<R>(seed, make_uid(step, cl, 2 * q), step, inst, X);
-            }
-#pragma unroll 1
-            for (int h = 0; h < 2; ++h) {
-                const long long k = 2 * q + h;
+        // runs of 64 particles (ns is even, so a pair never straddles two runs)
+        for (long long k0 = 0; k0 < ns; k0 += kWave) {
+            const long long k = k0 + lane;
+            R h0 = f0, h1 = f1;
+            if (k0 > 0 && k < ns) half_normal<R>(seed, make_uid(step, cl, k & ~1LL), step, inst, odd, h0, h1);
+            const R X0 = __shfl(h0, lane & ~1), X1 = __shfl(h1, lane & ~1), X2 = __shfl(h0, lane | 1);
+            if (k < ns) {
                 const long long i = base + k;
                 const uint64_t uid = make_uid(step, cl, k);
-                const R sg = h ? -one : one;
+                const R sg = odd ? -one : one;
+                const R X[3] = {X0, X1, X2};
                 R u[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
