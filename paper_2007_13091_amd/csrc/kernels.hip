@@ -1,15 +1,20 @@
-// HIP kernels of one UGKWP time step for gfx950 (FP64 path).
+// HIP kernels of one UGKWP time step for gfx950 (FP64 path and the FP32-transport form).
 //
 // Order inside a step (paper Sec. 2.3, the four-step particle procedure, and Eq.
 // update_macro_variables):
 //   k_prim_dt      S0  primitives, tau = mu_ref T^omega / p, min Omega/Lambda     (Sec. 2.4(a))
 //   k_cell_prep    S0  dt, exp(-dt/tau), rho^h, sample counts N_sam            (Sec. 2.4(b))
 //   scan           exclusive prefix of N_sam -> slots of the new particles
-//   k_flux         S2  wave flux F^eq + F^{fr,wave} per face                    (Sec. 2.2, 2.4)
+//   k_grad         S1  least-squares gradients and limiters (second order only)
+//   k_flux(2)      S2  wave flux F^eq + F^{fr,wave} per face                    (Sec. 2.2, 2.4)
 //   k_sample       S3  antithetic Maxwellian pairs, uniform positions; start sums S
-//   k_stream       S4+S5 free-flight time and face-to-face transport; end-cell keys
-//   scan           exclusive prefix of the per-cell counts
-//   k_scatter      bucket the particles by end cell (survivors, then collided)
+//   k_inject       S5  free-stream particles entering through far-field faces
+//   k_stream       S4+S5 free-flight time and face-to-face transport; end-cell keys;
+//                  particles meeting a diffuse wall stop there and are queued
+//   k_stream_wall  S5  diffuse re-emission of the queued particles, rest of their flight
+//   k_count        bucket sizes (survivors and collided per end cell), slots of movers
+//   scan           exclusive prefix of the bucket sizes
+//   k_scatter      bucket the movers and collided particles by end cell
 //   k_gather       S6  deterministic order per cell, sums E and W^p, update of W
 //   k_finalize     step bookkeeping
 // No floating-point atomics: per-cell sums use fixed reduction trees, so a run is bitwise
@@ -1998,25 +2003,6 @@ __device__ __forceinline__ void load_rec(const Particles &src, int s, Rec32 &q) 
     q.v[7] = t1.w;
     q.v[8] = src.m32[s];
 }
-// add phi of the record to acc and write it to slot o of dst (cell c)
-__device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, const Rec64 &q, double acc[5]) {
-    const double u[3] = {q.v[3], q.v[4], q.v[5]};
-    add_phi<double>(acc, q.v[6], u);
-    double2 *b = reinterpret_cast<double2 *>(dst.rec + o);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) b[k] = make_double2(q.v[2 * k], q.v[2 * k + 1]);
-    dst.cell[o] = c;
-}
-__device__ __forceinline__ void put_rec(const Particles &dst, int o, int c, const Rec32 &q, double acc[5]) {
-    const float u[3] = {q.v[3], q.v[4], q.v[5]};
-    add_phi<float>(acc, q.v[8], u);
-    float4 *b = reinterpret_cast<float4 *>(dst.rec32 + o);
-    b[0] = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
-    b[1] = make_float4(q.v[4], q.v[5], q.v[6], q.v[7]);
-    dst.m32[o] = q.v[8];
-    dst.cell[o] = c;
-}
-
 // Staged output: a lane adds phi of its record, puts the record into its slot of the wave's
 // LDS stage and writes the small per-particle arrays (cell; FP32: mass) itself; then the wave
 // stores the run of staged records with consecutive lanes on consecutive 16-byte chunks, a
