@@ -187,7 +187,7 @@ int32_t ugkwp_graph_enable(ugkwp_ctx *ctx, int32_t on);
 /* Launch shapes of the tunable kernels, cfg[4] = {k_stream block size (128, 256, 512),
  * k_stream particles per thread (1, 2), k_sample cells (waves) per block (1, 2, 4, 8), k_flux
  * block size (64, 128, 256)}.  Every shape gives bit-identical results.  Defaults: {256, 1,
- * 4, 128} in the FP64 form, {512, 2, 4, 128} in the FP32 form. */
+ * 4, 128}. */
 int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg);
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
 

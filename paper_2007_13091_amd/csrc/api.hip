@@ -354,12 +354,6 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     }
     ctx->p = p[0];
     ctx->ps.assign(p, p + n_inst);
-    // blocks of 512 threads with two particles each in the FP32 form's transport (measured
-    // fastest there); one particle per thread in blocks of 256 in the FP64 form
-    if (p[0].precision == 1) {
-        ctx->cfg.stream_bs = 512;
-        ctx->cfg.stream_ilp = 2;
-    }
     ctx->stream = (hipStream_t)hip_stream;
     ctx->prof.s = ctx->stream;
     ctx->ws = (char *)dev_workspace;

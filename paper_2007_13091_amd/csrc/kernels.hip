@@ -1335,18 +1335,31 @@ __device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u
 // diffuse wall ends the call with 2: x is then the wall point, u the incoming velocity,
 // cell the cell at the wall, entry the wall face and ts the time still to fly; the
 // re-emission and the rest of the flight are left to a later call (the wall kernel).
+// ct0 >= 0: the start cell's type and, for a box cell, its bounds B0 (loaded by the caller
+// together with the particle's other start-cell data, so that the first pass does not
+// wait for them).
 template <typename R, bool STOP>
 __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry, uint64_t uid, const StepCtx &sx,
-                     int &ncross, int &nwall, int &bounce) {
+                     int &ncross, int &nwall, int &bounce, int ct0 = -1, const R *B0 = nullptr) {
     // margin of the exact division skip below: well above the rounding of the products
     const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
     int c = cell;
     R trem = ts;
+    bool first = ct0 >= 0;
     for (;;) {
         R best = (R)INFINITY;
         int bf = -1;
-        if (D.ctype[c] == 8) {
-            const R *B = cell_box<R>(D, c);
+        const int ctc = first ? ct0 : (int)D.ctype[c];
+        if (ctc == 8) {
+            R B[6];
+            if (first) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) B[q] = B0[q];
+            } else {
+                const R *Bg = cell_box<R>(D, c);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) B[q] = Bg[q];
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 // a face at distance a >= |u_d| trem (1 + margin) has a computed exit time
@@ -1391,6 +1404,7 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
                 }
             }
         }
+        first = false;
         if (bf < 0 || best >= trem) {
             x[0] = x[0] + u[0] * trem;
             x[1] = x[1] + u[1] * trem;
@@ -1540,7 +1554,8 @@ __device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa,
 template <typename R, bool MULTI, bool STORE>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
                                            long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
-                                           R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued) {
+                                           R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued,
+                                           int ct0, const R *B0) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
     // a single instance reads its values through uniform addresses
@@ -1572,7 +1587,7 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, co
     }
     int nx = 0, nw = 0, bounce = 0;
     int entry = entry0;
-    const int rc = track<R, true>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
+    const int rc = track<R, true>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce, ct0, B0);
     nx_ += (unsigned long long)nx;
     if (rc == 2) {
         if (STORE) store_state(pa, i, x, u);
@@ -1643,7 +1658,8 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     int cc[ILP];
     bool qq[ILP];
     uint4 tl[ILP];
-    R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP];
+    R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP], bx[ILP][6];
+    int ct[ILP];
     uint64_t id[ILP];
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
@@ -1654,19 +1670,23 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
             tl[j] = rec_tail(pa, ii[j], R(0));
         }
     }
-    // start-cell data, loaded before the generators run
+    // start-cell data (e, tau, cell type, box bounds), loaded before the generators run
 #pragma unroll
     for (int j = 0; j < ILP; ++j)
         if (ii[j] < n_tot) {
             ee[j] = (R)D.ec[cc[j]];
             tt[j] = (R)D.tau[cc[j]];
+            ct[j] = (int)D.ctype[cc[j]];
+            const R *Bg = cell_box<R>(D, cc[j]);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) bx[j][q] = Bg[q];
         }
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
         qq[j] = false;
         if (ii[j] < n_tot) {
             stream_one<R, MULTI, false>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_,
-                                        lost, qq[j]);
+                                        lost, qq[j], ct[j], bx[j]);
             stage_state(&stage[threadIdx.x / kWave][j][lane_id() * CPR], xx[j], uu[j], tl[j]);
         }
     }
