@@ -51,7 +51,7 @@ def lib():
         L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), P(d)]
         L.orc_create.restype = vp
         L.orc_create.argtypes = [i64, P(d), i64, P(C.c_uint8), P(i64), P(i64), i64, P(i64), P(i32), i32,
-                                 P(i32), P(d), P(d), P(d), d, d, d, d, i32, i32, i32, u64, i64, P(i32)]
+                                 P(i32), P(d), P(d), P(d), P(d), d, d, d, d, i32, i32, i32, u64, i64, P(i32)]
         L.orc_destroy.argtypes = [vp]
         for name in ("orc_n_cells", "orc_n_faces", "orc_n_particles", "orc_step_index"):
             getattr(L, name).restype = i64
@@ -204,13 +204,13 @@ class Oracle:
         L = lib()
         self.mesh = mesh
         self.params = params
-        t, tw, uw, wi = mesh.bc_arrays()
+        t, tw, uw, wi, sh = mesh.bc_arrays()
         self._keep = [np.ascontiguousarray(mesh.xyz, dtype=np.float64),
                       np.ascontiguousarray(mesh.cell_type, dtype=np.uint8),
                       np.ascontiguousarray(mesh.cell_node_off, dtype=np.int64),
                       np.ascontiguousarray(mesh.cell_nodes, dtype=np.int64),
                       np.ascontiguousarray(mesh.bface_nodes, dtype=np.int64),
-                      np.ascontiguousarray(mesh.bface_bc, dtype=np.int32), t, tw, uw, wi]
+                      np.ascontiguousarray(mesh.bface_bc, dtype=np.int32), t, tw, uw, wi, sh]
         k = self._keep
         st = C.c_int32(0)
         if abs(params.gamma - 5.0 / 3.0) > 1e-12:
@@ -218,7 +218,8 @@ class Oracle:
         h = L.orc_create(mesh.n_nodes, _p(k[0], C.c_double), mesh.n_cells, _p(k[1], C.c_uint8),
                          _p(k[2], C.c_int64), _p(k[3], C.c_int64), k[4].shape[0], _p(k[4], C.c_int64),
                          _p(k[5], C.c_int32), len(mesh.bcs), _p(t, C.c_int32), _p(tw, C.c_double),
-                         _p(uw, C.c_double), _p(wi, C.c_double), params.mu_ref, params.omega, params.cfl,
+                         _p(uw, C.c_double), _p(wi, C.c_double), _p(sh, C.c_double), params.mu_ref,
+                         params.omega, params.cfl,
                          params.c2, params.n_ref, params.n_min, params.max_crossings, params.seed, instance,
                          C.byref(st))
         if not h:

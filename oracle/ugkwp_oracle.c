@@ -40,7 +40,9 @@
 #define ORC_E_LOST 4
 #define ORC_E_NONPHYS 5
 
-enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2 };
+/* BC_PERIODIC is test support, not a condition of the paper: a tagged face leads to the
+   face at x + shift, which makes every face interior and all five totals exact invariants */
+enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2, BC_PERIODIC = 3 };
 
 /* relative floor of the hydro density rho^h = rho - rho^p (see phase_cells) */
 #define RHOH_EPS 1e-12
@@ -618,6 +620,7 @@ void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15
 typedef struct {
     int type;
     double Tw, Uw[3], Winf[5];
+    double shift[3];  /* periodic */
 } obc_t;
 
 typedef struct {
@@ -644,6 +647,8 @@ typedef struct oracle {
     double *bo, *be1, *be2, *barea; /* per input boundary face: corner, two edges, area */
     int *btri;                       /* triangle (1) or parallelogram (0) */
     int *cnblf;       /* [nc][6] local face index in the neighbour */
+    int *cper;        /* [nc][6] periodic face: 1 + its bc index (crossing adds that bc's shift) */
+    int64_t nper;     /* periodic face pairs */
     double *orig, *edge; /* sampling frame: [nc][3], [nc][3][3] */
     double *lfx;         /* [nc][6][3] centre of each local face */
     double *fx;          /* [nf][3] face centre (the owner's) */
@@ -700,7 +705,8 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                      const int64_t *cell_node_off, const int64_t *cell_nodes, int64_t n_bfaces,
                      const int64_t *bface_nodes, const int32_t *bface_bc, int32_t n_bc,
                      const int32_t *bc_type, const double *bc_Tw, const double *bc_Uw,
-                     const double *bc_Winf, double mu_ref, double omega, double cfl, double c2,
+                     const double *bc_Winf, const double *bc_shift, double mu_ref, double omega, double cfl,
+                     double c2,
                      int32_t n_ref, int32_t n_min, int32_t max_cross, uint64_t seed, int64_t inst,
                      int32_t *status)
 {
@@ -725,6 +731,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     o->cbf = (int64_t *)xcalloc(6 * nc, sizeof(int64_t));
     for (int64_t i = 0; i < 6 * nc; ++i) o->cbf[i] = -1;
     o->cnblf = (int *)xcalloc(6 * nc, sizeof(int));
+    o->cper = (int *)xcalloc(6 * nc, sizeof(int));
     o->orig = (double *)xcalloc(3 * nc, sizeof(double));
     o->lfx = (double *)xcalloc(18 * nc, sizeof(double));
     o->venkat_k = 1.0;
@@ -739,6 +746,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
         o->bc[b].Tw = bc_Tw[b];
         for (int d = 0; d < 3; ++d) o->bc[b].Uw[d] = bc_Uw[3 * b + d];
         for (int k = 0; k < 5; ++k) o->bc[b].Winf[k] = bc_Winf[5 * b + k];
+        for (int d = 0; d < 3; ++d) o->bc[b].shift[d] = bc_shift[3 * b + d];
     }
 
     /* per-cell local geometry: outward plane, area and face centre of each local face */
@@ -895,6 +903,13 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
                 }
                 if (found < 0) { bad = 1; break; }
                 int b = (int)bk[found].cell;
+                if (o->bc[b].type == BC_PERIODIC) {
+                    /* paired after this loop; mark the slot with its bc for now */
+                    o->cper[6 * c + lf] = 1 + b;
+                    o->cbf[6 * c + lf] = bk[found].lf;
+                    i = j;
+                    continue;
+                }
                 o->fown[nf] = c;
                 o->fnb[nf] = -1 - b;
                 for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
@@ -911,6 +926,48 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
         }
         free(keys);
         free(bk);
+        if (bad) goto fail;
+        /* periodic pairs: face A of bc b leads to the face B whose centre is A's centre plus
+           b's shift, tagged with the opposite shift; they become one face owned by A's cell */
+        char *paired = (char *)xcalloc(6 * nc, 1);
+        for (int64_t c = 0; c < nc && !bad; ++c) {
+            for (int lf = 0; lf < o->cnf[c] && !bad; ++lf) {
+                int ba = o->cper[6 * c + lf] - 1;
+                if (ba < 0 || paired[6 * c + lf]) continue;
+                const double *s = o->bc[ba].shift, *xa = o->lfx + 18 * c + 3 * lf;
+                double tx[3];
+                for (int d = 0; d < 3; ++d) tx[d] = xa[d] + s[d];
+                double scale = 1.0 + fabs(tx[0]) + fabs(tx[1]) + fabs(tx[2]);
+                int64_t c2 = -1;
+                int lf2 = -1;
+                for (int64_t q = 0; q < nc && c2 < 0; ++q) {
+                    for (int l2 = 0; l2 < o->cnf[q]; ++l2) {
+                        int bb = o->cper[6 * q + l2] - 1;
+                        if (bb < 0 || (q == c && l2 == lf) || paired[6 * q + l2]) continue;
+                        const double *sb = o->bc[bb].shift, *xb = o->lfx + 18 * q + 3 * l2;
+                        if (fabs(sb[0] + s[0]) + fabs(sb[1] + s[1]) + fabs(sb[2] + s[2]) > 1e-12 * scale) continue;
+                        if (fabs(xb[0] - tx[0]) + fabs(xb[1] - tx[1]) + fabs(xb[2] - tx[2]) > 1e-9 * scale) continue;
+                        c2 = q;
+                        lf2 = l2;
+                        break;
+                    }
+                }
+                if (c2 < 0) { bad = 1; break; }
+                o->fown[nf] = c;
+                o->fnb[nf] = c2;
+                for (int d = 0; d < 3; ++d) o->fn[3 * nf + d] = o->pn[18 * c + 3 * lf + d];
+                for (int d = 0; d < 3; ++d) o->fx[3 * nf + d] = xa[d];
+                o->farea[nf] = larea[6 * c + lf];
+                o->cface[6 * c + lf] = nf; o->csign[6 * c + lf] = 1;
+                o->cface[6 * c2 + lf2] = nf; o->csign[6 * c2 + lf2] = -1;
+                o->cnb[6 * c + lf] = c2; o->cnblf[6 * c + lf] = lf2;
+                o->cnb[6 * c2 + lf2] = c; o->cnblf[6 * c2 + lf2] = lf;
+                paired[6 * c + lf] = paired[6 * c2 + lf2] = 1;
+                ++o->nper;
+                ++nf;
+            }
+        }
+        free(paired);
         if (bad) goto fail;
         o->nf = nf;
     }
@@ -959,6 +1016,7 @@ void orc_destroy(oracle_t *o)
     if (!o) return;
     free(o->ctype); free(o->cnf); free(o->vol); free(o->xc); free(o->dS);
     free(o->cface); free(o->csign); free(o->pn); free(o->pd); free(o->cnb); free(o->cnblf); free(o->cbf);
+    free(o->cper);
     free(o->bo); free(o->be1); free(o->be2); free(o->barea); free(o->btri);
     free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
     free(o->lfx); free(o->fx);
@@ -977,6 +1035,8 @@ double orc_time(const oracle_t *o) { return o->t; }
 int orc_set_recon(oracle_t *o, int recon, double venkat_k)
 {
     if (recon < 0 || recon > 2 || !(venkat_k > 0.0)) return ORC_E_ARG;
+    /* the gradients use neighbour centres, which a periodic face would need shifted */
+    if (recon != 0 && o->nper > 0) return ORC_E_ARG;
     o->recon = recon;
     o->venkat_k = venkat_k;
     return ORC_OK;
@@ -1091,6 +1151,12 @@ int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double
         if (++*ncross > o->max_cross) { *cell = c; return -1; }
         int64_t nb = o->cnb[6 * c + bf];
         if (nb >= 0) {
+            int per = o->cper[6 * c + bf];
+            if (per) {
+                /* periodic face: the particle goes on from the partner face */
+                const double *s = o->bc[per - 1].shift;
+                for (int d = 0; d < 3; ++d) x[d] = x[d] + s[d];
+            }
             entry = o->cnblf[6 * c + bf];
             c = nb;
             continue;

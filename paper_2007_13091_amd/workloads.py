@@ -21,6 +21,7 @@ import numpy as np
 BC_SPECULAR = 0
 BC_DIFFUSE = 1
 BC_FARFIELD = 2
+BC_PERIODIC = 3  # test support: a face leads to the face at x + shift (not a condition of the paper)
 
 CELL_TET = 4
 CELL_HEX = 8
@@ -35,6 +36,7 @@ class BC:
     Tw: float = 1.0
     Uw: tuple = (0.0, 0.0, 0.0)
     Winf: tuple = (0.0, 0.0, 0.0, 0.0, 0.0)
+    shift: tuple = (0.0, 0.0, 0.0)  # periodic: a point x of a tagged face matches x + shift
 
 
 @dataclass
@@ -60,7 +62,8 @@ class Mesh:
         tw = np.array([b.Tw for b in self.bcs], dtype=np.float64)
         uw = np.array([b.Uw for b in self.bcs], dtype=np.float64).reshape(-1, 3)
         wi = np.array([b.Winf for b in self.bcs], dtype=np.float64).reshape(-1, 5)
-        return t, tw, np.ascontiguousarray(uw), np.ascontiguousarray(wi)
+        sh = np.array([b.shift for b in self.bcs], dtype=np.float64).reshape(-1, 3)
+        return t, tw, np.ascontiguousarray(uw), np.ascontiguousarray(wi), np.ascontiguousarray(sh)
 
 
 @dataclass
@@ -284,6 +287,35 @@ def closed_box(n=(4, 3, 2), n_ref=50, kn=0.05, cfl=0.5, seed=7, bc=BC_SPECULAR, 
     T = 1.0 + perturb * rng.uniform(-1, 1, nc)
     prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
     return Workload("closed_box", mesh, prm, conservative(rho, U, T), 10)
+
+
+def periodic_box(n=(4, 3, 3), n_ref=50, kn=0.05, cfl=0.5, seed=5, perturb=0.2, drift=(0.3, -0.2, 0.1),
+                 tets=False) -> Workload:
+    """Fully periodic box [0,1]x[0,0.75]x[0,0.5] (every side leads to the opposite one), with a
+    seeded non-uniform initial state drifting at `drift` on average: no face is a wall, so
+    mass, all three momenta and energy are conserved exactly by the scheme."""
+    hi = (1.0, 0.75, 0.5)
+    bcs = []
+    side = {}
+    for a, (lo_s, hi_s) in enumerate((("xlo", "xhi"), ("ylo", "yhi"), ("zlo", "zhi"))):
+        sh = [0.0, 0.0, 0.0]
+        sh[a] = hi[a]
+        side[lo_s] = len(bcs)
+        bcs.append(BC(BC_PERIODIC, shift=tuple(sh)))
+        sh[a] = -hi[a]
+        side[hi_s] = len(bcs)
+        bcs.append(BC(BC_PERIODIC, shift=tuple(sh)))
+    if tets:
+        mesh = tet_box_mesh(n, (0.0, 0.0, 0.0), hi, side, bcs, jitter=0.0, seed=seed)
+    else:
+        mesh = box_hex_mesh(n, (0.0, 0.0, 0.0), hi, side, bcs)
+    rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x50455249], dtype=np.uint64)))
+    nc = mesh.n_cells
+    rho = 1.0 + perturb * rng.uniform(-1, 1, nc)
+    U = np.array(drift)[None, :] + 0.3 * perturb * rng.uniform(-1, 1, (nc, 3))
+    T = 1.0 + perturb * rng.uniform(-1, 1, nc)
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    return Workload("periodic_box", mesh, prm, conservative(rho, U, T), 10)
 
 
 def free_stream_box(n=(4, 3, 3), U=(0.8, 0.3, 0.0), T=1.0, rho=1.0, n_ref=100, kn=0.5, cfl=0.5, seed=11,
