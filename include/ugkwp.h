@@ -64,9 +64,14 @@ typedef enum {
 typedef enum {
     UGKWP_BC_SPECULAR = 0, /* symmetry plane / specular wall (Sec. 4.1) */
     UGKWP_BC_DIFFUSE = 1,  /* diffuse isothermal wall at T_w moving at U_w (Sec. 2.4(e)) */
-    UGKWP_BC_FARFIELD = 2  /* free stream W_inf outside (Sec. 4.3): wave flux against W_inf,
+    UGKWP_BC_FARFIELD = 2, /* free stream W_inf outside (Sec. 4.3): wave flux against W_inf,
                               particles leaving are removed, and the collisionless part of
                               the free stream enters as particles (see ugkwp_step_stats) */
+    UGKWP_BC_PERIODIC = 3  /* test support, not a condition of the paper: a face tagged with
+                              it leads to the boundary face whose centre is its own plus
+                              `shift` (tagged with the opposite shift); the pair is one
+                              interior face, a particle crossing it goes on at x + shift.
+                              First order only (recon must be 0 on such a mesh) */
 } ugkwp_bc_type;
 
 typedef struct {
@@ -74,6 +79,7 @@ typedef struct {
     double T_w;     /* wall temperature (diffuse) */
     double U_w[3];  /* wall velocity, tangential to the wall (diffuse) */
     double W_inf[5];/* free-stream conservative state (far field) */
+    double shift[3];/* periodic: translation from this face to its partner */
 } ugkwp_bc;
 
 /* One mesh, host arrays.  Cells: 4-node tetrahedra (type 4) or 8-node axis-aligned boxes

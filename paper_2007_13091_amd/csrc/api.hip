@@ -244,6 +244,11 @@ int32_t prepare_batch(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p
         int32_t st = ugkwp::prepare_mesh(m[k], parts[k], err);
         long long ck = 0;
         if (st == UGKWP_OK) st = check_params(p[k], parts[k].nc, ck, err);
+        if (st == UGKWP_OK && parts[k].nper > 0 && p[k].recon != 0) {
+            // the least-squares gradients would need the partner's centre shifted
+            err = "params: periodic faces need recon = 0 (first order)";
+            st = UGKWP_E_ARG;
+        }
         if (st == UGKWP_OK && p[k].precision != p[0].precision) {
             err = "params: every instance of a batch must use the same precision";
             st = UGKWP_E_ARG;
@@ -418,6 +423,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         bcs[b].Tw = H.bcs[b].T_w;
         for (int d = 0; d < 3; ++d) bcs[b].Uw[d] = H.bcs[b].U_w[d];
         for (int k = 0; k < 5; ++k) bcs[b].Winf[k] = H.bcs[b].W_inf[k];
+        for (int d = 0; d < 3; ++d) bcs[b].shift[d] = H.bcs[b].shift[d];
     }
     std::vector<int4> ffi((size_t)H.nff);
     for (int32_t j = 0; j < H.nff; ++j) ffi[j] = make_int4(H.ff_cell[j], H.ff_lf[j] | (H.ff_tri[j] << 8), H.ff_bf[j], H.ff_bc[j]);

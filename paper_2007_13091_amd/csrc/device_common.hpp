@@ -19,12 +19,18 @@ enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5 
 // bucket key flag: the particle stays collisionless in the cell it started in
 constexpr int32_t kStayBit = 1 << 30;
 
+// the neighbour's local face of a slot whose face is periodic: the neighbour's local face lf2
+// and the face's boundary condition b (whose shift a crossing particle takes) as
+// lf2 + kPeriodicEntry (b + 1); plain neighbours have entries below kPeriodicEntry
+constexpr int32_t kPeriodicEntry = 8;
+
 struct DevBC {
     int32_t type;
     int32_t pad;
     double Tw;
     double Uw[3];
     double Winf[5];
+    double shift[3];  // periodic: a particle crossing a face of this condition goes on at x + shift
 };
 
 // Parameters of one instance of a batch (constant after set-up).  An instance owns a

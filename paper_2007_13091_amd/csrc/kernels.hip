@@ -1422,7 +1422,16 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
         }
         const int2 nb = D.nbl[c * 6 + bf];
         if (nb.x >= 0) {
-            entry = nb.y;
+            int ent = nb.y;
+            if (ent >= kPeriodicEntry) {
+                // periodic face: the particle goes on from the partner face at x + shift
+                const DevBC &pb = D.bc[ent / kPeriodicEntry - 1];
+                x[0] = x[0] + (R)pb.shift[0];
+                x[1] = x[1] + (R)pb.shift[1];
+                x[2] = x[2] + (R)pb.shift[2];
+                ent = ent % kPeriodicEntry;
+            }
+            entry = ent;
             c = nb.x;
             continue;
         }

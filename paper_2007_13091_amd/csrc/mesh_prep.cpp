@@ -57,8 +57,14 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     }
     for (int32_t b = 0; b < m.n_bc; ++b) {
         const ugkwp_bc &bc = m.bc[b];
-        if (bc.type < UGKWP_BC_SPECULAR || bc.type > UGKWP_BC_FARFIELD) {
+        if (bc.type < UGKWP_BC_SPECULAR || bc.type > UGKWP_BC_PERIODIC) {
             err = "mesh: unknown boundary type";
+            return UGKWP_E_ARG;
+        }
+        if (bc.type == UGKWP_BC_PERIODIC &&
+            !(std::isfinite(bc.shift[0]) && std::isfinite(bc.shift[1]) && std::isfinite(bc.shift[2]) &&
+              std::fabs(bc.shift[0]) + std::fabs(bc.shift[1]) + std::fabs(bc.shift[2]) > 0.0)) {
+            err = "mesh: a periodic boundary needs a finite, nonzero shift";
             return UGKWP_E_ARG;
         }
         if (bc.type == UGKWP_BC_DIFFUSE && !(bc.T_w > 0.0)) {
@@ -261,6 +267,11 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     rest.reserve(open.size());
     for (auto &kv : open) rest.emplace_back(kv.second.cell, kv.second.lf);
     std::sort(rest.begin(), rest.end());
+    // periodic faces are paired after the others: (cell, local face, bc)
+    struct Per {
+        int32_t c, lf, bc;
+    };
+    std::vector<Per> per;
     for (auto &cl : rest) {
         int32_t c = cl.first, lf = cl.second;
         const int64_t *cn = m.cell_nodes + m.cell_node_off[c];
@@ -278,6 +289,11 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
         int32_t f = (int32_t)fown.size();
         const int32_t bci = it->second.bc;
         const int64_t b = it->second.b;
+        if (m.bc[bci].type == UGKWP_BC_PERIODIC) {
+            H.bf_lf[(size_t)b] = (uint8_t)lf;
+            per.push_back(Per{c, lf, bci});
+            continue;
+        }
         fown.push_back(c);
         fnb.push_back(-1 - bci);
         for (int d = 0; d < 3; ++d) fn.push_back(H.plane[4 * so + d]);
@@ -320,6 +336,76 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
     if (matched_b != m.n_bfaces) {
         err = "mesh: a boundary face does not belong to any cell";
         return UGKWP_E_MESH;
+    }
+    // periodic pairs: face A (condition b) leads to the periodic face B whose centre is A's
+    // centre plus b's shift and whose condition has the opposite shift.  Centres are matched
+    // through a hash of their coordinates quantised at 1e-9 of the domain's extent (the 27
+    // neighbouring quanta are searched, so a rounding split cannot hide a partner).  The
+    // pair becomes one interior face owned by the earlier of the two in (cell, face) order.
+    if (!per.empty()) {
+        double ext = 0.0;
+        for (int64_t i = 0; i < 3 * m.n_nodes; ++i) ext = std::max(ext, std::fabs(m.xyz[i]));
+        const double q = 1e-9 * (ext > 0.0 ? ext : 1.0);
+        auto qkey = [q](const double *x, int dx, int dy, int dz) {
+            const int64_t a = (int64_t)std::llround(x[0] / q) + dx, b = (int64_t)std::llround(x[1] / q) + dy,
+                          c = (int64_t)std::llround(x[2] / q) + dz;
+            return std::array<int64_t, 3>{a, b, c};
+        };
+        struct QHash {
+            size_t operator()(const std::array<int64_t, 3> &k) const {
+                return (size_t)(k[0] * 0x9E3779B97F4A7C15ULL ^ k[1] * 0xC2B2AE3D27D4EB4FULL ^ k[2] * 0x165667B19E3779F9ULL);
+            }
+        };
+        std::unordered_map<std::array<int64_t, 3>, std::vector<int32_t>, QHash> at;
+        for (int32_t i = 0; i < (int32_t)per.size(); ++i)
+            at[qkey(&H.lfx[((size_t)per[i].c * kMaxFaces + per[i].lf) * 3], 0, 0, 0)].push_back(i);
+        std::vector<char> done(per.size(), 0);
+        for (int32_t i = 0; i < (int32_t)per.size(); ++i) {
+            if (done[i]) continue;
+            const Per &A = per[i];
+            const double *s = m.bc[A.bc].shift;
+            const double *xa = &H.lfx[((size_t)A.c * kMaxFaces + A.lf) * 3];
+            const double t[3] = {xa[0] + s[0], xa[1] + s[1], xa[2] + s[2]};
+            int32_t jb = -1;
+            for (int dx = -1; dx <= 1 && jb < 0; ++dx)
+                for (int dy = -1; dy <= 1 && jb < 0; ++dy)
+                    for (int dz = -1; dz <= 1 && jb < 0; ++dz) {
+                        auto hit = at.find(qkey(t, dx, dy, dz));
+                        if (hit == at.end()) continue;
+                        for (int32_t j : hit->second) {
+                            if (j == i || done[j]) continue;
+                            const double *sb = m.bc[per[j].bc].shift;
+                            const double *xb = &H.lfx[((size_t)per[j].c * kMaxFaces + per[j].lf) * 3];
+                            if (std::fabs(sb[0] + s[0]) + std::fabs(sb[1] + s[1]) + std::fabs(sb[2] + s[2]) > 1e-12 * ext)
+                                continue;
+                            if (std::fabs(xb[0] - t[0]) + std::fabs(xb[1] - t[1]) + std::fabs(xb[2] - t[2]) > 3e-9 * ext)
+                                continue;
+                            jb = j;
+                            break;
+                        }
+                    }
+            if (jb < 0) {
+                err = "mesh: periodic face " + std::to_string(A.lf) + " of cell " + std::to_string(A.c) +
+                      " has no partner at its centre plus the shift";
+                return UGKWP_E_MESH;
+            }
+            const Per &B = per[jb];
+            done[i] = done[jb] = 1;
+            const size_t sa = (size_t)A.c * kMaxFaces + A.lf, sb = (size_t)B.c * kMaxFaces + B.lf;
+            const int32_t f = (int32_t)fown.size();
+            fown.push_back(A.c);
+            fnb.push_back(B.c);
+            for (int d = 0; d < 3; ++d) fn.push_back(H.plane[4 * sa + d]);
+            for (int d = 0; d < 3; ++d) H.fx.push_back(xa[d]);
+            farea.push_back(larea[sa]);
+            H.nb[sa] = B.c;
+            H.nblf[sa] = B.lf + kPeriodicEntry * (A.bc + 1);
+            H.nb[sb] = A.c;
+            H.nblf[sb] = A.lf + kPeriodicEntry * (B.bc + 1);
+            H.cface[sa] = f + 1;
+            H.cface[sb] = -(f + 1);
+            ++H.nper;
+        }
     }
     H.nff = (int32_t)H.ff_cell.size();
     H.nf = (int32_t)fown.size();
@@ -369,7 +455,11 @@ int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::ve
         app(o.box, h.box);
         app(o.orig, h.orig);
         app(o.edge, h.edge);
-        app(o.nblf, h.nblf);
+        // a periodic entry carries its boundary condition's index, offset like the others
+        for (int32_t v : h.nblf)
+            o.nblf.push_back(v >= kPeriodicEntry ? (v % kPeriodicEntry) + kPeriodicEntry * (v / kPeriodicEntry + boff)
+                                                 : v);
+        o.nper += h.nper;
         for (int32_t v : h.nb) o.nb.push_back(v >= 0 ? v + coff : -1 - (-1 - v + boff));
         for (int32_t v : h.cface) o.cface.push_back(v > 0 ? v + foff : (v < 0 ? v - foff : 0));
         for (int32_t v : h.fown) o.fown.push_back(v + coff);

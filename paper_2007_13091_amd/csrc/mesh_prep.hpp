@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "ugkwp.h"
+#include "device_common.hpp"  // kPeriodicEntry
 
 namespace ugkwp {
 
@@ -38,7 +39,9 @@ struct HostMesh {
     std::vector<int32_t> ff_cell, ff_lf, ff_bf, ff_bc, ff_tri;  // [nff]; ff_bf: input boundary-face index
     std::vector<double> ff_geo;  // [nff][10]: corner p0, edges p1 - p0 and (p2 or p3) - p0, area
     std::vector<uint8_t> bf_lf;  // [n_bfaces]: local face of an input boundary face in its cell
+    int32_t nper = 0;            // periodic face pairs (each one interior face)
 };
+
 
 // Returns UGKWP_OK or UGKWP_E_ARG / UGKWP_E_MESH with a message in *err.
 int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &out, std::string &err);

@@ -28,7 +28,8 @@ N_PROFILE_SLOTS = 12
 
 
 class UgkwpBC(C.Structure):
-    _fields_ = [("type", C.c_int32), ("T_w", C.c_double), ("U_w", C.c_double * 3), ("W_inf", C.c_double * 5)]
+    _fields_ = [("type", C.c_int32), ("T_w", C.c_double), ("U_w", C.c_double * 3), ("W_inf", C.c_double * 5),
+                ("shift", C.c_double * 3)]
 
 
 class UgkwpMesh(C.Structure):
@@ -140,6 +141,8 @@ class _MeshArgs:
                 self.bcs[i].U_w[d] = b.Uw[d]
             for k in range(5):
                 self.bcs[i].W_inf[k] = b.Winf[k]
+            for d in range(3):
+                self.bcs[i].shift[d] = getattr(b, "shift", (0.0, 0.0, 0.0))[d]
         self.s = UgkwpMesh(self.xyz.shape[0], _ptr(self.xyz, C.c_double), self.ct.shape[0], _ptr(self.ct, C.c_uint8),
                            _ptr(self.off, C.c_int64), _ptr(self.cn, C.c_int64), self.bf.shape[0],
                            _ptr(self.bf, C.c_int64), _ptr(self.bt, C.c_int32), len(mesh.bcs), self.bcs)

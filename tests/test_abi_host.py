@@ -116,3 +116,41 @@ def test_reconstruction_parameters():
     p.recon, p.venkat_k = 2, 0.0
     with pytest.raises(U.UgkwpError):
         U.workspace_bytes(w.mesh, p)
+
+
+def test_periodic_meshes_are_paired_or_refused():
+    """Periodic faces (test support): a fully periodic box is accepted (hexahedra and
+    tetrahedra); a periodic face without a partner is a mesh error; second order and a zero
+    shift are refused."""
+    for tets in (False, True):
+        w = wl.periodic_box(n=(3, 2, 2), tets=tets)
+        assert U.workspace_bytes(w.mesh, w.params) > 0
+    w = wl.periodic_box(n=(3, 2, 2))
+    # the x-high side turned into a wall: the x-low faces have no partner
+    bcs = list(w.mesh.bcs) + [wl.BC(wl.BC_SPECULAR)]
+    bt = np.where(w.mesh.bface_bc == 1, len(bcs) - 1, w.mesh.bface_bc).astype(np.int32)
+    m = w.mesh
+    bad = wl.Mesh(m.xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes, bt, bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_MESH
+    # a shift that does not land on the opposite side
+    bcs = [copy.copy(b) for b in m.bcs]
+    bcs[0].shift = (0.5, 0.0, 0.0)
+    bad = wl.Mesh(m.xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes, m.bface_bc, bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_MESH
+    # a zero shift
+    bcs = [copy.copy(b) for b in m.bcs]
+    bcs[0].shift = (0.0, 0.0, 0.0)
+    bad = wl.Mesh(m.xyz, m.cell_type, m.cell_node_off, m.cell_nodes, m.bface_nodes, m.bface_bc, bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(bad, w.params)
+    assert e.value.status == U.E_ARG
+    # second order on a periodic mesh
+    p = copy.copy(w.params)
+    p.recon = 1
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(m, p)
+    assert e.value.status == U.E_ARG

@@ -76,7 +76,8 @@ def test_mixed_batch_with_far_field_and_tets():
                              jitter=0.15),
           wl.cavity(n=4, n_ref=60),
           wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=60, kn=0.05, perturb=0.3),
-          wl.closed_box(n=(3, 2, 2), n_ref=80, kn=2.0, bc=wl.BC_DIFFUSE, perturb=0.3)]
+          wl.closed_box(n=(3, 2, 2), n_ref=80, kn=2.0, bc=wl.BC_DIFFUSE, perturb=0.3),
+          wl.periodic_box(n=(4, 3, 2), n_ref=60, kn=0.1)]
     _run_batch(ws, 6, name="mixed-batch")
 
 

@@ -80,6 +80,31 @@ def test_diffuse_box_rarefied_many_bounces():
     run_pair(w, 6, name="diffuse-kn2")
 
 
+@pytest.mark.parametrize("tets", [False, True])
+def test_periodic_box(tets):
+    """Periodic faces (test support): every face interior, particles re-entering through
+    the partner face at x + shift."""
+    w = wl.periodic_box(n=(5, 4, 3), n_ref=80, kn=0.05, tets=tets)
+    s, _ = run_pair(w, 8, every=2, name="periodic" + ("-tets" if tets else ""))
+    assert s.step(0)["wall_hits"] == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_periodic_box_conserves_all_five_totals(precision):
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.periodic_box(n=(6, 5, 4), n_ref=100, kn=0.02)
+    s = Solver(w.mesh, w.params, precision=precision)
+    s.init_state(w.W0)
+    vol, _, _ = s.geometry()
+    t0 = (s.moments(0) * vol[:, None]).sum(0)
+    st = s.step(20)
+    assert st["crossings"] > 0 and st["n_escaped"] == 0
+    t1 = (s.moments(0) * vol[:, None]).sum(0)
+    _say("periodic totals", precision, t0, t1)
+    np.testing.assert_allclose(t1, t0, rtol=5e-14, atol=0)
+
+
 def test_free_molecular_sod():
     w = wl.sod(nx=20, ny=2, nz=2, n_ref=100)
     w.params.mu_ref = 1e30
