@@ -130,6 +130,57 @@ def timed_run(w, precision, warmup, steps):
     return t1 - t0, st1["moved_total"] - moved0, kern, cfg, dom, st1
 
 
+# algorithmic bytes of the first-order flux per face: both cells' W (2 x 40), the face's
+# geometry (normal, area, owner and neighbour: 48) and its flux out (40)
+BYTES_PER_FACE = 168
+
+
+def gks_side(steps, warmup):
+    """Side number: the GKS limit of the scheme, the cavity at Kn 1e-6, FP64 plain.  There
+    exp(-dt/tau) underflows to 0, so no particle is ever sampled and a step is the wave part
+    alone (at Kn 1e-4 the sampling rule, N_sam = 2 ceil(N_ref rho^hp / (2 (rho^p + rho^hp))),
+    still draws N_ref particles of tiny mass per cell once the previous ones have collided).
+    Cell-steps/s, and the flux kernel's position against HBM (its time from hip events over
+    the warm-up steps)."""
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.cavity(kn=1e-6)
+    s = Solver(w.mesh, w.params)
+    s.init_state(w.W0)
+    s.step(1, stats=False)
+    s.profile(True)
+    s.profile_read()
+    s.step(max(warmup - 1, 1), stats=False)
+    warm = s.profile_read()
+    s.profile(False)
+    st0 = s.step(0, stats=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = s.step(0, stats=True)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    el = t1 - t0
+    nc = w.mesh.n_cells
+    faces = (6 * nc + int(w.mesh.bface_nodes.shape[0])) // 2  # box hexes: shared faces counted twice
+    flux_ms = warm["flux"][0] / max(warm["flux"][1], 1)
+    achieved = BYTES_PER_FACE * faces / (flux_ms * 1e-3) / 1e9
+    return {"workload": "cavity 32^3 at Kn 1e-6 (GKS limit: no particles), FP64 plain",
+            "cell_steps_per_s": nc * steps / el, "ms_per_step": el / steps * 1e3, "steps": steps,
+            "particles_per_step": int((st1["moved_total"] - st0["moved_total"]) / steps),
+            "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in warm.items()},
+            "flux_roofline": {"kernel": "k_flux<double, 128>", "kernel_avg_ms": round(flux_ms, 4),
+                              "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_face": BYTES_PER_FACE,
+                              "faces": faces}}
+
+
 def stated_fp32_error():
     """The FP32 form's error against the FP64 oracle, as measured by tests/test_gpu_fp32.py
     and committed under profiles/ (L1 and Linf of rho, |U|, T, with the seed-to-seed noise)."""
@@ -246,6 +297,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-gks", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=8)
     ap.add_argument("--batched-only", action="store_true",
@@ -301,6 +353,8 @@ def main():
                             "stated_error": stated_fp32_error()}
     if not args.no_batched:
         out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)
+    if not args.no_gks:
+        out["gks_limit"] = gks_side(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
