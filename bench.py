@@ -135,6 +135,9 @@ def timed_run(w, precision, warmup, steps):
 BYTES_PER_FACE = 168
 
 
+GKS_CAPACITY = 65536
+
+
 def gks_side(steps, warmup):
     """Side number: the GKS limit of the scheme, the cavity at Kn 1e-6, FP64 plain.  There
     exp(-dt/tau) underflows to 0, so no particle is ever sampled and a step is the wave part
@@ -148,7 +151,9 @@ def gks_side(steps, warmup):
     from paper_2007_13091_amd.ugkwp import Solver
 
     w = wl.cavity(kn=1e-6)
-    s = Solver(w.mesh, w.params)
+    # no particle is ever sampled: a small capacity keeps the particle kernels' grids, which
+    # cover the capacity, from launching blocks that find nothing to do
+    s = Solver(w.mesh, w.params, capacity=GKS_CAPACITY)
     s.init_state(w.W0)
     s.step(1, stats=False)
     s.profile(True)
@@ -173,12 +178,53 @@ def gks_side(steps, warmup):
     achieved = BYTES_PER_FACE * faces / (flux_ms * 1e-3) / 1e9
     return {"workload": "cavity 32^3 at Kn 1e-6 (GKS limit: no particles), FP64 plain",
             "cell_steps_per_s": nc * steps / el, "ms_per_step": el / steps * 1e3, "steps": steps,
-            "particles_per_step": int((st1["moved_total"] - st0["moved_total"]) / steps),
+            "particles_per_step": int((st1["moved_total"] - st0["moved_total"]) / steps), "capacity": GKS_CAPACITY,
             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in warm.items()},
             "flux_roofline": {"kernel": "k_flux<double, 128>", "kernel_avg_ms": round(flux_ms, 4),
                               "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_face": BYTES_PER_FACE,
                               "faces": faces}}
+
+
+def configs_run():
+    """The other configurations, timed (not part of the default run): the shock tube over
+    its 40 steps (FP64; launch-bound at 200 cells), and the Mach 10 cube (1.2e6 tets) and the
+    Mach 15 vehicle at Kn 1e-3 (3.1e6 tets) in both forms over the steps after the first
+    (sampling from an empty start) and before their wakes empty (the impulsive start)."""
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    def one(w, precision, warm, steps):
+        s = Solver(w.mesh, w.params, precision=precision)
+        s.init_state(w.W0)
+        st0 = s.step(warm, stats=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, stats=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st1 = s.step(0, stats=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        el = t1 - t0
+        moves = st1["moved_total"] - st0["moved_total"]
+        return {"value": moves / el, "unit": "particle moves/s", "cell_steps_per_s": w.mesh.n_cells * steps / el,
+                "ms_per_step": el / steps * 1e3, "particles_per_step": int(moves / steps), "steps": steps,
+                "after_steps": warm}
+
+    out = {}
+    w = wl.sod()
+    out["sod_50x2x2_fp64"] = one(w, 0, 1, 39)
+    w = wl.cube()
+    out["cube_mach10_fp64"] = one(w, 0, 1, 3)
+    out["cube_mach10_fp32"] = one(w, 1, 1, 3)
+    w = wl.vehicle(kn=1e-3)
+    out["vehicle_mach15_kn1e-3_fp64"] = one(w, 0, 1, 2)
+    out["vehicle_mach15_kn1e-3_fp32"] = one(w, 1, 1, 2)
+    return out
 
 
 def stated_fp32_error():
@@ -300,6 +346,8 @@ def main():
     ap.add_argument("--no-gks", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=8)
+    ap.add_argument("--configs", action="store_true",
+                    help="time the tube, the cube and the vehicle (their own JSON object; not the bench line)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg and print its JSON object (for profiling it alone)")
     args = ap.parse_args()
@@ -309,6 +357,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.configs:
+        print(json.dumps({"configs": configs_run()}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched_form": batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)}),

@@ -1054,8 +1054,15 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     const int nc = D.nc;
     const Scalars *sc = D.sc;
     const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;  // even
+    // S = P + the new particles' sums, lane k < 5 writing component k; a cell that samples
+    // nothing copies P (loaded in the same round as its count)
+    const double Pk = lane < 5 ? D.P[lane * nc + c] : 0.0;
+    if (ns == 0) {
+        if (lane < 5) D.S[lane * nc + c] = Pk + 0.0;
+        return;
+    }
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (ns > 0) {
+    {
         const Particles pa = D.pa[buf];
         const long long base = sc->n_old + D.samoff[c];
         const int inst = inst_of(D, c);
@@ -1137,10 +1144,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane == 0) {
+    double ak = acc[0];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) D.S[k * nc + c] = D.P[k * nc + c] + acc[k];
-    }
+    for (int k = 1; k < 5; ++k)
+        if (lane == k) ak = acc[k];
+    if (lane < 5) D.S[lane * nc + c] = D.P[lane * nc + c] + ak;
 }
 
 // ---------------------------------------------------------------------------------------
