@@ -14,6 +14,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,11 +36,25 @@ BYTES_PER_COLLIDED = {"double": 52, "float": 40}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_digest():
+def code_text(src):
+    """C++ source without its comments and with runs of white space made one space, so that
+    an edit of a comment or of the layout leaves the digest alone (the sources hold no string
+    literal with comment markers)."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
+def kernel_source_digest(read=None):
+    """Digest of the kernel sources' code (comments and layout aside); `read(name)` gives a
+    source's text, by default the file in the package."""
+    if read is None:
+        def read(f):
+            with open(os.path.join(ROOT, "paper_2007_13091_amd", "csrc", f)) as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in ("kernels.hip", "device_common.hpp"):
-        with open(os.path.join(ROOT, "paper_2007_13091_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(code_text(read(f)).encode())
     return h.hexdigest()[:16]
 
 

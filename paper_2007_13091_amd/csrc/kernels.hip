@@ -36,7 +36,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
 constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
-constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (1, 2 and 4 measured alike)
+constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (2 and 4 are slower in FP32)
 
 // ---------------------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11); counter = (uid, step, tag<<32|sub, 0),
