@@ -96,7 +96,7 @@ typedef struct {
     int64_t n_bfaces;
     const int64_t *bface_nodes;   /* [n_bfaces][4] */
     const int32_t *bface_bc;      /* [n_bfaces] */
-    int32_t n_bc;
+    int32_t n_bc;                 /* below 2^27 (over all instances of a batch) */
     const ugkwp_bc *bc;           /* [n_bc] */
 } ugkwp_mesh;
 

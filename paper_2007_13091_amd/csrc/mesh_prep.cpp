@@ -425,15 +425,21 @@ int32_t prepare_mesh(const ugkwp_mesh &m, HostMesh &H, std::string &err) {
 
 int32_t concat_meshes(const std::vector<HostMesh> &parts, HostMesh &out, std::vector<InstRange> &ranges,
                       std::string &err) {
-    int64_t nc = 0, nf = 0, nff = 0, nbf = 0;
+    int64_t nc = 0, nf = 0, nff = 0, nbf = 0, nbc = 0;
     for (const HostMesh &h : parts) {
         nc += h.nc;
         nf += h.nf;
         nff += h.nff;
         nbf += (int64_t)h.bf_lf.size();
+        nbc += (int64_t)h.bcs.size();
     }
     if (nc > 2147483647LL - 1 || nf > 2147483647LL - 1 || nbf > 2147483647LL - 1) {
         err = "batch: more than 2^31 - 1 cells, faces or boundary faces in total";
+        return UGKWP_E_ARG;
+    }
+    // a periodic slot's entry, lf + kPeriodicEntry (bc + 1), must fit in 32 bits
+    if (nbc >= (int64_t(1) << 27)) {
+        err = "batch: 2^27 or more boundary conditions in total";
         return UGKWP_E_ARG;
     }
     HostMesh o;
