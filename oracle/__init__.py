@@ -79,6 +79,9 @@ def lib():
         L.orc_set_recon.argtypes = [vp, C.c_int, d]
         L.orc_gradients.restype = C.c_int
         L.orc_gradients.argtypes = [vp, P(d), P(d), P(d)]
+        L.orc_set_averaging.argtypes = [vp, i64]
+        L.orc_average.restype = C.c_int
+        L.orc_average.argtypes = [vp, P(d), P(d), P(i64)]
         L.orc_track.restype = C.c_int
         L.orc_track.argtypes = [vp, P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
         _lib = L
@@ -247,6 +250,20 @@ class Oracle:
             rc = lib().orc_step(self.h)
             if rc != OK:
                 raise OracleError(f"orc_step failed with status {rc}")
+
+    def set_averaging(self, n_avg):
+        """Average the steps n > n_avg from now on (Sec. 2.4(c)); n_avg < 0: off."""
+        lib().orc_set_averaging(self.h, int(n_avg))
+
+    def average(self):
+        """(Wbar [nc][5], relative change of the last averaged step, steps averaged)."""
+        Wb = np.zeros((self.nc, 5))
+        r = C.c_double(0)
+        n = C.c_int64(0)
+        rc = lib().orc_average(self.h, _p(Wb, C.c_double), C.byref(r), C.byref(n))
+        if rc != OK:
+            raise OracleError(f"orc_average failed with status {rc} (no step averaged yet)")
+        return Wb, r.value, int(n.value)
 
     @property
     def step_index(self):

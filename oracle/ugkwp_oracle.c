@@ -16,6 +16,7 @@
  *   (Sec. 2.4(b)), free-flight times (Eq. sampling_of_free_transport_time), free transport
  *   (Sec. 2.3), particle sums and the conservative update (Eq. update_macro_variables),
  *   deletion of collided particles (the four-step particle procedure of Sec. 2.3).
+ * Optionally, time averaging of W for steady states (Sec. 2.4(c)).
  * All arithmetic is IEEE double with libm transcendental functions; it must be compiled
  * with -ffp-contract=off and without -ffast-math.
  *
@@ -668,6 +669,12 @@ typedef struct oracle {
     double *px, *pu, *pm;
     int64_t *pc;
     uint64_t *pid;
+    /* time averaging (Sec. 2.4(c)): steps n > avg_from are averaged (avg_from < 0: off) */
+    int64_t avg_from;
+    double *avgA;      /* [nc][5] sum of dt^n W^n */
+    double avg_D;      /* sum of dt^n */
+    int64_t avg_n;     /* steps averaged */
+    double avg_res;    /* relative change of the average in the last averaged step */
     /* last step statistics */
     double st_dt;
     int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits, st_injected;
@@ -738,6 +745,9 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     o->edge = (double *)xcalloc(9 * nc, sizeof(double));
     o->W = (double *)xcalloc(5 * nc, sizeof(double));
     o->P = (double *)xcalloc(5 * nc, sizeof(double));
+    o->avgA = (double *)xcalloc(5 * nc, sizeof(double));
+    o->avg_from = -1;
+    o->avg_res = INFINITY;
     o->nleft = (int64_t *)xcalloc(nc, sizeof(int64_t));
     o->nbc = n_bc;
     o->bc = (obc_t *)xcalloc(n_bc, sizeof(obc_t));
@@ -1020,7 +1030,7 @@ void orc_destroy(oracle_t *o)
     free(o->bo); free(o->be1); free(o->be2); free(o->barea); free(o->btri);
     free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
     free(o->lfx); free(o->fx);
-    free(o->bc); free(o->W); free(o->P); free(o->nleft);
+    free(o->bc); free(o->W); free(o->P); free(o->avgA); free(o->nleft);
     free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
     free(o);
 }
@@ -1064,6 +1074,33 @@ int orc_set_state(oracle_t *o, const double *W)
     o->np = 0;
     o->step = 0;
     o->t = 0.0;
+    memset(o->avgA, 0, sizeof(double) * 5 * o->nc);
+    o->avg_D = 0.0;
+    o->avg_n = 0;
+    o->avg_res = INFINITY;
+    return ORC_OK;
+}
+
+/* Average the steps n > n_avg (counted from orc_set_state) from now on; n_avg < 0 turns
+   averaging off.  Clears what was accumulated. */
+void orc_set_averaging(oracle_t *o, int64_t n_avg)
+{
+    o->avg_from = n_avg < 0 ? -1 : n_avg;
+    memset(o->avgA, 0, sizeof(double) * 5 * o->nc);
+    o->avg_D = 0.0;
+    o->avg_n = 0;
+    o->avg_res = INFINITY;
+}
+
+/* Wbar ([nc][5], may be NULL), the relative change of the last averaged step and the number
+   of steps averaged; ORC_E_ARG while nothing has been averaged. */
+int orc_average(const oracle_t *o, double *Wbar, double *residual, int64_t *n_averaged)
+{
+    if (o->avg_n == 0) return ORC_E_ARG;
+    if (Wbar)
+        for (int64_t i = 0; i < 5 * o->nc; ++i) Wbar[i] = o->avgA[i] / o->avg_D;
+    if (residual) *residual = o->avg_res;
+    if (n_averaged) *n_averaged = o->avg_n;
     return ORC_OK;
 }
 
@@ -1597,6 +1634,36 @@ int orc_sample_only(oracle_t *o, double *dt)
     return st;
 }
 
+/* Time averaging for steady states (Sec. 2.4(c)): the average over the steps n > N_avg,
+   each weighted by the step dt^n that produced W^n,
+       Wbar^n = sum_{m > N_avg} dt^m W^m / sum_{m > N_avg} dt^m,
+   kept as the running sums A = sum dt^m W^m and D = sum dt^m.  Its relative change from
+   Wbar^{n-1} (the paper leaves the norm open) in the volume-weighted L1 norm of the whole
+   field, sum_c Omega_c sum_k |Wbar^n_ck - Wbar^{n-1}_ck| / sum_c Omega_c sum_k |Wbar^n_ck|
+   (+infinity until two steps are averaged). */
+static void phase_average(oracle_t *o, double dt)
+{
+    double diff = 0.0, mag = 0.0;
+    const double d0 = o->avg_D, d1 = d0 + dt;
+    const int prev = o->avg_n > 0;
+    for (int64_t c = 0; c < o->nc; ++c) {
+        double dc = 0.0, mc = 0.0;
+        for (int k = 0; k < 5; ++k) {
+            const double a0 = o->avgA[5 * c + k];
+            const double a1 = a0 + dt * o->W[5 * c + k];
+            o->avgA[5 * c + k] = a1;
+            const double wb1 = a1 / d1;
+            mc = mc + fabs(wb1);
+            if (prev) dc = dc + fabs(wb1 - a0 / d0);
+        }
+        mag = mag + o->vol[c] * mc;
+        diff = diff + o->vol[c] * dc;
+    }
+    o->avg_res = prev ? diff / mag : INFINITY;
+    o->avg_D = d1;
+    o->avg_n += 1;
+}
+
 int orc_step(oracle_t *o)
 {
     const int64_t nc = o->nc, nf = o->nf;
@@ -1733,6 +1800,7 @@ int orc_step(oracle_t *o)
     o->st_wallhits = nwall;
     o->step += 1;
     o->t += dt;
+    if (o->avg_from >= 0 && o->step > o->avg_from) phase_average(o, dt);
 done:
     cellq_free(&q);
     free(Phi); free(S); free(E); free(Pn); free(nl); free(tin); free(ein);
