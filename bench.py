@@ -242,6 +242,55 @@ def configs_run():
     return out
 
 
+# algorithmic bytes of the time averaging per cell: W and the running sum read, the sum
+# written, the volume read (5 x 8 x 3 + 8)
+BYTES_PER_AVG_CELL = 128
+
+
+def averaging_side(steps, warmup, ms_plain):
+    """Side number: the cost of time averaging (Sec. 2.4(c)) on the FP64 cavity, the whole
+    step with averaging on against the plain step, and the averaging kernel's position
+    against HBM (k_avg_cells and k_avg_fin are timed with k_finalize in one group; the
+    group's time with averaging off is subtracted)."""
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.cavity()
+    s = Solver(w.mesh, w.params)
+    s.init_state(w.W0)
+    s.step(warmup, stats=False)
+    s.profile(True, slots=["finalize"])
+    s.profile_read()
+    s.step(warmup, stats=False)
+    fin0 = s.profile_read()["finalize"]
+    s.set_averaging(0)
+    s.step(warmup, stats=False)
+    fin1 = s.profile_read()["finalize"]
+    s.profile(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, res, n = s.average()
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    nc = w.mesh.n_cells
+    avg_ms = fin1[0] / max(fin1[1], 1) - fin0[0] / max(fin0[1], 1)
+    achieved = BYTES_PER_AVG_CELL * nc / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
+    ms = (t1 - t0) / steps * 1e3
+    return {"workload": "cavity 32^3, FP64 plain, every step averaged", "ms_per_step": ms,
+            "ms_per_step_without": ms_plain, "steps_averaged": int(n[0]), "last_relative_change": float(res[0]),
+            "averaging_kernels_ms": round(avg_ms, 4),
+            "roofline": {"bound": "hbm", "achieved": None if achieved is None else round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": None if achieved is None else round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_cell": BYTES_PER_AVG_CELL, "cells": nc}}
+
+
 def stated_fp32_error():
     """The FP32 form's error against the FP64 oracle, as measured by tests/test_gpu_fp32.py
     and committed under profiles/ (L1 and Linf of rho, |U|, T, with the seed-to-seed noise)."""
@@ -359,6 +408,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gks", action="store_true")
+    ap.add_argument("--no-avg", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=8)
     ap.add_argument("--configs", action="store_true",
@@ -421,6 +471,8 @@ def main():
         out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)
     if not args.no_gks:
         out["gks_limit"] = gks_side(args.steps, args.warmup)
+    if not args.no_avg:
+        out["time_averaging"] = averaging_side(args.steps, args.warmup, out["ms_per_step"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

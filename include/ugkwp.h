@@ -171,6 +171,26 @@ int32_t ugkwp_instance_cells(const ugkwp_ctx *ctx, int32_t inst, int64_t *cell0,
  * out_is_device != 0.  Synchronises the stream. */
 int32_t ugkwp_moments(ugkwp_ctx *ctx, int32_t which, double *out, int32_t out_is_device);
 
+/* Time averaging for steady states (Sec. 2.4(c)).  From now on, every step n > n_avg
+ * (n counted per instance from ugkwp_init_state) adds its state W^n, weighted by its own time
+ * step dt^n, to the running average Wbar = sum dt^n W^n / sum dt^n of each instance.  Clears
+ * whatever was accumulated; n_avg < 0 turns averaging off.  ugkwp_init_state clears the sums
+ * and keeps the setting.  A captured step graph is dropped and captured again.  Synchronises
+ * when a state is present.  Device memory: the sums live in the workspace (40 bytes per
+ * cell). */
+int32_t ugkwp_set_averaging(ugkwp_ctx *ctx, int64_t n_avg);
+
+/* The time average and its convergence measure (Sec. 2.4(c)).
+ * Wbar: [n_cells][5] conservative, host memory unless out_is_device != 0; NULL: not copied.
+ * residual: [n_inst] host, NULL: not copied.  The relative change of each instance's average
+ *   in its last averaged step, in the volume-weighted L1 norm of the whole field:
+ *   sum_c Omega_c sum_k |Wbar^n_ck - Wbar^{n-1}_ck| / sum_c Omega_c sum_k |Wbar^n_ck|.  The
+ *   paper declares a steady state converged when this falls below a tolerance such as 1e-8.
+ *   +infinity until two steps have been averaged.
+ * n_averaged: [n_inst] host, NULL: not copied; steps averaged so far.
+ * UGKWP_E_STATE when averaging is off or no step has been averaged yet.  Synchronises. */
+int32_t ugkwp_average(ugkwp_ctx *ctx, double *Wbar, int32_t out_is_device, double *residual, int64_t *n_averaged);
+
 /* Number of particles currently held (synchronises). */
 int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n);
 

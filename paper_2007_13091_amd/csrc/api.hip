@@ -197,6 +197,8 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
         P.cell = C.take<int32_t>((size_t)cap);
     }
     D.sc = C.take<Scalars>(1);
+    D.avgA = C.take<double>(5 * nc);
+    D.avgpart = C.take<double>(2 * (size_t)n_inst * ugkwp::kAvgBlocks);
     return (C.off + 255) & ~size_t(255);
 }
 
@@ -375,6 +377,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
     }
     const HostMesh &H = ctx->H;
+    D.avg_from = -1;
     D.nc = H.nc;
     D.nf = H.nf;
     D.nbc = (int32_t)H.bcs.size();
@@ -496,6 +499,7 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     ugkwp::launch_fill_i32(D.nleft, (long long)nc, 0, s);
     ugkwp::launch_fill_i32(D.segoff[0], (long long)nc + 1, 0, s);
     ugkwp::launch_fill_i32(D.segoff[1], (long long)nc + 1, 0, s);
+    ugkwp::launch_fill_f64(D.avgA, 5 * (long long)nc, 0.0, s);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
     std::vector<ugkwp::InstS> is((size_t)D.n_inst);
@@ -606,6 +610,54 @@ int32_t ugkwp_moments(ugkwp_ctx *ctx, int32_t which, double *out, int32_t out_is
                                ctx->stream));
     Scalars s;
     return read_scalars(ctx, s);
+}
+
+int32_t ugkwp_set_averaging(ugkwp_ctx *ctx, int64_t n_avg) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "null argument");
+    Dev &D = ctx->D;
+    D.avg_from = n_avg < 0 ? -1 : (long long)n_avg;
+    ctx->drop_graphs();  // a captured step holds the old setting
+    if (!ctx->have_state) return UGKWP_OK;  // ugkwp_init_state clears the sums
+    hipStream_t s = ctx->stream;
+    ugkwp::launch_fill_f64(D.avgA, 5 * (long long)D.nc, 0.0, s);
+    HIPCHK(ctx, hipGetLastError());
+    std::vector<ugkwp::InstS> is((size_t)D.n_inst);
+    HIPCHK(ctx, hipMemcpyAsync(is.data(), D.is, is.size() * sizeof(ugkwp::InstS), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (auto &v : is) {
+        v.avg_D = 0.0;
+        v.avg_n = 0;
+        v.avg_res = 0.0;
+    }
+    HIPCHK(ctx, up(D.is, is, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_average(ugkwp_ctx *ctx, double *Wbar, int32_t out_is_device, double *residual, int64_t *n_averaged) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "null argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "average before init_state");
+    Dev &D = ctx->D;
+    if (D.avg_from < 0) return fail(ctx, UGKWP_E_STATE, "time averaging is off (ugkwp_set_averaging)");
+    hipStream_t s = ctx->stream;
+    std::vector<ugkwp::InstS> is((size_t)D.n_inst);
+    HIPCHK(ctx, hipMemcpyAsync(is.data(), D.is, is.size() * sizeof(ugkwp::InstS), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    for (const auto &v : is)
+        if (v.avg_n < 1) return fail(ctx, UGKWP_E_STATE, "no step has been averaged yet");
+    if (Wbar) {
+        double *scratch = D.S;  // [5][nc] per-step scratch, free between steps
+        ugkwp::launch_avg_out(D, scratch, s);
+        HIPCHK(ctx, hipGetLastError());
+        HIPCHK(ctx, hipMemcpyAsync(Wbar, scratch, sizeof(double) * 5 * (size_t)D.nc,
+                                   out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    }
+    for (size_t i = 0; i < is.size(); ++i) {
+        if (residual) residual[i] = is[i].avg_n >= 2 ? is[i].avg_res : HUGE_VAL;
+        if (n_averaged) n_averaged[i] = is[i].avg_n;
+    }
+    Scalars sc;
+    return read_scalars(ctx, sc);
 }
 
 int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n) {

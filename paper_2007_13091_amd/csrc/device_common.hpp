@@ -53,6 +53,11 @@ struct InstS {
     long long step;
     long long n_alive, n_sampled, n_injected, n_collided, n_escaped;
     long long moved_total;
+    // time averaging: sum of dt over the averaged steps, their number, and the relative change
+    // of the average in the last of them
+    double avg_D;
+    long long avg_n;
+    double avg_res;
 };
 
 // Step scalars of the whole batch, resident in device memory: the host never reads them
@@ -61,6 +66,9 @@ struct InstS {
 // blocks b with b % kWallSeg == s (one counter per segment, not one for the whole grid);
 // a segment holds ceil(blocks / kWallSeg) x (particles per block) entries, so the segments
 // need at most kWallSlack entries beyond the capacity
+// blocks per instance of the averaging kernel (each a contiguous run of its cells)
+constexpr int kAvgBlocks = 64;
+
 constexpr int kWallSeg = 64;
 constexpr long long kWallSlack = (long long)kWallSeg * 1024;
 
@@ -167,6 +175,10 @@ struct Dev {
     int32_t *perm;          // [cap]
     Particles pa[2];
     Scalars *sc;
+    // time averaging: steps n > avg_from are averaged (avg_from < 0: off)
+    long long avg_from;
+    double *avgA;           // [5][nc] sum of dt^n W^n over the averaged steps
+    double *avgpart;        // [n_inst * kAvgBlocks][2] partial sums of the change and the magnitude
 };
 
 }  // namespace ugkwp

@@ -2365,6 +2365,81 @@ __global__ void k_fill(T *p, long long n, T v) {
     if (i < n) p[i] = v;
 }
 
+// ---------------------------------------------------------------------------------------
+// Time averaging for steady states (Sec. 2.4(c)): over the steps n > N_avg of an instance,
+// Wbar = A / D with A = sum dt^n W^n per cell and D = sum dt^n, and the relative change of
+// Wbar in a step, sum_c Omega_c sum_k |Wbar^n - Wbar^{n-1}| / sum_c Omega_c sum_k |Wbar^n|
+// (+infinity until two steps are averaged).  k_avg_cells: kAvgBlocks blocks per instance,
+// each a contiguous run of its cells, fixed per-thread assignment and reduction tree;
+// k_avg_fin: one wave per instance sums its blocks' partials and advances D.  Both run after
+// k_finalize (the instance's step counter and dt are those of the step just taken).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_avg_cells(Dev D) {
+    __shared__ double red[2][256];
+    const int inst = (int)blockIdx.x / kAvgBlocks, j = (int)blockIdx.x % kAvgBlocks;
+    const InstS &I = D.is[inst];
+    if (I.step <= D.avg_from) return;
+    const InstP &P = D.ip[inst];
+    const int nc = D.nc, t = (int)threadIdx.x;
+    const int n = P.cell1 - P.cell0, chunk = (n + kAvgBlocks - 1) / kAvgBlocks;
+    const int c0 = P.cell0 + j * chunk, c1 = min(P.cell1, c0 + chunk);
+    const double dt = I.dt, d0 = I.avg_D, d1 = d0 + dt;
+    const bool prev = I.avg_n > 0;
+    double diff = 0.0, mag = 0.0;
+    for (int c = c0 + t; c < c1; c += 256) {
+        double dc = 0.0, mc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const double a0 = D.avgA[(long long)k * nc + c];
+            const double a1 = a0 + dt * D.W[(long long)k * nc + c];
+            D.avgA[(long long)k * nc + c] = a1;
+            const double wb1 = a1 / d1;
+            mc = mc + fabs(wb1);
+            if (prev) dc = dc + fabs(wb1 - a0 / d0);
+        }
+        const double vol = D.vol[c];
+        mag = mag + vol * mc;
+        diff = diff + vol * dc;
+    }
+    red[0][t] = diff;
+    red[1][t] = mag;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] = red[0][t] + red[0][t + h];
+            red[1][t] = red[1][t] + red[1][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < 2) D.avgpart[2 * (long long)blockIdx.x + t] = red[t][0];
+}
+
+__global__ void __launch_bounds__(64) k_avg_fin(Dev D) {
+    const int inst = (int)blockIdx.x, lane = lane_id();
+    InstS &I = D.is[inst];
+    if (I.step <= D.avg_from) return;
+    double diff = 0.0, mag = 0.0;
+    for (int b = lane; b < kAvgBlocks; b += kWave) {
+        diff = diff + D.avgpart[2 * ((long long)inst * kAvgBlocks + b)];
+        mag = mag + D.avgpart[2 * ((long long)inst * kAvgBlocks + b) + 1];
+    }
+    diff = wave_sum(diff);
+    mag = wave_sum(mag);
+    if (lane == 0) {
+        I.avg_res = I.avg_n > 0 ? diff / mag : __builtin_inf();
+        I.avg_D = I.avg_D + I.dt;
+        I.avg_n = I.avg_n + 1;
+    }
+}
+
+// Wbar = A / D into out, [nc][5]
+__global__ void k_avg_out(Dev D, double *out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= D.nc) return;
+    const double d = D.is[inst_of(D, c)].avg_D;
+    for (int k = 0; k < 5; ++k) out[5 * (long long)c + k] = D.avgA[(long long)k * D.nc + c] / d;
+}
+
 // field output for ugkwp_moments, [nc][5] in out
 __global__ void k_moments(Dev D, int which, double *out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2582,7 +2657,15 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
     k_finalize<<<1, 256, 0, s>>>(D, buf);
+    if (D.avg_from >= 0) {
+        k_avg_cells<<<(unsigned)(D.n_inst * kAvgBlocks), 256, 0, s>>>(D);
+        k_avg_fin<<<(unsigned)D.n_inst, 64, 0, s>>>(D);
+    }
     pr->end(kSlotFinal);
+}
+
+void launch_avg_out(const Dev &D, double *out, hipStream_t s) {
+    k_avg_out<<<(unsigned)((D.nc + 255) / 256), 256, 0, s>>>(D, out);
 }
 
 void launch_moments(const Dev &D, int which, double *out, hipStream_t s) {

@@ -22,7 +22,7 @@ enum ProfSlot : int {
     kSlotScan2,         // scan of the bucket counts
     kSlotScatter,       // k_scatter
     kSlotGather,        // k_gather
-    kSlotFinal,         // k_finalize
+    kSlotFinal,         // k_finalize (and the averaging kernels when averaging is on)
     kNumSlots
 };
 struct Prof {
@@ -46,5 +46,7 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s);
 void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr);
 // [nc][5] field (0 W, 1 W^p, 2 W^h, 3 primitives) into device memory out
 void launch_moments(const Dev &D, int which, double *out, hipStream_t s);
+// Wbar = A / D of the time averaging, [nc][5] in out
+void launch_avg_out(const Dev &D, double *out, hipStream_t s);
 
 }  // namespace ugkwp

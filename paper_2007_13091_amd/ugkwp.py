@@ -23,7 +23,7 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
-           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask")
+           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask", "ugkwp_set_averaging", "ugkwp_average")
 N_PROFILE_SLOTS = 12
 
 
@@ -98,6 +98,10 @@ def lib():
         L.ugkwp_step.argtypes = [vp, C.c_int32, P(UgkwpStats)]
         L.ugkwp_moments.restype = C.c_int32
         L.ugkwp_moments.argtypes = [vp, C.c_int32, vp, C.c_int32]
+        L.ugkwp_set_averaging.restype = C.c_int32
+        L.ugkwp_set_averaging.argtypes = [vp, C.c_int64]
+        L.ugkwp_average.restype = C.c_int32
+        L.ugkwp_average.argtypes = [vp, vp, C.c_int32, P(C.c_double), P(C.c_int64)]
         L.ugkwp_particle_count.restype = C.c_int32
         L.ugkwp_particle_count.argtypes = [vp, P(C.c_int64)]
         L.ugkwp_export_particles.restype = C.c_int32
@@ -273,6 +277,20 @@ class Solver:
         out = np.zeros((self.nc, 5), dtype=np.float64)
         self._check(lib().ugkwp_moments(self.h, int(which), C.c_void_p(out.ctypes.data), 0))
         return out
+
+    def set_averaging(self, n_avg):
+        """Time-average the steps n > n_avg from now on (Sec. 2.4(c)); n_avg < 0: off."""
+        self._check(lib().ugkwp_set_averaging(self.h, int(n_avg)))
+
+    def average(self):
+        """(Wbar [n_cells][5], relative change of the last averaged step per instance, steps
+        averaged per instance)."""
+        out = np.zeros((self.nc, 5), dtype=np.float64)
+        res = np.zeros(self.n_inst)
+        n = np.zeros(self.n_inst, dtype=np.int64)
+        self._check(lib().ugkwp_average(self.h, C.c_void_p(out.ctypes.data), 0, _ptr(res, C.c_double),
+                                        _ptr(n, C.c_int64)))
+        return out, res, n
 
     def particle_count(self):
         n = C.c_int64(0)
