@@ -154,3 +154,31 @@ def test_periodic_meshes_are_paired_or_refused():
     with pytest.raises(U.UgkwpError) as e:
         U.workspace_bytes(m, p)
     assert e.value.status == U.E_ARG
+
+
+def test_empty_and_degenerate_inputs_are_refused():
+    w = wl.sod(nx=4, ny=1, nz=1)
+    m = w.mesh
+    # no cells
+    empty = wl.Mesh(m.xyz, m.cell_type[:0], m.cell_node_off[:1], m.cell_nodes[:0], m.bface_nodes[:0],
+                    m.bface_bc[:0], m.bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(empty, w.params)
+    assert e.value.status == U.E_ARG
+    # a flat tetrahedron (its four nodes in one plane): no positive volume
+    t = wl.tet_box_mesh((1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), {s: 0 for s in wl.SIDES},
+                        [wl.BC(wl.BC_SPECULAR)])
+    xyz = t.xyz.copy()
+    xyz[:, 2] = 0.0  # squash the box onto z = 0
+    flat = wl.Mesh(xyz, t.cell_type, t.cell_node_off, t.cell_nodes, t.bface_nodes, t.bface_bc, t.bcs)
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes(flat, w.params)
+    assert e.value.status == U.E_MESH
+    # nearly flat is still a tetrahedron (it only makes the time step small)
+    xyz[:, 2] = np.where(t.xyz[:, 2] > 0.5, 1e-12, 0.0)
+    thin = wl.Mesh(xyz, t.cell_type, t.cell_node_off, t.cell_nodes, t.bface_nodes, t.bface_bc, t.bcs)
+    assert U.workspace_bytes(thin, w.params) > 0
+    # a batch of no instances
+    with pytest.raises(U.UgkwpError) as e:
+        U.workspace_bytes([], [])
+    assert e.value.status == U.E_ARG

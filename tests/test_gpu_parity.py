@@ -65,6 +65,17 @@ def test_sod_40_steps():
     run_pair(w, 40, every=1, name="sod")
 
 
+@pytest.mark.parametrize("tets", [False, True])
+def test_single_cell_and_one_column_meshes(tets):
+    # degenerate sizes: one box cell (or the six tetrahedra of one box), and a one-cell-wide
+    # column with diffuse walls, where every particle leaves its cell only through walls or
+    # along the column
+    w = wl.closed_box(n=(1, 1, 1), n_ref=64, kn=0.05, tets=tets)
+    run_pair(w, 5, name="single box" if not tets else "one box of tets")
+    w = wl.closed_box(n=(1, 1, 7), n_ref=30, kn=0.5, bc=wl.BC_DIFFUSE, tets=tets)
+    run_pair(w, 5, name="column")
+
+
 def test_sod_tets_jittered_box():
     w = wl.closed_box(n=(4, 3, 3), n_ref=60, kn=0.02, tets=True, jitter=0.15)
     run_pair(w, 8, name="tet-box")
