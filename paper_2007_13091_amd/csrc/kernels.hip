@@ -17,6 +17,8 @@
 //   k_scatter      bucket the movers and collided particles by end cell
 //   k_gather       S6  deterministic order per cell, sums E and W^p, update of W
 //   k_finalize     step bookkeeping
+//   k_avg_cells,   time averaging for steady states, when turned on        (Sec. 2.4(c))
+//   k_avg_fin
 // No floating-point atomics: per-cell sums use fixed reduction trees, so a run is bitwise
 // reproducible.  Integer atomics only hand out bucket slots and counts; the order inside a
 // bucket is then fixed by sorting the source indices.
