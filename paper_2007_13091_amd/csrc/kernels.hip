@@ -35,6 +35,15 @@ namespace ugkwp {
 namespace {
 
 constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Whole-line stores of particle records with the non-temporal hint: neither the transport nor
+// the gather reads back what it writes, and the next kernel's reads of ~1 GB of records do
+// not fit in the L2 (measured: transport and gather 3-5% faster)
+typedef unsigned int u32x4_nt __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(uint4 *p, const uint4 &v) {
+    const u32x4_nt x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<u32x4_nt *>(p));
+}
 constexpr int kWave = 64;
 constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
 constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
@@ -1717,7 +1726,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
         const long long nr = n_tot - wb;
         const int nch = (nr <= 0 ? 0 : (nr >= kWave ? kWave : (int)nr)) * CPR;
         uint4 *g = rec_chunks(pa, wb, R(0));
-        for (int k = lane_id(); k < nch; k += kWave) g[k] = stage[threadIdx.x / kWave][j][k];
+        for (int k = lane_id(); k < nch; k += kWave) st_nt(&g[k], stage[threadIdx.x / kWave][j][k]);
     }
     // wall queue (held in the rank array, which the bucket count fills only later): this
     // block's segment, qseg entries from seg * qseg
@@ -2072,7 +2081,7 @@ __device__ __forceinline__ void stage_out(const uint4 *st, const Particles &dst,
     constexpr int CPR = RecChunks<R>::N;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     uint4 *g = rec_chunks(dst, o0, R(0));
-    for (int k = lane_id(); k < n * CPR; k += kWave) g[k] = st[k];
+    for (int k = lane_id(); k < n * CPR; k += kWave) st_nt(&g[k], st[k]);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
