@@ -413,6 +413,8 @@ def main():
     ap.add_argument("--batched-warmup", type=int, default=8)
     ap.add_argument("--configs", action="store_true",
                     help="time the tube, the cube and the vehicle (their own JSON object; not the bench line)")
+    ap.add_argument("--gks-only", action="store_true",
+                    help="run only the GKS-limit leg and print its JSON object (for profiling it alone)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg and print its JSON object (for profiling it alone)")
     args = ap.parse_args()
@@ -425,6 +427,9 @@ def main():
         return
     if args.configs:
         print(json.dumps({"configs": configs_run()}), flush=True)
+        return
+    if args.gks_only:
+        print(json.dumps({"gks_limit": gks_side(args.steps, args.warmup)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched_form": batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)}),

@@ -2144,6 +2144,21 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             }
         }
     }
+    if (nmov == 0 && cb1 == cb0 && s00 == s01 && (n_new == 0 || s10 == s11)) {
+        // no particle ends in c and none stays there: the update is -sum_f s_f Phi_f - S, with
+        // the particle sums exactly 0 (as the reductions below would give)
+        if (lane < 5) {
+            const double acc = facc + (0.0 - D.S[lane * nc + c]);
+            D.W[lane * nc + c] = D.W[lane * nc + c] + acc / D.vol[c];
+            D.P[lane * nc + c] = 0.0;
+        }
+        if (lane == 0) {
+            D.nleft[c] = bend - base;
+            D.segoff[buf ^ 1][c] = base;
+            if (base != bend) atomicOr(&D.sc->err, kErrCapacity);
+        }
+        return;
+    }
     double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
     // movers (part 0) and collided (part 1): source lists sorted ascending
     for (int part = 0; part < 2; ++part) {
