@@ -307,6 +307,53 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Totals over the wave of P[0..4] and C[0..4], lane k < 5 receiving P_k and C_k.  Each total
+// is built from the same pairwise additions as wave_sum (partial sums of lanes that differ
+// in bit 5, then 4, ..., then 0), so it is bitwise wave_sum's; but at each of the first levels
+// a lane keeps half of the values it carries and hands its partner the other half: 13
+// exchanges instead of 60.
+__device__ __forceinline__ void wave_sum_pc(const double P[5], const double C[5], double &pk, double &ck) {
+    const int lane = lane_id();
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+    double x[6];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double send = b5 ? P[k] : C[k];
+        const double keep = b5 ? C[k] : P[k];
+        x[k] = keep + __shfl_xor(send, 32);
+    }
+    x[5] = 0.0;  // lanes with bit 5 clear now carry the P partial sums, the others the C ones
+    double y[4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double send = b4 ? x[j] : x[3 + j];
+        const double keep = b4 ? x[3 + j] : x[j];
+        y[j] = keep + __shfl_xor(send, 16);
+    }
+    y[3] = 0.0;
+    double z[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double send = b3 ? y[j] : y[2 + j];
+        const double keep = b3 ? y[2 + j] : y[j];
+        z[j] = keep + __shfl_xor(send, 8);
+    }
+    double q;
+    {
+        const double send = b2 ? z[0] : z[1];
+        const double keep = b2 ? z[1] : z[0];
+        q = keep + __shfl_xor(send, 4);
+    }
+    q = q + __shfl_xor(q, 2);
+    q = q + __shfl_xor(q, 1);
+    // a lane's total is component 3 b4 + 2 b3 + b2 (combinations above 4, or with b3 and b2
+    // both set below bit 4, carry the zero padding): P_0..P_4 sit in lanes 0, 4, 8, 16, 20 and
+    // C_k 32 lanes above P_k
+    const int src = lane < 3 ? 4 * lane : (lane < 5 ? 4 * lane + 4 : 0);
+    pk = __shfl(q, src);
+    ck = __shfl(q, src + 32);
+}
+
 // ---------------------------------------------------------------------------------------
 // S0: primitives, tau, min Omega / Lambda
 // ---------------------------------------------------------------------------------------
@@ -2217,19 +2264,9 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             pos += (int)__popcll(mb);
         }
     }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        Pn[k] = wave_sum(Pn[k]);
-        Cn[k] = wave_sum(Cn[k]);
-    }
+    double Pk, Ck;
+    wave_sum_pc(Pn, Cn, Pk, Ck);
     if (lane < 5) {
-        double Pk = Pn[0], Ck = Cn[0];
-#pragma unroll
-        for (int k = 1; k < 5; ++k)
-            if (lane == k) {
-                Pk = Pn[k];
-                Ck = Cn[k];
-            }
         const double E = Pk + Ck;
         const double acc = facc + (E - D.S[lane * nc + c]);
         D.W[lane * nc + c] = D.W[lane * nc + c] + acc / D.vol[c];
