@@ -2387,24 +2387,16 @@ __global__ void k_scan_reduce(L in, long long n, T *part) {
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-template <typename T>
-__global__ void k_scan_partials(T *part, int nb, T *total_out) {
-    __shared__ T sh[kScanBS];
-    T carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += kScanBS) {
-        const int b = b0 + threadIdx.x;
-        T v = b < nb ? part[b] : T(0);
-        T tot;
-        T ex = block_exclusive_scan<T>(v, sh, tot);
-        if (b < nb) part[b] = carry + ex;
-        carry = carry + tot;
-    }
-    if (threadIdx.x == 0) *total_out = carry;
-}
-
+// Each block finds its own offset, the totals of the blocks before it (a few thousand at
+// most, read from the L2), so no kernel in between scans the block totals; the last block
+// writes the grand total to out[n].  Integer sums: the order does not matter.
 template <typename T, typename L>
 __global__ void k_scan_apply(L in, long long n, const T *part, T *out) {
     __shared__ T sh[kScanBS];
+    T o = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanBS) o = o + part[b];
+    T off;
+    block_exclusive_scan<T>(o, sh, off);
     const long long base = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanPer;
     T v[kScanPer];
     T s = 0;
@@ -2414,12 +2406,13 @@ __global__ void k_scan_apply(L in, long long n, const T *part, T *out) {
         s = s + v[q];
     }
     T tot;
-    T ex = block_exclusive_scan<T>(s, sh, tot) + part[blockIdx.x];
+    T ex = block_exclusive_scan<T>(s, sh, tot) + off;
     for (int q = 0; q < kScanPer; ++q) {
         long long i = base + q;
         if (i < n) out[i] = ex;
         ex = ex + v[q];
     }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
 }
 
 template <typename T>
@@ -2542,7 +2535,6 @@ void scan(L in, long long n, T *out, T *part, hipStream_t s) {
         return;
     }
     k_scan_reduce<T, L><<<nb, kScanBS, 0, s>>>(in, n, part);
-    k_scan_partials<T><<<1, kScanBS, 0, s>>>(part, nb, out + n);
     k_scan_apply<T, L><<<nb, kScanBS, 0, s>>>(in, n, part, out);
 }
 
