@@ -78,7 +78,7 @@ def cpu_baseline(steps=12):
     import oracle
     from paper_2007_13091_amd import workloads as wl
 
-    w = wl.cavity()
+    w = wl.morton_numbered(wl.cavity())
     o = oracle.Oracle(w.mesh, w.params)
     o.set_state(w.W0)
     moved = 0
@@ -89,7 +89,7 @@ def cpu_baseline(steps=12):
         moved += st["n_alive"] + st["n_collided"] + st["n_escaped"]
     el = time.perf_counter() - t0
     return {"value": moved / el, "unit": "particle moves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} steps of the 32^3 cavity (400 particles/cell) from the initial state, "
+            "sample": f"first {steps} steps of the 32^3 cavity (Morton-numbered, 400 particles/cell) from the initial state, "
                       f"{moved} particle moves in {el:.1f} s; cell-steps/s {steps * w.mesh.n_cells / el:.3g}"}
 
 
@@ -165,7 +165,7 @@ def gks_side(steps, warmup):
     from paper_2007_13091_amd import workloads as wl
     from paper_2007_13091_amd.ugkwp import Solver
 
-    w = wl.cavity(kn=1e-6)
+    w = wl.morton_numbered(wl.cavity(kn=1e-6))
     # no particle is ever sampled: a small capacity keeps the particle kernels' grids, which
     # cover the capacity, from launching blocks that find nothing to do
     s = Solver(w.mesh, w.params, capacity=GKS_CAPACITY)
@@ -191,7 +191,7 @@ def gks_side(steps, warmup):
     faces = (6 * nc + int(w.mesh.bface_nodes.shape[0])) // 2  # box hexes: shared faces counted twice
     flux_ms = warm["flux"][0] / max(warm["flux"][1], 1)
     achieved = BYTES_PER_FACE * faces / (flux_ms * 1e-3) / 1e9
-    return {"workload": "cavity 32^3 at Kn 1e-6 (GKS limit: no particles), FP64 plain",
+    return {"workload": "cavity 32^3 (Morton-numbered) at Kn 1e-6 (GKS limit: no particles), FP64 plain",
             "cell_steps_per_s": nc * steps / el, "ms_per_step": el / steps * 1e3, "steps": steps,
             "particles_per_step": int((st1["moved_total"] - st0["moved_total"]) / steps), "capacity": GKS_CAPACITY,
             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in warm.items()},
@@ -231,12 +231,12 @@ def configs_run():
                 "after_steps": warm}
 
     out = {}
-    w = wl.sod()
+    w = wl.morton_numbered(wl.sod())
     out["sod_50x2x2_fp64"] = one(w, 0, 1, 39)
-    w = wl.cube()
+    w = wl.morton_numbered(wl.cube())
     out["cube_mach10_fp64"] = one(w, 0, 1, 3)
     out["cube_mach10_fp32"] = one(w, 1, 1, 3)
-    w = wl.vehicle(kn=1e-3)
+    w = wl.morton_numbered(wl.vehicle(kn=1e-3))
     out["vehicle_mach15_kn1e-3_fp64"] = one(w, 0, 1, 2)
     out["vehicle_mach15_kn1e-3_fp32"] = one(w, 1, 1, 2)
     return out
@@ -247,17 +247,17 @@ def configs_run():
 BYTES_PER_AVG_CELL = 128
 
 
-def averaging_side(steps, warmup, ms_plain):
-    """Side number: the cost of time averaging (Sec. 2.4(c)) on the FP64 cavity, the whole
-    step with averaging on against the plain step, and the averaging kernel's position
-    against HBM (k_avg_cells and k_avg_fin are timed with k_finalize in one group; the
-    group's time with averaging off is subtracted)."""
+def averaging_side(steps, warmup):
+    """Side number: the cost of time averaging (Sec. 2.4(c)) on the FP64 cavity: the same
+    solver timed over `steps` steps without averaging and then over `steps` steps averaging
+    every step, and the averaging kernels' position against HBM (k_avg_cells and k_avg_fin are
+    timed with k_finalize in one group; the group's time without averaging is subtracted)."""
     import torch
 
     from paper_2007_13091_amd import workloads as wl
     from paper_2007_13091_amd.ugkwp import Solver
 
-    w = wl.cavity()
+    w = wl.morton_numbered(wl.cavity())
     s = Solver(w.mesh, w.params)
     s.init_state(w.W0)
     s.step(warmup, stats=False)
@@ -265,15 +265,23 @@ def averaging_side(steps, warmup, ms_plain):
     s.profile_read()
     s.step(warmup, stats=False)
     fin0 = s.profile_read()["finalize"]
+    s.profile(False)
+
+    def timed():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, stats=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    ms_plain = timed()
     s.set_averaging(0)
+    s.profile(True, slots=["finalize"])
+    s.profile_read()
     s.step(warmup, stats=False)
     fin1 = s.profile_read()["finalize"]
     s.profile(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps, stats=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = timed()
     _, res, n = s.average()
     s.close()
     del s
@@ -281,8 +289,7 @@ def averaging_side(steps, warmup, ms_plain):
     nc = w.mesh.n_cells
     avg_ms = fin1[0] / max(fin1[1], 1) - fin0[0] / max(fin0[1], 1)
     achieved = BYTES_PER_AVG_CELL * nc / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None
-    ms = (t1 - t0) / steps * 1e3
-    return {"workload": "cavity 32^3, FP64 plain, every step averaged", "ms_per_step": ms,
+    return {"workload": "cavity 32^3 (Morton-numbered), FP64 plain, every step averaged", "ms_per_step": ms,
             "ms_per_step_without": ms_plain, "steps_averaged": int(n[0]), "last_relative_change": float(res[0]),
             "averaging_kernels_ms": round(avg_ms, 4),
             "roofline": {"bound": "hbm", "achieved": None if achieved is None else round(achieved, 1),
@@ -307,7 +314,8 @@ def stated_fp32_error():
 
 def batched_run(steps, warmup, plain_steps):
     """The batched form on 64 independent tube and cavity instances (log-uniform cell counts in
-    [2e3, 2e5], Kn in [1e-4, 1], 50 to 500 particles per cell): FP32 transport, all instances in
+    [2e3, 2e5], Kn in [1e-4, 1], 50 to 500 particles per cell; each instance's cells numbered
+    along a Morton curve): FP32 transport, all instances in
     one launch per kernel, launch shapes autotuned on real steps, steps replayed from a
     captured hip graph.  Against it: the FP64 plain form run instance by instance (each alone,
     eager launches), timed over `plain_steps` steps after the same number of warm-up steps."""
@@ -316,7 +324,7 @@ def batched_run(steps, warmup, plain_steps):
     from paper_2007_13091_amd import workloads as wl
     from paper_2007_13091_amd.ugkwp import Solver
 
-    ws = wl.batched()
+    ws = [wl.morton_numbered(w) for w in wl.batched()]
     meshes, params = [w.mesh for w in ws], [w.params for w in ws]
     W0 = np.concatenate([w.W0 for w in ws])
     nc = int(sum(w.mesh.n_cells for w in ws))
@@ -438,7 +446,7 @@ def main():
 
     from paper_2007_13091_amd import workloads as wl
 
-    w = wl.cavity()
+    w = wl.morton_numbered(wl.cavity())
     nc = w.mesh.n_cells
     el, moves, prof, cfg, dom, last = timed_run(w, 0, args.warmup, args.steps)
     value = moves / el
@@ -457,8 +465,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "lid-driven cavity, 32^3 box hexes, 400 particles/cell, Kn 0.075, diffuse walls, "
-                               "lid 0.16 sqrt(gamma T_w); FP64 plain form",
+        "config": {"workload": "lid-driven cavity, 32^3 box hexes numbered along a Morton curve, 400 particles/cell, "
+                               "Kn 0.075, diffuse walls, lid 0.16 sqrt(gamma T_w); FP64 plain form",
                    "cells": nc, "faces": int(w.mesh.n_cells * 3 + 3 * 32 * 32), "particles_per_step": int(moves_per_launch)},
         "cell_steps_per_s": nc * args.steps / el,
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
@@ -477,7 +485,7 @@ def main():
     if not args.no_gks:
         out["gks_limit"] = gks_side(args.steps, args.warmup)
     if not args.no_avg:
-        out["time_averaging"] = averaging_side(args.steps, args.warmup, out["ms_per_step"])
+        out["time_averaging"] = averaging_side(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

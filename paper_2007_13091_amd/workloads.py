@@ -240,6 +240,35 @@ class Workload:
     steps: int
 
 
+def morton_numbered(w: Workload, bits: int = 10) -> Workload:
+    """The same workload with its cells numbered along a Morton (Z-order) curve through their
+    centroids (quantised to 2^bits levels per axis over the cells' bounding box; ties keep
+    their order).  Cells close in space then get close indices: the neighbours a particle
+    crosses into, and the cells that exchange particles, sit close in memory and are
+    processed close in time, so their data stay in the L2.  The mesh, its boundary faces and
+    the initial state are the same; only the numbering of the cells changes (and with it the
+    random draws, which are keyed by cell index)."""
+    m = w.mesh
+    cnt = np.diff(m.cell_node_off)
+    cid = np.repeat(np.arange(m.n_cells), cnt)
+    cen = np.stack([np.bincount(cid, weights=m.xyz[m.cell_nodes, d], minlength=m.n_cells) for d in range(3)], 1)
+    cen /= cnt[:, None]
+    lo, hi = cen.min(0), cen.max(0)
+    top = (1 << bits) - 1
+    q = np.clip(((cen - lo) / np.maximum(hi - lo, 1e-300) * top).astype(np.int64), 0, top)
+    key = np.zeros(m.n_cells, dtype=np.int64)
+    for b in range(bits):
+        for d in range(3):
+            key |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    order = np.argsort(key, kind="stable")
+    lens = cnt[order]
+    noff = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    idx = np.repeat(m.cell_node_off[:-1][order] - noff[:-1], lens) + np.arange(int(noff[-1]))
+    mesh = Mesh(m.xyz, m.cell_type[order], noff, m.cell_nodes[idx].astype(np.int64), m.bface_nodes, m.bface_bc,
+                list(m.bcs))
+    return Workload(w.name + " (Morton-numbered)", mesh, w.params, w.W0.reshape(-1, 5)[order].copy(), w.steps)
+
+
 def sod(nx=50, ny=2, nz=2, n_ref=200, kn=1e-3, cfl=0.5, steps=40, seed=1, tets=False) -> Workload:
     """Shock tube in a square column (paper Sec. 4.1) at the hot-path size: [0,1]x[0,0.04]^2,
     monatomic, rho = 1, p = 1 left of x = 0.5 and rho = 0.125, p = 0.1 right; all walls specular."""

@@ -182,3 +182,32 @@ def test_empty_and_degenerate_inputs_are_refused():
     with pytest.raises(U.UgkwpError) as e:
         U.workspace_bytes([], [])
     assert e.value.status == U.E_ARG
+
+
+def test_morton_numbering_is_a_renumbering_of_the_same_mesh():
+    w = wl.closed_box(n=(5, 4, 3), n_ref=20, tets=True, jitter=0.1)
+    m = wl.morton_numbered(w)
+    assert m.mesh.n_cells == w.mesh.n_cells
+    # each new cell is an old cell: same type, same nodes, same initial state
+    old = {tuple(w.mesh.cell_nodes[w.mesh.cell_node_off[c]:w.mesh.cell_node_off[c + 1]]): c
+           for c in range(w.mesh.n_cells)}
+    seen = set()
+    W0 = w.W0.reshape(-1, 5)
+    for c in range(m.mesh.n_cells):
+        nodes = tuple(m.mesh.cell_nodes[m.mesh.cell_node_off[c]:m.mesh.cell_node_off[c + 1]])
+        o = old[nodes]
+        seen.add(o)
+        assert m.mesh.cell_type[c] == w.mesh.cell_type[o]
+        np.testing.assert_array_equal(m.W0[c], W0[o])
+    assert len(seen) == w.mesh.n_cells
+    # the library accepts it with the same workspace, and the oracle sees the same geometry
+    assert U.workspace_bytes(m.mesh, m.params) == U.workspace_bytes(w.mesh, w.params)
+    import oracle
+    v0 = np.sort(oracle.Oracle(w.mesh, w.params).geometry()[0])
+    v1 = np.sort(oracle.Oracle(m.mesh, m.params).geometry()[0])
+    np.testing.assert_allclose(v1, v0, rtol=1e-14)
+    # on a box grid the curve visits 2x2x2 blocks first
+    g = wl.morton_numbered(wl.cavity(n=8, n_ref=10))
+    first = g.mesh.cell_nodes[:g.mesh.cell_node_off[8]].reshape(8, 8)
+    xyz = g.mesh.xyz[first].mean(1)
+    assert np.ptp(xyz, 0).max() <= 1.0 / 8 + 1e-12

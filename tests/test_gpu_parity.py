@@ -299,8 +299,9 @@ def test_nonphysical_initial_state_rejected():
     assert e.value.status == E_NONPHYS
 
 
-@pytest.mark.parametrize("steps", [2])
-def test_cavity_full_size(steps):
-    """32^3 cavity, 400 particles/cell (~1.3e7 particles): the benchmark's configuration."""
-    w = wl.cavity()
-    run_pair(w, steps, every=1, name="cavity32")
+@pytest.mark.parametrize("morton", [True, False])
+def test_cavity_full_size(morton, steps=2):
+    """32^3 cavity, 400 particles/cell (~1.3e7 particles): the benchmark's configuration (cells
+    numbered along a Morton curve), and the same cavity numbered x fastest."""
+    w = wl.morton_numbered(wl.cavity()) if morton else wl.cavity()
+    run_pair(w, steps, every=1, name="cavity32 morton" if morton else "cavity32")
