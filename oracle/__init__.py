@@ -46,9 +46,9 @@ def lib():
         L.orc_make_uid.argtypes = [C.c_int, i64, i64, i64]
         L.orc_moments.argtypes = [C.c_int, d, d, P(d)]
         L.orc_qcoef.argtypes = [d, d, P(d)]
-        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, P(d)]
-        L.orc_flux_specular.argtypes = [P(d), d, P(d), d, d, d, d, P(d)]
-        L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), P(d)]
+        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_flux_specular.argtypes = [P(d), d, P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), C.c_int, P(d)]
         L.orc_create.restype = vp
         L.orc_create.argtypes = [i64, P(d), i64, P(C.c_uint8), P(i64), P(i64), i64, P(i64), P(i32), i32,
                                  P(i32), P(d), P(d), P(d), P(d), d, d, d, d, i32, i32, i32, u64, i64, P(i32)]
@@ -64,6 +64,9 @@ def lib():
         L.orc_set_state.argtypes = [vp, P(d)]
         L.orc_get_state.argtypes = [vp, P(d), P(d), P(i64)]
         L.orc_get_particles.argtypes = [vp, P(d), P(d), P(d), P(i64), P(u64)]
+        L.orc_last_terms.argtypes = [vp, P(d), P(d), P(d)]
+        L.orc_import_state.restype = C.c_int
+        L.orc_import_state.argtypes = [vp, P(d), P(d), i64, P(d), P(d), P(d), P(i64), P(u64), i64, d]
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [vp]
         L.orc_sample_only.restype = C.c_int
@@ -72,10 +75,14 @@ def lib():
         L.orc_flux_speed.argtypes = [d, d]
         L.orc_slope.argtypes = [d, d, d, d, P(d), P(d)]
         L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, P(d)]
-        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, P(d)]
-        L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, P(d)]
-        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, P(d)]
+        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_set_gks_steps.restype = C.c_int
+        L.orc_set_gks_steps.argtypes = [vp, i64]
         L.orc_set_recon.restype = C.c_int
+        L.orc_set_sampling.restype = C.c_int
+        L.orc_set_sampling.argtypes = [vp, C.c_int]
         L.orc_set_recon.argtypes = [vp, C.c_int, d]
         L.orc_gradients.restype = C.c_int
         L.orc_gradients.argtypes = [vp, P(d), P(d), P(d)]
@@ -127,11 +134,12 @@ def _v(a, n):
     return a
 
 
-def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2):
+def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2, gks=False):
+    """gks: the wave-only flux of the start phase (the waves carry all of the hydro part)."""
     F = np.zeros(5)
     Wl, Wr, n = _v(Wl, 5), _v(Wr, 5), _v(n, 3)
     lib().orc_flux_interior(_p(Wl, C.c_double), _p(Wr, C.c_double), rhohl, rhohr, _p(n, C.c_double), dt,
-                            mu_ref, omega, c2, _p(F, C.c_double))
+                            mu_ref, omega, c2, int(bool(gks)), _p(F, C.c_double))
     return F
 
 
@@ -152,52 +160,54 @@ def mvec(p, q, r, a, rng, un, v, w, lam):
     return out
 
 
-def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2):
+def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2, gks=False):
     """Second-order interior flux; G[k][d] = dW_k/dx_d ([5][3])."""
     F = np.zeros(5)
     args = [_v(Wl, 5), _v(Wr, 5), _v(Whl, 5), _v(Whr, 5), _v(Gl, 15), _v(Gr, 15), _v(Ghl, 15), _v(Ghr, 15)]
     n = _v(n, 3)
     lib().orc_flux2_interior(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             _p(F, C.c_double))
+                             int(bool(gks)), _p(F, C.c_double))
     return F
 
 
-def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2):
+def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2, gks=False):
     F = np.zeros(5)
     args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15)]
     n = _v(n, 3)
     lib().orc_flux2_specular(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             _p(F, C.c_double))
+                             int(bool(gks)), _p(F, C.c_double))
     return F
 
 
-def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2):
+def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2, gks=False):
     F = np.zeros(5)
     args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15), _v(Winf, 5)]
     n = _v(n, 3)
     lib().orc_flux2_farfield(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             _p(F, C.c_double))
+                             int(bool(gks)), _p(F, C.c_double))
     return F
 
 
-def flux_specular(W, rhoh, n, dt, mu_ref, omega, c2):
+def flux_specular(W, rhoh, n, dt, mu_ref, omega, c2, gks=False):
     F = np.zeros(5)
     W, n = _v(W, 5), _v(n, 3)
-    lib().orc_flux_specular(_p(W, C.c_double), rhoh, _p(n, C.c_double), dt, mu_ref, omega, c2,
+    lib().orc_flux_specular(_p(W, C.c_double), rhoh, _p(n, C.c_double), dt, mu_ref, omega, c2, int(bool(gks)),
                             _p(F, C.c_double))
     return F
 
 
-def flux_diffuse(W, rhoh, tau_c, n, dt, Tw, Uw):
+def flux_diffuse(W, rhoh, tau_c, n, dt, Tw, Uw, gks=False):
     F = np.zeros(5)
     W, n, Uw = _v(W, 5), _v(n, 3), _v(Uw, 3)
     lib().orc_flux_diffuse(_p(W, C.c_double), rhoh, tau_c, _p(n, C.c_double), dt, Tw, _p(Uw, C.c_double),
-                           _p(F, C.c_double))
+                           int(bool(gks)), _p(F, C.c_double))
     return F
 
 
 class OracleError(RuntimeError):
-    pass
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 class Oracle:
@@ -233,6 +243,11 @@ class Oracle:
             rc = L.orc_set_recon(self.h, recon, float(getattr(params, "venkat_k", 1.0)))
             if rc != OK:
                 raise OracleError(f"orc_set_recon failed with status {rc}")
+        rc = L.orc_set_sampling(self.h, int(getattr(params, "sampling", 0)))
+        if rc == OK:
+            rc = L.orc_set_gks_steps(self.h, int(getattr(params, "gks_steps", 0)))
+        if rc != OK:
+            raise OracleError(f"orc_set_sampling failed with status {rc}")
         self.nc = int(L.orc_n_cells(self.h))
         self.nf = int(L.orc_n_faces(self.h))
 
@@ -245,11 +260,43 @@ class Oracle:
         W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(self.nc, 5)
         lib().orc_set_state(self.h, _p(W0, C.c_double))
 
+    def import_state(self, state, instance=0):
+        """Replace the state between steps: W, P ([nc][5]), particles (dict of x, u, m, cell,
+        uid), step and t (scalars, or per-instance arrays indexed by `instance`)."""
+        W = np.ascontiguousarray(state["W"], dtype=np.float64).reshape(self.nc, 5)
+        P = np.ascontiguousarray(state["P"], dtype=np.float64).reshape(self.nc, 5)
+        p = state["particles"]
+        n = int(np.asarray(p["uid"]).shape[0])
+        x = np.ascontiguousarray(p["x"], dtype=np.float64).reshape(n, 3)
+        u = np.ascontiguousarray(p["u"], dtype=np.float64).reshape(n, 3)
+        m = np.ascontiguousarray(p["m"], dtype=np.float64).reshape(n)
+        c = np.ascontiguousarray(p["cell"], dtype=np.int64).reshape(n)
+        uid = np.ascontiguousarray(p["uid"], dtype=np.uint64).reshape(n)
+        step = int(np.asarray(state["step"]).reshape(-1)[instance])
+        t = float(np.asarray(state["t"]).reshape(-1)[instance])
+        rc = lib().orc_import_state(self.h, _p(W, C.c_double), _p(P, C.c_double), n, _p(x, C.c_double),
+                                    _p(u, C.c_double), _p(m, C.c_double), _p(c, C.c_int64), _p(uid, C.c_uint64),
+                                    step, t)
+        if rc != OK:
+            raise OracleError(f"orc_import_state failed with status {rc}")
+
+    def last_terms(self):
+        """Terms of the last update per cell, raw (times Omega): wave flux -sum_f s_f Phi_f, E
+        (particles ending in the cell) and S (particles starting in it), [nc][5] each."""
+        F = np.zeros((self.nc, 5)); E = np.zeros((self.nc, 5)); S = np.zeros((self.nc, 5))
+        lib().orc_last_terms(self.h, _p(F, C.c_double), _p(E, C.c_double), _p(S, C.c_double))
+        return F, E, S
+
+    def export_state(self):
+        """W, P, particles, step and t (the form import_state takes)."""
+        W, P, _ = self.state()
+        return dict(W=W, P=P, particles=self.particles(), step=self.step_index, t=self.time)
+
     def step(self, n=1):
         for _ in range(n):
             rc = lib().orc_step(self.h)
             if rc != OK:
-                raise OracleError(f"orc_step failed with status {rc}")
+                raise OracleError(f"orc_step failed with status {rc}", status=rc)
 
     def set_averaging(self, n_avg):
         """Average the steps n > n_avg from now on (Sec. 2.4(c)); n_avg < 0: off."""

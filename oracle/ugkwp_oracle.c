@@ -209,6 +209,18 @@ void orc_qcoef(double dt, double tau, double out[5])
     out[0] = q1; out[1] = q2; out[2] = q3; out[3] = q4m; out[4] = q5p;
 }
 
+/* The wave-only (gas-kinetic) phase that starts a run (the continuum start of Sec. 4.3 and
+ * Sec. 4.4): no particle is sampled, so the waves carry the whole free transport of W^h,
+ * F^{fr,UGKS} = int u_n (q4 g0^h + q5 u.g_x^h) psi, i.e. the wave flux of Sec. 2.4 with the
+ * terms of the sampled collisionless particles (-dt e and + dt^2 e / 2) left out:
+ * q4 = (q4 - dt e) + dt e and q5 = (q5 + dt^2 e / 2) - dt^2 e / 2. */
+static void wave_only_coef(double dt, double tau, double q[5])
+{
+    double e = exp(-dt / tau);
+    q[3] = q[3] + dt * e;
+    q[4] = q[4] - 0.5 * dt * dt * e;
+}
+
 static void rotate_back(const double Ff[5], const double n[3], const double t1[3], const double t2[3],
                         double F[5])
 {
@@ -226,7 +238,7 @@ static void rotate_back(const double Ff[5], const double n[3], const double t1[3
 /* rhoh_l, rhoh_r: density of the hydro Maxwellian (U and T of the total state).           */
 /* ------------------------------------------------------------------------------------ */
 static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rhohr, double dt,
-                      double mu_ref, double omega, double c2, double Ff[5])
+                      double mu_ref, double omega, double c2, int gks, double Ff[5])
 {
     double ml[NMOM], mr[NMOM], Hl[5], Gl[5], Hr[5], Gr[5];
     orc_moments(+1, l->un, l->lam, ml);
@@ -246,6 +258,7 @@ static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rho
     double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
     double q[5];
     orc_qcoef(dt, tau, q);
+    if (gks) wave_only_coef(dt, tau, q);
     double m0[NMOM], H0[5], G0[5];
     orc_moments(0, z.un, z.lam, m0);
     psi_moments(&z, m0, H0, G0);
@@ -254,27 +267,27 @@ static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rho
 }
 
 void orc_flux_interior(const double Wl[5], const double Wr[5], double rhohl, double rhohr,
-                       const double n[3], double dt, double mu_ref, double omega, double c2,
+                       const double n[3], double dt, double mu_ref, double omega, double c2, int gks,
                        double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     prim_t l = to_frame(Wl, n, t1, t2), r = to_frame(Wr, n, t1, t2);
-    flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, Ff);
+    flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
 /* Specular (symmetry) wall: interior flux against the mirror state (u_n -> -u_n), then only
  * the normal-momentum component is kept; n points out of the domain. */
 void orc_flux_specular(const double W[5], double rhoh, const double n[3], double dt,
-                       double mu_ref, double omega, double c2, double F[5])
+                       double mu_ref, double omega, double c2, int gks, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     prim_t l = to_frame(W, n, t1, t2);
     prim_t g = l;
     g.un = -l.un;
-    flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, Ff);
+    flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, gks, Ff);
     Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -283,13 +296,14 @@ void orc_flux_specular(const double W[5], double rhoh, const double n[3], double
  * (u_n > 0): q1 g + (q4 - dt e) g^h at the cell state with the cell's tau; the wall emits
  * rho_w M(T_w, U_w) over u_n < 0 for the whole step, rho_w fixed by zero net mass flux. */
 void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double n[3], double dt,
-                      double Tw, const double Uw[3], double F[5])
+                      double Tw, const double Uw[3], int gks, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     prim_t l = to_frame(W, n, t1, t2);
     double q[5];
     orc_qcoef(dt, tau_c, q);
+    if (gks) wave_only_coef(dt, tau_c, q);
     double ml[NMOM], Hl[5], Gl[5];
     orc_moments(+1, l.un, l.lam, ml);
     psi_moments(&l, ml, Hl, Gl);
@@ -463,7 +477,7 @@ typedef struct {
  *   F^wave = sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e / 2) <u (u a~_n + v a~_t1 + w a~_t2) . psi psi>_s]
  *   over the half spaces, with a~ the slopes of W~^h. */
 static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_ref, double omega, double c2,
-                       double Ff[5])
+                       int gks, double Ff[5])
 {
     poly_t one, pu, pv, pw, puu, puv, puw;
     poly_mono(0, 0, 0, &one);
@@ -504,6 +518,7 @@ static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_re
     double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
     double q[5];
     orc_qcoef(dt, tau, q);
+    if (gks) wave_only_coef(dt, tau, q);
     double G0[5], X0[5], X1[5], X2[5], GA[5];
     mvec(&pu, NULL, 0, &z, G0);
     mvec(&puu, abar[0], 0, &z, X0);
@@ -562,14 +577,14 @@ static void make_side(const double W[5], const double G[15], const double Wh[5],
  * states Whl, Whr (conservative), gradients G[k][d] = dW_k/dx_d of each. */
 void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl[5], const double Whr[5],
                         const double Gl[15], const double Gr[15], const double Ghl[15], const double Ghr[15],
-                        const double n[3], double dt, double mu_ref, double omega, double c2, double F[5])
+                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     side_t L, R;
     make_side(Wl, Gl, Whl, Ghl, n, t1, t2, &L);
     make_side(Wr, Gr, Whr, Ghr, n, t1, t2, &R);
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
@@ -577,7 +592,7 @@ void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl
  * momentum and normal derivatives flip sign, twice for the normal momentum's normal
  * derivative), then only the normal-momentum component is kept. */
 void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
-                        const double n[3], double dt, double mu_ref, double omega, double c2, double F[5])
+                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
@@ -594,7 +609,7 @@ void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15
             R.dWh[d][k] = sd * sk * L.dWh[d][k];
         }
     }
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
     Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -602,7 +617,7 @@ void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15
 /* Far field at second order: the free stream with zero gradients as the right side. */
 void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
                         const double Winf[5], const double n[3], double dt, double mu_ref, double omega,
-                        double c2, double F[5])
+                        double c2, int gks, double F[5])
 {
     double t1[3], t2[3], Ff[5], zero[15];
     memset(zero, 0, sizeof(zero));
@@ -610,7 +625,7 @@ void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15
     side_t L, R;
     make_side(W, G, Wh, Gh, n, t1, t2, &L);
     make_side(Winf, zero, Winf, zero, n, t1, t2, &R);
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
@@ -655,6 +670,10 @@ typedef struct oracle {
     double *fx;          /* [nf][3] face centre (the owner's) */
     int recon;           /* 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan */
     double venkat_k;     /* Venkatakrishnan constant K in eps^2 = (K h)^3 */
+    int64_t gks_steps;   /* the steps n < gks_steps (counted from orc_set_state) are wave-only:
+                            no particle is sampled or enters, the waves carry all of W^h */
+    int sampling;        /* hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b);
+                            1 the energy-exact variant (one factor per cell on the deviations) */
     int64_t *fown, *fnb; /* fnb: neighbour cell or -1 - bc index */
     double *fn, *farea;
     int nbc;
@@ -672,6 +691,8 @@ typedef struct oracle {
     /* time averaging (Sec. 2.4(c)): steps n > avg_from are averaged (avg_from < 0: off) */
     int64_t avg_from;
     double *avgA;      /* [nc][5] sum of dt^n W^n */
+    /* terms of the last update per cell (test hook): -sum_f s_f Phi_f, E and S, raw */
+    double *tflux, *tE, *tS;
     double avg_D;      /* sum of dt^n */
     int64_t avg_n;     /* steps averaged */
     double avg_res;    /* relative change of the average in the last averaged step */
@@ -705,6 +726,7 @@ static const int HEXF[6][4] = {{0, 3, 7, 4}, {1, 2, 6, 5}, {0, 1, 5, 4}, {3, 2, 
 static const int TETF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
 
 void orc_destroy(oracle_t *o);
+static int reserve(oracle_t *o, int64_t n);
 
 static void *xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
 
@@ -746,6 +768,9 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     o->W = (double *)xcalloc(5 * nc, sizeof(double));
     o->P = (double *)xcalloc(5 * nc, sizeof(double));
     o->avgA = (double *)xcalloc(5 * nc, sizeof(double));
+    o->tflux = (double *)xcalloc(5 * nc, sizeof(double));
+    o->tE = (double *)xcalloc(5 * nc, sizeof(double));
+    o->tS = (double *)xcalloc(5 * nc, sizeof(double));
     o->avg_from = -1;
     o->avg_res = INFINITY;
     o->nleft = (int64_t *)xcalloc(nc, sizeof(int64_t));
@@ -1031,6 +1056,7 @@ void orc_destroy(oracle_t *o)
     free(o->orig); free(o->edge); free(o->fown); free(o->fnb); free(o->fn); free(o->farea);
     free(o->lfx); free(o->fx);
     free(o->bc); free(o->W); free(o->P); free(o->avgA); free(o->nleft);
+    free(o->tflux); free(o->tE); free(o->tS);
     free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
     free(o);
 }
@@ -1049,6 +1075,26 @@ int orc_set_recon(oracle_t *o, int recon, double venkat_k)
     if (recon != 0 && o->nper > 0) return ORC_E_ARG;
     o->recon = recon;
     o->venkat_k = venkat_k;
+    return ORC_OK;
+}
+
+/* Wave-only start (the continuum start of the paper's hypersonic cases, Sec. 4.3 and 4.4: the
+   flow field is first computed by the gas-kinetic scheme alone): the steps n < gks_steps,
+   counted from orc_set_state, sample no particle and inject none, and their wave flux carries
+   the whole free transport of W^h (see wave_only_coef). */
+int orc_set_gks_steps(oracle_t *o, int64_t gks_steps)
+{
+    if (gks_steps < 0) return ORC_E_ARG;
+    o->gks_steps = gks_steps;
+    return ORC_OK;
+}
+
+/* sampling of the hydro particles' velocities: 0 as printed in Sec. 2.4(b) (default), 1 the
+   energy-exact variant (a departure from the paper, see phase_sample) */
+int orc_set_sampling(oracle_t *o, int mode)
+{
+    if (mode != 0 && mode != 1) return ORC_E_ARG;
+    o->sampling = mode;
     return ORC_OK;
 }
 
@@ -1074,6 +1120,37 @@ int orc_set_state(oracle_t *o, const double *W)
     o->np = 0;
     o->step = 0;
     o->t = 0.0;
+    memset(o->avgA, 0, sizeof(double) * 5 * o->nc);
+    o->avg_D = 0.0;
+    o->avg_n = 0;
+    o->avg_res = INFINITY;
+    return ORC_OK;
+}
+
+/* Replace the state between steps: W and the raw sums P ([nc][5]) of the n particles that
+   remain (x, u, m, cell, uid), the step counter and the time.  The particles become the old
+   particles of the next step (any order); N_left of a cell is its count.  The averaging sums
+   are cleared and its setting kept. */
+int orc_import_state(oracle_t *o, const double *W, const double *P, int64_t n, const double *x, const double *u,
+                     const double *m, const int64_t *cell, const uint64_t *uid, int64_t step, double t)
+{
+    if (n < 0 || step < 0) return ORC_E_ARG;
+    for (int64_t i = 0; i < n; ++i)
+        if (cell[i] < 0 || cell[i] >= o->nc) return ORC_E_ARG;
+    if (reserve(o, n)) return ORC_E_CAPACITY;
+    memcpy(o->W, W, sizeof(double) * 5 * o->nc);
+    memcpy(o->P, P, sizeof(double) * 5 * o->nc);
+    memset(o->nleft, 0, sizeof(int64_t) * o->nc);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int d = 0; d < 3; ++d) { o->px[3 * i + d] = x[3 * i + d]; o->pu[3 * i + d] = u[3 * i + d]; }
+        o->pm[i] = m[i];
+        o->pc[i] = cell[i];
+        o->pid[i] = uid[i];
+        o->nleft[cell[i]] += 1;
+    }
+    o->np = n;
+    o->step = step;
+    o->t = t;
     memset(o->avgA, 0, sizeof(double) * 5 * o->nc);
     o->avg_D = 0.0;
     o->avg_n = 0;
@@ -1109,6 +1186,16 @@ void orc_get_state(const oracle_t *o, double *W, double *P, int64_t *nleft)
     memcpy(W, o->W, sizeof(double) * 5 * o->nc);
     memcpy(P, o->P, sizeof(double) * 5 * o->nc);
     memcpy(nleft, o->nleft, sizeof(int64_t) * o->nc);
+}
+
+/* Test hook: the terms of the last update of every cell, raw (times Omega): the wave flux
+   -sum_f s_f Phi_f, the sums E over the particles that ended the step in the cell and S over
+   those that started it there ([nc][5] each). */
+void orc_last_terms(const oracle_t *o, double *flux, double *E, double *S)
+{
+    memcpy(flux, o->tflux, sizeof(double) * 5 * o->nc);
+    memcpy(E, o->tE, sizeof(double) * 5 * o->nc);
+    memcpy(S, o->tS, sizeof(double) * 5 * o->nc);
 }
 
 void orc_get_particles(const oracle_t *o, double *x, double *u, double *m, int64_t *cell, uint64_t *uid)
@@ -1274,7 +1361,7 @@ static int phase_cells(oracle_t *o, cellq_t *q)
            and counts as an empty hydro part */
         double rh = o->W[5 * c] - o->P[5 * c] / o->vol[c];
         q->rhoh[c] = rh > RHOH_EPS * o->W[5 * c] ? rh : 0.0;
-        q->ec[c] = exp(-q->dt / q->tau[c]);
+        q->ec[c] = o->step < o->gks_steps ? 0.0 : exp(-q->dt / q->tau[c]);
     }
     return ORC_OK;
 }
@@ -1427,10 +1514,13 @@ static void extrap(const double *Vc, const double *g, const double *xc, const do
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
  * ones.  Per cell: rho^hp = exp(-dt/tau) rho^h, m_ref = (rho^p + rho^hp) Omega / N_ref,
  * N_sam = 2 ceil(rho^hp Omega / (2 m_ref)) raised to cover N_min - N_left (rounded up to
- * even), m_sam = rho^hp Omega / N_sam.  Pair j: X_j ~ N(0, I) by Box-Muller, velocities
- * U + s sqrt(T) X_j and U - s sqrt(T) X_j with s = sqrt(3 N_sam/2 / sum_j |X_j|^2) (one factor
- * per cell: the sample then carries exactly the mass, momentum and energy of the hydro
- * wave's collisionless part); each partner its own uniform position in the cell.
+ * even), m_sam = rho^hp Omega / N_sam.  Pair j: X_j ~ N(0, I) by Box-Muller; the partners
+ * get the velocities U + sqrt(T) X_j and U - sqrt(T) X_j (the pair of Sec. 2.4(b): the sample
+ * carries exactly the mass rho^hp Omega and the momentum rho^hp Omega U of the Maxwellian, its
+ * thermal energy is random); each partner its own uniform position in the cell.
+ * sampling = 1 (a departure from the paper): every deviation is multiplied by one factor per
+ * cell, s = sqrt(3 N_sam/2 / sum_j |X_j|^2), so that the sample also carries exactly the
+ * energy rho^hp Omega (|U|^2/2 + 3T/2).
  * S (if given) receives the sums of phi over the new particles. */
 static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsampled)
 {
@@ -1450,7 +1540,7 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
         double msam = rhohp * o->vol[c] / ns;
         if (reserve(o, o->np + ns)) return ORC_E_CAPACITY;
         double sT = sqrt(q->T[c]);
-        {
+        if (o->sampling == 1) {
             /* energy-exact pairs: the pairs already carry the momentum rho^hp U exactly; one
                factor on every thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2),
                makes their energy rho^hp (|U|^2/2 + 3T/2) exact as well */
@@ -1536,6 +1626,7 @@ double orc_flux_speed(double a, double eta)
 static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t *ninj)
 {
     *ninj = 0;
+    if (o->step < o->gks_steps) return ORC_OK; /* wave-only phase: the free stream enters as waves */
     int64_t cap = 0;
     for (int64_t c = 0; c < o->nc; ++c) {
         for (int lf = 0; lf < o->cnf[c]; ++lf) {
@@ -1681,6 +1772,7 @@ int orc_step(oracle_t *o)
     o->st_dt = dt;
 
     if (o->recon) phase_grad(o, &q);
+    const int gks = o->step < o->gks_steps;
 
     /* wave flux over every face, oriented owner -> neighbour, times the face area */
     for (int64_t f = 0; f < nf; ++f) {
@@ -1698,29 +1790,30 @@ int orc_step(oracle_t *o)
                 extrap(o->W + 5 * nb, q.gW + 15 * nb, o->xc + 3 * nb, xf, Wr);
                 extrap(q.Wh + 5 * nb, q.gH + 15 * nb, o->xc + 3 * nb, xf, Whr);
                 orc_flux2_interior(Wl, Wr, Whl, Whr, q.gW + 15 * c, q.gW + 15 * nb, q.gH + 15 * c, q.gH + 15 * nb, n,
-                                   dt, o->mu_ref, o->omega, o->c2, F);
+                                   dt, o->mu_ref, o->omega, o->c2, gks, F);
             } else {
                 const obc_t *b = o->bc + (-1 - nb);
                 if (b->type == BC_SPECULAR)
-                    orc_flux2_specular(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, n, dt, o->mu_ref, o->omega, o->c2, F);
+                    orc_flux2_specular(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, n, dt, o->mu_ref, o->omega, o->c2, gks,
+                                       F);
                 else if (b->type == BC_DIFFUSE)
-                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, F);
+                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, gks, F);
                 else
                     orc_flux2_farfield(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, b->Winf, n, dt, o->mu_ref, o->omega,
-                                       o->c2, F);
+                                       o->c2, gks, F);
             }
         } else if (nb >= 0) {
             orc_flux_interior(o->W + 5 * c, o->W + 5 * nb, q.rhoh[c], q.rhoh[nb], n, dt, o->mu_ref, o->omega,
-                              o->c2, F);
+                              o->c2, gks, F);
         } else {
             const obc_t *b = o->bc + (-1 - nb);
             if (b->type == BC_SPECULAR)
-                orc_flux_specular(o->W + 5 * c, q.rhoh[c], n, dt, o->mu_ref, o->omega, o->c2, F);
+                orc_flux_specular(o->W + 5 * c, q.rhoh[c], n, dt, o->mu_ref, o->omega, o->c2, gks, F);
             else if (b->type == BC_DIFFUSE)
-                orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, F);
+                orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, gks, F);
             else
                 orc_flux_interior(o->W + 5 * c, b->Winf, q.rhoh[c], b->Winf[0], n, dt, o->mu_ref, o->omega,
-                                  o->c2, F);
+                                  o->c2, gks, F);
         }
         for (int k = 0; k < 5; ++k) Phi[5 * f + k] = F[k] * o->farea[f];
     }
@@ -1787,6 +1880,9 @@ int orc_step(oracle_t *o)
             for (int k = 0; k < 5; ++k) acc[k] = acc[k] - s * Phi[5 * f + k];
         }
         for (int k = 0; k < 5; ++k) {
+            o->tflux[5 * c + k] = acc[k];
+            o->tE[5 * c + k] = E[5 * c + k];
+            o->tS[5 * c + k] = S[5 * c + k];
             acc[k] = acc[k] + (E[5 * c + k] - S[5 * c + k]);
             o->W[5 * c + k] = o->W[5 * c + k] + acc[k] / o->vol[c];
             o->P[5 * c + k] = Pn[5 * c + k];

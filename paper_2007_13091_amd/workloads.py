@@ -79,6 +79,10 @@ class Params:
     gamma: float = 5.0 / 3.0
     recon: int = 0          # 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan
     venkat_k: float = 1.0   # Venkatakrishnan constant K
+    sampling: int = 0       # hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b),
+                            # 1 the energy-exact variant (one factor per cell on the deviations)
+    gks_steps: int = 0      # steps from the initial state run wave-only (no particles): the
+                            # continuum start of the paper's hypersonic cases
 
 
 def mu_ref_from_kn(kn: float, omega: float) -> float:
@@ -497,23 +501,33 @@ def small_cube(**kw) -> Workload:
 # --------------------------------------------------------------------------------------
 # batches of independent instances
 # --------------------------------------------------------------------------------------
-def batched(n_inst=64, cells=(2e3, 2e5), kn=(1e-4, 1.0), n_ref=(50, 500), cfl=0.5, seed=1):
-    """Independent instances alternating shock tube and cavity: cell counts log-uniform in
-    `cells`, Knudsen numbers log-uniform in `kn`, N_ref uniform integers in `n_ref` (seeded).
-    Tube: N_x x 2 x 2 boxes with N_x = ceil(cells / 4), h = 1 / N_x, the Sod data.  Cavity: n^3
-    boxes with n = round(cells^(1/3)), the lid-driven cavity data.  All CFL `cfl`, N_min 0."""
+def batched_specs(n_inst=64, cells=(2e3, 2e5), kn=(1e-4, 1.0), n_ref=(50, 500), seed=1):
+    """The seeded draws of `batched`: per instance (kind, target cell count, Kn, N_ref), kind
+    'sod' for even and 'cavity' for odd instances."""
     rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0x42415443], dtype=np.uint64)))
     out = []
     for k in range(n_inst):
         nc = math.exp(rng.uniform(math.log(cells[0]), math.log(cells[1])))
         knk = math.exp(rng.uniform(math.log(kn[0]), math.log(kn[1])))
         nr = int(rng.integers(n_ref[0], n_ref[1] + 1))
-        if k % 2 == 0:
-            w = sod(nx=max(2, math.ceil(nc / 4)), ny=2, nz=2, n_ref=nr, kn=knk, cfl=cfl, seed=seed)
-        else:
-            w = cavity(n=max(2, int(round(nc ** (1.0 / 3.0)))), n_ref=nr, kn=knk, cfl=cfl, seed=seed)
-        out.append(w)
+        out.append(("sod" if k % 2 == 0 else "cavity", nc, knk, nr))
     return out
+
+
+def batched_instance(spec, cfl=0.5, seed=1) -> Workload:
+    """One instance of `batched` from its draws (kind, cells, Kn, N_ref)."""
+    kind, nc, knk, nr = spec
+    if kind == "sod":
+        return sod(nx=max(2, math.ceil(nc / 4)), ny=2, nz=2, n_ref=nr, kn=knk, cfl=cfl, seed=seed)
+    return cavity(n=max(2, int(round(nc ** (1.0 / 3.0)))), n_ref=nr, kn=knk, cfl=cfl, seed=seed)
+
+
+def batched(n_inst=64, cells=(2e3, 2e5), kn=(1e-4, 1.0), n_ref=(50, 500), cfl=0.5, seed=1):
+    """Independent instances alternating shock tube and cavity: cell counts log-uniform in
+    `cells`, Knudsen numbers log-uniform in `kn`, N_ref uniform integers in `n_ref` (seeded).
+    Tube: N_x x 2 x 2 boxes with N_x = ceil(cells / 4), h = 1 / N_x, the Sod data.  Cavity: n^3
+    boxes with n = round(cells^(1/3)), the lid-driven cavity data.  All CFL `cfl`, N_min 0."""
+    return [batched_instance(sp, cfl=cfl, seed=seed) for sp in batched_specs(n_inst, cells, kn, n_ref, seed)]
 
 
 def small_batch(n_inst=6, seed=1):
