@@ -117,6 +117,20 @@ typedef struct {
     uint64_t seed;        /* Philox4x64-10 key word 0 */
     double venkat_k;      /* Venkatakrishnan constant K, eps^2 = (K h)^3 with h = Omega^(1/3)
                              (recon = 2; must be > 0 then) */
+    int32_t sampling;     /* velocities of the sampled hydro particles (Sec. 2.4(b)):
+                             0 = the pairs u = U + sqrt(T) X, u' = U - sqrt(T) X with X ~ N(0, I),
+                                 as the paper states them: the sample carries exactly the mass
+                                 and momentum of rho^hp, its thermal energy is random;
+                             1 = energy-exact pairs (a departure from the paper): one factor
+                                 per cell on every deviation, sqrt(3 N_pairs / sum_j |X_j|^2),
+                                 so that the sample also carries exactly the energy */
+    int32_t gks_steps;    /* wave-only start: the steps n < gks_steps, counted from
+                             ugkwp_init_state, sample no particle and let no free-stream particle
+                             enter; their wave flux carries the whole free transport of W^h,
+                             int u_n (q4 g0^h + q5 u.g_x^h) psi (the wave flux of Sec. 2.4 without
+                             the terms of the sampled particles).  This is how the paper starts
+                             its hypersonic cases (Sec. 4.3, Sec. 4.4): from a field computed by
+                             the gas-kinetic scheme alone.  0 = off */
 } ugkwp_params;
 
 /* Statistics of a step.  For a batch, ugkwp_step reports the counts summed over the
@@ -199,6 +213,29 @@ int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n);
  * Any pointer may be NULL to skip that field.  Synchronises. */
 int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell,
                                uint64_t *uid);
+
+/* State between steps, for checkpoints, restarts and tests: everything a step reads
+ * that the previous step left (Sec. 2.3: the conservative state W, the raw sums P of the
+ * collisionless particles that remain, so that W^p = P/Omega, and those particles), plus each
+ * instance's step counter and time.  The particles themselves are copied with
+ * ugkwp_export_particles (grouped by cell, the library's order).
+ * ugkwp_export_state: W [n_cells][5] conservative, P [n_cells][5] raw particle sums, step
+ * [n_inst], t [n_inst]; host arrays, any may be NULL.  Synchronises; reports a pending device
+ * error like ugkwp_moments. */
+int32_t ugkwp_export_state(ugkwp_ctx *ctx, double *W, double *P, int64_t *step, double *t);
+
+/* Replace the state: W and P as above (host, [n_cells][5]); n particles (host) x [n][3],
+ * u [n][3], m [n], cell [n] (concatenated cell numbering, non-decreasing: grouped by cell),
+ * uid [n]; step [n_inst] (each below 2^19, the particle-id field) and t [n_inst].  The
+ * particles become the old particles of the next step, N_left of a cell is its count; the
+ * time-averaging sums are cleared (the setting is kept).  The FP32 form rounds x, u and m to
+ * single precision.  Importing what ugkwp_export_state and ugkwp_export_particles gave
+ * continues the run bit for bit.  Errors: E_ARG (null pointers, unsorted or out-of-range
+ * cells, bad step or t), E_CAPACITY (n above the capacity), E_NONPHYS (rho <= 0 or T <= 0 in
+ * W); on error the previous state is untouched.  Clears a poisoned context.  Synchronises. */
+int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int64_t n, const double *x,
+                           const double *u, const double *m, const int32_t *cell, const uint64_t *uid,
+                           const int64_t *step, const double *t);
 
 /* Per-cell geometry as the library computed it: volume [n_cells], centroid [n_cells][3],
  * projections Delta S [n_cells][3] (host arrays). */

@@ -220,6 +220,14 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
         err = "params: recon is 0, 1 or 2 (2 needs venkat_k > 0); precision is 0 (FP64) or 1 (FP32 form)";
         return UGKWP_E_ARG;
     }
+    if (p.gks_steps < 0) {
+        err = "params: gks_steps must be >= 0";
+        return UGKWP_E_ARG;
+    }
+    if (p.sampling != 0 && p.sampling != 1) {
+        err = "params: sampling is 0 (the pairs of Sec. 2.4(b)) or 1 (energy-exact pairs)";
+        return UGKWP_E_ARG;
+    }
     long long c = p.capacity;
     if (c == 0) {
         long long per = (long long)(p.n_ref > p.n_min ? p.n_ref : p.n_min);
@@ -406,6 +414,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         q.recon = p[k].recon;
         q.venkat_k = p[k].venkat_k;
         q.seed = p[k].seed;
+        q.sampling = p[k].sampling;
+        q.gks_steps = p[k].gks_steps;
         q.cell0 = r.cell0;
         q.cell1 = r.cell1;
         q.ff0 = r.ff0;
@@ -703,6 +713,135 @@ int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, 
         }
         if (cell) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
     }
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_export_state(ugkwp_ctx *ctx, double *W, double *P, int64_t *step, double *t) {
+    if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "export before init_state");
+    Dev &D = ctx->D;
+    const size_t nc = (size_t)D.nc;
+    hipStream_t s = ctx->stream;
+    Scalars sc;
+    int32_t st = read_scalars(ctx, sc);
+    if (st != UGKWP_OK) return st;
+    std::vector<double> buf(5 * nc);
+    const double *src[2] = {D.W, D.P};
+    double *dst[2] = {W, P};
+    for (int q = 0; q < 2; ++q) {
+        if (!dst[q]) continue;
+        HIPCHK(ctx, hipMemcpyAsync(buf.data(), src[q], 5 * nc * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        for (size_t c = 0; c < nc; ++c)
+            for (int k = 0; k < 5; ++k) dst[q][5 * c + k] = buf[k * nc + c];
+    }
+    if (step || t) {
+        std::vector<ugkwp::InstS> is((size_t)D.n_inst);
+        HIPCHK(ctx, hipMemcpyAsync(is.data(), D.is, is.size() * sizeof(ugkwp::InstS), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        for (size_t k = 0; k < is.size(); ++k) {
+            if (step) step[k] = is[k].step;
+            if (t) t[k] = is[k].t;
+        }
+    }
+    return UGKWP_OK;
+}
+
+int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int64_t n, const double *x,
+                           const double *u, const double *m, const int32_t *cell, const uint64_t *uid,
+                           const int64_t *step, const double *t) {
+    if (!ctx || !W || !P || !step || !t || n < 0 || (n > 0 && (!x || !u || !m || !cell || !uid)))
+        return fail(ctx, UGKWP_E_ARG, "import_state: null argument or negative particle count");
+    Dev &D = ctx->D;
+    const size_t nc = (size_t)D.nc;
+    if (n > D.cap) return fail(ctx, UGKWP_E_CAPACITY, "import_state: more particles than the capacity");
+    for (size_t c = 0; c < nc; ++c) {
+        const double *w = W + 5 * c;
+        const double rho = w[0];
+        const double T = (2.0 / 3.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
+        if (!(rho > 0.0) || !(T > 0.0) || !std::isfinite(rho) || !std::isfinite(T))
+            return fail(ctx, UGKWP_E_NONPHYS, "import_state: cell " + std::to_string(c) + " has rho <= 0 or T <= 0");
+    }
+    // particles grouped by cell: cell indices non-decreasing and in range
+    std::vector<int32_t> cnt(nc, 0), seg(nc + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (cell[i] < 0 || (size_t)cell[i] >= nc || (i > 0 && cell[i] < cell[i - 1]))
+            return fail(ctx, UGKWP_E_ARG, "import_state: particle " + std::to_string(i) +
+                                              ": cells must be in range and non-decreasing (grouped by cell)");
+        ++cnt[(size_t)cell[i]];
+    }
+    for (size_t c = 0; c < nc; ++c) seg[c + 1] = seg[c] + cnt[c];
+    for (int32_t k = 0; k < D.n_inst; ++k)
+        if (step[k] < 0 || step[k] >= (1LL << 19) || !std::isfinite(t[k]) || t[k] < 0.0)
+            return fail(ctx, UGKWP_E_ARG, "import_state: step must be in [0, 2^19) and t finite and >= 0");
+    hipStream_t s = ctx->stream;
+    const int b = ctx->buf;
+    const ugkwp::Particles &pa = D.pa[b];
+    std::vector<double> Wt(5 * nc), Pt(5 * nc);
+    for (size_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 5; ++k) {
+            Wt[k * nc + c] = W[5 * c + k];
+            Pt[k * nc + c] = P[5 * c + k];
+        }
+    HIPCHK(ctx, up(D.W, Wt, s));
+    HIPCHK(ctx, up(D.P, Pt, s));
+    HIPCHK(ctx, up(D.nleft, cnt, s));
+    HIPCHK(ctx, up(D.segoff[b], seg, s));
+    std::vector<ugkwp::PRec> rec;
+    std::vector<ugkwp::PRec32> rec32;
+    std::vector<float> m32;
+    if (n > 0) {
+        if (D.prec == 1) {
+            rec32.resize((size_t)n);
+            m32.resize((size_t)n);
+            for (int64_t i = 0; i < n; ++i) {
+                for (int d = 0; d < 3; ++d) {
+                    rec32[i].x[d] = (float)x[3 * i + d];
+                    rec32[i].u[d] = (float)u[3 * i + d];
+                }
+                rec32[i].uid = uid[i];
+                m32[i] = (float)m[i];
+            }
+            HIPCHK(ctx, up(pa.rec32, rec32, s));
+            HIPCHK(ctx, up(pa.m32, m32, s));
+        } else {
+            rec.resize((size_t)n);
+            for (int64_t i = 0; i < n; ++i) {
+                for (int d = 0; d < 3; ++d) {
+                    rec[i].x[d] = x[3 * i + d];
+                    rec[i].u[d] = u[3 * i + d];
+                }
+                rec[i].m = m[i];
+                rec[i].uid = uid[i];
+            }
+            HIPCHK(ctx, up(pa.rec, rec, s));
+        }
+        HIPCHK(ctx, hipMemcpyAsync(pa.cell, cell, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    // step bookkeeping as after a step: the particles are the old ones of the next step
+    Scalars sc;
+    std::memset(&sc, 0, sizeof(sc));
+    sc.dtmin_bits = 0x7FF0000000000000ULL;
+    sc.n_old = n;
+    sc.n_alive = n;
+    sc.step = step[0];
+    sc.t = t[0];
+    HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
+    std::vector<ugkwp::InstS> is((size_t)D.n_inst);
+    std::memset(is.data(), 0, is.size() * sizeof(ugkwp::InstS));
+    for (int32_t k = 0; k < D.n_inst; ++k) {
+        const ugkwp::InstRange &r = ctx->ranges[k];
+        is[k].dtmin_bits = 0x7FF0000000000000ULL;
+        is[k].step = step[k];
+        is[k].t = t[k];
+        is[k].n_alive = seg[(size_t)r.cell1] - seg[(size_t)r.cell0];
+    }
+    HIPCHK(ctx, up(D.is, is, s));
+    ugkwp::launch_fill_f64(D.avgA, 5 * (long long)nc, 0.0, s);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->have_state = true;
+    ctx->poisoned = false;
     return UGKWP_OK;
 }
 

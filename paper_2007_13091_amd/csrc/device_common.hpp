@@ -42,6 +42,8 @@ struct InstP {
     unsigned long long seed;
     int32_t cell0, cell1;  // cells [cell0, cell1)
     int32_t ff0, ff1;      // far-field faces [ff0, ff1)
+    int32_t sampling;      // hydro-particle velocities: 0 U +- sqrt(T) X (Sec. 2.4(b)), 1 energy-exact
+    int32_t gks_steps;     // steps n < gks_steps of the instance are wave-only (no particles)
     long long bf0;         // its first input boundary face in the concatenated list
 };
 

@@ -257,13 +257,14 @@ __device__ __forceinline__ void qcoef(R dt, R tau, R &q1, R &q4m) {
     }
 }
 
-// First-order wave flux between two face-frame states:
+// First-order wave flux between two face-frame states (gks: the wave-only start phase, in which
+// no particle is sampled and the waves carry the whole free transport q4 g^h of the hydro part):
 //   F = rho0 q1 <u_n psi>_0 + (q4 - dt e) (rhoh_l <u_n psi>_{l,u>0} + rhoh_r <u_n psi>_{r,u<0})
 // with g0 from the upwind moments of both sides and tau at the face from g0 plus the
 // numerical dissipation C2 |pl - pr| / (pl + pr) dt of Sec. 2.4(d).
 template <typename R>
 __device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R hl, R hr, R dt, R mu_ref, R omega,
-                                          R c2, R Ff[5]) {
+                                          R c2, bool gks, R Ff[5]) {
     R ml[4], mr[4], Hl[5], Gl[5], Hr[5], Gr[5];
     moments4<R>(1, l.un, l.lam, ml);
     moments4<R>(-1, r.un, r.lam, mr);
@@ -283,6 +284,7 @@ __device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R 
     R tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
     R q1, q4m;
     qcoef<R>(dt, tau, q1, q4m);
+    if (gks) q4m = q4m + dt * exp(-dt / tau);  // wave-only start: the waves carry all of W^h
     R m0[4], H0[5], G0[5];
     moments4<R>(0, z.un, z.lam, m0);
     psi_moments<R>(z, m0, H0, G0);
@@ -435,7 +437,8 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
     const double rho = D.W[c];
     const double rh = rho - rhop;
     const double rhoh = rh > 1e-12 * rho ? rh : 0.0;
-    const double e = exp(-dt / D.tau[c]);
+    // wave-only start phase: no particle is sampled
+    const double e = D.is[inst].step < P.gks_steps ? 0.0 : exp(-dt / D.tau[c]);
     D.rhoh[c] = rhoh;
     D.ec[c] = e;
     const double rhohp = e * rhoh;
@@ -483,9 +486,10 @@ __global__ void k_sample_setup(Dev D) {
 // u_n < 0 for the step, rho_w from zero net mass flux; the mass component is exactly 0.
 template <typename R>
 __device__ __forceinline__ void diffuse_flux(const Prim<R> &l, R h, R tau_c, const R n[3], const R t1[3],
-                                             const R t2[3], const DevBC &bc, R dt, R Ff[5]) {
+                                             const R t2[3], const DevBC &bc, R dt, bool gks, R Ff[5]) {
     R q1, q4m;
     qcoef<R>(dt, tau_c, q1, q4m);
+    if (gks) q4m = q4m + dt * exp(-dt / tau_c);
     R ml[4], Hl[5], Gl[5];
     moments4<R>(1, l.un, l.lam, ml);
     psi_moments<R>(l, ml, Hl, Gl);
@@ -524,6 +528,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
     if (P.recon != 0) return;
     const R dt = (R)D.is[inst].dt;
     const R mu = (R)P.mu_ref, om = (R)P.omega, c2 = (R)P.c2;
+    const bool gks = D.is[inst].step < P.gks_steps;
     const int nb = D.fnb[f];
     R n[3] = {(R)D.fn[f], (R)D.fn[nf + f], (R)D.fn[2 * nf + f]};
     R t1[3], t2[3];
@@ -538,7 +543,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) Wr[k] = D.W[k * nc + nb];
         const Prim<R> r = to_frame<R>(Wr, n, t1, t2);
-        flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, Ff);
+        flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, gks, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
         if (bc.type == 0) {
@@ -546,17 +551,17 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
             Prim<R> g = l;
             g.un = -l.un;
             const R h = (R)D.rhoh[c];
-            flux_pair<R>(l, g, h, h, dt, mu, om, c2, Ff);
+            flux_pair<R>(l, g, h, h, dt, mu, om, c2, gks, Ff);
             Ff[0] = (R)0;
             Ff[2] = (R)0;
             Ff[3] = (R)0;
             Ff[4] = (R)0;
         } else if (bc.type == 1) {
-            diffuse_flux<R>(l, (R)D.rhoh[c], (R)D.tau[c], n, t1, t2, bc, dt, Ff);
+            diffuse_flux<R>(l, (R)D.rhoh[c], (R)D.tau[c], n, t1, t2, bc, dt, gks, Ff);
         } else {
             // far field: the free stream as the right state (hydro density = its density)
             const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2);
-            flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, Ff);
+            flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, gks, Ff);
         }
     }
     const R a = (R)D.farea[f];
@@ -726,7 +731,7 @@ __device__ __forceinline__ void frame_derivs(const double *G, long long stride, 
 //   F = rho0 [q1 <u psi> + q2 <u (u.abar) psi> + q3 <u Abar psi>]
 //     + sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e/2) <u (u.a~_s) psi>_s]
 template <typename R>
-__device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref, R omega, R c2, R Ff[5]) {
+__device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref, R omega, R c2, bool gks, R Ff[5]) {
     Mom3<R> ML, MR, M0;
     mom3<R>(1, L.g, ML);
     mom3<R>(-1, Rs.g, MR);
@@ -773,6 +778,12 @@ __device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref
     const R tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
     R q[5];
     qcoef5<R>(dt, tau, q);
+    if (gks) {
+        // wave-only start: q4 = (q4 - dt e) + dt e, q5 = (q5 + dt^2 e / 2) - dt^2 e / 2
+        const R e = exp(-dt / tau);
+        q[3] = q[3] + dt * e;
+        q[4] = q[4] - (R)0.5 * dt * dt * e;
+    }
     {
         R G0[5], X0[5], X1[5], X2[5], GA[5];
         uvec<R>(M0, G0);
@@ -999,6 +1010,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
     if (P.recon == 0) return;
     const R dt = (R)D.is[inst].dt;
     const R mu = (R)P.mu_ref, om = (R)P.omega, c2 = (R)P.c2;
+    const bool gks = D.is[inst].step < P.gks_steps;
     const int nb = D.fnb[f];
     R n[3] = {(R)D.fn[f], (R)D.fn[nf + f], (R)D.fn[2 * nf + f]};
     R t1[3], t2[3];
@@ -1013,7 +1025,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
         double Wr[5], Whr[5];
         extrap(D, nb, xf, Wr, Whr);
         make_side<R>(D, nb, Wr, Whr, n, t1, t2, Rs);
-        flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
+        flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
         if (bc.type == 0) {
@@ -1028,13 +1040,13 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
                     Rs.dW[d][k] = sg * L.dW[d][k];
                     Rs.dWh[d][k] = sg * L.dWh[d][k];
                 }
-            flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
             Ff[0] = (R)0;
             Ff[2] = (R)0;
             Ff[3] = (R)0;
             Ff[4] = (R)0;
         } else if (bc.type == 1) {
-            diffuse_flux<R>(L.g, (R)Whl[0], (R)D.tau[c], n, t1, t2, bc, dt, Ff);
+            diffuse_flux<R>(L.g, (R)Whl[0], (R)D.tau[c], n, t1, t2, bc, dt, gks, Ff);
         } else {
             Rs.g = to_frame<R>(bc.Winf, n, t1, t2);
             Rs.h = Rs.g;
@@ -1042,7 +1054,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int k = 0; k < 5; ++k) Rs.dW[d][k] = Rs.dWh[d][k] = (R)0;
-            flux2_pair<R>(L, Rs, dt, mu, om, c2, Ff);
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
         }
     }
     const R a = (R)D.farea[f];
@@ -1086,9 +1098,11 @@ __device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
 // X0, X1 = r1 (cos, sin)(2 pi e1), r1 = sqrt(-2 ln e0), and X2 = r2 cos(2 pi e3), r2 =
 // sqrt(-2 ln e2).  The even partner evaluates the first half, the odd one the second (the
 // same code on the other two uniforms), and they exchange halves.  Partners get
-// U + s sqrt(T) X and U - s sqrt(T) X (s: the cell's energy-exact factor) and their own
-// uniform position (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).
-// The first pass sums |X|^2 for s and keeps each lane's first half for the second.
+// U + sqrt(T) X and U - sqrt(T) X, the pair of Sec. 2.4(b), and their own uniform position
+// (box: per axis; tetrahedron: Rocchini-Cignoni folding of the unit cube).  With the
+// energy-exact variant (sampling = 1, a departure from the paper) the deviations carry one
+// factor s per cell, s = sqrt(3 N_pairs / sum_j |X_j|^2): a first pass sums |X|^2 for s and
+// keeps each lane's first half for the second.
 // S = P + sum of phi over the new particles (fixed tree over the wave).
 // ---------------------------------------------------------------------------------------
 // this lane's half of its pair's normal: (r cos a, r sin a), r = sqrt(-2 ln e0 or e2),
@@ -1134,8 +1148,9 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         R sT = sqrt(T);
         const R one = (R)1;
         const bool odd = (lane & 1) != 0;
-        R f0 = (R)0, f1 = (R)0;  // this lane's half of its first pair's normal
-        {
+        const bool exact = P.sampling == 1;
+        R f0 = (R)0, f1 = (R)0;  // this lane's half of its first pair's normal (energy-exact pass)
+        if (exact) {
             // energy-exact pairs: the pairs carry the momentum exactly; one factor on every
             // thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2), makes the energy
             // exact too (a first pass over the pairs' normal draws, summed in FP64)
@@ -1164,7 +1179,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         for (long long k0 = 0; k0 < ns; k0 += kWave) {
             const long long k = k0 + lane;
             R h0 = f0, h1 = f1;
-            if (k0 > 0 && k < ns) half_normal<R>(seed, make_uid(step, cl, k & ~1LL), step, inst, odd, h0, h1);
+            if ((k0 > 0 || !exact) && k < ns) half_normal<R>(seed, make_uid(step, cl, k & ~1LL), step, inst, odd, h0, h1);
             const R X0 = __shfl(h0, lane & ~1), X1 = __shfl(h1, lane & ~1), X2 = __shfl(h0, lane | 1);
             if (k < ns) {
                 const long long i = base + k;
@@ -1267,7 +1282,8 @@ __device__ Inflow inflow_face(const Dev &D, int j) {
         (2.0 / 3.0) * (b.Winf[4] - 0.5 * (b.Winf[1] * b.Winf[1] + b.Winf[2] * b.Winf[2] + b.Winf[3] * b.Winf[3]) / rho) /
         rho;
     const double tau = P.mu_ref * pow(T, P.omega) / (rho * T);
-    const double e = exp(-dt / tau);
+    // wave-only start phase: the free stream enters as waves only
+    const double e = D.is[q.inst].step < P.gks_steps ? 0.0 : exp(-dt / tau);
     const double4 pl = D.plane[q.c * 6 + q.lf];  // outward: the particle enters along -n
     q.nin[0] = -pl.x;
     q.nin[1] = -pl.y;

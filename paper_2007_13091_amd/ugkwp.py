@@ -23,7 +23,8 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
-           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask", "ugkwp_set_averaging", "ugkwp_average")
+           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask", "ugkwp_set_averaging", "ugkwp_average",
+           "ugkwp_export_state", "ugkwp_import_state")
 N_PROFILE_SLOTS = 12
 
 
@@ -44,7 +45,8 @@ class UgkwpParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu_ref", C.c_double), ("omega", C.c_double), ("cfl", C.c_double),
                 ("c2", C.c_double), ("n_ref", C.c_int32), ("n_min", C.c_int32), ("recon", C.c_int32),
                 ("precision", C.c_int32), ("capacity", C.c_int64), ("max_crossings", C.c_int32),
-                ("seed", C.c_uint64), ("venkat_k", C.c_double)]
+                ("seed", C.c_uint64), ("venkat_k", C.c_double), ("sampling", C.c_int32),
+                ("gks_steps", C.c_int32)]
 
 
 class UgkwpStats(C.Structure):
@@ -107,6 +109,12 @@ def lib():
         L.ugkwp_export_particles.restype = C.c_int32
         L.ugkwp_export_particles.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int32),
                                              P(C.c_uint64)]
+        L.ugkwp_export_state.restype = C.c_int32
+        L.ugkwp_export_state.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_int64), P(C.c_double)]
+        L.ugkwp_import_state.restype = C.c_int32
+        L.ugkwp_import_state.argtypes = [vp, P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double),
+                                         P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_uint64),
+                                         P(C.c_int64), P(C.c_double)]
         L.ugkwp_geometry.restype = C.c_int32
         L.ugkwp_geometry.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.ugkwp_profile_enable.restype = C.c_int32
@@ -154,7 +162,8 @@ class _MeshArgs:
 
 def make_params(p, capacity=0, precision=0) -> UgkwpParams:
     return UgkwpParams(p.gamma, p.mu_ref, p.omega, p.cfl, p.c2, p.n_ref, p.n_min, int(getattr(p, "recon", 0)),
-                       precision, capacity, p.max_crossings, p.seed, float(getattr(p, "venkat_k", 1.0)))
+                       precision, capacity, p.max_crossings, p.seed, float(getattr(p, "venkat_k", 1.0)),
+                       int(getattr(p, "sampling", 0)), int(getattr(p, "gks_steps", 0)))
 
 
 class _BatchArgs:
@@ -304,6 +313,33 @@ class Solver:
         self._check(lib().ugkwp_export_particles(self.h, _ptr(x, C.c_double), _ptr(u, C.c_double),
                                                  _ptr(m, C.c_double), _ptr(c, C.c_int32), _ptr(uid, C.c_uint64)))
         return dict(x=x, u=u, m=m, cell=c, uid=uid)
+
+    def export_state(self):
+        """The state between steps: W, P ([n_cells][5]; W^p = P / Omega), the particles (grouped
+        by cell) and each instance's step and time."""
+        W = np.zeros((self.nc, 5)); P = np.zeros((self.nc, 5))
+        step = np.zeros(self.n_inst, dtype=np.int64); t = np.zeros(self.n_inst)
+        self._check(lib().ugkwp_export_state(self.h, _ptr(W, C.c_double), _ptr(P, C.c_double),
+                                             _ptr(step, C.c_int64), _ptr(t, C.c_double)))
+        return dict(W=W, P=P, particles=self.particles(), step=step, t=t)
+
+    def import_state(self, state):
+        """Replace the state by one of export_state's (or any state of that form)."""
+        W = np.ascontiguousarray(state["W"], dtype=np.float64).reshape(self.nc, 5)
+        P = np.ascontiguousarray(state["P"], dtype=np.float64).reshape(self.nc, 5)
+        p = state["particles"]
+        n = int(np.asarray(p["uid"]).shape[0])
+        x = np.ascontiguousarray(p["x"], dtype=np.float64).reshape(n, 3)
+        u = np.ascontiguousarray(p["u"], dtype=np.float64).reshape(n, 3)
+        m = np.ascontiguousarray(p["m"], dtype=np.float64).reshape(n)
+        c = np.ascontiguousarray(p["cell"], dtype=np.int32).reshape(n)
+        uid = np.ascontiguousarray(p["uid"], dtype=np.uint64).reshape(n)
+        step = np.ascontiguousarray(np.broadcast_to(state["step"], (self.n_inst,)), dtype=np.int64)
+        t = np.ascontiguousarray(np.broadcast_to(state["t"], (self.n_inst,)), dtype=np.float64)
+        self._check(lib().ugkwp_import_state(self.h, _ptr(W, C.c_double), _ptr(P, C.c_double), n,
+                                             _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(m, C.c_double),
+                                             _ptr(c, C.c_int32), _ptr(uid, C.c_uint64), _ptr(step, C.c_int64),
+                                             _ptr(t, C.c_double)))
 
     def profile(self, on=True, slots=None):
         """Bracket each kernel group of a step with hip events (measurement support); slots:

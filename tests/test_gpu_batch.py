@@ -64,10 +64,13 @@ def _run_batch(ws, steps, precision=0, check_every=1, name=""):
     return g, os_
 
 
-def test_small_batch_matches_instances_alone():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_small_batch_matches_instances_alone(sampling):
     ws = wl.small_batch(6)
+    for w in ws:
+        w.params.sampling = sampling
     _say("cells", [w.mesh.n_cells for w in ws])
-    _run_batch(ws, 6, name="small-batch")
+    _run_batch(ws, 6, name=f"small-batch sampling={sampling}")
 
 
 def test_mixed_batch_with_far_field_and_tets():
@@ -78,6 +81,9 @@ def test_mixed_batch_with_far_field_and_tets():
           wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=60, kn=0.05, perturb=0.3),
           wl.closed_box(n=(3, 2, 2), n_ref=80, kn=2.0, bc=wl.BC_DIFFUSE, perturb=0.3),
           wl.periodic_box(n=(4, 3, 2), n_ref=60, kn=0.1)]
+    # the sampling rule is a per-instance parameter: alternate the two modes
+    for k, w in enumerate(ws):
+        w.params.sampling = k % 2
     _run_batch(ws, 6, name="mixed-batch")
 
 

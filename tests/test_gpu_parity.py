@@ -40,7 +40,13 @@ def _oracle(w):
     return o
 
 
-def run_pair(w, steps, every=1, capacity=0, length=1.0, vscale=3.0, name=""):
+def run_pair(w, steps, every=1, capacity=0, length=1.0, vscale=3.0, name="", sampling=None, min_steps=None):
+    """GPU and oracle side by side for `steps` steps.  min_steps: the run may end earlier with a
+    non-physical state (E_NONPHYS), provided both sides report it at the same step and at
+    least min_steps steps were compared before it."""
+    if sampling is not None:
+        w.params.sampling = sampling
+        name = f"{name} sampling={sampling}"
     s = _solver(w, capacity)
     o = _oracle(w)
     vol, _, _ = o.geometry()
@@ -50,8 +56,24 @@ def run_pair(w, steps, every=1, capacity=0, length=1.0, vscale=3.0, name=""):
     np.testing.assert_allclose(dSg, dSo, rtol=1e-14, atol=1e-300)
     for n in range(steps):
         _say(name, "step", n)
-        sg = s.step(1)
-        o.step()
+        if min_steps is None:
+            sg = s.step(1)
+            o.step()
+        else:
+            import oracle
+            from paper_2007_13091_amd.ugkwp import E_NONPHYS, UgkwpError
+
+            try:
+                sg = s.step(1)
+            except UgkwpError as e:
+                assert e.status == E_NONPHYS, f"{name}: {e}"
+                with pytest.raises(oracle.OracleError) as eo:
+                    o.step()
+                assert eo.value.status == oracle.E_NONPHYS, f"{name}: oracle did not fail at step {n}"
+                assert n >= min_steps, f"{name}: non-physical after only {n} steps"
+                _say(name, "both sides non-physical at step", n)
+                return s, o
+            o.step()
         compare_stats(sg, o.stats(), what=f"{name} step {n}")
         if (n + 1) % every == 0 or n == steps - 1:
             Wo, Po, _ = o.state()
@@ -60,43 +82,49 @@ def run_pair(w, steps, every=1, capacity=0, length=1.0, vscale=3.0, name=""):
     return s, o
 
 
-def test_sod_40_steps():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_sod_40_steps(sampling):
     w = wl.sod()  # 50x2x2 boxes, 200 particles/cell, Kn 1e-3, specular walls
-    run_pair(w, 40, every=1, name="sod")
+    run_pair(w, 40, every=1, name="sod", sampling=sampling)
 
 
+@pytest.mark.parametrize("sampling", [0, 1])
 @pytest.mark.parametrize("tets", [False, True])
-def test_single_cell_and_one_column_meshes(tets):
+def test_single_cell_and_one_column_meshes(tets, sampling):
     # degenerate sizes: one box cell (or the six tetrahedra of one box), and a one-cell-wide
     # column with diffuse walls, where every particle leaves its cell only through walls or
     # along the column
     w = wl.closed_box(n=(1, 1, 1), n_ref=64, kn=0.05, tets=tets)
-    run_pair(w, 5, name="single box" if not tets else "one box of tets")
+    run_pair(w, 5, name="single box" if not tets else "one box of tets", sampling=sampling)
     w = wl.closed_box(n=(1, 1, 7), n_ref=30, kn=0.5, bc=wl.BC_DIFFUSE, tets=tets)
-    run_pair(w, 5, name="column")
+    run_pair(w, 5, name="column", sampling=sampling)
 
 
-def test_sod_tets_jittered_box():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_sod_tets_jittered_box(sampling):
     w = wl.closed_box(n=(4, 3, 3), n_ref=60, kn=0.02, tets=True, jitter=0.15)
-    run_pair(w, 8, name="tet-box")
+    run_pair(w, 8, name="tet-box", sampling=sampling)
 
 
-def test_cavity_small_diffuse_lid():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_cavity_small_diffuse_lid(sampling):
     w = wl.cavity(n=8, n_ref=400)
-    run_pair(w, 10, every=2, name="cavity8")
+    run_pair(w, 10, every=2, name="cavity8", sampling=sampling)
 
 
-def test_diffuse_box_rarefied_many_bounces():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_diffuse_box_rarefied_many_bounces(sampling):
     w = wl.closed_box(n=(3, 2, 2), n_ref=300, kn=2.0, bc=wl.BC_DIFFUSE, perturb=0.3)
-    run_pair(w, 6, name="diffuse-kn2")
+    run_pair(w, 6, name="diffuse-kn2", sampling=sampling)
 
 
+@pytest.mark.parametrize("sampling", [0, 1])
 @pytest.mark.parametrize("tets", [False, True])
-def test_periodic_box(tets):
+def test_periodic_box(tets, sampling):
     """Periodic faces (test support): every face interior, particles re-entering through
     the partner face at x + shift."""
     w = wl.periodic_box(n=(5, 4, 3), n_ref=80, kn=0.05, tets=tets)
-    s, _ = run_pair(w, 8, every=2, name="periodic" + ("-tets" if tets else ""))
+    s, _ = run_pair(w, 8, every=2, name="periodic" + ("-tets" if tets else ""), sampling=sampling)
     assert s.step(0)["wall_hits"] == 0
 
 
@@ -116,10 +144,11 @@ def test_periodic_box_conserves_all_five_totals(precision):
     np.testing.assert_allclose(t1, t0, rtol=5e-14, atol=0)
 
 
-def test_free_molecular_sod():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_free_molecular_sod(sampling):
     w = wl.sod(nx=20, ny=2, nz=2, n_ref=100)
     w.params.mu_ref = 1e30
-    run_pair(w, 10, name="sod-free-molecular")
+    run_pair(w, 10, name="sod-free-molecular", sampling=sampling)
 
 
 def test_continuum_limit_no_particles():
@@ -129,10 +158,11 @@ def test_continuum_limit_no_particles():
     assert s.particle_count() == 0
 
 
-def test_n_min_raises_sample_count():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_n_min_raises_sample_count(sampling):
     w = wl.closed_box(n=(3, 3, 2), n_ref=20, kn=0.01, perturb=0.2)
     w.params.n_min = 64
-    run_pair(w, 5, name="n_min")
+    run_pair(w, 5, name="n_min", sampling=sampling)
 
 
 def test_numerical_dissipation_c2():
@@ -141,17 +171,19 @@ def test_numerical_dissipation_c2():
     run_pair(w, 10, every=5, name="sod-c2")
 
 
-def test_farfield_box_transitional():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_farfield_box_transitional(sampling):
     # far field on all six sides, non-uniform inside: wave flux against W_inf, particles
     # leaving are removed and free-stream particles enter
     w = wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=120, kn=0.05, perturb=0.3)
-    run_pair(w, 8, name="farfield-hex")
+    run_pair(w, 8, name="farfield-hex", sampling=sampling)
 
 
-def test_farfield_box_tets_jittered():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_farfield_box_tets_jittered(sampling):
     w = wl.free_stream_box(n=(4, 3, 3), U=(0.5, 0.4, -0.3), T=1.2, n_ref=80, kn=0.2, perturb=0.2, tets=True,
                            jitter=0.15)
-    run_pair(w, 6, name="farfield-tet")
+    run_pair(w, 6, name="farfield-tet", sampling=sampling)
 
 
 def test_farfield_free_molecular_inflow_only():
@@ -161,20 +193,22 @@ def test_farfield_free_molecular_inflow_only():
     run_pair(w, 6, name="farfield-free-molecular")
 
 
-def test_supersonic_inflow_with_diffuse_walls():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_supersonic_inflow_with_diffuse_walls(sampling):
     # Mach 3 stream along x over a diffuse cold wall (z = 0), specular side planes
     U = 3.0 * np.sqrt(5.0 / 3.0)
     w = wl.free_stream_box(n=(6, 2, 4), U=(U, 0.0, 0.0), n_ref=60, kn=0.1, perturb=0.1,
                            walls={"zlo": wl.BC(wl.BC_DIFFUSE, Tw=1.0), "ylo": wl.BC(wl.BC_SPECULAR),
                                   "yhi": wl.BC(wl.BC_SPECULAR)})
-    run_pair(w, 8, name="supersonic-wall")
+    run_pair(w, 8, name="supersonic-wall", sampling=sampling)
 
 
-def test_cube_small_mach10():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_cube_small_mach10(sampling):
     # the Mach 10 cube case (far-field outer box, diffuse cube, jittered tets, N_min = N_ref,
     # C2 = 10) on a coarse mesh, over the steps before the wake behind the cube empties
     w = wl.small_cube(n_ref=50)
-    run_pair(w, 5, name="cube-small", length=4.0, vscale=15.0)
+    run_pair(w, 5, name="cube-small", length=4.0, vscale=15.0, sampling=sampling, min_steps=3)
 
 
 @pytest.mark.timeout(600)
@@ -186,12 +220,13 @@ def test_cube_full_size_first_steps():
     run_pair(w, 2, name="cube-full", length=12.0, vscale=15.0)
 
 
+@pytest.mark.parametrize("sampling", [0, 1])
 @pytest.mark.parametrize("kn", [1e-3, 1.0])
-def test_vehicle_small_mach15(kn):
+def test_vehicle_small_mach15(kn, sampling):
     # the Mach 15 sphere-cone (staircase body, diffuse wall at 0.2 T_0, far field) on a coarse
     # mesh at both ends of its Knudsen range, over the steps before its wake empties
     w = wl.small_vehicle(kn=kn)
-    run_pair(w, 5, name=f"vehicle-small-kn{kn}", length=4.0, vscale=25.0)
+    run_pair(w, 5, name=f"vehicle-small-kn{kn}", length=4.0, vscale=25.0, sampling=sampling, min_steps=3)
 
 
 @pytest.mark.timeout(900)
@@ -202,12 +237,13 @@ def test_vehicle_full_size_first_step():
     run_pair(w, 1, name="vehicle-full", length=8.0, vscale=25.0)
 
 
+@pytest.mark.parametrize("sampling", [0, 1])
 @pytest.mark.parametrize("recon", [1, 2])
-def test_second_order_sod(recon):
+def test_second_order_sod(recon, sampling):
     # second order: least-squares gradients with Barth-Jespersen (1) or Venkatakrishnan (2)
     w = wl.sod(n_ref=100)
     w.params.recon = recon
-    run_pair(w, 20, every=5, name=f"sod-recon{recon}")
+    run_pair(w, 20, every=5, name=f"sod-recon{recon}", sampling=sampling)
 
 
 @pytest.mark.parametrize("recon", [1, 2])
@@ -218,10 +254,11 @@ def test_second_order_farfield_tets(recon):
     run_pair(w, 6, name=f"farfield-tet-recon{recon}")
 
 
-def test_second_order_cavity_diffuse_walls():
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_second_order_cavity_diffuse_walls(sampling):
     w = wl.cavity(n=8, n_ref=200, kn=0.01)
     w.params.recon = 2
-    run_pair(w, 8, every=2, name="cavity-recon2")
+    run_pair(w, 8, every=2, name="cavity-recon2", sampling=sampling)
 
 
 def test_second_order_specular_tets_near_continuum():
@@ -299,9 +336,28 @@ def test_nonphysical_initial_state_rejected():
     assert e.value.status == E_NONPHYS
 
 
-@pytest.mark.parametrize("morton", [True, False])
-def test_cavity_full_size(morton, steps=2):
+@pytest.mark.parametrize("morton,sampling", [(True, 0), (False, 0), (True, 1)])
+def test_cavity_full_size(morton, sampling, steps=2):
     """32^3 cavity, 400 particles/cell (~1.3e7 particles): the benchmark's configuration (cells
     numbered along a Morton curve), and the same cavity numbered x fastest."""
     w = wl.morton_numbered(wl.cavity()) if morton else wl.cavity()
-    run_pair(w, steps, every=1, name="cavity32 morton" if morton else "cavity32")
+    run_pair(w, steps, every=1, name="cavity32 morton" if morton else "cavity32", sampling=sampling)
+
+
+@pytest.mark.parametrize("case", ["sod", "cavity-recon2", "farfield-tets"])
+def test_wave_only_start_then_switch(case):
+    """The wave-only start (no particles for the first gks_steps steps, the waves carry the
+    whole hydro transport) and the switch to wave-particle steps, against the oracle."""
+    if case == "sod":
+        w = wl.sod(nx=30, ny=2, nz=2, n_ref=80, kn=1e-2)
+        w.params.gks_steps = 4
+    elif case == "cavity-recon2":
+        w = wl.cavity(n=8, n_ref=120, kn=0.02)
+        w.params.recon = 2
+        w.params.gks_steps = 3
+    else:
+        w = wl.free_stream_box(n=(4, 3, 3), U=(2.5, 0.4, -0.3), T=1.2, n_ref=60, kn=0.1, perturb=0.2, tets=True,
+                               jitter=0.15, walls={"zlo": wl.BC(wl.BC_DIFFUSE, Tw=1.0)})
+        w.params.gks_steps = 3
+    s, o = run_pair(w, w.params.gks_steps + 4, name=f"wave-only-{case}")
+    assert s.step(0)["n_alive"] > 0
