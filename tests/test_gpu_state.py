@@ -122,7 +122,8 @@ def test_import_refusals_leave_the_state():
     with pytest.raises(UgkwpError) as e:
         a.import_state(bad(cell=cells))
     assert e.value.status == E_ARG
-    big = {k: np.concatenate([v] * 3) for k, v in good["particles"].items()}
+    reps = 5000 // n + 1  # more particles than the capacity of 5000
+    big = {k: np.concatenate([v] * reps) for k, v in good["particles"].items()}
     big["cell"] = np.sort(big["cell"])
     st = dict(good)
     st["particles"] = big
