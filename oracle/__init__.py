@@ -46,9 +46,9 @@ def lib():
         L.orc_make_uid.argtypes = [C.c_int, i64, i64, i64]
         L.orc_moments.argtypes = [C.c_int, d, d, P(d)]
         L.orc_qcoef.argtypes = [d, d, P(d)]
-        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, C.c_int, P(d)]
-        L.orc_flux_specular.argtypes = [P(d), d, P(d), d, d, d, d, C.c_int, P(d)]
-        L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), C.c_int, P(d)]
+        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux_specular.argtypes = [P(d), d, P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), C.c_int, C.c_int, P(d)]
         L.orc_create.restype = vp
         L.orc_create.argtypes = [i64, P(d), i64, P(C.c_uint8), P(i64), P(i64), i64, P(i64), P(i32), i32,
                                  P(i32), P(d), P(d), P(d), P(d), d, d, d, d, i32, i32, i32, u64, i64, P(i32)]
@@ -63,21 +63,23 @@ def lib():
         L.orc_set_state.restype = C.c_int
         L.orc_set_state.argtypes = [vp, P(d)]
         L.orc_get_state.argtypes = [vp, P(d), P(d), P(i64)]
-        L.orc_get_particles.argtypes = [vp, P(d), P(d), P(d), P(i64), P(u64)]
+        L.orc_get_particles.argtypes = [vp, P(d), P(d), P(d), P(i64), P(u64), P(d)]
         L.orc_last_terms.argtypes = [vp, P(d), P(d), P(d)]
         L.orc_import_state.restype = C.c_int
-        L.orc_import_state.argtypes = [vp, P(d), P(d), i64, P(d), P(d), P(d), P(i64), P(u64), i64, d]
+        L.orc_import_state.argtypes = [vp, P(d), P(d), i64, P(d), P(d), P(d), P(i64), P(u64), P(d), i64, d]
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [vp]
         L.orc_sample_only.restype = C.c_int
         L.orc_sample_only.argtypes = [vp, P(d)]
         L.orc_flux_speed.restype = d
         L.orc_flux_speed.argtypes = [d, d]
-        L.orc_slope.argtypes = [d, d, d, d, P(d), P(d)]
-        L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, P(d)]
-        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, P(d)]
-        L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, C.c_int, P(d)]
-        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, C.c_int, P(d)]
+        L.orc_slope.argtypes = [d, d, d, d, C.c_int, P(d), P(d)]
+        L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, C.c_int, P(d)]
+        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_set_internal_dof.restype = C.c_int
+        L.orc_set_internal_dof.argtypes = [vp, C.c_int]
         L.orc_set_gks_steps.restype = C.c_int
         L.orc_set_gks_steps.argtypes = [vp, i64]
         L.orc_set_recon.restype = C.c_int
@@ -90,7 +92,7 @@ def lib():
         L.orc_average.restype = C.c_int
         L.orc_average.argtypes = [vp, P(d), P(d), P(i64)]
         L.orc_track.restype = C.c_int
-        L.orc_track.argtypes = [vp, P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
+        L.orc_track.argtypes = [vp, P(d), P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
         _lib = L
     return _lib
 
@@ -134,74 +136,86 @@ def _v(a, n):
     return a
 
 
-def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2, gks=False):
-    """gks: the wave-only flux of the start phase (the waves carry all of the hydro part)."""
+def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2, gks=False, K=0):
+    """gks: the wave-only flux of the start phase (the waves carry all of the hydro part);
+    K: internal degrees of freedom of the gas."""
     F = np.zeros(5)
     Wl, Wr, n = _v(Wl, 5), _v(Wr, 5), _v(n, 3)
     lib().orc_flux_interior(_p(Wl, C.c_double), _p(Wr, C.c_double), rhohl, rhohr, _p(n, C.c_double), dt,
-                            mu_ref, omega, c2, int(bool(gks)), _p(F, C.c_double))
+                            mu_ref, omega, c2, int(bool(gks)), int(K), _p(F, C.c_double))
     return F
 
 
-def slope(un, v, w, lam, b):
-    """Micro slope a with <(a . psi) psi> = b over the unit Maxwellian (face frame)."""
+def slope(un, v, w, lam, b, K=0):
+    """Micro slope a with <(a . psi) psi> = b over the unit Maxwellian (face frame), K internal
+    degrees of freedom."""
     b = _v(b, 5)
     a = np.zeros(5)
-    lib().orc_slope(float(un), float(v), float(w), float(lam), _p(b, C.c_double), _p(a, C.c_double))
+    lib().orc_slope(float(un), float(v), float(w), float(lam), int(K), _p(b, C.c_double), _p(a, C.c_double))
     return a
 
 
-def mvec(p, q, r, a, rng, un, v, w, lam):
-    """<u^p v^q w^r (a . psi) psi> (a None: without the a . psi factor) over the unit Maxwellian."""
+def mvec(p, q, r, a, rng, un, v, w, lam, K=0):
+    """<u^p v^q w^r (a . psi) psi> (a None: without the a . psi factor) over the unit Maxwellian
+    with K internal degrees of freedom."""
     out = np.zeros(5)
     ap = None if a is None else _v(a, 5)
     lib().orc_mvec(int(p), int(q), int(r), None if ap is None else _p(ap, C.c_double), int(rng), float(un),
-                   float(v), float(w), float(lam), _p(out, C.c_double))
+                   float(v), float(w), float(lam), int(K), _p(out, C.c_double))
     return out
 
 
-def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2, gks=False):
+def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2, gks=False, K=0):
     """Second-order interior flux; G[k][d] = dW_k/dx_d ([5][3])."""
     F = np.zeros(5)
     args = [_v(Wl, 5), _v(Wr, 5), _v(Whl, 5), _v(Whr, 5), _v(Gl, 15), _v(Gr, 15), _v(Ghl, 15), _v(Ghr, 15)]
     n = _v(n, 3)
     lib().orc_flux2_interior(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             int(bool(gks)), _p(F, C.c_double))
+                             int(bool(gks)), int(K), _p(F, C.c_double))
     return F
 
 
-def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2, gks=False):
+def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2, gks=False, K=0):
     F = np.zeros(5)
     args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15)]
     n = _v(n, 3)
     lib().orc_flux2_specular(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             int(bool(gks)), _p(F, C.c_double))
+                             int(bool(gks)), int(K), _p(F, C.c_double))
     return F
 
 
-def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2, gks=False):
+def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2, gks=False, K=0):
     F = np.zeros(5)
     args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15), _v(Winf, 5)]
     n = _v(n, 3)
     lib().orc_flux2_farfield(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             int(bool(gks)), _p(F, C.c_double))
+                             int(bool(gks)), int(K), _p(F, C.c_double))
     return F
 
 
-def flux_specular(W, rhoh, n, dt, mu_ref, omega, c2, gks=False):
+def flux_specular(W, rhoh, n, dt, mu_ref, omega, c2, gks=False, K=0):
     F = np.zeros(5)
     W, n = _v(W, 5), _v(n, 3)
     lib().orc_flux_specular(_p(W, C.c_double), rhoh, _p(n, C.c_double), dt, mu_ref, omega, c2, int(bool(gks)),
-                            _p(F, C.c_double))
+                            int(K), _p(F, C.c_double))
     return F
 
 
-def flux_diffuse(W, rhoh, tau_c, n, dt, Tw, Uw, gks=False):
+def flux_diffuse(W, rhoh, tau_c, n, dt, Tw, Uw, gks=False, K=0):
     F = np.zeros(5)
     W, n, Uw = _v(W, 5), _v(n, 3), _v(Uw, 3)
     lib().orc_flux_diffuse(_p(W, C.c_double), rhoh, tau_c, _p(n, C.c_double), dt, Tw, _p(Uw, C.c_double),
-                           int(bool(gks)), _p(F, C.c_double))
+                           int(bool(gks)), int(K), _p(F, C.c_double))
     return F
+
+
+def internal_dof(gamma):
+    """K of gamma = (K + 5) / (K + 3): an integer from 0 (monatomic, 5/3) to 8."""
+    K = 2.0 / (gamma - 1.0) - 3.0
+    Ki = int(round(K))
+    if abs(K - Ki) > 1e-9 or not 0 <= Ki <= 8:
+        raise OracleError(f"gamma = {gamma}: needs gamma = (K + 5)/(K + 3) with an integer 0 <= K <= 8")
+    return Ki
 
 
 class OracleError(RuntimeError):
@@ -226,8 +240,7 @@ class Oracle:
                       np.ascontiguousarray(mesh.bface_bc, dtype=np.int32), t, tw, uw, wi, sh]
         k = self._keep
         st = C.c_int32(0)
-        if abs(params.gamma - 5.0 / 3.0) > 1e-12:
-            raise OracleError("the oracle implements the monatomic gas (gamma = 5/3) only")
+        K = internal_dof(params.gamma)
         h = L.orc_create(mesh.n_nodes, _p(k[0], C.c_double), mesh.n_cells, _p(k[1], C.c_uint8),
                          _p(k[2], C.c_int64), _p(k[3], C.c_int64), k[4].shape[0], _p(k[4], C.c_int64),
                          _p(k[5], C.c_int32), len(mesh.bcs), _p(t, C.c_int32), _p(tw, C.c_double),
@@ -244,6 +257,8 @@ class Oracle:
             if rc != OK:
                 raise OracleError(f"orc_set_recon failed with status {rc}")
         rc = L.orc_set_sampling(self.h, int(getattr(params, "sampling", 0)))
+        if rc == OK:
+            rc = L.orc_set_internal_dof(self.h, K)
         if rc == OK:
             rc = L.orc_set_gks_steps(self.h, int(getattr(params, "gks_steps", 0)))
         if rc != OK:
@@ -272,11 +287,12 @@ class Oracle:
         m = np.ascontiguousarray(p["m"], dtype=np.float64).reshape(n)
         c = np.ascontiguousarray(p["cell"], dtype=np.int64).reshape(n)
         uid = np.ascontiguousarray(p["uid"], dtype=np.uint64).reshape(n)
+        e = np.ascontiguousarray(p["e"] if p.get("e") is not None else np.zeros(n), dtype=np.float64).reshape(n)
         step = int(np.asarray(state["step"]).reshape(-1)[instance])
         t = float(np.asarray(state["t"]).reshape(-1)[instance])
         rc = lib().orc_import_state(self.h, _p(W, C.c_double), _p(P, C.c_double), n, _p(x, C.c_double),
                                     _p(u, C.c_double), _p(m, C.c_double), _p(c, C.c_int64), _p(uid, C.c_uint64),
-                                    step, t)
+                                    _p(e, C.c_double), step, t)
         if rc != OK:
             raise OracleError(f"orc_import_state failed with status {rc}")
 
@@ -344,10 +360,10 @@ class Oracle:
     def particles(self):
         n = int(lib().orc_n_particles(self.h))
         x = np.zeros((n, 3)); u = np.zeros((n, 3)); m = np.zeros(n)
-        c = np.zeros(n, dtype=np.int64); uid = np.zeros(n, dtype=np.uint64)
+        c = np.zeros(n, dtype=np.int64); uid = np.zeros(n, dtype=np.uint64); e = np.zeros(n)
         lib().orc_get_particles(self.h, _p(x, C.c_double), _p(u, C.c_double), _p(m, C.c_double),
-                                _p(c, C.c_int64), _p(uid, C.c_uint64))
-        return dict(x=x, u=u, m=m, cell=c, uid=uid)
+                                _p(c, C.c_int64), _p(uid, C.c_uint64), _p(e, C.c_double))
+        return dict(x=x, u=u, m=m, cell=c, uid=uid, e=e)
 
     def gradients(self):
         """Limited gradients of W and of the hydro state ([nc][5][3] each) and the hydro state."""
@@ -365,10 +381,13 @@ class Oracle:
             raise OracleError(f"orc_sample_only failed with status {rc}")
         return dt.value
 
-    def track(self, x, u, cell, ts, uid=0, step=0):
-        """Free transport of one particle (for tracking pins); returns (rc, x, u, cell, crossings)."""
+    def track(self, x, u, cell, ts, uid=0, step=0, e=0.0, with_e=False):
+        """Free transport of one particle (for tracking pins); returns (rc, x, u, cell, crossings),
+        and its internal energy variable after the flight with with_e."""
         x = np.array(x, dtype=np.float64); u = np.array(u, dtype=np.float64)
-        c = C.c_int64(cell); nc = C.c_int64(0); nw = C.c_int64(0)
-        rc = lib().orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(c), ts, -1, uid, step,
-                             C.byref(nc), C.byref(nw))
+        c = C.c_int64(cell); nc = C.c_int64(0); nw = C.c_int64(0); ee = C.c_double(e)
+        rc = lib().orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(ee), C.byref(c), ts, -1, uid,
+                             step, C.byref(nc), C.byref(nw))
+        if with_e:
+            return rc, x, u, c.value, nc.value, ee.value
         return rc, x, u, c.value, nc.value

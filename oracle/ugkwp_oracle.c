@@ -47,7 +47,8 @@ enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2, BC_PERIODIC = 3 };
 
 /* relative floor of the hydro density rho^h = rho - rho^p (see phase_cells) */
 #define RHOH_EPS 1e-12
-enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5 };
+enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5, TAG_INT = 6, TAG_WALLINT = 7 };
+#define KMAX 8 /* internal degrees of freedom supported (gamma = (K + 5) / (K + 3)) */
 
 /* ------------------------------------------------------------------------------------ */
 /* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter based.       */
@@ -131,10 +132,17 @@ static void face_frame(const double n[3], double t1[3], double t2[3])
     t2[2] = n[0] * t1[1] - n[1] * t1[0];
 }
 
-/* Primitive state in a face frame. */
-typedef struct { double rho, un, v, w, lam, T; } prim_t;
+/* Primitive state in a face frame; K internal degrees of freedom (Sec. 2.1: the Maxwellian
+ * carries exp(-lambda xi^2) over K components of xi, and rho E = rho |U|^2 / 2 + (3 + K) rho T / 2). */
+typedef struct { double rho, un, v, w, lam, T; int K; } prim_t;
 
-static prim_t to_frame(const double W[5], const double n[3], const double t1[3], const double t2[3])
+/* temperature of a conservative state (R = 1, N = 3 + K) */
+static double temp_k(const double W[5], int K)
+{
+    return (2.0 / (3.0 + K)) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+}
+
+static prim_t to_frame(const double W[5], const double n[3], const double t1[3], const double t2[3], int K)
 {
     prim_t p;
     p.rho = W[0];
@@ -142,16 +150,18 @@ static prim_t to_frame(const double W[5], const double n[3], const double t1[3],
     p.un = U * n[0] + V * n[1] + Wz * n[2];
     p.v = U * t1[0] + V * t1[1] + Wz * t1[2];
     p.w = U * t2[0] + V * t2[1] + Wz * t2[2];
-    p.T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+    p.T = temp_k(W, K);
     p.lam = 1.0 / (2.0 * p.T);
+    p.K = K;
     return p;
 }
 
 /* <psi> and <u_n psi> of a unit-density Maxwellian in the face frame, with the normal
- * moments m[] taken over the chosen range of u_n; psi = (1, u_n, v, w, (u_n^2+v^2+w^2)/2). */
+ * moments m[] taken over the chosen range of u_n; psi = (1, u_n, v, w, (u_n^2+v^2+w^2+xi^2)/2),
+ * <xi^2> = K / (2 lambda). */
 static void psi_moments(const prim_t *p, const double m[NMOM], double H[5], double G[5])
 {
-    double tr = p->v * p->v + p->w * p->w + 1.0 / p->lam; /* <v^2 + w^2> */
+    double tr = p->v * p->v + p->w * p->w + 1.0 / p->lam + p->K / (2.0 * p->lam); /* <v^2 + w^2 + xi^2> */
     H[0] = m[0];
     H[1] = m[1];
     H[2] = m[0] * p->v;
@@ -252,7 +262,8 @@ static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rho
     z.un = W0[1] / W0[0];
     z.v = W0[2] / W0[0];
     z.w = W0[3] / W0[0];
-    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.K = l->K;
+    z.T = temp_k(W0, z.K);
     z.lam = 1.0 / (2.0 * z.T);
     double pl = l->rho * l->T, pr = r->rho * r->T;
     double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
@@ -267,12 +278,12 @@ static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rho
 }
 
 void orc_flux_interior(const double Wl[5], const double Wr[5], double rhohl, double rhohr,
-                       const double n[3], double dt, double mu_ref, double omega, double c2, int gks,
+                       const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K,
                        double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
-    prim_t l = to_frame(Wl, n, t1, t2), r = to_frame(Wr, n, t1, t2);
+    prim_t l = to_frame(Wl, n, t1, t2, K), r = to_frame(Wr, n, t1, t2, K);
     flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -280,11 +291,11 @@ void orc_flux_interior(const double Wl[5], const double Wr[5], double rhohl, dou
 /* Specular (symmetry) wall: interior flux against the mirror state (u_n -> -u_n), then only
  * the normal-momentum component is kept; n points out of the domain. */
 void orc_flux_specular(const double W[5], double rhoh, const double n[3], double dt,
-                       double mu_ref, double omega, double c2, int gks, double F[5])
+                       double mu_ref, double omega, double c2, int gks, int K, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
-    prim_t l = to_frame(W, n, t1, t2);
+    prim_t l = to_frame(W, n, t1, t2, K);
     prim_t g = l;
     g.un = -l.un;
     flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, gks, Ff);
@@ -296,11 +307,11 @@ void orc_flux_specular(const double W[5], double rhoh, const double n[3], double
  * (u_n > 0): q1 g + (q4 - dt e) g^h at the cell state with the cell's tau; the wall emits
  * rho_w M(T_w, U_w) over u_n < 0 for the whole step, rho_w fixed by zero net mass flux. */
 void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double n[3], double dt,
-                      double Tw, const double Uw[3], int gks, double F[5])
+                      double Tw, const double Uw[3], int gks, int K, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
-    prim_t l = to_frame(W, n, t1, t2);
+    prim_t l = to_frame(W, n, t1, t2, K);
     double q[5];
     orc_qcoef(dt, tau_c, q);
     if (gks) wave_only_coef(dt, tau_c, q);
@@ -316,6 +327,7 @@ void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double
     w.w = Uw[0] * t2[0] + Uw[1] * t2[1] + Uw[2] * t2[2];
     w.T = Tw;
     w.lam = 1.0 / (2.0 * Tw);
+    w.K = K;
     double mw[NMOM], Hw[5], Gw[5];
     orc_moments(-1, w.un, w.lam, mw);
     psi_moments(&w, mw, Hw, Gw);
@@ -329,43 +341,46 @@ void orc_flux_diffuse(const double W[5], double rhoh, double tau_c, const double
 /* Second order (Sec. 2.2: the initial distribution with slopes, the equilibrium state    */
 /* with its slopes and time derivative; Sec. 2.4 for the wave part).                       */
 /*                                                                                          */
-/* Moments of polynomials in (u, v, w) (face frame) over a Maxwellian: a polynomial of     */
-/* degree < 7 in each variable as dense coefficients, multiplied out and integrated term   */
-/* by term with <u^a v^b w^c> = <u^a>_range <v^b> <w^c>.                                    */
+/* Moments of polynomials in (u, v, w, z = xi^2) (face frame) over a Maxwellian: degree < 7 */
+/* in each velocity and < 3 in z, as dense coefficients, multiplied out and integrated term  */
+/* by term with <u^a v^b w^c z^d> = <u^a>_range <v^b> <w^c> <z^d>, where for K internal      */
+/* components <z> = K/(2 lambda) and <z^2> = K (K + 2) / (4 lambda^2).                      */
 /* ------------------------------------------------------------------------------------ */
 #define PD 7
-typedef struct { double c[PD][PD][PD]; } poly_t;
+#define PZ 3
+typedef struct { double c[PD][PD][PD][PZ]; } poly_t;
 
 static void poly_clear(poly_t *p) { memset(p, 0, sizeof(*p)); }
 
 static void poly_mono(int a, int b, int c, poly_t *p)
 {
     poly_clear(p);
-    p->c[a][b][c] = 1.0;
+    p->c[a][b][c][0] = 1.0;
 }
 
-/* psi_k: 1, u, v, w, (u^2 + v^2 + w^2)/2 */
+/* psi_k: 1, u, v, w, (u^2 + v^2 + w^2 + xi^2)/2 */
 static void poly_psi(int k, poly_t *p)
 {
     poly_clear(p);
-    if (k == 0) p->c[0][0][0] = 1.0;
-    else if (k == 1) p->c[1][0][0] = 1.0;
-    else if (k == 2) p->c[0][1][0] = 1.0;
-    else if (k == 3) p->c[0][0][1] = 1.0;
-    else { p->c[2][0][0] = 0.5; p->c[0][2][0] = 0.5; p->c[0][0][2] = 0.5; }
+    if (k == 0) p->c[0][0][0][0] = 1.0;
+    else if (k == 1) p->c[1][0][0][0] = 1.0;
+    else if (k == 2) p->c[0][1][0][0] = 1.0;
+    else if (k == 3) p->c[0][0][1][0] = 1.0;
+    else { p->c[2][0][0][0] = 0.5; p->c[0][2][0][0] = 0.5; p->c[0][0][2][0] = 0.5; p->c[0][0][0][1] = 0.5; }
 }
 
 /* a . psi */
 static void poly_apsi(const double a[5], poly_t *p)
 {
     poly_clear(p);
-    p->c[0][0][0] = a[0];
-    p->c[1][0][0] = a[1];
-    p->c[0][1][0] = a[2];
-    p->c[0][0][1] = a[3];
-    p->c[2][0][0] = 0.5 * a[4];
-    p->c[0][2][0] = 0.5 * a[4];
-    p->c[0][0][2] = 0.5 * a[4];
+    p->c[0][0][0][0] = a[0];
+    p->c[1][0][0][0] = a[1];
+    p->c[0][1][0][0] = a[2];
+    p->c[0][0][1][0] = a[3];
+    p->c[2][0][0][0] = 0.5 * a[4];
+    p->c[0][2][0][0] = 0.5 * a[4];
+    p->c[0][0][2][0] = 0.5 * a[4];
+    p->c[0][0][0][1] = 0.5 * a[4];
 }
 
 static int g_poly_overflow = 0;
@@ -375,33 +390,40 @@ static void poly_mul(const poly_t *x, const poly_t *y, poly_t *z)
     poly_clear(z);
     for (int i = 0; i < PD; ++i)
         for (int j = 0; j < PD; ++j)
-            for (int k = 0; k < PD; ++k) {
-                double a = x->c[i][j][k];
-                if (a == 0.0) continue;
-                for (int l = 0; l < PD; ++l)
-                    for (int m = 0; m < PD; ++m)
-                        for (int n = 0; n < PD; ++n) {
-                            double b = y->c[l][m][n];
-                            if (b == 0.0) continue;
-                            if (i + l >= PD || j + m >= PD || k + n >= PD) { g_poly_overflow = 1; continue; }
-                            z->c[i + l][j + m][k + n] += a * b;
-                        }
-            }
+            for (int k = 0; k < PD; ++k)
+                for (int q = 0; q < PZ; ++q) {
+                    double a = x->c[i][j][k][q];
+                    if (a == 0.0) continue;
+                    for (int l = 0; l < PD; ++l)
+                        for (int m = 0; m < PD; ++m)
+                            for (int n = 0; n < PD; ++n)
+                                for (int r = 0; r < PZ; ++r) {
+                                    double b = y->c[l][m][n][r];
+                                    if (b == 0.0) continue;
+                                    if (i + l >= PD || j + m >= PD || k + n >= PD || q + r >= PZ) {
+                                        g_poly_overflow = 1;
+                                        continue;
+                                    }
+                                    z->c[i + l][j + m][k + n][q + r] += a * b;
+                                }
+                }
 }
 
 /* <p> over a unit-density Maxwellian g in the face frame, u over range (0 all, +1 u > 0,
- * -1 u < 0), v and w over the full line */
+ * -1 u < 0), v, w and xi over the full space */
 static double poly_moment(const poly_t *p, int range, const prim_t *g)
 {
     double mu[NMOM], mv[NMOM], mw[NMOM];
     orc_moments(range, g->un, g->lam, mu);
     orc_moments(0, g->v, g->lam, mv);
     orc_moments(0, g->w, g->lam, mw);
+    const double mz[PZ] = {1.0, g->K / (2.0 * g->lam), g->K * (g->K + 2.0) / (4.0 * g->lam * g->lam)};
     double s = 0.0;
     for (int i = 0; i < PD; ++i)
         for (int j = 0; j < PD; ++j)
             for (int k = 0; k < PD; ++k)
-                if (p->c[i][j][k] != 0.0) s += p->c[i][j][k] * mu[i] * mv[j] * mw[k];
+                for (int q = 0; q < PZ; ++q)
+                    if (p->c[i][j][k][q] != 0.0) s += p->c[i][j][k][q] * mu[i] * mv[j] * mw[k] * mz[q];
     return s;
 }
 
@@ -423,38 +445,39 @@ static void mvec(const poly_t *pre, const double *a, int range, const prim_t *g,
 }
 
 /* Micro slope from a macro derivative (Sec. 2.2): a with < (a . psi) psi > = b over the full
- * Maxwellian g (b = derivative of W divided by the density).  With c = u - U, the moments
- * <c^2> = T = 1/(2 lambda) per direction give, for K = 0:
- *   R = 2 b5 - (|U|^2 + 3/(2 lambda)) b1,  R_i = b_{i+1} - U_i b1 (i = 1..3)
- *   a5 = (4 lambda^2 / 3) (R - 2 sum_i U_i R_i),  a_{i+1} = 2 lambda R_i - U_i a5,
- *   a1 = b1 - sum_i U_i a_{i+1} - a5 (|U|^2 + 3/(2 lambda)) / 2. */
-void orc_slope(double un, double v, double w, double lam, const double b[5], double a[5])
+ * Maxwellian g (b = derivative of W divided by the density), N = 3 + K.  With c = u - U, the
+ * moments <c^2> = T = 1/(2 lambda) per direction and <xi^2> = K T give
+ *   R = 2 b5 - (|U|^2 + N/(2 lambda)) b1,  R_i = b_{i+1} - U_i b1 (i = 1..3)
+ *   a5 = (4 lambda^2 / N) (R - 2 sum_i U_i R_i),  a_{i+1} = 2 lambda R_i - U_i a5,
+ *   a1 = b1 - sum_i U_i a_{i+1} - a5 (|U|^2 + N/(2 lambda)) / 2. */
+void orc_slope(double un, double v, double w, double lam, int K, const double b[5], double a[5])
 {
     double U[3] = {un, v, w};
+    double N = 3.0 + K;
     double q2 = un * un + v * v + w * w;
-    double R = 2.0 * b[4] - (q2 + 3.0 / (2.0 * lam)) * b[0];
+    double R = 2.0 * b[4] - (q2 + N / (2.0 * lam)) * b[0];
     double Ri[3];
     for (int i = 0; i < 3; ++i) Ri[i] = b[1 + i] - U[i] * b[0];
-    a[4] = (4.0 * lam * lam / 3.0) * (R - 2.0 * (U[0] * Ri[0] + U[1] * Ri[1] + U[2] * Ri[2]));
+    a[4] = (4.0 * lam * lam / N) * (R - 2.0 * (U[0] * Ri[0] + U[1] * Ri[1] + U[2] * Ri[2]));
     for (int i = 0; i < 3; ++i) a[1 + i] = 2.0 * lam * Ri[i] - U[i] * a[4];
-    a[0] = b[0] - (U[0] * a[1] + U[1] * a[2] + U[2] * a[3]) - 0.5 * a[4] * (q2 + 3.0 / (2.0 * lam));
+    a[0] = b[0] - (U[0] * a[1] + U[1] * a[2] + U[2] * a[3]) - 0.5 * a[4] * (q2 + N / (2.0 * lam));
 }
 
 static void slope_of(const prim_t *g, const double dW[5], double a[5])
 {
     double b[5];
     for (int k = 0; k < 5; ++k) b[k] = dW[k] / g->rho;
-    orc_slope(g->un, g->v, g->w, g->lam, b, a);
+    orc_slope(g->un, g->v, g->w, g->lam, g->K, b, a);
 }
 
 /* test hook: <u^p v^q w^r (a . psi) psi> over a Maxwellian in the frame */
-void orc_mvec(int p, int q, int r, const double *a, int range, double un, double v, double w, double lam,
+void orc_mvec(int p, int q, int r, const double *a, int range, double un, double v, double w, double lam, int K,
               double out[5])
 {
     poly_t pre;
     poly_mono(p, q, r, &pre);
     prim_t g;
-    g.rho = 1.0; g.un = un; g.v = v; g.w = w; g.lam = lam; g.T = 1.0 / (2.0 * lam);
+    g.rho = 1.0; g.un = un; g.v = v; g.w = w; g.lam = lam; g.T = 1.0 / (2.0 * lam); g.K = K;
     mvec(&pre, a, range, &g, out);
 }
 
@@ -496,7 +519,8 @@ static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_re
     z.un = W0[1] / W0[0];
     z.v = W0[2] / W0[0];
     z.w = W0[3] / W0[0];
-    z.T = (2.0 / 3.0) * (W0[4] - 0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.K = L->g.K;
+    z.T = temp_k(W0, z.K);
     z.lam = 1.0 / (2.0 * z.T);
     double abar[3][5];
     for (int d = 0; d < 3; ++d) {
@@ -513,7 +537,7 @@ static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_re
     mvec(&pv, abar[1], 0, &z, t1);
     mvec(&pw, abar[2], 0, &z, t2);
     for (int k = 0; k < 5; ++k) bt[k] = -(t0[k] + t1[k] + t2[k]);
-    orc_slope(z.un, z.v, z.w, z.lam, bt, At);
+    orc_slope(z.un, z.v, z.w, z.lam, z.K, bt, At);
     double pl = L->g.rho * L->g.T, pr = R->g.rho * R->g.T;
     double tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
     double q[5];
@@ -560,15 +584,16 @@ static void frame_derivs(const double G[15], const double n[3], const double t1[
 }
 
 static void make_side(const double W[5], const double G[15], const double Wh[5], const double Gh[15],
-                      const double n[3], const double t1[3], const double t2[3], side_t *s)
+                      const double n[3], const double t1[3], const double t2[3], int K, side_t *s)
 {
-    s->g = to_frame(W, n, t1, t2);
+    s->g = to_frame(W, n, t1, t2, K);
     frame_derivs(G, n, t1, t2, s->dW);
     if (Wh[0] > 0.0) {
-        s->h = to_frame(Wh, n, t1, t2);
+        s->h = to_frame(Wh, n, t1, t2, K);
         frame_derivs(Gh, n, t1, t2, s->dWh);
     } else {
         memset(&s->h, 0, sizeof(s->h));
+        s->h.K = K;
         memset(s->dWh, 0, sizeof(s->dWh));
     }
 }
@@ -577,13 +602,13 @@ static void make_side(const double W[5], const double G[15], const double Wh[5],
  * states Whl, Whr (conservative), gradients G[k][d] = dW_k/dx_d of each. */
 void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl[5], const double Whr[5],
                         const double Gl[15], const double Gr[15], const double Ghl[15], const double Ghr[15],
-                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, double F[5])
+                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     side_t L, R;
-    make_side(Wl, Gl, Whl, Ghl, n, t1, t2, &L);
-    make_side(Wr, Gr, Whr, Ghr, n, t1, t2, &R);
+    make_side(Wl, Gl, Whl, Ghl, n, t1, t2, K, &L);
+    make_side(Wr, Gr, Whr, Ghr, n, t1, t2, K, &R);
     flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -592,12 +617,12 @@ void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl
  * momentum and normal derivatives flip sign, twice for the normal momentum's normal
  * derivative), then only the normal-momentum component is kept. */
 void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
-                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, double F[5])
+                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     side_t L, R;
-    make_side(W, G, Wh, Gh, n, t1, t2, &L);
+    make_side(W, G, Wh, Gh, n, t1, t2, K, &L);
     R = L;
     R.g.un = -L.g.un;
     R.h.un = -L.h.un;
@@ -617,14 +642,14 @@ void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15
 /* Far field at second order: the free stream with zero gradients as the right side. */
 void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
                         const double Winf[5], const double n[3], double dt, double mu_ref, double omega,
-                        double c2, int gks, double F[5])
+                        double c2, int gks, int K, double F[5])
 {
     double t1[3], t2[3], Ff[5], zero[15];
     memset(zero, 0, sizeof(zero));
     face_frame(n, t1, t2);
     side_t L, R;
-    make_side(W, G, Wh, Gh, n, t1, t2, &L);
-    make_side(Winf, zero, Winf, zero, n, t1, t2, &R);
+    make_side(W, G, Wh, Gh, n, t1, t2, K, &L);
+    make_side(Winf, zero, Winf, zero, n, t1, t2, K, &R);
     flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -670,6 +695,7 @@ typedef struct oracle {
     double *fx;          /* [nf][3] face centre (the owner's) */
     int recon;           /* 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan */
     double venkat_k;     /* Venkatakrishnan constant K in eps^2 = (K h)^3 */
+    int K;               /* internal degrees of freedom (Sec. 2.1), gamma = (K + 5)/(K + 3) */
     int64_t gks_steps;   /* the steps n < gks_steps (counted from orc_set_state) are wave-only:
                             no particle is sampled or enters, the waves carry all of W^h */
     int sampling;        /* hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b);
@@ -686,6 +712,7 @@ typedef struct oracle {
     /* particles */
     int64_t np, cap;
     double *px, *pu, *pm;
+    double *pe;          /* internal energy variable xi^2 of each particle (K > 0), phi_4 = m (|u|^2 + e) / 2 */
     int64_t *pc;
     uint64_t *pid;
     /* time averaging (Sec. 2.4(c)): steps n > avg_from are averaged (avg_from < 0: off) */
@@ -1057,7 +1084,7 @@ void orc_destroy(oracle_t *o)
     free(o->lfx); free(o->fx);
     free(o->bc); free(o->W); free(o->P); free(o->avgA); free(o->nleft);
     free(o->tflux); free(o->tE); free(o->tS);
-    free(o->px); free(o->pu); free(o->pm); free(o->pc); free(o->pid);
+    free(o->px); free(o->pu); free(o->pm); free(o->pe); free(o->pc); free(o->pid);
     free(o);
 }
 
@@ -1086,6 +1113,17 @@ int orc_set_gks_steps(oracle_t *o, int64_t gks_steps)
 {
     if (gks_steps < 0) return ORC_E_ARG;
     o->gks_steps = gks_steps;
+    return ORC_OK;
+}
+
+/* Internal degrees of freedom (Sec. 2.1): K components of xi in the Maxwellian, so that
+   rho E = rho |U|^2 / 2 + (3 + K) rho T / 2 and gamma = (K + 5)/(K + 3) (K = 2: a diatomic gas,
+   gamma = 7/5).  A particle carries its internal energy variable e = |xi|^2, sampled like xi
+   (Sec. 2.3: sampled from the temperature and K, as in DSMC); 0 <= K <= KMAX. */
+int orc_set_internal_dof(oracle_t *o, int K)
+{
+    if (K < 0 || K > KMAX) return ORC_E_ARG;
+    o->K = K;
     return ORC_OK;
 }
 
@@ -1132,7 +1170,8 @@ int orc_set_state(oracle_t *o, const double *W)
    particles of the next step (any order); N_left of a cell is its count.  The averaging sums
    are cleared and its setting kept. */
 int orc_import_state(oracle_t *o, const double *W, const double *P, int64_t n, const double *x, const double *u,
-                     const double *m, const int64_t *cell, const uint64_t *uid, int64_t step, double t)
+                     const double *m, const int64_t *cell, const uint64_t *uid, const double *e, int64_t step,
+                     double t)
 {
     if (n < 0 || step < 0) return ORC_E_ARG;
     for (int64_t i = 0; i < n; ++i)
@@ -1144,6 +1183,7 @@ int orc_import_state(oracle_t *o, const double *W, const double *P, int64_t n, c
     for (int64_t i = 0; i < n; ++i) {
         for (int d = 0; d < 3; ++d) { o->px[3 * i + d] = x[3 * i + d]; o->pu[3 * i + d] = u[3 * i + d]; }
         o->pm[i] = m[i];
+        o->pe[i] = e ? e[i] : 0.0;
         o->pc[i] = cell[i];
         o->pid[i] = uid[i];
         o->nleft[cell[i]] += 1;
@@ -1198,11 +1238,12 @@ void orc_last_terms(const oracle_t *o, double *flux, double *E, double *S)
     memcpy(S, o->tS, sizeof(double) * 5 * o->nc);
 }
 
-void orc_get_particles(const oracle_t *o, double *x, double *u, double *m, int64_t *cell, uint64_t *uid)
+void orc_get_particles(const oracle_t *o, double *x, double *u, double *m, int64_t *cell, uint64_t *uid, double *e)
 {
     memcpy(x, o->px, sizeof(double) * 3 * o->np);
     memcpy(u, o->pu, sizeof(double) * 3 * o->np);
     memcpy(m, o->pm, sizeof(double) * o->np);
+    if (e) memcpy(e, o->pe, sizeof(double) * o->np);
     memcpy(cell, o->pc, sizeof(int64_t) * o->np);
     memcpy(uid, o->pid, sizeof(uint64_t) * o->np);
 }
@@ -1218,23 +1259,44 @@ static int reserve(oracle_t *o, int64_t n)
     if (pu) o->pu = pu;
     double *pm = (double *)realloc(o->pm, sizeof(double) * cap);
     if (pm) o->pm = pm;
+    double *pe = (double *)realloc(o->pe, sizeof(double) * cap);
+    if (pe) o->pe = pe;
     int64_t *pc = (int64_t *)realloc(o->pc, sizeof(int64_t) * cap);
     if (pc) o->pc = pc;
     uint64_t *pid = (uint64_t *)realloc(o->pid, sizeof(uint64_t) * cap);
     if (pid) o->pid = pid;
-    if (!px || !pu || !pm || !pc || !pid) return -1;
+    if (!px || !pu || !pm || !pe || !pc || !pid) return -1;
     o->cap = cap;
     return 0;
 }
 
-/* phi = m (1, u, |u|^2 / 2): mass, momentum and energy carried by a particle (K = 0). */
-static void add_phi(double S[5], double m, const double u[3])
+/* phi = m (1, u, (|u|^2 + e) / 2): mass, momentum and energy carried by a particle (Sec. 2.3),
+   e its internal energy variable (0 for K = 0). */
+static void add_phi(double S[5], double m, const double u[3], double e)
 {
     S[0] += m;
     S[1] += m * u[0];
     S[2] += m * u[1];
     S[3] += m * u[2];
-    S[4] += m * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+    S[4] += m * (0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + e));
+}
+
+/* e = T |X|^2 with X the first K of standard normals drawn by Box-Muller from the draws
+   (seed, uid, step, tag, sub0 + j, inst), j = 0, 1: the internal energy variable of a particle
+   in equilibrium at temperature T (a chi-squared law with K degrees of freedom, times T) */
+static double internal_energy(uint64_t seed, uint64_t uid, int64_t step, int tag, uint32_t sub0, int64_t inst,
+                              int K, double T)
+{
+    double acc = 0.0;
+    for (int j = 0; 4 * j < K; ++j) {
+        double ev[4];
+        draw4(seed, uid, step, tag, sub0 + (uint32_t)j, inst, ev);
+        double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
+        double X[4] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3]),
+                       r2 * sin(2.0 * M_PI * ev[3])};
+        for (int i = 0; i < 4 && 4 * j + i < K; ++i) acc = acc + X[i] * X[i];
+    }
+    return T * acc;
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -1244,8 +1306,8 @@ static void add_phi(double S[5], double m, const double u[3])
 /* diffuse re-emits from the wall Maxwellian (flux-weighted normal component); far-field  */
 /* removes the particle.  Returns 0 (inside), 1 (escaped) or -1 (too many crossings).      */
 /* ------------------------------------------------------------------------------------ */
-int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double ts, int entry0, uint64_t uid,
-              int64_t step, int64_t *ncross, int64_t *nwall)
+int orc_track(const oracle_t *o, double x[3], double u[3], double *e, int64_t *cell, double ts, int entry0,
+              uint64_t uid, int64_t step, int64_t *ncross, int64_t *nwall)
 {
     int64_t c = *cell;
     int entry = entry0;
@@ -1302,6 +1364,9 @@ int orc_track(const oracle_t *o, double x[3], double u[3], int64_t *cell, double
             double r = sqrt(-2.0 * log(eta[1]));
             double X1 = r * cos(2.0 * M_PI * eta[2]), X2 = r * sin(2.0 * M_PI * eta[2]);
             for (int d = 0; d < 3; ++d) u[d] = b->Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+            /* full accommodation: the internal energy leaves in equilibrium at T_w too */
+            if (o->K > 0 && e)
+                *e = internal_energy(o->seed, uid, step, TAG_WALLINT, 2u * (uint32_t)(bounce - 1), o->inst, o->K, b->Tw);
             entry = bf;
         } else {
             *cell = c;
@@ -1343,7 +1408,7 @@ static int phase_cells(oracle_t *o, cellq_t *q)
         double rho = W[0];
         if (!(rho > 0.0) || !isfinite(rho)) return ORC_E_NONPHYS;
         double U = W[1] / rho, V = W[2] / rho, Z = W[3] / rho;
-        double T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / rho) / rho;
+        double T = temp_k(W, o->K);
         if (!(T > 0.0) || !isfinite(T)) return ORC_E_NONPHYS;
         q->U[3 * c] = U; q->U[3 * c + 1] = V; q->U[3 * c + 2] = Z;
         q->T[c] = T;
@@ -1366,11 +1431,8 @@ static int phase_cells(oracle_t *o, cellq_t *q)
     return ORC_OK;
 }
 
-/* Temperature of a conservative state (R = 1, K = 0). */
-static double temp_of(const double W[5])
-{
-    return (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
-}
+/* Temperature of a conservative state of this gas (R = 1). */
+static double temp_of(const oracle_t *o, const double W[5]) { return temp_k(W, o->K); }
 
 /* The state seen across local face lf of cell c for the gradient: the neighbour's (at its
  * centre) or, at a boundary, a ghost at the centre mirrored in the face plane: specular, the
@@ -1395,7 +1457,7 @@ static void across(const oracle_t *o, const cellq_t *q, int64_t c, int lf, doubl
         for (int k = 0; k < 5; ++k) { Wj[k] = b->Winf[k]; Whj[k] = b->Winf[k]; }
         return;
     }
-    double rho = Wc[0], U[3] = {Wc[1] / rho, Wc[2] / rho, Wc[3] / rho}, T = temp_of(Wc), Ug[3];
+    double rho = Wc[0], U[3] = {Wc[1] / rho, Wc[2] / rho, Wc[3] / rho}, T = temp_of(o, Wc), Ug[3];
     if (b->type == BC_SPECULAR) {
         double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
         for (int d = 0; d < 3; ++d) Ug[d] = U[d] - 2.0 * un * n[d];
@@ -1404,7 +1466,7 @@ static void across(const oracle_t *o, const cellq_t *q, int64_t c, int lf, doubl
     }
     Wj[0] = rho;
     for (int d = 0; d < 3; ++d) Wj[1 + d] = rho * Ug[d];
-    Wj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 1.5 * rho * T;
+    Wj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 0.5 * (3.0 + o->K) * rho * T;
     double f = q->rhoh[c] / rho;
     for (int k = 0; k < 5; ++k) Whj[k] = f * Wj[k];
 }
@@ -1492,9 +1554,9 @@ static void phase_grad(oracle_t *o, cellq_t *q)
             double Wf[10];
             for (int k = 0; k < 10; ++k)
                 Wf[k] = vc[k] + g[k][0] * (xf[0] - xc[0]) + g[k][1] * (xf[1] - xc[1]) + g[k][2] * (xf[2] - xc[2]);
-            if (!(Wf[0] > 0.0) || !(temp_of(Wf) > 0.0)) ok = 0;
+            if (!(Wf[0] > 0.0) || !(temp_of(o, Wf) > 0.0)) ok = 0;
             if (!(Wf[5] >= 0.0)) ok = 0;
-            if (Wf[5] > 0.0 && !(temp_of(Wf + 5) > 0.0)) ok = 0;
+            if (Wf[5] > 0.0 && !(temp_of(o, Wf + 5) > 0.0)) ok = 0;
         }
         for (int k = 0; k < 5; ++k)
             for (int a = 0; a < 3; ++a) {
@@ -1512,7 +1574,9 @@ static void extrap(const double *Vc, const double *g, const double *xc, const do
 }
 
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
- * ones.  Per cell: rho^hp = exp(-dt/tau) rho^h, m_ref = (rho^p + rho^hp) Omega / N_ref,
+ * ones.  With K > 0 each particle also gets its internal energy variable e = T |X'|^2 from
+ * K standard normals of its own (Sec. 2.3: sampled from the temperature and K).
+ * Per cell: rho^hp = exp(-dt/tau) rho^h, m_ref = (rho^p + rho^hp) Omega / N_ref,
  * N_sam = 2 ceil(rho^hp Omega / (2 m_ref)) raised to cover N_min - N_left (rounded up to
  * even), m_sam = rho^hp Omega / N_sam.  Pair j: X_j ~ N(0, I) by Box-Muller; the partners
  * get the velocities U + sqrt(T) X_j and U - sqrt(T) X_j (the pair of Sec. 2.4(b): the sample
@@ -1555,6 +1619,15 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
             }
             sT = sT * sqrt(3.0 * (double)(ns / 2) / sx2);
         }
+        double fint = 1.0;
+        if (o->sampling == 1 && o->K > 0) {
+            /* energy-exact internal energies: one factor K N_sam / sum_k |X_k|^2 on every particle's
+               e, so that the sample carries exactly rho^hp Omega K T / 2 of internal energy */
+            double se = 0.0;
+            for (int64_t k = 0; k < ns; ++k)
+                se += internal_energy(o->seed, orc_make_uid(0, o->step, c, k), o->step, TAG_INT, 0, o->inst, o->K, 1.0);
+            fint = (double)o->K * (double)ns / se;
+        }
         for (int64_t k = 0; k < ns; ++k) {
             int64_t i = o->np++;
             uint64_t uid = orc_make_uid(0, o->step, c, k);
@@ -1586,7 +1659,13 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
             o->pm[i] = msam;
             o->pc[i] = c;
             o->pid[i] = uid;
-            if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i);
+            double e = 0.0;
+            if (o->K > 0) {
+                e = internal_energy(o->seed, uid, o->step, TAG_INT, 0, o->inst, o->K, q->T[c]);
+                if (o->sampling == 1) e = e * fint;
+            }
+            o->pe[i] = e;
+            if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i, e);
         }
         *nsampled += ns;
     }
@@ -1636,7 +1715,7 @@ static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t
             const double *Wi = b->Winf;
             double rho = Wi[0];
             double Ui[3] = {Wi[1] / rho, Wi[2] / rho, Wi[3] / rho};
-            double T = (2.0 / 3.0) * (Wi[4] - 0.5 * (Wi[1] * Wi[1] + Wi[2] * Wi[2] + Wi[3] * Wi[3]) / rho) / rho;
+            double T = temp_k(Wi, o->K);
             double tau = o->mu_ref * pow(T, o->omega) / (rho * T);
             double e = exp(-dt / tau);
             int64_t bf = o->cbf[6 * c + lf];
@@ -1683,6 +1762,7 @@ static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t
                 int64_t i = o->np++;
                 for (int d = 0; d < 3; ++d) { o->px[3 * i + d] = xs[d]; o->pu[3 * i + d] = u[d]; }
                 o->pm[i] = msam;
+                o->pe[i] = o->K > 0 ? internal_energy(o->seed, uid, o->step, TAG_INT, 0, o->inst, o->K, T) : 0.0;
                 o->pc[i] = c;
                 o->pid[i] = uid;
                 (*tin)[*ninj] = ev[3] * dt;
@@ -1790,30 +1870,30 @@ int orc_step(oracle_t *o)
                 extrap(o->W + 5 * nb, q.gW + 15 * nb, o->xc + 3 * nb, xf, Wr);
                 extrap(q.Wh + 5 * nb, q.gH + 15 * nb, o->xc + 3 * nb, xf, Whr);
                 orc_flux2_interior(Wl, Wr, Whl, Whr, q.gW + 15 * c, q.gW + 15 * nb, q.gH + 15 * c, q.gH + 15 * nb, n,
-                                   dt, o->mu_ref, o->omega, o->c2, gks, F);
+                                   dt, o->mu_ref, o->omega, o->c2, gks, o->K, F);
             } else {
                 const obc_t *b = o->bc + (-1 - nb);
                 if (b->type == BC_SPECULAR)
                     orc_flux2_specular(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, n, dt, o->mu_ref, o->omega, o->c2, gks,
-                                       F);
+                                       o->K, F);
                 else if (b->type == BC_DIFFUSE)
-                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, gks, F);
+                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, gks, o->K, F);
                 else
                     orc_flux2_farfield(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, b->Winf, n, dt, o->mu_ref, o->omega,
-                                       o->c2, gks, F);
+                                       o->c2, gks, o->K, F);
             }
         } else if (nb >= 0) {
             orc_flux_interior(o->W + 5 * c, o->W + 5 * nb, q.rhoh[c], q.rhoh[nb], n, dt, o->mu_ref, o->omega,
-                              o->c2, gks, F);
+                              o->c2, gks, o->K, F);
         } else {
             const obc_t *b = o->bc + (-1 - nb);
             if (b->type == BC_SPECULAR)
-                orc_flux_specular(o->W + 5 * c, q.rhoh[c], n, dt, o->mu_ref, o->omega, o->c2, gks, F);
+                orc_flux_specular(o->W + 5 * c, q.rhoh[c], n, dt, o->mu_ref, o->omega, o->c2, gks, o->K, F);
             else if (b->type == BC_DIFFUSE)
-                orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, gks, F);
+                orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, gks, o->K, F);
             else
                 orc_flux_interior(o->W + 5 * c, b->Winf, q.rhoh[c], b->Winf[0], n, dt, o->mu_ref, o->omega,
-                                  o->c2, gks, F);
+                                  o->c2, gks, o->K, F);
         }
         for (int k = 0; k < 5; ++k) Phi[5 * f + k] = F[k] * o->farea[f];
     }
@@ -1849,19 +1929,20 @@ int orc_step(oracle_t *o)
             if (tf < dt) { ts = tf; collided = 1; }
         }
         int64_t cross = 0;
-        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pc + i, ts, entry0, o->pid[i], o->step, &cross,
-                           &nwall);
+        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pe + i, o->pc + i, ts, entry0, o->pid[i], o->step,
+                           &cross, &nwall);
         ncross_tot += cross;
         if (rc < 0) { status = ORC_E_LOST; goto done; }
         if (rc == 1) { ++nesc; continue; }
         int64_t c = o->pc[i];
-        add_phi(E + 5 * c, o->pm[i], o->pu + 3 * i);
+        add_phi(E + 5 * c, o->pm[i], o->pu + 3 * i, o->pe[i]);
         if (collided) { ++ncoll; continue; }
-        add_phi(Pn + 5 * c, o->pm[i], o->pu + 3 * i);
+        add_phi(Pn + 5 * c, o->pm[i], o->pu + 3 * i, o->pe[i]);
         nl[c] += 1;
         if (keep != i) {
             for (int d = 0; d < 3; ++d) { o->px[3 * keep + d] = o->px[3 * i + d]; o->pu[3 * keep + d] = o->pu[3 * i + d]; }
             o->pm[keep] = o->pm[i];
+            o->pe[keep] = o->pe[i];
             o->pc[keep] = o->pc[i];
             o->pid[keep] = o->pid[i];
         }

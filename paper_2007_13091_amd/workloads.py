@@ -90,15 +90,25 @@ def mu_ref_from_kn(kn: float, omega: float) -> float:
     return 15.0 * math.sqrt(2.0 * math.pi) * kn / (2.0 * (5.0 - 2.0 * omega) * (7.0 - 2.0 * omega))
 
 
-def conservative(rho, U, T):
-    """W = (rho, rho U, rho E) for a monatomic gas with R = 1; rho E = rho |U|^2/2 + 3/2 rho T."""
+def internal_dof(gamma: float) -> int:
+    """K internal degrees of freedom of gamma = (K + 5)/(K + 3) (5/3: K = 0; 7/5: K = 2)."""
+    K = 2.0 / (gamma - 1.0) - 3.0
+    Ki = int(round(K))
+    if abs(K - Ki) > 1e-9 or Ki < 0:
+        raise ValueError(f"gamma = {gamma} is not (K + 5)/(K + 3) for an integer K >= 0")
+    return Ki
+
+
+def conservative(rho, U, T, K=0):
+    """W = (rho, rho U, rho E) with R = 1 and K internal degrees of freedom:
+    rho E = rho |U|^2/2 + (3 + K)/2 rho T (K = 0: monatomic)."""
     rho = np.asarray(rho, dtype=np.float64)
     U = np.asarray(U, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
     W = np.empty(rho.shape + (5,), dtype=np.float64)
     W[..., 0] = rho
     W[..., 1:4] = rho[..., None] * U
-    W[..., 4] = 0.5 * rho * (U * U).sum(-1) + 1.5 * rho * T
+    W[..., 4] = 0.5 * rho * (U * U).sum(-1) + 0.5 * (3 + K) * rho * T
     return W
 
 
@@ -273,9 +283,10 @@ def morton_numbered(w: Workload, bits: int = 10) -> Workload:
     return Workload(w.name + " (Morton-numbered)", mesh, w.params, w.W0.reshape(-1, 5)[order].copy(), w.steps)
 
 
-def sod(nx=50, ny=2, nz=2, n_ref=200, kn=1e-3, cfl=0.5, steps=40, seed=1, tets=False) -> Workload:
+def sod(nx=50, ny=2, nz=2, n_ref=200, kn=1e-3, cfl=0.5, steps=40, seed=1, tets=False, gamma=5.0 / 3.0) -> Workload:
     """Shock tube in a square column (paper Sec. 4.1) at the hot-path size: [0,1]x[0,0.04]^2,
-    monatomic, rho = 1, p = 1 left of x = 0.5 and rho = 0.125, p = 0.1 right; all walls specular."""
+    rho = 1, p = 1 left of x = 0.5 and rho = 0.125, p = 0.1 right; all walls specular; monatomic
+    unless gamma says otherwise (7/5: the paper's diatomic gas, K = 2)."""
     h = 1.0 / nx
     lo, hi = (0.0, 0.0, 0.0), (1.0, ny * h, nz * h)
     bcs = [BC(BC_SPECULAR)]
@@ -285,8 +296,9 @@ def sod(nx=50, ny=2, nz=2, n_ref=200, kn=1e-3, cfl=0.5, steps=40, seed=1, tets=F
     left = xc[:, 0] < 0.5
     rho = np.where(left, 1.0, 0.125)
     p = np.where(left, 1.0, 0.1)
-    W0 = conservative(rho, np.zeros((mesh.n_cells, 3)), p / rho)
-    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    W0 = conservative(rho, np.zeros((mesh.n_cells, 3)), p / rho, K=internal_dof(gamma))
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed,
+                 gamma=gamma)
     return Workload("sod", mesh, prm, W0, steps)
 
 
@@ -305,7 +317,7 @@ def cavity(n=32, n_ref=400, kn=0.075, cfl=0.95, steps=2000, seed=1, Tw=1.0) -> W
 
 
 def closed_box(n=(4, 3, 2), n_ref=50, kn=0.05, cfl=0.5, seed=7, bc=BC_SPECULAR, perturb=0.2, tets=False,
-               jitter=0.0) -> Workload:
+               jitter=0.0, gamma=5.0 / 3.0) -> Workload:
     """Small closed box with a seeded non-uniform initial state (for conservation checks)."""
     bcs = [BC(bc, Tw=1.0)]
     side = {s: 0 for s in SIDES}
@@ -318,8 +330,9 @@ def closed_box(n=(4, 3, 2), n_ref=50, kn=0.05, cfl=0.5, seed=7, bc=BC_SPECULAR, 
     rho = 1.0 + perturb * rng.uniform(-1, 1, nc)
     U = 0.3 * perturb * rng.uniform(-1, 1, (nc, 3))
     T = 1.0 + perturb * rng.uniform(-1, 1, nc)
-    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
-    return Workload("closed_box", mesh, prm, conservative(rho, U, T), 10)
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed,
+                 gamma=gamma)
+    return Workload("closed_box", mesh, prm, conservative(rho, U, T, K=internal_dof(gamma)), 10)
 
 
 def periodic_box(n=(4, 3, 3), n_ref=50, kn=0.05, cfl=0.5, seed=5, perturb=0.2, drift=(0.3, -0.2, 0.1),
@@ -352,11 +365,12 @@ def periodic_box(n=(4, 3, 3), n_ref=50, kn=0.05, cfl=0.5, seed=5, perturb=0.2, d
 
 
 def free_stream_box(n=(4, 3, 3), U=(0.8, 0.3, 0.0), T=1.0, rho=1.0, n_ref=100, kn=0.5, cfl=0.5, seed=11,
-                    tets=False, jitter=0.0, perturb=0.0, walls=None) -> Workload:
+                    tets=False, jitter=0.0, perturb=0.0, walls=None, gamma=5.0 / 3.0) -> Workload:
     """Box of [0,1]x[0,0.75]x[0,0.5] with far-field faces on its sides, filled with the free stream
     it is bathed in (perturb > 0: a seeded non-uniform initial state instead).  walls: optional
     dict side name -> BC for sides that are not far field."""
-    Winf = conservative(np.array([rho]), np.array([U]), np.array([T]))[0]
+    K = internal_dof(gamma)
+    Winf = conservative(np.array([rho]), np.array([U]), np.array([T]), K=K)[0]
     bcs = [BC(BC_FARFIELD, Winf=tuple(float(v) for v in Winf))]
     side = {s_: 0 for s_ in SIDES}
     for nm, b in (walls or {}).items():
@@ -371,10 +385,11 @@ def free_stream_box(n=(4, 3, 3), U=(0.8, 0.3, 0.0), T=1.0, rho=1.0, n_ref=100, k
         r = rho * (1.0 + perturb * rng.uniform(-1, 1, nc_))
         Uc = np.asarray(U, dtype=np.float64)[None, :] * (1.0 + perturb * rng.uniform(-1, 1, (nc_, 3)))
         Tc = T * (1.0 + perturb * rng.uniform(-1, 1, nc_))
-        W0 = conservative(r, Uc, Tc)
+        W0 = conservative(r, Uc, Tc, K=K)
     else:
         W0 = np.tile(Winf, (nc_, 1))
-    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed)
+    prm = Params(mu_ref=mu_ref_from_kn(kn, 0.81), omega=0.81, cfl=cfl, c2=0.0, n_ref=n_ref, n_min=0, seed=seed,
+                 gamma=gamma)
     return Workload("free_stream_box", mesh, prm, W0, 10)
 
 
