@@ -1,14 +1,18 @@
 """Benchmark of the UGKWP hot path on one MI355X.
 
-Workload: the lid-driven cubic cavity (paper Sec. 4.2) at the hot-path size: unit cube of
-32^3 box hexes, diffuse isothermal walls at T_w = 1, lid z = 1 moving at 0.16 sqrt(gamma T_w),
-Kn 0.075 (VHS, omega = 0.81), 400 particles per cell (about 1.3e7 particles), CFL 0.95,
-synthetic initial state (gas at rest).  A step is one full time step of the scheme: wave
-flux, sampling, free-flight times, free transport, particle sums and the cell update.
+Headline workload: the batched form (64 independent shock-tube and cavity instances, 2.8e6
+box cells, 50-500 particles per cell, Knudsen numbers 1e-4 to 1) in the FP32 form (flux and
+transport in FP32; per-cell sums, W - W^p and energy -> T in FP64), every instance in one
+launch per kernel, launch shapes autotuned, against the same 64 instances run one by one in
+the FP64 plain form on the same GPU.  A step is one full time step of the scheme: wave flux,
+sampling, free-flight times, free transport, particle sums and the cell update.
 
-Prints ONE JSON line: particle moves/s (value) and cell-steps/s, the dominant kernel's
-roofline position (timed live with hip events on the library's stream), and the CPU
-oracle's rate on a bounded sample of the same workload.
+Prints ONE JSON line: particle moves/s (value) and cell-steps/s of the batched FP32 form;
+the FP64 plain comparison; the FP32 form's one-step error against the FP64 plain form from the
+same state, per instance; the roofline position of both particle kernels (timed live with hip
+events on the library's stream over the timed steps) and of the whole step; the lid-driven
+cavity legs (second order, after 1000 steps); side numbers; and the CPU oracle's rate on a
+bounded sample of the batch (its first instances, one step each from their warm states).
 """
 import argparse
 import hashlib
@@ -26,14 +30,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # algorithmic bytes of one particle move: the particle state read once and written once
 # (FP64: x 24 + u 24 + m 8 + cell 4 + uid 8 = 68 B; FP32 form: 12 + 12 + 4 + 4 + 8 = 40 B)
-BYTES_PER_MOVE_FP64 = 136
-BYTES_PER_MOVE_FP32 = 80
+BYTES_PER_MOVE = {"double": 136, "float": 80}
 # algorithmic bytes of the gather (S6): a survivor's record read and written with its cell,
 # plus its bucket key read (FP64: 64 + 64 + 4 + 4 = 136 B; FP32: 36 + 40 + 4 = 80 B); a
 # collided particle's velocity and mass read with its key (FP64: 48 + 4 = 52 B; FP32: 36 + 4)
 BYTES_PER_SURVIVOR = {"double": 136, "float": 80}
 BYTES_PER_COLLIDED = {"double": 52, "float": 40}
+# algorithmic bytes of a first-order cell-step: W and P read and written, volume and the
+# projections Delta S read (192 B), plus the face geometry (normal, area, owner and neighbour)
+# of its share of the faces: box hex 3 faces (FP64 40 B each, FP32 24 B); second order adds
+# the least-squares data of the cell (48 B) and the face-centre offsets (24 B per face)
+BYTES_PER_CELL = {("hex", "double", 0): 312, ("hex", "float", 0): 264,
+                  ("hex", "double", 2): 312 + 48 + 3 * 24, ("hex", "float", 2): 264 + 24 + 3 * 12}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CAVITY_START = 1000  # the cavity legs time the steps after this many (the paper's cavity runs
+#                      thousands of steps; the survey's window is steps 1001-2000)
+BATCH_START = 100    # the batched legs time the steps after this many
 
 
 def code_text(src):
@@ -58,39 +70,18 @@ def kernel_source_digest(read=None):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs, if the kernel
-    source has not changed since they were taken (else None)."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from committed rocprofv3 counter runs,
+    if the kernel source has not changed since they were taken (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = t.get(kernel)
+    e = t.get(workload, {}).get(kernel)
     if not e or e.get("source_digest") != kernel_source_digest():
         return None
     return e.get("bytes_per_launch")
-
-
-def cpu_baseline(steps=12):
-    """The oracle as it stands, single-threaded, on the same workload from the same initial
-    state: the first `steps` steps (the first samples every particle, the rest are typical)."""
-    import oracle
-    from paper_2007_13091_amd import workloads as wl
-
-    w = wl.morton_numbered(wl.cavity())
-    o = oracle.Oracle(w.mesh, w.params)
-    o.set_state(w.W0)
-    moved = 0
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        o.step()
-        st = o.stats()
-        moved += st["n_alive"] + st["n_collided"] + st["n_escaped"]
-    el = time.perf_counter() - t0
-    return {"value": moved / el, "unit": "particle moves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} steps of the 32^3 cavity (Morton-numbered, 400 particles/cell) from the initial state, "
-                      f"{moved} particle moves in {el:.1f} s; cell-steps/s {steps * w.mesh.n_cells / el:.3g}"}
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -105,30 +96,22 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
-def timed_run(w, precision, warmup, steps):
-    """W untimed steps (every kernel group timed with hip events, to find the dominant one),
-    then K timed steps bracketed by device synchronisation, with hip events on the library's
-    stream around the dominant kernel only (events around every group cost about 5% of a
-    step).  Returns the per-group times of the warm-up and the dominant group's time over the
-    timed steps."""
+def kernel_names(rtype, cfg, multi):
+    """Names of the two particle kernels as the profiler lists them (cfg: launch shapes)."""
+    return {"stream": f"k_stream<{rtype}, {cfg[0]}, {'true' if multi else 'false'}, {cfg[1]}>",
+            "gather": f"k_gather<{rtype}, 1>"}
+
+
+def timed_steps(s, steps):
+    """K steps, eager launches, bracketed by device synchronisation, with hip events on the
+    library's stream around the two particle kernels (transport and gather) in every step.
+    Returns wall seconds, particle moves, the two kernels' average launch times (ms) and the
+    statistics before and after."""
     import torch
 
-    from paper_2007_13091_amd.ugkwp import Solver
-
-    s = Solver(w.mesh, w.params, precision=precision)
-    s.init_state(w.W0)
-    cfg = s.launch_config()
-    s.step(1, stats=False)
-    s.profile(True)
-    s.profile_read()  # clear
-    st0 = s.step(max(warmup - 1, 1), stats=True)
-    warm = s.profile_read()
-    # the heavier of the two kernels that carry the step's particle traffic (the others are
-    # a few percent of a step; under a counter-collecting profiler their launch overheads
-    # can look larger in a short warm-up)
-    dom = max(("stream", "gather"), key=lambda k: warm[k][0])
-    s.profile(True, slots=[dom])
-    moved0 = st0["moved_total"]
+    s.profile(True, slots=["stream", "gather"])
+    s.profile_read()
+    st0 = s.step(0, stats=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(steps, stats=False)
@@ -137,29 +120,266 @@ def timed_run(w, precision, warmup, steps):
     st1 = s.step(0, stats=True)
     prof = s.profile_read()
     s.profile(False)
+    kms = {k: prof[k][0] / max(prof[k][1], 1) for k in ("stream", "gather")}
+    return t1 - t0, st1["moved_total"] - st0["moved_total"], kms, st0, st1
+
+
+def kernel_roofline(kms, moves_per_step, last, rtype, names, workload):
+    """Roofline position of the transport and the gather: algorithmic bytes per launch over
+    the average launch time.  Transport: the particle moves of a step; gather: the survivors
+    and collided particles of a step (those of the last timed step)."""
+    algo = {"stream": BYTES_PER_MOVE[rtype] * moves_per_step,
+            "gather": BYTES_PER_SURVIVOR[rtype] * last["n_alive"] + BYTES_PER_COLLIDED[rtype] * last["n_collided"]}
+    out = {}
+    for k in ("stream", "gather"):
+        ach = algo[k] / (kms[k] * 1e-3) / 1e9
+        out[k] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(names[k], workload),
+                  "kernel": names[k], "kernel_avg_ms": round(kms[k], 4), "algorithmic_bytes_per_launch": int(algo[k])}
+    dom = max(("stream", "gather"), key=lambda k: kms[k])
+    return dom, out
+
+
+def whole_step(ms_per_step, moves_per_step, cells, rtype, recon=0):
+    """The whole step against HBM: the particle moves' and the cells' algorithmic bytes over
+    the wall time of a step."""
+    algo = BYTES_PER_MOVE[rtype] * moves_per_step + BYTES_PER_CELL[("hex", rtype, recon)] * cells
+    ach = algo / (ms_per_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": int(algo)}
+
+
+def _prim(W):
+    rho = W[:, 0]
+    U = W[:, 1:4] / rho[:, None]
+    T = (2 / 3) * (W[:, 4] - 0.5 * rho * (U * U).sum(1)) / rho
+    return rho, np.linalg.norm(U, axis=1), T
+
+
+def field_error(Wa, Wb):
+    """L1 (mean over cells) and Linf of rho, |U| and T of Wa against Wb, relative to the mean
+    density, the thermal speed and the mean temperature of Wb."""
+    ra, ua, ta = _prim(Wa)
+    rb, ub, tb = _prim(Wb)
+    out = {}
+    for name, a, b, sc in (("rho", ra, rb, rb.mean()), ("U", ua, ub, np.sqrt(tb.mean())), ("T", ta, tb, tb.mean())):
+        d = np.abs(a - b) / sc
+        out[name] = {"L1": float(d.mean()), "Linf": float(d.max())}
+    return out
+
+
+def batch_workloads(sampling):
+    from paper_2007_13091_amd import workloads as wl
+
+    ws = [wl.morton_numbered(w) for w in wl.batched()]
+    for w in ws:
+        w.params.sampling = sampling
+    return ws
+
+
+def batch_capacity(w, steps):
+    # N_sam = 2 ceil(r) adds up to two particles per cell and step wherever the hydro wave has a
+    # collisionless part, and rarefied cells lose only their collided share, so counts drift up
+    # by up to two per cell and step on top of about N_ref
+    return int(1.3 * w.params.n_ref * w.mesh.n_cells + 2.2 * steps * w.mesh.n_cells) + 65536
+
+
+def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
+    """The batched FP32 form: `start` steps (of which the autotuner's trials), `warmup` more,
+    then `steps` timed; then the same `steps` replayed from a captured hip graph (side number).
+    Then each instance alone in the FP64 plain form, `start + warmup` steps, `steps` timed, and
+    the FP32 form's one-step error from that instance's state (exported from the FP64 run and
+    imported into both forms)."""
+    import torch
+
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    ws = batch_workloads(sampling)
+    meshes, params = [w.mesh for w in ws], [w.params for w in ws]
+    W0 = np.concatenate([w.W0 for w in ws])
+    nc = int(sum(w.mesh.n_cells for w in ws))
+    tuning = 13 * 2
+    total = start + warmup + 2 * steps + 2
+    caps = [batch_capacity(w, total) for w in ws]
+    stream = torch.cuda.Stream()
+    s = Solver(meshes, params, capacity=caps, precision=1, stream=stream)
+    s.init_state(W0)
+    s.step(max(start - tuning, 1), stats=False)
+    cfg = s.autotune(steps_per_trial=1)
+    s.step(warmup, stats=True)
+    el, moves, kms, st0, st1 = timed_steps(s, steps)
+    done_steps = int(st1["step"])
+    names = kernel_names("float", cfg, True)
+    workload = "batch64"
+    dom, kr = kernel_roofline(kms, moves / steps, st1, "float", names, workload)
+    s.graph(True)
+    s.step(1, stats=False)  # capture
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    s.step(steps, stats=False)
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - tg0) / steps * 1e3
     s.close()
     del s
     torch.cuda.empty_cache()
-    kern = {k: v for k, v in warm.items()}
-    kern[dom] = prof[dom]
-    return t1 - t0, st1["moved_total"] - moved0, kern, cfg, dom, st1
+    ms = el / steps * 1e3
+    out = {"value": moves / el, "ms_per_step": ms, "cell_steps_per_s": nc * steps / el,
+           "particles_per_step": int(moves / steps), "steps": steps, "timed_after_step": done_steps - steps,
+           "launch_config": {"stream_bs": cfg[0], "stream_ilp": cfg[1], "sample_wpb": cfg[2], "flux_bs": cfg[3]},
+           "dominant": dom, "kernels": kr, "whole_step": whole_step(ms, moves / steps, nc, "float"),
+           "graph_replay_ms_per_step": round(tg, 4), "cells": nc, "instances": len(ws)}
+    # FP64 plain, one instance after the other (eager launches), then the one-step error
+    pm, pt, pc = 0, 0.0, 0
+    kt = {"stream": 0.0, "gather": 0.0}
+    last64 = {"n_alive": 0, "n_collided": 0}
+    errs = []
+    flips = 0
+    sample, sample_moves = [], 0  # warm states of the first instances, for the CPU baseline
+    for k, (w, cap) in enumerate(zip(ws, caps)):
+        g = Solver(w.mesh, w.params, capacity=cap, precision=0)
+        g.init_state(w.W0)
+        g.step(done_steps - steps, stats=False)
+        e, mv, km, a, b = timed_steps(g, steps)
+        pm += mv
+        pt += e
+        pc += w.mesh.n_cells * steps
+        for q in kt:
+            kt[q] += km[q] * steps
+        last64["n_alive"] += b["n_alive"]
+        last64["n_collided"] += b["n_collided"]
+        st = g.export_state()
+        if sample_moves < cpu_sample_moves:
+            sample.append((k, w, st))
+            sample_moves += mv / steps
+        f = Solver(w.mesh, w.params, capacity=cap, precision=1)
+        f.import_state(st)
+        s64, s32 = g.step(1), f.step(1)
+        flips += abs(s64["n_collided"] - s32["n_collided"]) + abs(s64["n_alive"] - s32["n_alive"])
+        err = field_error(f.moments(0), g.moments(0))
+        errs.append({"instance": k, "cells": w.mesh.n_cells, "n_ref": w.params.n_ref,
+                     "mu_ref": w.params.mu_ref, "step": int(s64["step"]), **err})
+        f.close()
+        g.close()
+        del f, g
+        torch.cuda.empty_cache()
+    p_ms = pt / steps * 1e3
+    kms64 = {q: kt[q] / (len(ws) * steps) for q in kt}
+    out["fp64_plain_one_by_one"] = {
+        "value": pm / pt, "unit": "particle moves/s", "cell_steps_per_s": pc / pt, "ms_per_step": p_ms,
+        "kernel_ms_per_step_sum": {q: round(kt[q] / steps, 4) for q in kt},
+        "whole_step": whole_step(p_ms, pm / steps, nc, "double"),
+        "kernels": {q: {"kernel_avg_ms_mean_over_instances": round(kms64[q], 4),
+                        "achieved": round((BYTES_PER_MOVE["double"] * pm / steps if q == "stream" else
+                                           BYTES_PER_SURVIVOR["double"] * last64["n_alive"] +
+                                           BYTES_PER_COLLIDED["double"] * last64["n_collided"])
+                                          / (kt[q] / steps * 1e-3) / 1e9, 1),
+                        "unit": "GB/s", "peak": HBM_PEAK_GBS} for q in kt}}
+    for q in kt:
+        ach = out["fp64_plain_one_by_one"]["kernels"][q]["achieved"]
+        out["fp64_plain_one_by_one"]["kernels"][q]["frac"] = round(ach / HBM_PEAK_GBS, 4)
+    out["speedup_vs_fp64_plain_one_by_one"] = out["value"] / (pm / pt)
+    worst = {v: max(e[v]["L1"] for e in errs) for v in ("rho", "U", "T")}
+    worst_inf = {v: max(e[v]["Linf"] for e in errs) for v in ("rho", "U", "T")}
+    out["stated_error"] = {
+        "protocol": "one step of the FP32 form against one step of the FP64 plain form from the same state "
+                    "(each instance's FP64 state after the timed steps, exported and imported into both; the same "
+                    "Philox draws); FP64 plain matches the oracle to 1e-12 (parity tests)",
+        "worst_over_instances_L1": worst, "worst_over_instances_Linf": worst_inf,
+        "decision_flips": int(flips), "per_instance": errs}
+    return out, sample
+
+
+def cavity_leg(precision, steps, warmup, start, sampling=0, recon=2):
+    """The lid-driven cavity (Sec. 4.2) at 32^3, 400 particles per cell, second order
+    (least-squares gradients with the Venkatakrishnan limiter, as the paper's cavity): `start`
+    steps, `warmup` more, then `steps` timed."""
+    import torch
+
+    from paper_2007_13091_amd import workloads as wl
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.morton_numbered(wl.cavity())
+    w.params.sampling = sampling
+    w.params.recon = recon
+    nc = w.mesh.n_cells
+    s = Solver(w.mesh, w.params, precision=precision)
+    s.init_state(w.W0)
+    cfg = s.launch_config()
+    s.step(start, stats=False)
+    s.step(warmup, stats=True)
+    el, moves, kms, st0, st1 = timed_steps(s, steps)
+    rtype = "double" if precision == 0 else "float"
+    names = kernel_names(rtype, cfg, False)
+    workload = f"cavity32_recon{recon}"
+    dom, kr = kernel_roofline(kms, moves / steps, st1, rtype, names, workload)
+    ms = el / steps * 1e3
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    leg = {"value": moves / el, "unit": "particle moves/s", "ms_per_step": ms, "cell_steps_per_s": nc * steps / el,
+           "particles_per_step": int(moves / steps), "steps": steps, "timed_after_step": int(st1["step"]) - steps,
+           "dominant": dom, "kernels": kr, "whole_step": whole_step(ms, moves / steps, nc, rtype, recon)}
+    return leg
+
+
+def cpu_baseline(sample):
+    """The oracle as it stands on a sample of the batch: the first instances (in instance
+    order), each from the state the GPU's FP64 plain run reached after its timed steps
+    (imported into the oracle, with its instance index), one step each, timed.  Twice: the
+    serial build on one core, then the OpenMP build (the same results bit for bit) on every
+    thread OpenMP is given; the value is the OpenMP one."""
+    import oracle
+
+    def run(omp):
+        moved, cells, el = 0, 0, 0.0
+        for k, w, st in sample:
+            o = oracle.Oracle(w.mesh, w.params, instance=k, omp=omp)
+            o.set_state(w.W0)
+            o.import_state(st)
+            t0 = time.perf_counter()
+            o.step()
+            el += time.perf_counter() - t0
+            so = o.stats()
+            moved += so["n_alive"] + so["n_collided"] + so["n_escaped"]
+            cells += w.mesh.n_cells
+            del o
+        return moved, cells, el
+
+    m1, c1, e1 = run(False)
+    nth = oracle.threads(0)
+    mp, cp, ep = run(True)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    names = [k for k, _, _ in sample]
+    step = int(np.asarray(sample[0][2]["step"]).reshape(-1)[0]) if sample else 0
+    return {"value": mp / ep if ep > 0 else None, "unit": "particle moves/s", "cores": nth, "kind": "oracle",
+            "build": "OpenMP (per-face, per-cell and per-particle loops parallel; sums in serial order)",
+            "cpu_model": model, "cell_steps_per_s": cp / ep if ep > 0 else None,
+            "single_core": {"value": m1 / e1 if e1 > 0 else None, "cores": 1, "seconds": round(e1, 2),
+                            "cell_steps_per_s": c1 / e1 if e1 > 0 else None},
+            "sample": f"instances {names} of the batch (FP64, first order, energy-exact sampling), one step each from "
+                      f"the GPU run's state at step {step}: {mp} particle moves and {cp} cell-steps, {ep:.1f} s on "
+                      f"{nth} threads, {e1:.1f} s on one"}
 
 
 # algorithmic bytes of the first-order flux per face: both cells' W (2 x 40), the face's
 # geometry (normal, area, owner and neighbour: 48) and its flux out (40)
 BYTES_PER_FACE = 168
-
-
 GKS_CAPACITY = 65536
 
 
 def gks_side(steps, warmup):
     """Side number: the GKS limit of the scheme, the cavity at Kn 1e-6, FP64 plain.  There
     exp(-dt/tau) underflows to 0, so no particle is ever sampled and a step is the wave part
-    alone (at Kn 1e-4 the sampling rule, N_sam = 2 ceil(N_ref rho^hp / (2 (rho^p + rho^hp))),
-    still draws N_ref particles of tiny mass per cell once the previous ones have collided).
-    Cell-steps/s, and the flux kernel's position against HBM (its time from hip events over
-    the warm-up steps)."""
+    alone.  Cell-steps/s, and the flux kernel's position against HBM (its time from hip events
+    over the warm-up steps)."""
     import torch
 
     from paper_2007_13091_amd import workloads as wl
@@ -201,11 +421,12 @@ def gks_side(steps, warmup):
                               "faces": faces}}
 
 
-def configs_run():
-    """The other configurations, timed (not part of the default run): the shock tube over
-    its 40 steps (FP64; launch-bound at 200 cells), and the Mach 10 cube (1.2e6 tets) and the
-    Mach 15 vehicle at Kn 1e-3 (3.1e6 tets) in both forms over the steps after the first
-    (sampling from an empty start) and before their wakes empty (the impulsive start)."""
+def configs_run(gks_steps=3000):
+    """The other configurations, timed (not part of the default run): the shock tube over its
+    40 steps (FP64; launch-bound at 200 cells), and the Mach 10 cube (1.2e6 tets) and the
+    Mach 15 vehicle at Kn 1e-3 (3.1e6 tets) in both forms, started wave-only for `gks_steps`
+    steps (the paper's continuum start), timed over the wave-particle steps that follow, until
+    the near-wake turns non-physical."""
     import torch
 
     from paper_2007_13091_amd import workloads as wl
@@ -233,12 +454,12 @@ def configs_run():
     out = {}
     w = wl.morton_numbered(wl.sod())
     out["sod_50x2x2_fp64"] = one(w, 0, 1, 39)
-    w = wl.morton_numbered(wl.cube())
-    out["cube_mach10_fp64"] = one(w, 0, 1, 3)
-    out["cube_mach10_fp32"] = one(w, 1, 1, 3)
-    w = wl.morton_numbered(wl.vehicle(kn=1e-3))
-    out["vehicle_mach15_kn1e-3_fp64"] = one(w, 0, 1, 2)
-    out["vehicle_mach15_kn1e-3_fp32"] = one(w, 1, 1, 2)
+    for name, w in (("cube_mach10", wl.morton_numbered(wl.cube())),
+                    ("vehicle_mach15_kn1e-3", wl.morton_numbered(wl.vehicle(kn=1e-3)))):
+        w.params.gks_steps = gks_steps
+        w.params.sampling = 1
+        for prec in (0, 1):
+            out[f"{name}_{'fp64' if prec == 0 else 'fp32'}"] = one(w, prec, gks_steps + 1, 4)
     return out
 
 
@@ -298,133 +519,36 @@ def averaging_side(steps, warmup):
                          "bytes_per_cell": BYTES_PER_AVG_CELL, "cells": nc}}
 
 
-def stated_fp32_error():
-    """The FP32 form's error against the FP64 oracle, as measured by tests/test_gpu_fp32.py
-    and committed under profiles/ (L1 and Linf of rho, |U|, T, with the seed-to-seed noise)."""
-    f = os.path.join(ROOT, "profiles", "fp32_error_cavity16.json")
-    try:
-        with open(f) as fh:
-            rows = json.load(fh)
-        last = rows[-1]
-        return {"workload": "cavity 16^3, 400 particles/cell", "step": last["step"],
-                "fp32_vs_fp64_oracle": last["fp32_vs_oracle"], "fp64_seed_noise": last["noise_floor"]}
-    except (OSError, ValueError, KeyError, IndexError):
-        return None
-
-
-def batched_run(steps, warmup, plain_steps):
-    """The batched form on 64 independent tube and cavity instances (log-uniform cell counts in
-    [2e3, 2e5], Kn in [1e-4, 1], 50 to 500 particles per cell; each instance's cells numbered
-    along a Morton curve): FP32 transport, all instances in
-    one launch per kernel, launch shapes autotuned on real steps, steps replayed from a
-    captured hip graph.  Against it: the FP64 plain form run instance by instance (each alone,
-    eager launches), timed over `plain_steps` steps after the same number of warm-up steps."""
-    import torch
-
-    from paper_2007_13091_amd import workloads as wl
-    from paper_2007_13091_amd.ugkwp import Solver
-
-    ws = [wl.morton_numbered(w) for w in wl.batched()]
-    meshes, params = [w.mesh for w in ws], [w.params for w in ws]
-    W0 = np.concatenate([w.W0 for w in ws])
-    nc = int(sum(w.mesh.n_cells for w in ws))
-    # capacity: N_sam = 2 ceil(r) adds at least two particles per cell and step wherever the
-    # hydro wave has a collisionless part, and rarefied cells lose only their collided share,
-    # so counts drift up by up to two per cell and step on top of about N_ref
-    total_steps = warmup + 13 * 2 + 1 + steps
-    caps = [int(1.3 * w.params.n_ref * w.mesh.n_cells + 2.2 * total_steps * w.mesh.n_cells) + 65536 for w in ws]
-    stream = torch.cuda.Stream()
-    s = Solver(meshes, params, capacity=caps, precision=1, stream=stream)
-    s.init_state(W0)
-    s.step(max(warmup, 1), stats=False)
-    cfg = s.autotune(steps_per_trial=1)
-    s.graph(True)
-    st0 = s.step(1, stats=True)
-    s.profile(True)
-    s.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps, stats=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = s.step(0, stats=True)
-    done_steps = st1["step"]
-    s.close()
-    del s
-    torch.cuda.empty_cache()
-    el = t1 - t0
-    moves = st1["moved_total"] - st0["moved_total"]
-    out = {"value": moves / el, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
-           "ms_per_step": el / steps * 1e3, "cell_steps_per_s": nc * steps / el, "steps": steps,
-           "warmup_and_tuning_steps": int(done_steps - steps),
-           "instances": len(ws), "cells": nc, "particles_per_step": int(moves / steps),
-           "launch_config": {"stream_bs": cfg[0], "stream_ilp": cfg[1], "sample_wpb": cfg[2], "flux_bs": cfg[3]},
-           "graph_replay": True}
-    # FP64 plain, one instance after the other, each on the current stream with eager launches
-    pm, pt, pc = 0, 0.0, 0
-    for w, cap in zip(ws, caps):
-        g = Solver(w.mesh, w.params, capacity=cap, precision=0)
-        g.init_state(w.W0)
-        a = g.step(int(done_steps - steps), stats=True)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        g.step(plain_steps, stats=False)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        b = g.step(0, stats=True)
-        pm += b["moved_total"] - a["moved_total"]
-        pt += tb - ta
-        pc += w.mesh.n_cells * plain_steps
-        g.close()
-        del g
-    torch.cuda.empty_cache()
-    out["fp64_plain_one_by_one"] = {"value": pm / pt, "unit": "particle moves/s", "cell_steps_per_s": pc / pt,
-                                    "steps": plain_steps}
-    out["speedup_vs_fp64_plain_one_by_one"] = out["value"] / (pm / pt)
-    return out
-
-
-def roofline(prof, dom, moves_per_launch, last, rtype, cfg):
-    """Roofline position of the dominant kernel group dom (transport or gather): its
-    algorithmic bytes per launch over its average duration.  Transport: the particle moves
-    of a step; gather: the survivors and collided particles of a step (last: statistics of
-    the last timed step).  cfg: the solver's launch shapes (they name the kernel instance)."""
-    dom_ms, dom_n = prof[dom]
-    avg_ms = dom_ms / max(dom_n, 1)
-    if dom == "stream":
-        algo = (BYTES_PER_MOVE_FP64 if rtype == "double" else BYTES_PER_MOVE_FP32) * moves_per_launch
-        kname = f"k_stream<{rtype}, {cfg[0]}, false, {cfg[1]}>"
-    elif dom == "gather":
-        algo = BYTES_PER_SURVIVOR[rtype] * last["n_alive"] + BYTES_PER_COLLIDED[rtype] * last["n_collided"]
-        kname = f"k_gather<{rtype}, 1>"  # one wave (cell) per block
-    else:
-        raise RuntimeError(f"no algorithmic byte count for kernel group {dom}")
-    achieved = algo / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-            "kernel": kname, "kernel_avg_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(algo)}
+BATCH_WORKLOAD = ("64 independent instances alternating shock tube (Nx x 2 x 2 box hexes) and lid-driven cavity (n^3), "
+                  "cells log-uniform in [2e3, 2e5] (2.79e6 in all), Kn log-uniform in [1e-4, 1], 50-500 particles per "
+                  "cell, CFL 0.5, each numbered along a Morton curve; FP32 form, all instances in one launch per kernel, "
+                  "launch shapes autotuned; energy-exact sampling (the printed pairs turn 2 of the 64 instances "
+                  "non-physical)")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch-start", type=int, default=BATCH_START,
+                    help="steps of the batch before its warm-up (the autotuner's trials are among them)")
+    ap.add_argument("--cavity-start", type=int, default=CAVITY_START)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-moves", type=float, default=2e8,
+                    help="particle moves per step of the batch instances the CPU baseline steps once each")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cavity", action="store_true")
     ap.add_argument("--no-gks", action="store_true")
     ap.add_argument("--no-avg", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=40)
-    ap.add_argument("--batched-warmup", type=int, default=8)
     ap.add_argument("--configs", action="store_true",
                     help="time the tube, the cube and the vehicle (their own JSON object; not the bench line)")
     ap.add_argument("--gks-only", action="store_true",
                     help="run only the GKS-limit leg and print its JSON object (for profiling it alone)")
     ap.add_argument("--batched-only", action="store_true",
-                    help="run only the batched leg and print its JSON object (for profiling it alone)")
+                    help="run only the batched FP32 leg (no FP64 comparison) and print its JSON object")
+    ap.add_argument("--cavity-only", type=int, default=-1, metavar="PRECISION",
+                    help="run only the cavity leg in that precision (0 FP64, 1 FP32) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -439,55 +563,71 @@ def main():
     if args.gks_only:
         print(json.dumps({"gks_limit": gks_side(args.steps, args.warmup)}), flush=True)
         return
+    if args.cavity_only >= 0:
+        leg = cavity_leg(args.cavity_only, args.steps, args.warmup, args.cavity_start)
+        print(json.dumps({"cavity": leg}), flush=True)
+        return
     if args.batched_only:
-        print(json.dumps({"batched_form": batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)}),
-              flush=True)
+        import torch
+
+        from paper_2007_13091_amd.ugkwp import Solver
+
+        ws = batch_workloads(1)
+        caps = [batch_capacity(w, args.batch_start + args.warmup + args.steps + 2) for w in ws]
+        s = Solver([w.mesh for w in ws], [w.params for w in ws], capacity=caps, precision=1,
+                   stream=torch.cuda.Stream())
+        s.init_state(np.concatenate([w.W0 for w in ws]))
+        s.step(max(args.batch_start - 26, 1), stats=False)
+        cfg = s.autotune(steps_per_trial=1)
+        s.step(args.warmup, stats=True)
+        el, moves, kms, _, st1 = timed_steps(s, args.steps)
+        print(json.dumps({"batched_only": {"value": moves / el, "ms_per_step": el / args.steps * 1e3,
+                                           "kernel_ms": kms, "launch_config": list(cfg)}}), flush=True)
         return
 
-    from paper_2007_13091_amd import workloads as wl
-
-    w = wl.morton_numbered(wl.cavity())
-    nc = w.mesh.n_cells
-    el, moves, prof, cfg, dom, last = timed_run(w, 0, args.warmup, args.steps)
-    value = moves / el
-    moves_per_launch = moves / args.steps
-    roof = roofline(prof, dom, moves_per_launch, last, "double", cfg)
+    b, sample = batched_run(args.steps, args.warmup, args.batch_start, sampling=1,
+                            cpu_sample_moves=0 if args.no_cpu_baseline else args.cpu_moves)
+    plain = b["fp64_plain_one_by_one"]
+    roof = dict(b["kernels"][b["dominant"]])
+    roof["other_kernel"] = b["kernels"]["gather" if b["dominant"] == "stream" else "stream"]
+    roof["whole_step"] = b["whole_step"]
     out = {
         "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
-        "value": value,
+        "value": b["value"],
         "unit": "particle moves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": b["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32/f64",
         "data": "synthetic",
-        "config": {"workload": "lid-driven cavity, 32^3 box hexes numbered along a Morton curve, 400 particles/cell, "
-                               "Kn 0.075, diffuse walls, lid 0.16 sqrt(gamma T_w); FP64 plain form",
-                   "cells": nc, "faces": int(w.mesh.n_cells * 3 + 3 * 32 * 32), "particles_per_step": int(moves_per_launch)},
-        "cell_steps_per_s": nc * args.steps / el,
-        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+        "config": {"workload": BATCH_WORKLOAD, "instances": b["instances"], "cells": b["cells"],
+                   "particles_per_step": b["particles_per_step"], "timed_after_step": b["timed_after_step"],
+                   "launch_config": b["launch_config"]},
+        "cell_steps_per_s": b["cell_steps_per_s"],
+        "fp64_plain_one_by_one": plain,
+        "speedup_vs_fp64_plain": b["speedup_vs_fp64_plain_one_by_one"],
+        "stated_error": b["stated_error"],
+        "graph_replay_ms_per_step": b["graph_replay_ms_per_step"],
         "roofline": roof,
     }
-    if not args.no_fp32:
-        el32, moves32, prof32, cfg32, dom32, last32 = timed_run(w, 1, args.warmup, args.steps)
-        out["fp32_form"] = {"value": moves32 / el32, "unit": "particle moves/s", "dtype": "f32 transport, f64 sums",
-                            "ms_per_step": el32 / args.steps * 1e3, "cell_steps_per_s": nc * args.steps / el32,
-                            "speedup_vs_fp64_plain": (moves32 / el32) / value,
-                            "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof32.items()},
-                            "roofline": roofline(prof32, dom32, moves32 / args.steps, last32, "float", cfg32),
-                            "stated_error": stated_fp32_error()}
-    if not args.no_batched:
-        out["batched_form"] = batched_run(args.batched_steps, args.batched_warmup, args.batched_steps)
+    if not args.no_cavity:
+        c64 = cavity_leg(0, args.steps, args.warmup, args.cavity_start)
+        c32 = cavity_leg(1, args.steps, args.warmup, args.cavity_start)
+        c32["speedup_vs_fp64_plain"] = c32["value"] / c64["value"]
+        out["cavity32"] = {"workload": "lid-driven cavity, 32^3 box hexes (Morton-numbered), 400 particles/cell, "
+                                       "Kn 0.075, diffuse walls, lid 0.16 sqrt(gamma T_w), second order "
+                                       "(Venkatakrishnan), the printed pairs of Sec. 2.4(b)",
+                           "fp64_plain": c64, "fp32_form": c32}
     if not args.no_gks:
         out["gks_limit"] = gks_side(args.steps, args.warmup)
     if not args.no_avg:
         out["time_averaging"] = averaging_side(args.steps, args.warmup)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    if sample:
+        out["cpu_baseline"] = cpu_baseline(sample)
     print(json.dumps(out), flush=True)
 
 

@@ -12,9 +12,11 @@
  *      particles and new particle sums W^p
  * All of it runs in HIP kernels on the caller's stream.
  *
- * Units: R = 1 (p = rho T, lambda = 1/(2T)); monatomic gas (gamma = 5/3, K = 0).
+ * Units: R = 1 (p = rho T, lambda = 1/(2T)); K internal degrees of freedom (Sec. 2.1), from
+ * gamma = (K + 5)/(K + 3): K = 0 monatomic (5/3), K = 2 diatomic (7/5).
  * Conservative state per cell, per unit volume: W = (rho, rho U, rho V, rho W, rho E) with
- * rho E = rho |U|^2 / 2 + 3 rho T / 2.
+ * rho E = rho |U|^2 / 2 + (3 + K) rho T / 2.  A particle carries mass, position, velocity and,
+ * for K > 0, its internal energy variable e = |xi|^2 (its energy is m (|u|^2 + e) / 2).
  *
  * Memory and ownership.  Host arrays passed in are copied during the call and never
  * retained.  All device memory the library uses lives in ONE caller-owned device buffer
@@ -101,7 +103,8 @@ typedef struct {
 } ugkwp_mesh;
 
 typedef struct {
-    double gamma;         /* must be 5/3 (monatomic) */
+    double gamma;         /* (K + 5)/(K + 3) for an integer 0 <= K <= 8: 5/3 monatomic, 7/5 diatomic;
+                             the same for every instance of a batch */
     double mu_ref;        /* tau = mu_ref T^omega / p  (T_ref = 1), Eq. tau_via_T_ref */
     double omega;
     double cfl;           /* C in dt = C min Omega / (Lambda^x + Lambda^y + Lambda^z) */
@@ -209,10 +212,10 @@ int32_t ugkwp_average(ugkwp_ctx *ctx, double *Wbar, int32_t out_is_device, doubl
 int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n);
 
 /* Copy the particles out to host arrays sized by ugkwp_particle_count:
- * x [n][3], u [n][3], m [n], cell [n] (int32), uid [n].  Order: grouped by cell.
- * Any pointer may be NULL to skip that field.  Synchronises. */
+ * x [n][3], u [n][3], m [n], cell [n] (int32), uid [n], e [n] (internal energy variable, 0 for
+ * K = 0).  Order: grouped by cell.  Any pointer may be NULL to skip that field.  Synchronises. */
 int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell,
-                               uint64_t *uid);
+                               uint64_t *uid, double *e);
 
 /* State between steps, for checkpoints, restarts and tests: everything a step reads
  * that the previous step left (Sec. 2.3: the conservative state W, the raw sums P of the
@@ -226,7 +229,8 @@ int32_t ugkwp_export_state(ugkwp_ctx *ctx, double *W, double *P, int64_t *step, 
 
 /* Replace the state: W and P as above (host, [n_cells][5]); n particles (host) x [n][3],
  * u [n][3], m [n], cell [n] (concatenated cell numbering, non-decreasing: grouped by cell),
- * uid [n]; step [n_inst] (each below 2^19, the particle-id field) and t [n_inst].  The
+ * uid [n], e [n] (internal energy variables; NULL: 0, ignored for K = 0); step [n_inst] (each
+ * below 2^19, the particle-id field) and t [n_inst].  The
  * particles become the old particles of the next step, N_left of a cell is its count; the
  * time-averaging sums are cleared (the setting is kept).  The FP32 form rounds x, u and m to
  * single precision.  Importing what ugkwp_export_state and ugkwp_export_particles gave
@@ -235,7 +239,7 @@ int32_t ugkwp_export_state(ugkwp_ctx *ctx, double *W, double *P, int64_t *step, 
  * W); on error the previous state is untouched.  Clears a poisoned context.  Synchronises. */
 int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int64_t n, const double *x,
                            const double *u, const double *m, const int32_t *cell, const uint64_t *uid,
-                           const int64_t *step, const double *t);
+                           const double *e, const int64_t *step, const double *t);
 
 /* Per-cell geometry as the library computed it: volume [n_cells], centroid [n_cells][3],
  * projections Delta S [n_cells][3] (host arrays). */

@@ -15,30 +15,33 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ugkwp_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 OK, E_ARG, E_MESH, E_CAPACITY, E_LOST, E_NONPHYS = range(6)
 TAG_TF, TAG_POS, TAG_VEL, TAG_WALL, TAG_INJECT = 1, 2, 3, 4, 5
 
-_lib = None
+_libs = {}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain IEEE double, no contraction, no fast-math)."""
-    stale = not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)
+def build(force: bool = True, omp: bool = False) -> str:
+    """Compile the oracle with gcc (plain IEEE double, no contraction, no fast-math).  omp:
+    the same source with OpenMP on (its per-cell, per-face and per-particle loops run in
+    parallel; every sum keeps the serial order, so the results are the same bit for bit)."""
+    out = LIB_OMP if omp else LIB
+    stale = not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC)
     if force or stale:
-        tmp = LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-o", tmp, SRC, "-lm"]
+        tmp = out + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+        cmd += ["-fopenmp"] if omp else []
+        cmd += ["-o", tmp, SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build(force=False)
-        L = C.CDLL(LIB)
+def lib(omp: bool = False):
+    if omp not in _libs:
+        L = C.CDLL(build(force=False, omp=True) if omp else build(force=False))
         d, i64, i32, u64, vp = C.c_double, C.c_int64, C.c_int32, C.c_uint64, C.c_void_p
         P = C.POINTER
         L.orc_philox4x64_10.argtypes = [P(u64), P(u64), P(u64)]
@@ -74,6 +77,7 @@ def lib():
         L.orc_flux_speed.restype = d
         L.orc_flux_speed.argtypes = [d, d]
         L.orc_slope.argtypes = [d, d, d, d, C.c_int, P(d), P(d)]
+        L.orc_gp_eval.argtypes = [P(d), P(d), d, d, C.c_int, i64, P(d), P(d), P(d), P(d), P(d)]
         L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, C.c_int, P(d)]
         L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
         L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
@@ -93,8 +97,15 @@ def lib():
         L.orc_average.argtypes = [vp, P(d), P(d), P(i64)]
         L.orc_track.restype = C.c_int
         L.orc_track.argtypes = [vp, P(d), P(d), P(d), P(i64), d, C.c_int, u64, i64, P(i64), P(i64)]
-        _lib = L
-    return _lib
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = [C.c_int]
+        _libs[omp] = L
+    return _libs[omp]
+
+
+def threads(n=0, omp=True):
+    """Threads the OpenMP build uses (n > 0 sets them first); 1 for the serial build."""
+    return int(lib(omp).orc_threads(int(n)))
 
 
 def _p(a, ct):
@@ -218,6 +229,20 @@ def internal_dof(gamma):
     return Ki
 
 
+def gp_eval(W, gW, tau, dt, K, u, e=None):
+    """First-order g_p of one cell (sampling 2): (alpha, B, 1 + alpha (...) at the points u, e)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    gW = np.ascontiguousarray(gW, dtype=np.float64).reshape(15)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+    n = u.shape[0]
+    e = np.zeros(n) if e is None else np.ascontiguousarray(e, dtype=np.float64)
+    w = np.zeros(n)
+    a, B = C.c_double(0), C.c_double(0)
+    lib().orc_gp_eval(_p(W, C.c_double), _p(gW, C.c_double), float(tau), float(dt), int(K), n, _p(u, C.c_double),
+                      _p(e, C.c_double), C.byref(a), C.byref(B), _p(w, C.c_double))
+    return a.value, B.value, w
+
+
 class OracleError(RuntimeError):
     def __init__(self, msg, status=None):
         super().__init__(msg)
@@ -227,8 +252,8 @@ class OracleError(RuntimeError):
 class Oracle:
     """One instance of the CPU reference solver on a mesh (see paper_2007_13091_amd.workloads)."""
 
-    def __init__(self, mesh, params, instance=0):
-        L = lib()
+    def __init__(self, mesh, params, instance=0, omp=False):
+        L = self.L = lib(omp)
         self.mesh = mesh
         self.params = params
         t, tw, uw, wi, sh = mesh.bc_arrays()
@@ -268,12 +293,12 @@ class Oracle:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self.L.orc_destroy(self.h)
             self.h = None
 
     def set_state(self, W0):
         W0 = np.ascontiguousarray(W0, dtype=np.float64).reshape(self.nc, 5)
-        lib().orc_set_state(self.h, _p(W0, C.c_double))
+        self.L.orc_set_state(self.h, _p(W0, C.c_double))
 
     def import_state(self, state, instance=0):
         """Replace the state between steps: W, P ([nc][5]), particles (dict of x, u, m, cell,
@@ -290,7 +315,7 @@ class Oracle:
         e = np.ascontiguousarray(p["e"] if p.get("e") is not None else np.zeros(n), dtype=np.float64).reshape(n)
         step = int(np.asarray(state["step"]).reshape(-1)[instance])
         t = float(np.asarray(state["t"]).reshape(-1)[instance])
-        rc = lib().orc_import_state(self.h, _p(W, C.c_double), _p(P, C.c_double), n, _p(x, C.c_double),
+        rc = self.L.orc_import_state(self.h, _p(W, C.c_double), _p(P, C.c_double), n, _p(x, C.c_double),
                                     _p(u, C.c_double), _p(m, C.c_double), _p(c, C.c_int64), _p(uid, C.c_uint64),
                                     _p(e, C.c_double), step, t)
         if rc != OK:
@@ -300,7 +325,7 @@ class Oracle:
         """Terms of the last update per cell, raw (times Omega): wave flux -sum_f s_f Phi_f, E
         (particles ending in the cell) and S (particles starting in it), [nc][5] each."""
         F = np.zeros((self.nc, 5)); E = np.zeros((self.nc, 5)); S = np.zeros((self.nc, 5))
-        lib().orc_last_terms(self.h, _p(F, C.c_double), _p(E, C.c_double), _p(S, C.c_double))
+        self.L.orc_last_terms(self.h, _p(F, C.c_double), _p(E, C.c_double), _p(S, C.c_double))
         return F, E, S
 
     def export_state(self):
@@ -310,65 +335,66 @@ class Oracle:
 
     def step(self, n=1):
         for _ in range(n):
-            rc = lib().orc_step(self.h)
+            rc = self.L.orc_step(self.h)
             if rc != OK:
                 raise OracleError(f"orc_step failed with status {rc}", status=rc)
 
     def set_averaging(self, n_avg):
         """Average the steps n > n_avg from now on (Sec. 2.4(c)); n_avg < 0: off."""
-        lib().orc_set_averaging(self.h, int(n_avg))
+        self.L.orc_set_averaging(self.h, int(n_avg))
 
     def average(self):
         """(Wbar [nc][5], relative change of the last averaged step, steps averaged)."""
         Wb = np.zeros((self.nc, 5))
         r = C.c_double(0)
         n = C.c_int64(0)
-        rc = lib().orc_average(self.h, _p(Wb, C.c_double), C.byref(r), C.byref(n))
+        rc = self.L.orc_average(self.h, _p(Wb, C.c_double), C.byref(r), C.byref(n))
         if rc != OK:
             raise OracleError(f"orc_average failed with status {rc} (no step averaged yet)")
         return Wb, r.value, int(n.value)
 
     @property
     def step_index(self):
-        return int(lib().orc_step_index(self.h))
+        return int(self.L.orc_step_index(self.h))
 
     @property
     def time(self):
-        return float(lib().orc_time(self.h))
+        return float(self.L.orc_time(self.h))
 
     def stats(self):
         dt = C.c_double(0)
-        out = np.zeros(7, dtype=np.int64)
-        lib().orc_stats(self.h, C.byref(dt), _p(out, C.c_int64))
+        out = np.zeros(9, dtype=np.int64)
+        self.L.orc_stats(self.h, C.byref(dt), _p(out, C.c_int64))
         return dict(dt=dt.value, n_alive=int(out[0]), n_sampled=int(out[1]), n_collided=int(out[2]),
-                    n_escaped=int(out[3]), crossings=int(out[4]), wall_hits=int(out[5]), n_injected=int(out[6]))
+                    n_escaped=int(out[3]), crossings=int(out[4]), wall_hits=int(out[5]), n_injected=int(out[6]),
+                    rhoh_floored=int(out[7]), rhoh_negative=int(out[8]))
 
     def geometry(self):
         vol = np.zeros(self.nc)
         xc = np.zeros((self.nc, 3))
         dS = np.zeros((self.nc, 3))
-        lib().orc_geometry(self.h, _p(vol, C.c_double), _p(xc, C.c_double), _p(dS, C.c_double))
+        self.L.orc_geometry(self.h, _p(vol, C.c_double), _p(xc, C.c_double), _p(dS, C.c_double))
         return vol, xc, dS
 
     def state(self):
         W = np.zeros((self.nc, 5))
         P = np.zeros((self.nc, 5))
         nl = np.zeros(self.nc, dtype=np.int64)
-        lib().orc_get_state(self.h, _p(W, C.c_double), _p(P, C.c_double), _p(nl, C.c_int64))
+        self.L.orc_get_state(self.h, _p(W, C.c_double), _p(P, C.c_double), _p(nl, C.c_int64))
         return W, P, nl
 
     def particles(self):
-        n = int(lib().orc_n_particles(self.h))
+        n = int(self.L.orc_n_particles(self.h))
         x = np.zeros((n, 3)); u = np.zeros((n, 3)); m = np.zeros(n)
         c = np.zeros(n, dtype=np.int64); uid = np.zeros(n, dtype=np.uint64); e = np.zeros(n)
-        lib().orc_get_particles(self.h, _p(x, C.c_double), _p(u, C.c_double), _p(m, C.c_double),
+        self.L.orc_get_particles(self.h, _p(x, C.c_double), _p(u, C.c_double), _p(m, C.c_double),
                                 _p(c, C.c_int64), _p(uid, C.c_uint64), _p(e, C.c_double))
         return dict(x=x, u=u, m=m, cell=c, uid=uid, e=e)
 
     def gradients(self):
         """Limited gradients of W and of the hydro state ([nc][5][3] each) and the hydro state."""
         gW = np.zeros((self.nc, 5, 3)); gH = np.zeros((self.nc, 5, 3)); Wh = np.zeros((self.nc, 5))
-        rc = lib().orc_gradients(self.h, _p(gW, C.c_double), _p(gH, C.c_double), _p(Wh, C.c_double))
+        rc = self.L.orc_gradients(self.h, _p(gW, C.c_double), _p(gH, C.c_double), _p(Wh, C.c_double))
         if rc != OK:
             raise OracleError(f"orc_gradients failed with status {rc}")
         return gW, gH, Wh
@@ -376,7 +402,7 @@ class Oracle:
     def sample_only(self):
         """Test hook: run the cell phase and the sampling of the current step only."""
         dt = C.c_double(0)
-        rc = lib().orc_sample_only(self.h, C.byref(dt))
+        rc = self.L.orc_sample_only(self.h, C.byref(dt))
         if rc != OK:
             raise OracleError(f"orc_sample_only failed with status {rc}")
         return dt.value
@@ -386,7 +412,7 @@ class Oracle:
         and its internal energy variable after the flight with with_e."""
         x = np.array(x, dtype=np.float64); u = np.array(u, dtype=np.float64)
         c = C.c_int64(cell); nc = C.c_int64(0); nw = C.c_int64(0); ee = C.c_double(e)
-        rc = lib().orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(ee), C.byref(c), ts, -1, uid,
+        rc = self.L.orc_track(self.h, _p(x, C.c_double), _p(u, C.c_double), C.byref(ee), C.byref(c), ts, -1, uid,
                              step, C.byref(nc), C.byref(nw))
         if with_e:
             return rc, x, u, c.value, nc.value, ee.value

@@ -10,13 +10,17 @@
  * moments, interface flux, sampling, tracking and update, written from the paper's
  * equations and the readings of the paper written down in the design notes.
  *
- * Every loop is sequential, in the plain order of the scheme (paper Sec. 2.2-2.4):
+ * The phases run in the plain order of the scheme (paper Sec. 2.2-2.4):
  *   primitives and the time step (Sec. 2.4(a)), hydro/particle split (Eq. of W^p),
  *   wave flux per face (Eqs. of F^eq and F^{fr,wave}), sampling of hydro particles
  *   (Sec. 2.4(b)), free-flight times (Eq. sampling_of_free_transport_time), free transport
  *   (Sec. 2.3), particle sums and the conservative update (Eq. update_macro_variables),
  *   deletion of collided particles (the four-step particle procedure of Sec. 2.3).
  * Optionally, time averaging of W for steady states (Sec. 2.4(c)).
+ * Every sum runs sequentially in that plain order.  Built with OpenMP (a second library,
+ * for timing on many cores only), the loops whose items are independent -- the faces'
+ * fluxes, the cells' gradients and samples, the particles' flights -- run in parallel, each
+ * item writing only its own outputs; the results are the same bit for bit.
  * All arithmetic is IEEE double with libm transcendental functions; it must be compiled
  * with -ffp-contract=off and without -ffast-math.
  *
@@ -33,6 +37,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_E_ARG 1
@@ -47,7 +54,7 @@ enum { BC_SPECULAR = 0, BC_DIFFUSE = 1, BC_FARFIELD = 2, BC_PERIODIC = 3 };
 
 /* relative floor of the hydro density rho^h = rho - rho^p (see phase_cells) */
 #define RHOH_EPS 1e-12
-enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5, TAG_INT = 6, TAG_WALLINT = 7 };
+enum { TAG_TF = 1, TAG_POS = 2, TAG_VEL = 3, TAG_WALL = 4, TAG_INJECT = 5, TAG_INT = 6, TAG_WALLINT = 7, TAG_GP = 8 };
 #define KMAX 8 /* internal degrees of freedom supported (gamma = (K + 5) / (K + 3)) */
 
 /* ------------------------------------------------------------------------------------ */
@@ -358,19 +365,23 @@ static void poly_mono(int a, int b, int c, poly_t *p)
     p->c[a][b][c][0] = 1.0;
 }
 
-/* psi_k: 1, u, v, w, (u^2 + v^2 + w^2 + xi^2)/2 */
-static void poly_psi(int k, poly_t *p)
+/* psi_k: 1, u, v, w, (u^2 + v^2 + w^2 + xi^2)/2 (xi: 0 leaves the xi^2 term out, for K = 0,
+   where all its moments vanish) */
+static void poly_psi(int k, int xi, poly_t *p)
 {
     poly_clear(p);
     if (k == 0) p->c[0][0][0][0] = 1.0;
     else if (k == 1) p->c[1][0][0][0] = 1.0;
     else if (k == 2) p->c[0][1][0][0] = 1.0;
     else if (k == 3) p->c[0][0][1][0] = 1.0;
-    else { p->c[2][0][0][0] = 0.5; p->c[0][2][0][0] = 0.5; p->c[0][0][2][0] = 0.5; p->c[0][0][0][1] = 0.5; }
+    else {
+        p->c[2][0][0][0] = 0.5; p->c[0][2][0][0] = 0.5; p->c[0][0][2][0] = 0.5;
+        if (xi) p->c[0][0][0][1] = 0.5;
+    }
 }
 
 /* a . psi */
-static void poly_apsi(const double a[5], poly_t *p)
+static void poly_apsi(const double a[5], int xi, poly_t *p)
 {
     poly_clear(p);
     p->c[0][0][0][0] = a[0];
@@ -380,33 +391,47 @@ static void poly_apsi(const double a[5], poly_t *p)
     p->c[2][0][0][0] = 0.5 * a[4];
     p->c[0][2][0][0] = 0.5 * a[4];
     p->c[0][0][2][0] = 0.5 * a[4];
-    p->c[0][0][0][1] = 0.5 * a[4];
+    if (xi) p->c[0][0][0][1] = 0.5 * a[4];
 }
 
 static int g_poly_overflow = 0;
 
-static void poly_mul(const poly_t *x, const poly_t *y, poly_t *z)
+/* the nonzero terms of a polynomial: exponents and coefficients */
+typedef struct { int n; int e[PD * PD * PD * PZ][4]; double c[PD * PD * PD * PZ]; } terms_t;
+
+static void poly_terms(const poly_t *p, int nz, terms_t *t)
 {
-    poly_clear(z);
+    t->n = 0;
     for (int i = 0; i < PD; ++i)
         for (int j = 0; j < PD; ++j)
             for (int k = 0; k < PD; ++k)
-                for (int q = 0; q < PZ; ++q) {
-                    double a = x->c[i][j][k][q];
-                    if (a == 0.0) continue;
-                    for (int l = 0; l < PD; ++l)
-                        for (int m = 0; m < PD; ++m)
-                            for (int n = 0; n < PD; ++n)
-                                for (int r = 0; r < PZ; ++r) {
-                                    double b = y->c[l][m][n][r];
-                                    if (b == 0.0) continue;
-                                    if (i + l >= PD || j + m >= PD || k + n >= PD || q + r >= PZ) {
-                                        g_poly_overflow = 1;
-                                        continue;
-                                    }
-                                    z->c[i + l][j + m][k + n][q + r] += a * b;
-                                }
-                }
+                for (int q = 0; q < nz; ++q)
+                    if (p->c[i][j][k][q] != 0.0) {
+                        t->e[t->n][0] = i; t->e[t->n][1] = j; t->e[t->n][2] = k; t->e[t->n][3] = q;
+                        t->c[t->n] = p->c[i][j][k][q];
+                        ++t->n;
+                    }
+}
+
+/* z = x y, term by term (the products of x's terms in order, each with y's terms in order);
+   nz: how many powers of xi^2 the factors may hold (1 for K = 0) */
+static void poly_mul(const poly_t *x, const poly_t *y, int nz, poly_t *z)
+{
+    terms_t tx, ty;
+    poly_terms(x, nz, &tx);
+    poly_terms(y, nz, &ty);
+    poly_clear(z);
+    for (int a = 0; a < tx.n; ++a)
+        for (int b = 0; b < ty.n; ++b) {
+            const int i = tx.e[a][0] + ty.e[b][0], j = tx.e[a][1] + ty.e[b][1];
+            const int k = tx.e[a][2] + ty.e[b][2], q = tx.e[a][3] + ty.e[b][3];
+            if (i >= PD || j >= PD || k >= PD || q >= PZ) {
+#pragma omp atomic write
+                g_poly_overflow = 1;
+                continue;
+            }
+            z->c[i][j][k][q] += tx.c[a] * ty.c[b];
+        }
 }
 
 /* <p> over a unit-density Maxwellian g in the face frame, u over range (0 all, +1 u > 0,
@@ -418,11 +443,12 @@ static double poly_moment(const poly_t *p, int range, const prim_t *g)
     orc_moments(0, g->v, g->lam, mv);
     orc_moments(0, g->w, g->lam, mw);
     const double mz[PZ] = {1.0, g->K / (2.0 * g->lam), g->K * (g->K + 2.0) / (4.0 * g->lam * g->lam)};
+    const int nz = g->K > 0 ? PZ : 1;
     double s = 0.0;
     for (int i = 0; i < PD; ++i)
         for (int j = 0; j < PD; ++j)
             for (int k = 0; k < PD; ++k)
-                for (int q = 0; q < PZ; ++q)
+                for (int q = 0; q < nz; ++q)
                     if (p->c[i][j][k][q] != 0.0) s += p->c[i][j][k][q] * mu[i] * mv[j] * mw[k] * mz[q];
     return s;
 }
@@ -431,15 +457,17 @@ static double poly_moment(const poly_t *p, int range, const prim_t *g)
 static void mvec(const poly_t *pre, const double *a, int range, const prim_t *g, double out[5])
 {
     poly_t t, ap, pk, r;
+    const int xi = g->K > 0;
+    const int nz = xi ? PZ : 1;
     if (a) {
-        poly_apsi(a, &ap);
-        poly_mul(pre, &ap, &t);
+        poly_apsi(a, xi, &ap);
+        poly_mul(pre, &ap, nz, &t);
     } else {
         t = *pre;
     }
     for (int k = 0; k < 5; ++k) {
-        poly_psi(k, &pk);
-        poly_mul(&t, &pk, &r);
+        poly_psi(k, xi, &pk);
+        poly_mul(&t, &pk, nz, &r);
         out[k] = poly_moment(&r, range, g);
     }
 }
@@ -726,6 +754,7 @@ typedef struct oracle {
     /* last step statistics */
     double st_dt;
     int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits, st_injected;
+    int64_t st_floored, st_rhoh_neg; /* cells whose rho - rho^p was in (0, 1e-12 rho], or below 0 */
 } oracle_t;
 
 static int cmp_fkey(const void *a, const void *b)
@@ -1092,6 +1121,18 @@ int64_t orc_n_cells(const oracle_t *o) { return o->nc; }
 int64_t orc_n_faces(const oracle_t *o) { return o->nf; }
 int64_t orc_n_particles(const oracle_t *o) { return o->np; }
 int64_t orc_step_index(const oracle_t *o) { return o->step; }
+
+/* Threads of the OpenMP build (n > 0 sets them first); the serial build always runs one. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 double orc_time(const oracle_t *o) { return o->t; }
 
 /* reconstruction: 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan (K) */
@@ -1131,7 +1172,9 @@ int orc_set_internal_dof(oracle_t *o, int K)
    energy-exact variant (a departure from the paper, see phase_sample) */
 int orc_set_sampling(oracle_t *o, int mode)
 {
-    if (mode != 0 && mode != 1) return ORC_E_ARG;
+    if (mode < 0 || mode > 2) return ORC_E_ARG;
+    /* the first-order g_p needs the cell gradients of the reconstruction */
+    if (mode == 2 && o->recon == 0) return ORC_E_ARG;
     o->sampling = mode;
     return ORC_OK;
 }
@@ -1143,11 +1186,12 @@ void orc_geometry(const oracle_t *o, double *vol, double *xc, double *dS)
     memcpy(dS, o->dS, sizeof(double) * 3 * o->nc);
 }
 
-void orc_stats(const oracle_t *o, double *dt, int64_t out[7])
+void orc_stats(const oracle_t *o, double *dt, int64_t out[9])
 {
     *dt = o->st_dt;
     out[0] = o->st_alive; out[1] = o->st_sampled; out[2] = o->st_collided;
     out[3] = o->st_escaped; out[4] = o->st_cross; out[5] = o->st_wallhits; out[6] = o->st_injected;
+    out[7] = o->st_floored; out[8] = o->st_rhoh_neg;
 }
 
 int orc_set_state(oracle_t *o, const double *W)
@@ -1420,12 +1464,16 @@ static int phase_cells(oracle_t *o, cellq_t *q)
         if (r < dtmin) dtmin = r;
     }
     q->dt = o->cfl * dtmin;
+    o->st_floored = 0;
+    o->st_rhoh_neg = 0;
     for (int64_t c = 0; c < nc; ++c) {
         /* rho^h = rho - rho^p is a difference of two sums; below 1e-12 rho it is roundoff of
            that subtraction (e.g. free-molecular cells where the particles hold all the mass)
            and counts as an empty hydro part */
         double rh = o->W[5 * c] - o->P[5 * c] / o->vol[c];
         q->rhoh[c] = rh > RHOH_EPS * o->W[5 * c] ? rh : 0.0;
+        if (rh > 0.0 && q->rhoh[c] == 0.0) ++o->st_floored;
+        if (rh < 0.0) ++o->st_rhoh_neg;
         q->ec[c] = o->step < o->gks_steps ? 0.0 : exp(-q->dt / q->tau[c]);
     }
     return ORC_OK;
@@ -1491,6 +1539,7 @@ static void phase_grad(oracle_t *o, cellq_t *q)
         double f = q->rhoh[c] / o->W[5 * c];
         for (int k = 0; k < 5; ++k) q->Wh[5 * c + k] = f * o->W[5 * c + k];
     }
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < nc; ++c) {
         const double *xc = o->xc + 3 * c;
         double A[3][3] = {{0}}, r[10][3] = {{0}}, vmax[10], vmin[10], vc[10];
@@ -1573,6 +1622,130 @@ static void extrap(const double *Vc, const double *g, const double *xc, const do
         out[k] = Vc[k] + g[3 * k] * (x[0] - xc[0]) + g[3 * k + 1] * (x[1] - xc[1]) + g[3 * k + 2] * (x[2] - xc[2]);
 }
 
+/* a uniform point in cell c from the draw (uid, step, TAG_POS): per axis in a box; in a
+ * tetrahedron the unit cube folded onto it (Rocchini & Cignoni 2000) */
+static void place_in_cell(const oracle_t *o, int64_t c, uint64_t uid, double x[3])
+{
+    double ep[4];
+    draw4(o->seed, uid, o->step, TAG_POS, 0, o->inst, ep);
+    const double *org = o->orig + 3 * c, *Ed = o->edge + 9 * c;
+    double s = ep[0], t = ep[1], w = ep[2];
+    if (o->ctype[c] == 4) {
+        if (s + t > 1.0) { s = 1.0 - s; t = 1.0 - t; }
+        if (t + w > 1.0) {
+            double tmp = w;
+            w = 1.0 - s - t;
+            t = 1.0 - tmp;
+        } else if (s + t + w > 1.0) {
+            double tmp = w;
+            w = s + t + w - 1.0;
+            s = 1.0 - t - tmp;
+        }
+    }
+    for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+}
+
+/* First-order g_p (Sec. 2.3), the law of the hydro particles with sampling = 2.  The particles
+ * that collided by time t follow the modified equilibrium
+ *   g_p = g_0 + (t e/(1 - e) - tau) u . grad g + (t/(1 - e) - tau) d_t g,   e = exp(-t/tau).
+ * Reading: at t = dt, with g expanded to first order about the end of that interval, which is
+ * the state W^n the step starts from (g_0 + dt d_t g = g(W^n)), this is
+ *   g_p = g(W^n) [1 + alpha (sum_d u_d (a_d . psi) + A . psi)],
+ *   alpha = dt e/(1 - e) - tau = dt / expm1(dt/tau) - tau,
+ * where a_d is the micro slope of the cell's limited gradient of W along x_d (the slope solve
+ * of dW/dx_d / rho) and A the time slope from the compatibility condition
+ * <(sum_d u_d (a_d . psi) + A . psi) psi g> = 0; the correction carries no mass, momentum or
+ * energy.  alpha tends to -tau in the continuum limit (the Chapman-Enskog distribution) and
+ * to -dt/2 in the free-molecular one.
+ * Sampling by acceptance-rejection: proposals u = U + sqrt(T) X (X ~ N(0, I) by Box-Muller on
+ * the draw (uid, step, TAG_GP, 2j) of attempt j; with K > 0 the internal energy T chi^2_K from
+ * the draws (TAG_INT, 2j, 2j + 1)), accepted when eta B < 1 + alpha (...) with eta the first
+ * uniform of the draw (uid, step, TAG_GP, 2j + 1).  B bounds |1 + alpha (...)| where every
+ * normal of the proposal is at most R = 4 in size (Chapman-Enskog form of the correction,
+ * below); beyond that box, and where 1 + alpha (...) < 0, the law is clipped.  After 64
+ * rejected attempts the last proposal is kept.
+ * The bound: with the correction written as (X = (u - U)/sqrt(T), z = e/T)
+ *   X_i X_j d_j U_i - (|X|^2 + z)/(3 + K) div U + ((|X|^2 + z)/2 - (5 + K)/2) sqrt(T) X . grad ln T,
+ *   B = 1 + |alpha| (R^2 (sum_ij |d_j U_i| + |div U|)
+ *                    + ((3 + K) R^2 + 5 + K)/2 R sqrt(T) sum_j |d_j T| / T). */
+typedef struct { double a[3][5], A[5], alpha, B; } gp_t;
+
+enum { GP_ATTEMPTS = 64 };
+
+/* g_p of a cell of state W with limited gradient gW ([5][3], d W_k / d x_d), tau and dt */
+static void gp_setup(const double W[5], const double gW[15], double tau, double dt, int Kdof, gp_t *gp)
+{
+    const double rho = W[0], U[3] = {W[1] / rho, W[2] / rho, W[3] / rho}, T = temp_k(W, Kdof), lam = 0.5 / T;
+    const prim_t g = {1.0, U[0], U[1], U[2], lam, T, Kdof};
+    double bt[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+        double b[5], m[5];
+        for (int k = 0; k < 5; ++k) b[k] = gW[3 * k + d] / rho;
+        orc_slope(U[0], U[1], U[2], lam, Kdof, b, gp->a[d]);
+        poly_t pre;
+        poly_mono(d == 0, d == 1, d == 2, &pre);
+        mvec(&pre, gp->a[d], 0, &g, m);
+        for (int k = 0; k < 5; ++k) bt[k] -= m[k];
+    }
+    orc_slope(U[0], U[1], U[2], lam, Kdof, bt, gp->A);
+    gp->alpha = dt / expm1(dt / tau) - tau;
+    /* primitive gradients for the bound: d_j U_i and d_j T */
+    double sU = 0.0, divU = 0.0, sT = 0.0;
+    for (int j = 0; j < 3; ++j) {
+        double dU[3], dT;
+        for (int i = 0; i < 3; ++i) dU[i] = (gW[3 * (1 + i) + j] - U[i] * gW[j]) / rho;
+        dT = (gW[12 + j] - W[4] / rho * gW[j]) / rho - (U[0] * dU[0] + U[1] * dU[1] + U[2] * dU[2]);
+        dT = 2.0 / (3.0 + Kdof) * dT;
+        for (int i = 0; i < 3; ++i) sU += fabs(dU[i]);
+        divU += dU[j];
+        sT += fabs(dT);
+    }
+    const double R = 4.0, K = (double)Kdof;
+    gp->B = 1.0 + fabs(gp->alpha) * (R * R * (sU + fabs(divU)) + 0.5 * ((3.0 + K) * R * R + 5.0 + K) * R * sqrt(T) * sT / T);
+}
+
+/* 1 + alpha (sum_d u_d (a_d . psi) + A . psi) at velocity u and internal energy e */
+static double gp_weight(const gp_t *gp, const double u[3], double e)
+{
+    const double psi[5] = {1.0, u[0], u[1], u[2], 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + e)};
+    double s = 0.0;
+    for (int k = 0; k < 5; ++k) s += gp->A[k] * psi[k];
+    for (int d = 0; d < 3; ++d) {
+        double ad = 0.0;
+        for (int k = 0; k < 5; ++k) ad += gp->a[d][k] * psi[k];
+        s += u[d] * ad;
+    }
+    return 1.0 + gp->alpha * s;
+}
+
+/* The first-order g_p of one cell, for the tests: alpha, B, and 1 + alpha (...) at n points
+ * (u[n][3], e[n]). */
+void orc_gp_eval(const double W[5], const double gW[15], double tau, double dt, int K, int64_t n, const double *u,
+                 const double *e, double *alpha, double *B, double *w)
+{
+    gp_t gp;
+    gp_setup(W, gW, tau, dt, K, &gp);
+    *alpha = gp.alpha;
+    *B = gp.B;
+    for (int64_t i = 0; i < n; ++i) w[i] = gp_weight(&gp, u + 3 * i, e[i]);
+}
+
+/* one hydro particle from g_p (sampling = 2): its velocity and internal energy */
+static void gp_draw(const oracle_t *o, const gp_t *gp, uint64_t uid, const double U[3], double T, double u[3],
+                    double *e)
+{
+    for (int j = 0; j < GP_ATTEMPTS; ++j) {
+        double ev[4], ea[4];
+        draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j, o->inst, ev);
+        double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
+        double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
+        for (int d = 0; d < 3; ++d) u[d] = U[d] + sqrt(T) * X[d];
+        *e = o->K > 0 ? internal_energy(o->seed, uid, o->step, TAG_INT, 2u * (uint32_t)j, o->inst, o->K, T) : 0.0;
+        draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j + 1u, o->inst, ea);
+        if (ea[0] * gp->B < gp_weight(gp, u, *e)) return;
+    }
+}
+
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
  * ones.  With K > 0 each particle also gets its internal energy variable e = T |X'|^2 from
  * K standard normals of its own (Sec. 2.3: sampled from the temperature and K).
@@ -1588,22 +1761,54 @@ static void extrap(const double *Vc, const double *g, const double *xc, const do
  * S (if given) receives the sums of phi over the new particles. */
 static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsampled)
 {
-    *nsampled = 0;
-    for (int64_t c = 0; c < o->nc; ++c) {
+    /* the counts first, so that every cell knows where its particles go; the cells are then
+       sampled independently (in parallel in the OpenMP build) */
+    const int64_t nc = o->nc, np0 = o->np;
+    int64_t *first = (int64_t *)xcalloc(nc + 1, sizeof(int64_t));
+    first[0] = np0;
+    for (int64_t c = 0; c < nc; ++c) {
         double rhohp = q->ec[c] * q->rhoh[c];
         double rhop = o->P[5 * c] / o->vol[c];
-        if (!(rhohp > 0.0) || !(rhop + rhohp > 0.0)) continue;
-        double r = (0.5 * o->n_ref) * (rhohp / (rhop + rhohp));
-        int64_t ns = 2 * (int64_t)ceil(r);
-        int64_t need = (int64_t)o->n_min - o->nleft[c];
-        if (need > 0) {
-            int64_t ne = 2 * ((need + 1) / 2);
-            if (ne > ns) ns = ne;
+        int64_t ns = 0;
+        if (rhohp > 0.0 && rhop + rhohp > 0.0) {
+            double r = (0.5 * o->n_ref) * (rhohp / (rhop + rhohp));
+            ns = 2 * (int64_t)ceil(r);
+            int64_t need = (int64_t)o->n_min - o->nleft[c];
+            if (need > 0) {
+                int64_t ne = 2 * ((need + 1) / 2);
+                if (ne > ns) ns = ne;
+            }
+            if (ns > (1 << 20)) { free(first); return ORC_E_CAPACITY; }
         }
-        if (ns > (1 << 20)) return ORC_E_CAPACITY;
+        first[c + 1] = first[c] + ns;
+    }
+    if (reserve(o, first[nc])) { free(first); return ORC_E_CAPACITY; }
+    o->np = first[nc];
+    *nsampled = first[nc] - np0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < nc; ++c) {
+        const int64_t ns = first[c + 1] - first[c];
+        if (ns == 0) continue;
+        double rhohp = q->ec[c] * q->rhoh[c];
         double msam = rhohp * o->vol[c] / ns;
-        if (reserve(o, o->np + ns)) return ORC_E_CAPACITY;
         double sT = sqrt(q->T[c]);
+        if (o->sampling == 2) {
+            gp_t gp;
+            gp_setup(o->W + 5 * c, q->gW + 15 * c, q->tau[c], q->dt, o->K, &gp);
+            for (int64_t k = 0; k < ns; ++k) {
+                const int64_t i = first[c] + k;
+                const uint64_t uid = orc_make_uid(0, o->step, c, k);
+                double e = 0.0;
+                gp_draw(o, &gp, uid, q->U + 3 * c, q->T[c], o->pu + 3 * i, &e);
+                place_in_cell(o, c, uid, o->px + 3 * i);
+                o->pm[i] = msam;
+                o->pc[i] = c;
+                o->pid[i] = uid;
+                o->pe[i] = e;
+                if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i, e);
+            }
+            continue;
+        }
         if (o->sampling == 1) {
             /* energy-exact pairs: the pairs already carry the momentum rho^hp U exactly; one
                factor on every thermal deviation of the cell, sqrt(3 N_pairs / sum_j |X_j|^2),
@@ -1629,33 +1834,16 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
             fint = (double)o->K * (double)ns / se;
         }
         for (int64_t k = 0; k < ns; ++k) {
-            int64_t i = o->np++;
+            int64_t i = first[c] + k;
             uint64_t uid = orc_make_uid(0, o->step, c, k);
             uint64_t puid = orc_make_uid(0, o->step, c, k & ~(int64_t)1);
-            double ev[4], ep[4];
+            double ev[4];
             draw4(o->seed, puid, o->step, TAG_VEL, 0, o->inst, ev);
             double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
             double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
             double sg = (k & 1) ? -1.0 : 1.0;
             for (int d = 0; d < 3; ++d) o->pu[3 * i + d] = q->U[3 * c + d] + sg * (sT * X[d]);
-            draw4(o->seed, uid, o->step, TAG_POS, 0, o->inst, ep);
-            const double *org = o->orig + 3 * c, *Ed = o->edge + 9 * c;
-            double s = ep[0], t = ep[1], w = ep[2];
-            if (o->ctype[c] == 4) {
-                /* uniform point in a tetrahedron: fold the unit cube (Rocchini & Cignoni 2000) */
-                if (s + t > 1.0) { s = 1.0 - s; t = 1.0 - t; }
-                if (t + w > 1.0) {
-                    double tmp = w;
-                    w = 1.0 - s - t;
-                    t = 1.0 - tmp;
-                } else if (s + t + w > 1.0) {
-                    double tmp = w;
-                    w = s + t + w - 1.0;
-                    s = 1.0 - t - tmp;
-                }
-            }
-            for (int d = 0; d < 3; ++d)
-                o->px[3 * i + d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+            place_in_cell(o, c, uid, o->px + 3 * i);
             o->pm[i] = msam;
             o->pc[i] = c;
             o->pid[i] = uid;
@@ -1667,8 +1855,8 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
             o->pe[i] = e;
             if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i, e);
         }
-        *nsampled += ns;
     }
+    free(first);
     return ORC_OK;
 }
 
@@ -1798,6 +1986,7 @@ int orc_sample_only(oracle_t *o, double *dt)
     cellq_t q = {0};
     int st = phase_cells(o, &q);
     int64_t ns = 0;
+    if (st == ORC_OK && o->recon) phase_grad(o, &q);
     if (st == ORC_OK) st = phase_sample(o, &q, NULL, &ns);
     *dt = q.dt;
     o->st_sampled = ns;
@@ -1855,6 +2044,7 @@ int orc_step(oracle_t *o)
     const int gks = o->step < o->gks_steps;
 
     /* wave flux over every face, oriented owner -> neighbour, times the face area */
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t f = 0; f < nf; ++f) {
         int64_t c = o->fown[f], nb = o->fnb[f];
         const double *n = o->fn + 3 * f;
@@ -1914,10 +2104,17 @@ int orc_step(oracle_t *o)
 
     /* free-flight time of every old particle t_f = min(-tau ln eta, dt), with tau of the cell it
        starts in; new particles fly for dt.  Stream, sum, and delete the collided and escaped. */
-    int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0;
-    for (int64_t i = 0; i < o->np; ++i) {
+    /* each particle's flight is independent of the others: tracked first (in parallel in the
+       OpenMP build), then summed and compacted in particle order */
+    const int64_t np = o->np;
+    int8_t *prc = (int8_t *)xcalloc(np > 0 ? np : 1, sizeof(int8_t));
+    int8_t *pcol = (int8_t *)xcalloc(np > 0 ? np : 1, sizeof(int8_t));
+    int64_t *pcross = (int64_t *)xcalloc(np > 0 ? np : 1, sizeof(int64_t));
+    int64_t *pwall = (int64_t *)xcalloc(np > 0 ? np : 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < np; ++i) {
         double ts = dt;
-        int collided = 0, entry0 = -1;
+        int entry0 = -1;
         if (i >= ninj_start) {
             ts = tin[i - ninj_start];
             entry0 = ein[i - ninj_start];
@@ -1926,17 +2123,22 @@ int orc_step(oracle_t *o)
             double eta[4];
             draw4(o->seed, o->pid[i], o->step, TAG_TF, 0, o->inst, eta);
             double tf = -q.tau[o->pc[i]] * log(eta[0]);
-            if (tf < dt) { ts = tf; collided = 1; }
+            if (tf < dt) { ts = tf; pcol[i] = 1; }
         }
-        int64_t cross = 0;
-        int rc = orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pe + i, o->pc + i, ts, entry0, o->pid[i], o->step,
-                           &cross, &nwall);
-        ncross_tot += cross;
-        if (rc < 0) { status = ORC_E_LOST; goto done; }
-        if (rc == 1) { ++nesc; continue; }
+        prc[i] = (int8_t)orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pe + i, o->pc + i, ts, entry0, o->pid[i],
+                                   o->step, pcross + i, pwall + i);
+    }
+    int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0;
+    for (int64_t i = 0; i < np; ++i) {
+        ncross_tot += pcross[i];
+        nwall += pwall[i];
+        if (prc[i] < 0) status = ORC_E_LOST;
+    }
+    for (int64_t i = 0; i < np && status == ORC_OK; ++i) {
+        if (prc[i] == 1) { ++nesc; continue; }
         int64_t c = o->pc[i];
         add_phi(E + 5 * c, o->pm[i], o->pu + 3 * i, o->pe[i]);
-        if (collided) { ++ncoll; continue; }
+        if (pcol[i]) { ++ncoll; continue; }
         add_phi(Pn + 5 * c, o->pm[i], o->pu + 3 * i, o->pe[i]);
         nl[c] += 1;
         if (keep != i) {
@@ -1948,6 +2150,8 @@ int orc_step(oracle_t *o)
         }
         ++keep;
     }
+    free(prc); free(pcol); free(pcross); free(pwall);
+    if (status != ORC_OK) goto done;
     o->np = keep;
 
     /* conservative update: W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega, where E sums phi

@@ -127,7 +127,7 @@ struct Carver {
 };
 
 // Lay the workspace out; with base == nullptr only the size is computed.
-size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, Dev &D, char *base) {
+size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, int K, Dev &D, char *base) {
     Carver C{base};
     D.ip = C.take<ugkwp::InstP>((size_t)n_inst);
     D.is = C.take<ugkwp::InstS>((size_t)n_inst);
@@ -188,11 +188,15 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
         P.rec = nullptr;
         P.rec32 = nullptr;
         P.m32 = nullptr;
+        P.e64 = nullptr;
+        P.e32 = nullptr;
         if (prec == 1) {
             P.rec32 = C.take<ugkwp::PRec32>((size_t)cap);
             P.m32 = C.take<float>((size_t)cap);
+            if (K > 0) P.e32 = C.take<float>((size_t)cap);
         } else {
             P.rec = C.take<ugkwp::PRec>((size_t)cap);
+            if (K > 0) P.e64 = C.take<double>((size_t)cap);
         }
         P.cell = C.take<int32_t>((size_t)cap);
     }
@@ -202,9 +206,18 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     return (C.off + 255) & ~size_t(255);
 }
 
+// internal degrees of freedom of gamma = (K + 5)/(K + 3), or -1 if gamma is not of that form
+int internal_dof(double gamma) {
+    if (!(gamma > 1.0)) return -1;
+    const double K = 2.0 / (gamma - 1.0) - 3.0;
+    const long Ki = std::lround(K);
+    if (!(std::fabs(K - (double)Ki) < 1e-9) || Ki < 0 || Ki > ugkwp::kMaxK) return -1;
+    return (int)Ki;
+}
+
 int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::string &err) {
-    if (!(std::fabs(p.gamma - 5.0 / 3.0) < 1e-12)) {
-        err = "params: only the monatomic gas (gamma = 5/3) is implemented";
+    if (internal_dof(p.gamma) < 0) {
+        err = "params: gamma must be (K + 5)/(K + 3) for an integer 0 <= K <= 8 (5/3 monatomic, 7/5 diatomic)";
         return UGKWP_E_ARG;
     }
     if (!(p.mu_ref > 0.0) || !std::isfinite(p.omega) || !(p.cfl > 0.0 && p.cfl <= 1.0) || !(p.c2 >= 0.0)) {
@@ -261,6 +274,10 @@ int32_t prepare_batch(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p
         }
         if (st == UGKWP_OK && p[k].precision != p[0].precision) {
             err = "params: every instance of a batch must use the same precision";
+            st = UGKWP_E_ARG;
+        }
+        if (st == UGKWP_OK && internal_dof(p[k].gamma) != internal_dof(p[0].gamma)) {
+            err = "params: every instance of a batch must have the same gamma (internal degrees of freedom)";
             st = UGKWP_E_ARG;
         }
         if (st != UGKWP_OK) {
@@ -350,7 +367,7 @@ int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_p
     Dev D{};
     bool recon = false;
     for (int32_t k = 0; k < n_inst; ++k) recon = recon || p[k].recon != 0;
-    *bytes = carve(H, n_inst, cap, p[0].precision, recon, D, nullptr);
+    *bytes = carve(H, n_inst, cap, p[0].precision, recon, internal_dof(p[0].gamma), D, nullptr);
     return UGKWP_OK;
 }
 
@@ -379,7 +396,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         recon_any = recon_any || p[k].recon != 0;
         recon_all = recon_all && p[k].recon != 0;
     }
-    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, recon_any, D, ctx->ws);
+    const int K = internal_dof(p[0].gamma);
+    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, recon_any, K, D, ctx->ws);
     if (ws_bytes < need) {
         delete ctx;
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -397,6 +415,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
     D.cap = cap;
     D.prec = p[0].precision;
+    D.K = K;
     std::vector<ugkwp::InstP> ip((size_t)n_inst);
     std::vector<int32_t> cinst;
     if (n_inst > 1) cinst.resize((size_t)H.nc);
@@ -492,7 +511,7 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     for (size_t c = 0; c < nc; ++c) {
         const double *w = W0 + 5 * c;
         double rho = w[0];
-        double T = (2.0 / 3.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
+        double T = (2.0 / (3.0 + ctx->D.K)) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
         if (!(rho > 0.0) || !(T > 0.0) || !std::isfinite(rho) || !std::isfinite(T))
             return fail(ctx, UGKWP_E_NONPHYS, "init_state: cell " + std::to_string(c) + " has rho <= 0 or T <= 0");
     }
@@ -680,7 +699,8 @@ int32_t ugkwp_particle_count(ugkwp_ctx *ctx, int64_t *n) {
     return UGKWP_OK;
 }
 
-int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell, uint64_t *uid) {
+int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, int32_t *cell, uint64_t *uid,
+                               double *e) {
     if (!ctx) return fail(ctx, UGKWP_E_ARG, "bad argument");
     int64_t n = 0;
     int32_t st = ugkwp_particle_count(ctx, &n);
@@ -700,6 +720,13 @@ int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, 
             if (uid) uid[i] = rec[i].uid;
         }
         if (cell) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (e && P.e32) {
+            std::vector<float> ee((size_t)n);
+            HIPCHK(ctx, hipMemcpy(ee.data(), P.e32, n * sizeof(float), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) e[i] = ee[i];
+        } else if (e) {
+            for (int64_t i = 0; i < n; ++i) e[i] = 0.0;
+        }
     } else if (n > 0) {
         std::vector<ugkwp::PRec> rec((size_t)n);
         HIPCHK(ctx, hipMemcpy(rec.data(), P.rec, n * sizeof(ugkwp::PRec), hipMemcpyDeviceToHost));
@@ -712,6 +739,11 @@ int32_t ugkwp_export_particles(ugkwp_ctx *ctx, double *x, double *u, double *m, 
             if (uid) uid[i] = rec[i].uid;
         }
         if (cell) HIPCHK(ctx, hipMemcpy(cell, P.cell, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (e && P.e64) {
+            HIPCHK(ctx, hipMemcpy(e, P.e64, n * sizeof(double), hipMemcpyDeviceToHost));
+        } else if (e) {
+            for (int64_t i = 0; i < n; ++i) e[i] = 0.0;
+        }
     }
     return UGKWP_OK;
 }
@@ -749,7 +781,7 @@ int32_t ugkwp_export_state(ugkwp_ctx *ctx, double *W, double *P, int64_t *step, 
 
 int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int64_t n, const double *x,
                            const double *u, const double *m, const int32_t *cell, const uint64_t *uid,
-                           const int64_t *step, const double *t) {
+                           const double *e, const int64_t *step, const double *t) {
     if (!ctx || !W || !P || !step || !t || n < 0 || (n > 0 && (!x || !u || !m || !cell || !uid)))
         return fail(ctx, UGKWP_E_ARG, "import_state: null argument or negative particle count");
     Dev &D = ctx->D;
@@ -758,7 +790,7 @@ int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int
     for (size_t c = 0; c < nc; ++c) {
         const double *w = W + 5 * c;
         const double rho = w[0];
-        const double T = (2.0 / 3.0) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
+        const double T = (2.0 / (3.0 + D.K)) * (w[4] - 0.5 * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) / rho) / rho;
         if (!(rho > 0.0) || !(T > 0.0) || !std::isfinite(rho) || !std::isfinite(T))
             return fail(ctx, UGKWP_E_NONPHYS, "import_state: cell " + std::to_string(c) + " has rho <= 0 or T <= 0");
     }
@@ -804,6 +836,11 @@ int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int
             }
             HIPCHK(ctx, up(pa.rec32, rec32, s));
             HIPCHK(ctx, up(pa.m32, m32, s));
+            if (pa.e32) {
+                std::vector<float> e32((size_t)n);
+                for (int64_t i = 0; i < n; ++i) e32[i] = e ? (float)e[i] : 0.0f;
+                HIPCHK(ctx, up(pa.e32, e32, s));
+            }
         } else {
             rec.resize((size_t)n);
             for (int64_t i = 0; i < n; ++i) {
@@ -815,6 +852,11 @@ int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int
                 rec[i].uid = uid[i];
             }
             HIPCHK(ctx, up(pa.rec, rec, s));
+            if (pa.e64) {
+                std::vector<double> e64((size_t)n);
+                for (int64_t i = 0; i < n; ++i) e64[i] = e ? e[i] : 0.0;
+                HIPCHK(ctx, up(pa.e64, e64, s));
+            }
         }
         HIPCHK(ctx, hipMemcpyAsync(pa.cell, cell, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     }

@@ -14,9 +14,13 @@ enum : uint32_t {
     kErrCellCount = 8u,  // more than 2^20 particles sampled in one cell (particle-id field)
 };
 
-enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5 };
+enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5, kTagInt = 6, kTagWallInt = 7 };
 
-// bucket key flag: the particle stays collisionless in the cell it started in
+// internal degrees of freedom supported: gamma = (K + 5)/(K + 3), 0 <= K <= kMaxK
+constexpr int kMaxK = 8;
+
+// bucket key flag: the particle flew collisionless for the whole step without meeting a face
+// (so it ends in the cell it started in, at x + u dt; its record is not rewritten)
 constexpr int32_t kStayBit = 1 << 30;
 
 // the neighbour's local face of a slot whose face is periodic: the neighbour's local face lf2
@@ -111,6 +115,8 @@ struct Particles {
     PRec32 *rec32;  // FP32 form
     float *m32;     // FP32 form
     int32_t *cell;
+    double *e64;    // internal energy variable |xi|^2 of each particle (K > 0; FP64 form)
+    float *e32;     // the same in the FP32 form
 };
 
 struct Dev {
@@ -142,6 +148,7 @@ struct Dev {
     const uint8_t *bflf;    // [n_bfaces]  local face of an input boundary face
     // parameters
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
+    int32_t K, pad2;        // internal degrees of freedom of the gas (every instance)
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
     const InstP *ip;        // [n_inst]

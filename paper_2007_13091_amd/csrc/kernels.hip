@@ -133,7 +133,14 @@ __device__ __forceinline__ uint64_t make_uid(long long step, int cell, long long
 template <typename R>
 struct Prim {
     R rho, un, v, w, lam, T;
+    int K;  // internal degrees of freedom (Sec. 2.1): <xi^2> = K / (2 lambda)
 };
+
+// temperature of a conservative state with K internal degrees of freedom (R = 1):
+// rho E = rho |U|^2 / 2 + (3 + K) rho T / 2
+__device__ __forceinline__ double temp_k(const double W[5], int K) {
+    return (2.0 / (3.0 + K)) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+}
 
 template <typename R>
 __device__ __forceinline__ void moments4(int rng, R U, R lam, R m[4]) {
@@ -152,10 +159,10 @@ __device__ __forceinline__ void moments4(int rng, R U, R lam, R m[4]) {
     m[3] = U * m[2] + (R)2 / ((R)2 * lam) * m[1];
 }
 
-// <psi> (H) and <u_n psi> (G) of a unit-density Maxwellian; psi = (1, u_n, v, w, |u|^2/2)
+// <psi> (H) and <u_n psi> (G) of a unit-density Maxwellian; psi = (1, u_n, v, w, (|u|^2 + xi^2)/2)
 template <typename R>
 __device__ __forceinline__ void psi_moments(const Prim<R> &p, const R m[4], R H[5], R G[5]) {
-    R tr = p.v * p.v + p.w * p.w + (R)1 / p.lam;
+    R tr = p.v * p.v + p.w * p.w + (R)1 / p.lam + (R)p.K / ((R)2 * p.lam);
     H[0] = m[0];
     H[1] = m[1];
     H[2] = m[0] * p.v;
@@ -187,10 +194,10 @@ __device__ __forceinline__ void face_frame(const R n[3], R t1[3], R t2[3]) {
 
 // primitives of a cell state in the face frame; the energy -> temperature recovery is FP64
 template <typename R>
-__device__ __forceinline__ Prim<R> to_frame(const double W[5], const R n[3], const R t1[3], const R t2[3]) {
+__device__ __forceinline__ Prim<R> to_frame(const double W[5], const R n[3], const R t1[3], const R t2[3], int K) {
     Prim<R> p;
     const double U = W[1] / W[0], V = W[2] / W[0], Z = W[3] / W[0];
-    const double T = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
+    const double T = temp_k(W, K);
     const R u = (R)U, v = (R)V, z = (R)Z;
     p.rho = (R)W[0];
     p.un = u * n[0] + v * n[1] + z * n[2];
@@ -198,6 +205,7 @@ __device__ __forceinline__ Prim<R> to_frame(const double W[5], const R n[3], con
     p.w = u * t2[0] + v * t2[1] + z * t2[2];
     p.T = (R)T;
     p.lam = (R)1 / ((R)2 * p.T);
+    p.K = K;
     return p;
 }
 
@@ -278,7 +286,8 @@ __device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R 
     z.un = W0[1] / W0[0];
     z.v = W0[2] / W0[0];
     z.w = W0[3] / W0[0];
-    z.T = ((R)2 / (R)3) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.K = l.K;
+    z.T = ((R)2 / (R)(3 + z.K)) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
     z.lam = (R)1 / ((R)2 * z.T);
     R pl = l.rho * l.T, pr = r.rho * r.T;
     R tau = mu_ref * pow(z.T, omega) / (z.rho * z.T) + c2 * (fabs(pl - pr) / (pl + pr)) * dt;
@@ -383,7 +392,7 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
             U = m0 / rho;
             V = m1 / rho;
             Z = m2 / rho;
-            T = (2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
+            T = (2.0 / (3.0 + D.K)) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
             bad = !(T > 0.0) || !isfinite(T);
         }
         if (bad) {
@@ -504,6 +513,7 @@ __device__ __forceinline__ void diffuse_flux(const Prim<R> &l, R h, R tau_c, con
     w.w = uw[0] * t2[0] + uw[1] * t2[1] + uw[2] * t2[2];
     w.T = (R)bc.Tw;
     w.lam = (R)1 / ((R)2 * w.T);
+    w.K = l.K;
     R mw[4], Hw[5], Gw[5];
     moments4<R>(-1, w.un, w.lam, mw);
     psi_moments<R>(w, mw, Hw, Gw);
@@ -536,13 +546,13 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
     double Wl[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) Wl[k] = D.W[k * nc + c];
-    const Prim<R> l = to_frame<R>(Wl, n, t1, t2);
+    const Prim<R> l = to_frame<R>(Wl, n, t1, t2, D.K);
     R Ff[5];
     if (nb >= 0) {
         double Wr[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) Wr[k] = D.W[k * nc + nb];
-        const Prim<R> r = to_frame<R>(Wr, n, t1, t2);
+        const Prim<R> r = to_frame<R>(Wr, n, t1, t2, D.K);
         flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, gks, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
@@ -560,7 +570,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
             diffuse_flux<R>(l, (R)D.rhoh[c], (R)D.tau[c], n, t1, t2, bc, dt, gks, Ff);
         } else {
             // far field: the free stream as the right state (hydro density = its density)
-            const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2);
+            const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2, D.K);
             flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, gks, Ff);
         }
     }
@@ -628,27 +638,39 @@ __device__ __forceinline__ void moments_n(int rng, R U, R lam, R m[N]) {
     for (int k = 0; k + 2 < N; ++k) m[k + 2] = U * m[k + 1] + (R)(k + 1) / ((R)2 * lam) * m[k];
 }
 
-// normal moments over a range to order 6, tangential ones over the full line to order 5
+// normal moments over a range to order 6, tangential ones over the full line to order 5, and
+// of the K internal components: x2 = <xi^2> = K / (2 lambda), x4 = <xi^4> = K (K + 2) / (4 lambda^2)
 template <typename R>
 struct Mom3 {
     R u[7], v[6], w[6];
+    R x2, x4;
 };
 template <typename R>
 __device__ __forceinline__ void mom3(int rng, const Prim<R> &g, Mom3<R> &M) {
     moments_n<R, 7>(rng, g.un, g.lam, M.u);
     moments_n<R, 6>(0, g.v, g.lam, M.v);
     moments_n<R, 6>(0, g.w, g.lam, M.w);
+    M.x2 = (R)g.K / ((R)2 * g.lam);
+    M.x4 = (R)(g.K * (g.K + 2)) / ((R)4 * g.lam * g.lam);
 }
 template <int I, int J, int K, typename R>
 __device__ __forceinline__ R mono(const Mom3<R> &M) {
     return M.u[I] * M.v[J] * M.w[K];
 }
-// < u^I v^J w^K (a . psi) >
+// < u^I v^J w^K (a . psi) >, a . psi = a0 + a1 u + a2 v + a3 w + a4 (u^2 + v^2 + w^2 + xi^2) / 2
 template <int I, int J, int K, typename R>
 __device__ __forceinline__ R amom(const Mom3<R> &M, const R a[5]) {
     return a[0] * mono<I, J, K>(M) + a[1] * mono<I + 1, J, K>(M) + a[2] * mono<I, J + 1, K>(M) +
            a[3] * mono<I, J, K + 1>(M) +
-           (R)0.5 * a[4] * (mono<I + 2, J, K>(M) + mono<I, J + 2, K>(M) + mono<I, J, K + 2>(M));
+           (R)0.5 * a[4] * (mono<I + 2, J, K>(M) + mono<I, J + 2, K>(M) + mono<I, J, K + 2>(M) + mono<I, J, K>(M) * M.x2);
+}
+// < u^I v^J w^K (a . psi) xi^2 > (the xi components are independent of u, v, w)
+template <int I, int J, int K, typename R>
+__device__ __forceinline__ R amom_xi(const Mom3<R> &M, const R a[5]) {
+    return M.x2 * (a[0] * mono<I, J, K>(M) + a[1] * mono<I + 1, J, K>(M) + a[2] * mono<I, J + 1, K>(M) +
+                   a[3] * mono<I, J, K + 1>(M) +
+                   (R)0.5 * a[4] * (mono<I + 2, J, K>(M) + mono<I, J + 2, K>(M) + mono<I, J, K + 2>(M))) +
+           (R)0.5 * a[4] * mono<I, J, K>(M) * M.x4;
 }
 // out_k = < u^P v^Q w^S (a . psi) psi_k >
 template <int P, int Q, int S, typename R>
@@ -657,7 +679,8 @@ __device__ __forceinline__ void gvec(const Mom3<R> &M, const R a[5], R out[5]) {
     out[1] = amom<P + 1, Q, S>(M, a);
     out[2] = amom<P, Q + 1, S>(M, a);
     out[3] = amom<P, Q, S + 1>(M, a);
-    out[4] = (R)0.5 * (amom<P + 2, Q, S>(M, a) + amom<P, Q + 2, S>(M, a) + amom<P, Q, S + 2>(M, a));
+    out[4] = (R)0.5 * (amom<P + 2, Q, S>(M, a) + amom<P, Q + 2, S>(M, a) + amom<P, Q, S + 2>(M, a) +
+                       amom_xi<P, Q, S>(M, a));
 }
 // out_k = < u psi_k >
 template <typename R>
@@ -666,20 +689,21 @@ __device__ __forceinline__ void uvec(const Mom3<R> &M, R out[5]) {
     out[1] = mono<2, 0, 0>(M);
     out[2] = mono<1, 1, 0>(M);
     out[3] = mono<1, 0, 1>(M);
-    out[4] = (R)0.5 * (mono<3, 0, 0>(M) + mono<1, 2, 0>(M) + mono<1, 0, 2>(M));
+    out[4] = (R)0.5 * (mono<3, 0, 0>(M) + mono<1, 2, 0>(M) + mono<1, 0, 2>(M) + mono<1, 0, 0>(M) * M.x2);
 }
 
-// micro slope a with <(a . psi) psi> = b over the unit Maxwellian g (K = 0):
-//   R = 2 b5 - (|U|^2 + 3/(2 lambda)) b1, R_i = b_{i+1} - U_i b1, a5 = 4 lambda^2/3 (R - 2 U.R_i),
-//   a_{i+1} = 2 lambda R_i - U_i a5, a1 = b1 - U.a_{2..4} - a5 (|U|^2 + 3/(2 lambda))/2
+// micro slope a with <(a . psi) psi> = b over the unit Maxwellian g, N = 3 + K:
+//   R = 2 b5 - (|U|^2 + N/(2 lambda)) b1, R_i = b_{i+1} - U_i b1, a5 = 4 lambda^2/N (R - 2 U.R_i),
+//   a_{i+1} = 2 lambda R_i - U_i a5, a1 = b1 - U.a_{2..4} - a5 (|U|^2 + N/(2 lambda))/2
 template <typename R>
 __device__ __forceinline__ void slope(const Prim<R> &g, const R b[5], R a[5]) {
     const R U0 = g.un, U1 = g.v, U2 = g.w, lam = g.lam;
+    const R N = (R)(3 + g.K);
     const R q2 = U0 * U0 + U1 * U1 + U2 * U2;
-    const R th = (R)3 / ((R)2 * lam);
+    const R th = N / ((R)2 * lam);
     const R Rr = (R)2 * b[4] - (q2 + th) * b[0];
     const R R0 = b[1] - U0 * b[0], R1 = b[2] - U1 * b[0], R2 = b[3] - U2 * b[0];
-    a[4] = ((R)4 * lam * lam / (R)3) * (Rr - (R)2 * (U0 * R0 + U1 * R1 + U2 * R2));
+    a[4] = ((R)4 * lam * lam / N) * (Rr - (R)2 * (U0 * R0 + U1 * R1 + U2 * R2));
     a[1] = (R)2 * lam * R0 - U0 * a[4];
     a[2] = (R)2 * lam * R1 - U1 * a[4];
     a[3] = (R)2 * lam * R2 - U2 * a[4];
@@ -749,7 +773,8 @@ __device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref
     z.un = W0[1] / W0[0];
     z.v = W0[2] / W0[0];
     z.w = W0[3] / W0[0];
-    z.T = ((R)2 / (R)3) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
+    z.K = L.g.K;
+    z.T = ((R)2 / (R)(3 + z.K)) * (W0[4] - (R)0.5 * (W0[1] * W0[1] + W0[2] * W0[2] + W0[3] * W0[3]) / W0[0]) / W0[0];
     z.lam = (R)1 / ((R)2 * z.T);
     mom3<R>(0, z, M0);
     R abar[3][5];
@@ -815,10 +840,6 @@ __device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref
     }
 }
 
-// temperature of a conservative state (R = 1, K = 0)
-__device__ __forceinline__ double temp_of(const double W[5]) {
-    return (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / W[0]) / W[0];
-}
 
 // Gradients for second order, one cell per thread, FP64 in both forms: the unweighted
 // least-squares gradient over the face neighbours of the 5 components of W and of the hydro
@@ -877,7 +898,7 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
             } else {
                 const double rho = vc[0];
                 const double U[3] = {vc[1] / rho, vc[2] / rho, vc[3] / rho};
-                const double T = temp_of(vc);
+                const double T = temp_k(vc, D.K);
                 double Ug[3];
                 if (b.type == 0) {
                     const double un = U[0] * nn[0] + U[1] * nn[1] + U[2] * nn[2];
@@ -890,7 +911,7 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
                 vj[0] = rho;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) vj[1 + d] = rho * Ug[d];
-                vj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 1.5 * rho * T;
+                vj[4] = 0.5 * rho * (Ug[0] * Ug[0] + Ug[1] * Ug[1] + Ug[2] * Ug[2]) + 0.5 * (3.0 + D.K) * rho * T;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) vj[5 + k] = fc * vj[k];
             }
@@ -956,9 +977,9 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
         for (int k = 0; k < 10; ++k)
             wf[k] = vc[k] + g[k][0] * (lfx[3 * lf] - xc[0]) + g[k][1] * (lfx[3 * lf + 1] - xc[1]) +
                     g[k][2] * (lfx[3 * lf + 2] - xc[2]);
-        if (!(wf[0] > 0.0) || !(temp_of(wf) > 0.0)) ok = false;
+        if (!(wf[0] > 0.0) || !(temp_k(wf, D.K) > 0.0)) ok = false;
         if (!(wf[5] >= 0.0)) ok = false;
-        if (wf[5] > 0.0 && !(temp_of(wf + 5) > 0.0)) ok = false;
+        if (wf[5] > 0.0 && !(temp_k(wf + 5, D.K) > 0.0)) ok = false;
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k)
@@ -985,13 +1006,14 @@ __device__ __forceinline__ void extrap(const Dev &D, int c, const double x[3], d
 template <typename R>
 __device__ __forceinline__ void make_side(const Dev &D, int c, const double W[5], const double Wh[5], const R n[3],
                                           const R t1[3], const R t2[3], Side2<R> &S) {
-    S.g = to_frame<R>(W, n, t1, t2);
+    S.g = to_frame<R>(W, n, t1, t2, D.K);
     frame_derivs<R>(D.gW, D.nc, c, n, t1, t2, S.dW);
     if (Wh[0] > 0.0) {
-        S.h = to_frame<R>(Wh, n, t1, t2);
+        S.h = to_frame<R>(Wh, n, t1, t2, D.K);
         frame_derivs<R>(D.gH, D.nc, c, n, t1, t2, S.dWh);
     } else {
         S.h.rho = (R)0;
+        S.h.K = D.K;
     }
 }
 
@@ -1048,7 +1070,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
         } else if (bc.type == 1) {
             diffuse_flux<R>(L.g, (R)Whl[0], (R)D.tau[c], n, t1, t2, bc, dt, gks, Ff);
         } else {
-            Rs.g = to_frame<R>(bc.Winf, n, t1, t2);
+            Rs.g = to_frame<R>(bc.Winf, n, t1, t2, D.K);
             Rs.h = Rs.g;
 #pragma unroll
             for (int d = 0; d < 3; ++d)
@@ -1083,14 +1105,38 @@ __device__ __forceinline__ void store_new(const Particles &pa, long long i, cons
 
 // phi = m (1, u, |u|^2 / 2) of a stored particle, accumulated in FP64
 template <typename R>
-__device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3]) {
-    const double m = (double)m_, u0 = (double)u_[0], u1 = (double)u_[1], u2 = (double)u_[2];
+__device__ __forceinline__ void add_phi(double acc[5], R m_, const R u_[3], R e_ = (R)0) {
+    const double m = (double)m_, u0 = (double)u_[0], u1 = (double)u_[1], u2 = (double)u_[2], e = (double)e_;
     acc[0] += m;
     acc[1] += m * u0;
     acc[2] += m * u1;
     acc[3] += m * u2;
-    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+    acc[4] += m * (0.5 * (u0 * u0 + u1 * u1 + u2 * u2 + e));
 }
+
+// internal energy variable e = T |X|^2 of a particle in equilibrium at temperature T: the first K
+// of the standard normals that Box-Muller makes of the draws (seed, uid, step, tag, sub0 + j,
+// inst), j = 0, 1 (four per draw)
+template <typename R>
+__device__ __forceinline__ R internal_energy(uint64_t seed, uint64_t uid, long long step, int tag, uint32_t sub0,
+                                             int inst, int K, R T) {
+    const R two_pi = (R)2 * (R)kPi;
+    R acc = (R)0;
+    for (int j = 0; 4 * j < K; ++j) {
+        const U4 r = draw(seed, uid, step, tag, sub0 + (uint32_t)j, inst);
+        const R r1 = sqrt((R)-2 * log(unif<R>(r.v[0]))), r2 = sqrt((R)-2 * log(unif<R>(r.v[2])));
+        const R a1 = two_pi * unif<R>(r.v[1]), a2 = two_pi * unif<R>(r.v[3]);
+        const R X[4] = {r1 * cos(a1), r1 * sin(a1), r2 * cos(a2), r2 * sin(a2)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (4 * j + i < K) acc = acc + X[i] * X[i];
+    }
+    return T * acc;
+}
+__device__ __forceinline__ void store_e(const Particles &pa, long long i, double e) { pa.e64[i] = e; }
+__device__ __forceinline__ void store_e(const Particles &pa, long long i, float e) { pa.e32[i] = e; }
+__device__ __forceinline__ double load_e(const Particles &pa, long long i, double) { return pa.e64[i]; }
+__device__ __forceinline__ float load_e(const Particles &pa, long long i, float) { return pa.e32[i]; }
 
 // ---------------------------------------------------------------------------------------
 // S3: hydro particles, one wave per cell, lane l takes the particles l, l + 64, ...  Pair
@@ -1117,7 +1163,7 @@ __device__ __forceinline__ void half_normal(uint64_t seed, uint64_t puid, long l
     h0 = r * cos(two_pi * eb);
     h1 = r * sin(two_pi * eb);
 }
-template <typename R, int WPB>
+template <typename R, int WPB, bool KE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -1144,8 +1190,19 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         const int cl = c - P.cell0;  // ids carry the cell index within the instance
         const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c], E = D.W[4 * nc + c];
         const R U[3] = {(R)(m0 / rho), (R)(m1 / rho), (R)(m2 / rho)};
-        const R T = (R)((2.0 / 3.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
+        const R T = (R)((2.0 / (3.0 + D.K)) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
         R sT = sqrt(T);
+        const int K = KE ? D.K : 0;  // KE: K > 0 (a compile-time switch, see add_rec)
+        // energy-exact variant with internal degrees of freedom: one factor K N_sam / sum_k |X'_k|^2
+        // on every particle's internal energy makes the sample's internal energy exact too
+        R fint = (R)1;
+        if (P.sampling == 1 && K > 0) {
+            R se = (R)0;
+            for (long long k = lane; k < ns; k += kWave)
+                se = se + internal_energy<R>(seed, make_uid(step, cl, k), step, kTagInt, 0, inst, K, (R)1);
+            double sd = wave_sum((double)se);
+            fint = (R)((double)K * (double)ns / sd);
+        }
         const R one = (R)1;
         const bool odd = (lane & 1) != 0;
         const bool exact = P.sampling == 1;
@@ -1211,7 +1268,13 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
                 for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
                 store_new(pa, i, x, u, msam, uid);
                 pa.cell[i] = c;
-                add_phi<R>(acc, msam, u);
+                R e = (R)0;
+                if (K > 0) {
+                    e = internal_energy<R>(seed, uid, step, kTagInt, 0, inst, K, T);
+                    if (P.sampling == 1) e = e * fint;
+                    store_e(pa, i, e);
+                }
+                add_phi<R>(acc, msam, u, e);
             }
         }
     }
@@ -1260,7 +1323,7 @@ struct Inflow {
     int c, lf, bf, tri, inst;
     double dt;
     long long N;
-    double m, sig, a, vt1, vt2;
+    double m, sig, a, vt1, vt2, T;
     double nin[3], t1[3], t2[3];
 };
 
@@ -1278,9 +1341,8 @@ __device__ Inflow inflow_face(const Dev &D, int j) {
     const DevBC &b = D.bc[fi.w];
     const double rho = b.Winf[0];
     const double Ui[3] = {b.Winf[1] / rho, b.Winf[2] / rho, b.Winf[3] / rho};
-    const double T =
-        (2.0 / 3.0) * (b.Winf[4] - 0.5 * (b.Winf[1] * b.Winf[1] + b.Winf[2] * b.Winf[2] + b.Winf[3] * b.Winf[3]) / rho) /
-        rho;
+    const double T = temp_k(b.Winf, D.K);
+    q.T = T;
     const double tau = P.mu_ref * pow(T, P.omega) / (rho * T);
     // wave-only start phase: the free stream enters as waves only
     const double e = D.is[q.inst].step < P.gks_steps ? 0.0 : exp(-dt / tau);
@@ -1356,6 +1418,7 @@ __global__ void __launch_bounds__(64) k_inject(Dev D, int buf) {
         }
         store_new(pa, base + k, x, u, (R)q.m, uid);
         pa.cell[base + k] = q.c;
+        if (D.K > 0) store_e(pa, base + k, (R)internal_energy<double>(seed, uid, step, kTagInt, 0, q.inst, D.K, q.T));
     }
 }
 
@@ -1393,10 +1456,11 @@ __device__ __forceinline__ void cell_plane(const Dev &D, int s, float p[4]) {
 }
 
 // diffuse re-emission: u_n = sqrt(-2 T_w ln eta) into the domain, tangential components
-// N(U_w, T_w) in the face frame
+// N(U_w, T_w) in the face frame; with K internal degrees of freedom (e != nullptr) the internal
+// energy variable leaves in equilibrium at T_w too (full accommodation)
 template <typename R>
 __device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u[3], uint64_t uid, const StepCtx &sx,
-                                               int bounce) {
+                                               int bounce, R *e = nullptr, int K = 0) {
     U4 r = draw(sx.seed, uid, sx.step, kTagWall, (uint32_t)bounce, sx.inst);
     R t1[3], t2[3];
     face_frame<R>(n, t1, t2);
@@ -1408,6 +1472,7 @@ __device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u
     const R X1 = rr * cos(a), X2 = rr * sin(a);
 #pragma unroll
     for (int d = 0; d < 3; ++d) u[d] = (R)b.Uw[d] - vn * n[d] + sq * (X1 * t1[d] + X2 * t2[d]);
+    if (e) *e = internal_energy<R>(sx.seed, uid, sx.step, kTagWallInt, 2u * (uint32_t)bounce, sx.inst, K, Tw);
 }
 
 // Flight of one particle for the time ts from cell `cell`, entered through its local face
@@ -1422,7 +1487,7 @@ __device__ __forceinline__ void reemit_diffuse(const DevBC &b, const R n[3], R u
 // wait for them).
 template <typename R, bool STOP>
 __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry, uint64_t uid, const StepCtx &sx,
-                     int &ncross, int &nwall, int &bounce, int ct0 = -1, const R *B0 = nullptr) {
+                     int &ncross, int &nwall, int &bounce, int ct0 = -1, const R *B0 = nullptr, R *e = nullptr) {
     // margin of the exact division skip below: well above the rounding of the products
     const R skip = sizeof(R) == 8 ? (R)(1.0 + 1e-12) : (R)(1.0f + 1e-5f);
     int c = cell;
@@ -1542,7 +1607,7 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
             R p[4];
             cell_plane(D, c * 6 + bf, p);
             const R n[3] = {p[0], p[1], p[2]};
-            reemit_diffuse<R>(b, n, u, uid, sx, bounce);
+            reemit_diffuse<R>(b, n, u, uid, sx, bounce, e, D.K);
             ++bounce;
             ++nwall;
             entry = bf;
@@ -1599,7 +1664,8 @@ __device__ __forceinline__ void store_state(const Particles &pa, long long i, co
 // without the logarithm (the same decision as the formula, which is evaluated near the
 // threshold and for every collided particle).
 // Key of the end bucket: end cell (stays collisionless), nc + end cell (collided), -1
-// (escaped); stayers (collisionless in the cell they started in) carry kStayBit.
+// (escaped); stayers (collisionless, no face met) carry kStayBit and their records are not
+// stored (the gather advances them), nor are those of escaped particles.
 // A particle that meets a diffuse wall stops there (its state at the wall is stored) and is
 // queued with what its flight still needs (WallCont, kept in the next step's buffer, which
 // is free until the gather); the wall kernel re-emits it and finishes the flight with the
@@ -1627,26 +1693,31 @@ __device__ __forceinline__ WallCont<float> *wall_cont<float>(const Particles &p,
 
 // end of a flight: state (unless the caller stores it) and bucket key of particle i (the key
 // carries the end cell; the cell array of this buffer is not read again, the gather writes
-// the next one)
+// the next one).  A stayer (kStayBit) flew collisionless for the whole step without meeting
+// any face: its state is x + u dt of its record, which the gather forms itself, so its record
+// is not rewritten here.  Returns whether the record must be stored (every particle that is
+// neither a stayer nor escaped).
 template <typename R, bool STORE>
-__device__ __forceinline__ void finish_flight(const Dev &D, const Particles &pa, long long i, const R x[3],
-                                              const R u[3], int c, int rc, bool collided, int c0, bool &lost) {
+__device__ __forceinline__ bool finish_flight(const Dev &D, const Particles &pa, long long i, const R x[3],
+                                              const R u[3], int c, int rc, bool collided, int c0, int ncross,
+                                              bool &lost) {
     if (STORE) store_state(pa, i, x, u);
     int key = -1;
     bool stay = false;
     if (rc != 1) {
         lost = lost || rc < 0;
         key = collided ? D.nc + c : c;
-        stay = !collided && c == c0;
+        stay = !collided && c == c0 && ncross == 0;
     }
     D.key[i] = stay ? (key | kStayBit) : key;
+    return rc != 1 && !stay;
 }
 
 template <typename R, bool MULTI, bool STORE>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
                                            long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
                                            R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued,
-                                           int ct0, const R *B0) {
+                                           bool &wr, int ct0, const R *B0) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
     // a single instance reads its values through uniform addresses
@@ -1684,9 +1755,10 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, co
         if (STORE) store_state(pa, i, x, u);
         *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0, c};
         queued = true;
+        wr = true;
         return;
     }
-    finish_flight<R, STORE>(D, pa, i, x, u, c, rc, collided, c0, lost);
+    wr = finish_flight<R, STORE>(D, pa, i, x, u, c, rc, collided, c0, nx, lost);
 }
 
 // a record as 16-byte chunks
@@ -1747,7 +1819,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     bool lost = false;
     long long ii[ILP];
     int cc[ILP];
-    bool qq[ILP];
+    bool qq[ILP], wr[ILP];
     uint4 tl[ILP];
     R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP], bx[ILP][6];
     int ct[ILP];
@@ -1772,16 +1844,20 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) bx[j][q] = Bg[q];
         }
+    unsigned long long wm[ILP];
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
         qq[j] = false;
+        wr[j] = false;
         if (ii[j] < n_tot) {
             stream_one<R, MULTI, false>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_,
-                                        lost, qq[j], ct[j], bx[j]);
+                                        lost, qq[j], wr[j], ct[j], bx[j]);
             stage_state(&stage[threadIdx.x / kWave][j][lane_id() * CPR], xx[j], uu[j], tl[j]);
         }
+        wm[j] = __ballot(wr[j]);
     }
-    // each wave stores its runs of records whole, consecutive lanes on consecutive chunks
+    // each wave stores the records of its runs that changed (stayers and escaped particles
+    // are skipped), consecutive lanes on consecutive chunks
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
@@ -1789,7 +1865,8 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
         const long long nr = n_tot - wb;
         const int nch = (nr <= 0 ? 0 : (nr >= kWave ? kWave : (int)nr)) * CPR;
         uint4 *g = rec_chunks(pa, wb, R(0));
-        for (int k = lane_id(); k < nch; k += kWave) st_nt(&g[k], stage[threadIdx.x / kWave][j][k]);
+        for (int k = lane_id(); k < nch; k += kWave)
+            if ((wm[j] >> (k / CPR)) & 1ULL) st_nt(&g[k], stage[threadIdx.x / kWave][j][k]);
     }
     // wall queue (held in the rank array, which the bucket count fills only later): this
     // block's segment, qseg entries from seg * qseg
@@ -1823,7 +1900,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
 // The diffuse re-emissions queued by k_stream and the rest of those flights (further walls
 // re-emitted here directly).  Block b serves queue segment b % kWallSeg in a block-stride
 // loop together with the other gridDim / kWallSeg blocks of that segment.
-template <typename R, bool MULTI>
+template <typename R, bool MULTI, bool KE>
 __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long qseg) {
     __shared__ unsigned long long red[2][4];
     const int seg = (int)(blockIdx.x % kWallSeg);
@@ -1846,14 +1923,17 @@ __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long q
         R p[4];
         cell_plane(D, c * 6 + w.entry, p);
         const R n[3] = {p[0], p[1], p[2]};
-        reemit_diffuse<R>(b, n, u, uid, sx, w.bounce);
+        R ev = (R)0;
+        R *ep = KE ? &ev : nullptr;
+        reemit_diffuse<R>(b, n, u, uid, sx, w.bounce, ep, KE ? D.K : 0);
         int nx = w.ncross, nw = 1, bounce = w.bounce + 1;
         int entry = w.entry;
         R ts = w.trem;
-        const int rc = track<R, false>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce);
+        const int rc = track<R, false>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce, -1, nullptr, ep);
+        if (ep) store_e(pa, i, ev);
         nx_ += (unsigned long long)(nx - w.ncross);
         nw_ += (unsigned long long)nw;
-        finish_flight<R, true>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, lost);
+        (void)finish_flight<R, true>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, nx, lost);
     }
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
@@ -2052,35 +2132,41 @@ __device__ void wave_sort(int *a, int len) {
 
 
 // ---------------------------------------------------------------------------------------
-// S6: one block per cell c.  The survivors ending in c are laid out in the next buffer as
-//   [movers into c, ascending source index] [stayers of c, in their segment order]
-// where stayers (collisionless, ended where they started) are found by scanning c's own
-// start segments (old particles, then the ones sampled this step) and movers come bucketed
-// by k_scatter.  Sums over survivors give P^{n+1}; with the collided particles ending in c
-// they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-thread
-// assignment and reduction tree: bitwise reproducible.
+// S6 helpers: records of the gather (k_gather below)
 // ---------------------------------------------------------------------------------------
-// add phi of a record without copying it (collided particles)
+// add phi of a record without copying it (collided particles).  KE: the particles carry an
+// internal energy (K > 0); the monatomic instantiations leave it out at compile time, which
+// keeps their register counts (and occupancy) those of a kernel without it.
+template <bool KE>
 __device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5], double) {
     const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
     const double2 r1 = a[1], r2 = a[2], r3 = a[3];
     const double u[3] = {r1.y, r2.x, r2.y};
-    add_phi<double>(acc, r3.x, u);
+    if constexpr (KE)
+        add_phi<double>(acc, r3.x, u, src.e64[s]);
+    else
+        add_phi<double>(acc, r3.x, u);
 }
+template <bool KE>
 __device__ __forceinline__ void add_rec(const Particles &src, int s, double acc[5], float) {
     const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
     const float4 r0 = a[0], r1 = a[1];
     const float u[3] = {r0.w, r1.x, r1.y};
-    add_phi<float>(acc, src.m32[s], u);
+    if constexpr (KE)
+        add_phi<float>(acc, src.m32[s], u, src.e32[s]);
+    else
+        add_phi<float>(acc, src.m32[s], u);
 }
 
 // a whole record in registers, so that several loads can be in flight before the stores
 // (scalar arrays: kept in registers, where structs of vectors went to scratch)
 struct Rec64 {
     double v[8];  // x0 x1 | x2 u0 | u1 u2 | m id
+    double e;     // internal energy variable (K > 0)
 };
 struct Rec32 {
     float v[9];  // x0 x1 x2 u0 | u1 u2 id.lo id.hi, then m
+    float e;
 };
 template <typename R>
 struct RecOf;
@@ -2092,6 +2178,7 @@ template <>
 struct RecOf<float> {
     using T = Rec32;
 };
+template <bool KE>
 __device__ __forceinline__ void load_rec(const Particles &src, int s, Rec64 &q) {
     const double2 *a = reinterpret_cast<const double2 *>(src.rec + s);
 #pragma unroll
@@ -2100,7 +2187,9 @@ __device__ __forceinline__ void load_rec(const Particles &src, int s, Rec64 &q) 
         q.v[2 * k] = t.x;
         q.v[2 * k + 1] = t.y;
     }
+    if constexpr (KE) q.e = src.e64[s];
 }
+template <bool KE>
 __device__ __forceinline__ void load_rec(const Particles &src, int s, Rec32 &q) {
     const float4 *a = reinterpret_cast<const float4 *>(src.rec32 + s);
     const float4 t0 = a[0], t1 = a[1];
@@ -2113,30 +2202,54 @@ __device__ __forceinline__ void load_rec(const Particles &src, int s, Rec32 &q) 
     q.v[6] = t1.z;
     q.v[7] = t1.w;
     q.v[8] = src.m32[s];
+    if constexpr (KE) q.e = src.e32[s];
 }
 // Staged output: a lane adds phi of its record, puts the record into its slot of the wave's
 // LDS stage and writes the small per-particle arrays (cell; FP32: mass) itself; then the wave
 // stores the run of staged records with consecutive lanes on consecutive 16-byte chunks, a
 // few whole cache lines per instruction instead of a 16-byte piece of 64 lines.
+template <bool KE>
 __device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, const Rec64 &q, double acc[5],
                                           uint4 *slot) {
     const double u[3] = {q.v[3], q.v[4], q.v[5]};
-    add_phi<double>(acc, q.v[6], u);
+    if constexpr (KE)
+        add_phi<double>(acc, q.v[6], u, q.e);
+    else
+        add_phi<double>(acc, q.v[6], u);
     double2 *b = reinterpret_cast<double2 *>(slot);
 #pragma unroll
     for (int k = 0; k < 4; ++k) b[k] = make_double2(q.v[2 * k], q.v[2 * k + 1]);
     dst.cell[o] = c;
+    if constexpr (KE) dst.e64[o] = q.e;
 }
+template <bool KE>
 __device__ __forceinline__ void stage_rec(const Particles &dst, int o, int c, const Rec32 &q, double acc[5],
                                           uint4 *slot) {
     const float u[3] = {q.v[3], q.v[4], q.v[5]};
-    add_phi<float>(acc, q.v[8], u);
+    if constexpr (KE)
+        add_phi<float>(acc, q.v[8], u, q.e);
+    else
+        add_phi<float>(acc, q.v[8], u);
     float4 *b = reinterpret_cast<float4 *>(slot);
     b[0] = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
     b[1] = make_float4(q.v[4], q.v[5], q.v[6], q.v[7]);
     dst.m32[o] = q.v[8];
     dst.cell[o] = c;
+    if constexpr (KE) dst.e32[o] = q.e;
 }
+// a stayer's state at the end of the step: x + u dt (its record holds the start of the step;
+// the same arithmetic as the transport's last move of a flight that meets no face)
+__device__ __forceinline__ void advance(Rec64 &q, double dt) {
+    q.v[0] = q.v[0] + q.v[3] * dt;
+    q.v[1] = q.v[1] + q.v[4] * dt;
+    q.v[2] = q.v[2] + q.v[5] * dt;
+}
+__device__ __forceinline__ void advance(Rec32 &q, float dt) {
+    q.v[0] = q.v[0] + q.v[3] * dt;
+    q.v[1] = q.v[1] + q.v[4] * dt;
+    q.v[2] = q.v[2] + q.v[5] * dt;
+}
+
 // the wave's n staged records to dst from record o0 on (called by the whole wave; the fences
 // order this wave's LDS accesses, which the hardware performs in order)
 template <typename R>
@@ -2151,13 +2264,14 @@ __device__ __forceinline__ void stage_out(const uint4 *st, const Particles &dst,
 // ---------------------------------------------------------------------------------------
 // S6: one wave per cell c.  The survivors ending in c are laid out in the next buffer as
 //   [movers into c, ascending source index] [stayers of c, in their segment order]
-// where stayers (collisionless, ended where they started) are found by scanning c's own
-// start segments (old particles, then the ones sampled this step) and movers come bucketed
-// by k_scatter.  Sums over survivors give P^{n+1}; with the collided particles ending in c
-// they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega.  Fixed per-lane
-// assignment and reduction tree: bitwise reproducible.
+// where stayers (collisionless for the whole step without meeting a face: advanced here by
+// u dt) are found by scanning c's own start segments (old particles, then the ones sampled
+// this step) and movers (every other survivor, including one that came back to its start
+// cell after a wall) come bucketed by k_scatter.  Sums over survivors give P^{n+1}; with the
+// collided particles ending in c they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) /
+// Omega.  Fixed per-lane assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-template <typename R, int WPB>
+template <typename R, int WPB, bool KE>
 __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     constexpr int BS = kWave;
     constexpr int kLds = 256;  // longer source lists are sorted in place in global memory
@@ -2242,20 +2356,22 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
                 const int j = j0 + lane;
                 const bool ha = j < len, hb = j + BS < len;
                 typename RecOf<R>::T A{}, B{};
-                if (ha) load_rec(src, list[j], A);
-                if (hb) load_rec(src, list[j + BS], B);
-                if (ha) stage_rec(dst, a0 + j, c, A, Pn, st + lane * CPR);
+                if (ha) load_rec<KE>(src, list[j], A);
+                if (hb) load_rec<KE>(src, list[j + BS], B);
+                if (ha) stage_rec<KE>(dst, a0 + j, c, A, Pn, st + lane * CPR);
                 stage_out<R>(st, dst, a0 + j0, min(BS, len - j0));
-                if (hb) stage_rec(dst, a0 + j + BS, c, B, Pn, st + lane * CPR);
+                if (hb) stage_rec<KE>(dst, a0 + j + BS, c, B, Pn, st + lane * CPR);
                 stage_out<R>(st, dst, a0 + j0 + BS, max(0, min(BS, len - j0 - BS)));
             }
         } else {
 #pragma unroll 2
-            for (int j = lane; j < len; j += BS) add_rec(src, list[j], Cn, R(0));
+            for (int j = lane; j < len; j += BS) add_rec<KE>(src, list[j], Cn, R(0));
         }
         wave_sync();
     }
-    // stayers: own segment of old particles, then own new particles, compacted in order
+    // stayers: own segment of old particles, then own new particles, compacted in order and
+    // advanced by u dt (the transport left their records as they were)
+    const R dtR = (R)D.is[inst_of(D, c)].dt;
     const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
     int pos = base + nmov;
     for (int seg = 0; seg < 2; ++seg) {
@@ -2269,13 +2385,15 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             const bool sa = ka >= 0 && (ka & kStayBit) != 0, sb = kb >= 0 && (kb & kStayBit) != 0;
             const unsigned long long ma = __ballot(sa), mb = __ballot(sb);
             typename RecOf<R>::T A{}, B{};
-            if (sa) load_rec(src, (int)ja, A);
-            if (sb) load_rec(src, (int)jb, B);
+            if (sa) load_rec<KE>(src, (int)ja, A);
+            if (sb) load_rec<KE>(src, (int)jb, B);
+            if (sa) advance(A, dtR);
+            if (sb) advance(B, dtR);
             const int ra = (int)__popcll(ma & below), rb = (int)__popcll(mb & below);
-            if (sa) stage_rec(dst, pos + ra, c, A, Pn, st + ra * CPR);
+            if (sa) stage_rec<KE>(dst, pos + ra, c, A, Pn, st + ra * CPR);
             stage_out<R>(st, dst, pos, (int)__popcll(ma));
             pos += (int)__popcll(ma);
-            if (sb) stage_rec(dst, pos + rb, c, B, Pn, st + rb * CPR);
+            if (sb) stage_rec<KE>(dst, pos + rb, c, B, Pn, st + rb * CPR);
             stage_out<R>(st, dst, pos, (int)__popcll(mb));
             pos += (int)__popcll(mb);
         }
@@ -2537,7 +2655,7 @@ __global__ void k_moments(Dev D, int which, double *out) {
         o[1] = W[1] / rho;
         o[2] = W[2] / rho;
         o[3] = W[3] / rho;
-        o[4] = (2.0 / 3.0) * (W[4] - 0.5 * (W[1] * W[1] + W[2] * W[2] + W[3] * W[3]) / rho) / rho;
+        o[4] = temp_k(W, D.K);
     }
     for (int k = 0; k < 5; ++k) out[5 * c + k] = o[k];
 }
@@ -2603,24 +2721,36 @@ template <typename R>
 void launch_stream_wall(const Dev &D, int buf, long long qseg, hipStream_t s) {
     // 16 blocks per queue segment, each segment's length known only on the device
     const unsigned g = 16 * kWallSeg;
-    if (D.n_inst > 1)
-        k_stream_wall<R, true><<<g, 256, 0, s>>>(D, buf, qseg);
+    if (D.n_inst > 1 && D.K > 0)
+        k_stream_wall<R, true, true><<<g, 256, 0, s>>>(D, buf, qseg);
+    else if (D.n_inst > 1)
+        k_stream_wall<R, true, false><<<g, 256, 0, s>>>(D, buf, qseg);
+    else if (D.K > 0)
+        k_stream_wall<R, false, true><<<g, 256, 0, s>>>(D, buf, qseg);
     else
-        k_stream_wall<R, false><<<g, 256, 0, s>>>(D, buf, qseg);
+        k_stream_wall<R, false, false><<<g, 256, 0, s>>>(D, buf, qseg);
+}
+
+template <typename R, bool KE>
+void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
+    if (w == 1)
+        k_sample<R, 1, KE><<<g, 64, 0, s>>>(D, buf);
+    else if (w == 2)
+        k_sample<R, 2, KE><<<g, 128, 0, s>>>(D, buf);
+    else if (w == 8)
+        k_sample<R, 8, KE><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_sample<R, 4, KE><<<g, 256, 0, s>>>(D, buf);
 }
 
 template <typename R>
 void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
     const int w = cfg.sample_wpb, nc = D.nc;
     const unsigned g = (unsigned)((nc + w - 1) / w);
-    if (w == 1)
-        k_sample<R, 1><<<g, 64, 0, s>>>(D, buf);
-    else if (w == 2)
-        k_sample<R, 2><<<g, 128, 0, s>>>(D, buf);
-    else if (w == 8)
-        k_sample<R, 8><<<g, 512, 0, s>>>(D, buf);
+    if (D.K > 0)
+        launch_sample_k<R, true>(D, buf, w, g, s);
     else
-        k_sample<R, 4><<<g, 256, 0, s>>>(D, buf);
+        launch_sample_k<R, false>(D, buf, w, g, s);
 }
 
 template <typename R>
@@ -2720,10 +2850,14 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     {
         constexpr int WPB = kGatherWaves;
         const unsigned g = (unsigned)((nc + WPB - 1) / WPB);
-        if (f32)
-            k_gather<float, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+        if (f32 && D.K > 0)
+            k_gather<float, WPB, true><<<g, WPB * 64, 0, s>>>(D, buf);
+        else if (f32)
+            k_gather<float, WPB, false><<<g, WPB * 64, 0, s>>>(D, buf);
+        else if (D.K > 0)
+            k_gather<double, WPB, true><<<g, WPB * 64, 0, s>>>(D, buf);
         else
-            k_gather<double, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+            k_gather<double, WPB, false><<<g, WPB * 64, 0, s>>>(D, buf);
     }
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);

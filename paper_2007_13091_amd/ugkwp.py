@@ -108,13 +108,13 @@ def lib():
         L.ugkwp_particle_count.argtypes = [vp, P(C.c_int64)]
         L.ugkwp_export_particles.restype = C.c_int32
         L.ugkwp_export_particles.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int32),
-                                             P(C.c_uint64)]
+                                             P(C.c_uint64), P(C.c_double)]
         L.ugkwp_export_state.restype = C.c_int32
         L.ugkwp_export_state.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_int64), P(C.c_double)]
         L.ugkwp_import_state.restype = C.c_int32
         L.ugkwp_import_state.argtypes = [vp, P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double),
                                          P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_uint64),
-                                         P(C.c_int64), P(C.c_double)]
+                                         P(C.c_double), P(C.c_int64), P(C.c_double)]
         L.ugkwp_geometry.restype = C.c_int32
         L.ugkwp_geometry.argtypes = [vp, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.ugkwp_profile_enable.restype = C.c_int32
@@ -309,10 +309,11 @@ class Solver:
     def particles(self):
         n = self.particle_count()
         x = np.zeros((n, 3)); u = np.zeros((n, 3)); m = np.zeros(n)
-        c = np.zeros(n, dtype=np.int32); uid = np.zeros(n, dtype=np.uint64)
+        c = np.zeros(n, dtype=np.int32); uid = np.zeros(n, dtype=np.uint64); e = np.zeros(n)
         self._check(lib().ugkwp_export_particles(self.h, _ptr(x, C.c_double), _ptr(u, C.c_double),
-                                                 _ptr(m, C.c_double), _ptr(c, C.c_int32), _ptr(uid, C.c_uint64)))
-        return dict(x=x, u=u, m=m, cell=c, uid=uid)
+                                                 _ptr(m, C.c_double), _ptr(c, C.c_int32), _ptr(uid, C.c_uint64),
+                                                 _ptr(e, C.c_double)))
+        return dict(x=x, u=u, m=m, cell=c, uid=uid, e=e)
 
     def export_state(self):
         """The state between steps: W, P ([n_cells][5]; W^p = P / Omega), the particles (grouped
@@ -334,12 +335,13 @@ class Solver:
         m = np.ascontiguousarray(p["m"], dtype=np.float64).reshape(n)
         c = np.ascontiguousarray(p["cell"], dtype=np.int32).reshape(n)
         uid = np.ascontiguousarray(p["uid"], dtype=np.uint64).reshape(n)
+        e = np.ascontiguousarray(p["e"] if p.get("e") is not None else np.zeros(n), dtype=np.float64).reshape(n)
         step = np.ascontiguousarray(np.broadcast_to(state["step"], (self.n_inst,)), dtype=np.int64)
         t = np.ascontiguousarray(np.broadcast_to(state["t"], (self.n_inst,)), dtype=np.float64)
         self._check(lib().ugkwp_import_state(self.h, _ptr(W, C.c_double), _ptr(P, C.c_double), n,
                                              _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(m, C.c_double),
-                                             _ptr(c, C.c_int32), _ptr(uid, C.c_uint64), _ptr(step, C.c_int64),
-                                             _ptr(t, C.c_double)))
+                                             _ptr(c, C.c_int32), _ptr(uid, C.c_uint64), _ptr(e, C.c_double),
+                                             _ptr(step, C.c_int64), _ptr(t, C.c_double)))
 
     def profile(self, on=True, slots=None):
         """Bracket each kernel group of a step with hip events (measurement support); slots:

@@ -54,6 +54,10 @@ def compare_particles(pg, po, length=1.0, vscale=1.0, rtol=RTOL, what=""):
     mscale = msum[cells] / np.maximum(mcnt[cells], 1)
     dm = (np.abs(pg["m"][ig] - po["m"][io]) / mscale).max() if cells.size else 0.0
     assert dx <= rtol and du <= rtol and dm <= rtol, f"{what} particle state dx {dx:.2e} du {du:.2e} dm {dm:.2e}"
+    if "e" in pg and "e" in po:
+        # internal energy variables (K > 0), against the thermal scale vscale^2
+        de = np.abs(pg["e"][ig] - po["e"][io]).max() / (vscale * vscale)
+        assert de <= rtol, f"{what} particle internal energies de {de:.2e}"
 
 
 def compare_stats(sg, so, what=""):

@@ -60,7 +60,7 @@ def test_mesh_errors_are_reported():
 
 def test_param_errors_are_reported():
     w = wl.sod(nx=4, ny=1, nz=1)
-    for field, val in (("gamma", 1.4), ("mu_ref", -1.0), ("cfl", 1.5), ("n_ref", 0)):
+    for field, val in (("gamma", 1.45), ("mu_ref", -1.0), ("cfl", 1.5), ("n_ref", 0)):
         p = wl.Params(**{**w.params.__dict__, field: val})
         with pytest.raises(U.UgkwpError) as e:
             U.workspace_bytes(w.mesh, p)
@@ -211,3 +211,25 @@ def test_morton_numbering_is_a_renumbering_of_the_same_mesh():
     first = g.mesh.cell_nodes[:g.mesh.cell_node_off[8]].reshape(8, 8)
     xyz = g.mesh.xyz[first].mean(1)
     assert np.ptp(xyz, 0).max() <= 1.0 / 8 + 1e-12
+
+
+def test_gamma_of_internal_degrees_of_freedom():
+    from paper_2007_13091_amd import ugkwp as U
+    from paper_2007_13091_amd import workloads as wl
+
+    for g in (5.0 / 3.0, 7.0 / 5.0, 9.0 / 7.0):
+        w = wl.sod(nx=10, ny=2, nz=2, n_ref=20, gamma=g)
+        assert U.workspace_bytes(w.mesh, w.params) > 0
+    w = wl.sod(nx=10, ny=2, nz=2, n_ref=20)
+    # 1.45 and 1.3: no integer K; 1.0 and 2.0: none at all; 1.1: K = 17, beyond 8
+    for bad in (1.45, 1.3, 1.0, 2.0, 1.1):
+        w.params.gamma = bad
+        try:
+            U.workspace_bytes(w.mesh, w.params)
+            raise AssertionError(f"gamma {bad} accepted")
+        except U.UgkwpError as e:
+            assert e.status == U.E_ARG
+    # the diatomic gas carries an internal-energy array per particle buffer
+    a = wl.sod(nx=10, ny=2, nz=2, n_ref=20)
+    b = wl.sod(nx=10, ny=2, nz=2, n_ref=20, gamma=7.0 / 5.0)
+    assert U.workspace_bytes(b.mesh, b.params) > U.workspace_bytes(a.mesh, a.params)

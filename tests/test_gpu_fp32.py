@@ -168,3 +168,65 @@ def test_fp32_counts_match_on_first_step():
     # few larger differences
     dx = np.abs(pg["x"][ig] - po["x"][io]).max(1)
     assert np.quantile(dx, 0.999) < 1e-5 and dx.max() < 1e-3, (np.quantile(dx, 0.999), dx.max())
+
+
+def test_fp32_continuum_limit_error_statement():
+    # tau -> 0 (exp(-dt/tau) underflows: no particles): the deterministic limit, where the
+    # FP32 form's difference from the FP64 oracle is the rounding of its FP32 flux alone
+    w = wl.sod()
+    w.params.mu_ref = 1e-14
+    import oracle
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    o = oracle.Oracle(w.mesh, w.params)
+    o.set_state(w.W0)
+    g = Solver(w.mesh, w.params, precision=1)
+    g.init_state(w.W0)
+    rows = []
+    for n in range(1, 41):
+        o.step()
+        st = g.step(1)
+        assert st["n_alive"] == 0
+        if n in (1, 10, 20, 40):
+            W1, _, _ = o.state()
+            rows.append({"step": n, "fp32_vs_oracle": _err(g.moments(0), W1)})
+    _record("sod_continuum_limit", rows)
+    for r in rows:
+        for q in ("rho", "U", "T"):
+            # FP32 rounding of the flux, accumulated over the steps: far below 1e-4
+            assert r["fp32_vs_oracle"][q]["L1"] < 1e-5 and r["fp32_vs_oracle"][q]["Linf"] < 1e-4, r
+
+
+def test_fp32_cavity_full_size_error_statement():
+    """The 32^3 cavity at 400 particles per cell, as the benchmark runs it: (1) one step of the
+    FP32 form from a state the FP64 oracle reached (imported, grouped by cell) against the
+    oracle's step from that state; (2) 20 steps from the initial state against the oracle,
+    beside the oracle's own seed-to-seed noise."""
+    import oracle
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    w = wl.morton_numbered(wl.cavity())
+    o = oracle.Oracle(w.mesh, w.params)
+    o.set_state(w.W0)
+    o.step(6)
+    st = o.export_state()
+    p = st["particles"]
+    order = np.argsort(p["cell"], kind="stable")
+    g = Solver(w.mesh, w.params, precision=1)
+    g.init_state(w.W0)
+    g.import_state(dict(W=st["W"], P=st["P"], step=st["step"], t=st["t"],
+                        particles={k: v[order] for k, v in p.items()}))
+    sg = g.step(1)
+    o.step()
+    so = o.stats()
+    W1, _, _ = o.state()
+    one = {"from_step": 6, "fp32_vs_oracle": _err(g.moments(0), W1),
+           "collided_flips": abs(sg["n_collided"] - so["n_collided"]), "alive_diff": abs(sg["n_alive"] - so["n_alive"]),
+           "particles": so["n_alive"]}
+    _say("cavity32 one step from oracle state", one)
+    rows = _runs(w, 20, 5)
+    _record("cavity32", {"one_step_from_oracle_state": one, "from_initial_state": rows})
+    for q in ("rho", "U", "T"):
+        assert one["fp32_vs_oracle"][q]["L1"] < 1e-4
+        assert rows[-1]["fp32_vs_oracle"][q]["L1"] <= 1.1 * rows[-1]["noise_floor"][q]["L1"]
+    assert one["collided_flips"] <= 1e-4 * one["particles"]

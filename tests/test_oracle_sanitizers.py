@@ -54,7 +54,9 @@ def test_oracle_steps_clean_under_asan_and_ubsan(tmp_path):
         o.step()
         print("sanitized run complete", flush=True)
     """))
-    env = dict(os.environ, LD_PRELOAD=_libasan(), ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    # the ASan runtime must come first; whatever the environment already preloads stays after it
+    pre = ":".join(p for p in (_libasan(), os.environ.get("LD_PRELOAD", "")) if p)
+    env = dict(os.environ, LD_PRELOAD=pre, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     r = subprocess.run([sys.executable, str(script)], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert "sanitized run complete" in r.stdout
