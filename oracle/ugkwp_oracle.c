@@ -616,7 +616,9 @@ static void make_side(const double W[5], const double G[15], const double Wh[5],
 {
     s->g = to_frame(W, n, t1, t2, K);
     frame_derivs(G, n, t1, t2, s->dW);
-    if (Wh[0] > 0.0) {
+    /* a face hydro density within 1e-12 of the face density of zero is roundoff of an empty
+       hydro part (the limiter can pin it exactly to a neighbour's zero) and counts as zero */
+    if (Wh[0] > RHOH_EPS * W[0]) {
         s->h = to_frame(Wh, n, t1, t2, K);
         frame_derivs(Gh, n, t1, t2, s->dWh);
     } else {
@@ -1528,7 +1530,10 @@ static void across(const oracle_t *o, const cellq_t *q, int64_t c, int lf, doubl
  *                     bound minus W_c, eps^2 = (K h)^3, h = Omega^(1/3)
  * with D = g . (x_f - x_c) (1 where D = 0), W_max and W_min over the cell and its neighbours.
  * A cell whose limited face states include rho <= 0, T <= 0 or a negative hydro density
- * (or a hydro temperature <= 0) falls back to first order (all its gradients zero). */
+ * (or a hydro temperature <= 0) falls back to first order (all its gradients zero).  A face
+ * hydro density within 1e-12 of the face density of zero is roundoff of an empty hydro part
+ * (the limiter pins it exactly to a neighbour's zero, and rounding picks the sign): it counts
+ * as zero, here and in the flux. */
 static void phase_grad(oracle_t *o, cellq_t *q)
 {
     const int64_t nc = o->nc;
@@ -1604,8 +1609,8 @@ static void phase_grad(oracle_t *o, cellq_t *q)
             for (int k = 0; k < 10; ++k)
                 Wf[k] = vc[k] + g[k][0] * (xf[0] - xc[0]) + g[k][1] * (xf[1] - xc[1]) + g[k][2] * (xf[2] - xc[2]);
             if (!(Wf[0] > 0.0) || !(temp_of(o, Wf) > 0.0)) ok = 0;
-            if (!(Wf[5] >= 0.0)) ok = 0;
-            if (Wf[5] > 0.0 && !(temp_of(o, Wf + 5) > 0.0)) ok = 0;
+            if (!(Wf[5] >= -RHOH_EPS * Wf[0])) ok = 0;
+            if (Wf[5] > RHOH_EPS * Wf[0] && !(temp_of(o, Wf + 5) > 0.0)) ok = 0;
         }
         for (int k = 0; k < 5; ++k)
             for (int a = 0; a < 3; ++a) {
@@ -2067,7 +2072,8 @@ int orc_step(oracle_t *o)
                     orc_flux2_specular(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, n, dt, o->mu_ref, o->omega, o->c2, gks,
                                        o->K, F);
                 else if (b->type == BC_DIFFUSE)
-                    orc_flux_diffuse(Wl, Whl[0], q.tau[c], n, dt, b->Tw, b->Uw, gks, o->K, F);
+                    orc_flux_diffuse(Wl, Whl[0] > RHOH_EPS * Wl[0] ? Whl[0] : 0.0, q.tau[c], n, dt, b->Tw, b->Uw,
+                                     gks, o->K, F);
                 else
                     orc_flux2_farfield(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, b->Winf, n, dt, o->mu_ref, o->omega,
                                        o->c2, gks, o->K, F);

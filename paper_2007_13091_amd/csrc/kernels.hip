@@ -848,7 +848,8 @@ __device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref
 // wall's; far field: the free stream); a limiter per component (Barth-Jespersen or
 // Venkatakrishnan with eps^2 = (K h)^3, h = Omega^(1/3)); a cell whose limited face states are
 // non-physical (rho <= 0, T <= 0, hydro density < 0 or hydro temperature <= 0) falls back to
-// first order.
+// first order; a face hydro density within 1e-12 of the face density of zero counts as zero
+// (roundoff of an empty hydro part, which the limiter can pin to a neighbour's zero).
 __global__ void __launch_bounds__(128) k_grad(Dev D) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= D.nc) return;
@@ -978,8 +979,8 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
             wf[k] = vc[k] + g[k][0] * (lfx[3 * lf] - xc[0]) + g[k][1] * (lfx[3 * lf + 1] - xc[1]) +
                     g[k][2] * (lfx[3 * lf + 2] - xc[2]);
         if (!(wf[0] > 0.0) || !(temp_k(wf, D.K) > 0.0)) ok = false;
-        if (!(wf[5] >= 0.0)) ok = false;
-        if (wf[5] > 0.0 && !(temp_k(wf + 5, D.K) > 0.0)) ok = false;
+        if (!(wf[5] >= -1e-12 * wf[0])) ok = false;
+        if (wf[5] > 1e-12 * wf[0] && !(temp_k(wf + 5, D.K) > 0.0)) ok = false;
     }
 #pragma unroll
     for (int k = 0; k < 5; ++k)
@@ -1008,7 +1009,9 @@ __device__ __forceinline__ void make_side(const Dev &D, int c, const double W[5]
                                           const R t1[3], const R t2[3], Side2<R> &S) {
     S.g = to_frame<R>(W, n, t1, t2, D.K);
     frame_derivs<R>(D.gW, D.nc, c, n, t1, t2, S.dW);
-    if (Wh[0] > 0.0) {
+    // a face hydro density at or below 1e-12 of the face density is roundoff of an empty hydro
+    // part (the limiter can pin it exactly to a neighbour's zero): no hydro wave on that side
+    if (Wh[0] > 1e-12 * W[0]) {
         S.h = to_frame<R>(Wh, n, t1, t2, D.K);
         frame_derivs<R>(D.gH, D.nc, c, n, t1, t2, S.dWh);
     } else {
@@ -1068,7 +1071,8 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
             Ff[3] = (R)0;
             Ff[4] = (R)0;
         } else if (bc.type == 1) {
-            diffuse_flux<R>(L.g, (R)Whl[0], (R)D.tau[c], n, t1, t2, bc, dt, gks, Ff);
+            diffuse_flux<R>(L.g, (R)(Whl[0] > 1e-12 * Wl[0] ? Whl[0] : 0.0), (R)D.tau[c], n, t1, t2, bc, dt, gks,
+                            Ff);
         } else {
             Rs.g = to_frame<R>(bc.Winf, n, t1, t2, D.K);
             Rs.h = Rs.g;
