@@ -96,10 +96,11 @@ def copy_calibration(nbytes=1 << 30):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
 
 
-def kernel_names(rtype, cfg, multi):
-    """Names of the two particle kernels as the profiler lists them (cfg: launch shapes)."""
+def kernel_names(rtype, cfg, multi, ke=False):
+    """Names of the two particle kernels as the profiler lists them (cfg: launch shapes; ke:
+    the gas has internal degrees of freedom)."""
     return {"stream": f"k_stream<{rtype}, {cfg[0]}, {'true' if multi else 'false'}, {cfg[1]}>",
-            "gather": f"k_gather<{rtype}, 1>"}
+            "gather": f"k_gather<{rtype}, 1, {'true' if ke else 'false'}>"}
 
 
 def timed_steps(s, steps):
@@ -421,7 +422,7 @@ def gks_side(steps, warmup):
                               "faces": faces}}
 
 
-def configs_run(gks_steps=3000):
+def configs_run(gks_steps=3000, only=None, recon=None):
     """The other configurations, timed (not part of the default run): the shock tube over its
     40 steps (FP64; launch-bound at 200 cells), and the Mach 10 cube (1.2e6 tets) and the
     Mach 15 vehicle at Kn 1e-3 (3.1e6 tets) in both forms, started wave-only for `gks_steps`
@@ -452,12 +453,17 @@ def configs_run(gks_steps=3000):
                 "after_steps": warm}
 
     out = {}
-    w = wl.morton_numbered(wl.sod())
-    out["sod_50x2x2_fp64"] = one(w, 0, 1, 39)
-    for name, w in (("cube_mach10", wl.morton_numbered(wl.cube())),
-                    ("vehicle_mach15_kn1e-3", wl.morton_numbered(wl.vehicle(kn=1e-3)))):
+    if only in (None, "sod"):
+        w = wl.morton_numbered(wl.sod())
+        out["sod_50x2x2_fp64"] = one(w, 0, 1, 39)
+    for name, make in (("cube_mach10", lambda: wl.cube()), ("vehicle_mach15_kn1e-3", lambda: wl.vehicle(kn=1e-3))):
+        if only not in (None, name.split("_")[0]):
+            continue
+        w = wl.morton_numbered(make())
         w.params.gks_steps = gks_steps
         w.params.sampling = 1
+        if recon is not None:
+            w.params.recon = recon
         for prec in (0, 1):
             out[f"{name}_{'fp64' if prec == 0 else 'fp32'}"] = one(w, prec, gks_steps + 1, 4)
     return out
@@ -543,6 +549,12 @@ def main():
     ap.add_argument("--no-avg", action="store_true")
     ap.add_argument("--configs", action="store_true",
                     help="time the tube, the cube and the vehicle (their own JSON object; not the bench line)")
+    ap.add_argument("--config", choices=["sod", "cube", "vehicle"], default=None,
+                    help="with --configs: only this configuration (for profiling it alone)")
+    ap.add_argument("--recon", type=int, choices=[0, 1, 2], default=None,
+                    help="with --configs: the reconstruction of the cube and vehicle (default: first order)")
+    ap.add_argument("--gks-steps", type=int, default=3000,
+                    help="with --configs: wave-only steps before the timed UGKWP steps of the cube and vehicle")
     ap.add_argument("--gks-only", action="store_true",
                     help="run only the GKS-limit leg and print its JSON object (for profiling it alone)")
     ap.add_argument("--batched-only", action="store_true",
@@ -558,7 +570,7 @@ def main():
         copy_calibration()
         return
     if args.configs:
-        print(json.dumps({"configs": configs_run()}), flush=True)
+        print(json.dumps({"configs": configs_run(args.gks_steps, args.config, args.recon)}), flush=True)
         return
     if args.gks_only:
         print(json.dumps({"gks_limit": gks_side(args.steps, args.warmup)}), flush=True)

@@ -5,7 +5,8 @@
  * One call of ugkwp_step advances the state by one time step of the scheme of Sec. 2:
  *   S0 primitives, tau = mu/p and the CFL time step                  (Sec. 2.4(a))
  *   S2 wave flux F^eq + F^{fr,wave} over every face                  (Sec. 2.2, Sec. 2.4)
- *   S3 sampling of hydro particles from the Maxwellian of W^h         (Sec. 2.3, Sec. 2.4(b))
+ *   S3 sampling of hydro particles from the Maxwellian of W^h, or     (Sec. 2.3, Sec. 2.4(b))
+ *      from its first-order g_p (sampling = 2)
  *   S4 free-flight time t_f = min(-tau ln eta, dt) of each particle   (Eq. for t_f, Sec. 2.3)
  *   S5 face-to-face free transport with wall reflection              (Sec. 2.3, Sec. 2.4(e))
  *   S6 net particle flux, conservative update, removal of collided    (Eq. update_macro_variables)
@@ -126,7 +127,12 @@ typedef struct {
                                  and momentum of rho^hp, its thermal energy is random;
                              1 = energy-exact pairs (a departure from the paper): one factor
                                  per cell on every deviation, sqrt(3 N_pairs / sum_j |X_j|^2),
-                                 so that the sample also carries exactly the energy */
+                                 so that the sample also carries exactly the energy;
+                             2 = the first-order g_p of Sec. 2.3 (the Chapman-Enskog correction
+                                 of the Maxwellian from the cell's limited gradients, weighted by
+                                 alpha = dt / expm1(dt/tau) - tau), by acceptance-rejection per
+                                 particle; needs recon 1 or 2 (else UGKWP_E_ARG); the sample
+                                 carries exactly the mass, its momentum and energy are random */
     int32_t gks_steps;    /* wave-only start: the steps n < gks_steps, counted from
                              ugkwp_init_state, sample no particle and let no free-stream particle
                              enter; their wave flux carries the whole free transport of W^h,

@@ -237,8 +237,9 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
         err = "params: gks_steps must be >= 0";
         return UGKWP_E_ARG;
     }
-    if (p.sampling != 0 && p.sampling != 1) {
-        err = "params: sampling is 0 (the pairs of Sec. 2.4(b)) or 1 (energy-exact pairs)";
+    if (p.sampling < 0 || p.sampling > 2 || (p.sampling == 2 && p.recon == 0)) {
+        err = "params: sampling is 0 (the pairs of Sec. 2.4(b)), 1 (energy-exact pairs) or 2 (first-order g_p of "
+              "Sec. 2.3, which needs recon 1 or 2 for the cell gradients)";
         return UGKWP_E_ARG;
     }
     long long c = p.capacity;
@@ -411,6 +412,8 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     D.n_inst = n_inst;
     D.recon_any = recon_any ? 1 : 0;
     D.recon_all = recon_all ? 1 : 0;
+    D.gp_any = 0;
+    for (int k = 0; k < n_inst; ++k) D.gp_any = D.gp_any || p[k].sampling == 2;
     D.any_diffuse = 0;
     for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
     D.cap = cap;

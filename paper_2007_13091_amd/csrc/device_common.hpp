@@ -14,7 +14,8 @@ enum : uint32_t {
     kErrCellCount = 8u,  // more than 2^20 particles sampled in one cell (particle-id field)
 };
 
-enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5, kTagInt = 6, kTagWallInt = 7 };
+enum : int { kTagTF = 1, kTagPos = 2, kTagVel = 3, kTagWall = 4, kTagInject = 5, kTagInt = 6, kTagWallInt = 7,
+             kTagGP = 8 };
 
 // internal degrees of freedom supported: gamma = (K + 5)/(K + 3), 0 <= K <= kMaxK
 constexpr int kMaxK = 8;
@@ -148,7 +149,8 @@ struct Dev {
     const uint8_t *bflf;    // [n_bfaces]  local face of an input boundary face
     // parameters
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
-    int32_t K, pad2;        // internal degrees of freedom of the gas (every instance)
+    int32_t K;              // internal degrees of freedom of the gas (every instance)
+    int32_t gp_any;         // some instance samples from the first-order g_p (sampling 2)
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
     const InstP *ip;        // [n_inst]

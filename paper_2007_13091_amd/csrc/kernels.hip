@@ -1167,6 +1167,33 @@ __device__ __forceinline__ void half_normal(uint64_t seed, uint64_t puid, long l
     h0 = r * cos(two_pi * eb);
     h1 = r * sin(two_pi * eb);
 }
+// a uniform point of a cell from the draw (uid, step, kTagPos): per axis in a box, the unit cube
+// folded onto the tetrahedron (Rocchini-Cignoni) in a tetrahedron; org + s e1 + t e2 + w e3
+template <typename R>
+__device__ __forceinline__ void cell_point(uint64_t seed, uint64_t uid, long long step, int inst, const R org[3],
+                                           const R Ed[9], bool tet, R x[3]) {
+    const R one = (R)1;
+    U4 rp = draw(seed, uid, step, kTagPos, 0, inst);
+    R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
+    if (tet) {
+        if (s + t > one) {
+            s = one - s;
+            t = one - t;
+        }
+        if (t + w > one) {
+            R tmp = w;
+            w = one - s - t;
+            t = one - tmp;
+        } else if (s + t + w > one) {
+            R tmp = w;
+            w = s + t + w - one;
+            s = one - t - tmp;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+}
+
 template <typename R, int WPB, bool KE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
     const int wave = threadIdx.x / kWave;
@@ -1175,6 +1202,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     if (c >= D.nc) return;
     const int nc = D.nc;
     const Scalars *sc = D.sc;
+    // cells of instances that sample the first-order g_p are k_sample_gp's
+    if (D.gp_any && D.ip[inst_of(D, c)].sampling == 2) return;
     const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;  // even
     // S = P + the new particles' sums, lane k < 5 writing component k; a cell that samples
     // nothing copies P (loaded in the same round as its count)
@@ -1250,26 +1279,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
                 R u[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
-                U4 rp = draw(seed, uid, step, kTagPos, 0, inst);
-                R s = unif<R>(rp.v[0]), t = unif<R>(rp.v[1]), w = unif<R>(rp.v[2]);
-                if (tet) {
-                    if (s + t > one) {
-                        s = one - s;
-                        t = one - t;
-                    }
-                    if (t + w > one) {
-                        R tmp = w;
-                        w = one - s - t;
-                        t = one - tmp;
-                    } else if (s + t + w > one) {
-                        R tmp = w;
-                        w = s + t + w - one;
-                        s = one - t - tmp;
-                    }
-                }
                 R x[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
+                cell_point<R>(seed, uid, step, inst, org, Ed, tet, x);
                 store_new(pa, i, x, u, msam, uid);
                 pa.cell[i] = c;
                 R e = (R)0;
@@ -1280,6 +1291,123 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
                 }
                 add_phi<R>(acc, msam, u, e);
             }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] = wave_sum(acc[k]);
+    double ak = acc[0];
+#pragma unroll
+    for (int k = 1; k < 5; ++k)
+        if (lane == k) ak = acc[k];
+    if (lane < 5) D.S[lane * nc + c] = D.P[lane * nc + c] + ak;
+}
+
+// ---------------------------------------------------------------------------------------
+// S3 with sampling = 2: hydro particles from the first-order g_p (Sec. 2.3).  With g expanded
+// about the state W^n the step starts from, at t = dt,
+//   g_p = g(W^n) [1 + alpha p],  alpha = dt e/(1 - e) - tau = dt / expm1(dt/tau) - tau,
+// and the first-order correction p of the BGK model written in its Chapman-Enskog form
+// (X = (u - U)/sqrt(T), z = e_int/T, G_ij = d_j U_i and grad T from the cell's limited
+// gradient of W):
+//   p = X_i X_j G_ij - (|X|^2 + z)/(3 + K) div U + ((|X|^2 + z)/2 - (5 + K)/2) sqrt(T) X . grad T / T.
+// Acceptance-rejection per particle, one lane each: attempt j proposes X by Box-Muller on the
+// draw (uid, step, kTagGP, 2j) (X0, X1 = r1 (cos, sin)(2 pi e1), X2 = r2 cos(2 pi e3)) and,
+// with K > 0, the internal energy T chi^2_K from (kTagInt, 2j, 2j + 1); it is kept when
+// eta B < 1 + alpha p, eta the first uniform of (uid, step, kTagGP, 2j + 1) in FP64 and
+// B = 1 + |alpha| (16 (sum_ij |G_ij| + |div U|) + ((3 + K) 16 + 5 + K)/2 4 sqrt(T) sum_j |d_j T| / T),
+// which bounds |1 + alpha p| wherever every normal is at most 4.  After 64 rejections the last
+// proposal is kept.  Positions as in k_sample.  One wave per cell; S = P + the new sums.
+// ---------------------------------------------------------------------------------------
+template <typename R, bool KE>
+__global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
+    constexpr int kAttempts = 64;
+    constexpr double kBox = 4.0;
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int c = blockIdx.x * 4 + wave;
+    if (c >= D.nc) return;
+    const int nc = D.nc;
+    const int inst = inst_of(D, c);
+    const InstP &P = D.ip[inst];
+    if (P.sampling != 2) return;
+    const Scalars *sc = D.sc;
+    const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ns > 0) {
+        const Particles pa = D.pa[buf];
+        const long long base = sc->n_old + D.samoff[c];
+        const long long step = D.is[inst].step;
+        const unsigned long long seed = P.seed;
+        const int cl = c - P.cell0;
+        const int K = KE ? D.K : 0;
+        const double W[5] = {D.W[c], D.W[nc + c], D.W[2 * nc + c], D.W[3 * nc + c], D.W[4 * nc + c]};
+        const double rho = W[0], Ud[3] = {W[1] / rho, W[2] / rho, W[3] / rho};
+        const double T = temp_k(W, K);
+        // primitive gradients from the limited gradient of W: G[i][j] = d_j U_i, gT[j] = d_j T
+        double G[3][3], gT[3], sU = 0.0, divU = 0.0, sTg = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double dr = D.gW[j * nc + c];
+            double dU[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dU[i] = (D.gW[(3 * (1 + i) + j) * nc + c] - Ud[i] * dr) / rho;
+            double dT = (D.gW[(12 + j) * nc + c] - W[4] / rho * dr) / rho - (Ud[0] * dU[0] + Ud[1] * dU[1] + Ud[2] * dU[2]);
+            dT = 2.0 / (3.0 + K) * dT;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                G[i][j] = dU[i];
+                sU += fabs(dU[i]);
+            }
+            divU += dU[j];
+            gT[j] = dT;
+            sTg += fabs(dT);
+        }
+        const double tau = D.tau[c], dt = D.is[inst].dt;
+        const double alpha = dt / expm1(dt / tau) - tau;
+        const double B = 1.0 + fabs(alpha) * (kBox * kBox * (sU + fabs(divU)) +
+                                              0.5 * ((3.0 + K) * kBox * kBox + 5.0 + K) * kBox * sqrt(T) * sTg / T);
+        const double sqT = sqrt(T);
+        const R U[3] = {(R)Ud[0], (R)Ud[1], (R)Ud[2]};
+        const R sT = (R)sqT, TR = (R)T;
+        const R msam = (R)(D.ec[c] * D.rhoh[c] * D.vol[c] / (double)ns);
+        const R org[3] = {(R)D.orig[c], (R)D.orig[nc + c], (R)D.orig[2 * nc + c]};
+        R Ed[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
+        const bool tet = D.ctype[c] == 4;
+        const R two_pi = (R)2 * (R)kPi;
+        for (long long k = lane; k < ns; k += kWave) {
+            const uint64_t uid = make_uid(step, cl, k);
+            R u[3], e = (R)0;
+            for (int j = 0; j < kAttempts; ++j) {
+                const U4 rv = draw(seed, uid, step, kTagGP, 2u * (uint32_t)j, inst);
+                const R r1 = sqrt((R)-2 * log(unif<R>(rv.v[0]))), r2 = sqrt((R)-2 * log(unif<R>(rv.v[2])));
+                const R a1 = two_pi * unif<R>(rv.v[1]), a2 = two_pi * unif<R>(rv.v[3]);
+                const R X[3] = {r1 * cos(a1), r1 * sin(a1), r2 * cos(a2)};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) u[d] = U[d] + sT * X[d];
+                if (KE && K > 0) e = internal_energy<R>(seed, uid, step, kTagInt, 2u * (uint32_t)j, inst, K, TR);
+                const U4 ra = draw(seed, uid, step, kTagGP, 2u * (uint32_t)j + 1u, inst);
+                const double x0 = (double)X[0], x1 = (double)X[1], x2 = (double)X[2];
+                const double s2 = x0 * x0 + x1 * x1 + x2 * x2 + (double)e / T;
+                const double Xd[3] = {x0, x1, x2};
+                double shear = 0.0, xg = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    xg += Xd[i] * gT[i];
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj) shear += Xd[i] * Xd[jj] * G[i][jj];
+                }
+                const double p = shear - s2 / (3.0 + K) * divU + (0.5 * s2 - 0.5 * (5.0 + K)) * sqT * xg / T;
+                if (unif<double>(ra.v[0]) * B < 1.0 + alpha * p) break;
+            }
+            const long long i = base + k;
+            R x[3];
+            cell_point<R>(seed, uid, step, inst, org, Ed, tet, x);
+            store_new(pa, i, x, u, msam, uid);
+            pa.cell[i] = c;
+            if (KE) store_e(pa, i, e);
+            add_phi<R>(acc, msam, u, e);
         }
     }
 #pragma unroll
@@ -2755,6 +2883,13 @@ void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
         launch_sample_k<R, true>(D, buf, w, g, s);
     else
         launch_sample_k<R, false>(D, buf, w, g, s);
+    if (D.gp_any) {
+        const unsigned g4 = (unsigned)((nc + 3) / 4);
+        if (D.K > 0)
+            k_sample_gp<R, true><<<g4, 256, 0, s>>>(D, buf);
+        else
+            k_sample_gp<R, false><<<g4, 256, 0, s>>>(D, buf);
+    }
 }
 
 template <typename R>

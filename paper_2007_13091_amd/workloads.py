@@ -80,7 +80,8 @@ class Params:
     recon: int = 0          # 0 first order, 1 LSQ + Barth-Jespersen, 2 LSQ + Venkatakrishnan
     venkat_k: float = 1.0   # Venkatakrishnan constant K
     sampling: int = 0       # hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b),
-                            # 1 the energy-exact variant (one factor per cell on the deviations)
+                            # 1 the energy-exact variant (one factor per cell on the deviations),
+                            # 2 the first-order g_p of Sec. 2.3 (needs recon 1 or 2)
     gks_steps: int = 0      # steps from the initial state run wave-only (no particles): the
                             # continuum start of the paper's hypersonic cases
 

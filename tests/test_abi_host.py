@@ -118,6 +118,21 @@ def test_reconstruction_parameters():
         U.workspace_bytes(w.mesh, p)
 
 
+def test_sampling_modes():
+    # 0 the pairs of Sec. 2.4(b), 1 energy-exact pairs, 2 the first-order g_p (needs gradients)
+    w = wl.sod(nx=10)
+    for mode, recon, ok in ((0, 0, True), (1, 0, True), (2, 1, True), (2, 2, True), (2, 0, False), (3, 1, False),
+                            (-1, 0, False)):
+        p = copy.deepcopy(w.params)
+        p.sampling, p.recon = mode, recon
+        if ok:
+            assert U.workspace_bytes(w.mesh, p) > 0
+        else:
+            with pytest.raises(U.UgkwpError) as e:
+                U.workspace_bytes(w.mesh, p)
+            assert e.value.status == U.E_ARG
+
+
 def test_periodic_meshes_are_paired_or_refused():
     """Periodic faces (test support): a fully periodic box is accepted (hexahedra and
     tetrahedra); a periodic face without a partner is a mesh error; second order and a zero

@@ -34,14 +34,14 @@ def test_digest_ignores_comments_and_layout_but_not_code():
 
 def test_unknown_kernel_has_no_measured_traffic():
     assert _bench().measured_traffic("k_no_such_kernel<double>", "batch64") is None
-    assert _bench().measured_traffic("k_gather<float, 1>", "no_such_workload") is None
+    assert _bench().measured_traffic("k_gather<float, 1, false>", "no_such_workload") is None
 
 
 def test_roofline_and_error_helpers():
     b = _bench()
     # 1e6 moves in FP32 at 80 B each over 0.02 ms: 4000 GB/s, half of the peak
     dom, kr = b.kernel_roofline({"stream": 0.02, "gather": 0.01}, 1e6, {"n_alive": 9e5, "n_collided": 1e5}, "float",
-                                {"stream": "k_stream<float, 256, true, 1>", "gather": "k_gather<float, 1>"}, "none")
+                                {"stream": "k_stream<float, 256, true, 1>", "gather": "k_gather<float, 1, false>"}, "none")
     assert dom == "stream" and abs(kr["stream"]["frac"] - 0.5) < 1e-12
     assert kr["gather"]["algorithmic_bytes_per_launch"] == 80 * 900000 + 40 * 100000
     ws = b.whole_step(1.0, 1e7, 32768, "double")
@@ -50,6 +50,14 @@ def test_roofline_and_error_helpers():
     W = np.tile([1.0, 0.1, 0.0, 0.0, 1.6], (4, 1))
     e = b.field_error(W, W)
     assert all(e[v]["L1"] == 0 and e[v]["Linf"] == 0 for v in ("rho", "U", "T"))
+
+
+def test_kernel_names_match_the_instantiations():
+    b = _bench()
+    n = b.kernel_names("float", (256, 1), True)
+    assert n == {"stream": "k_stream<float, 256, true, 1>", "gather": "k_gather<float, 1, false>"}
+    src = open(os.path.join(ROOT, "paper_2007_13091_amd", "csrc", "kernels.hip")).read()
+    assert "k_gather<float, WPB, false>" in src and "k_stream<R, " in src
 
 
 def test_more_than_one_gpu_is_refused():
