@@ -284,6 +284,26 @@ int32_t ugkwp_profile_mask(ugkwp_ctx *ctx, uint32_t mask);
 /* Name of a profiling slot ("" if out of range); static storage. */
 const char *ugkwp_profile_slot_name(int32_t slot);
 
+/* For callers that cannot allocate device memory (code under hip graph capture, serving loops
+ * that forbid allocation, harnesses without an allocator): ugkwp_init_mesh with the library's
+ * own static workspace instead of a caller's buffer.  The workspace is one array per GPU of
+ * ugkwp_static_workspace_bytes() bytes (32 MiB), part of the library's device code object,
+ * reserved on each GPU the library is loaded on and held until the process ends; its device
+ * address is looked up once per GPU on the first call there (the current device).  Nothing is
+ * allocated: no hipMalloc, no allocating library call.
+ * Limits and sharing: a mesh whose ugkwp_workspace_bytes exceeds the array is refused with
+ * UGKWP_E_CAPACITY (the shock tube of 200 box cells at 200 particles per cell needs 21 MiB).
+ * One context at a time may use a GPU's array: a second call on that GPU before
+ * ugkwp_destroy of the first returns UGKWP_E_STATE (two live contexts would overwrite each
+ * other's state, as would any overlapping use of the array).  The array keeps whatever the
+ * last context left; ugkwp_init_state clears what must start at zero, as with a caller's
+ * uninitialised workspace.  ugkwp_destroy waits for the context's stream before releasing the
+ * array.  Every other call works on such a context as on one from ugkwp_init_mesh. */
+int32_t ugkwp_init_mesh_static(ugkwp_ctx **ctx, const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p,
+                               void *hip_stream);
+/* Size in bytes of the static workspace of ugkwp_init_mesh_static (per GPU). */
+size_t ugkwp_static_workspace_bytes(void);
+
 /* Message for the last failure on this context (or of init when ctx is NULL). */
 const char *ugkwp_last_error(const ugkwp_ctx *ctx);
 

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -82,7 +83,22 @@ const char *kSlotNames[ugkwp::kNumSlots] = {"prim_dt", "cell_prep",    "scan_sam
                                              "gather",  "finalize"};
 }  // namespace
 
+// Workspace of ugkwp_init_mesh_static, for callers that cannot allocate device memory: one
+// array per GPU in the library's own device memory, reserved when the code object is loaded
+// on that GPU and held until the process ends.  Host code never passes its name to a kernel
+// or a copy: the array's device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticWorkspaceBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxStaticDevices] = {};   // device address of `scratch` on each GPU
+bool g_static_busy[kMaxStaticDevices] = {};   // a live context uses that GPU's array
+}  // namespace
+
 struct ugkwp_ctx {
+    int static_dev = -1;  // >= 0: the context lives in that GPU's static workspace
     EventProf prof;
     HostMesh H;
     ugkwp_params p{};                          // instance 0 (shared settings: precision)
@@ -1038,8 +1054,67 @@ const char *ugkwp_profile_slot_name(int32_t slot) {
     return (slot >= 0 && slot < ugkwp::kNumSlots) ? kSlotNames[slot] : "";
 }
 
+int32_t ugkwp_init_mesh_static(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, const ugkwp_params *p,
+                               void *hip_stream) {
+    if (!out || !m || !p) return fail(nullptr, UGKWP_E_ARG, "null argument");
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, UGKWP_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxStaticDevices)
+        return fail(nullptr, UGKWP_E_ARG, "init_mesh_static: device index beyond " + std::to_string(kMaxStaticDevices));
+    size_t need = 0;
+    int32_t st = ugkwp_workspace_bytes(m, n_inst, p, &need);
+    if (st != UGKWP_OK) return st;
+    if (need > kStaticWorkspaceBytes)
+        return fail(nullptr, UGKWP_E_CAPACITY,
+                    "init_mesh_static: this mesh and capacity need " + std::to_string(need) +
+                        " bytes of workspace; the static workspace holds " + std::to_string(kStaticWorkspaceBytes) +
+                        " (use ugkwp_init_mesh with a workspace of that size, or a smaller capacity)");
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_busy[dev])
+            return fail(nullptr, UGKWP_E_STATE,
+                        "init_mesh_static: the static workspace of device " + std::to_string(dev) +
+                            " is in use by another context (destroy it first)");
+        if (!g_static_ptr[dev]) {
+            // the current device is `dev`: its copy of the array
+            void *q = nullptr;
+            e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !q)
+                return fail(nullptr, UGKWP_E_DEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+            g_static_ptr[dev] = q;
+        }
+        ptr = g_static_ptr[dev];
+        g_static_busy[dev] = true;
+    }
+    st = ugkwp_init_mesh(out, m, n_inst, p, ptr, kStaticWorkspaceBytes, hip_stream);
+    if (st != UGKWP_OK) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[dev] = false;
+        return st;
+    }
+    (*out)->static_dev = dev;
+    return UGKWP_OK;
+}
+
+size_t ugkwp_static_workspace_bytes(void) { return kStaticWorkspaceBytes; }
+
 const char *ugkwp_last_error(const ugkwp_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
-void ugkwp_destroy(ugkwp_ctx *ctx) { delete ctx; }
+void ugkwp_destroy(ugkwp_ctx *ctx) {
+    if (!ctx) return;
+    const int dev = ctx->static_dev;
+    if (dev >= 0) {
+        // the next context on this GPU's array must not overlap work still in flight
+        (void)hipStreamSynchronize(ctx->stream);
+    }
+    delete ctx;
+    if (dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[dev] = false;
+    }
+}
 
 }  // extern "C"

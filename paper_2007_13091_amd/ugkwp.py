@@ -24,7 +24,7 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
            "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask", "ugkwp_set_averaging", "ugkwp_average",
-           "ugkwp_export_state", "ugkwp_import_state")
+           "ugkwp_export_state", "ugkwp_import_state", "ugkwp_init_mesh_static", "ugkwp_static_workspace_bytes")
 N_PROFILE_SLOTS = 12
 
 
@@ -80,6 +80,10 @@ def lib():
         L.ugkwp_workspace_bytes.argtypes = [P(UgkwpMesh), C.c_int32, P(UgkwpParams), P(C.c_size_t)]
         L.ugkwp_init_mesh.restype = C.c_int32
         L.ugkwp_init_mesh.argtypes = [P(vp), P(UgkwpMesh), C.c_int32, P(UgkwpParams), vp, C.c_size_t, vp]
+        L.ugkwp_init_mesh_static.restype = C.c_int32
+        L.ugkwp_init_mesh_static.argtypes = [P(vp), P(UgkwpMesh), C.c_int32, P(UgkwpParams), vp]
+        L.ugkwp_static_workspace_bytes.restype = C.c_size_t
+        L.ugkwp_static_workspace_bytes.argtypes = []
         L.ugkwp_instance_stats.restype = C.c_int32
         L.ugkwp_instance_stats.argtypes = [vp, C.c_int32, P(UgkwpStats)]
         L.ugkwp_profile_mask.restype = C.c_int32
@@ -199,9 +203,11 @@ def workspace_bytes(mesh, params, capacity=0, precision=0) -> int:
 class Solver:
     """One mesh, or a batch of independent instances (lists of meshes and params), on one
     GPU.  `mesh`, `params`: see paper_2007_13091_amd.workloads.  stream: a torch stream to
-    order the work on (default: the current stream)."""
+    order the work on (default: the current stream).  static_workspace: use the library's
+    own static workspace (ugkwp_init_mesh_static; nothing is allocated, small meshes only,
+    one such solver per GPU at a time)."""
 
-    def __init__(self, mesh, params, capacity=0, precision=0, device="cuda", stream=None):
+    def __init__(self, mesh, params, capacity=0, precision=0, device="cuda", stream=None, static_workspace=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -216,11 +222,16 @@ class Solver:
         if st != OK:
             raise UgkwpError(st, L.ugkwp_last_error(None).decode())
         self.precision = precision
-        self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
         h = C.c_void_p(0)
-        st = L.ugkwp_init_mesh(C.byref(h), b.m, b.n, b.p, C.c_void_p(self.ws.data_ptr()), n.value,
-                               C.c_void_p(self.stream.cuda_stream))
+        if static_workspace:
+            self.ws = None
+            self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+            st = L.ugkwp_init_mesh_static(C.byref(h), b.m, b.n, b.p, C.c_void_p(self.stream.cuda_stream))
+        else:
+            self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+            st = L.ugkwp_init_mesh(C.byref(h), b.m, b.n, b.p, C.c_void_p(self.ws.data_ptr()), n.value,
+                                   C.c_void_p(self.stream.cuda_stream))
         if st != OK:
             raise UgkwpError(st, L.ugkwp_last_error(None).decode())
         self.h = h
