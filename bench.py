@@ -178,11 +178,28 @@ def batch_workloads(sampling):
     return ws
 
 
+def collisionless_fraction(w):
+    """Largest e = exp(-dt/tau) over the cells of a box-hex workload's initial state: dt from the
+    CFL rule with h = (volume / cells)^(1/3) (uniform cubic cells), tau = mu_ref T^omega / p."""
+    xyz = np.asarray(w.mesh.xyz)
+    h = (np.prod(xyz.max(0) - xyz.min(0)) / w.mesh.n_cells) ** (1.0 / 3.0)
+    W = np.asarray(w.W0)
+    K = int(round(2.0 / (w.params.gamma - 1.0) - 3.0))
+    rho = W[:, 0]
+    U = W[:, 1:4] / rho[:, None]
+    T = (2.0 / (3.0 + K)) * (W[:, 4] / rho - 0.5 * (U * U).sum(1))
+    dt = w.params.cfl * h / (np.abs(U) + 3.0 * np.sqrt(T)[:, None]).sum(1).max()
+    tau = w.params.mu_ref * T ** w.params.omega / (rho * T)
+    return float(np.exp(-dt / tau).max())
+
+
 def batch_capacity(w, steps):
     # N_sam = 2 ceil(r) adds up to two particles per cell and step wherever the hydro wave has a
-    # collisionless part, and rarefied cells lose only their collided share, so counts drift up
-    # by up to two per cell and step on top of about N_ref
-    return int(1.3 * w.params.n_ref * w.mesh.n_cells + 2.2 * steps * w.mesh.n_cells) + 65536
+    # collisionless part, and a cell keeps the share e of its particles, so its count settles
+    # near N_ref + 2/(1 - e); before that it drifts up by up to two per step
+    e = collisionless_fraction(w)
+    drift = min(2.2 * steps, 2.2 / max(1.0 - e, 1e-9) + 8.0)
+    return int((1.2 * w.params.n_ref + drift) * w.mesh.n_cells) + 65536
 
 
 def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):

@@ -265,10 +265,12 @@ int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg);
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
 
 /* Autotuner: one pass of coordinate search over the shapes above, each candidate timed with
- * hip events around its own kernel over steps_per_trial steps (after one untimed step).
- * The trial steps are real steps of the simulation (the shape does not change results): the
- * state advances by (steps_per_trial + 1) x 13 steps.  The fastest shapes are kept and
- * returned in cfg_out[4] (may be NULL).  Discards pending ugkwp_profile_read records. */
+ * hip events around its own kernel over steps_per_trial steps (after one untimed step); the
+ * transport's candidates are compared per particle move (the particle count drifts from one
+ * trial to the next).  The trial steps are real steps of the simulation (the shape does not
+ * change results): the state advances by (steps_per_trial + 1) x 13 steps.  The fastest
+ * shapes are kept and returned in cfg_out[4] (may be NULL).  Discards pending
+ * ugkwp_profile_read records. */
 int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out);
 
 /* Measurement support.  While enabled, each group of kernel launches of ugkwp_step is

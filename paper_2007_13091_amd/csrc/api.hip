@@ -1004,23 +1004,30 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
             // one untimed step (first use of a kernel variant), then the timed ones
             ugkwp::launch_step(ctx->D, ctx->buf, c, ctx->stream, nullptr);
             ctx->buf ^= 1;
+            Scalars s0, s1;
+            st = read_scalars(ctx, s0);
+            if (st != UGKWP_OK) break;
+            ctx->prof.drain(nullptr, nullptr, 0);
             for (int32_t k = 0; k < steps_per_trial; ++k) {
                 ugkwp::launch_step(ctx->D, ctx->buf, c, ctx->stream, &ctx->prof);
                 ctx->buf ^= 1;
             }
             double ms[ugkwp::kNumSlots];
             int64_t cnt[ugkwp::kNumSlots];
-            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            st = read_scalars(ctx, s1);
+            if (st != UGKWP_OK) break;
             ctx->prof.drain(ms, cnt, ugkwp::kNumSlots);
-            const double t = ms[dims[d].slot] / (double)(cnt[dims[d].slot] ? cnt[dims[d].slot] : 1);
+            double t = ms[dims[d].slot] / (double)(cnt[dims[d].slot] ? cnt[dims[d].slot] : 1);
+            // the particle count drifts between trials: the transport's candidates are compared
+            // per particle move
+            const unsigned long long moved = s1.moved_total - s0.moved_total;
+            if (d == 0 && moved > 0) t = ms[dims[d].slot] / (double)moved;
             if (t < best_ms) {
                 best_ms = t;
                 keep = c;
             }
         }
         best = keep;
-        Scalars s;
-        st = read_scalars(ctx, s);
     }
     ctx->cfg = best;
     ctx->drop_graphs();

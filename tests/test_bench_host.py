@@ -60,6 +60,27 @@ def test_kernel_names_match_the_instantiations():
     assert "k_gather<float, WPB, false>" in src and "k_stream<R, " in src
 
 
+def test_batch_capacity_covers_the_drift_and_fits_an_index():
+    from paper_2007_13091_amd import workloads as wl
+
+    b = _bench()
+    specs = wl.batched_specs()
+    total = 0
+    for k in (0, 6, 19, 63):
+        w = wl.batched_instance(specs[k])
+        e = b.collisionless_fraction(w)
+        assert 0.0 < e <= 1.0
+        cap = b.batch_capacity(w, 127)
+        # N_ref plus the drift of up to two particles per cell and step
+        assert cap >= (w.params.n_ref + 2 * 127) * w.mesh.n_cells
+        total += cap
+    # a continuum-limit cavity settles: its capacity does not grow with the steps
+    w = wl.cavity(n=8, n_ref=100, kn=1e-7)
+    assert b.collisionless_fraction(w) < 1e-3
+    assert b.batch_capacity(w, 1000) == b.batch_capacity(w, 100)
+    assert sum(b.batch_capacity(wl.batched_instance(sp), 127) for sp in specs) < 2 ** 31 - 1024
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
