@@ -179,8 +179,9 @@ def batch_workloads(sampling):
 
 
 def collisionless_fraction(w):
-    """Largest e = exp(-dt/tau) over the cells of a box-hex workload's initial state: dt from the
-    CFL rule with h = (volume / cells)^(1/3) (uniform cubic cells), tau = mu_ref T^omega / p."""
+    """Smallest and largest e = exp(-dt/tau) over the cells of a box-hex workload's initial
+    state: dt from the CFL rule with h = (volume / cells)^(1/3) (uniform cubic cells),
+    tau = mu_ref T^omega / p."""
     xyz = np.asarray(w.mesh.xyz)
     h = (np.prod(xyz.max(0) - xyz.min(0)) / w.mesh.n_cells) ** (1.0 / 3.0)
     W = np.asarray(w.W0)
@@ -190,16 +191,29 @@ def collisionless_fraction(w):
     T = (2.0 / (3.0 + K)) * (W[:, 4] / rho - 0.5 * (U * U).sum(1))
     dt = w.params.cfl * h / (np.abs(U) + 3.0 * np.sqrt(T)[:, None]).sum(1).max()
     tau = w.params.mu_ref * T ** w.params.omega / (rho * T)
-    return float(np.exp(-dt / tau).max())
+    e = np.exp(-dt / tau)
+    return float(e.min()), float(e.max())
 
 
 def batch_capacity(w, steps):
-    # N_sam = 2 ceil(r) adds up to two particles per cell and step wherever the hydro wave has a
-    # collisionless part, and a cell keeps the share e of its particles, so its count settles
-    # near N_ref + 2/(1 - e); before that it drifts up by up to two per step
-    e = collisionless_fraction(w)
-    drift = min(2.2 * steps, 2.2 / max(1.0 - e, 1e-9) + 8.0)
-    return int((1.2 * w.params.n_ref + drift) * w.mesh.n_cells) + 65536
+    # Within a step a cell holds its old particles and the newly sampled ones (the collided are
+    # removed only at its end).  The sample is about N_ref (1 - e) + 2 (the share of the hydro
+    # wave's collisionless part, N_sam = 2 ceil(r)); the old ones are what the last steps kept:
+    # a cell keeps the share e, so its count settles near N_ref + 2/(1 - e), and before that it
+    # drifts up by up to two per step
+    e_lo, e_hi = collisionless_fraction(w)
+    drift = min(2.2 * steps, 2.2 / max(1.0 - e_hi, 1e-9) + 8.0)
+    per_cell = 1.15 * w.params.n_ref * (2.0 - e_lo) + drift + 8.0
+    return int(per_cell * w.mesh.n_cells) + 65536
+
+
+def batch_capacities(ws, steps):
+    """Capacities of the batch's instances for `steps` steps: the estimate above, or the plain
+    bound 1.3 N_ref + 2.2 per step per cell where that is larger and the batch's total still fits
+    a 32-bit particle index."""
+    est = [batch_capacity(w, steps) for w in ws]
+    plain = [max(e, int((1.3 * w.params.n_ref + 2.2 * steps) * w.mesh.n_cells) + 65536) for e, w in zip(est, ws)]
+    return plain if sum(plain) < 2 ** 31 - 1024 else est
 
 
 def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
@@ -218,7 +232,7 @@ def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
     nc = int(sum(w.mesh.n_cells for w in ws))
     tuning = 13 * 2
     total = start + warmup + 2 * steps + 2
-    caps = [batch_capacity(w, total) for w in ws]
+    caps = batch_capacities(ws, total)
     stream = torch.cuda.Stream()
     s = Solver(meshes, params, capacity=caps, precision=1, stream=stream)
     s.init_state(W0)
@@ -602,7 +616,7 @@ def main():
         from paper_2007_13091_amd.ugkwp import Solver
 
         ws = batch_workloads(1)
-        caps = [batch_capacity(w, args.batch_start + args.warmup + args.steps + 2) for w in ws]
+        caps = batch_capacities(ws, args.batch_start + args.warmup + args.steps + 2)
         s = Solver([w.mesh for w in ws], [w.params for w in ws], capacity=caps, precision=1,
                    stream=torch.cuda.Stream())
         s.init_state(np.concatenate([w.W0 for w in ws]))
