@@ -238,12 +238,25 @@ def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
     s.init_state(W0)
     s.step(max(start - tuning, 1), stats=False)
     cfg = s.autotune(steps_per_trial=1)
+    # the warm-up steps time the first-order flux kernel (the hip events bracket it alone)
+    s.profile(True, slots=["flux"])
+    s.profile_read()
     s.step(warmup, stats=True)
+    fl = s.profile_read()["flux"]
+    s.profile(False)
     el, moves, kms, st0, st1 = timed_steps(s, steps)
     done_steps = int(st1["step"])
     names = kernel_names("float", cfg, True)
     workload = "batch64"
     dom, kr = kernel_roofline(kms, moves / steps, st1, "float", names, workload)
+    faces = sum((6 * w.mesh.n_cells + int(w.mesh.bface_nodes.shape[0])) // 2 for w in ws)
+    flux_ms = fl[0] / max(fl[1], 1)
+    flux_name = f"k_flux<float, {cfg[3]}>"
+    flux_ach = BYTES_PER_FACE_FP32 * faces / (flux_ms * 1e-3) / 1e9
+    flux_roof = {"kernel": flux_name, "kernel_avg_ms": round(flux_ms, 4), "bound": "hbm", "achieved": round(flux_ach, 1),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(flux_ach / HBM_PEAK_GBS, 4),
+                 "bytes_per_face": BYTES_PER_FACE_FP32, "faces": faces,
+                 "traffic": measured_traffic(flux_name, workload), "timed": "the warm-up steps"}
     s.graph(True)
     s.step(1, stats=False)  # capture
     torch.cuda.synchronize()
@@ -259,6 +272,7 @@ def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
            "particles_per_step": int(moves / steps), "steps": steps, "timed_after_step": done_steps - steps,
            "launch_config": {"stream_bs": cfg[0], "stream_ilp": cfg[1], "sample_wpb": cfg[2], "flux_bs": cfg[3]},
            "dominant": dom, "kernels": kr, "whole_step": whole_step(ms, moves / steps, nc, "float"),
+           "flux": flux_roof,
            "graph_replay_ms_per_step": round(tg, 4), "cells": nc, "instances": len(ws)}
     # FP64 plain, one instance after the other (eager launches), then the one-step error
     pm, pt, pc = 0, 0.0, 0
@@ -404,6 +418,8 @@ def cpu_baseline(sample):
 # algorithmic bytes of the first-order flux per face: both cells' W (2 x 40), the face's
 # geometry (normal, area, owner and neighbour: 48) and its flux out (40)
 BYTES_PER_FACE = 168
+# in the FP32 form the face geometry is FP32 (normal 12, area 4, owner and neighbour 8): 144 B
+BYTES_PER_FACE_FP32 = 144
 GKS_CAPACITY = 65536
 
 
@@ -634,6 +650,7 @@ def main():
     roof = dict(b["kernels"][b["dominant"]])
     roof["other_kernel"] = b["kernels"]["gather" if b["dominant"] == "stream" else "stream"]
     roof["whole_step"] = b["whole_step"]
+    roof["flux_kernel"] = b["flux"]
     out = {
         "metric": "particle moves/s + cell-steps/s, FP32/batched vs FP64 plain at stated error",
         "value": b["value"],

@@ -25,19 +25,24 @@ def _state(s):
 
 def _same(a, b, what):
     np.testing.assert_array_equal(a[0], b[0], err_msg=f"{what}: W")
-    for k in ("uid", "cell", "x", "u", "m"):
+    for k in ("uid", "cell", "x", "u", "m", "e"):
         np.testing.assert_array_equal(a[1][k], b[1][k], err_msg=f"{what}: particles {k}")
 
 
 SHAPES = [(128, 1, 1, 64), (512, 2, 8, 256), (256, 2, 2, 128), (256, 1, 4, 64), (512, 1, 1, 256), (128, 2, 8, 128)]
 
 
+@pytest.mark.parametrize("gas", ["monatomic", "diatomic-gp"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_every_launch_shape_gives_identical_results(precision):
+def test_every_launch_shape_gives_identical_results(precision, gas):
     from paper_2007_13091_amd.ugkwp import Solver
 
+    g = 5.0 / 3.0 if gas == "monatomic" else 7.0 / 5.0
     ws = [wl.cavity(n=8, n_ref=200), wl.free_stream_box(n=(4, 3, 3), n_ref=60, kn=0.2, perturb=0.2, tets=True,
-                                                         jitter=0.15)]
+                                                         jitter=0.15, gamma=g)]
+    if gas != "monatomic":
+        ws[0] = wl.closed_box(n=(6, 5, 4), n_ref=120, kn=0.1, bc=wl.BC_DIFFUSE, perturb=0.3, gamma=g)
+        ws[0].params.recon, ws[0].params.sampling = 2, 2
     ref = None
     for shape in [None] + SHAPES:
         _say("precision", precision, "shape", shape)
@@ -82,6 +87,39 @@ def test_graph_replay_equals_eager_every_step():
     for key in ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits", "step"):
         assert sa[key] == sb[key], key
     _same(_state(b), _state(a), "graph replay end")
+
+
+@pytest.mark.parametrize("case", ["diatomic-gp-diffuse", "batch-mixed-modes"])
+def test_graph_replay_with_internal_energy_and_gp_sampling(case):
+    # the internal-energy instantiations and the g_p sampling kernel, captured and replayed
+    import torch
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    if case == "diatomic-gp-diffuse":
+        w = wl.closed_box(n=(4, 3, 3), n_ref=60, kn=0.2, bc=wl.BC_DIFFUSE, tets=True, jitter=0.15, perturb=0.3,
+                          gamma=7.0 / 5.0)
+        w.params.recon, w.params.sampling = 2, 2
+        meshes, params, W0 = w.mesh, w.params, w.W0
+    else:
+        ws = wl.small_batch(4)
+        for k, x in enumerate(ws):
+            x.params.recon = 1 if k % 2 == 0 else 0
+            x.params.sampling = 2 if k % 2 == 0 else 1
+        meshes, params, W0 = [x.mesh for x in ws], [x.params for x in ws], np.concatenate([x.W0 for x in ws])
+    stream = torch.cuda.Stream()
+    a = Solver(meshes, params, stream=stream)
+    b = Solver(meshes, params, stream=stream)
+    a.init_state(W0)
+    b.init_state(W0)
+    b.graph(True)
+    for k in range(5):
+        a.step(1, stats=False)
+        b.step(1, stats=False)
+        torch.cuda.synchronize()
+        x = torch.ones(1000, device="cuda").cumsum(0)
+        assert float(x[-1]) == 1000.0
+        _same(_state(b), _state(a), f"{case} graph replay step {k}")
+    assert a.step(0)["n_alive"] > 0
 
 
 def test_graph_needs_a_created_stream():
