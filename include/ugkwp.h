@@ -139,7 +139,9 @@ typedef struct {
                              int u_n (q4 g0^h + q5 u.g_x^h) psi (the wave flux of Sec. 2.4 without
                              the terms of the sampled particles).  This is how the paper starts
                              its hypersonic cases (Sec. 4.3, Sec. 4.4): from a field computed by
-                             the gas-kinetic scheme alone.  0 = off */
+                             the gas-kinetic scheme alone.  While no particle exists (from
+                             ugkwp_init_state, or an imported state without particles) these
+                             steps skip the particle kernels, with the same results.  0 = off */
 } ugkwp_params;
 
 /* Statistics of a step.  For a batch, ugkwp_step reports the counts summed over the

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -112,16 +113,21 @@ struct ugkwp_ctx {
     ugkwp::LaunchCfg cfg;
     bool have_state = false;
     bool poisoned = false;
-    // graph replay: one captured step per starting particle buffer
+    // graph replay: one captured step per starting particle buffer (and per launch sequence)
     bool graph_on = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_wave[2] = {nullptr, nullptr};
+    // steps ahead that are wave-only for every instance while no particle exists: they take the
+    // shorter launch sequence (the particle kernels would find nothing to do)
+    long long wave_only_empty = 0;
     std::string err;
     void drop_graphs() {
-        for (auto &g : gexec)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
+        for (auto *gs : {gexec, gexec_wave})
+            for (int b = 0; b < 2; ++b)
+                if (gs[b]) {
+                    (void)hipGraphExecDestroy(gs[b]);
+                    gs[b] = nullptr;
+                }
     }
     ~ugkwp_ctx() { drop_graphs(); }
 };
@@ -558,6 +564,9 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     ctx->buf = 0;
     ctx->have_state = true;
     ctx->poisoned = false;
+    long long wo = ctx->ps.empty() ? 0 : (long long)ctx->ps[0].gks_steps;
+    for (const auto &q : ctx->ps) wo = std::min(wo, (long long)q.gks_steps);
+    ctx->wave_only_empty = wo;
     return UGKWP_OK;
 }
 
@@ -566,14 +575,18 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
     if (!ctx->have_state) return fail(ctx, UGKWP_E_STATE, "step before init_state");
     if (ctx->poisoned) return fail(ctx, UGKWP_E_STATE, "context poisoned by an earlier device error; call init_state");
     for (int32_t i = 0; i < n_steps; ++i) {
+        const bool wave = ctx->wave_only_empty > 0;
         if (ctx->graph_on) {
-            hipGraphExec_t &ge = ctx->gexec[ctx->buf];
+            hipGraphExec_t &ge = wave ? ctx->gexec_wave[ctx->buf] : ctx->gexec[ctx->buf];
             if (!ge) {
                 // capture the launch sequence of a step once; every count it needs is read
                 // on the device, so the same graph serves every later step
                 hipGraph_t g = nullptr;
                 HIPCHK(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-                ugkwp::launch_step(ctx->D, ctx->buf, ctx->cfg, ctx->stream, nullptr);
+                if (wave)
+                    ugkwp::launch_step_wave_only(ctx->D, ctx->buf, ctx->cfg, ctx->stream, nullptr);
+                else
+                    ugkwp::launch_step(ctx->D, ctx->buf, ctx->cfg, ctx->stream, nullptr);
                 hipError_t e = hipStreamEndCapture(ctx->stream, &g);
                 if (e != hipSuccess) return fail(ctx, UGKWP_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
                 e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -584,10 +597,13 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
                 }
             }
             HIPCHK(ctx, hipGraphLaunch(ge, ctx->stream));
+        } else if (wave) {
+            ugkwp::launch_step_wave_only(ctx->D, ctx->buf, ctx->cfg, ctx->stream, &ctx->prof);
         } else {
             ugkwp::launch_step(ctx->D, ctx->buf, ctx->cfg, ctx->stream, &ctx->prof);
         }
         ctx->buf ^= 1;
+        if (ctx->wave_only_empty > 0) --ctx->wave_only_empty;
     }
     HIPCHK(ctx, hipGetLastError());
     if (stats) {
@@ -903,6 +919,11 @@ int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int
     HIPCHK(ctx, hipStreamSynchronize(s));
     ctx->have_state = true;
     ctx->poisoned = false;
+    // wave-only steps ahead of every instance, if no particle was imported
+    long long wo = n > 0 ? 0 : (long long)1 << 62;
+    for (int32_t k = 0; k < D.n_inst && wo > 0; ++k)
+        wo = std::min(wo, std::max(0LL, (long long)ctx->ps[k].gks_steps - (long long)step[k]));
+    ctx->wave_only_empty = wo;
     return UGKWP_OK;
 }
 
@@ -987,6 +1008,7 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
         dims[2].cand.push_back(c);
     }
     int32_t st = UGKWP_OK;
+    long long tuned_steps = 0;  // the trials are real steps (full launch sequences)
     for (int d = 0; d < 3 && st == UGKWP_OK; ++d) {
         double best_ms = INFINITY;
         ugkwp::LaunchCfg keep = best;
@@ -1004,6 +1026,7 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
             // one untimed step (first use of a kernel variant), then the timed ones
             ugkwp::launch_step(ctx->D, ctx->buf, c, ctx->stream, nullptr);
             ctx->buf ^= 1;
+            tuned_steps += 1 + steps_per_trial;
             Scalars s0, s1;
             st = read_scalars(ctx, s0);
             if (st != UGKWP_OK) break;
@@ -1032,6 +1055,7 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     ctx->cfg = best;
     ctx->drop_graphs();
     ctx->graph_on = graph_was;
+    ctx->wave_only_empty = std::max(0LL, ctx->wave_only_empty - tuned_steps);
     ctx->prof.on = prof_was;
     ctx->prof.mask = mask_was;
     if (cfg_out) (void)ugkwp_get_launch(ctx, cfg_out);

@@ -2545,6 +2545,38 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     }
 }
 
+// S6 in a wave-only step with no particle anywhere (none is left, sampled or let in): the
+// update W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) / Omega with E = 0 and S = P = 0, one
+// thread per cell, in the arithmetic and order of the gather's cells without particles (so the
+// results are those of the full step bit for bit); the bucket offsets are those of empty cells
+__global__ void __launch_bounds__(256) k_gks_update(Dev D, int buf) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= D.nc) return;
+    const int nc = D.nc, nf = D.nf, nfc = D.nfc[c];
+    int codes[6];
+#pragma unroll
+    for (int lf = 0; lf < 6; ++lf) codes[lf] = lf < nfc ? D.cface[c * 6 + lf] : 0;
+    const double vol = D.vol[c];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double facc = 0.0;
+        for (int lf = 0; lf < nfc; ++lf) {
+            const int cd = codes[lf];
+            const int f = (cd > 0 ? cd : -cd) - 1;
+            const double sg = cd > 0 ? 1.0 : -1.0;
+            facc = facc - sg * D.Phi[k * nf + f];
+        }
+        const double S = D.P[k * nc + c] + 0.0;
+        const double acc = facc + (0.0 - S);
+        D.W[k * nc + c] = D.W[k * nc + c] + acc / vol;
+        D.P[k * nc + c] = 0.0;
+    }
+    const int base = D.off[c], bend = D.off[c + 1];
+    D.nleft[c] = bend - base;
+    D.segoff[buf ^ 1][c] = base;
+    if (base != bend) atomicOr(&D.sc->err, kErrCapacity);
+}
+
 __global__ void __launch_bounds__(256) k_finalize(Dev D, int buf) {
     __shared__ unsigned long long red[2][64];
     Scalars *s = D.sc;
@@ -2998,6 +3030,51 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
         else
             k_gather<double, WPB, false><<<g, WPB * 64, 0, s>>>(D, buf);
     }
+    pr->end(kSlotGather);
+    pr->begin(kSlotFinal);
+    k_finalize<<<1, 256, 0, s>>>(D, buf);
+    if (D.avg_from >= 0) {
+        k_avg_cells<<<(unsigned)(D.n_inst * kAvgBlocks), 256, 0, s>>>(D);
+        k_avg_fin<<<(unsigned)D.n_inst, 64, 0, s>>>(D);
+    }
+    pr->end(kSlotFinal);
+}
+
+// A wave-only step when no particle exists: no particle is sampled or let in (e = 0 in the
+// wave-only phase), so the particle kernels would find nothing to do; the bucket counts (zeroed
+// by k_prim_dt) are still scanned so that the offsets are those of empty cells.
+void launch_step_wave_only(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr) {
+    const int nc = D.nc, nf = D.nf;
+    const unsigned gc = (unsigned)((nc + 255) / 256);
+    Prof none;
+    if (!pr) pr = &none;
+    pr->begin(kSlotPrim);
+    k_prim_dt<<<gc, 256, 0, s>>>(D);
+    pr->end(kSlotPrim);
+    pr->begin(kSlotCellPrep);
+    k_cell_prep<<<gc, 256, 0, s>>>(D);
+    pr->end(kSlotCellPrep);
+    pr->begin(kSlotScan);
+    scan<long long>(LoadPlain<long long>{D.nsam}, nc, D.samoff, D.scan64, s);
+    if (D.nff > 0) {
+        k_inject_count<<<(unsigned)((D.nff + 255) / 256), 256, 0, s>>>(D);
+        scan<long long>(LoadPlain<long long>{D.ninj}, D.nff, D.injoff, D.scan64, s);
+    }
+    k_sample_setup<<<1, 1, 0, s>>>(D);
+    pr->end(kSlotScan);
+    pr->begin(kSlotFlux);
+    if (nf > 0) {
+        if (D.prec == 1)
+            launch_flux<float>(D, cfg, s);
+        else
+            launch_flux<double>(D, cfg, s);
+    }
+    pr->end(kSlotFlux);
+    pr->begin(kSlotScan2);
+    scan<int32_t>(LoadBucket{D.cnt64}, 2LL * nc, D.off, D.scan32, s);
+    pr->end(kSlotScan2);
+    pr->begin(kSlotGather);
+    k_gks_update<<<gc, 256, 0, s>>>(D, buf);
     pr->end(kSlotGather);
     pr->begin(kSlotFinal);
     k_finalize<<<1, 256, 0, s>>>(D, buf);
