@@ -49,7 +49,7 @@ def lib(omp: bool = False):
         L.orc_make_uid.argtypes = [C.c_int, i64, i64, i64]
         L.orc_moments.argtypes = [C.c_int, d, d, P(d)]
         L.orc_qcoef.argtypes = [d, d, P(d)]
-        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux_interior.argtypes = [P(d), P(d), d, d, P(d), d, d, d, d, C.c_int, C.c_int, d, P(d)]
         L.orc_flux_specular.argtypes = [P(d), d, P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
         L.orc_flux_diffuse.argtypes = [P(d), d, d, P(d), d, d, P(d), C.c_int, C.c_int, P(d)]
         L.orc_create.restype = vp
@@ -79,9 +79,13 @@ def lib(omp: bool = False):
         L.orc_slope.argtypes = [d, d, d, d, C.c_int, P(d), P(d)]
         L.orc_gp_eval.argtypes = [P(d), P(d), d, d, C.c_int, i64, P(d), P(d), P(d), P(d), P(d)]
         L.orc_mvec.argtypes = [C.c_int, C.c_int, C.c_int, P(d), C.c_int, d, d, d, d, C.c_int, P(d)]
-        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux2_interior.argtypes = [P(d)] * 8 + [P(d), d, d, d, d, C.c_int, C.c_int, d, P(d)]
         L.orc_flux2_specular.argtypes = [P(d)] * 4 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
-        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, C.c_int, C.c_int, P(d)]
+        L.orc_flux2_farfield.argtypes = [P(d)] * 5 + [P(d), d, d, d, d, C.c_int, C.c_int, d, P(d)]
+        L.orc_set_prandtl.restype = C.c_int
+        L.orc_set_prandtl.argtypes = [vp, d]
+        L.orc_heat_flux.argtypes = [vp, P(d)]
+        L.orc_shakhov_eval.argtypes = [P(d), d, P(d), d, i64, P(d), P(d), P(d), P(d)]
         L.orc_set_internal_dof.restype = C.c_int
         L.orc_set_internal_dof.argtypes = [vp, C.c_int]
         L.orc_set_gks_steps.restype = C.c_int
@@ -147,13 +151,13 @@ def _v(a, n):
     return a
 
 
-def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2, gks=False, K=0):
+def flux_interior(Wl, Wr, rhohl, rhohr, n, dt, mu_ref, omega, c2, gks=False, K=0, qsh=0.0):
     """gks: the wave-only flux of the start phase (the waves carry all of the hydro part);
-    K: internal degrees of freedom of the gas."""
+    K: internal degrees of freedom of the gas; qsh: the Shakhov term (1 - Pr) q_f . n."""
     F = np.zeros(5)
     Wl, Wr, n = _v(Wl, 5), _v(Wr, 5), _v(n, 3)
     lib().orc_flux_interior(_p(Wl, C.c_double), _p(Wr, C.c_double), rhohl, rhohr, _p(n, C.c_double), dt,
-                            mu_ref, omega, c2, int(bool(gks)), int(K), _p(F, C.c_double))
+                            mu_ref, omega, c2, int(bool(gks)), int(K), float(qsh), _p(F, C.c_double))
     return F
 
 
@@ -176,13 +180,13 @@ def mvec(p, q, r, a, rng, un, v, w, lam, K=0):
     return out
 
 
-def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2, gks=False, K=0):
-    """Second-order interior flux; G[k][d] = dW_k/dx_d ([5][3])."""
+def flux2_interior(Wl, Wr, Whl, Whr, Gl, Gr, Ghl, Ghr, n, dt, mu_ref, omega, c2, gks=False, K=0, qsh=0.0):
+    """Second-order interior flux; G[k][d] = dW_k/dx_d ([5][3]); qsh as in flux_interior."""
     F = np.zeros(5)
     args = [_v(Wl, 5), _v(Wr, 5), _v(Whl, 5), _v(Whr, 5), _v(Gl, 15), _v(Gr, 15), _v(Ghl, 15), _v(Ghr, 15)]
     n = _v(n, 3)
     lib().orc_flux2_interior(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             int(bool(gks)), int(K), _p(F, C.c_double))
+                             int(bool(gks)), int(K), float(qsh), _p(F, C.c_double))
     return F
 
 
@@ -195,12 +199,12 @@ def flux2_specular(W, Wh, G, Gh, n, dt, mu_ref, omega, c2, gks=False, K=0):
     return F
 
 
-def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2, gks=False, K=0):
+def flux2_farfield(W, Wh, G, Gh, Winf, n, dt, mu_ref, omega, c2, gks=False, K=0, qsh=0.0):
     F = np.zeros(5)
     args = [_v(W, 5), _v(Wh, 5), _v(G, 15), _v(Gh, 15), _v(Winf, 5)]
     n = _v(n, 3)
     lib().orc_flux2_farfield(*[_p(a, C.c_double) for a in args], _p(n, C.c_double), dt, mu_ref, omega, c2,
-                             int(bool(gks)), int(K), _p(F, C.c_double))
+                             int(bool(gks)), int(K), float(qsh), _p(F, C.c_double))
     return F
 
 
@@ -241,6 +245,21 @@ def gp_eval(W, gW, tau, dt, K, u, e=None):
     lib().orc_gp_eval(_p(W, C.c_double), _p(gW, C.c_double), float(tau), float(dt), int(K), n, _p(u, C.c_double),
                       _p(e, C.c_double), C.byref(a), C.byref(B), _p(w, C.c_double))
     return a.value, B.value, w
+
+
+def shakhov_eval(W, T, q, pr, X):
+    """Shakhov weight of one cell (Pr != 1): (a, B, (a . X)(|X|^2 - 5) at the points X[n][3]),
+    a = (1 - Pr) q / (5 rho T^(3/2))."""
+    W = _v(W, 5)
+    q = _v(q, 3)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 3)
+    n = X.shape[0]
+    a = np.zeros(3)
+    w = np.zeros(n)
+    B = C.c_double(0)
+    lib().orc_shakhov_eval(_p(W, C.c_double), float(T), _p(q, C.c_double), float(pr), n, _p(X, C.c_double),
+                           _p(a, C.c_double), C.byref(B), _p(w, C.c_double))
+    return a, B.value, w
 
 
 class OracleError(RuntimeError):
@@ -286,6 +305,10 @@ class Oracle:
             rc = L.orc_set_internal_dof(self.h, K)
         if rc == OK:
             rc = L.orc_set_gks_steps(self.h, int(getattr(params, "gks_steps", 0)))
+        if rc == OK:
+            # 0 (the library's default) and 1 both select the BGK model
+            pr = float(getattr(params, "prandtl", 1.0))
+            rc = L.orc_set_prandtl(self.h, 1.0 if pr == 0.0 else pr)
         if rc != OK:
             raise OracleError(f"orc_set_sampling failed with status {rc}")
         self.nc = int(L.orc_n_cells(self.h))
@@ -398,6 +421,12 @@ class Oracle:
         if rc != OK:
             raise OracleError(f"orc_gradients failed with status {rc}")
         return gW, gH, Wh
+
+    def heat_flux(self):
+        """Heat flux of the gas per cell ([nc][3]) for the current state (Shakhov model)."""
+        q = np.zeros((self.nc, 3))
+        self.L.orc_heat_flux(self.h, _p(q, C.c_double))
+        return q
 
     def sample_only(self):
         """Test hook: run the cell phase and the sampling of the current step only."""

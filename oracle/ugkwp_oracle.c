@@ -247,6 +247,18 @@ static void rotate_back(const double Ff[5], const double n[3], const double t1[3
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Shakhov model (Pr != 1).  The state the particles relax to is                           */
+/*   g^+ = g [1 + (1 - Pr) c.q (|c|^2 / T - 5) / (5 p T)],  c = u - U, p = rho T (R = 1, K = 0), */
+/* q the heat flux of the gas.  Reading: in the interface distribution the g0 term becomes    */
+/* g0^+ (the slope and time-derivative terms keep the Maxwellian).  Over all velocities the    */
+/* correction carries no mass and no momentum (its weight is odd in c and <c_i c_j (|c|^2/T -  */
+/* 5)> = 0) and the energy flux (1 - Pr) q.n (from <c_n^2 |c|^2> = 5 T^2 and <c_n^2 |c|^4> =   */
+/* 35 T^3 per unit density), whatever rho0, U0 and T0 are.  So F^eq gains q1 qsh in its        */
+/* energy component, qsh = (1 - Pr) q_f.n with q_f the heat flux at the face (see orc_step).  */
+/* qsh = 0 leaves the BGK flux untouched.                                                    */
+/* ------------------------------------------------------------------------------------ */
+
+/* ------------------------------------------------------------------------------------ */
 /* First-order interface flux of the wave part over dt, per unit area, global frame:      */
 /*   F = F^eq + F^{fr,wave}                                                               */
 /*   F^eq      = rho0 q1 <u_n psi>_0           (g0 from the upwind moments of both sides)  */
@@ -255,7 +267,7 @@ static void rotate_back(const double Ff[5], const double n[3], const double t1[3
 /* rhoh_l, rhoh_r: density of the hydro Maxwellian (U and T of the total state).           */
 /* ------------------------------------------------------------------------------------ */
 static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rhohr, double dt,
-                      double mu_ref, double omega, double c2, int gks, double Ff[5])
+                      double mu_ref, double omega, double c2, int gks, double qsh, double Ff[5])
 {
     double ml[NMOM], mr[NMOM], Hl[5], Gl[5], Hr[5], Gr[5];
     orc_moments(+1, l->un, l->lam, ml);
@@ -282,16 +294,17 @@ static void flux_pair(const prim_t *l, const prim_t *r, double rhohl, double rho
     psi_moments(&z, m0, H0, G0);
     for (int k = 0; k < 5; ++k)
         Ff[k] = q[0] * z.rho * G0[k] + q[3] * (rhohl * Gl[k] + rhohr * Gr[k]);
+    if (qsh != 0.0) Ff[4] = Ff[4] + q[0] * qsh;
 }
 
 void orc_flux_interior(const double Wl[5], const double Wr[5], double rhohl, double rhohr,
                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K,
-                       double F[5])
+                       double qsh, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     prim_t l = to_frame(Wl, n, t1, t2, K), r = to_frame(Wr, n, t1, t2, K);
-    flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, gks, Ff);
+    flux_pair(&l, &r, rhohl, rhohr, dt, mu_ref, omega, c2, gks, qsh, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
@@ -305,7 +318,7 @@ void orc_flux_specular(const double W[5], double rhoh, const double n[3], double
     prim_t l = to_frame(W, n, t1, t2, K);
     prim_t g = l;
     g.un = -l.un;
-    flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, gks, Ff);
+    flux_pair(&l, &g, rhoh, rhoh, dt, mu_ref, omega, c2, gks, 0.0, Ff);
     Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -528,7 +541,7 @@ typedef struct {
  *   F^wave = sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e / 2) <u (u a~_n + v a~_t1 + w a~_t2) . psi psi>_s]
  *   over the half spaces, with a~ the slopes of W~^h. */
 static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_ref, double omega, double c2,
-                       int gks, double Ff[5])
+                       int gks, double qsh, double Ff[5])
 {
     poly_t one, pu, pv, pw, puu, puv, puw;
     poly_mono(0, 0, 0, &one);
@@ -592,6 +605,7 @@ static void flux2_pair(const side_t *L, const side_t *R, double dt, double mu_re
         mvec(&puw, ah[2], range, h, Y2);
         for (int k = 0; k < 5; ++k) Ff[k] += h->rho * (q[3] * Gh[k] + q[4] * (Y0[k] + Y1[k] + Y2[k]));
     }
+    if (qsh != 0.0) Ff[4] = Ff[4] + q[0] * qsh;
 }
 
 /* derivatives of a conservative state along n, t1, t2 from its gradient G[k][d] (global
@@ -632,14 +646,15 @@ static void make_side(const double W[5], const double G[15], const double Wh[5],
  * states Whl, Whr (conservative), gradients G[k][d] = dW_k/dx_d of each. */
 void orc_flux2_interior(const double Wl[5], const double Wr[5], const double Whl[5], const double Whr[5],
                         const double Gl[15], const double Gr[15], const double Ghl[15], const double Ghr[15],
-                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K, double F[5])
+                        const double n[3], double dt, double mu_ref, double omega, double c2, int gks, int K,
+                        double qsh, double F[5])
 {
     double t1[3], t2[3], Ff[5];
     face_frame(n, t1, t2);
     side_t L, R;
     make_side(Wl, Gl, Whl, Ghl, n, t1, t2, K, &L);
     make_side(Wr, Gr, Whr, Ghr, n, t1, t2, K, &R);
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, qsh, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
@@ -664,7 +679,7 @@ void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15
             R.dWh[d][k] = sd * sk * L.dWh[d][k];
         }
     }
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, 0.0, Ff);
     Ff[0] = 0.0; Ff[2] = 0.0; Ff[3] = 0.0; Ff[4] = 0.0;
     rotate_back(Ff, n, t1, t2, F);
 }
@@ -672,7 +687,7 @@ void orc_flux2_specular(const double W[5], const double Wh[5], const double G[15
 /* Far field at second order: the free stream with zero gradients as the right side. */
 void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15], const double Gh[15],
                         const double Winf[5], const double n[3], double dt, double mu_ref, double omega,
-                        double c2, int gks, int K, double F[5])
+                        double c2, int gks, int K, double qsh, double F[5])
 {
     double t1[3], t2[3], Ff[5], zero[15];
     memset(zero, 0, sizeof(zero));
@@ -680,7 +695,7 @@ void orc_flux2_farfield(const double W[5], const double Wh[5], const double G[15
     side_t L, R;
     make_side(W, G, Wh, Gh, n, t1, t2, K, &L);
     make_side(Winf, zero, Winf, zero, n, t1, t2, K, &R);
-    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, Ff);
+    flux2_pair(&L, &R, dt, mu_ref, omega, c2, gks, qsh, Ff);
     rotate_back(Ff, n, t1, t2, F);
 }
 
@@ -729,7 +744,11 @@ typedef struct oracle {
     int64_t gks_steps;   /* the steps n < gks_steps (counted from orc_set_state) are wave-only:
                             no particle is sampled or enters, the waves carry all of W^h */
     int sampling;        /* hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b);
-                            1 the energy-exact variant (one factor per cell on the deviations) */
+                            1 the energy-exact variant (one factor per cell on the deviations);
+                            2 the first-order g_p; 3 independent draws from the equilibrium of
+                            the collision model (see phase_sample) */
+    double pr;           /* Prandtl number of the collision model: 1 the BGK model of the paper,
+                            otherwise the Shakhov model (see shakhov_setup) */
     int64_t *fown, *fnb; /* fnb: neighbour cell or -1 - bc index */
     double *fn, *farea;
     int nbc;
@@ -830,6 +849,7 @@ oracle_t *orc_create(int64_t n_nodes, const double *xyz, int64_t n_cells, const 
     o->tE = (double *)xcalloc(5 * nc, sizeof(double));
     o->tS = (double *)xcalloc(5 * nc, sizeof(double));
     o->avg_from = -1;
+    o->pr = 1.0;
     o->avg_res = INFINITY;
     o->nleft = (int64_t *)xcalloc(nc, sizeof(int64_t));
     o->nbc = n_bc;
@@ -1171,13 +1191,25 @@ int orc_set_internal_dof(oracle_t *o, int K)
 }
 
 /* sampling of the hydro particles' velocities: 0 as printed in Sec. 2.4(b) (default), 1 the
-   energy-exact variant (a departure from the paper, see phase_sample) */
+   energy-exact variant (a departure from the paper), 2 the first-order g_p, 3 independent
+   draws from the equilibrium of the collision model (see phase_sample) */
 int orc_set_sampling(oracle_t *o, int mode)
 {
-    if (mode < 0 || mode > 2) return ORC_E_ARG;
+    if (mode < 0 || mode > 3) return ORC_E_ARG;
     /* the first-order g_p needs the cell gradients of the reconstruction */
     if (mode == 2 && o->recon == 0) return ORC_E_ARG;
     o->sampling = mode;
+    return ORC_OK;
+}
+
+/* Collision model: Pr = 1 is the BGK model the paper builds the method on (Sec. 2.1); any other
+   0 < Pr < 2 selects the Shakhov model, one of the relaxation models the paper names in its
+   place (Sec. 2.1, Sec. 5), for a monatomic gas only (K = 0) and with the hydro particles drawn
+   one by one (sampling 2 or 3: pairs U +- sqrt(T) X carry no heat flux); checked by orc_step. */
+int orc_set_prandtl(oracle_t *o, double pr)
+{
+    if (!(pr > 0.0 && pr < 2.0)) return ORC_E_ARG;
+    o->pr = pr;
     return ORC_OK;
 }
 
@@ -1429,13 +1461,37 @@ typedef struct {
     double *tau, *ec, *rhoh, *U, *T;
     double *Wh;      /* [nc][5] hydro state (rho^h / rho) W (second order) */
     double *gW, *gH; /* [nc][5][3] limited gradients of W and of the hydro state */
+    double *qh;      /* [nc][3] heat flux of the gas (Shakhov model only) */
 } cellq_t;
 
 static void cellq_free(cellq_t *q)
 {
     free(q->tau); free(q->ec); free(q->rhoh); free(q->U); free(q->T);
-    free(q->Wh); free(q->gW); free(q->gH);
+    free(q->Wh); free(q->gW); free(q->gH); free(q->qh);
 }
+
+/* Heat flux of the gas in each cell at the start of a step (Shakhov model):
+ *   q = (1/Omega) sum_k m_k c_k |c_k|^2 / 2,  c_k = u_k - U,
+ * over the particles in the cell, U = (W_1, W_2, W_3) / W_0 the cell's velocity (K = 0).
+ * Reading: the hydro part is a Maxwellian at the cell's U and T (the law it is sampled from)
+ * and carries none.  Summed in particle order. */
+static void cell_heat_flux(const oracle_t *o, double *qh)
+{
+    memset(qh, 0, sizeof(double) * 3 * o->nc);
+    for (int64_t i = 0; i < o->np; ++i) {
+        const int64_t c = o->pc[i];
+        const double *W = o->W + 5 * c;
+        double cv[3];
+        for (int d = 0; d < 3; ++d) cv[d] = o->pu[3 * i + d] - W[1 + d] / W[0];
+        const double h = 0.5 * o->pm[i] * (cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2]);
+        for (int d = 0; d < 3; ++d) qh[3 * c + d] += h * cv[d];
+    }
+    for (int64_t c = 0; c < o->nc; ++c)
+        for (int d = 0; d < 3; ++d) qh[3 * c + d] = qh[3 * c + d] / o->vol[c];
+}
+
+/* the cells' heat fluxes for the current state (test hook) */
+void orc_heat_flux(const oracle_t *o, double *qh) { cell_heat_flux(o, qh); }
 
 /* Primitives, relaxation time tau = mu_ref T^omega / p (Eq. tau_via_T_ref, T_ref = 1), the
  * time step dt = CFL min Omega / sum_d (|U_d| + 3 sqrt(T)) dS_d (Sec. 2.4(a)), the hydro
@@ -1735,10 +1791,33 @@ void orc_gp_eval(const double W[5], const double gW[15], double tau, double dt, 
     for (int64_t i = 0; i < n; ++i) w[i] = gp_weight(&gp, u + 3 * i, e[i]);
 }
 
-/* one hydro particle from g_p (sampling = 2): its velocity and internal energy */
-static void gp_draw(const oracle_t *o, const gp_t *gp, uint64_t uid, const double U[3], double T, double u[3],
-                    double *e)
+/* Shakhov weight of a hydro particle (Pr != 1): with X = (u - U)/sqrt(T) the equilibrium g^+
+ * of the Shakhov model (see flux_pair) is g [1 + (a.X)(|X|^2 - 5)], a = (1 - Pr) q / (5 rho
+ * T^(3/2)), q the cell's heat flux, rho and T the cell's.  Reading: the hydro part is drawn from
+ * it with the cell's U and T, like the Maxwellian it replaces (sampling 3), or with the
+ * correction added to that of g_p (sampling 2).  B bounds |(a.X)(|X|^2 - 5)| on |X| <= 4, where
+ * the largest value is 4 (16 - 5) |a|; beyond, the law is clipped (P(|X| > 4) = 1.1e-3). */
+typedef struct { double a[3], B; } sh_t;
+
+static void shakhov_setup(const double W[5], double T, const double q[3], double pr, sh_t *s)
 {
+    const double f = (1.0 - pr) / (5.0 * W[0] * T * sqrt(T));
+    for (int d = 0; d < 3; ++d) s->a[d] = f * q[d];
+    s->B = 44.0 * sqrt(s->a[0] * s->a[0] + s->a[1] * s->a[1] + s->a[2] * s->a[2]);
+}
+
+static double shakhov_term(const sh_t *s, const double X[3])
+{
+    return (s->a[0] * X[0] + s->a[1] * X[1] + s->a[2] * X[2]) * ((X[0] * X[0] + X[1] * X[1] + X[2] * X[2]) - 5.0);
+}
+
+/* one hydro particle drawn by itself (sampling 2: gp, else NULL; the Shakhov model: sh, else
+ * NULL): proposals u = U + sqrt(T) X, accepted when eta B < w, w = (1 + alpha (...) of g_p, or 1)
+ * + (a.X)(|X|^2 - 5), B = (B of g_p, or 1) + B of sh; its velocity and internal energy */
+static void hydro_draw(const oracle_t *o, const gp_t *gp, const sh_t *sh, uint64_t uid, const double U[3], double T,
+                       double u[3], double *e)
+{
+    const double B = (gp ? gp->B : 1.0) + (sh ? sh->B : 0.0);
     for (int j = 0; j < GP_ATTEMPTS; ++j) {
         double ev[4], ea[4];
         draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j, o->inst, ev);
@@ -1747,8 +1826,21 @@ static void gp_draw(const oracle_t *o, const gp_t *gp, uint64_t uid, const doubl
         for (int d = 0; d < 3; ++d) u[d] = U[d] + sqrt(T) * X[d];
         *e = o->K > 0 ? internal_energy(o->seed, uid, o->step, TAG_INT, 2u * (uint32_t)j, o->inst, o->K, T) : 0.0;
         draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j + 1u, o->inst, ea);
-        if (ea[0] * gp->B < gp_weight(gp, u, *e)) return;
+        double w = gp ? gp_weight(gp, u, *e) : 1.0;
+        if (sh) w = w + shakhov_term(sh, X);
+        if (ea[0] * B < w) return;
     }
+}
+
+/* the Shakhov weight of one cell, for the tests: a, B, and (a.X)(|X|^2 - 5) at n points X[n][3] */
+void orc_shakhov_eval(const double W[5], double T, const double q[3], double pr, int64_t n, const double *X,
+                      double *a, double *B, double *w)
+{
+    sh_t s;
+    shakhov_setup(W, T, q, pr, &s);
+    for (int d = 0; d < 3; ++d) a[d] = s.a[d];
+    *B = s.B;
+    for (int64_t i = 0; i < n; ++i) w[i] = shakhov_term(&s, X + 3 * i);
 }
 
 /* Hydro particles sampled at the start of the step (Sec. 2.4(b)), appended after the old
@@ -1797,14 +1889,17 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
         double rhohp = q->ec[c] * q->rhoh[c];
         double msam = rhohp * o->vol[c] / ns;
         double sT = sqrt(q->T[c]);
-        if (o->sampling == 2) {
+        if (o->sampling >= 2) {
             gp_t gp;
-            gp_setup(o->W + 5 * c, q->gW + 15 * c, q->tau[c], q->dt, o->K, &gp);
+            sh_t sh;
+            if (o->sampling == 2) gp_setup(o->W + 5 * c, q->gW + 15 * c, q->tau[c], q->dt, o->K, &gp);
+            if (o->pr != 1.0) shakhov_setup(o->W + 5 * c, q->T[c], q->qh + 3 * c, o->pr, &sh);
             for (int64_t k = 0; k < ns; ++k) {
                 const int64_t i = first[c] + k;
                 const uint64_t uid = orc_make_uid(0, o->step, c, k);
                 double e = 0.0;
-                gp_draw(o, &gp, uid, q->U + 3 * c, q->T[c], o->pu + 3 * i, &e);
+                hydro_draw(o, o->sampling == 2 ? &gp : NULL, o->pr != 1.0 ? &sh : NULL, uid, q->U + 3 * c, q->T[c],
+                           o->pu + 3 * i, &e);
                 place_in_cell(o, c, uid, o->px + 3 * i);
                 o->pm[i] = msam;
                 o->pc[i] = c;
@@ -1967,8 +2062,6 @@ static int phase_inject(oracle_t *o, double dt, double **tin, int **ein, int64_t
     return ORC_OK;
 }
 
-/* Test hook: the cell phase and the sampling of the current step only (the new particles are
- * appended at their sampled positions; nothing streams and the step does not advance). */
 /* Test hook: the limited gradients of W and of the hydro state for the current state
  * ([nc][5][3] each) and the hydro state ([nc][5]); nothing advances. */
 int orc_gradients(oracle_t *o, double *gW, double *gH, double *Wh)
@@ -1986,12 +2079,18 @@ int orc_gradients(oracle_t *o, double *gW, double *gH, double *Wh)
     return st;
 }
 
+/* Test hook: the cell phase and the sampling of the current step only (the new particles are
+ * appended at their sampled positions; nothing streams and the step does not advance). */
 int orc_sample_only(oracle_t *o, double *dt)
 {
     cellq_t q = {0};
     int st = phase_cells(o, &q);
     int64_t ns = 0;
     if (st == ORC_OK && o->recon) phase_grad(o, &q);
+    if (st == ORC_OK && o->pr != 1.0) {
+        q.qh = (double *)xcalloc(3 * o->nc, sizeof(double));
+        cell_heat_flux(o, q.qh);
+    }
     if (st == ORC_OK) st = phase_sample(o, &q, NULL, &ns);
     *dt = q.dt;
     o->st_sampled = ns;
@@ -2040,10 +2139,18 @@ int orc_step(oracle_t *o)
     int64_t *nl = (int64_t *)xcalloc(nc, sizeof(int64_t));
     double *tin = NULL;
     int *ein = NULL;
-    int status = phase_cells(o, &q);
+    int status = ORC_OK;
+    /* the Shakhov model is built for a monatomic gas and drawn particle by particle */
+    if (o->pr != 1.0 && (o->K != 0 || o->sampling < 2)) status = ORC_E_ARG;
+    if (status == ORC_OK) status = phase_cells(o, &q);
     if (status != ORC_OK) goto done;
     const double dt = q.dt;
     o->st_dt = dt;
+    const double pr = o->pr;
+    if (pr != 1.0) {
+        q.qh = (double *)xcalloc(3 * nc, sizeof(double));
+        cell_heat_flux(o, q.qh);
+    }
 
     if (o->recon) phase_grad(o, &q);
     const int gks = o->step < o->gks_steps;
@@ -2054,6 +2161,16 @@ int orc_step(oracle_t *o)
         int64_t c = o->fown[f], nb = o->fnb[f];
         const double *n = o->fn + 3 * f;
         double F[5];
+        /* Shakhov model: the heat flux at the face is the mean of the two cells' (a far-field
+           face: the free stream's is zero); walls keep the BGK flux (reading) */
+        double qsh = 0.0;
+        if (pr != 1.0 && (nb >= 0 || o->bc[-1 - nb].type == BC_FARFIELD)) {
+            const double *qa = q.qh + 3 * c, zero[3] = {0.0, 0.0, 0.0};
+            const double *qb = nb >= 0 ? q.qh + 3 * nb : zero;
+            const double qn = (0.5 * (qa[0] + qb[0])) * n[0] + (0.5 * (qa[1] + qb[1])) * n[1] +
+                              (0.5 * (qa[2] + qb[2])) * n[2];
+            qsh = (1.0 - pr) * qn;
+        }
         if (o->recon) {
             /* second order: states extrapolated to the face centre from both sides */
             const double *xf = o->fx + 3 * f;
@@ -2065,7 +2182,7 @@ int orc_step(oracle_t *o)
                 extrap(o->W + 5 * nb, q.gW + 15 * nb, o->xc + 3 * nb, xf, Wr);
                 extrap(q.Wh + 5 * nb, q.gH + 15 * nb, o->xc + 3 * nb, xf, Whr);
                 orc_flux2_interior(Wl, Wr, Whl, Whr, q.gW + 15 * c, q.gW + 15 * nb, q.gH + 15 * c, q.gH + 15 * nb, n,
-                                   dt, o->mu_ref, o->omega, o->c2, gks, o->K, F);
+                                   dt, o->mu_ref, o->omega, o->c2, gks, o->K, qsh, F);
             } else {
                 const obc_t *b = o->bc + (-1 - nb);
                 if (b->type == BC_SPECULAR)
@@ -2076,11 +2193,11 @@ int orc_step(oracle_t *o)
                                      gks, o->K, F);
                 else
                     orc_flux2_farfield(Wl, Whl, q.gW + 15 * c, q.gH + 15 * c, b->Winf, n, dt, o->mu_ref, o->omega,
-                                       o->c2, gks, o->K, F);
+                                       o->c2, gks, o->K, qsh, F);
             }
         } else if (nb >= 0) {
             orc_flux_interior(o->W + 5 * c, o->W + 5 * nb, q.rhoh[c], q.rhoh[nb], n, dt, o->mu_ref, o->omega,
-                              o->c2, gks, o->K, F);
+                              o->c2, gks, o->K, qsh, F);
         } else {
             const obc_t *b = o->bc + (-1 - nb);
             if (b->type == BC_SPECULAR)
@@ -2089,7 +2206,7 @@ int orc_step(oracle_t *o)
                 orc_flux_diffuse(o->W + 5 * c, q.rhoh[c], q.tau[c], n, dt, b->Tw, b->Uw, gks, o->K, F);
             else
                 orc_flux_interior(o->W + 5 * c, b->Winf, q.rhoh[c], b->Winf[0], n, dt, o->mu_ref, o->omega,
-                                  o->c2, gks, o->K, F);
+                                  o->c2, gks, o->K, qsh, F);
         }
         for (int k = 0; k < 5; ++k) Phi[5 * f + k] = F[k] * o->farea[f];
     }

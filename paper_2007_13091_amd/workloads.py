@@ -81,9 +81,12 @@ class Params:
     venkat_k: float = 1.0   # Venkatakrishnan constant K
     sampling: int = 0       # hydro-particle velocities: 0 the pairs U +- sqrt(T) X of Sec. 2.4(b),
                             # 1 the energy-exact variant (one factor per cell on the deviations),
-                            # 2 the first-order g_p of Sec. 2.3 (needs recon 1 or 2)
+                            # 2 the first-order g_p of Sec. 2.3 (needs recon 1 or 2),
+                            # 3 independent draws from the collision model's equilibrium
     gks_steps: int = 0      # steps from the initial state run wave-only (no particles): the
                             # continuum start of the paper's hypersonic cases
+    prandtl: float = 1.0    # collision model: 1 the BGK model of the paper, otherwise the Shakhov
+                            # model with this Prandtl number (K = 0, sampling 2 or 3)
 
 
 def mu_ref_from_kn(kn: float, omega: float) -> float:
