@@ -132,7 +132,10 @@ typedef struct {
                                  of the Maxwellian from the cell's limited gradients, weighted by
                                  alpha = dt / expm1(dt/tau) - tau), by acceptance-rejection per
                                  particle; needs recon 1 or 2 (else UGKWP_E_ARG); the sample
-                                 carries exactly the mass, its momentum and energy are random */
+                                 carries exactly the mass, its momentum and energy are random;
+                             3 = independent draws from the equilibrium of the collision model
+                                 (the Maxwellian, or the Shakhov g^+ when prandtl != 1), per
+                                 particle; any recon */
     int32_t gks_steps;    /* wave-only start: the steps n < gks_steps, counted from
                              ugkwp_init_state, sample no particle and let no free-stream particle
                              enter; their wave flux carries the whole free transport of W^h,
@@ -142,6 +145,17 @@ typedef struct {
                              the gas-kinetic scheme alone.  While no particle exists (from
                              ugkwp_init_state, or an imported state without particles) these
                              steps skip the particle kernels, with the same results.  0 = off */
+    double prandtl;       /* collision model (Sec. 2.1 names the alternatives to BGK; Sec. 4.3 and
+                             Sec. 5 the Shakhov model as the remedy for the BGK model's Prandtl
+                             number of 1): 0 or 1 = the BGK model of the paper; 0 < Pr < 2 else
+                             = the Shakhov model with that Prandtl number, for a monatomic gas
+                             (gamma 5/3) with sampling 2 or 3 (else UGKWP_E_ARG).  Its equilibrium
+                             is g^+ = g [1 + (1 - Pr) c.q (|c|^2/T - 5) / (5 p T)], c = u - U, with
+                             q the heat flux of the cell's particles at the start of the step:
+                             the hydro particles are drawn from g^+ (or g_p plus that correction),
+                             and the g0 term of the wave flux becomes g0^+, which adds
+                             q1 (1 - Pr) q_f.n to its energy flux (q_f the mean of the two cells'
+                             heat fluxes; walls keep the BGK flux) */
 } ugkwp_params;
 
 /* Statistics of a step.  For a batch, ugkwp_step reports the counts summed over the

@@ -149,7 +149,8 @@ struct Carver {
 };
 
 // Lay the workspace out; with base == nullptr only the size is computed.
-size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, int K, Dev &D, char *base) {
+size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, int K, bool shakhov, Dev &D,
+             char *base) {
     Carver C{base};
     D.ip = C.take<ugkwp::InstP>((size_t)n_inst);
     D.is = C.take<ugkwp::InstS>((size_t)n_inst);
@@ -178,6 +179,7 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     D.Wh = recon ? C.take<double>(5 * nc) : nullptr;
     D.gW = recon ? C.take<double>(15 * nc) : nullptr;
     D.gH = recon ? C.take<double>(15 * nc) : nullptr;
+    D.qh = shakhov ? C.take<double>(3 * nc) : nullptr;
     const size_t nff = (size_t)H.nff;
     D.ffi = C.take<int4>(nff);
     D.ffg = C.take<double>(10 * nff);
@@ -228,6 +230,9 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     return (C.off + 255) & ~size_t(255);
 }
 
+// the Prandtl number of an instance's collision model: 0 (the default) and 1 are the BGK model
+double prandtl_of(const ugkwp_params &p) { return p.prandtl == 0.0 ? 1.0 : p.prandtl; }
+
 // internal degrees of freedom of gamma = (K + 5)/(K + 3), or -1 if gamma is not of that form
 int internal_dof(double gamma) {
     if (!(gamma > 1.0)) return -1;
@@ -259,9 +264,20 @@ int32_t check_params(const ugkwp_params &p, int64_t nc, long long &cap, std::str
         err = "params: gks_steps must be >= 0";
         return UGKWP_E_ARG;
     }
-    if (p.sampling < 0 || p.sampling > 2 || (p.sampling == 2 && p.recon == 0)) {
-        err = "params: sampling is 0 (the pairs of Sec. 2.4(b)), 1 (energy-exact pairs) or 2 (first-order g_p of "
-              "Sec. 2.3, which needs recon 1 or 2 for the cell gradients)";
+    if (p.sampling < 0 || p.sampling > 3 || (p.sampling == 2 && p.recon == 0)) {
+        err = "params: sampling is 0 (the pairs of Sec. 2.4(b)), 1 (energy-exact pairs), 2 (first-order g_p of "
+              "Sec. 2.3, which needs recon 1 or 2 for the cell gradients) or 3 (independent draws from the "
+              "equilibrium of the collision model)";
+        return UGKWP_E_ARG;
+    }
+    const double pr = prandtl_of(p);
+    if (!(pr > 0.0 && pr < 2.0)) {
+        err = "params: prandtl must be 0 or 1 (the BGK model) or lie in (0, 2) (the Shakhov model)";
+        return UGKWP_E_ARG;
+    }
+    if (pr != 1.0 && (internal_dof(p.gamma) != 0 || p.sampling < 2)) {
+        err = "params: the Shakhov model (prandtl != 1) is built for a monatomic gas (gamma 5/3) and draws its "
+              "hydro particles one by one (sampling 2 or 3)";
         return UGKWP_E_ARG;
     }
     long long c = p.capacity;
@@ -388,9 +404,12 @@ int32_t ugkwp_workspace_bytes(const ugkwp_mesh *m, int32_t n_inst, const ugkwp_p
     int32_t st = prepare_batch(m, n_inst, p, H, ranges, cap, err);
     if (st != UGKWP_OK) return fail(nullptr, st, err);
     Dev D{};
-    bool recon = false;
-    for (int32_t k = 0; k < n_inst; ++k) recon = recon || p[k].recon != 0;
-    *bytes = carve(H, n_inst, cap, p[0].precision, recon, internal_dof(p[0].gamma), D, nullptr);
+    bool recon = false, shakhov = false;
+    for (int32_t k = 0; k < n_inst; ++k) {
+        recon = recon || p[k].recon != 0;
+        shakhov = shakhov || prandtl_of(p[k]) != 1.0;
+    }
+    *bytes = carve(H, n_inst, cap, p[0].precision, recon, internal_dof(p[0].gamma), shakhov, D, nullptr);
     return UGKWP_OK;
 }
 
@@ -414,13 +433,14 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     ctx->ws = (char *)dev_workspace;
     ctx->ws_bytes = ws_bytes;
     Dev &D = ctx->D;
-    bool recon_any = false, recon_all = true;
+    bool recon_any = false, recon_all = true, shakhov = false;
     for (int32_t k = 0; k < n_inst; ++k) {
         recon_any = recon_any || p[k].recon != 0;
         recon_all = recon_all && p[k].recon != 0;
+        shakhov = shakhov || prandtl_of(p[k]) != 1.0;
     }
     const int K = internal_dof(p[0].gamma);
-    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, recon_any, K, D, ctx->ws);
+    size_t need = carve(ctx->H, n_inst, cap, p[0].precision, recon_any, K, shakhov, D, ctx->ws);
     if (ws_bytes < need) {
         delete ctx;
         return fail(nullptr, UGKWP_E_ARG, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -435,7 +455,11 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     D.recon_any = recon_any ? 1 : 0;
     D.recon_all = recon_all ? 1 : 0;
     D.gp_any = 0;
-    for (int k = 0; k < n_inst; ++k) D.gp_any = D.gp_any || p[k].sampling == 2;
+    D.sh_any = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        D.gp_any = D.gp_any || p[k].sampling >= 2;
+        D.sh_any = D.sh_any || prandtl_of(p[k]) != 1.0;
+    }
     D.any_diffuse = 0;
     for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
     D.cap = cap;
@@ -460,6 +484,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
         q.seed = p[k].seed;
         q.sampling = p[k].sampling;
         q.gks_steps = p[k].gks_steps;
+        q.pr = prandtl_of(p[k]);
         q.cell0 = r.cell0;
         q.cell1 = r.cell1;
         q.ff0 = r.ff0;

@@ -47,9 +47,11 @@ struct InstP {
     unsigned long long seed;
     int32_t cell0, cell1;  // cells [cell0, cell1)
     int32_t ff0, ff1;      // far-field faces [ff0, ff1)
-    int32_t sampling;      // hydro-particle velocities: 0 U +- sqrt(T) X (Sec. 2.4(b)), 1 energy-exact
+    int32_t sampling;      // hydro-particle velocities: 0 U +- sqrt(T) X (Sec. 2.4(b)), 1 energy-exact,
+                           // 2 first-order g_p, 3 independent draws from the equilibrium
     int32_t gks_steps;     // steps n < gks_steps of the instance are wave-only (no particles)
     long long bf0;         // its first input boundary face in the concatenated list
+    double pr;             // Prandtl number: 1 the BGK model, otherwise the Shakhov model
 };
 
 // Step state of one instance: its own time step, time and step counter, and the counts of
@@ -150,7 +152,8 @@ struct Dev {
     // parameters
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
     int32_t K;              // internal degrees of freedom of the gas (every instance)
-    int32_t gp_any;         // some instance samples from the first-order g_p (sampling 2)
+    int32_t gp_any;         // some instance draws its hydro particles one by one (sampling 2 or 3)
+    int32_t sh_any, pad2;   // some instance uses the Shakhov model (the heat-flux kernel runs)
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
     const InstP *ip;        // [n_inst]
@@ -168,6 +171,7 @@ struct Dev {
     double *Phi;            // [5][nf]
     double *Wh;             // [5][nc] hydro state (rho^h / rho) W (second order)
     double *gW, *gH;        // [15][nc] limited gradients dW_k/dx_d at [3k+d][nc] (second order)
+    double *qh;             // [3][nc] heat flux of the gas (Shakhov model)
     double *S;              // [5][nc] particle sums at the start of the step
     long long *nsam;        // [nc]
     long long *samoff;      // [nc+1]

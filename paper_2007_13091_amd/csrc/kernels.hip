@@ -270,9 +270,13 @@ __device__ __forceinline__ void qcoef(R dt, R tau, R &q1, R &q4m) {
 //   F = rho0 q1 <u_n psi>_0 + (q4 - dt e) (rhoh_l <u_n psi>_{l,u>0} + rhoh_r <u_n psi>_{r,u<0})
 // with g0 from the upwind moments of both sides and tau at the face from g0 plus the
 // numerical dissipation C2 |pl - pr| / (pl + pr) dt of Sec. 2.4(d).
+// Shakhov model (qsh != 0): the g0 term becomes g0^+ = g0 [1 + (1 - Pr) c.q (|c|^2/T - 5) / (5 p T)],
+// whose correction carries, over all velocities, no mass or momentum and the energy flux
+// (1 - Pr) q.n for any g0 (Gaussian moments <c_n^2 |c|^2> = 5 T^2, <c_n^2 |c|^4> = 35 T^3): F^eq
+// gains q1 qsh in energy, qsh = (1 - Pr) q_f.n with q_f the heat flux at the face (shakhov_qsh).
 template <typename R>
 __device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R hl, R hr, R dt, R mu_ref, R omega,
-                                          R c2, bool gks, R Ff[5]) {
+                                          R c2, bool gks, R qsh, R Ff[5]) {
     R ml[4], mr[4], Hl[5], Gl[5], Hr[5], Gr[5];
     moments4<R>(1, l.un, l.lam, ml);
     moments4<R>(-1, r.un, r.lam, mr);
@@ -299,6 +303,7 @@ __device__ __forceinline__ void flux_pair(const Prim<R> &l, const Prim<R> &r, R 
     psi_moments<R>(z, m0, H0, G0);
 #pragma unroll
     for (int k = 0; k < 5; ++k) Ff[k] = q1 * z.rho * G0[k] + q4m * (hl * Gl[k] + hr * Gr[k]);
+    if (qsh != (R)0) Ff[4] = Ff[4] + q1 * qsh;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -523,6 +528,25 @@ __device__ __forceinline__ void diffuse_flux(const Prim<R> &l, R h, R tau_c, con
     Ff[0] = (R)0;
 }
 
+// Shakhov term of face f (owner c, neighbour nb), FP64: (1 - Pr) q_f.n with the heat flux at the
+// face the mean of the two cells' (a far-field face: the free stream's is zero); walls keep the
+// BGK flux (0 here).  0 for Pr = 1.
+__device__ __forceinline__ double shakhov_qsh(const Dev &D, const InstP &P, int f, int c, int nb) {
+    if (P.pr == 1.0) return 0.0;
+    if (nb < 0 && D.bc[-1 - nb].type != 2) return 0.0;
+    const int nc = D.nc, nf = D.nf;
+    const double qa[3] = {D.qh[c], D.qh[nc + c], D.qh[2 * nc + c]};
+    double qb[3] = {0.0, 0.0, 0.0};
+    if (nb >= 0) {
+        qb[0] = D.qh[nb];
+        qb[1] = D.qh[nc + nb];
+        qb[2] = D.qh[2 * nc + nb];
+    }
+    const double qn = (0.5 * (qa[0] + qb[0])) * D.fn[f] + (0.5 * (qa[1] + qb[1])) * D.fn[nf + f] +
+                      (0.5 * (qa[2] + qb[2])) * D.fn[2 * nf + f];
+    return (1.0 - P.pr) * qn;
+}
+
 // ---------------------------------------------------------------------------------------
 // S2: wave flux per face, times the area, oriented owner -> neighbour.  Arithmetic in R
 // (FP32 form: float), inputs recovered from the FP64 state, result stored in FP64.
@@ -547,13 +571,14 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) Wl[k] = D.W[k * nc + c];
     const Prim<R> l = to_frame<R>(Wl, n, t1, t2, D.K);
+    const R qsh = (R)shakhov_qsh(D, P, f, c, nb);
     R Ff[5];
     if (nb >= 0) {
         double Wr[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) Wr[k] = D.W[k * nc + nb];
         const Prim<R> r = to_frame<R>(Wr, n, t1, t2, D.K);
-        flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, gks, Ff);
+        flux_pair<R>(l, r, (R)D.rhoh[c], (R)D.rhoh[nb], dt, mu, om, c2, gks, qsh, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
         if (bc.type == 0) {
@@ -561,7 +586,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
             Prim<R> g = l;
             g.un = -l.un;
             const R h = (R)D.rhoh[c];
-            flux_pair<R>(l, g, h, h, dt, mu, om, c2, gks, Ff);
+            flux_pair<R>(l, g, h, h, dt, mu, om, c2, gks, (R)0, Ff);
             Ff[0] = (R)0;
             Ff[2] = (R)0;
             Ff[3] = (R)0;
@@ -571,7 +596,7 @@ __global__ void __launch_bounds__(BS) k_flux(Dev D) {
         } else {
             // far field: the free stream as the right state (hydro density = its density)
             const Prim<R> r = to_frame<R>(bc.Winf, n, t1, t2, D.K);
-            flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, gks, Ff);
+            flux_pair<R>(l, r, (R)D.rhoh[c], (R)bc.Winf[0], dt, mu, om, c2, gks, qsh, Ff);
         }
     }
     const R a = (R)D.farea[f];
@@ -754,8 +779,10 @@ __device__ __forceinline__ void frame_derivs(const double *G, long long stride, 
 //   + rho_r <(a_r . psi) psi>_{<0}; Abar from <(u abar_n + v abar_t1 + w abar_t2 + Abar) . psi psi> = 0;
 //   F = rho0 [q1 <u psi> + q2 <u (u.abar) psi> + q3 <u Abar psi>]
 //     + sum_s rho^h_s [(q4 - dt e) <u psi>_s + (q5 + dt^2 e/2) <u (u.a~_s) psi>_s]
+// (Shakhov model: + q1 qsh in energy, as in flux_pair)
 template <typename R>
-__device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref, R omega, R c2, bool gks, R Ff[5]) {
+__device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref, R omega, R c2, bool gks, R qsh,
+                           R Ff[5]) {
     Mom3<R> ML, MR, M0;
     mom3<R>(1, L.g, ML);
     mom3<R>(-1, Rs.g, MR);
@@ -838,6 +865,7 @@ __device__ void flux2_pair(const Side2<R> &L, const Side2<R> &Rs, R dt, R mu_ref
 #pragma unroll
         for (int k = 0; k < 5; ++k) Ff[k] += S.h.rho * (q[3] * Gh[k] + q[4] * (acc[k] + Y[k]));
     }
+    if (qsh != (R)0) Ff[4] = Ff[4] + q[0] * qsh;
 }
 
 
@@ -1045,12 +1073,13 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
     extrap(D, c, xf, Wl, Whl);
     Side2<R> L, Rs;
     make_side<R>(D, c, Wl, Whl, n, t1, t2, L);
+    const R qsh = (R)shakhov_qsh(D, P, f, c, nb);
     R Ff[5];
     if (nb >= 0) {
         double Wr[5], Whr[5];
         extrap(D, nb, xf, Wr, Whr);
         make_side<R>(D, nb, Wr, Whr, n, t1, t2, Rs);
-        flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
+        flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, qsh, Ff);
     } else {
         const DevBC bc = D.bc[-1 - nb];
         if (bc.type == 0) {
@@ -1065,7 +1094,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
                     Rs.dW[d][k] = sg * L.dW[d][k];
                     Rs.dWh[d][k] = sg * L.dWh[d][k];
                 }
-            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, (R)0, Ff);
             Ff[0] = (R)0;
             Ff[2] = (R)0;
             Ff[3] = (R)0;
@@ -1080,7 +1109,7 @@ __global__ void __launch_bounds__(BS) k_flux2(Dev D) {
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int k = 0; k < 5; ++k) Rs.dW[d][k] = Rs.dWh[d][k] = (R)0;
-            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, Ff);
+            flux2_pair<R>(L, Rs, dt, mu, om, c2, gks, qsh, Ff);
         }
     }
     const R a = (R)D.farea[f];
@@ -1143,6 +1172,57 @@ __device__ __forceinline__ double load_e(const Particles &pa, long long i, doubl
 __device__ __forceinline__ float load_e(const Particles &pa, long long i, float) { return pa.e32[i]; }
 
 // ---------------------------------------------------------------------------------------
+// Shakhov model: the heat flux of the gas in each cell at the start of the step,
+//   q = (1/Omega) sum_k m_k c_k |c_k|^2 / 2,  c_k = u_k - U,  U = (W_1, W_2, W_3) / W_0,
+// over the particles the cell holds (the hydro part, a Maxwellian at the cell's U and T,
+// carries none); one wave per cell, FP64 sums with a fixed tree.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void load_um(const Particles &pa, long long i, double u[3], double &m, double) {
+    const double2 *r = reinterpret_cast<const double2 *>(pa.rec + i);
+    const double2 a = r[1], b = r[2], t = r[3];
+    u[0] = a.y;
+    u[1] = b.x;
+    u[2] = b.y;
+    m = t.x;
+}
+__device__ __forceinline__ void load_um(const Particles &pa, long long i, double u[3], double &m, float) {
+    const float4 *r = reinterpret_cast<const float4 *>(pa.rec32 + i);
+    const float4 a = r[0], b = r[1];
+    u[0] = (double)a.w;
+    u[1] = (double)b.x;
+    u[2] = (double)b.y;
+    m = (double)pa.m32[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_heat(Dev D, int buf) {
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int c = blockIdx.x * 4 + wave;
+    if (c >= D.nc) return;
+    const int nc = D.nc;
+    double h[3] = {0.0, 0.0, 0.0};
+    if (D.ip[inst_of(D, c)].pr != 1.0) {
+        const double W0 = D.W[c];
+        const double U[3] = {D.W[nc + c] / W0, D.W[2 * nc + c] / W0, D.W[3 * nc + c] / W0};
+        const long long s0 = D.segoff[buf][c], s1 = D.segoff[buf][c + 1];
+        const Particles pa = D.pa[buf];
+        for (long long i = s0 + lane; i < s1; i += kWave) {
+            double u[3], m;
+            load_um(pa, i, u, m, R(0));
+            const double cv[3] = {u[0] - U[0], u[1] - U[1], u[2] - U[2]};
+            const double e = 0.5 * m * (cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) h[d] += e * cv[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) h[d] = wave_sum(h[d]);
+    const double hk = lane == 1 ? h[1] : (lane == 2 ? h[2] : h[0]);
+    if (lane < 3) D.qh[lane * nc + c] = hk / D.vol[c];
+}
+
+// ---------------------------------------------------------------------------------------
 // S3: hydro particles, one wave per cell, lane l takes the particles l, l + 64, ...  Pair
 // (2p, 2p+1) shares X ~ N(0, I) from Box-Muller on the draw keyed by the even partner's id:
 // X0, X1 = r1 (cos, sin)(2 pi e1), r1 = sqrt(-2 ln e0), and X2 = r2 cos(2 pi e3), r2 =
@@ -1203,7 +1283,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     const int nc = D.nc;
     const Scalars *sc = D.sc;
     // cells of instances that sample the first-order g_p are k_sample_gp's
-    if (D.gp_any && D.ip[inst_of(D, c)].sampling == 2) return;
+    if (D.gp_any && D.ip[inst_of(D, c)].sampling >= 2) return;
     const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;  // even
     // S = P + the new particles' sums, lane k < 5 writing component k; a cell that samples
     // nothing copies P (loaded in the same round as its count)
@@ -1317,6 +1397,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
 // B = 1 + |alpha| (16 (sum_ij |G_ij| + |div U|) + ((3 + K) 16 + 5 + K)/2 4 sqrt(T) sum_j |d_j T| / T),
 // which bounds |1 + alpha p| wherever every normal is at most 4.  After 64 rejections the last
 // proposal is kept.  Positions as in k_sample.  One wave per cell; S = P + the new sums.
+// Sampling 3 takes the same draws from the equilibrium itself (weight 1, B = 1: the first
+// proposal).  The Shakhov model (Pr != 1) adds (a.X)(|X|^2 - 5) to the weight and 44 |a| to B.
 // ---------------------------------------------------------------------------------------
 template <typename R, bool KE>
 __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
@@ -1329,7 +1411,8 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
     const int nc = D.nc;
     const int inst = inst_of(D, c);
     const InstP &P = D.ip[inst];
-    if (P.sampling != 2) return;
+    if (P.sampling < 2) return;
+    const bool gp = P.sampling == 2, sh = P.pr != 1.0;
     const Scalars *sc = D.sc;
     const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1344,28 +1427,49 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
         const double rho = W[0], Ud[3] = {W[1] / rho, W[2] / rho, W[3] / rho};
         const double T = temp_k(W, K);
         // primitive gradients from the limited gradient of W: G[i][j] = d_j U_i, gT[j] = d_j T
+        // (sampling 2 only; sampling 3 draws from the equilibrium itself)
         double G[3][3], gT[3], sU = 0.0, divU = 0.0, sTg = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double dr = D.gW[j * nc + c];
-            double dU[3];
+            gT[j] = 0.0;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) dU[i] = (D.gW[(3 * (1 + i) + j) * nc + c] - Ud[i] * dr) / rho;
-            double dT = (D.gW[(12 + j) * nc + c] - W[4] / rho * dr) / rho - (Ud[0] * dU[0] + Ud[1] * dU[1] + Ud[2] * dU[2]);
-            dT = 2.0 / (3.0 + K) * dT;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                G[i][j] = dU[i];
-                sU += fabs(dU[i]);
-            }
-            divU += dU[j];
-            gT[j] = dT;
-            sTg += fabs(dT);
+            for (int i = 0; i < 3; ++i) G[i][j] = 0.0;
         }
-        const double tau = D.tau[c], dt = D.is[inst].dt;
-        const double alpha = dt / expm1(dt / tau) - tau;
-        const double B = 1.0 + fabs(alpha) * (kBox * kBox * (sU + fabs(divU)) +
-                                              0.5 * ((3.0 + K) * kBox * kBox + 5.0 + K) * kBox * sqrt(T) * sTg / T);
+        double alpha = 0.0, Bgp = 1.0;
+        if (gp) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double dr = D.gW[j * nc + c];
+                double dU[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) dU[i] = (D.gW[(3 * (1 + i) + j) * nc + c] - Ud[i] * dr) / rho;
+                double dT = (D.gW[(12 + j) * nc + c] - W[4] / rho * dr) / rho -
+                            (Ud[0] * dU[0] + Ud[1] * dU[1] + Ud[2] * dU[2]);
+                dT = 2.0 / (3.0 + K) * dT;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    G[i][j] = dU[i];
+                    sU += fabs(dU[i]);
+                }
+                divU += dU[j];
+                gT[j] = dT;
+                sTg += fabs(dT);
+            }
+            const double tau = D.tau[c], dt = D.is[inst].dt;
+            alpha = dt / expm1(dt / tau) - tau;
+            Bgp = 1.0 + fabs(alpha) * (kBox * kBox * (sU + fabs(divU)) +
+                                       0.5 * ((3.0 + K) * kBox * kBox + 5.0 + K) * kBox * sqrt(T) * sTg / T);
+        }
+        // Shakhov model: g^+ / g = 1 + (a.X)(|X|^2 - 5), a = (1 - Pr) q / (5 rho T^(3/2)) with the
+        // cell's heat flux q; 44 |a| bounds the correction on |X| <= 4 (clipped beyond)
+        double a[3] = {0.0, 0.0, 0.0}, Bsh = 0.0;
+        if (sh) {
+            const double fa = (1.0 - P.pr) / (5.0 * W[0] * T * sqrt(T));
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a[d] = fa * D.qh[d * nc + c];
+            Bsh = 44.0 * sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        }
+        const double B = Bgp + Bsh;
         const double sqT = sqrt(T);
         const R U[3] = {(R)Ud[0], (R)Ud[1], (R)Ud[2]};
         const R sT = (R)sqT, TR = (R)T;
@@ -1398,8 +1502,13 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
 #pragma unroll
                     for (int jj = 0; jj < 3; ++jj) shear += Xd[i] * Xd[jj] * G[i][jj];
                 }
-                const double p = shear - s2 / (3.0 + K) * divU + (0.5 * s2 - 0.5 * (5.0 + K)) * sqT * xg / T;
-                if (unif<double>(ra.v[0]) * B < 1.0 + alpha * p) break;
+                double w = 1.0;
+                if (gp) {
+                    const double p = shear - s2 / (3.0 + K) * divU + (0.5 * s2 - 0.5 * (5.0 + K)) * sqT * xg / T;
+                    w = 1.0 + alpha * p;
+                }
+                if (sh) w = w + (a[0] * x0 + a[1] * x1 + a[2] * x2) * ((x0 * x0 + x1 * x1 + x2 * x2) - 5.0);
+                if (unif<double>(ra.v[0]) * B < w) break;
             }
             const long long i = base + k;
             R x[3];
@@ -2925,9 +3034,11 @@ void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
 }
 
 template <typename R>
-void launch_flux(const Dev &D, const LaunchCfg &cfg, hipStream_t s) {
+void launch_flux(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
     const int bs = cfg.flux_bs, nf = D.nf;
     const unsigned g = (unsigned)((nf + bs - 1) / bs);
+    // Shakhov model: the cells' heat fluxes, which the flux and the sampling read
+    if (D.sh_any) k_heat<R><<<(unsigned)((D.nc + 3) / 4), 256, 0, s>>>(D, buf);
     if (D.recon_any) {
         // second order: gradients (one thread per cell), then the faces of reconstructing
         // instances; the first-order kernel takes the others
@@ -2980,9 +3091,9 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     pr->begin(kSlotFlux);
     if (nf > 0) {
         if (f32)
-            launch_flux<float>(D, cfg, s);
+            launch_flux<float>(D, buf, cfg, s);
         else
-            launch_flux<double>(D, cfg, s);
+            launch_flux<double>(D, buf, cfg, s);
     }
     pr->end(kSlotFlux);
     pr->begin(kSlotSample);
@@ -3065,9 +3176,9 @@ void launch_step_wave_only(const Dev &D, int buf, const LaunchCfg &cfg, hipStrea
     pr->begin(kSlotFlux);
     if (nf > 0) {
         if (D.prec == 1)
-            launch_flux<float>(D, cfg, s);
+            launch_flux<float>(D, buf, cfg, s);
         else
-            launch_flux<double>(D, cfg, s);
+            launch_flux<double>(D, buf, cfg, s);
     }
     pr->end(kSlotFlux);
     pr->begin(kSlotScan2);

@@ -46,7 +46,7 @@ class UgkwpParams(C.Structure):
                 ("c2", C.c_double), ("n_ref", C.c_int32), ("n_min", C.c_int32), ("recon", C.c_int32),
                 ("precision", C.c_int32), ("capacity", C.c_int64), ("max_crossings", C.c_int32),
                 ("seed", C.c_uint64), ("venkat_k", C.c_double), ("sampling", C.c_int32),
-                ("gks_steps", C.c_int32)]
+                ("gks_steps", C.c_int32), ("prandtl", C.c_double)]
 
 
 class UgkwpStats(C.Structure):
@@ -167,7 +167,8 @@ class _MeshArgs:
 def make_params(p, capacity=0, precision=0) -> UgkwpParams:
     return UgkwpParams(p.gamma, p.mu_ref, p.omega, p.cfl, p.c2, p.n_ref, p.n_min, int(getattr(p, "recon", 0)),
                        precision, capacity, p.max_crossings, p.seed, float(getattr(p, "venkat_k", 1.0)),
-                       int(getattr(p, "sampling", 0)), int(getattr(p, "gks_steps", 0)))
+                       int(getattr(p, "sampling", 0)), int(getattr(p, "gks_steps", 0)),
+                       float(getattr(p, "prandtl", 1.0)))
 
 
 class _BatchArgs:

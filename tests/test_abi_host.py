@@ -119,14 +119,34 @@ def test_reconstruction_parameters():
 
 
 def test_sampling_modes():
-    # 0 the pairs of Sec. 2.4(b), 1 energy-exact pairs, 2 the first-order g_p (needs gradients)
+    # 0 the pairs of Sec. 2.4(b), 1 energy-exact pairs, 2 the first-order g_p (needs gradients),
+    # 3 independent draws from the equilibrium
     w = wl.sod(nx=10)
-    for mode, recon, ok in ((0, 0, True), (1, 0, True), (2, 1, True), (2, 2, True), (2, 0, False), (3, 1, False),
-                            (-1, 0, False)):
+    for mode, recon, ok in ((0, 0, True), (1, 0, True), (2, 1, True), (2, 2, True), (2, 0, False), (3, 0, True),
+                            (3, 1, True), (4, 1, False), (-1, 0, False)):
         p = copy.deepcopy(w.params)
         p.sampling, p.recon = mode, recon
         if ok:
             assert U.workspace_bytes(w.mesh, p) > 0
+        else:
+            with pytest.raises(U.UgkwpError) as e:
+                U.workspace_bytes(w.mesh, p)
+            assert e.value.status == U.E_ARG
+
+
+def test_shakhov_parameters():
+    # prandtl 0 or 1 = BGK; the Shakhov model needs a monatomic gas and sampling 2 or 3, and
+    # its heat-flux array enlarges the workspace
+    w = wl.sod(nx=10)
+    base = U.workspace_bytes(w.mesh, w.params)
+    for pr, mode, gamma, ok in ((0.0, 0, 5 / 3, True), (1.0, 0, 5 / 3, True), (2 / 3, 3, 5 / 3, True),
+                                (2 / 3, 0, 5 / 3, False), (2 / 3, 1, 5 / 3, False), (2 / 3, 3, 7 / 5, False),
+                                (2.0, 3, 5 / 3, False), (-0.5, 3, 5 / 3, False), (float("nan"), 3, 5 / 3, False)):
+        p = copy.deepcopy(w.params)
+        p.prandtl, p.sampling, p.gamma = pr, mode, gamma
+        if ok:
+            n = U.workspace_bytes(w.mesh, p)
+            assert (n > base) == (pr not in (0.0, 1.0))
         else:
             with pytest.raises(U.UgkwpError) as e:
                 U.workspace_bytes(w.mesh, p)

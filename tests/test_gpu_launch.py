@@ -89,7 +89,7 @@ def test_graph_replay_equals_eager_every_step():
     _same(_state(b), _state(a), "graph replay end")
 
 
-@pytest.mark.parametrize("case", ["diatomic-gp-diffuse", "batch-mixed-modes"])
+@pytest.mark.parametrize("case", ["diatomic-gp-diffuse", "batch-mixed-modes", "batch-shakhov"])
 def test_graph_replay_with_internal_energy_and_gp_sampling(case):
     # the internal-energy instantiations and the g_p sampling kernel, captured and replayed
     import torch
@@ -100,11 +100,19 @@ def test_graph_replay_with_internal_energy_and_gp_sampling(case):
                           gamma=7.0 / 5.0)
         w.params.recon, w.params.sampling = 2, 2
         meshes, params, W0 = w.mesh, w.params, w.W0
-    else:
+    elif case == "batch-mixed-modes":
         ws = wl.small_batch(4)
         for k, x in enumerate(ws):
             x.params.recon = 1 if k % 2 == 0 else 0
             x.params.sampling = 2 if k % 2 == 0 else 1
+        meshes, params, W0 = [x.mesh for x in ws], [x.params for x in ws], np.concatenate([x.W0 for x in ws])
+    else:
+        # the heat-flux kernel and the Shakhov terms (sampling 3 and 2), next to a BGK instance
+        ws = wl.small_batch(4)
+        for k, x in enumerate(ws):
+            x.params.prandtl = 2.0 / 3.0 if k < 3 else 1.0
+            x.params.sampling = (3, 2, 3, 0)[k]
+            x.params.recon = 2 if k == 1 else 0
         meshes, params, W0 = [x.mesh for x in ws], [x.params for x in ws], np.concatenate([x.W0 for x in ws])
     stream = torch.cuda.Stream()
     a = Solver(meshes, params, stream=stream)
