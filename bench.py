@@ -335,10 +335,11 @@ def batched_run(steps, warmup, start, sampling, cpu_sample_moves=0):
     return out, sample
 
 
-def cavity_leg(precision, steps, warmup, start, sampling=0, recon=2):
+def cavity_leg(precision, steps, warmup, start, sampling=0, recon=2, prandtl=1.0):
     """The lid-driven cavity (Sec. 4.2) at 32^3, 400 particles per cell, second order
     (least-squares gradients with the Venkatakrishnan limiter, as the paper's cavity): `start`
-    steps, `warmup` more, then `steps` timed."""
+    steps, `warmup` more, then `steps` timed.  sampling 2: the first-order g_p; prandtl != 1:
+    the Shakhov model (with sampling 2 or 3)."""
     import torch
 
     from paper_2007_13091_amd import workloads as wl
@@ -347,6 +348,7 @@ def cavity_leg(precision, steps, warmup, start, sampling=0, recon=2):
     w = wl.morton_numbered(wl.cavity())
     w.params.sampling = sampling
     w.params.recon = recon
+    w.params.prandtl = prandtl
     nc = w.mesh.n_cells
     s = Solver(w.mesh, w.params, precision=precision)
     s.init_state(w.W0)
@@ -356,7 +358,7 @@ def cavity_leg(precision, steps, warmup, start, sampling=0, recon=2):
     el, moves, kms, st0, st1 = timed_steps(s, steps)
     rtype = "double" if precision == 0 else "float"
     names = kernel_names(rtype, cfg, False)
-    workload = f"cavity32_recon{recon}"
+    workload = f"cavity32_recon{recon}" + ("_gp" if sampling == 2 else "") + ("_shakhov" if prandtl != 1.0 else "")
     dom, kr = kernel_roofline(kms, moves / steps, st1, rtype, names, workload)
     ms = el / steps * 1e3
     s.close()
@@ -608,6 +610,10 @@ def main():
                     help="run only the batched FP32 leg (no FP64 comparison) and print its JSON object")
     ap.add_argument("--cavity-only", type=int, default=-1, metavar="PRECISION",
                     help="run only the cavity leg in that precision (0 FP64, 1 FP32) and print its JSON object")
+    ap.add_argument("--cavity-sampling", type=int, choices=[0, 1, 2, 3], default=0,
+                    help="with --cavity-only: the hydro-particle sampling")
+    ap.add_argument("--cavity-prandtl", type=float, default=1.0,
+                    help="with --cavity-only: the Prandtl number (1 BGK, else the Shakhov model)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -623,7 +629,8 @@ def main():
         print(json.dumps({"gks_limit": gks_side(args.steps, args.warmup)}), flush=True)
         return
     if args.cavity_only >= 0:
-        leg = cavity_leg(args.cavity_only, args.steps, args.warmup, args.cavity_start)
+        leg = cavity_leg(args.cavity_only, args.steps, args.warmup, args.cavity_start, sampling=args.cavity_sampling,
+                         prandtl=args.cavity_prandtl)
         print(json.dumps({"cavity": leg}), flush=True)
         return
     if args.batched_only:
@@ -678,10 +685,15 @@ def main():
         c64 = cavity_leg(0, args.steps, args.warmup, args.cavity_start)
         c32 = cavity_leg(1, args.steps, args.warmup, args.cavity_start)
         c32["speedup_vs_fp64_plain"] = c32["value"] / c64["value"]
+        # the first-order g_p, with the BGK model and with the Shakhov model at Pr = 2/3
+        gp = cavity_leg(0, args.steps, args.warmup, args.cavity_start, sampling=2)
+        sh = cavity_leg(0, args.steps, args.warmup, args.cavity_start, sampling=2, prandtl=2.0 / 3.0)
+        sh["ms_per_step_vs_bgk_gp"] = sh["ms_per_step"] / gp["ms_per_step"]
         out["cavity32"] = {"workload": "lid-driven cavity, 32^3 box hexes (Morton-numbered), 400 particles/cell, "
                                        "Kn 0.075, diffuse walls, lid 0.16 sqrt(gamma T_w), second order "
                                        "(Venkatakrishnan), the printed pairs of Sec. 2.4(b)",
-                           "fp64_plain": c64, "fp32_form": c32}
+                           "fp64_plain": c64, "fp32_form": c32,
+                           "fp64_gp_bgk": gp, "fp64_gp_shakhov_pr_2_3": sh}
     if not args.no_gks:
         out["gks_limit"] = gks_side(args.steps, args.warmup)
     if not args.no_avg:
