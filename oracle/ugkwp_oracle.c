@@ -1718,20 +1718,19 @@ static void place_in_cell(const oracle_t *o, int64_t c, uint64_t uid, double x[3
  * <(sum_d u_d (a_d . psi) + A . psi) psi g> = 0; the correction carries no mass, momentum or
  * energy.  alpha tends to -tau in the continuum limit (the Chapman-Enskog distribution) and
  * to -dt/2 in the free-molecular one.
- * Sampling by acceptance-rejection: proposals u = U + sqrt(T) X (X ~ N(0, I) by Box-Muller on
- * the draw (uid, step, TAG_GP, 2j) of attempt j; with K > 0 the internal energy T chi^2_K from
- * the draws (TAG_INT, 2j, 2j + 1)), accepted when eta B < 1 + alpha (...) with eta the first
- * uniform of the draw (uid, step, TAG_GP, 2j + 1).  B bounds |1 + alpha (...)| where every
- * normal of the proposal is at most R = 4 in size (Chapman-Enskog form of the correction,
- * below); beyond that box, and where 1 + alpha (...) < 0, the law is clipped.  After 64
- * rejected attempts the last proposal is kept.
+ * Sampling by acceptance-rejection from one stream of proposals per cell (see
+ * sample_one_by_one): proposal p is u = U + sqrt(T) X (X ~ N(0, I) by Box-Muller on the draw
+ * (uid_p, step, TAG_GP, 0), uid_p the id a particle p of the cell would have; with K > 0 the
+ * internal energy T chi^2_K from the draws (uid_p, TAG_INT, 0 and 1)), accepted when
+ * eta B < 1 + alpha (...) with eta the first uniform of (uid_p, step, TAG_GP, 1).  B bounds
+ * |1 + alpha (...)| where every normal of the proposal is at most R = 4 in size
+ * (Chapman-Enskog form of the correction, below); beyond that box, and where 1 + alpha (...)
+ * < 0, the law is clipped.
  * The bound: with the correction written as (X = (u - U)/sqrt(T), z = e/T)
  *   X_i X_j d_j U_i - (|X|^2 + z)/(3 + K) div U + ((|X|^2 + z)/2 - (5 + K)/2) sqrt(T) X . grad ln T,
  *   B = 1 + |alpha| (R^2 (sum_ij |d_j U_i| + |div U|)
  *                    + ((3 + K) R^2 + 5 + K)/2 R sqrt(T) sum_j |d_j T| / T). */
 typedef struct { double a[3][5], A[5], alpha, B; } gp_t;
-
-enum { GP_ATTEMPTS = 64 };
 
 /* g_p of a cell of state W with limited gradient gW ([5][3], d W_k / d x_d), tau and dt */
 static void gp_setup(const double W[5], const double gW[15], double tau, double dt, int Kdof, gp_t *gp)
@@ -1811,24 +1810,54 @@ static double shakhov_term(const sh_t *s, const double X[3])
     return (s->a[0] * X[0] + s->a[1] * X[1] + s->a[2] * X[2]) * ((X[0] * X[0] + X[1] * X[1] + X[2] * X[2]) - 5.0);
 }
 
-/* one hydro particle drawn by itself (sampling 2: gp, else NULL; the Shakhov model: sh, else
- * NULL): proposals u = U + sqrt(T) X, accepted when eta B < w, w = (1 + alpha (...) of g_p, or 1)
- * + (a.X)(|X|^2 - 5), B = (B of g_p, or 1) + B of sh; its velocity and internal energy */
-static void hydro_draw(const oracle_t *o, const gp_t *gp, const sh_t *sh, uint64_t uid, const double U[3], double T,
-                       double u[3], double *e)
+/* proposal p of a cell for the hydro particles drawn one by one (sampling 2: gp, else NULL;
+ * the Shakhov model: sh, else NULL): u = U + sqrt(T) X and e from the draws of uid_p (see
+ * gp_setup's comment); returns its weight w = (1 + alpha (...) of g_p, or 1) + (a.X)(|X|^2 - 5)
+ * and the acceptance uniform eta */
+static double hydro_proposal(const oracle_t *o, const gp_t *gp, const sh_t *sh, uint64_t uidp, const double U[3],
+                             double T, double u[3], double *e, double *eta)
+{
+    double ev[4], ea[4];
+    draw4(o->seed, uidp, o->step, TAG_GP, 0u, o->inst, ev);
+    double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
+    double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
+    for (int d = 0; d < 3; ++d) u[d] = U[d] + sqrt(T) * X[d];
+    *e = o->K > 0 ? internal_energy(o->seed, uidp, o->step, TAG_INT, 0u, o->inst, o->K, T) : 0.0;
+    draw4(o->seed, uidp, o->step, TAG_GP, 1u, o->inst, ea);
+    *eta = ea[0];
+    double w = gp ? gp_weight(gp, u, *e) : 1.0;
+    if (sh) w = w + shakhov_term(sh, X);
+    return w;
+}
+
+/* The ns hydro particles of cell c drawn one by one (sampling 2 and 3), stored from index i0:
+ * the proposals p = 0, 1, 2, ... of the cell are tried in order, B = (B of g_p, or 1) + (B of
+ * sh, or 0), and the k-th accepted one becomes particle k (id uid_k, its own uniform position),
+ * until ns are accepted or P = min(64 ns, 2^20) proposals are spent; a particle k still
+ * missing then takes proposal k whether accepted or not.  (One stream per cell rather than
+ * per particle: a wave of 64 lanes then tries 64 proposals at once and keeps every lane busy.)
+ * S (if given) receives the sums of phi. */
+static void sample_one_by_one(oracle_t *o, int64_t c, int64_t ns, int64_t i0, double msam, const gp_t *gp,
+                              const sh_t *sh, const double U[3], double T, double *S)
 {
     const double B = (gp ? gp->B : 1.0) + (sh ? sh->B : 0.0);
-    for (int j = 0; j < GP_ATTEMPTS; ++j) {
-        double ev[4], ea[4];
-        draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j, o->inst, ev);
-        double r1 = sqrt(-2.0 * log(ev[0])), r2 = sqrt(-2.0 * log(ev[2]));
-        double X[3] = {r1 * cos(2.0 * M_PI * ev[1]), r1 * sin(2.0 * M_PI * ev[1]), r2 * cos(2.0 * M_PI * ev[3])};
-        for (int d = 0; d < 3; ++d) u[d] = U[d] + sqrt(T) * X[d];
-        *e = o->K > 0 ? internal_energy(o->seed, uid, o->step, TAG_INT, 2u * (uint32_t)j, o->inst, o->K, T) : 0.0;
-        draw4(o->seed, uid, o->step, TAG_GP, 2u * (uint32_t)j + 1u, o->inst, ea);
-        double w = gp ? gp_weight(gp, u, *e) : 1.0;
-        if (sh) w = w + shakhov_term(sh, X);
-        if (ea[0] * B < w) return;
+    const int64_t pmax = 64 * ns < ((int64_t)1 << 20) ? 64 * ns : ((int64_t)1 << 20);
+    int64_t k = 0;
+    for (int64_t p = 0; p < pmax + ns && k < ns; ++p) {
+        const int fill = p >= pmax; /* the proposals are spent: particle k takes proposal k */
+        const int64_t pp = fill ? k : p;
+        const int64_t i = i0 + k;
+        double e = 0.0, eta = 0.0;
+        const double w = hydro_proposal(o, gp, sh, orc_make_uid(0, o->step, c, pp), U, T, o->pu + 3 * i, &e, &eta);
+        if (!fill && !(eta * B < w)) continue;
+        const uint64_t uid = orc_make_uid(0, o->step, c, k);
+        place_in_cell(o, c, uid, o->px + 3 * i);
+        o->pm[i] = msam;
+        o->pc[i] = c;
+        o->pid[i] = uid;
+        o->pe[i] = e;
+        if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i, e);
+        ++k;
     }
 }
 
@@ -1894,19 +1923,8 @@ static int phase_sample(oracle_t *o, const cellq_t *q, double *S, int64_t *nsamp
             sh_t sh;
             if (o->sampling == 2) gp_setup(o->W + 5 * c, q->gW + 15 * c, q->tau[c], q->dt, o->K, &gp);
             if (o->pr != 1.0) shakhov_setup(o->W + 5 * c, q->T[c], q->qh + 3 * c, o->pr, &sh);
-            for (int64_t k = 0; k < ns; ++k) {
-                const int64_t i = first[c] + k;
-                const uint64_t uid = orc_make_uid(0, o->step, c, k);
-                double e = 0.0;
-                hydro_draw(o, o->sampling == 2 ? &gp : NULL, o->pr != 1.0 ? &sh : NULL, uid, q->U + 3 * c, q->T[c],
-                           o->pu + 3 * i, &e);
-                place_in_cell(o, c, uid, o->px + 3 * i);
-                o->pm[i] = msam;
-                o->pc[i] = c;
-                o->pid[i] = uid;
-                o->pe[i] = e;
-                if (S) add_phi(S + 5 * c, msam, o->pu + 3 * i, e);
-            }
+            sample_one_by_one(o, c, ns, first[c], msam, o->sampling == 2 ? &gp : NULL, o->pr != 1.0 ? &sh : NULL,
+                              q->U + 3 * c, q->T[c], S);
             continue;
         }
         if (o->sampling == 1) {

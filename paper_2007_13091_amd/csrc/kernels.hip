@@ -1390,19 +1390,23 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
 // (X = (u - U)/sqrt(T), z = e_int/T, G_ij = d_j U_i and grad T from the cell's limited
 // gradient of W):
 //   p = X_i X_j G_ij - (|X|^2 + z)/(3 + K) div U + ((|X|^2 + z)/2 - (5 + K)/2) sqrt(T) X . grad T / T.
-// Acceptance-rejection per particle, one lane each: attempt j proposes X by Box-Muller on the
-// draw (uid, step, kTagGP, 2j) (X0, X1 = r1 (cos, sin)(2 pi e1), X2 = r2 cos(2 pi e3)) and,
-// with K > 0, the internal energy T chi^2_K from (kTagInt, 2j, 2j + 1); it is kept when
-// eta B < 1 + alpha p, eta the first uniform of (uid, step, kTagGP, 2j + 1) in FP64 and
+// Acceptance-rejection from one stream of proposals per cell: proposal p draws X by Box-Muller
+// on (uid_p, step, kTagGP, 0) (X0, X1 = r1 (cos, sin)(2 pi e1), X2 = r2 cos(2 pi e3)), uid_p the
+// id a particle p of the cell would have, and, with K > 0, the internal energy T chi^2_K from
+// (uid_p, kTagInt, 0 and 1); it is accepted when eta B < 1 + alpha p, eta the first uniform of
+// (uid_p, step, kTagGP, 1) in FP64 and
 // B = 1 + |alpha| (16 (sum_ij |G_ij| + |div U|) + ((3 + K) 16 + 5 + K)/2 4 sqrt(T) sum_j |d_j T| / T),
-// which bounds |1 + alpha p| wherever every normal is at most 4.  After 64 rejections the last
-// proposal is kept.  Positions as in k_sample.  One wave per cell; S = P + the new sums.
-// Sampling 3 takes the same draws from the equilibrium itself (weight 1, B = 1: the first
-// proposal).  The Shakhov model (Pr != 1) adds (a.X)(|X|^2 - 5) to the weight and 44 |a| to B.
+// which bounds |1 + alpha p| wherever every normal is at most 4.  The wave tries proposals
+// 64 at a time, and the k-th accepted one (in proposal order) becomes particle k, until the
+// cell's ns are accepted or min(64 ns, 2^20) proposals are spent; a particle k still missing
+// then takes proposal k.  Unlike a proposal loop per particle, no lane idles while the
+// slowest lane of its wave keeps rejecting.  Positions as in k_sample.  One wave per cell;
+// S = P + the new sums.
+// Sampling 3 takes the same draws from the equilibrium itself (weight 1, B = 1: proposal k is
+// particle k).  The Shakhov model (Pr != 1) adds (a.X)(|X|^2 - 5) to the weight and 44 |a| to B.
 // ---------------------------------------------------------------------------------------
 template <typename R, bool KE>
 __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
-    constexpr int kAttempts = 64;
     constexpr double kBox = 4.0;
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -1480,19 +1484,22 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
         for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
         const bool tet = D.ctype[c] == 4;
         const R two_pi = (R)2 * (R)kPi;
-        for (long long k = lane; k < ns; k += kWave) {
-            const uint64_t uid = make_uid(step, cl, k);
-            R u[3], e = (R)0;
-            for (int j = 0; j < kAttempts; ++j) {
-                const U4 rv = draw(seed, uid, step, kTagGP, 2u * (uint32_t)j, inst);
-                const R r1 = sqrt((R)-2 * log(unif<R>(rv.v[0]))), r2 = sqrt((R)-2 * log(unif<R>(rv.v[2])));
-                const R a1 = two_pi * unif<R>(rv.v[1]), a2 = two_pi * unif<R>(rv.v[3]);
-                const R X[3] = {r1 * cos(a1), r1 * sin(a1), r2 * cos(a2)};
+        // proposal p of the cell (draws keyed by the id a particle p would have): its velocity,
+        // internal energy and whether it is accepted
+        auto propose = [&](long long p, R u[3], R &e) -> bool {
+            const uint64_t uidp = make_uid(step, cl, p);
+            const U4 rv = draw(seed, uidp, step, kTagGP, 0u, inst);
+            const R r1 = sqrt((R)-2 * log(unif<R>(rv.v[0]))), r2 = sqrt((R)-2 * log(unif<R>(rv.v[2])));
+            const R a1 = two_pi * unif<R>(rv.v[1]), a2 = two_pi * unif<R>(rv.v[3]);
+            const R X[3] = {(R)(r1 * cos(a1)), (R)(r1 * sin(a1)), (R)(r2 * cos(a2))};
 #pragma unroll
-                for (int d = 0; d < 3; ++d) u[d] = U[d] + sT * X[d];
-                if (KE && K > 0) e = internal_energy<R>(seed, uid, step, kTagInt, 2u * (uint32_t)j, inst, K, TR);
-                const U4 ra = draw(seed, uid, step, kTagGP, 2u * (uint32_t)j + 1u, inst);
-                const double x0 = (double)X[0], x1 = (double)X[1], x2 = (double)X[2];
+            for (int d = 0; d < 3; ++d) u[d] = U[d] + sT * X[d];
+            e = (R)0;
+            if (KE && K > 0) e = internal_energy<R>(seed, uidp, step, kTagInt, 0u, inst, K, TR);
+            const U4 ra = draw(seed, uidp, step, kTagGP, 1u, inst);
+            const double x0 = (double)X[0], x1 = (double)X[1], x2 = (double)X[2];
+            double w = 1.0;
+            if (gp) {
                 const double s2 = x0 * x0 + x1 * x1 + x2 * x2 + (double)e / T;
                 const double Xd[3] = {x0, x1, x2};
                 double shear = 0.0, xg = 0.0;
@@ -1502,14 +1509,15 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
 #pragma unroll
                     for (int jj = 0; jj < 3; ++jj) shear += Xd[i] * Xd[jj] * G[i][jj];
                 }
-                double w = 1.0;
-                if (gp) {
-                    const double p = shear - s2 / (3.0 + K) * divU + (0.5 * s2 - 0.5 * (5.0 + K)) * sqT * xg / T;
-                    w = 1.0 + alpha * p;
-                }
-                if (sh) w = w + (a[0] * x0 + a[1] * x1 + a[2] * x2) * ((x0 * x0 + x1 * x1 + x2 * x2) - 5.0);
-                if (unif<double>(ra.v[0]) * B < w) break;
+                const double pw = shear - s2 / (3.0 + K) * divU + (0.5 * s2 - 0.5 * (5.0 + K)) * sqT * xg / T;
+                w = 1.0 + alpha * pw;
             }
+            if (sh) w = w + (a[0] * x0 + a[1] * x1 + a[2] * x2) * ((x0 * x0 + x1 * x1 + x2 * x2) - 5.0);
+            return unif<double>(ra.v[0]) * B < w;
+        };
+        // particle k: its id, position, record and sums
+        auto put = [&](long long k, const R u[3], R e) {
+            const uint64_t uid = make_uid(step, cl, k);
             const long long i = base + k;
             R x[3];
             cell_point<R>(seed, uid, step, inst, org, Ed, tet, x);
@@ -1517,6 +1525,26 @@ __global__ void __launch_bounds__(256) k_sample_gp(Dev D, int buf) {
             pa.cell[i] = c;
             if (KE) store_e(pa, i, e);
             add_phi<R>(acc, msam, u, e);
+        };
+        // the wave tries 64 proposals at a time; the accepted ones, in proposal order, become the
+        // next particles (ballot prefix counts), until ns are accepted or the proposals are spent
+        const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
+        const long long pmax = 64 * ns < (1LL << 20) ? 64 * ns : (1LL << 20);
+        long long cnt = 0;
+        for (long long p0 = 0; p0 < pmax && cnt < ns; p0 += kWave) {
+            const long long p = p0 + lane;
+            R u[3] = {(R)0, (R)0, (R)0}, e = (R)0;
+            const bool ok = p < pmax && propose(p, u, e);
+            const unsigned long long m = __ballot(ok);
+            const long long k = cnt + (long long)__popcll(m & below);
+            if (ok && k < ns) put(k, u, e);
+            cnt += (long long)__popcll(m);
+        }
+        // proposals spent: a particle k still missing takes proposal k, accepted or not
+        for (long long k = (cnt < ns ? cnt : ns) + lane; k < ns; k += kWave) {
+            R u[3], e;
+            (void)propose(k, u, e);
+            put(k, u, e);
         }
     }
 #pragma unroll

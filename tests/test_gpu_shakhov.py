@@ -134,3 +134,12 @@ def test_shakhov_fp32_form():
         out.append(W)
     # the FP32 form stays near FP64 in density (different draws decide only where it rounds)
     assert np.abs(out[1][:, 0] / out[0][:, 0] - 1).max() < 0.05
+
+
+def test_shakhov_cavity_full_size():
+    """The bench's Shakhov leg at its size: 32^3 cavity (Morton-numbered), 400 particles per
+    cell, second order, g_p plus the correction, Pr = 2/3; the first step has no particles
+    (q = 0), the next two draw from g^+ and add the flux term."""
+    w = _shakhov(wl.morton_numbered(wl.cavity()), sampling=2, recon=2)
+    s, o = run_pair(w, 3, every=1, name="cavity32-shakhov-gp")
+    assert np.abs(o.heat_flux()).max() > 0
