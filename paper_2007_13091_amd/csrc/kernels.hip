@@ -47,6 +47,7 @@ __device__ __forceinline__ void st_nt(uint4 *p, const uint4 &v) {
 constexpr int kWave = 64;
 constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
 constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
+constexpr int kSampleCells = 8;     // consecutive cells per wave in k_sample
 constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (2 and 4 are slower in FP32)
 
 // ---------------------------------------------------------------------------------------
@@ -1274,24 +1275,13 @@ __device__ __forceinline__ void cell_point(uint64_t seed, uint64_t uid, long lon
     for (int d = 0; d < 3; ++d) x[d] = org[d] + s * Ed[d] + t * Ed[3 + d] + w * Ed[6 + d];
 }
 
-template <typename R, int WPB, bool KE>
-__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
-    const int wave = threadIdx.x / kWave;
+// one cell's ns > 0 new particles by the whole wave in runs of 64 (ns is even, so a pair never
+// straddles two runs), and its S
+template <typename R, bool KE>
+__device__ __forceinline__ void sample_cell(const Dev &D, int buf, int c, long long ns) {
     const int lane = lane_id();
-    const int c = blockIdx.x * WPB + wave;
-    if (c >= D.nc) return;
     const int nc = D.nc;
     const Scalars *sc = D.sc;
-    // cells of instances that sample the first-order g_p are k_sample_gp's
-    if (D.gp_any && D.ip[inst_of(D, c)].sampling >= 2) return;
-    const long long ns = sc->n_new > 0 ? D.nsam[c] : 0;  // even
-    // S = P + the new particles' sums, lane k < 5 writing component k; a cell that samples
-    // nothing copies P (loaded in the same round as its count)
-    const double Pk = lane < 5 ? D.P[lane * nc + c] : 0.0;
-    if (ns == 0) {
-        if (lane < 5) D.S[lane * nc + c] = Pk + 0.0;
-        return;
-    }
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     {
         const Particles pa = D.pa[buf];
@@ -1380,6 +1370,166 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     for (int k = 1; k < 5; ++k)
         if (lane == k) ak = acc[k];
     if (lane < 5) D.S[lane * nc + c] = D.P[lane * nc + c] + ak;
+}
+
+// segmented sum over consecutive lanes: lane l of the segment [first, last] receives the sum of
+// v over the segment (fixed order: an inclusive scan by doubling offsets, read at `last`)
+__device__ __forceinline__ double seg_sum(double v, int first, int last) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double t = __shfl_up(v, (unsigned)o);
+        if (lane - o >= first) v = v + t;
+    }
+    return __shfl(v, last);
+}
+
+// Each wave takes kSampleCells consecutive cells.  BIG = false: runs of consecutive cells whose
+// new particles fit in 64 lanes together are sampled at once, lane by lane in cell order (most
+// cells sample a few particles: one wave per cell left most lanes idle).  BIG = true (a second
+// launch, with its own register budget): each cell with more than 64 takes the whole wave by
+// itself (sample_cell).  A pair's partners sit in neighbouring lanes of one cell (every count
+// and prefix is even); the energy-exact factor and S come from segmented sums over the cell's
+// lanes.  The arithmetic per particle is that of sample_cell.
+template <typename R, int WPB, bool KE, bool BIG>
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
+    constexpr int G = kSampleCells;
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int c0 = (blockIdx.x * WPB + wave) * G;
+    if (c0 >= D.nc) return;
+    const int nc = D.nc;
+    const Scalars *sc = D.sc;
+    // new particles of the group's cells; -1 marks a lane without a cell of its own (past the
+    // mesh) and a cell of an instance that samples one by one (k_sample_gp's, which also writes
+    // its S): neither is sampled nor has S written here
+    int myns = -1;
+    if (lane < G && c0 + lane < nc) {
+        const int c = c0 + lane;
+        if (D.gp_any && D.ip[inst_of(D, c)].sampling >= 2)
+            myns = -1;
+        else
+            myns = sc->n_new > 0 ? (int)D.nsam[c] : 0;  // even, at most 2^20
+    }
+    // wave-uniform counts and prefixes (scalar registers)
+    int ns[G];
+    int pre[G + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        ns[j] = __builtin_amdgcn_readfirstlane(__shfl(myns, j));
+        const int n = ns[j] > 0 ? ns[j] : 0;
+        pre[j + 1] = pre[j] + (n <= kWave ? n : kWave + 1);
+    }
+    if constexpr (BIG) {
+#pragma unroll 1
+        for (int j = 0; j < G; ++j) {
+            const int nj = __builtin_amdgcn_readfirstlane(__shfl(myns, j));
+            if (c0 + j < nc && nj > kWave) sample_cell<R, KE>(D, buf, c0 + j, (long long)nj);
+        }
+        return;
+    }
+    // cells without new particles: S = P
+    if (lane < G && myns == 0) {
+        const int c = c0 + lane;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) D.S[k * nc + c] = D.P[k * nc + c] + 0.0;
+    }
+    int g = 0;
+    while (g < G) {
+        if (c0 + g >= nc) break;
+        if (ns[g] > kWave) {
+            ++g;  // the BIG launch's
+            continue;
+        }
+        // the longest run [g, h) of cells of at most 64 particles each that fits in 64 lanes
+        int h = g + 1;
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (j >= h && j == h && c0 + j < nc && ns[j] <= kWave && pre[j + 1] - pre[g] <= kWave) h = j + 1;
+        const int nrun = pre[h] - pre[g];
+        if (nrun > 0) {
+            // this lane's cell j of the run and its particle k there
+            int j = g;
+#pragma unroll
+            for (int jj = 0; jj < G; ++jj)
+                if (jj > g && jj < h && pre[jj] - pre[g] <= lane) j = jj;
+            const bool act = lane < nrun;
+            const int first = act ? pre[j] - pre[g] : lane, last = act ? pre[j + 1] - pre[g] - 1 : lane;
+            const long long k = act ? (long long)(lane - first) : 0;
+            const long long nsj = act ? (long long)ns[j] : 0;
+            const int c = c0 + j;
+            double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            const Particles pa = D.pa[buf];
+            const int inst = inst_of(D, c);
+            const InstP &P = D.ip[inst];
+            const long long step = D.is[inst].step;
+            const unsigned long long seed = P.seed;
+            const int cl = c - P.cell0;
+            const bool exact = P.sampling == 1;
+            const bool odd = (k & 1) != 0;
+            R h0 = (R)0, h1 = (R)0, sT = (R)0, T = (R)0, fint = (R)1;
+            R U[3] = {(R)0, (R)0, (R)0};
+            const int K = KE ? D.K : 0;
+            double sx2 = 0.0, se = 0.0;
+            if (act) {
+                const double rho = D.W[c], m0 = D.W[nc + c], m1 = D.W[2 * nc + c], m2 = D.W[3 * nc + c],
+                             E = D.W[4 * nc + c];
+                U[0] = (R)(m0 / rho);
+                U[1] = (R)(m1 / rho);
+                U[2] = (R)(m2 / rho);
+                T = (R)((2.0 / (3.0 + D.K)) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho);
+                sT = sqrt(T);
+                half_normal<R>(seed, make_uid(step, cl, k & ~1LL), step, inst, odd, h0, h1);
+                const double a = (double)h0, b = (double)h1;
+                sx2 = odd ? a * a : a * a + b * b;
+                if (exact && K > 0) se = (double)internal_energy<R>(seed, make_uid(step, cl, k), step, kTagInt, 0, inst, K, (R)1);
+            }
+            // energy-exact pairs: one factor per cell on every thermal deviation, sqrt(3 N_pairs /
+            // sum_j |X_j|^2), and (K > 0) K N_sam / sum_k |X'_k|^2 on every internal energy
+            sx2 = seg_sum(sx2, first, last);
+            if (KE) se = seg_sum(se, first, last);
+            if (act && exact) {
+                sT = (R)((double)sT * sqrt(3.0 * (double)(nsj / 2) / sx2));
+                if (K > 0) fint = (R)((double)K * (double)nsj / se);
+            }
+            const R X0 = __shfl(h0, lane & ~1), X1 = __shfl(h1, lane & ~1), X2 = __shfl(h0, lane | 1);
+            if (act) {
+                const long long base = sc->n_old + D.samoff[c];
+                const R msam = (R)(D.ec[c] * D.rhoh[c] * D.vol[c] / (double)nsj);
+                const R org[3] = {(R)D.orig[c], (R)D.orig[nc + c], (R)D.orig[2 * nc + c]};
+                R Ed[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) Ed[q] = (R)D.edge[q * nc + c];
+                const bool tet = D.ctype[c] == 4;
+                const long long i = base + k;
+                const uint64_t uid = make_uid(step, cl, k);
+                const R sg = odd ? (R)-1 : (R)1;
+                const R X[3] = {X0, X1, X2};
+                R u[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) u[d] = U[d] + sg * (sT * X[d]);
+                R x[3];
+                cell_point<R>(seed, uid, step, inst, org, Ed, tet, x);
+                store_new(pa, i, x, u, msam, uid);
+                pa.cell[i] = c;
+                R e = (R)0;
+                if (K > 0) {
+                    e = internal_energy<R>(seed, uid, step, kTagInt, 0, inst, K, T);
+                    if (exact) e = e * fint;
+                    store_e(pa, i, e);
+                }
+                add_phi<R>(acc, msam, u, e);
+            }
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[q] = seg_sum(acc[q], first, last);
+            if (act && lane == last) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) D.S[q * nc + c] = D.P[q * nc + c] + acc[q];
+            }
+        }
+        g = h;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -3032,22 +3182,29 @@ void launch_stream_wall(const Dev &D, int buf, long long qseg, hipStream_t s) {
         k_stream_wall<R, false, false><<<g, 256, 0, s>>>(D, buf, qseg);
 }
 
+template <typename R, bool KE, bool BIG>
+void launch_sample_b(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
+    if (w == 1)
+        k_sample<R, 1, KE, BIG><<<g, 64, 0, s>>>(D, buf);
+    else if (w == 2)
+        k_sample<R, 2, KE, BIG><<<g, 128, 0, s>>>(D, buf);
+    else if (w == 8)
+        k_sample<R, 8, KE, BIG><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_sample<R, 4, KE, BIG><<<g, 256, 0, s>>>(D, buf);
+}
+
+// the cells of at most 64 new particles, then those with more
 template <typename R, bool KE>
 void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
-    if (w == 1)
-        k_sample<R, 1, KE><<<g, 64, 0, s>>>(D, buf);
-    else if (w == 2)
-        k_sample<R, 2, KE><<<g, 128, 0, s>>>(D, buf);
-    else if (w == 8)
-        k_sample<R, 8, KE><<<g, 512, 0, s>>>(D, buf);
-    else
-        k_sample<R, 4, KE><<<g, 256, 0, s>>>(D, buf);
+    launch_sample_b<R, KE, false>(D, buf, w, g, s);
+    launch_sample_b<R, KE, true>(D, buf, w, g, s);
 }
 
 template <typename R>
 void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
     const int w = cfg.sample_wpb, nc = D.nc;
-    const unsigned g = (unsigned)((nc + w - 1) / w);
+    const unsigned g = (unsigned)((nc + w * kSampleCells - 1) / (w * kSampleCells));
     if (D.K > 0)
         launch_sample_k<R, true>(D, buf, w, g, s);
     else
