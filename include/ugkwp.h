@@ -176,6 +176,8 @@ typedef struct {
                               face exp(-dt/tau_inf) rho_inf Gamma A dt of mass (Gamma the one-sided
                               number flux of the free-stream Maxwellian) in
                               ceil(Gamma A dt n_ref / Omega) equal particles */
+    int64_t max_crossings_seen; /* the most face crossings of one particle in the step (to set
+                              max_crossings with a margin) */
 } ugkwp_step_stats;
 
 /* Device bytes needed for n_inst >= 1 instances: m[n_inst], p[n_inst].  Host-side only (no
@@ -274,9 +276,9 @@ int32_t ugkwp_geometry(ugkwp_ctx *ctx, double *vol, double *xc, double *dS);
 int32_t ugkwp_graph_enable(ugkwp_ctx *ctx, int32_t on);
 
 /* Launch shapes of the tunable kernels, cfg[4] = {k_stream block size (128, 256, 512),
- * k_stream particles per thread (1, 2), k_sample cells (waves) per block (1, 2, 4, 8), k_flux
- * block size (64, 128, 256)}.  Every shape gives bit-identical results.  Defaults: {256, 1,
- * 4, 128}. */
+ * k_stream particles per thread (1, 2), k_sample waves per block (1, 2, 4, 8; a wave takes 8
+ * cells), k_flux block size (64, 128, 256)}.  Every shape gives bit-identical results.
+ * Defaults: {256, 1, 4, 128}. */
 int32_t ugkwp_set_launch(ugkwp_ctx *ctx, const int32_t *cfg);
 int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
 
@@ -288,6 +290,18 @@ int32_t ugkwp_get_launch(const ugkwp_ctx *ctx, int32_t *cfg);
  * shapes are kept and returned in cfg_out[4] (may be NULL).  Discards pending
  * ugkwp_profile_read records. */
 int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out);
+
+/* The autotuner with a result cache, for callers that run the same workload again.  The cache
+ * is a text file of JSON lines {"key": "<workload signature>", "launch": [a, b, c, d]}; the
+ * signature names the device architecture, the precision, K, the instance count, the cells,
+ * faces and capacity, and every instance's reconstruction, sampling mode and collision model.
+ * A hit (the last line with the signature, its shapes in range) sets those shapes with no trial
+ * step: the state does not advance.  A miss runs ugkwp_autotune (the state advances as there)
+ * and appends its result.  cache_path must name a readable and appendable file (created if
+ * missing; UGKWP_E_ARG if it cannot be written).  cfg_out[4] and hit (1 on a hit, else 0) may
+ * be NULL.  Lines of other keys, or that do not parse, are ignored. */
+int32_t ugkwp_autotune_cached(ugkwp_ctx *ctx, int32_t steps_per_trial, const char *cache_path, int32_t *cfg_out,
+                              int32_t *hit);
 
 /* Measurement support.  While enabled, each group of kernel launches of ugkwp_step is
  * bracketed by hip events recorded on the library's stream.  ugkwp_profile_read waits for

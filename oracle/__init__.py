@@ -386,11 +386,11 @@ class Oracle:
 
     def stats(self):
         dt = C.c_double(0)
-        out = np.zeros(9, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         self.L.orc_stats(self.h, C.byref(dt), _p(out, C.c_int64))
         return dict(dt=dt.value, n_alive=int(out[0]), n_sampled=int(out[1]), n_collided=int(out[2]),
                     n_escaped=int(out[3]), crossings=int(out[4]), wall_hits=int(out[5]), n_injected=int(out[6]),
-                    rhoh_floored=int(out[7]), rhoh_negative=int(out[8]))
+                    rhoh_floored=int(out[7]), rhoh_negative=int(out[8]), max_crossings_seen=int(out[9]))
 
     def geometry(self):
         vol = np.zeros(self.nc)

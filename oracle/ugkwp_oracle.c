@@ -776,6 +776,7 @@ typedef struct oracle {
     double st_dt;
     int64_t st_sampled, st_collided, st_escaped, st_alive, st_cross, st_wallhits, st_injected;
     int64_t st_floored, st_rhoh_neg; /* cells whose rho - rho^p was in (0, 1e-12 rho], or below 0 */
+    int64_t st_maxcross;             /* the most face crossings of one particle */
 } oracle_t;
 
 static int cmp_fkey(const void *a, const void *b)
@@ -1220,12 +1221,12 @@ void orc_geometry(const oracle_t *o, double *vol, double *xc, double *dS)
     memcpy(dS, o->dS, sizeof(double) * 3 * o->nc);
 }
 
-void orc_stats(const oracle_t *o, double *dt, int64_t out[9])
+void orc_stats(const oracle_t *o, double *dt, int64_t out[10])
 {
     *dt = o->st_dt;
     out[0] = o->st_alive; out[1] = o->st_sampled; out[2] = o->st_collided;
     out[3] = o->st_escaped; out[4] = o->st_cross; out[5] = o->st_wallhits; out[6] = o->st_injected;
-    out[7] = o->st_floored; out[8] = o->st_rhoh_neg;
+    out[7] = o->st_floored; out[8] = o->st_rhoh_neg; out[9] = o->st_maxcross;
 }
 
 int orc_set_state(oracle_t *o, const double *W)
@@ -2269,9 +2270,10 @@ int orc_step(oracle_t *o)
         prc[i] = (int8_t)orc_track(o, o->px + 3 * i, o->pu + 3 * i, o->pe + i, o->pc + i, ts, entry0, o->pid[i],
                                    o->step, pcross + i, pwall + i);
     }
-    int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0;
+    int64_t ncoll = 0, nesc = 0, ncross_tot = 0, nwall = 0, keep = 0, maxcross = 0;
     for (int64_t i = 0; i < np; ++i) {
         ncross_tot += pcross[i];
+        if (pcross[i] > maxcross) maxcross = pcross[i];
         nwall += pwall[i];
         if (prc[i] < 0) status = ORC_E_LOST;
     }
@@ -2319,6 +2321,7 @@ int orc_step(oracle_t *o)
     o->st_escaped = nesc;
     o->st_alive = keep;
     o->st_cross = ncross_tot;
+    o->st_maxcross = maxcross;
     o->st_wallhits = nwall;
     o->step += 1;
     o->t += dt;

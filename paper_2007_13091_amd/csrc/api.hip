@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <algorithm>
 #include <mutex>
@@ -647,6 +648,7 @@ int32_t ugkwp_step(ugkwp_ctx *ctx, int32_t n_steps, ugkwp_step_stats *stats) {
         stats->error_word = s.err;
         stats->moved_total = (int64_t)s.moved_total;
         stats->n_injected = (int64_t)s.n_injected;
+        stats->max_crossings_seen = (int64_t)s.max_cross;
         // particles streamed in the last step: those alive at its start, the sampled and the
         // entering ones
         stats->n_moved = s.n_alive + (int64_t)s.n_collided + (int64_t)s.n_escaped;
@@ -675,6 +677,7 @@ int32_t ugkwp_instance_stats(ugkwp_ctx *ctx, int32_t inst, ugkwp_step_stats *sta
     stats->moved_total = I.moved_total;
     stats->crossings = ctx->D.n_inst > 1 ? -1 : (int64_t)s.n_cross;
     stats->wall_hits = ctx->D.n_inst > 1 ? -1 : (int64_t)s.n_wall;
+    stats->max_crossings_seen = ctx->D.n_inst > 1 ? -1 : (int64_t)s.max_cross;
     stats->error_word = s.err;
     return st;
 }
@@ -1085,6 +1088,88 @@ int32_t ugkwp_autotune(ugkwp_ctx *ctx, int32_t steps_per_trial, int32_t *cfg_out
     ctx->prof.mask = mask_was;
     if (cfg_out) (void)ugkwp_get_launch(ctx, cfg_out);
     return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The workload signature that keys the autotuner's cache: the device, the precision, K, the
+// sizes and every instance's reconstruction, sampling mode and collision model.
+std::string tune_key(const ugkwp_ctx *ctx) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "?";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    std::string k = arch + " prec=" + std::to_string(ctx->D.prec) + " K=" + std::to_string(ctx->D.K) +
+                    " inst=" + std::to_string(ctx->D.n_inst) + " cells=" + std::to_string(ctx->D.nc) +
+                    " faces=" + std::to_string(ctx->D.nf) + " cap=" + std::to_string(ctx->D.cap) + " modes=";
+    for (const ugkwp_params &p : ctx->ps) {
+        char b[64];
+        std::snprintf(b, sizeof b, "%d%d%s", p.recon, p.sampling, prandtl_of(p) != 1.0 ? "s" : "");
+        k += b;
+    }
+    return k;
+}
+
+// the last line of the cache file with this key: {"key": "<key>", "launch": [a, b, c, d]}
+bool tune_lookup(const char *path, const std::string &key, int32_t cfg[4]) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[4096];
+    const std::string want = "{\"key\": \"" + key + "\", \"launch\": [";
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+        int a, b, c, d;
+        if (std::sscanf(line + want.size(), "%d, %d, %d, %d]", &a, &b, &c, &d) == 4) {
+            cfg[0] = a;
+            cfg[1] = b;
+            cfg[2] = c;
+            cfg[3] = d;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ugkwp_autotune_cached(ugkwp_ctx *ctx, int32_t steps_per_trial, const char *cache_path, int32_t *cfg_out,
+                              int32_t *hit) {
+    if (!ctx || !cache_path || steps_per_trial < 1) return fail(ctx, UGKWP_E_ARG, "bad argument");
+    if (hit) *hit = 0;
+    const std::string key = tune_key(ctx);
+    if (key.find('"') != std::string::npos || key.find('\n') != std::string::npos)
+        return fail(ctx, UGKWP_E_ARG, "workload signature not storable");
+    int32_t cfg[4];
+    if (tune_lookup(cache_path, key, cfg)) {
+        ugkwp::LaunchCfg c;
+        c.stream_bs = cfg[0];
+        c.stream_ilp = cfg[1];
+        c.sample_wpb = cfg[2];
+        c.flux_bs = cfg[3];
+        if (ugkwp::launch_cfg_valid(c)) {
+            const int32_t st = ugkwp_set_launch(ctx, cfg);
+            if (st != UGKWP_OK) return st;
+            if (hit) *hit = 1;
+            if (cfg_out) (void)ugkwp_get_launch(ctx, cfg_out);
+            return UGKWP_OK;
+        }
+        // an entry out of range (another build's shapes) counts as a miss
+    }
+    const int32_t st = ugkwp_autotune(ctx, steps_per_trial, cfg);
+    if (st != UGKWP_OK) return st;
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f) return fail(ctx, UGKWP_E_ARG, std::string("cannot append to the autotune cache ") + cache_path);
+    std::fprintf(f, "{\"key\": \"%s\", \"launch\": [%d, %d, %d, %d]}\n", key.c_str(), cfg[0], cfg[1], cfg[2], cfg[3]);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) return fail(ctx, UGKWP_E_ARG, std::string("cannot write the autotune cache ") + cache_path);
+    if (cfg_out) std::memcpy(cfg_out, cfg, sizeof cfg);
+    return UGKWP_OK;
 }
 
 int32_t ugkwp_profile_enable(ugkwp_ctx *ctx, int32_t on) {

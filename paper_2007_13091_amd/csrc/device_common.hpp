@@ -93,7 +93,7 @@ struct Scalars {
     unsigned long long n_sampled, n_injected, n_collided, n_escaped, n_cross, n_wall;
     unsigned long long moved_total;  // particles streamed since the state was set
     unsigned int err;
-    unsigned int pad;
+    unsigned int max_cross;  // the most face crossings of one particle in the step
 };
 
 // One particle: position, velocity, mass and id in a 64-byte record, so that a particle

@@ -324,6 +324,19 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, s));
+    return v;
+}
+
+// the step's most crossings of one particle: a block's maximum raises the step's (reset by
+// k_prim_dt); the atomic is issued only when it would change it (the value read first only
+// grows during the step, so a stale read costs at most an extra atomic)
+__device__ __forceinline__ void raise_max_cross(const Dev &D, unsigned m) {
+    if (m > *(volatile unsigned *)&D.sc->max_cross) atomicMax(&D.sc->max_cross, m);
+}
+
 // Totals over the wave of P[0..4] and C[0..4], lane k < 5 receiving P_k and C_k.  Each total
 // is built from the same pairwise additions as wave_sum (partial sums of lanes that differ
 // in bit 5, then 4, ..., then 0), so it is bitwise wave_sum's; but at each of the first levels
@@ -380,6 +393,7 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Scalars *s = D.sc;
         s->n_sampled = 0;
+        s->max_cross = 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x < kWallSeg) D.wallq[threadIdx.x] = 0u;
     // partial sums of crossings and wall hits of this step's transport
@@ -1384,14 +1398,13 @@ __device__ __forceinline__ double seg_sum(double v, int first, int last) {
     return __shfl(v, last);
 }
 
-// Each wave takes kSampleCells consecutive cells.  BIG = false: runs of consecutive cells whose
-// new particles fit in 64 lanes together are sampled at once, lane by lane in cell order (most
-// cells sample a few particles: one wave per cell left most lanes idle).  BIG = true (a second
-// launch, with its own register budget): each cell with more than 64 takes the whole wave by
-// itself (sample_cell).  A pair's partners sit in neighbouring lanes of one cell (every count
+// Each wave takes kSampleCells consecutive cells: runs of consecutive cells whose new
+// particles fit in 64 lanes together are sampled at once, lane by lane in cell order (most
+// cells sample a few particles: one wave per cell left most lanes idle).  A cell with more than
+// 64 is k_sample_big's.  A pair's partners sit in neighbouring lanes of one cell (every count
 // and prefix is even); the energy-exact factor and S come from segmented sums over the cell's
 // lanes.  The arithmetic per particle is that of sample_cell.
-template <typename R, int WPB, bool KE, bool BIG>
+template <typename R, int WPB, bool KE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
     constexpr int G = kSampleCells;
     const int wave = threadIdx.x / kWave;
@@ -1421,14 +1434,6 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         const int n = ns[j] > 0 ? ns[j] : 0;
         pre[j + 1] = pre[j] + (n <= kWave ? n : kWave + 1);
     }
-    if constexpr (BIG) {
-#pragma unroll 1
-        for (int j = 0; j < G; ++j) {
-            const int nj = __builtin_amdgcn_readfirstlane(__shfl(myns, j));
-            if (c0 + j < nc && nj > kWave) sample_cell<R, KE>(D, buf, c0 + j, (long long)nj);
-        }
-        return;
-    }
     // cells without new particles: S = P
     if (lane < G && myns == 0) {
         const int c = c0 + lane;
@@ -1439,7 +1444,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     while (g < G) {
         if (c0 + g >= nc) break;
         if (ns[g] > kWave) {
-            ++g;  // the BIG launch's
+            ++g;  // k_sample_big's
             continue;
         }
         // the longest run [g, h) of cells of at most 64 particles each that fits in 64 lanes
@@ -1530,6 +1535,17 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         }
         g = h;
     }
+}
+
+// The cells with more than 64 new particles, one wave each (a launch of its own, so that its
+// registers do not add to k_sample's); the waves of the other cells leave at once.
+template <typename R, bool KE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_sample_big(Dev D, int buf) {
+    const int c = blockIdx.x * 8 + (int)(threadIdx.x / kWave);
+    if (c >= D.nc) return;
+    if (D.gp_any && D.ip[inst_of(D, c)].sampling >= 2) return;
+    const long long ns = D.sc->n_new > 0 ? D.nsam[c] : 0;
+    if (ns > kWave) sample_cell<R, KE>(D, buf, c, ns);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2135,8 +2151,8 @@ __device__ __forceinline__ bool finish_flight(const Dev &D, const Particles &pa,
 template <typename R, bool MULTI, bool STORE>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
                                            long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
-                                           R e, R tauc, unsigned long long &nx_, bool &lost, bool &queued,
-                                           bool &wr, int ct0, const R *B0) {
+                                           R e, R tauc, unsigned long long &nx_, unsigned &mx_, bool &lost,
+                                           bool &queued, bool &wr, int ct0, const R *B0) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
     // a single instance reads its values through uniform addresses
@@ -2170,13 +2186,14 @@ __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, co
     int entry = entry0;
     const int rc = track<R, true>(D, x, u, c, ts, entry, uid, sx, nx, nw, bounce, ct0, B0);
     nx_ += (unsigned long long)nx;
-    if (rc == 2) {
+    if (rc == 2) {  // its count goes on in k_stream_wall
         if (STORE) store_state(pa, i, x, u);
         *wall_cont<R>(pc, i) = WallCont<R>{ts, nx, bounce, entry, c0, collided ? 1 : 0, c};
         queued = true;
         wr = true;
         return;
     }
+    mx_ = max(mx_, (unsigned)nx);
     wr = finish_flight<R, STORE>(D, pa, i, x, u, c, rc, collided, c0, nx, lost);
 }
 
@@ -2235,6 +2252,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     if (i0 >= n_tot) return;
     const Particles pa = D.pa[buf], pc = D.pa[buf ^ 1];
     unsigned long long nx_ = 0;
+    unsigned mx_ = 0;  // most crossings of one of this lane's particles
     bool lost = false;
     long long ii[ILP];
     int cc[ILP];
@@ -2270,7 +2288,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
         wr[j] = false;
         if (ii[j] < n_tot) {
             stream_one<R, MULTI, false>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_,
-                                        lost, qq[j], wr[j], ct[j], bx[j]);
+                                        mx_, lost, qq[j], wr[j], ct[j], bx[j]);
             stage_state(&stage[threadIdx.x / kWave][j][lane_id() * CPR], xx[j], uu[j], tl[j]);
         }
         wm[j] = __ballot(wr[j]);
@@ -2305,14 +2323,22 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     }
     if (__ballot(lost) && lane == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
+    mx_ = wave_max_u32(mx_);
     const int wave = threadIdx.x / kWave;
-    if (lane == 0) red[0][wave] = nx_;
+    if (lane == 0) {
+        red[0][wave] = nx_;
+        red[1][wave] = mx_;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0;
+        unsigned long long a = 0, m = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) a += red[0][w];
+        for (int w = 0; w < NW; ++w) {
+            a += red[0][w];
+            m = max(m, red[1][w]);
+        }
         if (a) atomicAdd(&D.spart[blockIdx.x & 63], a);
+        raise_max_cross(D, (unsigned)m);
     }
 }
 
@@ -2322,11 +2348,13 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
 template <typename R, bool MULTI, bool KE>
 __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long qseg) {
     __shared__ unsigned long long red[2][4];
+    __shared__ unsigned redm[4];
     const int seg = (int)(blockIdx.x % kWallSeg);
     const long long nq = (long long)D.wallq[seg];
     const long long per = (long long)(gridDim.x / kWallSeg) * 256;
     const Particles pa = D.pa[buf], pc = D.pa[buf ^ 1];
     unsigned long long nx_ = 0, nw_ = 0;
+    unsigned mx_ = 0;
     bool lost = false;
     for (long long q = (long long)(blockIdx.x / kWallSeg) * 256 + threadIdx.x; q < nq; q += per) {
         const long long i = D.rank[seg * qseg + q];
@@ -2352,15 +2380,18 @@ __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long q
         if (ep) store_e(pa, i, ev);
         nx_ += (unsigned long long)(nx - w.ncross);
         nw_ += (unsigned long long)nw;
+        mx_ = max(mx_, (unsigned)nx);
         (void)finish_flight<R, true>(D, pa, i, x, u, c, rc, w.collided != 0, w.c0, nx, lost);
     }
     if (__ballot(lost) && lane_id() == 0) atomicOr(&D.sc->err, kErrLost);
     nx_ = wave_sum_u64(nx_);
     nw_ = wave_sum_u64(nw_);
+    mx_ = wave_max_u32(mx_);
     const int wave = threadIdx.x / kWave;
     if (lane_id() == 0) {
         red[0][wave] = nx_;
         red[1][wave] = nw_;
+        redm[wave] = mx_;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -2369,6 +2400,7 @@ __global__ void __launch_bounds__(256) k_stream_wall(Dev D, int buf, long long q
         const int slot64 = blockIdx.x & 63;
         if (a) atomicAdd(&D.spart[slot64], a);
         if (bw) atomicAdd(&D.spart[64 + slot64], bw);
+        raise_max_cross(D, max(max(redm[0], redm[1]), max(redm[2], redm[3])));
     }
 }
 
@@ -3182,23 +3214,18 @@ void launch_stream_wall(const Dev &D, int buf, long long qseg, hipStream_t s) {
         k_stream_wall<R, false, false><<<g, 256, 0, s>>>(D, buf, qseg);
 }
 
-template <typename R, bool KE, bool BIG>
-void launch_sample_b(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
-    if (w == 1)
-        k_sample<R, 1, KE, BIG><<<g, 64, 0, s>>>(D, buf);
-    else if (w == 2)
-        k_sample<R, 2, KE, BIG><<<g, 128, 0, s>>>(D, buf);
-    else if (w == 8)
-        k_sample<R, 8, KE, BIG><<<g, 512, 0, s>>>(D, buf);
-    else
-        k_sample<R, 4, KE, BIG><<<g, 256, 0, s>>>(D, buf);
-}
-
 // the cells of at most 64 new particles, then those with more
 template <typename R, bool KE>
 void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
-    launch_sample_b<R, KE, false>(D, buf, w, g, s);
-    launch_sample_b<R, KE, true>(D, buf, w, g, s);
+    if (w == 1)
+        k_sample<R, 1, KE><<<g, 64, 0, s>>>(D, buf);
+    else if (w == 2)
+        k_sample<R, 2, KE><<<g, 128, 0, s>>>(D, buf);
+    else if (w == 8)
+        k_sample<R, 8, KE><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_sample<R, 4, KE><<<g, 256, 0, s>>>(D, buf);
+    k_sample_big<R, KE><<<(unsigned)((D.nc + 7) / 8), 512, 0, s>>>(D, buf);
 }
 
 template <typename R>

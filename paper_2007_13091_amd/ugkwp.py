@@ -23,8 +23,8 @@ SYMBOLS = ("ugkwp_workspace_bytes", "ugkwp_init_mesh", "ugkwp_init_state", "ugkw
            "ugkwp_particle_count", "ugkwp_export_particles", "ugkwp_geometry", "ugkwp_profile_enable",
            "ugkwp_profile_read", "ugkwp_profile_slot_name", "ugkwp_last_error", "ugkwp_destroy",
            "ugkwp_instance_stats", "ugkwp_instance_cells", "ugkwp_graph_enable", "ugkwp_set_launch",
-           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_profile_mask", "ugkwp_set_averaging", "ugkwp_average",
-           "ugkwp_export_state", "ugkwp_import_state", "ugkwp_init_mesh_static", "ugkwp_static_workspace_bytes")
+           "ugkwp_get_launch", "ugkwp_autotune", "ugkwp_autotune_cached", "ugkwp_profile_mask",
+           "ugkwp_set_averaging", "ugkwp_average", "ugkwp_export_state", "ugkwp_import_state", "ugkwp_init_mesh_static", "ugkwp_static_workspace_bytes")
 N_PROFILE_SLOTS = 12
 
 
@@ -53,7 +53,8 @@ class UgkwpStats(C.Structure):
     _fields_ = [("dt", C.c_double), ("t", C.c_double), ("step", C.c_int64), ("n_alive", C.c_int64),
                 ("n_sampled", C.c_int64), ("n_collided", C.c_int64), ("n_escaped", C.c_int64),
                 ("n_moved", C.c_int64), ("crossings", C.c_int64), ("wall_hits", C.c_int64),
-                ("error_word", C.c_uint32), ("moved_total", C.c_int64), ("n_injected", C.c_int64)]
+                ("error_word", C.c_uint32), ("moved_total", C.c_int64), ("n_injected", C.c_int64),
+                ("max_crossings_seen", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +97,8 @@ def lib():
         L.ugkwp_get_launch.argtypes = [vp, P(C.c_int32)]
         L.ugkwp_autotune.restype = C.c_int32
         L.ugkwp_autotune.argtypes = [vp, C.c_int32, P(C.c_int32)]
+        L.ugkwp_autotune_cached.restype = C.c_int32
+        L.ugkwp_autotune_cached.argtypes = [vp, C.c_int32, C.c_char_p, P(C.c_int32), P(C.c_int32)]
         L.ugkwp_instance_cells.restype = C.c_int32
         L.ugkwp_instance_cells.argtypes = [vp, C.c_int32, P(C.c_int64), P(C.c_int64)]
         L.ugkwp_init_state.restype = C.c_int32
@@ -288,11 +291,18 @@ class Solver:
         self._check(lib().ugkwp_get_launch(self.h, _ptr(out, C.c_int32)))
         return tuple(int(v) for v in out)
 
-    def autotune(self, steps_per_trial=3):
-        """Pick the fastest launch shapes on real steps (the state advances)."""
+    def autotune(self, steps_per_trial=3, cache=None):
+        """Pick the fastest launch shapes on real steps (the state advances).  cache: the path
+        of a result cache (JSON lines); a hit sets the cached shapes without stepping.  Returns
+        the shapes, and with a cache also whether it was a hit."""
         out = np.zeros(4, dtype=np.int32)
-        self._check(lib().ugkwp_autotune(self.h, int(steps_per_trial), _ptr(out, C.c_int32)))
-        return tuple(int(v) for v in out)
+        if cache is None:
+            self._check(lib().ugkwp_autotune(self.h, int(steps_per_trial), _ptr(out, C.c_int32)))
+            return tuple(int(v) for v in out)
+        hit = C.c_int32(0)
+        self._check(lib().ugkwp_autotune_cached(self.h, int(steps_per_trial), str(cache).encode(),
+                                                _ptr(out, C.c_int32), C.byref(hit)))
+        return tuple(int(v) for v in out), bool(hit.value)
 
     def moments(self, which=0):
         out = np.zeros((self.nc, 5), dtype=np.float64)

@@ -10,7 +10,9 @@ relative error.
 import numpy as np
 
 RTOL = 1e-12
-INT_KEYS = ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits")
+INT_KEYS = ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits",
+            "max_crossings_seen")
+BATCH_TOTALS = ("crossings", "wall_hits", "max_crossings_seen")  # reported for the whole batch only
 
 
 def _field_err(a, b, W_ref):

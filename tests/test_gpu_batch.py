@@ -9,7 +9,7 @@ import pytest
 
 from paper_2007_13091_amd import workloads as wl
 
-from parity import INT_KEYS, compare_fields, compare_particles
+from parity import BATCH_TOTALS, INT_KEYS, compare_fields, compare_particles
 
 pytestmark = pytest.mark.gpu
 
@@ -34,21 +34,23 @@ def _run_batch(ws, steps, precision=0, check_every=1, name=""):
     for n in range(steps):
         _say(name, "step", n)
         sb = g.step(1)
-        tot_cross = tot_wall = 0
+        tot_cross = tot_wall = max_cross = 0
         for k, (w, o) in enumerate(zip(ws, os_)):
             o.step()
             so = o.stats()
             si = g.instance_stats(k)
             tot_cross += so["crossings"]
             tot_wall += so["wall_hits"]
+            max_cross = max(max_cross, so["max_crossings_seen"])
             for key in INT_KEYS:
-                if key in ("crossings", "wall_hits"):
+                if key in BATCH_TOTALS:
                     continue
                 assert si[key] == so[key], f"{name} step {n} instance {k} {key}: gpu {si[key]} oracle {so[key]}"
             assert si["step"] == n + 1
             assert abs(si["dt"] - so["dt"]) <= 1e-12 * so["dt"], (k, si["dt"], so["dt"])
             assert abs(si["t"] - o.time) <= 1e-12 * o.time
         assert sb["crossings"] == tot_cross and sb["wall_hits"] == tot_wall
+        assert sb["max_crossings_seen"] == max_cross
         if (n + 1) % check_every == 0 or n == steps - 1:
             Wg, Pg = g.moments(0), g.moments(1) * vol_g[:, None]
             pg = g.particles()

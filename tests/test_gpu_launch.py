@@ -84,7 +84,8 @@ def test_graph_replay_equals_eager_every_step():
             a.step(1, stats=False)
             b.graph(True)
     sa, sb = a.step(2), b.step(2)
-    for key in ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits", "step"):
+    for key in ("n_alive", "n_sampled", "n_injected", "n_collided", "n_escaped", "crossings", "wall_hits", "step",
+                "max_crossings_seen"):
         assert sa[key] == sb[key], key
     _same(_state(b), _state(a), "graph replay end")
 
@@ -184,3 +185,36 @@ def test_profile_events_change_nothing_and_mask_selects_slots():
         s.close()
     _same(runs[1], runs[0], "all groups timed")
     _same(runs[2], runs[0], "stream timed")
+
+
+def test_autotune_cache_hit_and_miss(tmp_path):
+    # a miss tunes on real steps and appends a JSON line; the same workload then hits without a
+    # step; another workload (the FP32 form) misses; unreadable lines are ignored
+    import json
+
+    from paper_2007_13091_amd.ugkwp import Solver
+
+    ws = wl.small_batch(3)
+    W0 = np.concatenate([w.W0 for w in ws])
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text("not json\n")
+
+    def solver(precision=0):
+        s = Solver([w.mesh for w in ws], [w.params for w in ws], precision=precision)
+        s.init_state(W0)
+        return s
+
+    a = solver()
+    cfg, hit = a.autotune(1, cache=cache)
+    assert not hit and a.instance_stats(0)["step"] == 2 * 13
+    b = solver()
+    cfg2, hit2 = b.autotune(1, cache=cache)
+    assert hit2 and cfg2 == cfg and b.instance_stats(0)["step"] == 0
+    assert tuple(b.launch_config()) == cfg
+    c = solver(precision=1)
+    _, hit3 = c.autotune(1, cache=cache)
+    assert not hit3
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 3
+    rec = [json.loads(x) for x in lines[1:]]
+    assert rec[0]["launch"] == list(cfg) and rec[0]["key"] != rec[1]["key"]

@@ -64,7 +64,8 @@ def test_resume_is_bitwise(case, precision):
     _same(a, b, f"{case} after import")
     for n in range(4):
         sa, sb = a.step(1), b.step(1)
-        for k in ("n_alive", "n_sampled", "n_collided", "n_escaped", "n_injected", "crossings", "wall_hits"):
+        for k in ("n_alive", "n_sampled", "n_collided", "n_escaped", "n_injected", "crossings", "wall_hits",
+                  "max_crossings_seen"):
             assert sa[k] == sb[k], (case, n, k)
         _same(a, b, f"{case} step {n} after import")
 

@@ -92,3 +92,38 @@ def test_second_order_refused_with_periodic_faces():
     w.params.recon = 1
     with pytest.raises(oracle.OracleError):
         oracle.Oracle(w.mesh, w.params)
+
+
+def test_step_counts_total_and_most_crossings():
+    # a free-molecular periodic box whose mass is all in imported particles (W = P / Omega, so no
+    # hydro part and nothing sampled): in one step every particle flies u dt in a straight line,
+    # and the step's crossing total and maximum are the per-particle counts of cell boundaries
+    # passed on each axis
+    w = wl.periodic_box(n=(4, 3, 3), n_ref=10, kn=1e6, perturb=0.0, drift=(0.0, 0.0, 0.0))
+    o = oracle.Oracle(w.mesh, w.params)
+    hi = np.array([1.0, 0.75, 0.5])
+    h = hi / np.array([4, 3, 3])
+    rng = np.random.default_rng(4)
+    n = 400
+    x = rng.uniform(0, 1, (n, 3)) * hi
+    u = rng.normal(0, 3.0, (n, 3))
+    cell = np.array([_cell_of(w, p) for p in x])
+    order = np.argsort(cell, kind="stable")
+    x, u, cell = x[order], u[order], cell[order]
+    vol, _, _ = o.geometry()
+    m = np.full(n, vol.sum() / n)
+    P = np.zeros((o.nc, 5))
+    np.add.at(P[:, 0], cell, m)
+    for d in range(3):
+        np.add.at(P[:, 1 + d], cell, m * u[:, d])
+    np.add.at(P[:, 4], cell, 0.5 * m * (u * u).sum(1))
+    uid = (np.uint64(1) << np.uint64(62)) + np.arange(n, dtype=np.uint64)
+    o.import_state(dict(W=P / vol[:, None], P=P, particles=dict(x=x, u=u, m=m, cell=cell, uid=uid), step=0, t=0.0))
+    o.step()
+    st = o.stats()
+    assert st["n_sampled"] == 0 and st["n_collided"] == 0 and st["n_alive"] == n
+    dt = st["dt"]
+    passed = np.abs(np.floor((x + u * dt) / h) - np.floor(x / h)).sum(1).astype(np.int64)
+    assert passed.max() >= 2
+    assert st["crossings"] == int(passed.sum())
+    assert st["max_crossings_seen"] == int(passed.max())
