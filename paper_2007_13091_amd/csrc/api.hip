@@ -208,6 +208,7 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     D.segoff[1] = C.take<int32_t>(nc + 1);
     D.key = C.take<int32_t>((size_t)cap);
     D.perm = C.take<int32_t>((size_t)cap);
+    D.big = C.take<int32_t>(nc);
     for (int b = 0; b < 2; ++b) {
         ugkwp::Particles &P = D.pa[b];
         P.rec = nullptr;
@@ -580,6 +581,7 @@ int32_t ugkwp_init_state(ugkwp_ctx *ctx, const double *W0) {
     ugkwp::launch_fill_i32(D.segoff[0], (long long)nc + 1, 0, s);
     ugkwp::launch_fill_i32(D.segoff[1], (long long)nc + 1, 0, s);
     ugkwp::launch_fill_f64(D.avgA, 5 * (long long)nc, 0.0, s);
+    ugkwp::launch_heat(D, 0, s);  // no particle yet: zero heat fluxes
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(D.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
     std::vector<ugkwp::InstS> is((size_t)D.n_inst);
@@ -943,6 +945,7 @@ int32_t ugkwp_import_state(ugkwp_ctx *ctx, const double *W, const double *P, int
     }
     HIPCHK(ctx, up(D.is, is, s));
     ugkwp::launch_fill_f64(D.avgA, 5 * (long long)nc, 0.0, s);
+    ugkwp::launch_heat(D, b, s);  // the imported particles' heat fluxes (Shakhov model)
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipStreamSynchronize(s));
     ctx->have_state = true;

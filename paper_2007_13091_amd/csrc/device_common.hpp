@@ -94,6 +94,8 @@ struct Scalars {
     unsigned long long moved_total;  // particles streamed since the state was set
     unsigned int err;
     unsigned int max_cross;  // the most face crossings of one particle in the step
+    unsigned int n_big;      // cells with more than 64 new particles this step (k_sample_big's list)
+    unsigned int pad;
 };
 
 // One particle: position, velocity, mass and id in a 64-byte record, so that a particle
@@ -188,6 +190,7 @@ struct Dev {
     int32_t *segoff[2];     // [nc+1] each: survivor segments per cell in pa[0] / pa[1]
     int32_t *key;           // [cap]
     int32_t *perm;          // [cap]
+    int32_t *big;           // [nc] cells with more than 64 new particles (listed by k_sample)
     Particles pa[2];
     Scalars *sc;
     // time averaging: steps n > avg_from are averaged (avg_from < 0: off)

@@ -24,6 +24,7 @@
 // bucket is then fixed by sorting the source indices.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -394,6 +395,7 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
         Scalars *s = D.sc;
         s->n_sampled = 0;
         s->max_cross = 0u;
+        s->n_big = 0u;
     }
     if (blockIdx.x == 0 && threadIdx.x < kWallSeg) D.wallq[threadIdx.x] = 0u;
     // partial sums of crossings and wall hits of this step's transport
@@ -1186,11 +1188,54 @@ __device__ __forceinline__ void store_e(const Particles &pa, long long i, float 
 __device__ __forceinline__ double load_e(const Particles &pa, long long i, double) { return pa.e64[i]; }
 __device__ __forceinline__ float load_e(const Particles &pa, long long i, float) { return pa.e32[i]; }
 
+// Shakhov model (SH): the survivors' raw moments sum m u_i |u|^2 and sum m u_i u_j as well, so
+// that the cell's heat flux for the next step, q = (1/Omega) sum m c |c|^2 / 2 with c = u - U
+// and U from W^{n+1}, follows from them and P^{n+1} by expanding c = u - U (the particles and
+// the state the next step starts from are exactly these)
+template <bool SH>
+__device__ __forceinline__ void add_heat(double m, double u0, double u1, double u2, double H[9]) {
+    if constexpr (SH) {
+        const double w = m * (u0 * u0 + u1 * u1 + u2 * u2);
+        H[0] += w * u0;
+        H[1] += w * u1;
+        H[2] += w * u2;
+        H[3] += m * u0 * u0;
+        H[4] += m * u0 * u1;
+        H[5] += m * u0 * u2;
+        H[6] += m * u1 * u1;
+        H[7] += m * u1 * u2;
+        H[8] += m * u2 * u2;
+    }
+}
+// q of one cell from its survivors' raw moments H (summed as above, then over the wave), its
+// P^{n+1} and W^{n+1}: lane i < 3 returns component i,
+//   sum m c_i |c|^2 = S3_i - 2 sum_j U_j S2_ij - U_i tr S2 + |U|^2 S1_i + 2 U_i (U . S1) - U_i |U|^2 S0
+__device__ __forceinline__ double heat_of(const double H[9], const double Wn[5], const double Pv[5], double vol) {
+    const int lane = lane_id();
+    const double U[3] = {Wn[1] / Wn[0], Wn[2] / Wn[0], Wn[3] / Wn[0]};
+    const double tr = H[3] + H[6] + H[8];
+    const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    const double us1 = U[0] * Pv[1] + U[1] * Pv[2] + U[2] * Pv[3];
+    // lane i takes component i (selects, not register-array indexing)
+    const double r0 = H[3] * U[0] + H[4] * U[1] + H[5] * U[2];
+    const double r1 = H[4] * U[0] + H[6] * U[1] + H[7] * U[2];
+    const double r2 = H[5] * U[0] + H[7] * U[1] + H[8] * U[2];
+    const double s2u = lane == 0 ? r0 : (lane == 1 ? r1 : r2);
+    const double s3 = lane == 0 ? H[0] : (lane == 1 ? H[1] : H[2]);
+    const double s1 = lane == 0 ? Pv[1] : (lane == 1 ? Pv[2] : Pv[3]);
+    const double ui = lane == 0 ? U[0] : (lane == 1 ? U[1] : U[2]);
+    const double t = s3 - 2.0 * s2u - ui * tr + uu * s1 + 2.0 * ui * us1 - ui * uu * Pv[0];
+    return 0.5 * t / vol;
+}
+
 // ---------------------------------------------------------------------------------------
 // Shakhov model: the heat flux of the gas in each cell at the start of the step,
 //   q = (1/Omega) sum_k m_k c_k |c_k|^2 / 2,  c_k = u_k - U,  U = (W_1, W_2, W_3) / W_0,
 // over the particles the cell holds (the hydro part, a Maxwellian at the cell's U and T,
-// carries none); one wave per cell, FP64 sums with a fixed tree.
+// carries none).  The gather of every step leaves it for the next one; this kernel computes it
+// after the state is set (init_state, import_state), from the raw moments sum m u_i |u|^2 and
+// sum m u_i u_j summed exactly as the gather sums them (lane l the particles s0 + l + 64 k, in
+// increasing k), so that both give the same bits.  One wave per cell.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void load_um(const Particles &pa, long long i, double u[3], double &m, double) {
     const double2 *r = reinterpret_cast<const double2 *>(pa.rec + i);
@@ -1216,25 +1261,26 @@ __global__ void __launch_bounds__(256) k_heat(Dev D, int buf) {
     const int c = blockIdx.x * 4 + wave;
     if (c >= D.nc) return;
     const int nc = D.nc;
-    double h[3] = {0.0, 0.0, 0.0};
-    if (D.ip[inst_of(D, c)].pr != 1.0) {
-        const double W0 = D.W[c];
-        const double U[3] = {D.W[nc + c] / W0, D.W[2 * nc + c] / W0, D.W[3 * nc + c] / W0};
+    const bool sh = D.ip[inst_of(D, c)].pr != 1.0;
+    double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (sh) {
         const long long s0 = D.segoff[buf][c], s1 = D.segoff[buf][c + 1];
         const Particles pa = D.pa[buf];
         for (long long i = s0 + lane; i < s1; i += kWave) {
             double u[3], m;
             load_um(pa, i, u, m, R(0));
-            const double cv[3] = {u[0] - U[0], u[1] - U[1], u[2] - U[2]};
-            const double e = 0.5 * m * (cv[0] * cv[0] + cv[1] * cv[1] + cv[2] * cv[2]);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) h[d] += e * cv[d];
+            add_heat<true>(m, u[0], u[1], u[2], H);
         }
-    }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) h[d] = wave_sum(h[d]);
-    const double hk = lane == 1 ? h[1] : (lane == 2 ? h[2] : h[0]);
-    if (lane < 3) D.qh[lane * nc + c] = hk / D.vol[c];
+        for (int k = 0; k < 9; ++k) H[k] = wave_sum(H[k]);
+    }
+    double Wn[5], Pv[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        Wn[k] = D.W[k * nc + c];
+        Pv[k] = D.P[k * nc + c];
+    }
+    if (lane < 3) D.qh[lane * nc + c] = sh ? heat_of(H, Wn, Pv, D.vol[c]) : 0.0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1440,6 +1486,19 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll
         for (int k = 0; k < 5; ++k) D.S[k * nc + c] = D.P[k * nc + c] + 0.0;
     }
+    // cells with more than 64 new particles go to k_sample_big's list (one atomic per wave)
+    {
+        const bool big = lane < G && myns > kWave;
+        const unsigned long long mb = __ballot(big);
+        if (mb) {
+            const int first = __ffsll((long long)mb) - 1;
+            unsigned int at = 0;
+            if (lane == first) at = atomicAdd(&D.sc->n_big, (unsigned int)__popcll(mb));
+            at = __shfl(at, first);
+            const unsigned long long below = lane == 0 ? 0ULL : (~0ULL >> (64 - lane));
+            if (big) D.big[at + __popcll(mb & below)] = c0 + lane;
+        }
+    }
     int g = 0;
     while (g < G) {
         if (c0 + g >= nc) break;
@@ -1537,15 +1596,17 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
     }
 }
 
-// The cells with more than 64 new particles, one wave each (a launch of its own, so that its
-// registers do not add to k_sample's); the waves of the other cells leave at once.
+// The cells with more than 64 new particles, which k_sample listed, one wave each (a launch
+// of its own, so that its registers do not add to k_sample's); the waves take the list in a
+// grid-stride loop (a cell's particles do not depend on which wave samples it).
 template <typename R, bool KE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_sample_big(Dev D, int buf) {
-    const int c = blockIdx.x * 8 + (int)(threadIdx.x / kWave);
-    if (c >= D.nc) return;
-    if (D.gp_any && D.ip[inst_of(D, c)].sampling >= 2) return;
-    const long long ns = D.sc->n_new > 0 ? D.nsam[c] : 0;
-    if (ns > kWave) sample_cell<R, KE>(D, buf, c, ns);
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) k_sample_big(Dev D, int buf) {
+    const long long nb = (long long)D.sc->n_big;
+    const long long waves = (long long)gridDim.x * 8;
+    for (long long k = (long long)blockIdx.x * 8 + (int)(threadIdx.x / kWave); k < nb; k += waves) {
+        const int c = D.big[k];
+        sample_cell<R, KE>(D, buf, c, D.nsam[c]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2722,13 +2783,36 @@ __device__ __forceinline__ void stage_out(const uint4 *st, const Particles &dst,
 // collided particles ending in c they give E; then W^{n+1} = W^n + (-sum_f s_f Phi_f + E - S) /
 // Omega.  Fixed per-lane assignment and reduction tree: bitwise reproducible.
 // ---------------------------------------------------------------------------------------
-template <typename R, int WPB, bool KE>
-__global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
+// The sums follow the output positions: the survivor at position base + l + 64 k is summed by
+// lane l, in increasing k, which is the order in which k_heat sums the same particles (so that
+// a state imported between steps gets the heat flux the gather would have left, bit for bit).
+// After a run of n records is stored from the stage to positions o0.., lane l takes the staged
+// record at index (l - (o0 - base)) mod 64.  FP32: the masses are staged beside the records.
+__device__ __forceinline__ void stage_mass(float *stm, int k, const Rec64 &) {}
+__device__ __forceinline__ void stage_mass(float *stm, int k, const Rec32 &q) { stm[k] = q.v[8]; }
+template <typename R>
+__device__ __forceinline__ void heat_from_stage(const uint4 *st, const float *stm, int r, int n, double H[9]) {
+    const int kk = (lane_id() - r) & (kWave - 1);
+    if (kk < n) {
+        if constexpr (sizeof(R) == 8) {
+            const double2 *a = reinterpret_cast<const double2 *>(st + kk * 4);
+            add_heat<true>(a[3].x, a[1].y, a[2].x, a[2].y, H);
+        } else {
+            const float4 *a = reinterpret_cast<const float4 *>(st + kk * 2);
+            add_heat<true>((double)stm[kk], (double)a[0].w, (double)a[1].x, (double)a[1].y, H);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+template <typename R, int WPB, bool KE, bool SH>
+__device__ __forceinline__ void gather_cells(const Dev &D, int buf) {
     constexpr int BS = kWave;
     constexpr int kLds = 256;  // longer source lists are sorted in place in global memory
     constexpr int CPR = RecChunks<R>::N;
     __shared__ int lds_all[WPB][kLds];
     __shared__ uint4 st_all[WPB][kWave * CPR];
+    __shared__ float stm_all[WPB][SH ? kWave : 1];  // staged FP32 masses (heat sums)
     // WPB waves per block, one cell each, independent of one another (no block barrier).
     // Blocks go round-robin to the 8 XCDs; give each XCD a contiguous range of cells so
     // that neighbouring cells (whose particles are exchanged) share an L2
@@ -2740,6 +2824,7 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
     if (c >= nc) return;
     int *lds = lds_all[wave];
     uint4 *st = st_all[wave];
+    float *stm = stm_all[wave];
     const int lane = lane_id();
     const Particles src = D.pa[buf], dst = D.pa[buf ^ 1];
     const Scalars *sc = D.sc;
@@ -2785,9 +2870,12 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             D.segoff[buf ^ 1][c] = base;
             if (base != bend) atomicOr(&D.sc->err, kErrCapacity);
         }
+        if (SH && lane < 3) D.qh[lane * nc + c] = 0.0;
         return;
     }
     double Pn[5] = {0, 0, 0, 0, 0}, Cn[5] = {0, 0, 0, 0, 0};
+    double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const bool shc = SH && D.ip[inst_of(D, c)].pr != 1.0;
     // movers (part 0) and collided (part 1): source lists sorted ascending
     for (int part = 0; part < 2; ++part) {
         const int a0 = part == 0 ? base : cb0;
@@ -2810,9 +2898,13 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
                 if (ha) load_rec<KE>(src, list[j], A);
                 if (hb) load_rec<KE>(src, list[j + BS], B);
                 if (ha) stage_rec<KE>(dst, a0 + j, c, A, Pn, st + lane * CPR);
+                if (SH && ha) stage_mass(stm, lane, A);
                 stage_out<R>(st, dst, a0 + j0, min(BS, len - j0));
+                if (shc) heat_from_stage<R>(st, stm, (a0 + j0 - base) & 63, min(BS, len - j0), H);
                 if (hb) stage_rec<KE>(dst, a0 + j + BS, c, B, Pn, st + lane * CPR);
+                if (SH && hb) stage_mass(stm, lane, B);
                 stage_out<R>(st, dst, a0 + j0 + BS, max(0, min(BS, len - j0 - BS)));
+                if (shc) heat_from_stage<R>(st, stm, (a0 + j0 + BS - base) & 63, max(0, min(BS, len - j0 - BS)), H);
             }
         } else {
 #pragma unroll 2
@@ -2842,19 +2934,25 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
             if (sb) advance(B, dtR);
             const int ra = (int)__popcll(ma & below), rb = (int)__popcll(mb & below);
             if (sa) stage_rec<KE>(dst, pos + ra, c, A, Pn, st + ra * CPR);
+            if (SH && sa) stage_mass(stm, ra, A);
             stage_out<R>(st, dst, pos, (int)__popcll(ma));
+            if (shc) heat_from_stage<R>(st, stm, (pos - base) & 63, (int)__popcll(ma), H);
             pos += (int)__popcll(ma);
             if (sb) stage_rec<KE>(dst, pos + rb, c, B, Pn, st + rb * CPR);
+            if (SH && sb) stage_mass(stm, rb, B);
             stage_out<R>(st, dst, pos, (int)__popcll(mb));
+            if (shc) heat_from_stage<R>(st, stm, (pos - base) & 63, (int)__popcll(mb), H);
             pos += (int)__popcll(mb);
         }
     }
     double Pk, Ck;
     wave_sum_pc(Pn, Cn, Pk, Ck);
+    double Wk = 0.0;
     if (lane < 5) {
         const double E = Pk + Ck;
         const double acc = facc + (E - D.S[lane * nc + c]);
-        D.W[lane * nc + c] = D.W[lane * nc + c] + acc / D.vol[c];
+        Wk = D.W[lane * nc + c] + acc / D.vol[c];
+        D.W[lane * nc + c] = Wk;
         D.P[lane * nc + c] = Pk;
     }
     if (lane == 0) {
@@ -2862,6 +2960,31 @@ __global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
         D.segoff[buf ^ 1][c] = base;
         if (pos != bend) atomicOr(&D.sc->err, kErrCapacity);
     }
+    if constexpr (SH) {
+        // sum m c_i |c|^2 = S3_i - 2 sum_j U_j S2_ij - U_i tr S2 + |U|^2 S1_i + 2 U_i (U . S1) - U_i |U|^2 S0
+        if (shc) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) H[k] = wave_sum(H[k]);
+        }
+        double Wn[5], Pv[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            Wn[k] = __shfl(Wk, k);
+            Pv[k] = __shfl(Pk, k);
+        }
+        if (lane < 3) D.qh[lane * nc + c] = shc ? heat_of(H, Wn, Pv, D.vol[c]) : 0.0;
+    }
+}
+
+template <typename R, int WPB, bool KE>
+__global__ void __launch_bounds__(WPB * 64) k_gather(Dev D, int buf) {
+    gather_cells<R, WPB, KE, false>(D, buf);
+}
+// the gather of a batch with an instance of the Shakhov model (K = 0): also each cell's heat
+// flux for the next step
+template <typename R, int WPB>
+__global__ void __launch_bounds__(WPB * 64) k_gather_sh(Dev D, int buf) {
+    gather_cells<R, WPB, false, true>(D, buf);
 }
 
 // S6 in a wave-only step with no particle anywhere (none is left, sampled or let in): the
@@ -3225,7 +3348,9 @@ void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
         k_sample<R, 8, KE><<<g, 512, 0, s>>>(D, buf);
     else
         k_sample<R, 4, KE><<<g, 256, 0, s>>>(D, buf);
-    k_sample_big<R, KE><<<(unsigned)((D.nc + 7) / 8), 512, 0, s>>>(D, buf);
+    // at most a wave per cell; a grid of a few thousand waves takes any list in turns
+    const unsigned gb = (unsigned)std::min<long long>((D.nc + 7) / 8, 2048);
+    k_sample_big<R, KE><<<gb, 512, 0, s>>>(D, buf);
 }
 
 template <typename R>
@@ -3249,8 +3374,6 @@ template <typename R>
 void launch_flux(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
     const int bs = cfg.flux_bs, nf = D.nf;
     const unsigned g = (unsigned)((nf + bs - 1) / bs);
-    // Shakhov model: the cells' heat fluxes, which the flux and the sampling read
-    if (D.sh_any) k_heat<R><<<(unsigned)((D.nc + 3) / 4), 256, 0, s>>>(D, buf);
     if (D.recon_any) {
         // second order: gradients (one thread per cell), then the faces of reconstructing
         // instances; the first-order kernel takes the others
@@ -3271,6 +3394,14 @@ void launch_flux(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
         k_flux<R, 128><<<g, 128, 0, s>>>(D);
 }
 }  // namespace
+
+void launch_heat(const Dev &D, int buf, hipStream_t s) {
+    if (!D.sh_any) return;
+    if (D.prec == 1)
+        k_heat<float><<<(unsigned)((D.nc + 3) / 4), 256, 0, s>>>(D, buf);
+    else
+        k_heat<double><<<(unsigned)((D.nc + 3) / 4), 256, 0, s>>>(D, buf);
+}
 
 bool launch_cfg_valid(const LaunchCfg &c) {
     const bool sb = (c.stream_bs == 128 || c.stream_bs == 256 || c.stream_bs == 512) &&
@@ -3344,7 +3475,11 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     {
         constexpr int WPB = kGatherWaves;
         const unsigned g = (unsigned)((nc + WPB - 1) / WPB);
-        if (f32 && D.K > 0)
+        if (D.sh_any && f32)
+            k_gather_sh<float, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+        else if (D.sh_any)
+            k_gather_sh<double, WPB><<<g, WPB * 64, 0, s>>>(D, buf);
+        else if (f32 && D.K > 0)
             k_gather<float, WPB, true><<<g, WPB * 64, 0, s>>>(D, buf);
         else if (f32)
             k_gather<float, WPB, false><<<g, WPB * 64, 0, s>>>(D, buf);

@@ -46,6 +46,9 @@ void launch_fill_f64(double *p, long long n, double v, hipStream_t s);
 void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr);
 // a wave-only step when no particle exists anywhere (the same results as launch_step)
 void launch_step_wave_only(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Prof *pr);
+// Shakhov model: each cell's heat flux from the particles in pa[buf] (after the state is set;
+// the gather keeps it up to date from then on)
+void launch_heat(const Dev &D, int buf, hipStream_t s);
 // [nc][5] field (0 W, 1 W^p, 2 W^h, 3 primitives) into device memory out
 void launch_moments(const Dev &D, int which, double *out, hipStream_t s);
 // Wbar = A / D of the time averaging, [nc][5] in out

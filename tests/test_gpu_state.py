@@ -1,7 +1,9 @@
 """State export and import through the C ABI (checkpoint and restart between steps).
 
 * Resume: a run exported after k steps and imported into a fresh context continues bit for
-  bit like the run that was never interrupted (both forms; a batch of instances).
+  bit like the run that was never interrupted (both forms; a batch of instances; the Shakhov
+  model, whose heat fluxes a pass of their own recomputes after the import in the order the
+  gather sums them).
 * Import of a state the oracle reached (particles in the oracle's order, grouped by cell for
   the library), then GPU-vs-oracle parity over the next steps: the imported particles are
   the old particles of the next step, with their free-flight draws keyed by their ids.
@@ -45,10 +47,15 @@ def _same(a, b, what):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("case", ["tets-diffuse", "farfield", "batch"])
+@pytest.mark.parametrize("case", ["tets-diffuse", "farfield", "batch", "shakhov"])
 def test_resume_is_bitwise(case, precision):
     if case == "tets-diffuse":
         w = wl.closed_box(n=(4, 3, 3), n_ref=60, kn=0.3, bc=wl.BC_DIFFUSE, tets=True, jitter=0.15, perturb=0.2)
+    elif case == "shakhov":
+        # the heat fluxes the gather leaves for the next step, recomputed after the import by a
+        # pass of their own summed in the same order
+        w = wl.cavity(n=6, n_ref=80)
+        w.params.recon, w.params.sampling, w.params.prandtl = 2, 2, 2.0 / 3.0
     elif case == "farfield":
         w = wl.free_stream_box(n=(5, 4, 3), U=(0.9, -0.3, 0.2), n_ref=80, kn=0.05, perturb=0.3)
     else:
