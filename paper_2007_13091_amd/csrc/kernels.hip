@@ -48,7 +48,8 @@ __device__ __forceinline__ void st_nt(uint4 *p, const uint4 &v) {
 constexpr int kWave = 64;
 constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
 constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
-constexpr int kSampleCells = 8;     // consecutive cells per wave in k_sample
+constexpr int kSampleCells = 8;     // consecutive cells per wave in k_sample (meshes of 32768 cells or more)
+constexpr int kSampleCellsMin = 32768;
 constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (2 and 4 are slower in FP32)
 
 // ---------------------------------------------------------------------------------------
@@ -1444,15 +1445,15 @@ __device__ __forceinline__ double seg_sum(double v, int first, int last) {
     return __shfl(v, last);
 }
 
-// Each wave takes kSampleCells consecutive cells: runs of consecutive cells whose new
-// particles fit in 64 lanes together are sampled at once, lane by lane in cell order (most
-// cells sample a few particles: one wave per cell left most lanes idle).  A cell with more than
-// 64 is k_sample_big's.  A pair's partners sit in neighbouring lanes of one cell (every count
-// and prefix is even); the energy-exact factor and S come from segmented sums over the cell's
-// lanes.  The arithmetic per particle is that of sample_cell.
-template <typename R, int WPB, bool KE>
+// Each wave takes G consecutive cells: runs of consecutive cells whose new particles fit in 64
+// lanes together are sampled at once, lane by lane in cell order (most cells sample a few
+// particles: one wave per cell left most lanes idle).  G = 8 on meshes of 32768 cells or more;
+// a smaller mesh would leave most of the chip idle with a wave per 8 cells, and takes G = 1.  A
+// cell with more than 64 is k_sample_big's.  A pair's partners sit in neighbouring lanes of
+// one cell (every count and prefix is even); the energy-exact factor and S come from
+// segmented sums over the cell's lanes.  The arithmetic per particle is that of sample_cell.
+template <typename R, int WPB, bool KE, int G>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3))) k_sample(Dev D, int buf) {
-    constexpr int G = kSampleCells;
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     const int c0 = (blockIdx.x * WPB + wave) * G;
@@ -3337,17 +3338,26 @@ void launch_stream_wall(const Dev &D, int buf, long long qseg, hipStream_t s) {
         k_stream_wall<R, false, false><<<g, 256, 0, s>>>(D, buf, qseg);
 }
 
+template <typename R, bool KE, int G>
+void launch_sample_g(const Dev &D, int buf, int w, hipStream_t s) {
+    const unsigned g = (unsigned)((D.nc + w * G - 1) / (w * G));
+    if (w == 1)
+        k_sample<R, 1, KE, G><<<g, 64, 0, s>>>(D, buf);
+    else if (w == 2)
+        k_sample<R, 2, KE, G><<<g, 128, 0, s>>>(D, buf);
+    else if (w == 8)
+        k_sample<R, 8, KE, G><<<g, 512, 0, s>>>(D, buf);
+    else
+        k_sample<R, 4, KE, G><<<g, 256, 0, s>>>(D, buf);
+}
+
 // the cells of at most 64 new particles, then those with more
 template <typename R, bool KE>
-void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
-    if (w == 1)
-        k_sample<R, 1, KE><<<g, 64, 0, s>>>(D, buf);
-    else if (w == 2)
-        k_sample<R, 2, KE><<<g, 128, 0, s>>>(D, buf);
-    else if (w == 8)
-        k_sample<R, 8, KE><<<g, 512, 0, s>>>(D, buf);
+void launch_sample_k(const Dev &D, int buf, int w, hipStream_t s) {
+    if (D.nc >= kSampleCellsMin)
+        launch_sample_g<R, KE, kSampleCells>(D, buf, w, s);
     else
-        k_sample<R, 4, KE><<<g, 256, 0, s>>>(D, buf);
+        launch_sample_g<R, KE, 1>(D, buf, w, s);
     // at most a wave per cell; a grid of a few thousand waves takes any list in turns
     const unsigned gb = (unsigned)std::min<long long>((D.nc + 7) / 8, 2048);
     k_sample_big<R, KE><<<gb, 512, 0, s>>>(D, buf);
@@ -3356,11 +3366,10 @@ void launch_sample_k(const Dev &D, int buf, int w, unsigned g, hipStream_t s) {
 template <typename R>
 void launch_sample(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s) {
     const int w = cfg.sample_wpb, nc = D.nc;
-    const unsigned g = (unsigned)((nc + w * kSampleCells - 1) / (w * kSampleCells));
     if (D.K > 0)
-        launch_sample_k<R, true>(D, buf, w, g, s);
+        launch_sample_k<R, true>(D, buf, w, s);
     else
-        launch_sample_k<R, false>(D, buf, w, g, s);
+        launch_sample_k<R, false>(D, buf, w, s);
     if (D.gp_any) {
         const unsigned g4 = (unsigned)((nc + 3) / 4);
         if (D.K > 0)
