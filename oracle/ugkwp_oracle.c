@@ -28,9 +28,10 @@
  * Philox against numpy, moments and q-coefficients against quadrature, the uniform-state
  * flux against the Euler flux, conservation in closed boxes, the free-molecular limit,
  * brute-force tracking on two-cell meshes, exact sampling counts and masses, and the
- * Euler-limit shock tube against an exact Riemann solver.  The complete multi-step
- * trajectory at finite Knudsen number has no printed values in the paper: beyond those
- * invariants it is "parity unpinned".
+ * Euler-limit shock tube against an exact Riemann solver; for the Shakhov model, Gauss-Hermite
+ * moments of its correction and the homogeneous relaxation of the heat flux.  The complete
+ * multi-step trajectory at finite Knudsen number has no printed values in the paper: beyond
+ * those invariants it is "parity unpinned".
  */
 #define _DEFAULT_SOURCE
 #include <math.h>
