@@ -6,7 +6,8 @@
  *   S0 primitives, tau = mu/p and the CFL time step                  (Sec. 2.4(a))
  *   S2 wave flux F^eq + F^{fr,wave} over every face                  (Sec. 2.2, Sec. 2.4)
  *   S3 sampling of hydro particles from the Maxwellian of W^h, or     (Sec. 2.3, Sec. 2.4(b))
- *      from its first-order g_p (sampling = 2)
+ *      from its first-order g_p (sampling = 2), or independently from the equilibrium of the
+ *      collision model (sampling = 3; the Shakhov g^+ when prandtl != 1, Sec. 2.1, Sec. 5)
  *   S4 free-flight time t_f = min(-tau ln eta, dt) of each particle   (Eq. for t_f, Sec. 2.3)
  *   S5 face-to-face free transport with wall reflection              (Sec. 2.3, Sec. 2.4(e))
  *   S6 net particle flux, conservative update, removal of collided    (Eq. update_macro_variables)
