@@ -149,6 +149,29 @@ struct Carver {
     }
 };
 
+// Every cell an axis-aligned box, and each interior face (periodic ones aside) a whole face of
+// both its cells: the cell across local face lf (2d low and 2d+1 high side of axis d) then has
+// this cell's bounds on the other two axes and, along d, this cell's high bound as its low one
+// (or the reverse) and a far bound of its own.  Checked bit for bit on the bounds themselves,
+// so that a box built that way during tracking equals the one stored.
+static bool conforming_boxes(const HostMesh &H) {
+    const size_t nc = (size_t)H.nc;
+    for (size_t c = 0; c < nc; ++c)
+        if (H.ctype[c] != 8) return false;
+    auto same = [](double a, double b) { return std::memcmp(&a, &b, sizeof(double)) == 0; };
+    for (size_t c = 0; c < nc; ++c)
+        for (int lf = 0; lf < 6; ++lf) {
+            const int32_t nb = H.nb[6 * c + lf];
+            if (nb < 0 || H.nblf[6 * c + lf] >= ugkwp::kPeriodicEntry) continue;
+            const int d = lf >> 1;
+            const double *a = &H.box[6 * c], *b = &H.box[6 * (size_t)nb];
+            for (int k = 0; k < 3; ++k)
+                if (k != d && !(same(a[k], b[k]) && same(a[3 + k], b[3 + k]))) return false;
+            if (!((lf & 1) ? same(b[d], a[3 + d]) : same(b[3 + d], a[d]))) return false;
+        }
+    return true;
+}
+
 // Lay the workspace out; with base == nullptr only the size is computed.
 size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon, int K, bool shakhov, Dev &D,
              char *base) {
@@ -167,6 +190,9 @@ size_t carve(const HostMesh &H, int n_inst, long long cap, int prec, bool recon,
     D.plane = C.take<double4>(6 * nc);
     D.box32 = prec == 1 ? C.take<float>(6 * nc) : nullptr;
     D.plane32 = prec == 1 ? C.take<float4>(6 * nc) : nullptr;
+    const bool cb = conforming_boxes(H);
+    D.nfar = cb ? C.take<double>(6 * nc) : nullptr;
+    D.nfar32 = cb && prec == 1 ? C.take<float>(6 * nc) : nullptr;
     D.nbl = C.take<int2>(6 * nc);
     D.cface = C.take<int32_t>(6 * nc);
     D.fown = C.take<int32_t>(nf);
@@ -464,6 +490,7 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     }
     D.any_diffuse = 0;
     for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
+    D.all_box = D.nfar != nullptr ? 1 : 0;
     D.cap = cap;
     D.prec = p[0].precision;
     D.K = K;
@@ -532,6 +559,22 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     e = e ? e : up((uint8_t *)D.ctype, H.ctype, s);
     e = e ? e : hipMemcpyAsync((void *)D.plane, H.plane.data(), H.plane.size() * sizeof(double), hipMemcpyHostToDevice, s);
     e = e ? e : up((int2 *)D.nbl, nbl, s);
+    std::vector<double> far;  // (host copies live until the synchronisation below)
+    std::vector<float> far32;
+    if (D.all_box) {
+        far.assign(6 * nc, 0.0);
+        for (size_t i = 0; i < 6 * nc; ++i) {
+            const int32_t nb = H.nb[i];
+            if (nb < 0 || H.nblf[i] >= ugkwp::kPeriodicEntry) continue;
+            const int lf = (int)(i % 6), d = lf >> 1;
+            far[i] = H.box[6 * (size_t)nb + ((lf & 1) ? 3 + d : d)];
+        }
+        e = e ? e : up((double *)D.nfar, far, s);
+        if (D.prec == 1) {
+            far32.assign(far.begin(), far.end());
+            e = e ? e : up((float *)D.nfar32, far32, s);
+        }
+    }
     e = e ? e : up((int32_t *)D.cface, H.cface, s);
     e = e ? e : up((int32_t *)D.fown, H.fown, s);
     e = e ? e : up((int32_t *)D.fnb, H.fnb, s);

@@ -137,6 +137,9 @@ struct Dev {
     const double4 *plane;   // [nc*6]  (n, d) outward
     const float *box32;     // FP32 copies for the FP32 form
     const float4 *plane32;
+    const double *nfar;     // [nc*6] conforming boxes (all_box): the bound of the neighbour across
+                            // the face on the far side along the face's axis
+    const float *nfar32;    // the same for the FP32 form
     const int2 *nbl;        // [nc*6]  (neighbour or -1-bc, local face in neighbour)
     const int32_t *cface;   // [nc*6]  +-(f+1)
     const int32_t *fown;    // [nf]
@@ -155,7 +158,10 @@ struct Dev {
     int32_t n_inst, prec;   // prec: 0 FP64 plain, 1 FP32 form
     int32_t K;              // internal degrees of freedom of the gas (every instance)
     int32_t gp_any;         // some instance draws its hydro particles one by one (sampling 2 or 3)
-    int32_t sh_any, pad2;   // some instance uses the Shakhov model (the heat-flux kernel runs)
+    int32_t sh_any;         // some instance uses the Shakhov model (the heat-flux kernel runs)
+    int32_t all_box;        // every cell is an axis-aligned box and interior neighbours share whole
+                            // faces: tracking needs no cell type, and the box of the cell across a
+                            // face is this one's with the bounds along the face's axis moved
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
     const InstP *ip;        // [n_inst]

@@ -1937,6 +1937,17 @@ template <>
 __device__ __forceinline__ const float *cell_box<float>(const Dev &D, int c) {
     return D.box32 + 6 * c;
 }
+template <typename R>
+__device__ __forceinline__ R face_far(const Dev &D, int s);
+template <>
+__device__ __forceinline__ double face_far<double>(const Dev &D, int s) {
+    return D.nfar[s];
+}
+template <>
+__device__ __forceinline__ float face_far<float>(const Dev &D, int s) {
+    return D.nfar32[s];
+}
+
 __device__ __forceinline__ void cell_plane(const Dev &D, int s, double p[4]) {
     const double4 q = D.plane[s];
     p[0] = q.x;
@@ -1990,19 +2001,23 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
     int c = cell;
     R trem = ts;
     bool first = ct0 >= 0;
+    // bounds of box cell c; on conforming boxes a crossing builds them for the next cell
+    R B[6];
+    bool haveB = first;
+    if (first) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) B[q] = B0[q];
+    }
     for (;;) {
         R best = (R)INFINITY;
         int bf = -1;
-        const int ctc = first ? ct0 : (int)D.ctype[c];
+        const int ctc = first ? ct0 : (D.all_box ? 8 : (int)D.ctype[c]);
         if (ctc == 8) {
-            R B[6];
-            if (first) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) B[q] = B0[q];
-            } else {
+            if (!haveB) {
                 const R *Bg = cell_box<R>(D, c);
 #pragma unroll
                 for (int q = 0; q < 6; ++q) B[q] = Bg[q];
+                haveB = true;
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -2065,6 +2080,8 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
             return -1;
         }
         const int2 nb = D.nbl[c * 6 + bf];
+        // the far bound of the next box, loaded together with the neighbour
+        const R far = D.all_box ? face_far<R>(D, c * 6 + bf) : (R)0;
         if (nb.x >= 0) {
             int ent = nb.y;
             if (ent >= kPeriodicEntry) {
@@ -2074,6 +2091,20 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
                 x[1] = x[1] + (R)pb.shift[1];
                 x[2] = x[2] + (R)pb.shift[2];
                 ent = ent % kPeriodicEntry;
+                haveB = false;
+            } else if (D.all_box) {
+                // the neighbour shares the whole face: its bounds along the face's axis are
+                // this cell's bound at the face and the far one
+                const int d = bf >> 1;
+                if (bf & 1) {
+                    B[d] = B[3 + d];
+                    B[3 + d] = far;
+                } else {
+                    B[3 + d] = B[d];
+                    B[d] = far;
+                }
+            } else {
+                haveB = false;
             }
             entry = ent;
             c = nb.x;
@@ -2081,7 +2112,7 @@ __device__ int track(const Dev &D, R x[3], R u[3], int &cell, R &ts, int &entry,
         }
         const DevBC &b = D.bc[-1 - nb.x];
         if (b.type == 0) {
-            if (D.ctype[c] == 8) {
+            if (ctc == 8) {
                 // u - 2 (u.n) n with n = +-e_d flips exactly component d
                 const int d = bf >> 1;
                 u[d] = -u[d];
