@@ -2584,16 +2584,32 @@ __global__ void __launch_bounds__(256) k_count(Dev D) {
         }
     }
     __syncthreads();
-    // block totals into the buckets; the entry's count is replaced by the block's base
-    for (int h = threadIdx.x; h < TS; h += 256) {
-        const int k = tkey[h];
-        if (k >= 0) tcnt[h] = atomicAdd(&D.cnt64[k], tcnt[h]);
+    // block totals into the buckets; the entry's count is replaced by the block's base (all
+    // of a thread's atomics are issued before the first result is waited for)
+    {
+        constexpr int PT = TS / 256;
+        int hk[PT];
+        unsigned long long hv[PT];
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            hk[q] = tkey[q * 256 + threadIdx.x];
+            hv[q] = tcnt[q * 256 + threadIdx.x];
+        }
+#pragma unroll
+        for (int q = 0; q < PT; ++q)
+            if (hk[q] >= 0) hv[q] = atomicAdd(&D.cnt64[hk[q]], hv[q]);
+#pragma unroll
+        for (int q = 0; q < PT; ++q)
+            if (hk[q] >= 0) tcnt[q * 256 + threadIdx.x] = hv[q];
     }
     __syncthreads();
+    unsigned long long base[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) base[j] = tcnt[slot[j] >= 0 ? slot[j] : 0];
 #pragma unroll
     for (int j = 0; j < CH; ++j)
         if (key[j] >= 0 && !stay[j] && slot[j] >= 0)
-            D.rank[w0 + j * kWave + lane] = (int)(tcnt[slot[j]] & 0xFFFFFFFFULL) + (int)local[j];
+            D.rank[w0 + j * kWave + lane] = (int)(base[j] & 0xFFFFFFFFULL) + (int)local[j];
 }
 
 // bucket the movers (collisionless particles that changed cell) and the collided particles:
@@ -2612,11 +2628,17 @@ __global__ void __launch_bounds__(256) k_scatter(Dev D) {
         const long long i = b0 + j * 256 + threadIdx.x;
         key[j] = i < n_tot ? D.key[i] : -1;
     }
+    // the offsets and ranks of all chunks in flight together: a particle that is not bucketed
+    // here reads entry 0 of both (a line the wave shares) and discards it
+    int o[CH], r[CH];
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-        const long long i = b0 + j * 256 + threadIdx.x;
-        dst[j] = (key[j] >= 0 && !(key[j] & kStayBit)) ? D.off[key[j]] + D.rank[i] : -1;
+        const bool mv = key[j] >= 0 && !(key[j] & kStayBit);
+        o[j] = D.off[mv ? key[j] : 0];
+        r[j] = D.rank[mv ? b0 + j * 256 + threadIdx.x : 0];
     }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) dst[j] = (key[j] >= 0 && !(key[j] & kStayBit)) ? o[j] + r[j] : -1;
 #pragma unroll
     for (int j = 0; j < CH; ++j)
         if (dst[j] >= 0) D.perm[dst[j]] = (int32_t)(b0 + j * 256 + threadIdx.x);
