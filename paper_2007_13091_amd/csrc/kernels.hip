@@ -2245,11 +2245,11 @@ template <typename R, bool MULTI, bool STORE>
 __device__ __forceinline__ void stream_one(const Dev &D, const Particles &pa, const Particles &pc, long long i,
                                            long long n_old, long long n_smp, int c, R x[3], R u[3], uint64_t uid,
                                            R e, R tauc, unsigned long long &nx_, unsigned &mx_, bool &lost,
-                                           bool &queued, bool &wr, int ct0, const R *B0) {
+                                           bool &queued, bool &wr, int ct0, const R *B0, int inst_c) {
     const R lmargin = sizeof(R) == 8 ? (R)(1.0 - 1e-12) : (R)(1.0f - 1e-5f);
     int c0 = c;
     // a single instance reads its values through uniform addresses
-    const int inst = MULTI ? D.cinst[c] : 0;
+    const int inst = MULTI ? inst_c : 0;
     const InstP &P = D.ip[inst];
     const double dt64 = D.is[inst].dt;
     const R dt = (R)dt64;
@@ -2352,7 +2352,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
     bool qq[ILP], wr[ILP];
     uint4 tl[ILP];
     R xx[ILP][3], uu[ILP][3], ee[ILP], tt[ILP], bx[ILP][6];
-    int ct[ILP];
+    int ct[ILP], ins[ILP];
     uint64_t id[ILP];
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
@@ -2363,13 +2363,15 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
             tl[j] = rec_tail(pa, ii[j], R(0));
         }
     }
-    // start-cell data (e, tau, cell type, box bounds), loaded before the generators run
+    // start-cell data (e, tau, cell type, box bounds, instance), loaded before the generators
+    // run, all in one round
 #pragma unroll
     for (int j = 0; j < ILP; ++j)
         if (ii[j] < n_tot) {
             ee[j] = (R)D.ec[cc[j]];
             tt[j] = (R)D.tau[cc[j]];
-            ct[j] = (int)D.ctype[cc[j]];
+            ct[j] = D.all_box ? 8 : (int)D.ctype[cc[j]];
+            ins[j] = MULTI ? D.cinst[cc[j]] : 0;
             const R *Bg = cell_box<R>(D, cc[j]);
 #pragma unroll
             for (int q = 0; q < 6; ++q) bx[j][q] = Bg[q];
@@ -2381,7 +2383,7 @@ __global__ void __launch_bounds__(BS) k_stream(Dev D, int buf, long long qseg) {
         wr[j] = false;
         if (ii[j] < n_tot) {
             stream_one<R, MULTI, false>(D, pa, pc, ii[j], n_old, n_smp, cc[j], xx[j], uu[j], id[j], ee[j], tt[j], nx_,
-                                        mx_, lost, qq[j], wr[j], ct[j], bx[j]);
+                                        mx_, lost, qq[j], wr[j], ct[j], bx[j], ins[j]);
             stage_state(&stage[threadIdx.x / kWave][j][lane_id() * CPR], xx[j], uu[j], tl[j]);
         }
         wm[j] = __ballot(wr[j]);
