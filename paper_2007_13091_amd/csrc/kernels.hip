@@ -1481,11 +1481,14 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
         const int n = ns[j] > 0 ? ns[j] : 0;
         pre[j + 1] = pre[j] + (n <= kWave ? n : kWave + 1);
     }
-    // cells without new particles: S = P
+    // cells without new particles: S = P (the five loads issued before the first store)
     if (lane < G && myns == 0) {
         const int c = c0 + lane;
+        double pv[5];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) D.S[k * nc + c] = D.P[k * nc + c] + 0.0;
+        for (int k = 0; k < 5; ++k) pv[k] = D.P[k * nc + c];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) D.S[k * nc + c] = pv[k] + 0.0;
     }
     // cells with more than 64 new particles go to k_sample_big's list (one atomic per wave)
     {
@@ -1589,8 +1592,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll
             for (int q = 0; q < 5; ++q) acc[q] = seg_sum(acc[q], first, last);
             if (act && lane == last) {
+                double pv[5];
 #pragma unroll
-                for (int q = 0; q < 5; ++q) D.S[q * nc + c] = D.P[q * nc + c] + acc[q];
+                for (int q = 0; q < 5; ++q) pv[q] = D.P[q * nc + c];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) D.S[q * nc + c] = pv[q] + acc[q];
             }
         }
         g = h;
@@ -3055,18 +3061,30 @@ __global__ void __launch_bounds__(256) k_gks_update(Dev D, int buf) {
 #pragma unroll
     for (int lf = 0; lf < 6; ++lf) codes[lf] = lf < nfc ? D.cface[c * 6 + lf] : 0;
     const double vol = D.vol[c];
+    // every load before the first store (the stores could alias them as far as the compiler
+    // knows, which would otherwise keep one round trip per component)
+    double ph[5][6], pv[5], wv[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int lf = 0; lf < 6; ++lf) {
+            const int cd = codes[lf];
+            const int f = (cd > 0 ? cd : -cd) - 1;
+            ph[k][lf] = lf < nfc ? D.Phi[k * nf + f] : 0.0;
+        }
+        pv[k] = D.P[k * nc + c];
+        wv[k] = D.W[k * nc + c];
+    }
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         double facc = 0.0;
         for (int lf = 0; lf < nfc; ++lf) {
-            const int cd = codes[lf];
-            const int f = (cd > 0 ? cd : -cd) - 1;
-            const double sg = cd > 0 ? 1.0 : -1.0;
-            facc = facc - sg * D.Phi[k * nf + f];
+            const double sg = codes[lf] > 0 ? 1.0 : -1.0;
+            facc = facc - sg * ph[k][lf];
         }
-        const double S = D.P[k * nc + c] + 0.0;
+        const double S = pv[k] + 0.0;
         const double acc = facc + (0.0 - S);
-        D.W[k * nc + c] = D.W[k * nc + c] + acc / vol;
+        D.W[k * nc + c] = wv[k] + acc / vol;
         D.P[k * nc + c] = 0.0;
     }
     const int base = D.off[c], bend = D.off[c + 1];
