@@ -418,14 +418,16 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
             T = (2.0 / (3.0 + D.K)) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rho;
             bad = !(T > 0.0) || !isfinite(T);
         }
+        // geometry loaded with W, before any store
+        const double dS0 = D.dS[c], dS1 = D.dS[nc + c], dS2 = D.dS[2 * nc + c], vol = D.vol[c];
         if (bad) {
             atomicOr(&D.sc->err, kErrNonPhys);
             D.tau[c] = 1.0;
         } else {
             D.tau[c] = P.mu_ref * pow(T, P.omega) / (rho * T);
             double cs = 3.0 * sqrt(T);
-            double lam = (fabs(U) + cs) * D.dS[c] + (fabs(V) + cs) * D.dS[nc + c] + (fabs(Z) + cs) * D.dS[2 * nc + c];
-            r = D.vol[c] / lam;
+            double lam = (fabs(U) + cs) * dS0 + (fabs(V) + cs) * dS1 + (fabs(Z) + cs) * dS2;
+            r = vol / lam;
         }
     }
     // the min over each instance's cells; a block whose cells straddle two instances
@@ -452,25 +454,30 @@ __global__ void __launch_bounds__(256) k_prim_dt(Dev D) {
 __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= D.nc) return;
-    // bucket counters of this step's transport (survivors ending in c, collided ending in c)
-    D.cnt64[c] = 0ULL;
-    D.cnt64[D.nc + c] = 0ULL;
     const int inst = inst_of(D, c);
     const InstP &P = D.ip[inst];
     const double dt = P.cfl * __longlong_as_double((long long)D.is[inst].dtmin_bits);
+    const long long step = D.is[inst].step;
+    // every per-cell value loaded before the first store
+    const double vol = D.vol[c];
+    const double Pm = D.P[c];
+    const double rho = D.W[c];
+    const double tau = D.tau[c];
+    const int nleft = D.nleft[c];
+    // bucket counters of this step's transport (survivors ending in c, collided ending in c)
+    D.cnt64[c] = 0ULL;
+    D.cnt64[D.nc + c] = 0ULL;
     if (c == P.cell0) {
         D.is[inst].dt = dt;
         if (inst == 0) D.sc->dt = dt;
     }
-    const double vol = D.vol[c];
-    const double rhop = D.P[c] / vol;
+    const double rhop = Pm / vol;
     // the hydro density is a difference of sums; below 1e-12 rho it is roundoff of that
     // subtraction (particles hold all the mass) and counts as zero
-    const double rho = D.W[c];
     const double rh = rho - rhop;
     const double rhoh = rh > 1e-12 * rho ? rh : 0.0;
     // wave-only start phase: no particle is sampled
-    const double e = D.is[inst].step < P.gks_steps ? 0.0 : exp(-dt / D.tau[c]);
+    const double e = step < P.gks_steps ? 0.0 : exp(-dt / tau);
     D.rhoh[c] = rhoh;
     D.ec[c] = e;
     const double rhohp = e * rhoh;
@@ -482,7 +489,7 @@ __global__ void __launch_bounds__(256) k_cell_prep(Dev D) {
             atomicOr(&D.sc->err, kErrCellCount);
         } else {
             ns = 2 * (long long)cr;
-            long long need = (long long)P.n_min - D.nleft[c];
+            long long need = (long long)P.n_min - nleft;
             if (need > 0) {
                 long long ne = 2 * ((need + 1) / 2);
                 if (ne > ns) ns = ne;
