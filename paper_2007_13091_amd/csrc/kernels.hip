@@ -915,7 +915,6 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
     for (int k = 0; k < 5; ++k) {
         vc[k] = D.W[k * nc + c];
         vc[5 + k] = fc * vc[k];
-        D.Wh[k * nc + c] = vc[5 + k];
     }
     const double xc[3] = {D.xc[c], D.xc[nc + c], D.xc[2 * nc + c]};
     double A00 = 0, A01 = 0, A02 = 0, A11 = 0, A12 = 0, A22 = 0;
@@ -1035,6 +1034,9 @@ __global__ void __launch_bounds__(128) k_grad(Dev D) {
         if (!(wf[5] >= -1e-12 * wf[0])) ok = false;
         if (wf[5] > 1e-12 * wf[0] && !(temp_k(wf + 5, D.K) > 0.0)) ok = false;
     }
+    // every store after the last load (a load issued after a store waits for it as well)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) D.Wh[k * nc + c] = vc[5 + k];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
 #pragma unroll
