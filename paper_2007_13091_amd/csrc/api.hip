@@ -491,6 +491,15 @@ int32_t ugkwp_init_mesh(ugkwp_ctx **out, const ugkwp_mesh *m, int32_t n_inst, co
     D.any_diffuse = 0;
     for (const auto &bc : ctx->H.bcs) D.any_diffuse |= bc.type == 1 ? 1 : 0;
     D.all_box = D.nfar != nullptr ? 1 : 0;
+    {
+        // sparsely filled cells (the tetrahedral runs, ~50 particles each) give a block of the
+        // bucket count many distinct keys: smaller blocks and a higher occupancy pay there;
+        // dense cells keep the larger blocks (fewer global atomics per key)
+        double per_cell = 0.0;
+        for (int k = 0; k < n_inst; ++k)
+            per_cell += (double)(ctx->ranges[k].cell1 - ctx->ranges[k].cell0) * std::max(p[k].n_ref, p[k].n_min);
+        D.count_ch = per_cell < 128.0 * (double)H.nc ? 4 : 8;
+    }
     D.cap = cap;
     D.prec = p[0].precision;
     D.K = K;

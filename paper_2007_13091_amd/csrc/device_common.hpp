@@ -164,6 +164,7 @@ struct Dev {
                             // face is this one's with the bounds along the face's axis moved
     int32_t recon_any, recon_all;  // some / every instance reconstructs to second order
     int32_t any_diffuse;           // the mesh has a diffuse wall (the wall kernel runs)
+    int32_t count_ch;              // runs of 64 particles per wave of the bucket count (4 or 8)
     const InstP *ip;        // [n_inst]
     InstS *is;              // [n_inst]
     const int32_t *cinst;   // [nc] instance of each cell (n_inst > 1 only)

@@ -46,8 +46,7 @@ __device__ __forceinline__ void st_nt(uint4 *p, const uint4 &v) {
     __builtin_nontemporal_store(x, reinterpret_cast<u32x4_nt *>(p));
 }
 constexpr int kWave = 64;
-constexpr int kCountChunks = 8;    // runs of 64 particles per wave in k_count
-constexpr int kScatterChunks = 4;  // particles per thread in k_scatter
+constexpr int kScatterChunks = 8;  // particles per thread in k_scatter
 constexpr int kSampleCells = 8;     // consecutive cells per wave in k_sample (meshes of 32768 cells or more)
 constexpr int kSampleCellsMin = 32768;
 constexpr int kGatherWaves = 1;    // cells (waves) per block in k_gather (2 and 4 are slower in FP32)
@@ -2531,7 +2530,7 @@ __device__ __forceinline__ unsigned long long key_group(int key) {
 
 // bucket counts: stayers are only counted, movers and collided particles get their slot in
 // the bucket (the order of those slots is fixed later by sorting in the gather).  A block
-// takes 4 waves x kCountChunks runs of 64 consecutive particles and counts them in an LDS
+// takes 4 waves x CH runs of 64 consecutive particles and counts them in an LDS
 // hash table keyed by bucket (open addressing, as many entries as the block has particles,
 // so it cannot fill up; entry = stayers << 32 | movers).  Stayers are grouped by ballots
 // (one LDS atomic per group); a mover or collided particle adds itself, and the returned
@@ -2539,8 +2538,9 @@ __device__ __forceinline__ unsigned long long key_group(int key) {
 // atomic per distinct key of the block adds the block's count to the bucket counter and
 // returns the block's base.  Particles are sorted by start cell, so a block holds a few
 // dozen distinct keys.
+template <int CH>
 __global__ void __launch_bounds__(256) k_count(Dev D) {
-    constexpr int CH = kCountChunks, TS = 256 * kCountChunks;
+    constexpr int TS = 256 * CH;
     constexpr int LOG_TS = __builtin_ctz(TS);
     static_assert((TS & (TS - 1)) == 0, "hash table size must be a power of two");
     __shared__ int tkey[TS];
@@ -3554,7 +3554,10 @@ void launch_step(const Dev &D, int buf, const LaunchCfg &cfg, hipStream_t s, Pro
     }
     pr->end(kSlotStreamWall);
     pr->begin(kSlotCount);
-    k_count<<<(unsigned)((D.cap + 256 * kCountChunks - 1) / (256 * kCountChunks)), 256, 0, s>>>(D);
+    if (D.count_ch == 4)
+        k_count<4><<<(unsigned)((D.cap + 256 * 4 - 1) / (256 * 4)), 256, 0, s>>>(D);
+    else
+        k_count<8><<<(unsigned)((D.cap + 256 * 8 - 1) / (256 * 8)), 256, 0, s>>>(D);
     pr->end(kSlotCount);
     pr->begin(kSlotScan2);
     scan<int32_t>(LoadBucket{D.cnt64}, 2LL * nc, D.off, D.scan32, s);
